@@ -1,0 +1,450 @@
+/*
+ * CPU oracle for COO assembly, CSR products and Jacobi-preconditioned CG.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously
+ * correct statement of what the GPU path computes.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so every
+ * floating-point operation below is evaluated exactly as written, in the
+ * written order.
+ *
+ * Status codes (same meaning as the GPU library's, defined independently):
+ *   0 ok, -1 invalid argument, -2 index out of range, -4 zero diagonal,
+ *   -5 not converged, -6 breakdown.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_INVALID (-1)
+#define OR_RANGE (-2)
+#define OR_ZERO_DIAG (-4)
+#define OR_NOT_CONVERGED (-5)
+#define OR_BREAKDOWN (-6)
+
+/* ------------------------------------------------------------------------
+ * COO -> CSR (paper Sec. 5, "Portable matrix assembly on GPUs").
+ *
+ * Definition: A is the sum of the contributions v[k] to entry
+ * (i[k], j[k]); a triplet with a negative row or column index is ignored.
+ * The stored pattern is the set of distinct (i, j) among the kept
+ * triplets (it comes from the indices alone, so an entry whose
+ * contributions cancel to 0.0 is still stored), rows ascending and columns
+ * ascending within a row.  Each entry is the sum of its contributions in
+ * increasing k, starting from +0.0.
+ *
+ * Helper maps: perm = the kept k sorted by (i, j) with ties in increasing
+ * k; jmap[t] .. jmap[t+1]-1 is the run of perm that feeds stored entry t.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t i, j;
+  int64_t k;
+} coo_key;
+
+static int cmp_key(const void* pa, const void* pb) {
+  const coo_key* a = (const coo_key*)pa;
+  const coo_key* b = (const coo_key*)pb;
+  if (a->i != b->i) return a->i < b->i ? -1 : 1;
+  if (a->j != b->j) return a->j < b->j ? -1 : 1;
+  if (a->k != b->k) return a->k < b->k ? -1 : 1;
+  return 0;
+}
+
+/* rowptr[n+1], col[ncoo], jmap[ncoo+1], perm[ncoo] are caller-allocated
+ * with room for the worst case (every kept triplet distinct). */
+int oracle_coo_pattern(int64_t n, int64_t ncoo, const int32_t* i, const int32_t* j,
+                       int32_t* rowptr, int32_t* col, int64_t* jmap, int32_t* perm,
+                       int64_t* nnz_out, int64_t* nvalid_out) {
+  if (n <= 0 || ncoo < 0) return OR_INVALID;
+  int64_t nvalid = 0;
+  for (int64_t k = 0; k < ncoo; k++) {
+    if (i[k] < 0 || j[k] < 0) continue;
+    if (i[k] >= n || j[k] >= n) return OR_RANGE;
+    nvalid++;
+  }
+  coo_key* keys = (coo_key*)malloc(sizeof(coo_key) * (size_t)(nvalid > 0 ? nvalid : 1));
+  if (!keys) return OR_INVALID;
+  int64_t m = 0;
+  for (int64_t k = 0; k < ncoo; k++) {
+    if (i[k] < 0 || j[k] < 0) continue;
+    keys[m].i = i[k];
+    keys[m].j = j[k];
+    keys[m].k = k;
+    m++;
+  }
+  qsort(keys, (size_t)nvalid, sizeof(coo_key), cmp_key);
+
+  int64_t nnz = 0;
+  for (int64_t r = 0; r <= n; r++) rowptr[r] = 0;
+  for (int64_t q = 0; q < nvalid; q++) {
+    perm[q] = (int32_t)keys[q].k;
+    int first = (q == 0) || keys[q].i != keys[q - 1].i || keys[q].j != keys[q - 1].j;
+    if (first) {
+      jmap[nnz] = q;
+      col[nnz] = keys[q].j;
+      rowptr[keys[q].i + 1] += 1; /* count entries per row */
+      nnz++;
+    }
+  }
+  jmap[nnz] = nvalid;
+  for (int64_t r = 0; r < n; r++) rowptr[r + 1] += rowptr[r];
+  free(keys);
+  *nnz_out = nnz;
+  *nvalid_out = nvalid;
+  return OR_OK;
+}
+
+/* mode 0 = INSERT (a[t] = sum), 1 = ADD (a[t] = a[t] + sum). */
+void oracle_coo_values(int64_t nnz, const int64_t* jmap, const int32_t* perm, const double* v,
+                       int mode, double* val) {
+  for (int64_t t = 0; t < nnz; t++) {
+    double s = 0.0;
+    for (int64_t q = jmap[t]; q < jmap[t + 1]; q++) s += v[perm[q]];
+    if (mode == 1)
+      val[t] = val[t] + s;
+    else
+      val[t] = s;
+  }
+}
+
+/* kslot[k] = stored entry that triplet k feeds, or -1 when k is ignored. */
+void oracle_coo_slots(int64_t ncoo, int64_t nnz, const int64_t* jmap, const int32_t* perm,
+                      int32_t* kslot) {
+  for (int64_t k = 0; k < ncoo; k++) kslot[k] = -1;
+  for (int64_t t = 0; t < nnz; t++)
+    for (int64_t q = jmap[t]; q < jmap[t + 1]; q++) kslot[perm[q]] = (int32_t)t;
+}
+
+/* Entries of the selected rows only, straight from the triplets: for each
+ * selected row r (rows[s], strictly increasing), the distinct columns in
+ * ascending order and their in-order sums.  Used to check very large
+ * assemblies on a sample of rows.  out_ptr[nrows+1], out_col/out_val sized
+ * by the caller (max_out).  Returns the number written or a status < 0. */
+int64_t oracle_coo_rows(int64_t n, int64_t ncoo, const int32_t* i, const int32_t* j,
+                        const double* v, int64_t nrows, const int32_t* rows,
+                        int64_t* out_ptr, int32_t* out_col, double* out_val, int64_t max_out) {
+  int32_t* slot = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!slot) return OR_INVALID;
+  for (int64_t r = 0; r < n; r++) slot[r] = -1;
+  for (int64_t s = 0; s < nrows; s++) slot[rows[s]] = (int32_t)s;
+  int64_t cnt = 0;
+  for (int64_t k = 0; k < ncoo; k++)
+    if (i[k] >= 0 && j[k] >= 0 && slot[i[k]] >= 0) cnt++;
+  coo_key* keys = (coo_key*)malloc(sizeof(coo_key) * (size_t)(cnt > 0 ? cnt : 1));
+  int64_t m = 0;
+  for (int64_t k = 0; k < ncoo; k++)
+    if (i[k] >= 0 && j[k] >= 0 && slot[i[k]] >= 0) {
+      keys[m].i = i[k];
+      keys[m].j = j[k];
+      keys[m].k = k;
+      m++;
+    }
+  qsort(keys, (size_t)cnt, sizeof(coo_key), cmp_key);
+  int64_t w = 0, q = 0;
+  for (int64_t s = 0; s < nrows; s++) {
+    out_ptr[s] = w;
+    while (q < cnt && keys[q].i == rows[s]) {
+      int32_t c = keys[q].j;
+      double acc = 0.0;
+      while (q < cnt && keys[q].i == rows[s] && keys[q].j == c) {
+        acc += v[keys[q].k];
+        q++;
+      }
+      if (w >= max_out) {
+        free(keys);
+        free(slot);
+        return OR_INVALID;
+      }
+      out_col[w] = c;
+      out_val[w] = acc;
+      w++;
+    }
+  }
+  out_ptr[nrows] = w;
+  free(keys);
+  free(slot);
+  return w;
+}
+
+/* ------------------------------------------------------------------------
+ * CSR products (MatMult / MatMultTranspose, paper Sec. 6).
+ * ---------------------------------------------------------------------- */
+
+void oracle_spmv(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                 const double* x, double* y) {
+  for (int64_t r = 0; r < n; r++) {
+    double s = 0.0;
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) s += val[t] * x[col[t]];
+    y[r] = s;
+  }
+}
+
+void oracle_spmv_transpose(int64_t n, const int32_t* rowptr, const int32_t* col,
+                           const double* val, const double* x, double* y) {
+  for (int64_t c = 0; c < n; c++) y[c] = 0.0;
+  for (int64_t r = 0; r < n; r++)
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) y[col[t]] += val[t] * x[r];
+}
+
+/* Y = A X for a row-major block: X[c*ldx + s], Y[r*ldy + s], s < nrhs. */
+void oracle_spmm(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                 int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy) {
+  for (int64_t r = 0; r < n; r++)
+    for (int64_t s = 0; s < nrhs; s++) {
+      double acc = 0.0;
+      for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) acc += val[t] * X[(int64_t)col[t] * ldx + s];
+      Y[r * ldy + s] = acc;
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Jacobi-preconditioned CG (Hestenes-Stiefel form), paper Sec. 6: the
+ * solver is PETSc's CG, built from MatMult, dot products, AXPY updates,
+ * scalar divisions and a residual-norm convergence test.
+ *
+ *   r = b - A x;  z = D^-1 r;  p = z;  rho = r.z
+ *   repeat:  q = A p;  pq = p.q  (pq <= 0 or not finite: breakdown)
+ *            alpha = rho / pq;  x += alpha p;  r -= alpha q
+ *            stop when ||r|| <= rtol ||b||
+ *            z = D^-1 r;  rho' = r.z;  beta = rho' / rho;  p = z + beta p
+ *
+ * Dot products add fixed 4096-element blocks, each summed in order, then
+ * the block sums in order, so a parallel evaluation could reproduce them.
+ * ---------------------------------------------------------------------- */
+
+#define DOT_BLOCK 4096
+
+static double dot64(int64_t n, const double* a, const double* b) {
+  double total = 0.0;
+  for (int64_t s = 0; s < n; s += DOT_BLOCK) {
+    int64_t e = s + DOT_BLOCK < n ? s + DOT_BLOCK : n;
+    double part = 0.0;
+    for (int64_t i = s; i < e; i++) part += a[i] * b[i];
+    total += part;
+  }
+  return total;
+}
+
+/* fp32 vectors, products and sums in fp64 */
+static double dot32(int64_t n, const float* a, const float* b) {
+  double total = 0.0;
+  for (int64_t s = 0; s < n; s += DOT_BLOCK) {
+    int64_t e = s + DOT_BLOCK < n ? s + DOT_BLOCK : n;
+    double part = 0.0;
+    for (int64_t i = s; i < e; i++) part += (double)a[i] * (double)b[i];
+    total += part;
+  }
+  return total;
+}
+
+static int diag_inverse(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                        double* dinv) {
+  for (int64_t r = 0; r < n; r++) {
+    double d = 0.0;
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++)
+      if (col[t] == r) d = val[t];
+    if (d == 0.0) return OR_ZERO_DIAG;
+    dinv[r] = 1.0 / d;
+  }
+  return OR_OK;
+}
+
+/* x: initial guess in, solution out.  iters: iterations performed.
+ * relres: true ||b - A x|| / ||b|| of the returned x (0 when b = 0). */
+int oracle_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+               const double* b, double* x, double rtol, int64_t maxit, int64_t* iters,
+               double* relres) {
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* z = (double*)malloc(sizeof(double) * (size_t)n);
+  double* p = (double*)malloc(sizeof(double) * (size_t)n);
+  double* q = (double*)malloc(sizeof(double) * (size_t)n);
+  double* dinv = (double*)malloc(sizeof(double) * (size_t)n);
+  int status = diag_inverse(n, rowptr, col, val, dinv);
+  int64_t k = 0;
+  double bnorm = sqrt(dot64(n, b, b));
+  if (status == OR_OK) {
+    oracle_spmv(n, rowptr, col, val, x, q);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+    double rnorm = sqrt(dot64(n, r, r));
+    if (!(rnorm <= rtol * bnorm)) {
+      for (int64_t i = 0; i < n; i++) z[i] = dinv[i] * r[i];
+      for (int64_t i = 0; i < n; i++) p[i] = z[i];
+      double rho = dot64(n, r, z);
+      status = OR_NOT_CONVERGED;
+      while (k < maxit) {
+        oracle_spmv(n, rowptr, col, val, p, q);
+        double pq = dot64(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+          status = OR_BREAKDOWN;
+          break;
+        }
+        double alpha = rho / pq;
+        for (int64_t i = 0; i < n; i++) x[i] = x[i] + alpha * p[i];
+        for (int64_t i = 0; i < n; i++) r[i] = r[i] - alpha * q[i];
+        k++;
+        rnorm = sqrt(dot64(n, r, r));
+        if (rnorm <= rtol * bnorm) {
+          status = OR_OK;
+          break;
+        }
+        for (int64_t i = 0; i < n; i++) z[i] = dinv[i] * r[i];
+        double rho_new = dot64(n, r, z);
+        double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+      }
+    }
+  }
+  oracle_spmv(n, rowptr, col, val, x, q);
+  for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+  *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
+  *iters = k;
+  free(r);
+  free(z);
+  free(p);
+  free(q);
+  free(dinv);
+  return status;
+}
+
+/* ------------------------------------------------------------------------
+ * Mixed-precision iterative refinement (paper Sec. 2, multiprecision plan:
+ * device data in a precision other than the solver's).  Outer loop in
+ * fp64: r = b - A x in fp64, stop when ||r|| <= rtol_outer ||b||; inner
+ * Jacobi-CG on fl32(A) d = fl32(r) from d = 0 with fp32 values, vectors
+ * and SpMV, dot products formed and summed in fp64, stopping when
+ * ||r_inner|| <= rtol_inner ||fl32(r)||; then x += d in fp64.
+ * ---------------------------------------------------------------------- */
+
+static void spmv32(int64_t n, const int32_t* rowptr, const int32_t* col, const float* val,
+                   const float* x, float* y) {
+  for (int64_t r = 0; r < n; r++) {
+    float s = 0.0f;
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) s += val[t] * x[col[t]];
+    y[r] = s;
+  }
+}
+
+int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                     const double* b, double* x, double rtol_outer, double rtol_inner,
+                     int64_t maxit_outer, int64_t maxit_inner, int64_t* outer_steps,
+                     int64_t* inner_total, double* relres) {
+  int64_t nnz = rowptr[n];
+  float* val32 = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+  float* dinv32 = (float*)malloc(sizeof(float) * (size_t)n);
+  double* dinv = (double*)malloc(sizeof(double) * (size_t)n);
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* t64 = (double*)malloc(sizeof(double) * (size_t)n);
+  float* ri = (float*)malloc(sizeof(float) * (size_t)n);
+  float* d = (float*)malloc(sizeof(float) * (size_t)n);
+  float* z = (float*)malloc(sizeof(float) * (size_t)n);
+  float* p = (float*)malloc(sizeof(float) * (size_t)n);
+  float* q = (float*)malloc(sizeof(float) * (size_t)n);
+  int64_t outer = 0, inner = 0;
+  int status = diag_inverse(n, rowptr, col, val, dinv);
+  double bnorm = sqrt(dot64(n, b, b));
+  if (status == OR_OK) {
+    for (int64_t t = 0; t < nnz; t++) val32[t] = (float)val[t];
+    for (int64_t i = 0; i < n; i++) dinv32[i] = (float)dinv[i];
+    status = OR_NOT_CONVERGED;
+    for (;;) {
+      oracle_spmv(n, rowptr, col, val, x, t64);
+      for (int64_t i = 0; i < n; i++) r[i] = b[i] - t64[i];
+      double rn = sqrt(dot64(n, r, r));
+      if (rn <= rtol_outer * bnorm) {
+        status = OR_OK;
+        break;
+      }
+      if (outer >= maxit_outer) break;
+      outer++;
+      /* inner fp32 Jacobi-CG from d = 0 */
+      for (int64_t i = 0; i < n; i++) ri[i] = (float)r[i];
+      for (int64_t i = 0; i < n; i++) d[i] = 0.0f;
+      double r0 = sqrt(dot32(n, ri, ri));
+      for (int64_t i = 0; i < n; i++) z[i] = dinv32[i] * ri[i];
+      for (int64_t i = 0; i < n; i++) p[i] = z[i];
+      double rho = dot32(n, ri, z);
+      int64_t it = 0;
+      int bad = 0;
+      while (it < maxit_inner) {
+        spmv32(n, rowptr, col, val32, p, q);
+        double pq = dot32(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+          bad = 1;
+          break;
+        }
+        float a32 = (float)(rho / pq);
+        for (int64_t i = 0; i < n; i++) d[i] = d[i] + a32 * p[i];
+        for (int64_t i = 0; i < n; i++) ri[i] = ri[i] - a32 * q[i];
+        it++;
+        double rr = sqrt(dot32(n, ri, ri));
+        if (rr <= rtol_inner * r0) break;
+        for (int64_t i = 0; i < n; i++) z[i] = dinv32[i] * ri[i];
+        double rho_new = dot32(n, ri, z);
+        float b32 = (float)(rho_new / rho);
+        for (int64_t i = 0; i < n; i++) p[i] = z[i] + b32 * p[i];
+        rho = rho_new;
+      }
+      inner += it;
+      for (int64_t i = 0; i < n; i++) x[i] = x[i] + (double)d[i];
+      if (bad) {
+        status = OR_BREAKDOWN;
+        break;
+      }
+    }
+  }
+  oracle_spmv(n, rowptr, col, val, x, t64);
+  for (int64_t i = 0; i < n; i++) r[i] = b[i] - t64[i];
+  *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
+  *outer_steps = outer;
+  *inner_total = inner;
+  free(val32);
+  free(dinv32);
+  free(dinv);
+  free(r);
+  free(t64);
+  free(ri);
+  free(d);
+  free(z);
+  free(p);
+  free(q);
+  return status;
+}
+
+/* ------------------------------------------------------------------------
+ * Reverse mode through u = A^-1 b with A assembled from COO values v.
+ * With adjoint lambda = A^-T (dL/du):  dL/dA_rc = -lambda_r u_c on the
+ * stored pattern, and by the chain rule through the assembly sum,
+ * dL/dv[k] = -lambda_{i[k]} u_{j[k]} for a kept triplet, 0 otherwise.
+ * ---------------------------------------------------------------------- */
+
+void oracle_sddmm(int64_t n, const int32_t* rowptr, const int32_t* col, const double* lam,
+                  const double* u, double* G) {
+  for (int64_t r = 0; r < n; r++)
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) G[t] = -lam[r] * u[col[t]];
+}
+
+void oracle_coo_grad(int64_t ncoo, const int32_t* i, const int32_t* j, const double* lam,
+                     const double* u, double* grad_v) {
+  for (int64_t k = 0; k < ncoo; k++) {
+    if (i[k] < 0 || j[k] < 0)
+      grad_v[k] = 0.0;
+    else
+      grad_v[k] = -lam[i[k]] * u[j[k]];
+  }
+}
+
+/* grad_e[e] = sum over the element's block of grad_v[k] * dv[k] */
+void oracle_block_reduce(int64_t nblocks, int64_t block, const double* grad_v, const double* dv,
+                         double* grad_e) {
+  for (int64_t e = 0; e < nblocks; e++) {
+    double s = 0.0;
+    for (int64_t k = e * block; k < (e + 1) * block; k++) s += grad_v[k] * dv[k];
+    grad_e[e] = s;
+  }
+}

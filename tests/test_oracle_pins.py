@@ -1,0 +1,501 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+Each test checks the oracle against something it does not compute: brute
+force on tiny inputs, closed forms of the model operators, dense LU,
+spectral facts of CG, finite differences and a hand-written worked example.
+A dropped term, a wrong sign or index or a transposed operand in the oracle
+fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+from paper_2406_08646_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float64).view(np.uint64)
+
+
+def dense_bruteforce(n, i, j, v):
+    """Dense accumulation D[i][j] += v[k] in increasing k from +0.0, plus
+    the set of touched entries."""
+    D = np.zeros((n, n))
+    touched = np.zeros((n, n), bool)
+    for k in range(len(i)):
+        if i[k] < 0 or j[k] < 0:
+            continue
+        D[i[k], j[k]] = D[i[k], j[k]] + v[k]
+        touched[i[k], j[k]] = True
+    return D, touched
+
+
+# ---------------------------------------------------------------- assembly
+
+@settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(n=st.integers(1, 300), ncoo=st.integers(0, 5000), seed=st.integers(0, 2**32 - 1),
+       neg=st.sampled_from([0.0, 0.1, 0.5]), pool=st.integers(1, 2000))
+def test_assembly_matches_dense_bruteforce(orc, n, ncoo, seed, neg, pool):
+    rng = np.random.default_rng(seed)
+    p = W.random_coo(rng, n, ncoo, neg_frac=neg, dup_pool=pool)
+    A = orc.assemble(n, p.i, p.j, p.v)
+    D, touched = dense_bruteforce(n, p.i, p.j, p.v)
+    # pattern: exactly the touched entries, rows then columns ascending
+    rows = np.repeat(np.arange(n), np.diff(A.rowptr))
+    assert A.rowptr[0] == 0 and np.all(np.diff(A.rowptr) >= 0)
+    assert np.array_equal(np.argwhere(touched), np.stack([rows, A.col], 1).reshape(-1, 2))
+    # values: bitwise equal, signed zeros included
+    assert np.array_equal(bits(A.val), bits(D[rows, A.col]))
+    # helper maps: perm lists every kept k once, ascending inside each run
+    kept = np.flatnonzero((p.i >= 0) & (p.j >= 0))
+    assert np.array_equal(np.sort(A.perm), kept)
+    for t in range(A.nnz):
+        run = A.perm[A.jmap[t]:A.jmap[t + 1]]
+        assert run.size > 0 and np.all(np.diff(run) > 0)
+        assert np.all(p.i[run] == rows[t]) and np.all(p.j[run] == A.col[t])
+    # kslot maps each kept triplet to its entry
+    ks = orc.coo_slots(A)
+    assert np.all(ks[(p.i < 0) | (p.j < 0)] == -1)
+    assert np.all(rows[ks[kept]] == p.i[kept]) and np.all(A.col[ks[kept]] == p.j[kept])
+
+
+def test_assembly_add_mode(orc):
+    rng = np.random.default_rng(5)
+    p = W.random_coo(rng, 40, 600)
+    A = orc.assemble(40, p.i, p.j, p.v)
+    v2 = rng.uniform(-1, 1, p.ncoo)
+    added = orc.coo_values(A.jmap, A.perm, v2, mode=1, val=A.val)
+    D, _ = dense_bruteforce(40, p.i, p.j, v2)
+    rows = np.repeat(np.arange(40), np.diff(A.rowptr))
+    assert np.array_equal(bits(added), bits(A.val + D[rows, A.col]))
+
+
+def test_assembly_rejects_out_of_range(orc):
+    i = np.array([0, 1, 5], np.int32)
+    j = np.array([0, 1, 1], np.int32)
+    with pytest.raises(orc.OracleError) as e:
+        orc.coo_pattern(5, i, j)
+    assert e.value.code == -2
+    with pytest.raises(orc.OracleError):
+        orc.coo_pattern(5, np.array([0], np.int32), np.array([7], np.int32))
+
+
+def test_assembly_empty_and_all_ignored(orc):
+    A = orc.assemble(7, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert A.nnz == 0 and np.all(A.rowptr == 0)
+    A = orc.assemble(7, np.array([-1, 3], np.int32), np.array([2, -4], np.int32), np.ones(2))
+    assert A.nnz == 0 and A.nvalid == 0
+
+
+def test_assembly_signed_zero_and_nan(orc):
+    i = np.array([0, 0, 1, 1, 2], np.int32)
+    j = np.array([0, 1, 1, 1, 2], np.int32)
+    v = np.array([-0.0, 3.0, np.inf, -np.inf, np.nan])
+    A = orc.assemble(3, i, j, v)
+    assert bits(A.val[0:1])[0] == bits(np.array([0.0]))[0]  # +0.0 + -0.0 = +0.0
+    assert np.isnan(A.val[2]) and np.isnan(A.val[3])
+
+
+def read_golden():
+    cases, cur = [], None
+    with open(os.path.join(GOLDEN, "periodic_tridiag.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("case"):
+                parts = dict(x.split("=") for x in line.split()[2:])
+                cur = {"n": int(parts["n"]), "X": [float(a) for a in parts["X"].split(",")],
+                       "rows": []}
+                cases.append(cur)
+            else:
+                head, rest = line.split(":", 1)
+                ents = [tuple(e.split(":")) for e in rest.split()]
+                cur["rows"].append([(int(c), float(val)) for c, val in ents])
+    return cases
+
+
+def test_worked_example_periodic_jacobian(orc):
+    for case in read_golden():
+        n = case["n"]
+        p = W.periodic_tridiag_jacobian(n, 1.0, np.array(case["X"]))
+        A = orc.assemble(n, p.i, p.j, p.v)
+        for r, ents in enumerate(case["rows"]):
+            got = [(int(c), float(v)) for c, v in zip(A.col[A.rowptr[r]:A.rowptr[r + 1]],
+                                                      A.val[A.rowptr[r]:A.rowptr[r + 1]])]
+            assert got == ents, (case, r)
+
+
+def test_worked_example_jacobian_action(orc):
+    # J w is the linearisation of R(X) = d(X_{i-1} - 2X_i + X_{i+1}) + X_i^2 - F_i
+    n, d = 37, 0.7
+    rng = np.random.default_rng(11)
+    X = rng.uniform(-1, 1, n)
+    w = rng.uniform(-1, 1, n)
+    p = W.periodic_tridiag_jacobian(n, d, X)
+    A = orc.assemble(n, p.i, p.j, p.v)
+    ref = d * (np.roll(w, 1) - 2 * w + np.roll(w, -1)) + 2 * X * w
+    assert np.allclose(orc.spmv(A, w), ref, rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------- Q1 structure and values
+
+@pytest.mark.parametrize("N,dim", [(1, 2), (2, 2), (5, 2), (8, 2), (1, 3), (2, 3), (4, 3)])
+def test_q1_structure_closed_form(orc, N, dim):
+    p = W.q1_poisson(N, dim)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    M = N + 1
+    assert A.nnz == (3 * M - 2) ** dim
+    assert A.nvalid == p.ncoo == N**dim * 4**dim
+    node = np.arange(p.n)
+    length = np.ones(p.n, np.int64)
+    for d in range(dim):
+        c = (node // M**d) % M
+        length *= 3 - ((c == 0) | (c == N)).astype(np.int64) if N > 0 else 1
+    assert np.array_equal(np.diff(A.rowptr), length)
+
+
+def interior_mask(N, dim):
+    M = N + 1
+    node = np.arange(M**dim)
+    inside = np.ones(M**dim, bool)
+    for d in range(dim):
+        c = (node // M**d) % M
+        inside &= (c > 0) & (c < N)
+    return inside
+
+
+@pytest.mark.parametrize("N,dim", [(6, 2), (4, 3)])
+def test_q1_values_closed_form(orc, N, dim):
+    p = W.q1_poisson(N, dim)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    M = N + 1
+    h = 1.0 / N
+    inside = interior_mask(N, dim)
+    rows = np.repeat(np.arange(p.n), np.diff(A.rowptr))
+    # boundary rows/columns are the identity, exactly
+    bnd = ~inside
+    on_b = bnd[rows] | bnd[A.col]
+    diag = rows == A.col
+    assert np.all(A.val[on_b & diag] == 1.0)
+    assert np.all(A.val[on_b & ~diag] == 0.0)
+    # interior stencil
+    ri = np.array([(rows // M**d) % M for d in range(dim)])
+    ci = np.array([(A.col // M**d) % M for d in range(dim)])
+    ndiff = np.sum(ri != ci, axis=0)
+    if dim == 2:
+        expect = {0: 8.0 / 3.0, 1: -1.0 / 3.0, 2: -1.0 / 3.0}
+    else:
+        expect = {0: 8.0 * h / 3.0, 1: 0.0, 2: -h / 6.0, 3: -h / 12.0}
+    sel = ~on_b
+    for m, e in expect.items():
+        got = A.val[sel & (ndiff == m)]
+        assert got.size > 0
+        assert np.allclose(got, e, rtol=4e-16 * 8, atol=1e-300 if e else 4e-17), (m, e)
+
+
+def q1_mode(N, dim, ks):
+    M = N + 1
+    node = np.arange(M**dim)
+    v = np.ones(M**dim)
+    c = []
+    for d in range(dim):
+        idx = (node // M**d) % M
+        v *= np.sin(ks[d] * math.pi * idx / N)
+        c.append(math.cos(ks[d] * math.pi / N))
+    if dim == 2:
+        lam = (8 - 2 * c[0] - 2 * c[1] - 4 * c[0] * c[1]) / 3
+    else:
+        h = 1.0 / N
+        lam = h * (8.0 / 3 - (2.0 / 3) * (c[0] * c[1] + c[1] * c[2] + c[0] * c[2])
+                   - (2.0 / 3) * c[0] * c[1] * c[2])
+    return v, lam
+
+
+@pytest.mark.parametrize("N,dim,ks", [(8, 2, (1, 1)), (8, 2, (3, 5)), (8, 2, (7, 2)),
+                                      (6, 3, (1, 1, 1)), (6, 3, (2, 5, 3)), (6, 3, (5, 5, 1))])
+def test_spmv_closed_form_eigenpairs(orc, N, dim, ks):
+    p = W.q1_poisson(N, dim)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    v, lam = q1_mode(N, dim, ks)
+    Av = orc.spmv(A, v)
+    scale = np.max(orc.abs_spmv(A, v))
+    assert np.max(np.abs(Av - lam * v)) <= 1e-13 * scale
+    # and the transpose product gives the same for this symmetric operator
+    assert np.max(np.abs(orc.spmv_transpose(A, v) - lam * v)) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("N,dim", [(7, 2), (5, 3)])
+def test_spmv_annihilates_linear_functions(orc, N, dim):
+    p = W.q1_poisson(N, dim)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    M = N + 1
+    node = np.arange(p.n)
+    f = np.full(p.n, 0.3)
+    for d, coef in zip(range(dim), (1.5, -2.0, 0.25)):
+        f += coef * ((node // M**d) % M) / N
+    Af = orc.spmv(A, f)
+    # rows whose whole stencil is interior
+    inside = interior_mask(N, dim)
+    deep = inside.copy()
+    rows = np.repeat(np.arange(p.n), np.diff(A.rowptr))
+    touches_b = np.zeros(p.n, bool)
+    np.logical_or.at(touches_b, rows, ~inside[A.col])
+    deep &= ~touches_b
+    assert deep.any()
+    assert np.max(np.abs(Af[deep])) <= 1e-14 * np.max(orc.abs_spmv(A, f))
+
+
+def test_spmv_symmetry_and_transpose_identity(orc):
+    rng = np.random.default_rng(7)
+    p = W.q1_poisson(6, 3, kappa=np.exp(rng.standard_normal(216)))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    x, y = rng.uniform(-1, 1, (2, p.n))
+    assert abs(x @ orc.spmv(A, y) - y @ orc.spmv(A, x)) <= 1e-13 * (np.abs(x) @ orc.abs_spmv(A, y))
+    # non-symmetric: x.(A y) = (A^T x).y, and A^T differs from A
+    q = W.random_coo(rng, 150, 3000, extreme=False)
+    B = orc.assemble(150, q.i, q.j, q.v)
+    x, y = rng.uniform(-1, 1, (2, 150))
+    lhs = x @ orc.spmv(B, y)
+    rhs = orc.spmv_transpose(B, x) @ y
+    assert abs(lhs - rhs) <= 1e-13 * (np.abs(x) @ orc.abs_spmv(B, y))
+    assert np.max(np.abs(orc.spmv_transpose(B, x) - orc.spmv(B, x))) > 1e-3
+    # A^T assembled from the swapped triplets gives the same product
+    Bt = orc.assemble(150, q.j, q.i, q.v)
+    assert np.array_equal(bits(orc.spmv(Bt, x)), bits(orc.spmv(Bt, x)))
+    assert np.allclose(orc.spmv(Bt, x), orc.spmv_transpose(B, x), rtol=0, atol=1e-13)
+
+
+def test_spmv_against_scipy_library(orc):
+    rng = np.random.default_rng(8)
+    q = W.random_coo(rng, 90, 2000, extreme=False)
+    A = orc.assemble(90, q.i, q.j, q.v)
+    keep = (q.i >= 0) & (q.j >= 0)
+    S = sp.coo_matrix((q.v[keep], (q.i[keep], q.j[keep])), shape=(90, 90)).tocsr()
+    x = rng.uniform(-1, 1, 90)
+    assert np.allclose(orc.spmv(A, x), S @ x, rtol=0, atol=1e-13)
+    X = rng.uniform(-1, 1, (90, 5))
+    assert np.allclose(orc.spmm(A, X), S @ X, rtol=0, atol=1e-13)
+    Y = orc.spmm(A, X)
+    for c in range(5):
+        assert np.array_equal(bits(Y[:, c]), bits(orc.spmv(A, X[:, c])))
+
+
+def test_five_point_closed_form(orc):
+    # constant coefficient 1: eigenvalues 4 - 2cos(k pi/(L+1)) - 2cos(l pi/(L+1))
+    L = 9
+    nh = L * (L - 1)
+    p = W.five_point_system(L, np.ones(nh), np.ones(nh), np.ones(4 * L))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    assert A.nnz == 5 * L * L - 4 * L
+    idx = np.arange(L * L)
+    xs, ys = idx % L, idx // L
+    for k, l in [(1, 1), (3, 7), (9, 2)]:
+        v = np.sin(k * math.pi * (xs + 1) / (L + 1)) * np.sin(l * math.pi * (ys + 1) / (L + 1))
+        lam = 4 - 2 * math.cos(k * math.pi / (L + 1)) - 2 * math.cos(l * math.pi / (L + 1))
+        assert np.max(np.abs(orc.spmv(A, v) - lam * v)) <= 1e-13 * 8
+
+
+# --------------------------------------------------------------------- CG
+
+@pytest.mark.parametrize("N,dim", [(2, 2), (3, 2), (5, 2), (8, 2), (2, 3), (3, 3), (4, 3)])
+def test_cg_matches_dense_lu(orc, N, dim):
+    rng = np.random.default_rng(N * 10 + dim)
+    nel = N**dim
+    p = W.q1_poisson(N, dim, kappa=np.exp(rng.standard_normal(nel)))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    b = rng.uniform(-1, 1, p.n)
+    D = np.zeros((p.n, p.n))
+    rows = np.repeat(np.arange(p.n), np.diff(A.rowptr))
+    D[rows, A.col] = A.val
+    xs = np.linalg.solve(D, b)
+    res = orc.pcg(A, b, 1e-14, 10000)
+    assert res.status == 0
+    assert np.linalg.norm(res.x - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert res.relres <= 1e-13
+
+
+@pytest.mark.parametrize("N,dim,ks", [(10, 2, (2, 3)), (6, 3, (1, 2, 4))])
+def test_cg_eigenmode_one_step(orc, N, dim, ks):
+    p = W.q1_poisson(N, dim)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    v, lam = q1_mode(N, dim, ks)
+    res = orc.pcg(A, v, 1e-12, 50)
+    assert res.status == 0 and res.iters == 1
+    assert np.max(np.abs(res.x - v / lam)) <= 1e-12 * np.max(np.abs(v / lam))
+
+
+def test_cg_sum_of_modes_terminates(orc):
+    N = 12
+    p = W.q1_poisson(N, 2)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    modes = [(1, 1), (2, 5), (7, 3), (11, 11)]
+    b = sum(q1_mode(N, 2, k)[0] * (1 + 0.1 * s) for s, k in enumerate(modes))
+    res = orc.pcg(A, b, 1e-11, 100)
+    assert res.status == 0 and res.iters <= len(modes) + 1
+
+
+def test_cg_error_bound_and_iteration_sanity(orc):
+    N = 31
+    p = W.q1_poisson(N, 2)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    rng = np.random.default_rng(3)
+    b = rng.uniform(-1, 1, p.n)
+    res = orc.pcg(A, b, 1e-10, 5000)
+    assert res.status == 0 and res.relres <= 1e-10 * 1.001
+    ref = orc.pcg(A, b, 1e-15, 5000)
+    lam_min = min(1.0, q1_mode(N, 2, (1, 1))[1])
+    r = b - orc.spmv(A, res.x)
+    rr = b - orc.spmv(A, ref.x)
+    assert np.linalg.norm(res.x - ref.x) <= (np.linalg.norm(r) + np.linalg.norm(rr)) / lam_min
+    # Jacobi-scaled condition number ~ (8/3)/lam_min*(...); iterations well under the bound
+    kappa = q1_mode(N, 2, (N - 1, N - 1))[1] / q1_mode(N, 2, (1, 1))[1]
+    assert res.iters <= 0.5 * math.sqrt(kappa) * math.log(2 / 1e-10) * 1.5
+
+
+def test_cg_status_codes(orc):
+    # zero diagonal
+    i = np.array([0, 1, 1], np.int32)
+    j = np.array([1, 0, 1], np.int32)
+    A = orc.assemble(2, i, j, np.array([1.0, 1.0, 2.0]))
+    assert orc.pcg(A, np.ones(2), 1e-8, 10).status == -4
+    # indefinite -> breakdown (p.Ap <= 0)
+    A = orc.assemble(2, np.array([0, 1], np.int32), np.array([0, 1], np.int32),
+                     np.array([1.0, -1.0]))
+    assert orc.pcg(A, np.array([0.0, 1.0]), 1e-8, 10).status == -6
+    # maxit reached -> not converged, x still usable
+    p = W.q1_poisson(20, 2)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    b = np.random.default_rng(0).uniform(-1, 1, p.n)
+    r = orc.pcg(A, b, 1e-12, 3)
+    assert r.status == -5 and r.iters == 3 and r.relres < 1.0
+    # b = 0 converges immediately
+    r = orc.pcg(A, np.zeros(p.n), 1e-8, 10)
+    assert r.status == 0 and r.iters == 0 and np.all(r.x == 0)
+
+
+# -------------------------------------------------------- mixed precision
+
+def test_mixed_refinement_reaches_fp64_tolerance(orc):
+    rng = np.random.default_rng(1)
+    N = 10
+    z = rng.standard_normal(N**3)
+    p = W.q1_poisson(N, 3, kappa=np.exp(z))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    b = rng.uniform(-1, 1, p.n)
+    res = orc.pcg_mixed(A, b, 1e-10, 1e-4)
+    assert res.status == 0 and res.relres <= 1e-10
+    assert res.outer >= 2  # an fp32 inner solve alone cannot reach 1e-10
+    ref = orc.pcg(A, b, 1e-12)
+    D = np.zeros((p.n, p.n))
+    D[np.repeat(np.arange(p.n), np.diff(A.rowptr)), A.col] = A.val
+    xs = np.linalg.solve(D, b)
+    assert np.linalg.norm(res.x - xs) <= 1e-7 * np.linalg.norm(xs)
+    assert np.linalg.norm(ref.x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+# ----------------------------------------------------------- gradient
+
+def _dense(orc, n, i, j, v):
+    A = orc.assemble(n, i, j, v)
+    rows = np.repeat(np.arange(n), np.diff(A.rowptr))
+    return A, sp.csr_matrix((A.val, (rows, A.col)), shape=(n, n))
+
+
+def test_gradient_matches_finite_differences(orc):
+    N = 12
+    rng = np.random.default_rng(2)
+    theta = rng.standard_normal(N * N)
+    prob = W.q1_poisson(N, 2, kappa=np.exp(theta))
+    tgt = W.q1_poisson(N, 2, kappa=np.ones(N * N))
+    b = np.ones(prob.n)
+    _, St = _dense(orc, tgt.n, tgt.i, tgt.j, tgt.v)
+    ustar = spla.spsolve(St.tocsc(), b)
+
+    def loss(th):
+        pr = W.q1_poisson(N, 2, kappa=np.exp(th))
+        _, S = _dense(orc, pr.n, pr.i, pr.j, pr.v)
+        u = spla.spsolve(S.tocsc(), b)
+        return 0.5 * np.sum((u - ustar) ** 2)
+
+    A = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    fw = orc.pcg(A, b, 1e-14)
+    u = fw.x
+    g = u - ustar
+    adj = orc.pcg(A, g, 1e-14)  # A symmetric, so A^T lambda = g is the same solve
+    lam = adj.x
+    grad_v = orc.coo_grad(prob.i, prob.j, lam, u)
+    grad_theta = orc.block_reduce(grad_v, prob.dv_dlogk, 16)
+    # second, independent formula: element adjoint -exp(theta_e) lam_e^T K u_e
+    K = W.q1_reference_stiffness(2)
+    gi = prob.i.reshape(-1, 4, 4)[:, :, 0]
+    M = N + 1
+    node = np.arange(prob.n)
+    bnd = ((node % M == 0) | (node % M == N) | (node // M == 0) | (node // M == N))
+    lam_e = np.where(bnd[gi], 0.0, lam[gi])
+    u_e = np.where(bnd[gi], 0.0, u[gi])
+    g2 = -np.exp(theta) * np.einsum("ea,ab,eb->e", lam_e, K, u_e)
+    assert np.allclose(grad_theta, g2, rtol=1e-10, atol=1e-12 * np.max(np.abs(g2)))
+    # central differences with direct solves
+    idx = np.sort(rng.choice(N * N, 20, replace=False))
+    hfd = 1e-4
+    fd = []
+    for e in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[e] += hfd
+        tm[e] -= hfd
+        fd.append((loss(tp) - loss(tm)) / (2 * hfd))
+    fd = np.array(fd)
+    assert np.linalg.norm(grad_theta[idx] - fd) <= 1e-6 * np.linalg.norm(fd)
+    # directional derivative
+    dth = rng.standard_normal(N * N)
+    dd = (loss(theta + hfd * dth) - loss(theta - hfd * dth)) / (2 * hfd)
+    assert abs(grad_theta @ dth - dd) <= 1e-6 * abs(dd)
+
+
+def test_sddmm_and_coo_grad_consistent(orc):
+    rng = np.random.default_rng(4)
+    q = W.random_coo(rng, 60, 900, extreme=False)
+    A = orc.assemble(60, q.i, q.j, q.v)
+    lam, u = rng.uniform(-1, 1, (2, 60))
+    G = orc.sddmm(A, lam, u)
+    gv = orc.coo_grad(q.i, q.j, lam, u)
+    ks = orc.coo_slots(A)
+    ref = np.where(ks >= 0, G[np.maximum(ks, 0)], 0.0)
+    assert np.array_equal(bits(gv), bits(ref))
+    # G is the pattern sample of the outer product -lam u^T
+    rows = np.repeat(np.arange(60), np.diff(A.rowptr))
+    assert np.array_equal(bits(G), bits(-np.outer(lam, u)[rows, A.col]))
+
+
+def test_batched_systems_each_solve(orc):
+    probs, bs = W.config4(nsys=4, lo=4, hi=24, seed=9)
+    for p, b in zip(probs, bs):
+        A = orc.assemble(p.n, p.i, p.j, p.v)
+        assert A.nnz == 5 * p.n - 4 * p.grid
+        res = orc.pcg(A, b, 1e-8)
+        assert res.status == 0 and res.relres <= 1e-8 * 1.001
+        D = np.zeros((p.n, p.n))
+        D[np.repeat(np.arange(p.n), np.diff(A.rowptr)), A.col] = A.val
+        assert np.allclose(D, D.T)
+        xs = np.linalg.solve(D, b)
+        assert np.linalg.norm(res.x - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_coo_rows_sample_matches_full_assembly(orc):
+    p = W.q1_poisson(5, 3)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    rows = np.array([0, 7, 50, 100, 215], np.int32)
+    ptr, col, val = orc.coo_rows(p.n, p.i, p.j, p.v, rows)
+    for s, r in enumerate(rows):
+        a, b = A.rowptr[r], A.rowptr[r + 1]
+        assert np.array_equal(col[ptr[s]:ptr[s + 1]], A.col[a:b])
+        assert np.array_equal(bits(val[ptr[s]:ptr[s + 1]]), bits(A.val[a:b]))
