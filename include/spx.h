@@ -1,0 +1,223 @@
+/*
+ * spx — sparse COO assembly, CSR products and Jacobi-preconditioned CG for
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Conventions for every entry point
+ *   - Return value: SPX_OK (0) on success, a negative status otherwise.  No
+ *     C++ exception crosses this boundary.  spx_last_error() returns a
+ *     human-readable message for the last failure on the calling thread.
+ *   - Array arguments are DEVICE pointers (memory of the GPU that was current
+ *     when the handle was created), contiguous, owned by the caller, unless
+ *     stated otherwise.  Scalar outputs (iters_out, relres_out, ...) are
+ *     HOST pointers and may be NULL when not wanted.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it in order; inputs must stay valid until the
+ *     stream has passed the call.  Calls marked "asynchronous" return before
+ *     the GPU has finished; the others synchronise `stream` as documented.
+ *   - Indices are int32, values float64 unless the name says otherwise.
+ *   - Handles are not thread-safe: one handle must not be used from two
+ *     threads or on two streams concurrently.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spx_matrix* spx_handle;
+typedef struct spx_batch* spx_batch_handle;
+
+enum spx_status {
+  SPX_OK = 0,
+  SPX_INVALID_ARG = -1,        /* null pointer, n <= 0, ncoo < 0, bad mode ... */
+  SPX_INDEX_OUT_OF_RANGE = -2, /* a COO index >= n (found on the device)      */
+  SPX_HIP_ERROR = -3,          /* a HIP runtime call failed                   */
+  SPX_ZERO_DIAGONAL = -4,      /* Jacobi preconditioner met a zero/absent a_ii */
+  SPX_NOT_CONVERGED = -5,      /* iteration limit reached; x holds the last iterate */
+  SPX_BREAKDOWN = -6,          /* p.Ap <= 0 or not finite (matrix not SPD)     */
+  SPX_NOT_IMPLEMENTED = -7,
+  SPX_OUT_OF_MEMORY = -8
+};
+
+enum spx_insert_mode { SPX_INSERT_VALUES = 0, SPX_ADD_VALUES = 1 };
+
+/* ---------------------------------------------------------------------------
+ * COO assembly — paper Sec. 5 ("Portable matrix assembly on GPUs"): the
+ * matrix is the sum of the contributions v[k] to entry (i[k], j[k]); a split
+ * into a symbolic stage (pattern and helper maps, once) and numeric stages
+ * (values, many times); negative indices mark ignored triplets.
+ * ------------------------------------------------------------------------- */
+
+/* Symbolic stage, on the device.  Drops triplets with i[k] < 0 or j[k] < 0,
+ * sorts the rest stably by (row, column), and builds the CSR pattern (rows
+ * ascending, columns ascending in a row, an entry for every distinct kept
+ * (i, j) even if its values later cancel) plus the helper maps that let
+ * spx_set_values_coo sum duplicates without atomics:
+ *   perm[q]  = original triplet index k, q < nvalid, ordered by (i, j, k);
+ *   jmap[t]  = first q feeding stored entry t; jmap[nnz] = nvalid.
+ * n: matrix order (1 <= n < 2^31).  ncoo: triplet count (0 <= ncoo < 2^31).
+ * i, j: device int32[ncoo]; they are not referenced after the call returns
+ * and may be freed (paper Sec. 5 allows this).  On success *out receives a
+ * new handle owning all pattern, value and workspace memory.  Errors:
+ * SPX_INVALID_ARG, SPX_INDEX_OUT_OF_RANGE (some kept index >= n),
+ * SPX_OUT_OF_MEMORY, SPX_HIP_ERROR; *out is then NULL.
+ * Synchronises `stream` (the host must learn nnz to size the pattern). */
+int spx_coo_preallocate(int64_t n, int64_t ncoo, const int32_t* i, const int32_t* j, void* stream,
+                        spx_handle* out);
+
+/* Numeric stage.  v: device float64[ncoo] in the same order as i/j.  For
+ * every stored entry t, s = +0.0 + v[perm[jmap[t]]] + ... in increasing k
+ * (one thread per entry, no atomics, bitwise reproducible); mode
+ * SPX_INSERT_VALUES stores s, SPX_ADD_VALUES adds s to the current value.
+ * v[k] of ignored triplets is never read.  Asynchronous. */
+int spx_set_values_coo(spx_handle h, const double* v, int mode, void* stream);
+
+/* Releases everything the handle owns (synchronises the device). NULL ok. */
+int spx_destroy(spx_handle h);
+
+/* ---------------------------------------------------------------------------
+ * Products — paper Sec. 6 (MatMult inside CG).
+ * ------------------------------------------------------------------------- */
+
+/* y = A x.  x, y: device float64[n], must not overlap.  Asynchronous. */
+int spx_matmult(spx_handle h, const double* x, double* y, void* stream);
+
+/* y = A^T x through an explicit transpose (built on first use, refreshed
+ * after each spx_set_values_coo; its entries are bitwise those of A).
+ * Asynchronous (the first call allocates). */
+int spx_matmult_transpose(spx_handle h, const double* x, double* y, void* stream);
+
+/* Y = A X for nrhs right-hand sides stored row-major: X[c*ldx + s],
+ * Y[r*ldy + s], s < nrhs (ldx, ldy >= nrhs).  Asynchronous. */
+int spx_spmm(spx_handle h, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
+             void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Jacobi-preconditioned CG — paper Sec. 6 (CG / CGAsync): scalars stay in
+ * device memory, the host only enqueues kernels and polls a device
+ * convergence flag every `check_every` iterations.
+ *   r = b - A x; z = D^-1 r; p = z; rho = r.z
+ *   repeat: q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q;
+ *           stop when ||r||_2 <= rtol ||b||_2;
+ *           z = D^-1 r; beta = r.z / rho; p = z + beta p
+ * The stopping test uses the recursively updated residual every iteration,
+ * so the iteration count is exact whatever check_every is.
+ * b: device float64[n]; x: device float64[n], initial guess in, solution out.
+ * maxit >= 0; check_every >= 1.  iters_out: iterations done; relres_out:
+ * true ||b - A x|| / ||b|| recomputed at exit (||b - A x|| when b = 0).
+ * Errors: SPX_ZERO_DIAGONAL, SPX_BREAKDOWN, SPX_NOT_CONVERGED (x valid).
+ * Synchronises `stream` at every poll and at exit. */
+int spx_cg_solve(spx_handle h, const double* b, double* x, double rtol, int64_t maxit,
+                 int32_t check_every, void* stream, int64_t* iters_out, double* relres_out);
+
+/* The same solver applied to A^T (adjoint solves). */
+int spx_cg_solve_transpose(spx_handle h, const double* b, double* x, double rtol, int64_t maxit,
+                           int32_t check_every, void* stream, int64_t* iters_out,
+                           double* relres_out);
+
+/* ---------------------------------------------------------------------------
+ * Mixed precision — paper Sec. 2 (multiprecision plan: device data in a
+ * lower precision than the solver's).  Iterative refinement: outer fp64
+ * residual r = b - A x and norm; inner Jacobi-CG on fl32(A) d = fl32(r) from
+ * d = 0 with fp32 matrix, vectors and SpMV but fp64 dot products, stopping
+ * at ||r_in|| <= rtol_inner ||fl32(r)||; x += d in fp64; stop when
+ * ||b - A x|| <= rtol_outer ||b||.  x: device float64[n], in/out (usually 0).
+ * outer_out: refinement steps; inner_out: total inner iterations.
+ * Synchronises `stream`. */
+int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, double rtol_outer,
+                       double rtol_inner, int64_t maxit_outer, int64_t maxit_inner,
+                       int32_t check_every, void* stream, int64_t* outer_out, int64_t* inner_out,
+                       double* relres_out);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves — paper Sec. 7: many independent small systems solved by one
+ * batched Jacobi-preconditioned Krylov solver instead of one stacked
+ * ("ensemble") system.
+ * ------------------------------------------------------------------------- */
+
+/* Groups nsys assembled handles (each with values set) into one batch.  The
+ * batch references the handles' matrices (they must outlive it) and owns
+ * the per-system descriptors and workspace.  Right-hand sides and solutions
+ * are packed back to back: system s occupies [off_s, off_s + n_s) with
+ * off_s = n_0 + ... + n_{s-1}.  Synchronises `stream`. */
+int spx_batch_create(int32_t nsys, const spx_handle* hs, void* stream, spx_batch_handle* out);
+int spx_batch_destroy(spx_batch_handle b);
+int spx_batch_total_rows(spx_batch_handle b, int64_t* total);
+
+/* One persistent launch solves every system with Jacobi-CG to its own
+ * ||r_s|| <= rtol ||b_s||.  Workgroups are split into one team per system
+ * (team sizes from `team_weight_exponent`: a system's share of the resident
+ * workgroups is proportional to (nnz_s * sqrt(n_s))^exponent, at least one
+ * workgroup); teams synchronise with bounded device barriers.  lanes: lanes
+ * per CSR row (0 = automatic).  b, x: packed device float64[total]; x is
+ * the initial guess and receives the solutions.  iters_out / relres_out:
+ * HOST int64[nsys] / float64[nsys] (relres here is the recursively updated
+ * residual norm ratio).  Returns SPX_NOT_CONVERGED if any system hit
+ * maxit, SPX_BREAKDOWN / SPX_ZERO_DIAGONAL if any system failed.
+ * Synchronises `stream`. */
+int spx_batch_cg(spx_batch_handle b, const double* bvec, double* x, double rtol, int64_t maxit,
+                 double team_weight_exponent, int32_t lanes, void* stream, int64_t* iters_out,
+                 double* relres_out);
+
+/* ---------------------------------------------------------------------------
+ * Differentiation of u = A(v)^-1 b through the COO assembly (reverse mode).
+ * ------------------------------------------------------------------------- */
+
+/* G[t] = -lam[row t] * u[col t] for every stored entry t (the gradient of a
+ * loss with respect to the assembled entries, given the adjoint lam).
+ * lam, u: device float64[n]; G: device float64[nnz].  Asynchronous. */
+int spx_sddmm(spx_handle h, const double* lam, const double* u, double* G, void* stream);
+
+/* Backward of the COO assembly: grad_v[k] = G[t(k)] where t(k) is the
+ * stored entry that triplet k feeds, 0.0 for ignored triplets.
+ * G: device float64[nnz]; grad_v: device float64[ncoo].  Asynchronous (the
+ * first call builds the triplet -> entry map). */
+int spx_coo_gather(spx_handle h, const double* G, double* grad_v, void* stream);
+
+/* Fused backward for element-contiguous COO streams (paper Sec. 5,
+ * finite-element usage: each element's triplets are stored contiguously at
+ * offset e*block): grad_e[e] = sum_{k in [e*block, (e+1)*block)}
+ * G[t(k)] * w[k] (ignored triplets contribute 0), summed in increasing k.
+ * w: device float64[ncoo] (dv[k]/dtheta_e); grad_e: device
+ * float64[ncoo/block]; ncoo must be a multiple of block.  Asynchronous. */
+int spx_coo_gather_blocks(spx_handle h, const double* G, const double* w, int64_t block,
+                          double* grad_e, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Introspection (tests and tools).
+ * ------------------------------------------------------------------------- */
+
+/* HOST outputs: order, stored entries, kept triplets, triplets. */
+int spx_get_info(spx_handle h, int64_t* n, int64_t* nnz, int64_t* nvalid, int64_t* ncoo);
+
+/* Copies the CSR arrays of A (transpose = 0) or of the explicit A^T (1)
+ * into caller DEVICE buffers rowptr[n+1], col[nnz], val[nnz]; any may be
+ * NULL.  Asynchronous. */
+int spx_get_csr(spx_handle h, int32_t transpose, int32_t* rowptr, int32_t* col, double* val,
+                void* stream);
+
+/* Copies the helper maps into caller DEVICE buffers jmap[nnz+1],
+ * perm[nvalid] (either may be NULL).  Asynchronous. */
+int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
+
+/* Tuning knobs.  SPX_OPT_SPMV_LANES: lanes per row for products (0 = auto,
+ * else 1..64, a power of two).  SPX_OPT_XCD_REMAP: 1 (default) to give each
+ * XCD a contiguous range of rows, 0 for plain block order. */
+enum spx_option { SPX_OPT_SPMV_LANES = 1, SPX_OPT_XCD_REMAP = 2 };
+int spx_set_option(spx_handle h, int32_t option, int64_t value);
+int spx_get_option(spx_handle h, int32_t option, int64_t* value);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* spx_last_error(void);
+
+/* Library version string. */
+const char* spx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPX_H */

@@ -1,0 +1,115 @@
+// Handle lifetime, error reporting, allocation and options of the C ABI.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace spx {
+
+namespace {
+thread_local char g_last_error[1024] = "";
+}
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_last_error[0] = '\0'; }
+
+int dalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return set_error(SPX_OUT_OF_MEMORY, "device allocation of %zu bytes failed: %s", bytes,
+                     hipGetErrorString(e));
+  }
+  return SPX_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+static void free_csr(Csr& M) {
+  dfree(M.rowptr);
+  dfree(M.col);
+  dfree(M.val);
+  dfree(M.val32);
+  dfree(M.dpos);
+  M = Csr();
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" int spx_destroy(spx_handle h) {
+  clear_error();
+  if (!h) return SPX_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != h->device) (void)hipSetDevice(h->device);
+  free_csr(h->A);
+  free_csr(h->At);
+  dfree(h->jmap);
+  dfree(h->perm);
+  dfree(h->tmap);
+  dfree(h->kslot);
+  dfree(h->dinv);
+  dfree(h->dinv32);
+  dfree(h->work);
+  dfree(h->work32);
+  dfree(h->scal);
+  dfree(h->partials);
+  if (h->scal_host) (void)hipHostFree(h->scal_host);
+  for (hipEvent_t& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (cur != h->device) (void)hipSetDevice(cur);
+  delete h;
+  return SPX_OK;
+}
+
+extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
+  clear_error();
+  if (!h) return set_error(SPX_INVALID_ARG, "set_option: NULL handle");
+  switch (option) {
+    case SPX_OPT_SPMV_LANES:
+      if (value != 0 && (value < 1 || value > 64 || (value & (value - 1))))
+        return set_error(SPX_INVALID_ARG, "set_option: lanes %lld is not 0 or a power of two <= 64",
+                         (long long)value);
+      h->lanes_opt = (int)value;
+      return SPX_OK;
+    case SPX_OPT_XCD_REMAP:
+      h->xcd_remap = value ? 1 : 0;
+      return SPX_OK;
+    default:
+      return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
+  }
+}
+
+extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
+  clear_error();
+  if (!h || !value) return set_error(SPX_INVALID_ARG, "get_option: NULL argument");
+  switch (option) {
+    case SPX_OPT_SPMV_LANES:
+      *value = h->lanes_opt ? h->lanes_opt : pick_lanes(h->A, 0);
+      return SPX_OK;
+    case SPX_OPT_XCD_REMAP:
+      *value = h->xcd_remap;
+      return SPX_OK;
+    default:
+      return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);
+  }
+}
+
+extern "C" const char* spx_last_error(void) { return g_last_error; }
+
+extern "C" const char* spx_version(void) { return "spx 0.1 gfx950"; }

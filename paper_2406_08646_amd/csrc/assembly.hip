@@ -1,0 +1,610 @@
+// COO -> CSR assembly on the device (paper Sec. 5, "Portable matrix assembly
+// on GPUs"): a symbolic stage that turns the index arrays into a CSR pattern
+// plus the jmap/perm maps, and a numeric stage in which one thread owns one
+// stored entry and sums its contributions in input order (no atomics).
+#include <algorithm>
+#include <new>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace spx {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kIpt = 8;
+constexpr int64_t kTile = kBlock * kIpt;
+
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* lds_wave, uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t t = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) lds_wave[w] = inc;
+  __syncthreads();
+  uint32_t wave_off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    uint32_t c = lds_wave[i];
+    if (i < w) wave_off += c;
+    tot += c;
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return wave_off + inc - v;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = value;
+}
+
+__global__ void k_fill_u32_local(uint32_t* p, int64_t count, uint32_t value) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = value;
+}
+
+__global__ void k_fill_f64(double* p, int64_t count, double value) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = value;
+}
+
+__global__ void k_iota_u32(uint32_t* p, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = (uint32_t)t;
+}
+
+// Per tile of kTile triplets: number of kept triplets; flags indices >= n.
+__global__ __launch_bounds__(kBlock) void k_coo_count(const int32_t* __restrict__ i,
+                                                      const int32_t* __restrict__ j,
+                                                      int64_t ncoo, int64_t n,
+                                                      uint32_t* __restrict__ tilecnt,
+                                                      int32_t* __restrict__ err) {
+  __shared__ uint32_t lds[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  uint32_t c = 0;
+  bool bad = false;
+#pragma unroll
+  for (int s = 0; s < kIpt; ++s) {
+    const int64_t k = base + (int64_t)s * kBlock + threadIdx.x;
+    if (k < ncoo) {
+      const int32_t a = i[k], b = j[k];
+      if (a >= 0 && b >= 0) {
+        if (a >= n || b >= n)
+          bad = true;
+        else
+          ++c;
+      }
+    }
+  }
+  if (bad) atomicOr(err, 1);
+  uint32_t tot;
+  (void)block_exscan(c, lds, &tot);
+  if (threadIdx.x == 0) tilecnt[blockIdx.x] = tot;
+}
+
+// Stable compaction of the kept triplets into (key, k) pairs with
+// key = row << cb | col.  Thread t of a tile handles kIpt consecutive k.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_coo_compact(const int32_t* __restrict__ i,
+                                                        const int32_t* __restrict__ j,
+                                                        int64_t ncoo, int64_t n, int cb,
+                                                        const uint32_t* __restrict__ tileoff,
+                                                        K* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+  __shared__ uint32_t lds[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kIpt;
+  int32_t a[kIpt], b[kIpt];
+  uint32_t c = 0;
+#pragma unroll
+  for (int s = 0; s < kIpt; ++s) {
+    const int64_t k = base + s;
+    a[s] = k < ncoo ? i[k] : -1;
+    b[s] = k < ncoo ? j[k] : -1;
+    if (a[s] >= 0 && b[s] >= 0 && a[s] < n && b[s] < n) ++c;
+  }
+  uint32_t pos = block_exscan(c, lds, nullptr) + tileoff[blockIdx.x];
+#pragma unroll
+  for (int s = 0; s < kIpt; ++s) {
+    if (a[s] >= 0 && b[s] >= 0 && a[s] < n && b[s] < n) {
+      keys[pos] = ((K)(uint32_t)a[s] << cb) | (K)(uint32_t)b[s];
+      vals[pos] = (uint32_t)(base + s);
+      ++pos;
+    }
+  }
+}
+
+// Number of run heads (first element of each distinct key) per tile.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_heads_count(const K* __restrict__ keys,
+                                                        int64_t count,
+                                                        uint32_t* __restrict__ tilecnt) {
+  __shared__ uint32_t lds[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kTile;
+  uint32_t c = 0;
+#pragma unroll
+  for (int s = 0; s < kIpt; ++s) {
+    const int64_t q = base + (int64_t)s * kBlock + threadIdx.x;
+    if (q < count && (q == 0 || keys[q] != keys[q - 1])) ++c;
+  }
+  uint32_t tot;
+  (void)block_exscan(c, lds, &tot);
+  if (threadIdx.x == 0) tilecnt[blockIdx.x] = tot;
+}
+
+// For each run head q (entry t): jmap[t] = q, col[t], diagonal position,
+// and rowptr for every row that starts at t (empty rows included).
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_heads_emit(const K* __restrict__ keys, int64_t count,
+                                                       int cb, const uint32_t* __restrict__ tileoff,
+                                                       int32_t* __restrict__ jmap,
+                                                       int32_t* __restrict__ col,
+                                                       int32_t* __restrict__ rowptr,
+                                                       int32_t* __restrict__ dpos) {
+  __shared__ uint32_t lds[kBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kIpt;
+  const K cmask = cb >= (int)(8 * sizeof(K)) ? ~K(0) : ((K(1) << cb) - K(1));
+  K cur[kIpt];
+  bool head[kIpt];
+  uint32_t c = 0;
+  K prev = base > 0 && base - 1 < count ? keys[base - 1] : K(0);
+#pragma unroll
+  for (int s = 0; s < kIpt; ++s) {
+    const int64_t q = base + s;
+    cur[s] = q < count ? keys[q] : K(0);
+    head[s] = q < count && (q == 0 || cur[s] != prev);
+    prev = cur[s];
+    c += head[s];
+  }
+  uint32_t t = block_exscan(c, lds, nullptr) + tileoff[blockIdx.x];
+#pragma unroll
+  for (int s = 0; s < kIpt; ++s) {
+    if (!head[s]) continue;
+    const int64_t q = base + s;
+    const int64_t r = (int64_t)(cur[s] >> cb);
+    const int32_t cc = (int32_t)(cur[s] & cmask);
+    jmap[t] = (int32_t)q;
+    col[t] = cc;
+    if (r == cc) dpos[r] = (int32_t)t;
+    const int64_t pr = q == 0 ? -1 : (int64_t)(keys[q - 1] >> cb);
+    for (int64_t rr = pr + 1; rr <= r; ++rr) rowptr[rr] = (int32_t)t;
+    ++t;
+  }
+}
+
+// rowptr of the rows after the last stored row, and the closing jmap entry.
+template <typename K>
+__global__ void k_rowptr_tail(const K* __restrict__ keys, int64_t count, int cb, int64_t n,
+                              const uint32_t* __restrict__ nnz_dev, int32_t* __restrict__ rowptr,
+                              int32_t* __restrict__ jmap) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t last = count > 0 ? (int64_t)(keys[count - 1] >> cb) : -1;
+  const int32_t nnz = (int32_t)*nnz_dev;
+  if (r <= n && r > last) rowptr[r] = nnz;
+  if (r == 0 && jmap) jmap[nnz] = (int32_t)count;
+}
+
+__global__ void k_max_row(const int32_t* __restrict__ rowptr, int64_t n, int32_t* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t len = r < n ? rowptr[r + 1] - rowptr[r] : 0;
+  len = max(len, __shfl_xor(len, 32, 64));
+  len = max(len, __shfl_xor(len, 16, 64));
+  len = max(len, __shfl_xor(len, 8, 64));
+  len = max(len, __shfl_xor(len, 4, 64));
+  len = max(len, __shfl_xor(len, 2, 64));
+  len = max(len, __shfl_xor(len, 1, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, len);
+}
+
+// One thread per stored entry: in-order sum of its contributions.
+__global__ __launch_bounds__(256) void k_set_values(const int32_t* __restrict__ jmap,
+                                                    const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ v, int64_t nnz,
+                                                    int mode, double* __restrict__ val) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnz) return;
+  const int32_t q0 = jmap[t], q1 = jmap[t + 1];
+  double s = 0.0;
+  for (int32_t q = q0; q < q1; ++q) s += v[perm[q]];
+  val[t] = mode ? val[t] + s : s;
+}
+
+__global__ void k_expand_rows(const int32_t* __restrict__ rowptr, int64_t n,
+                              int32_t* __restrict__ rowidx) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int32_t t = rowptr[r]; t < rowptr[r + 1]; ++t) rowidx[t] = (int32_t)r;
+}
+
+// Explicit transpose from the column-sorted entries: tmap[tt] = entry of A.
+__global__ void k_transpose_emit(const uint32_t* __restrict__ ckeys,
+                                 const uint32_t* __restrict__ tmap, const int32_t* __restrict__ rowidx,
+                                 int64_t nnz, int32_t* __restrict__ rowptrT,
+                                 int32_t* __restrict__ colT, int32_t* __restrict__ dposT) {
+  const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tt >= nnz) return;
+  const int64_t c = ckeys[tt];
+  const int32_t r = rowidx[tmap[tt]];
+  colT[tt] = r;
+  if (r == c) dposT[c] = (int32_t)tt;
+  const int64_t pc = tt == 0 ? -1 : (int64_t)ckeys[tt - 1];
+  for (int64_t cc = pc + 1; cc <= c; ++cc) rowptrT[cc] = (int32_t)tt;
+}
+
+__global__ void k_transpose_tail(const uint32_t* __restrict__ ckeys, int64_t nnz, int64_t n,
+                                 int32_t* __restrict__ rowptrT) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t last = nnz > 0 ? (int64_t)ckeys[nnz - 1] : -1;
+  if (r <= n && r > last) rowptrT[r] = (int32_t)nnz;
+}
+
+__global__ void k_gather_vals(const int32_t* __restrict__ tmap, const double* __restrict__ val,
+                              int64_t nnz, double* __restrict__ valT) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nnz) valT[t] = val[tmap[t]];
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, int64_t count, float* __restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) b[t] = (float)a[t];
+}
+
+__global__ void k_kslot(const int32_t* __restrict__ jmap, const int32_t* __restrict__ perm,
+                        int64_t nnz, int32_t* __restrict__ kslot) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nnz) return;
+  for (int32_t q = jmap[t]; q < jmap[t + 1]; ++q) kslot[perm[q]] = (int32_t)t;
+}
+
+__global__ void k_coo_gather(const int32_t* __restrict__ kslot, const double* __restrict__ G,
+                             int64_t ncoo, double* __restrict__ gv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncoo) return;
+  const int32_t t = kslot[k];
+  gv[k] = t >= 0 ? G[t] : 0.0;
+}
+
+__global__ void k_coo_gather_blocks(const int32_t* __restrict__ kslot,
+                                    const double* __restrict__ G, const double* __restrict__ w,
+                                    int64_t nblocks, int64_t block, double* __restrict__ ge) {
+#pragma clang fp contract(off)
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nblocks) return;
+  double s = 0.0;
+  for (int64_t k = e * block; k < (e + 1) * block; ++k) {
+    const int32_t t = kslot[k];
+    const double g = t >= 0 ? G[t] : 0.0;
+    s += g * w[k];
+  }
+  ge[e] = s;
+}
+
+inline unsigned grid_for(int64_t count, int block) {
+  return (unsigned)std::max<int64_t>(1, ceil_div(count, block));
+}
+
+template <typename K>
+int symbolic(spx_matrix* h, const int32_t* i, const int32_t* j, hipStream_t s) {
+  const int64_t n = h->n, ncoo = h->ncoo;
+  const int cb = h->colbits;
+  const int bits = 2 * cb;
+  const int64_t ntiles = std::max<int64_t>(1, ceil_div(ncoo, kTile));
+  // misc: [0] err, [1] nvalid, [2] nnz, [3] maxrow
+  uint32_t* misc = nullptr;
+  uint32_t* tilecnt = nullptr;
+  K* keys = nullptr;
+  uint32_t* vals = nullptr;
+  int st = SPX_OK;
+  uint32_t host_misc[4] = {0, 0, 0, 0};
+  const int64_t scratch_n = scan_scratch_elems(ntiles);
+  if ((st = dalloc_n(&misc, 64)) != SPX_OK) return st;
+  if ((st = dalloc_n(&tilecnt, (size_t)(ntiles + scratch_n))) != SPX_OK) {
+    dfree(misc);
+    return st;
+  }
+  uint32_t* scratch = tilecnt + ntiles;
+  const int64_t cap = std::max<int64_t>(ncoo, 1);
+  if ((st = dalloc(reinterpret_cast<void**>(&keys), sizeof(K) * (size_t)cap * 2 + 64)) != SPX_OK ||
+      (st = dalloc(reinterpret_cast<void**>(&vals), sizeof(uint32_t) * (size_t)cap * 2 + 64)) !=
+          SPX_OK) {
+    dfree(keys);
+    dfree(tilecnt);
+    dfree(misc);
+    return st;
+  }
+  K* keys_alt = keys + cap;
+  uint32_t* vals_alt = vals + cap;
+  K* skeys = keys;
+  uint32_t* svals = vals;
+  int64_t nvalid = 0, nnz = 0;
+
+  do {
+    hipLaunchKernelGGL(k_fill_u32_local, dim3(1), dim3(64), 0, s, misc, (int64_t)64, 0u);
+    hipLaunchKernelGGL(k_coo_count, dim3((unsigned)ntiles), dim3(kBlock), 0, s, i, j, ncoo, n,
+                       tilecnt, (int32_t*)misc);
+    if ((st = exclusive_scan_u32(tilecnt, tilecnt, ntiles, misc + 1, scratch, s)) != SPX_OK) break;
+    hipLaunchKernelGGL(k_coo_compact<K>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, i, j, ncoo, n,
+                       cb, tilecnt, keys, vals);
+    if (hipMemcpyAsync(host_misc, misc, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = set_error(SPX_HIP_ERROR, "coo_preallocate: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if (host_misc[0]) {
+      st = set_error(SPX_INDEX_OUT_OF_RANGE, "coo_preallocate: a COO index is >= n (%lld)",
+                     (long long)n);
+      break;
+    }
+    nvalid = host_misc[1];
+    if ((st = (sizeof(K) == 8
+                   ? radix_sort_pairs_u64((uint64_t*)keys, (uint64_t*)keys_alt, vals, vals_alt,
+                                          nvalid, bits, s, (uint64_t**)&skeys, &svals)
+                   : radix_sort_pairs_u32((uint32_t*)keys, (uint32_t*)keys_alt, vals, vals_alt,
+                                          nvalid, bits, s, (uint32_t**)&skeys, &svals))) != SPX_OK)
+      break;
+    const int64_t vt = std::max<int64_t>(1, ceil_div(nvalid, kTile));
+    hipLaunchKernelGGL(k_heads_count<K>, dim3((unsigned)vt), dim3(kBlock), 0, s, skeys, nvalid,
+                       tilecnt);
+    if ((st = exclusive_scan_u32(tilecnt, tilecnt, vt, misc + 2, scratch, s)) != SPX_OK) break;
+    if (hipMemcpyAsync(host_misc, misc, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = set_error(SPX_HIP_ERROR, "coo_preallocate: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    nnz = host_misc[2];
+    h->nvalid = nvalid;
+    h->A.n = n;
+    h->A.nnz = nnz;
+    if ((st = dalloc_n(&h->A.rowptr, (size_t)n + 1)) != SPX_OK) break;
+    if ((st = dalloc_n(&h->A.dpos, (size_t)n)) != SPX_OK) break;
+    if ((st = dalloc_n(&h->A.col, (size_t)std::max<int64_t>(nnz, 1))) != SPX_OK) break;
+    if ((st = dalloc_n(&h->A.val, (size_t)std::max<int64_t>(nnz, 1))) != SPX_OK) break;
+    if ((st = dalloc_n(&h->jmap, (size_t)nnz + 1)) != SPX_OK) break;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, h->A.dpos, n, -1);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(nnz, 256)), dim3(256), 0, s, h->A.val, nnz, 0.0);
+    hipLaunchKernelGGL(k_heads_emit<K>, dim3((unsigned)vt), dim3(kBlock), 0, s, skeys, nvalid, cb,
+                       tilecnt, h->jmap, h->A.col, h->A.rowptr, h->A.dpos);
+    hipLaunchKernelGGL(k_rowptr_tail<K>, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, skeys,
+                       nvalid, cb, n, misc + 2, h->A.rowptr, h->jmap);
+    hipLaunchKernelGGL(k_max_row, dim3(grid_for(n, 256)), dim3(256), 0, s, h->A.rowptr, n,
+                       (int32_t*)(misc + 3));
+    // The sorted values are perm; keep that buffer, release the rest.
+    if (hipMemcpyAsync(host_misc, misc, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = set_error(SPX_HIP_ERROR, "coo_preallocate: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    h->A.max_row = host_misc[3];
+    if ((st = dalloc_n(&h->perm, (size_t)std::max<int64_t>(nvalid, 1))) != SPX_OK) break;
+    if (nvalid > 0 &&
+        hipMemcpyAsync(h->perm, svals, sizeof(int32_t) * (size_t)nvalid, hipMemcpyDeviceToDevice,
+                       s) != hipSuccess) {
+      st = set_error(SPX_HIP_ERROR, "coo_preallocate: perm copy failed");
+      break;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+      st = set_error(SPX_HIP_ERROR, "coo_preallocate: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+  } while (false);
+
+  dfree(keys);
+  dfree(vals);
+  dfree(tilecnt);
+  dfree(misc);
+  return st;
+}
+
+}  // namespace
+
+int ensure_transpose(spx_matrix* h, hipStream_t s) {
+  const int64_t n = h->n, nnz = h->A.nnz;
+  if (!h->has_t) {
+    uint32_t *keys = nullptr, *vals = nullptr;
+    int32_t* rowidx = nullptr;
+    const int64_t cap = std::max<int64_t>(nnz, 1);
+    int st = SPX_OK;
+    do {
+      if ((st = dalloc_n(&keys, (size_t)cap * 2)) != SPX_OK) break;
+      if ((st = dalloc_n(&vals, (size_t)cap * 2)) != SPX_OK) break;
+      if ((st = dalloc_n(&rowidx, (size_t)cap)) != SPX_OK) break;
+      if ((st = dalloc_n(&h->At.rowptr, (size_t)n + 1)) != SPX_OK) break;
+      if ((st = dalloc_n(&h->At.col, (size_t)cap)) != SPX_OK) break;
+      if ((st = dalloc_n(&h->At.val, (size_t)cap)) != SPX_OK) break;
+      if ((st = dalloc_n(&h->At.dpos, (size_t)n)) != SPX_OK) break;
+      if ((st = dalloc_n(&h->tmap, (size_t)cap)) != SPX_OK) break;
+      hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(n, 256)), dim3(256), 0, s, h->A.rowptr, n,
+                         rowidx);
+      if (nnz > 0) {
+        SPX_CHECK_HIP(hipMemcpyAsync(keys, h->A.col, sizeof(int32_t) * (size_t)nnz,
+                                     hipMemcpyDeviceToDevice, s));
+      }
+      hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(nnz, 256)), dim3(256), 0, s, vals, nnz);
+      uint32_t *sk = nullptr, *sv = nullptr;
+      if ((st = radix_sort_pairs_u32(keys, keys + cap, vals, vals + cap, nnz, h->colbits, s, &sk,
+                                     &sv)) != SPX_OK)
+        break;
+      hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, h->At.dpos, n, -1);
+      hipLaunchKernelGGL(k_transpose_emit, dim3(grid_for(nnz, 256)), dim3(256), 0, s, sk, sv,
+                         rowidx, nnz, h->At.rowptr, h->At.col, h->At.dpos);
+      hipLaunchKernelGGL(k_transpose_tail, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, sk, nnz, n,
+                         h->At.rowptr);
+      if (nnz > 0)
+        SPX_CHECK_HIP(hipMemcpyAsync(h->tmap, sv, sizeof(int32_t) * (size_t)nnz,
+                                     hipMemcpyDeviceToDevice, s));
+      // row lengths of A^T
+      int32_t* mx = rowidx;  // reuse as scratch after the emit kernels
+      SPX_CHECK_HIP(hipStreamSynchronize(s));
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, mx, (int64_t)1, 0);
+      hipLaunchKernelGGL(k_max_row, dim3(grid_for(n, 256)), dim3(256), 0, s, h->At.rowptr, n, mx);
+      int32_t host_mx = 0;
+      SPX_CHECK_HIP(hipMemcpyAsync(&host_mx, mx, 4, hipMemcpyDeviceToHost, s));
+      SPX_CHECK_HIP(hipStreamSynchronize(s));
+      h->At.max_row = host_mx;
+      h->At.n = n;
+      h->At.nnz = nnz;
+    } while (false);
+    dfree(keys);
+    dfree(vals);
+    dfree(rowidx);
+    if (st != SPX_OK) return st;
+    h->has_t = true;
+    h->valT_fresh = false;
+  }
+  if (!h->valT_fresh) {
+    hipLaunchKernelGGL(k_gather_vals, dim3(grid_for(nnz, 256)), dim3(256), 0, s, h->tmap, h->A.val,
+                       nnz, h->At.val);
+    h->valT_fresh = true;
+    h->valT32_fresh = false;
+  }
+  return SPX_OK;
+}
+
+int ensure_val32(spx_matrix* h, hipStream_t s) {
+  if (!h->A.val32) SPX_TRY(dalloc_n(&h->A.val32, (size_t)std::max<int64_t>(h->A.nnz, 1)));
+  if (!h->val32_fresh) {
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(h->A.nnz, 256)), dim3(256), 0, s, h->A.val,
+                       h->A.nnz, h->A.val32);
+    h->val32_fresh = true;
+  }
+  return SPX_OK;
+}
+
+int ensure_kslot(spx_matrix* h, hipStream_t s) {
+  if (h->kslot) return SPX_OK;
+  SPX_TRY(dalloc_n(&h->kslot, (size_t)std::max<int64_t>(h->ncoo, 1)));
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(h->ncoo, 256)), dim3(256), 0, s, h->kslot, h->ncoo,
+                     -1);
+  hipLaunchKernelGGL(k_kslot, dim3(grid_for(h->A.nnz, 256)), dim3(256), 0, s, h->jmap, h->perm,
+                     h->A.nnz, h->kslot);
+  return SPX_OK;
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" int spx_coo_preallocate(int64_t n, int64_t ncoo, const int32_t* i, const int32_t* j,
+                                   void* stream, spx_handle* out) {
+  clear_error();
+  if (!out) return set_error(SPX_INVALID_ARG, "coo_preallocate: out is NULL");
+  *out = nullptr;
+  if (n <= 0 || n > INT32_MAX - 1)
+    return set_error(SPX_INVALID_ARG, "coo_preallocate: n = %lld out of [1, 2^31-2]", (long long)n);
+  if (ncoo < 0 || ncoo > INT32_MAX - 1)
+    return set_error(SPX_INVALID_ARG, "coo_preallocate: ncoo = %lld out of [0, 2^31-2]",
+                     (long long)ncoo);
+  if (ncoo > 0 && (!i || !j)) return set_error(SPX_INVALID_ARG, "coo_preallocate: i or j is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  spx_matrix* h = new (std::nothrow) spx_matrix();
+  if (!h) return set_error(SPX_OUT_OF_MEMORY, "coo_preallocate: host allocation failed");
+  SPX_CHECK_HIP(hipGetDevice(&h->device));
+  h->n = n;
+  h->ncoo = ncoo;
+  int cb = 0;
+  while (cb < 31 && ((int64_t)1 << cb) < n) ++cb;  // bits of n-1
+  h->colbits = cb;
+  const int st = (2 * cb <= 32) ? symbolic<uint32_t>(h, i, j, s) : symbolic<uint64_t>(h, i, j, s);
+  if (st != SPX_OK) {
+    spx_destroy(h);
+    return st;
+  }
+  *out = h;
+  return SPX_OK;
+}
+
+extern "C" int spx_set_values_coo(spx_handle h, const double* v, int mode, void* stream) {
+  clear_error();
+  if (!h) return set_error(SPX_INVALID_ARG, "set_values_coo: NULL handle");
+  if (mode != SPX_INSERT_VALUES && mode != SPX_ADD_VALUES)
+    return set_error(SPX_INVALID_ARG, "set_values_coo: mode %d is not INSERT(0) or ADD(1)", mode);
+  if (h->nvalid > 0 && !v) return set_error(SPX_INVALID_ARG, "set_values_coo: v is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t nnz = h->A.nnz;
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_set_values, dim3(grid_for(nnz, 256)), dim3(256), 0, s, h->jmap, h->perm,
+                       v, nnz, mode, h->A.val);
+  h->valT_fresh = false;
+  h->val32_fresh = false;
+  h->valT32_fresh = false;
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+extern "C" int spx_get_info(spx_handle h, int64_t* n, int64_t* nnz, int64_t* nvalid,
+                            int64_t* ncoo) {
+  clear_error();
+  if (!h) return set_error(SPX_INVALID_ARG, "get_info: NULL handle");
+  if (n) *n = h->n;
+  if (nnz) *nnz = h->A.nnz;
+  if (nvalid) *nvalid = h->nvalid;
+  if (ncoo) *ncoo = h->ncoo;
+  return SPX_OK;
+}
+
+extern "C" int spx_get_csr(spx_handle h, int32_t transpose, int32_t* rowptr, int32_t* col,
+                           double* val, void* stream) {
+  clear_error();
+  if (!h) return set_error(SPX_INVALID_ARG, "get_csr: NULL handle");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (transpose) SPX_TRY(ensure_transpose(h, s));
+  const Csr& M = transpose ? h->At : h->A;
+  if (rowptr)
+    SPX_CHECK_HIP(hipMemcpyAsync(rowptr, M.rowptr, sizeof(int32_t) * (size_t)(h->n + 1),
+                                 hipMemcpyDeviceToDevice, s));
+  if (col && M.nnz)
+    SPX_CHECK_HIP(hipMemcpyAsync(col, M.col, sizeof(int32_t) * (size_t)M.nnz,
+                                 hipMemcpyDeviceToDevice, s));
+  if (val && M.nnz)
+    SPX_CHECK_HIP(hipMemcpyAsync(val, M.val, sizeof(double) * (size_t)M.nnz,
+                                 hipMemcpyDeviceToDevice, s));
+  return SPX_OK;
+}
+
+extern "C" int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream) {
+  clear_error();
+  if (!h) return set_error(SPX_INVALID_ARG, "get_coo_maps: NULL handle");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (jmap)
+    SPX_CHECK_HIP(hipMemcpyAsync(jmap, h->jmap, sizeof(int32_t) * (size_t)(h->A.nnz + 1),
+                                 hipMemcpyDeviceToDevice, s));
+  if (perm && h->nvalid)
+    SPX_CHECK_HIP(hipMemcpyAsync(perm, h->perm, sizeof(int32_t) * (size_t)h->nvalid,
+                                 hipMemcpyDeviceToDevice, s));
+  return SPX_OK;
+}
+
+extern "C" int spx_coo_gather(spx_handle h, const double* G, double* grad_v, void* stream) {
+  clear_error();
+  if (!h || (h->ncoo > 0 && (!G || !grad_v)))
+    return set_error(SPX_INVALID_ARG, "coo_gather: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SPX_TRY(ensure_kslot(h, s));
+  if (h->ncoo > 0)
+    hipLaunchKernelGGL(k_coo_gather, dim3(grid_for(h->ncoo, 256)), dim3(256), 0, s, h->kslot, G,
+                       h->ncoo, grad_v);
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+extern "C" int spx_coo_gather_blocks(spx_handle h, const double* G, const double* w,
+                                     int64_t block, double* grad_e, void* stream) {
+  clear_error();
+  if (!h || block <= 0 || (h->ncoo > 0 && (!G || !w || !grad_e)))
+    return set_error(SPX_INVALID_ARG, "coo_gather_blocks: bad argument");
+  if (h->ncoo % block != 0)
+    return set_error(SPX_INVALID_ARG, "coo_gather_blocks: ncoo %lld is not a multiple of %lld",
+                     (long long)h->ncoo, (long long)block);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SPX_TRY(ensure_kslot(h, s));
+  const int64_t nb = h->ncoo / block;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_coo_gather_blocks, dim3(grid_for(nb, 256)), dim3(256), 0, s, h->kslot, G,
+                       w, nb, block, grad_e);
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}

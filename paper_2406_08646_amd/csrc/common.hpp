@@ -1,0 +1,127 @@
+// Internal declarations shared by the spx translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "spx.h"
+
+namespace spx {
+
+// ----------------------------------------------------------------- errors
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+
+#define SPX_CHECK_HIP(call)                                                               \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return ::spx::set_error(SPX_HIP_ERROR, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                              __FILE__, __LINE__);                                        \
+  } while (0)
+
+#define SPX_TRY(expr)       \
+  do {                      \
+    int s_ = (expr);        \
+    if (s_ != SPX_OK) return s_; \
+  } while (0)
+
+// ------------------------------------------------------------- allocation
+// Device memory through hipMalloc; every failure is reported as
+// SPX_OUT_OF_MEMORY with the requested size.
+int dalloc(void** p, size_t bytes);
+void dfree(void* p);
+
+template <typename T>
+inline int dalloc_n(T** p, size_t count) {
+  return dalloc(reinterpret_cast<void**>(p), count * sizeof(T) + 16);
+}
+
+// ----------------------------------------------------- launch geometry
+constexpr int kWave = 64;
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ----------------------------------------------------------------- sort
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
+// key (1 <= bits <= 64).  Sorted output is returned in (*keys_out,
+// *vals_out), which point either at the input buffers or at the alternates.
+// All buffers hold `count` elements; scratch is allocated internally.
+int radix_sort_pairs_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
+                         int64_t count, int bits, hipStream_t s, uint64_t** keys_out,
+                         uint32_t** vals_out);
+int radix_sort_pairs_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
+                         int64_t count, int bits, hipStream_t s, uint32_t** keys_out,
+                         uint32_t** vals_out);
+
+// Exclusive scan of uint32 counts; out may alias in.  If total != nullptr
+// the sum is written there (device).  scratch: scan_scratch_elems(count).
+int64_t scan_scratch_elems(int64_t count);
+int exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count, uint32_t* total,
+                       uint32_t* scratch, hipStream_t s);
+
+// -------------------------------------------------------------- matrix
+struct Csr {
+  int64_t n = 0, nnz = 0;
+  int32_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  int32_t* dpos = nullptr;  // position of the diagonal entry of each row, -1 if absent
+  int64_t max_row = 0;
+};
+
+// Device-resident solver scalars of one CG run.
+struct CgScalars {
+  double rho, alpha, beta, pq;
+  double rr, bb, bnorm, thresh;
+  double r0norm, rr_true, spare0, spare1;
+  int32_t iters, done, status, maxit;
+  uint32_t ticket[4];
+};
+
+}  // namespace spx
+
+struct spx_matrix {
+  int device = 0;
+  int64_t n = 0, ncoo = 0, nvalid = 0;
+  int colbits = 0;
+  spx::Csr A;   // the matrix
+  spx::Csr At;  // explicit transpose (built lazily)
+  int32_t* jmap = nullptr;  // [nnz+1]
+  int32_t* perm = nullptr;  // [nvalid] (buffer holds ncoo)
+  int32_t* tmap = nullptr;  // A^T entry -> A entry
+  int32_t* kslot = nullptr; // triplet -> entry (lazy)
+  bool has_t = false, valT_fresh = false, val32_fresh = false, valT32_fresh = false;
+  bool dinv_fresh = false;
+  double* dinv = nullptr;
+  float* dinv32 = nullptr;
+  // solver workspace (lazy): r, z/p, q vectors and scalars
+  double* work = nullptr;
+  size_t work_elems = 0;
+  float* work32 = nullptr;
+  spx::CgScalars* scal = nullptr;  // device [2]
+  spx::CgScalars* scal_host = nullptr;  // pinned [2]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double* partials = nullptr;  // device reduction partials
+  int64_t partial_cap = 0;
+  int lanes_opt = 0;  // 0 = auto
+  int xcd_remap = 1;
+};
+
+namespace spx {
+// assembly.hip
+int ensure_transpose(spx_matrix* h, hipStream_t s);
+int ensure_kslot(spx_matrix* h, hipStream_t s);
+int ensure_val32(spx_matrix* h, hipStream_t s);
+// spmv.hip
+int pick_lanes(const Csr& A, int opt);
+int launch_spmv(const Csr& A, const double* x, double* y, int lanes, int remap, hipStream_t s);
+int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                hipStream_t s);
+// cg.hip
+int fused_blocks();
+}  // namespace spx

@@ -1,0 +1,203 @@
+// CSR products for gfx950: y = A x, y = A^T x (on the explicit transpose)
+// and Y = A X for a row-major block of right-hand sides.
+//
+// A row is handled by an aligned group of L lanes of a 64-wide wave: the
+// group reads the row's values and column indices as one contiguous run
+// (coalesced, non-temporal so the streamed matrix does not evict x from
+// L2), gathers x, and reduces with a fixed butterfly.  L is chosen from the
+// mean row length.  Blocks are renumbered so each XCD walks a contiguous row
+// range, which keeps the x entries shared by neighbouring rows in that XCD's
+// L2.  No MFMA: SpMV moves ~6 bytes per flop, far below the matrix-core
+// ridge point, so the kernel is bound by HBM bandwidth.
+#include <algorithm>
+
+#include "common.hpp"
+#include "device.hpp"
+#include "spmv_core.hpp"
+
+namespace spx {
+
+namespace {
+
+template <int L, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ x,
+                                                double* __restrict__ y, int remap) {
+  constexpr int RPB = BLOCK / L;
+  const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t row = b * RPB + threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  if (row >= n) return;
+  double s = row_partial<L, double, double, double>(rowptr, col, val, x, row, lane);
+  s = group_sum<L>(s);
+  if (lane == 0) y[row] = s;
+}
+
+template <int L>
+int launch_spmv_l(const Csr& A, const double* x, double* y, int remap, hipStream_t s) {
+  constexpr int BLOCK = 256;
+  constexpr int RPB = BLOCK / L;
+  const int64_t nb = ceil_div(A.n, RPB);
+  hipLaunchKernelGGL((k_spmv<L, BLOCK>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n, A.rowptr,
+                     A.col, A.val, x, y, remap);
+  return SPX_OK;
+}
+
+// Y[r, c] for c < nrhs; a group of G lanes per row, lane c owns column c
+// (and c + G, ...).  The row's (value, column) pair is loaded once per lane
+// group and the 8*G contiguous bytes of X per nonzero are one transaction.
+template <int G, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col,
+                                                const double* __restrict__ val, int64_t nrhs,
+                                                const double* __restrict__ X, int64_t ldx,
+                                                double* __restrict__ Y, int64_t ldy, int remap) {
+  constexpr int RPB = BLOCK / G;
+  const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t row = b * RPB + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  const int32_t t0 = rowptr[row], t1 = rowptr[row + 1];
+  for (int64_t c0 = 0; c0 < nrhs; c0 += G) {
+    const int64_t c = c0 + lane;
+    double acc = 0.0;
+    if (c < nrhs) {
+      for (int32_t t = t0; t < t1; ++t) {
+        const double a = stream_load(val + t);
+        const int64_t cc = stream_load(col + t);
+        acc += a * X[cc * ldx + c];
+      }
+      Y[row * ldy + c] = acc;
+    }
+  }
+}
+
+// G[t] = -lam[row t] * u[col t] on the stored pattern.
+template <int L, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_sddmm(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const double* __restrict__ lam,
+                                                 const double* __restrict__ u,
+                                                 double* __restrict__ G) {
+  constexpr int RPB = BLOCK / L;
+  const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  if (row >= n) return;
+  const double nl = -lam[row];
+  for (int32_t t = rowptr[row] + lane; t < rowptr[row + 1]; t += L) G[t] = nl * u[col[t]];
+}
+
+template <int L>
+int launch_sddmm_l(const Csr& A, const double* lam, const double* u, double* G, hipStream_t s) {
+  constexpr int BLOCK = 256;
+  const int64_t nb = ceil_div(A.n, BLOCK / L);
+  hipLaunchKernelGGL((k_sddmm<L, BLOCK>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n, A.rowptr,
+                     A.col, lam, u, G);
+  return SPX_OK;
+}
+
+template <int G>
+int launch_spmm_g(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y,
+                  int64_t ldy, hipStream_t s) {
+  constexpr int BLOCK = 256;
+  constexpr int RPB = BLOCK / G;
+  const int64_t nb = ceil_div(A.n, RPB);
+  hipLaunchKernelGGL((k_spmm<G, BLOCK>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n, A.rowptr,
+                     A.col, A.val, nrhs, X, ldx, Y, ldy, 1);
+  return SPX_OK;
+}
+
+}  // namespace
+
+int pick_lanes(const Csr& A, int opt) {
+  if (opt > 0) return opt;
+  const double mean = A.n > 0 ? (double)A.nnz / (double)A.n : 0.0;
+  // smallest power of two that covers about half a mean row per lane
+  int L = 1;
+  while (L < 64 && 2.0 * L < mean) L <<= 1;
+  return L;
+}
+
+int launch_spmv(const Csr& A, const double* x, double* y, int lanes, int remap, hipStream_t s) {
+  if (A.n == 0) return SPX_OK;
+  switch (lanes) {
+    case 1: return launch_spmv_l<1>(A, x, y, remap, s);
+    case 2: return launch_spmv_l<2>(A, x, y, remap, s);
+    case 4: return launch_spmv_l<4>(A, x, y, remap, s);
+    case 8: return launch_spmv_l<8>(A, x, y, remap, s);
+    case 16: return launch_spmv_l<16>(A, x, y, remap, s);
+    case 32: return launch_spmv_l<32>(A, x, y, remap, s);
+    case 64: return launch_spmv_l<64>(A, x, y, remap, s);
+    default: return set_error(SPX_INVALID_ARG, "spmv: unsupported lane count %d", lanes);
+  }
+}
+
+int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                hipStream_t s) {
+  if (A.n == 0 || nrhs == 0) return SPX_OK;
+  if (nrhs <= 4) return launch_spmm_g<4>(A, nrhs, X, ldx, Y, ldy, s);
+  if (nrhs <= 8) return launch_spmm_g<8>(A, nrhs, X, ldx, Y, ldy, s);
+  if (nrhs <= 16) return launch_spmm_g<16>(A, nrhs, X, ldx, Y, ldy, s);
+  if (nrhs <= 32) return launch_spmm_g<32>(A, nrhs, X, ldx, Y, ldy, s);
+  return launch_spmm_g<64>(A, nrhs, X, ldx, Y, ldy, s);
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" int spx_matmult(spx_handle h, const double* x, double* y, void* stream) {
+  clear_error();
+  if (!h || !x || !y) return set_error(SPX_INVALID_ARG, "matmult: NULL argument");
+  if (x == y) return set_error(SPX_INVALID_ARG, "matmult: x and y must not alias");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SPX_TRY(launch_spmv(h->A, x, y, pick_lanes(h->A, h->lanes_opt), h->xcd_remap, s));
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+extern "C" int spx_matmult_transpose(spx_handle h, const double* x, double* y, void* stream) {
+  clear_error();
+  if (!h || !x || !y) return set_error(SPX_INVALID_ARG, "matmult_transpose: NULL argument");
+  if (x == y) return set_error(SPX_INVALID_ARG, "matmult_transpose: x and y must not alias");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SPX_TRY(ensure_transpose(h, s));
+  SPX_TRY(launch_spmv(h->At, x, y, pick_lanes(h->At, h->lanes_opt), h->xcd_remap, s));
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+extern "C" int spx_sddmm(spx_handle h, const double* lam, const double* u, double* G,
+                         void* stream) {
+  clear_error();
+  if (!h || !lam || !u || (h->A.nnz > 0 && !G))
+    return set_error(SPX_INVALID_ARG, "sddmm: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int L = pick_lanes(h->A, h->lanes_opt);
+  int st;
+  switch (L) {
+    case 1: st = launch_sddmm_l<1>(h->A, lam, u, G, s); break;
+    case 2: st = launch_sddmm_l<2>(h->A, lam, u, G, s); break;
+    case 4: st = launch_sddmm_l<4>(h->A, lam, u, G, s); break;
+    case 8: st = launch_sddmm_l<8>(h->A, lam, u, G, s); break;
+    case 16: st = launch_sddmm_l<16>(h->A, lam, u, G, s); break;
+    case 32: st = launch_sddmm_l<32>(h->A, lam, u, G, s); break;
+    default: st = launch_sddmm_l<64>(h->A, lam, u, G, s); break;
+  }
+  SPX_TRY(st);
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}
+
+extern "C" int spx_spmm(spx_handle h, int64_t nrhs, const double* X, int64_t ldx, double* Y,
+                        int64_t ldy, void* stream) {
+  clear_error();
+  if (!h || nrhs < 0 || (nrhs > 0 && (!X || !Y)) || ldx < nrhs || ldy < nrhs)
+    return set_error(SPX_INVALID_ARG, "spmm: bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SPX_TRY(launch_spmm(h->A, nrhs, X, ldx, Y, ldy, s));
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}

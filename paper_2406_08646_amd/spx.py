@@ -1,0 +1,360 @@
+"""Python binding of the ``libspx`` C ABI (argument marshalling only).
+
+Every method forwards to the ``extern "C"`` entry point of the same name in
+``include/spx.h``; all arithmetic runs in the HIP kernels of ``libspx.so``.
+torch supplies device memory and the current HIP stream.  If the library is
+missing the binding raises instead of computing anything elsewhere.
+
+    A = coo_preallocate(n, i, j)          # i, j: cuda int32 tensors
+    A.set_values_coo(v)                   # v: cuda float64, same length
+    y = A.matmult(x); yt = A.matmult_transpose(x)
+    res = A.cg_solve(b, rtol=1e-10)       # res.x, res.iters, res.relres
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch  # noqa: F401  (must be loaded before libspx so both share one HIP runtime)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libspx.so")
+
+OK = 0
+INVALID_ARG = -1
+INDEX_OUT_OF_RANGE = -2
+HIP_ERROR = -3
+ZERO_DIAGONAL = -4
+NOT_CONVERGED = -5
+BREAKDOWN = -6
+NOT_IMPLEMENTED = -7
+OUT_OF_MEMORY = -8
+STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "INDEX_OUT_OF_RANGE", -3: "HIP_ERROR",
+                -4: "ZERO_DIAGONAL", -5: "NOT_CONVERGED", -6: "BREAKDOWN",
+                -7: "NOT_IMPLEMENTED", -8: "OUT_OF_MEMORY"}
+INSERT_VALUES = 0
+ADD_VALUES = 1
+OPT_SPMV_LANES = 1
+OPT_XCD_REMAP = 2
+
+# hard failures raise; solver outcomes are returned as a status
+_SOLVER_OUTCOMES = (OK, NOT_CONVERGED, BREAKDOWN, ZERO_DIAGONAL)
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_d = ctypes.c_double
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_pd = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "spx_coo_preallocate": [_i64, _i64, _vp, _vp, _vp, ctypes.POINTER(_vp)],
+    "spx_set_values_coo": [_vp, _vp, ctypes.c_int, _vp],
+    "spx_destroy": [_vp],
+    "spx_matmult": [_vp, _vp, _vp, _vp],
+    "spx_matmult_transpose": [_vp, _vp, _vp, _vp],
+    "spx_spmm": [_vp, _i64, _vp, _i64, _vp, _i64, _vp],
+    "spx_cg_solve": [_vp, _vp, _vp, _d, _i64, _i32, _vp, _pi64, _pd],
+    "spx_cg_solve_transpose": [_vp, _vp, _vp, _d, _i64, _i32, _vp, _pi64, _pd],
+    "spx_cg_solve_mixed": [_vp, _vp, _vp, _d, _d, _i64, _i64, _i32, _vp, _pi64, _pi64, _pd],
+    "spx_batch_create": [_i32, ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp)],
+    "spx_batch_destroy": [_vp],
+    "spx_batch_total_rows": [_vp, _pi64],
+    "spx_batch_cg": [_vp, _vp, _vp, _d, _i64, _d, _i32, _vp, _pi64, _pd],
+    "spx_sddmm": [_vp, _vp, _vp, _vp, _vp],
+    "spx_coo_gather": [_vp, _vp, _vp, _vp],
+    "spx_coo_gather_blocks": [_vp, _vp, _vp, _i64, _vp, _vp],
+    "spx_get_info": [_vp, _pi64, _pi64, _pi64, _pi64],
+    "spx_get_csr": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "spx_get_coo_maps": [_vp, _vp, _vp, _vp],
+    "spx_set_option": [_vp, _i32, _i64],
+    "spx_get_option": [_vp, _i32, _pi64],
+    "spx_last_error": [],
+    "spx_version": [],
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libspx.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2406_08646_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, args in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name in ("spx_last_error", "spx_version") else ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class SpxError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+def _check(rc: int, allowed=(OK,)) -> int:
+    if rc not in allowed:
+        msg = load_library().spx_last_error().decode(errors="replace")
+        raise SpxError(rc, msg)
+    return rc
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, length: Optional[int], name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if length is not None and t.numel() != length:
+        raise ValueError(f"{name} must have {length} elements, got {t.numel()}")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None or t.numel() == 0 else t.data_ptr())
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor
+    iters: int
+    relres: float
+    status: int
+
+
+@dataclass
+class MixedResult:
+    x: torch.Tensor
+    outer: int
+    inner: int
+    relres: float
+    status: int
+
+
+class Matrix:
+    """A matrix assembled from COO triplets on the GPU (owns a spx handle)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, ncoo: int, device: torch.device):
+        self._h = handle
+        self.n = n
+        self.ncoo = ncoo
+        self.device = device
+
+    # -- lifetime
+    def destroy(self) -> None:
+        if self._h:
+            _check(load_library().spx_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise RuntimeError("matrix has been destroyed")
+        return self._h
+
+    # -- assembly
+    def set_values_coo(self, v: torch.Tensor, mode: int = INSERT_VALUES, stream=None) -> None:
+        _dev(v, torch.float64, self.ncoo, "v")
+        _check(load_library().spx_set_values_coo(self.handle, _ptr(v), mode, _stream(stream)))
+
+    def get_info(self):
+        n, nnz, nvalid, ncoo = (ctypes.c_int64() for _ in range(4))
+        _check(load_library().spx_get_info(self.handle, ctypes.byref(n), ctypes.byref(nnz),
+                                           ctypes.byref(nvalid), ctypes.byref(ncoo)))
+        return {"n": n.value, "nnz": nnz.value, "nvalid": nvalid.value, "ncoo": ncoo.value}
+
+    @property
+    def nnz(self) -> int:
+        return self.get_info()["nnz"]
+
+    def get_csr(self, transpose: bool = False, stream=None):
+        info = self.get_info()
+        rowptr = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        col = torch.empty(info["nnz"], dtype=torch.int32, device=self.device)
+        val = torch.empty(info["nnz"], dtype=torch.float64, device=self.device)
+        _check(load_library().spx_get_csr(self.handle, int(transpose), _ptr(rowptr), _ptr(col),
+                                          _ptr(val), _stream(stream)))
+        return rowptr, col, val
+
+    def get_coo_maps(self, stream=None):
+        info = self.get_info()
+        jmap = torch.empty(info["nnz"] + 1, dtype=torch.int32, device=self.device)
+        perm = torch.empty(info["nvalid"], dtype=torch.int32, device=self.device)
+        _check(load_library().spx_get_coo_maps(self.handle, _ptr(jmap), _ptr(perm),
+                                               _stream(stream)))
+        return jmap, perm
+
+    # -- products
+    def matmult(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        _dev(x, torch.float64, self.n, "x")
+        y = torch.empty_like(x) if y is None else _dev(y, torch.float64, self.n, "y")
+        _check(load_library().spx_matmult(self.handle, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def matmult_transpose(self, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+                          stream=None) -> torch.Tensor:
+        _dev(x, torch.float64, self.n, "x")
+        y = torch.empty_like(x) if y is None else _dev(y, torch.float64, self.n, "y")
+        _check(load_library().spx_matmult_transpose(self.handle, _ptr(x), _ptr(y),
+                                                    _stream(stream)))
+        return y
+
+    def spmm(self, X: torch.Tensor, Y: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if X.dim() != 2 or X.shape[0] != self.n:
+            raise ValueError("X must be n x nrhs (row-major)")
+        _dev(X, torch.float64, None, "X")
+        nrhs = X.shape[1]
+        Y = torch.empty_like(X) if Y is None else _dev(Y, torch.float64, self.n * nrhs, "Y")
+        _check(load_library().spx_spmm(self.handle, nrhs, _ptr(X), nrhs, _ptr(Y), nrhs,
+                                       _stream(stream)))
+        return Y
+
+    # -- solvers
+    def _solve(self, fn, b, x, rtol, maxit, check_every, stream):
+        _dev(b, torch.float64, self.n, "b")
+        x = torch.zeros_like(b) if x is None else _dev(x, torch.float64, self.n, "x")
+        it = ctypes.c_int64()
+        rr = ctypes.c_double()
+        rc = fn(self.handle, _ptr(b), _ptr(x), rtol, maxit, check_every, _stream(stream),
+                ctypes.byref(it), ctypes.byref(rr))
+        _check(rc, _SOLVER_OUTCOMES)
+        return SolveResult(x, it.value, rr.value, rc)
+
+    def cg_solve(self, b, x=None, rtol=1e-10, maxit=100000, check_every=20, stream=None):
+        return self._solve(load_library().spx_cg_solve, b, x, rtol, maxit, check_every, stream)
+
+    def cg_solve_transpose(self, b, x=None, rtol=1e-10, maxit=100000, check_every=20, stream=None):
+        return self._solve(load_library().spx_cg_solve_transpose, b, x, rtol, maxit, check_every,
+                           stream)
+
+    def cg_solve_mixed(self, b, x=None, rtol_outer=1e-10, rtol_inner=1e-4, maxit_outer=100,
+                       maxit_inner=100000, check_every=20, stream=None):
+        _dev(b, torch.float64, self.n, "b")
+        x = torch.zeros_like(b) if x is None else _dev(x, torch.float64, self.n, "x")
+        outer, inner = ctypes.c_int64(), ctypes.c_int64()
+        rr = ctypes.c_double()
+        rc = load_library().spx_cg_solve_mixed(self.handle, _ptr(b), _ptr(x), rtol_outer,
+                                               rtol_inner, maxit_outer, maxit_inner, check_every,
+                                               _stream(stream), ctypes.byref(outer),
+                                               ctypes.byref(inner), ctypes.byref(rr))
+        _check(rc, _SOLVER_OUTCOMES)
+        return MixedResult(x, outer.value, inner.value, rr.value, rc)
+
+    # -- reverse mode
+    def sddmm(self, lam, u, G=None, stream=None):
+        _dev(lam, torch.float64, self.n, "lam")
+        _dev(u, torch.float64, self.n, "u")
+        nnz = self.nnz
+        G = torch.empty(nnz, dtype=torch.float64, device=self.device) if G is None else \
+            _dev(G, torch.float64, nnz, "G")
+        _check(load_library().spx_sddmm(self.handle, _ptr(lam), _ptr(u), _ptr(G), _stream(stream)))
+        return G
+
+    def coo_gather(self, G, grad_v=None, stream=None):
+        _dev(G, torch.float64, self.nnz, "G")
+        grad_v = torch.empty(self.ncoo, dtype=torch.float64, device=self.device) \
+            if grad_v is None else _dev(grad_v, torch.float64, self.ncoo, "grad_v")
+        _check(load_library().spx_coo_gather(self.handle, _ptr(G), _ptr(grad_v), _stream(stream)))
+        return grad_v
+
+    def coo_gather_blocks(self, G, w, block: int, grad_e=None, stream=None):
+        _dev(G, torch.float64, self.nnz, "G")
+        _dev(w, torch.float64, self.ncoo, "w")
+        nb = self.ncoo // block if block > 0 else 0
+        grad_e = torch.empty(nb, dtype=torch.float64, device=self.device) \
+            if grad_e is None else _dev(grad_e, torch.float64, nb, "grad_e")
+        _check(load_library().spx_coo_gather_blocks(self.handle, _ptr(G), _ptr(w), block,
+                                                    _ptr(grad_e), _stream(stream)))
+        return grad_e
+
+    # -- options
+    def set_option(self, option: int, value: int) -> None:
+        _check(load_library().spx_set_option(self.handle, option, value))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64()
+        _check(load_library().spx_get_option(self.handle, option, ctypes.byref(v)))
+        return v.value
+
+
+def coo_preallocate(n: int, i: torch.Tensor, j: torch.Tensor, stream=None) -> Matrix:
+    """Symbolic COO stage on the GPU (paper Sec. 5); returns a Matrix."""
+    ncoo = i.numel()
+    _dev(i, torch.int32, None, "i")
+    _dev(j, torch.int32, ncoo, "j")
+    h = ctypes.c_void_p()
+    _check(load_library().spx_coo_preallocate(n, ncoo, _ptr(i), _ptr(j), _stream(stream),
+                                              ctypes.byref(h)))
+    return Matrix(h, n, ncoo, i.device)
+
+
+class Batch:
+    """Several assembled matrices solved together by one persistent launch."""
+
+    def __init__(self, mats: Sequence[Matrix], stream=None):
+        self.mats = list(mats)
+        arr = (ctypes.c_void_p * len(self.mats))(*[m.handle for m in self.mats])
+        h = ctypes.c_void_p()
+        _check(load_library().spx_batch_create(len(self.mats), arr, _stream(stream),
+                                               ctypes.byref(h)))
+        self._h = h
+        tot = ctypes.c_int64()
+        _check(load_library().spx_batch_total_rows(self._h, ctypes.byref(tot)))
+        self.total = tot.value
+        self.offsets = [0]
+        for m in self.mats:
+            self.offsets.append(self.offsets[-1] + m.n)
+
+    def destroy(self):
+        if self._h:
+            _check(load_library().spx_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def batch_cg(self, b, x=None, rtol=1e-8, maxit=100000, team_weight_exponent=1.0, lanes=0,
+                 stream=None):
+        _dev(b, torch.float64, self.total, "b")
+        x = torch.zeros_like(b) if x is None else _dev(x, torch.float64, self.total, "x")
+        ns = len(self.mats)
+        iters = (ctypes.c_int64 * ns)()
+        rel = (ctypes.c_double * ns)()
+        rc = load_library().spx_batch_cg(self._h, _ptr(b), _ptr(x), rtol, maxit,
+                                         team_weight_exponent, lanes, _stream(stream),
+                                         ctypes.cast(iters, _pi64), ctypes.cast(rel, _pd))
+        _check(rc, _SOLVER_OUTCOMES)
+        return x, list(iters), list(rel), rc
+
+
+def batch_create(mats: Sequence[Matrix], stream=None) -> Batch:
+    return Batch(mats, stream)
+
+
+def version() -> str:
+    return load_library().spx_version().decode()

@@ -1,0 +1,131 @@
+"""GPU COO assembly against the oracle: bit-exact pattern, maps and values."""
+import numpy as np
+import pytest
+
+from paper_2406_08646_amd import workloads as W
+from gpu_util import assemble, bits, csr_equal, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def check_full(orc, spx, prob):
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    info = A.get_info()
+    assert info["nnz"] == ref.nnz and info["nvalid"] == ref.nvalid and info["ncoo"] == prob.ncoo
+    rowptr, col, val = (host(t) for t in A.get_csr())
+    csr_equal(ref, rowptr, col, val)
+    jmap, perm = (host(t) for t in A.get_coo_maps())
+    assert np.array_equal(jmap.astype(np.int64), ref.jmap)
+    assert np.array_equal(perm, ref.perm)
+    return A, ref
+
+
+def test_config1_assembly_bitwise(orc):
+    spx = require_gpu()
+    prob, _, _ = W.config1()
+    print("config1 assembly n=%d ncoo=%d" % (prob.n, prob.ncoo), flush=True)
+    A, ref = check_full(orc, spx, prob)
+    assert ref.nnz == 190 * 190
+
+
+@pytest.mark.parametrize("n,ncoo,neg,seed", [
+    (1, 1, 0.0, 0), (1, 50, 0.3, 1), (7, 0, 0.0, 2), (7, 1000, 0.5, 3), (300, 5000, 0.1, 4),
+    (5000, 200000, 0.1, 5), (65536, 300000, 0.05, 6), (65537, 300000, 0.05, 7),
+    (3_000_000, 1_000_000, 0.1, 8), (2047, 2049, 0.0, 9), (4096, 2048 * 3 + 1, 0.2, 10),
+])
+def test_random_coo_bitwise(orc, n, ncoo, neg, seed):
+    spx = require_gpu()
+    print(f"random coo n={n} ncoo={ncoo} seed={seed}", flush=True)
+    rng = np.random.default_rng(seed)
+    prob = W.random_coo(rng, n, ncoo, neg_frac=neg)
+    check_full(orc, spx, prob)
+
+
+def test_all_ignored_and_empty(orc):
+    spx = require_gpu()
+    i = np.array([-1, 3, -7], np.int32)
+    j = np.array([2, -1, -1], np.int32)
+    A = spx.coo_preallocate(5, dev(i), dev(j))
+    A.set_values_coo(dev(np.ones(3)))
+    assert A.get_info()["nnz"] == 0
+    rowptr, col, val = (host(t) for t in A.get_csr())
+    assert np.all(rowptr == 0)
+    import torch
+    e = torch.zeros(0, dtype=torch.int32, device="cuda")
+    B = spx.coo_preallocate(4, e, e)
+    assert B.get_info()["nnz"] == 0
+    B.set_values_coo(torch.zeros(0, dtype=torch.float64, device="cuda"))
+    y = B.matmult(dev(np.ones(4)))
+    assert np.all(host(y) == 0.0)
+
+
+def test_out_of_range_index_is_an_error():
+    spx = require_gpu()
+    i = np.array([0, 1, 5], np.int32)
+    j = np.array([0, 1, 1], np.int32)
+    with pytest.raises(spx.SpxError) as e:
+        spx.coo_preallocate(5, dev(i), dev(j))
+    assert e.value.code == spx.INDEX_OUT_OF_RANGE
+    with pytest.raises(spx.SpxError) as e:
+        spx.coo_preallocate(0, dev(i), dev(j))
+    assert e.value.code == spx.INVALID_ARG
+
+
+def test_insert_then_add(orc):
+    spx = require_gpu()
+    rng = np.random.default_rng(12)
+    prob = W.random_coo(rng, 500, 20000)
+    A, ref = check_full(orc, spx, prob)
+    v2 = rng.uniform(-1, 1, prob.ncoo)
+    A.set_values_coo(dev(v2), mode=spx.ADD_VALUES)
+    want = orc.coo_values(ref.jmap, ref.perm, v2, mode=1, val=ref.val)
+    assert np.array_equal(bits(host(A.get_csr()[2])), bits(want))
+    A.set_values_coo(dev(v2))  # insert overwrites
+    want = orc.coo_values(ref.jmap, ref.perm, v2)
+    assert np.array_equal(bits(host(A.get_csr()[2])), bits(want))
+
+
+def test_transpose_is_assembly_of_swapped_triplets(orc):
+    spx = require_gpu()
+    rng = np.random.default_rng(13)
+    prob = W.random_coo(rng, 2000, 100000, neg_frac=0.1)
+    A = assemble(spx, prob)
+    ref_t = orc.assemble(prob.n, prob.j, prob.i, prob.v)
+    rowptr, col, val = (host(t) for t in A.get_csr(transpose=True))
+    csr_equal(ref_t, rowptr, col, val)
+    # refreshed after new values
+    v2 = rng.standard_normal(prob.ncoo)
+    A.set_values_coo(dev(v2))
+    ref_t2 = orc.assemble(prob.n, prob.j, prob.i, v2)
+    rowptr, col, val = (host(t) for t in A.get_csr(transpose=True))
+    csr_equal(ref_t2, rowptr, col, val)
+
+
+def test_worked_example_periodic_jacobian(orc):
+    spx = require_gpu()
+    for n in (1, 2, 5, 33):
+        X = np.linspace(-1, 2, n)
+        prob = W.periodic_tridiag_jacobian(n, 0.75, X)
+        check_full(orc, spx, prob)
+
+
+def test_repeat_assembly_is_deterministic(orc):
+    spx = require_gpu()
+    rng = np.random.default_rng(14)
+    prob = W.random_coo(rng, 10000, 500000)
+    outs = []
+    for _ in range(3):
+        A = assemble(spx, prob)
+        outs.append([host(t) for t in A.get_csr()] + [host(t) for t in A.get_coo_maps()])
+        A.destroy()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+@pytest.mark.parametrize("N", [24])
+def test_q1_3d_small_bitwise(orc, N):
+    spx = require_gpu()
+    prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(1).standard_normal(N**3)))
+    check_full(orc, spx, prob)

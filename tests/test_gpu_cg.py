@@ -1,0 +1,185 @@
+"""GPU Jacobi-PCG and mixed-precision refinement against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_08646_amd import workloads as W
+from gpu_util import assemble, bits, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def residual_norm(prob, x, b):
+    """||b - A x|| straight from the triplets (numpy, any summation order)."""
+    keep = (prob.i >= 0) & (prob.j >= 0)
+    Ax = np.bincount(prob.i[keep], weights=prob.v[keep] * x[prob.j[keep]], minlength=prob.n)
+    return np.linalg.norm(b - Ax)
+
+
+def check_against_oracle(orc, ref, res, ores, b, rtol, lam_min):
+    assert res.status == 0 and ores.status == 0
+    assert res.relres <= rtol * (1 + 1e-3)
+    assert abs(res.iters - ores.iters) <= max(2, math.ceil(0.01 * ores.iters))
+    x = host(res.x)
+    r_gpu = np.linalg.norm(b - orc.spmv(ref, x))
+    r_ref = np.linalg.norm(b - orc.spmv(ref, ores.x))
+    assert np.linalg.norm(x - ores.x) <= (r_gpu + r_ref) / lam_min * (1 + 1e-6)
+
+
+def test_config1_cg(orc):
+    spx = require_gpu()
+    prob, _, b = W.config1()
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    ores = orc.pcg(ref, b, 1e-8)
+    res = A.cg_solve(dev(b), rtol=1e-8)
+    print(f"config1 cg: gpu {res.iters} it relres {res.relres:.3e}; oracle {ores.iters} it", flush=True)
+    # lambda_min: identity rows give 1, interior lowest mode from the closed form
+    c = math.cos(math.pi / 63)
+    lam_min = min(1.0, (8 - 4 * c - 4 * c * c) / 3)
+    check_against_oracle(orc, ref, res, ores, b, 1e-8, lam_min)
+
+
+def test_cg_check_every_does_not_change_the_result(orc):
+    spx = require_gpu()
+    prob, _, b = W.config1()
+    A = assemble(spx, prob)
+    outs = [A.cg_solve(dev(b), rtol=1e-8, check_every=k) for k in (1, 7, 20, 1000)]
+    for o in outs[1:]:
+        assert o.iters == outs[0].iters
+        assert np.array_equal(bits(host(o.x)), bits(host(outs[0].x)))
+
+
+@pytest.mark.parametrize("N,dim", [(3, 2), (8, 2), (2, 3), (4, 3)])
+def test_cg_dense_lu(orc, N, dim):
+    spx = require_gpu()
+    rng = np.random.default_rng(40 + N)
+    prob = W.q1_poisson(N, dim, kappa=np.exp(rng.standard_normal(N**dim)))
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    D = np.zeros((prob.n, prob.n))
+    D[np.repeat(np.arange(prob.n), np.diff(ref.rowptr)), ref.col] = ref.val
+    b = rng.uniform(-1, 1, prob.n)
+    xs = np.linalg.solve(D, b)
+    res = A.cg_solve(dev(b), rtol=1e-14, maxit=10000)
+    assert res.status == 0
+    assert np.linalg.norm(host(res.x) - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_cg_eigenmode_converges_in_one_step():
+    spx = require_gpu()
+    N = 10
+    prob = W.q1_poisson(N, 2)
+    A = assemble(spx, prob)
+    M = N + 1
+    node = np.arange(prob.n)
+    v = np.sin(2 * math.pi * (node % M) / N) * np.sin(3 * math.pi * (node // M) / N)
+    cx, cy = math.cos(2 * math.pi / N), math.cos(3 * math.pi / N)
+    lam = (8 - 2 * cx - 2 * cy - 4 * cx * cy) / 3
+    res = A.cg_solve(dev(v), rtol=1e-12, maxit=50)
+    assert res.status == 0 and res.iters == 1
+    assert np.max(np.abs(host(res.x) - v / lam)) <= 1e-12 * np.max(np.abs(v / lam))
+
+
+def test_cg_status_codes():
+    spx = require_gpu()
+    # zero diagonal
+    A = spx.coo_preallocate(2, dev(np.array([0, 1, 1], np.int32)), dev(np.array([1, 0, 1], np.int32)))
+    A.set_values_coo(dev(np.array([1.0, 1.0, 2.0])))
+    assert A.cg_solve(dev(np.ones(2)), rtol=1e-8, maxit=10).status == spx.ZERO_DIAGONAL
+    # indefinite: breakdown
+    B = spx.coo_preallocate(2, dev(np.array([0, 1], np.int32)), dev(np.array([0, 1], np.int32)))
+    B.set_values_coo(dev(np.array([1.0, -1.0])))
+    assert B.cg_solve(dev(np.array([0.0, 1.0])), rtol=1e-8, maxit=10).status == spx.BREAKDOWN
+    # iteration limit
+    prob = W.q1_poisson(20, 2)
+    C = assemble(spx, prob)
+    b = np.random.default_rng(0).uniform(-1, 1, prob.n)
+    r = C.cg_solve(dev(b), rtol=1e-12, maxit=3)
+    assert r.status == spx.NOT_CONVERGED and r.iters == 3 and r.relres < 1.0
+    r = C.cg_solve(dev(b), rtol=1e-12, maxit=0)
+    assert r.status == spx.NOT_CONVERGED and r.iters == 0
+    # b = 0
+    r = C.cg_solve(dev(np.zeros(prob.n)), rtol=1e-8)
+    assert r.status == 0 and r.iters == 0 and np.all(host(r.x) == 0)
+    # nonzero initial guess is honoured
+    x0 = np.random.default_rng(1).uniform(-1, 1, prob.n)
+    r = C.cg_solve(dev(b), x=dev(x0), rtol=1e-10)
+    assert r.status == 0 and r.relres <= 1e-10 * 1.001
+
+
+def test_transpose_solve_of_symmetric_matrix_is_identical():
+    spx = require_gpu()
+    N = 12
+    prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(2).standard_normal(N**3)))
+    A = assemble(spx, prob)
+    b = dev(np.random.default_rng(3).uniform(-1, 1, prob.n))
+    r1 = A.cg_solve(b, rtol=1e-10)
+    r2 = A.cg_solve_transpose(b, rtol=1e-10)
+    assert r1.iters == r2.iters
+    assert np.array_equal(bits(host(r1.x)), bits(host(r2.x)))
+
+
+def test_mixed_precision_refinement(orc):
+    spx = require_gpu()
+    N = 16
+    rng = np.random.default_rng(1)
+    z = rng.standard_normal(N**3)
+    prob = W.q1_poisson(N, 3, kappa=np.exp(z))
+    b = rng.uniform(-1, 1, prob.n)
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    om = orc.pcg_mixed(ref, b, 1e-10, 1e-4)
+    o64 = orc.pcg(ref, b, 1e-12)
+    res = A.cg_solve_mixed(dev(b), rtol_outer=1e-10, rtol_inner=1e-4)
+    x = host(res.x)
+    err = np.linalg.norm(x - o64.x) / np.linalg.norm(o64.x)
+    print(f"mixed N={N}: gpu outer {res.outer} inner {res.inner} relres {res.relres:.3e}; "
+          f"oracle outer {om.outer} inner {om.inner}; error vs fp64 oracle {err:.3e}", flush=True)
+    assert res.status == 0 and res.relres <= 1e-10
+    assert np.linalg.norm(b - orc.spmv(ref, x)) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+    assert abs(res.outer - om.outer) <= 1
+    assert abs(res.inner - om.inner) <= max(3, 0.05 * om.inner)
+    assert err <= 1e-7
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("N", [127])
+def test_full_size_pipeline_sampled(orc, N):
+    """Full 128^3-node workload: bitwise assembly on sampled rows, SpMV on
+    sampled rows within 1e-12, CG to 1e-10 checked by an independent
+    residual, mixed precision to 1e-10."""
+    spx = require_gpu()
+    print(f"full-size Q1 3-D N={N}: generating", flush=True)
+    prob, x, b = W.config2(N)
+    A = assemble(spx, prob)
+    info = A.get_info()
+    assert info["nnz"] == (3 * (N + 1) - 2) ** 3 and info["nvalid"] == prob.ncoo
+    rng = np.random.default_rng(99)
+    rows = np.unique(np.concatenate([[0, 1, N, prob.n // 2, prob.n - 1],
+                                     rng.integers(0, prob.n, 3000)])).astype(np.int32)
+    ptr, scol, sval = orc.coo_rows(prob.n, prob.i, prob.j, prob.v, rows)
+    rowptr, col, val = (host(t) for t in A.get_csr())
+    for s, r in enumerate(rows):
+        a, e = rowptr[r], rowptr[r + 1]
+        assert np.array_equal(col[a:e], scol[ptr[s]:ptr[s + 1]])
+        assert np.array_equal(bits(val[a:e]), bits(sval[ptr[s]:ptr[s + 1]]))
+    print("sampled assembly rows bitwise equal", flush=True)
+    y = host(A.matmult(dev(x)))
+    yt = host(A.matmult_transpose(dev(x)))
+    for s, r in enumerate(rows):
+        c, v = scol[ptr[s]:ptr[s + 1]], sval[ptr[s]:ptr[s + 1]]
+        ref = 0.0
+        for cc, vv in zip(c, v):
+            ref += vv * x[cc]
+        scale = float(np.sum(np.abs(v) * np.abs(x[c])))
+        assert abs(y[r] - ref) <= 1e-12 * scale + 1e-300
+        assert abs(yt[r] - ref) <= 1e-12 * scale + 1e-300  # symmetric operator
+    print("sampled SpMV rows within 1e-12", flush=True)
+    res = A.cg_solve(dev(b), rtol=1e-10, check_every=20)
+    xs = host(res.x)
+    rel = residual_norm(prob, xs, b) / np.linalg.norm(b)
+    print(f"cg: {res.iters} iterations relres {res.relres:.3e} (independent {rel:.3e})", flush=True)
+    assert res.status == 0 and res.relres <= 1e-10 * 1.001 and rel <= 1e-10 * 1.01

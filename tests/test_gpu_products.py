@@ -1,0 +1,111 @@
+"""GPU products (MatMult, MatMultTranspose, SpMM, SDDMM, COO gather) against
+the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_08646_amd import workloads as W
+from gpu_util import assemble, bits, dev, host, require_gpu, spmv_within
+
+pytestmark = pytest.mark.gpu
+
+
+def test_config1_matmult(orc):
+    spx = require_gpu()
+    prob, x, _ = W.config1()
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    y = host(A.matmult(dev(x)))
+    spmv_within(y, orc.spmv(ref, x), orc.abs_spmv(ref, x))
+    yt = host(A.matmult_transpose(dev(x)))
+    spmv_within(yt, orc.spmv_transpose(ref, x), orc.abs_spmv_transpose(ref, x))
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+def test_matmult_every_lane_count(orc, lanes):
+    spx = require_gpu()
+    rng = np.random.default_rng(20 + lanes)
+    prob = W.random_coo(rng, 3001, 150000, extreme=False)
+    A = assemble(spx, prob)
+    A.set_option(spx.OPT_SPMV_LANES, lanes)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    x = rng.uniform(-1, 1, prob.n)
+    y = host(A.matmult(dev(x)))
+    spmv_within(y, orc.spmv(ref, x), orc.abs_spmv(ref, x))
+    yt = host(A.matmult_transpose(dev(x)))
+    spmv_within(yt, orc.spmv_transpose(ref, x), orc.abs_spmv_transpose(ref, x))
+    # the block order does not change any row's arithmetic
+    A.set_option(spx.OPT_XCD_REMAP, 0)
+    y2 = host(A.matmult(dev(x)))
+    assert np.array_equal(bits(y), bits(y2))
+
+
+def test_matmult_long_and_empty_rows(orc):
+    spx = require_gpu()
+    rng = np.random.default_rng(30)
+    n = 5000
+    # one very long row, many empty rows, a dense column
+    i = np.concatenate([np.zeros(40000, np.int32), rng.integers(0, n // 2, 20000).astype(np.int32),
+                        rng.integers(0, n, 3000).astype(np.int32)])
+    j = np.concatenate([rng.integers(0, n, 40000).astype(np.int32),
+                        rng.integers(0, n // 2, 20000).astype(np.int32), np.full(3000, 7, np.int32)])
+    v = rng.uniform(-1, 1, i.size)
+    prob = W.CooProblem(n=n, i=i, j=j, v=v)
+    A = assemble(spx, prob)
+    ref = orc.assemble(n, i, j, v)
+    x = rng.uniform(-1, 1, n)
+    spmv_within(host(A.matmult(dev(x))), orc.spmv(ref, x), orc.abs_spmv(ref, x))
+    spmv_within(host(A.matmult_transpose(dev(x))), orc.spmv_transpose(ref, x),
+                orc.abs_spmv_transpose(ref, x))
+
+
+def test_matmult_deterministic_and_transpose_identity(orc):
+    spx = require_gpu()
+    rng = np.random.default_rng(31)
+    prob = W.random_coo(rng, 20000, 400000, extreme=False)
+    A = assemble(spx, prob)
+    x, z = (dev(rng.uniform(-1, 1, prob.n)) for _ in range(2))
+    y0 = host(A.matmult(x))
+    for _ in range(5):
+        assert np.array_equal(bits(host(A.matmult(x))), bits(y0))
+    lhs = float(torch.dot(z, A.matmult(x)))
+    rhs = float(torch.dot(A.matmult_transpose(z), x))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs)) * 100
+
+
+def test_spmm_matches_oracle(orc):
+    spx = require_gpu()
+    prob, _, _ = W.config1()
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    for nrhs in (1, 3, 16, 40):
+        X = W.spmm_rhs(prob.n, nrhs)
+        Y = host(A.spmm(dev(X)))
+        Yr = orc.spmm(ref, X)
+        for c in range(nrhs):
+            spmv_within(Y[:, c], Yr[:, c], orc.abs_spmv(ref, X[:, c]))
+
+
+def test_sddmm_and_gather_bitwise(orc):
+    spx = require_gpu()
+    rng = np.random.default_rng(32)
+    prob = W.random_coo(rng, 3000, 60000, neg_frac=0.2, extreme=False)
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    lam, u = rng.uniform(-1, 1, (2, prob.n))
+    G = A.sddmm(dev(lam), dev(u))
+    assert np.array_equal(bits(host(G)), bits(orc.sddmm(ref, lam, u)))
+    gv = A.coo_gather(G)
+    assert np.array_equal(bits(host(gv)), bits(orc.coo_grad(prob.i, prob.j, lam, u)))
+
+
+def test_gather_blocks_bitwise(orc):
+    spx = require_gpu()
+    prob, theta, _, _ = W.config5(N=32)
+    A = assemble(spx, prob)
+    rng = np.random.default_rng(33)
+    lam, u = rng.uniform(-1, 1, (2, prob.n))
+    G = A.sddmm(dev(lam), dev(u))
+    ge = A.coo_gather_blocks(G, dev(prob.dv_dlogk), 16)
+    gv = orc.coo_grad(prob.i, prob.j, lam, u)
+    assert np.array_equal(bits(host(ge)), bits(orc.block_reduce(gv, prob.dv_dlogk, 16)))
