@@ -1,0 +1,322 @@
+#!/usr/bin/env python3
+"""Benchmark of the COO-assembly -> SpMV -> Jacobi-CG hot path on one MI355X.
+
+Workload (the full-size 3-D case): Q1 trilinear Poisson on 127^3 hexahedra
+(128^3 = 2,097,152 nodes), 64 FP64 COO triplets per element in element order
+(131,096,512 triplets, int32 indices) -> 55,742,968 CSR entries.  One step
+is one pass of the whole path over resident device inputs:
+
+  1. coo_preallocate (device sort -> CSR pattern + jmap/perm)
+  2. set_values_coo with the kappa = 1 values
+  3. 100 x MatMult and 100 x MatMultTranspose (x ~ U[-1,1], seed 0);
+     the first MatMultTranspose builds the explicit transpose
+  4. Jacobi-CG to ||r|| <= 1e-10 ||b|| (b ~ U[-1,1], seed 0)
+  5. set_values_coo with log-normal element diffusivity (sigma = 1, seed 1)
+  6. FP64 Jacobi-CG to 1e-10 and mixed FP32/FP64 refinement to 1e-10 on
+     that matrix (b ~ U[-1,1] from seed 1)
+
+The headline value is the SpMV rate: algorithmic bytes of one MatMult
+(values + column indices + row pointers + x + y) over the median event-timed
+MatMult kernel.  The roofline object is for the kernel that dominates the
+step's time, the fused SpMV + dot product of the CG iteration, timed with
+HIP events on the solver's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "SpMV HBM GB/s (% of peak); CG time to 1e-10 rel. resid, FP64 vs mixed"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmv_bytes(n: int, nnz: int, vbytes: int = 8) -> int:
+    """Algorithmic bytes of y = A x for CSR: values, int32 columns, int32
+    row pointers, x and y once each."""
+    return nnz * (vbytes + 4) + (n + 1) * 4 + 2 * n * vbytes
+
+
+def set_values_bytes(ncoo: int, nvalid: int, nnz: int) -> int:
+    """Algorithmic bytes of the numeric COO stage: v once, perm once, jmap
+    once, the values written once."""
+    return ncoo * 8 + nvalid * 4 + (nnz + 1) * 4 + nnz * 8
+
+
+def cg_iteration_bytes(n: int, nnz: int) -> int:
+    """SpMV + update (reads x p r q dinv, writes x r) + p update (reads r
+    dinv p, writes p), FP64."""
+    return spmv_bytes(n, nnz) + 7 * 8 * n + 4 * 8 * n
+
+
+def host_cpu():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(grid: int, calls: int):
+    """The oracle as it stands (plain C, one thread) on a bounded sample:
+    its own COO assembly of the same 3-D Q1 workload at grid^3 elements,
+    then `calls` SpMV calls, reported as SpMV GB/s with the same byte
+    count as the GPU figure."""
+    import numpy as np
+
+    import oracle
+    from paper_2406_08646_amd import workloads as W
+
+    prob, x, _ = W.config2(grid)
+    t0 = time.perf_counter()
+    A = oracle.assemble(prob.n, prob.i, prob.j, prob.v)
+    t_asm = time.perf_counter() - t0
+    times = []
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        oracle.spmv(A, x)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    gbs = spmv_bytes(A.n, A.nnz) / med / 1e9
+    model, ncpu = host_cpu()
+    return {
+        "value": round(gbs, 3),
+        "unit": "GB/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle (plain C, 1 thread, gcc -O2) COO assembly of the {grid}^3-element "
+                   f"3-D Q1 matrix (n={A.n}, ncoo={prob.ncoo}, nnz={A.nnz}) in {t_asm:.2f} s, "
+                   f"then median of {calls} SpMV calls = {med * 1e3:.2f} ms; host '{model}', "
+                   f"{ncpu} logical CPUs"),
+        "assembly_s": round(t_asm, 3),
+        "spmv_ms": round(med * 1e3, 3),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=127, help="elements per side (127 = full size)")
+    ap.add_argument("--spmv-calls", type=int, default=100)
+    ap.add_argument("--check-every", type=int, default=20)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per CSR row (0 = automatic)")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not bracket solver kernels with events (no roofline object)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-grid", type=int, default=63)
+    ap.add_argument("--cpu-calls", type=int, default=10)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md, 'How it would shard'). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2406_08646_amd import spx
+    from paper_2406_08646_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    spx.load_library()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    N = args.grid
+
+    log(f"generating the {N}^3-element workload")
+    prob, x_np, b_np = W.config2(N)
+    prob3, b3_np = W.config3(N)
+    n, ncoo = prob.n, prob.ncoo
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    i_d, j_d = d(prob.i), d(prob.j)
+    v2_d, v3_d = d(prob.v), d(prob3.v)
+    x_d, b2_d, b3_d = d(x_np), d(b_np), d(b3_np)
+    del prob3
+    y_d = torch.empty_like(x_d)
+    yt_d = torch.empty_like(x_d)
+    torch.cuda.synchronize()
+    log(f"inputs resident: n={n} ncoo={ncoo}")
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def run_step(profile: bool):
+        rec = {}
+        e = [ev() for _ in range(16)]
+        t0 = time.perf_counter()
+        e[0].record()
+        A = spx.coo_preallocate(n, i_d, j_d)
+        e[1].record()
+        A.set_values_coo(v2_d)
+        e[2].record()
+        if args.lanes:
+            A.set_option(spx.OPT_SPMV_LANES, args.lanes)
+        ms_mv, ms_mvt = [], []
+        for _ in range(args.spmv_calls):
+            s, t = ev(), ev()
+            s.record()
+            A.matmult(x_d, y_d)
+            t.record()
+            ms_mv.append((s, t))
+        e[3].record()
+        A.matmult_transpose(x_d, yt_d)  # builds the transpose
+        e[4].record()
+        for _ in range(args.spmv_calls):
+            s, t = ev(), ev()
+            s.record()
+            A.matmult_transpose(x_d, yt_d)
+            t.record()
+            ms_mvt.append((s, t))
+        e[5].record()
+        A.set_option(spx.OPT_PROFILE, 1 if profile else 0)
+        r2 = A.cg_solve(b2_d, rtol=1e-10, check_every=args.check_every)
+        e[6].record()
+        prof = A.get_profile()
+        A.set_option(spx.OPT_PROFILE, 0)
+        A.set_values_coo(v3_d)
+        e[7].record()
+        r3 = A.cg_solve(b3_d, rtol=1e-10, check_every=args.check_every)
+        e[8].record()
+        rm = A.cg_solve_mixed(b3_d, rtol_outer=1e-10, rtol_inner=1e-4,
+                              check_every=args.check_every)
+        e[9].record()
+        nnz = A.nnz
+        A.destroy()
+        torch.cuda.synchronize()
+        rec["wall_ms"] = (time.perf_counter() - t0) * 1e3
+        rec["preallocate_ms"] = e[0].elapsed_time(e[1])
+        rec["set_values_ms"] = e[1].elapsed_time(e[2])
+        rec["spmv_ms"] = [s.elapsed_time(t) for s, t in ms_mv]
+        rec["spmvt_ms"] = [s.elapsed_time(t) for s, t in ms_mvt]
+        rec["transpose_build_ms"] = e[3].elapsed_time(e[4])
+        rec["cg64_ms"] = e[5].elapsed_time(e[6])
+        rec["cg64"] = (r2.iters, r2.relres, r2.status)
+        rec["set_values2_ms"] = e[6].elapsed_time(e[7])
+        rec["cg64_ln_ms"] = e[7].elapsed_time(e[8])
+        rec["cg64_ln"] = (r3.iters, r3.relres, r3.status)
+        rec["mixed_ms"] = e[8].elapsed_time(e[9])
+        rec["mixed"] = (rm.outer, rm.inner, rm.relres, rm.status)
+        rec["profile"] = prof
+        rec["nnz"] = nnz
+        return rec
+
+    profile = not args.no_profile
+    for w in range(args.warmup):
+        r = run_step(profile)
+        log(f"warmup {w + 1}/{args.warmup}: {r['wall_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    recs = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        r = run_step(profile)
+        recs.append(r)
+        log(f"step {k + 1}/{args.steps}: {r['wall_ms']:.1f} ms; cg {r['cg64'][0]} it; "
+            f"lognormal fp64 {r['cg64_ln'][0]} it {r['cg64_ln_ms']:.1f} ms; mixed "
+            f"{r['mixed'][0]} outer/{r['mixed'][1]} inner {r['mixed_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+
+    nnz = recs[0]["nnz"]
+    mv_bytes = spmv_bytes(n, nnz)
+    mv = [t for r in recs for t in r["spmv_ms"]]
+    mvt = [t for r in recs for t in r["spmvt_ms"]]
+    mv_med = statistics.median(mv)
+    mvt_med = statistics.median(mvt)
+    gbs = mv_bytes / (mv_med * 1e-3) / 1e9
+    gbs_t = mv_bytes / (mvt_med * 1e-3) / 1e9
+    med = lambda key: statistics.median(r[key] for r in recs)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gbs, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_total * 1e3 / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"3-D Q1 trilinear Poisson, {N}^3 elements ({N + 1}^3 nodes), "
+                         f"{ncoo} FP64 COO triplets -> {nnz} CSR nnz (27-point rows); "
+                         f"{args.spmv_calls} MatMult + {args.spmv_calls} MatMultTranspose; "
+                         "Jacobi-CG to 1e-10; log-normal (sigma=1) values: FP64 CG vs "
+                         "FP32/FP64 refinement to 1e-10"),
+            "n": n, "ncoo": ncoo, "nnz": nnz,
+        },
+        "spmv": {
+            "median_ms": round(mv_med, 4), "mean_ms": round(statistics.fmean(mv), 4),
+            "bytes_per_call": mv_bytes, "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 2),
+            "transpose_median_ms": round(mvt_med, 4), "transpose_gbs": round(gbs_t, 2),
+            "transpose_build_ms": round(med("transpose_build_ms"), 3),
+        },
+        "assembly": {
+            "preallocate_ms": round(med("preallocate_ms"), 3),
+            "set_values_ms": round(med("set_values_ms"), 4),
+            "set_values_gbs": round(set_values_bytes(ncoo, ncoo, nnz)
+                                    / (med("set_values_ms") * 1e-3) / 1e9, 1),
+            "set_values_bytes": set_values_bytes(ncoo, ncoo, nnz),
+        },
+        "cg": {
+            "kappa1_fp64": {"ms": round(med("cg64_ms"), 2), "iters": recs[0]["cg64"][0],
+                            "relres": recs[0]["cg64"][1], "status": recs[0]["cg64"][2],
+                            "ms_per_iter": round(med("cg64_ms") / max(1, recs[0]["cg64"][0]), 4),
+                            "gbs_per_iter": round(cg_iteration_bytes(n, nnz) * recs[0]["cg64"][0]
+                                                  / (med("cg64_ms") * 1e-3) / 1e9, 1)},
+            "lognormal_fp64": {"ms": round(med("cg64_ln_ms"), 2), "iters": recs[0]["cg64_ln"][0],
+                               "relres": recs[0]["cg64_ln"][1], "status": recs[0]["cg64_ln"][2]},
+            "lognormal_mixed": {"ms": round(med("mixed_ms"), 2), "outer": recs[0]["mixed"][0],
+                                "inner": recs[0]["mixed"][1], "relres": recs[0]["mixed"][2],
+                                "status": recs[0]["mixed"][3]},
+            "mixed_speedup": round(med("cg64_ln_ms") / med("mixed_ms"), 3),
+        },
+    }
+    if profile:
+        tot_ms = sum(r["profile"]["spmv_dot_f64"][0] for r in recs)
+        cnt = sum(r["profile"]["spmv_dot_f64"][1] for r in recs)
+        avg_ms = tot_ms / max(1, cnt)
+        ach = mv_bytes / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_cg_spmv_dot (q = A p with the p.q partial, FP64)",
+            "bytes_per_launch": mv_bytes, "avg_launch_ms": round(avg_ms, 4), "launches": cnt,
+        }
+        out["solver_kernels_ms"] = {k: [round(sum(r["profile"][k][0] for r in recs) /
+                                               max(1, sum(r["profile"][k][1] for r in recs)), 4),
+                                        sum(r["profile"][k][1] for r in recs)]
+                                    for k in spx.PROFILE_KINDS[:3]}
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on the {args.cpu_grid}^3-element sample")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_grid, args.cpu_calls)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

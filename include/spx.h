@@ -205,10 +205,20 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
 
 /* Tuning knobs.  SPX_OPT_SPMV_LANES: lanes per row for products (0 = auto,
  * else 1..64, a power of two).  SPX_OPT_XCD_REMAP: 1 (default) to give each
- * XCD a contiguous range of rows, 0 for plain block order. */
-enum spx_option { SPX_OPT_SPMV_LANES = 1, SPX_OPT_XCD_REMAP = 2 };
+ * XCD a contiguous range of rows, 0 for plain block order.  SPX_OPT_PROFILE:
+ * 1 to bracket every solver-iteration kernel with HIP events on the
+ * solver's stream and accumulate their durations (read with
+ * spx_get_profile). */
+enum spx_option { SPX_OPT_SPMV_LANES = 1, SPX_OPT_XCD_REMAP = 2, SPX_OPT_PROFILE = 3 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);
+
+/* Accumulated event-timed durations (HOST outputs, milliseconds and launch
+ * count) of the solver kernels that did work since the last reset, by kind:
+ * 0 fp64 SpMV+dot (q = A p), 1 fp64 update (x, r, dots), 2 fp64 p update,
+ * 3..5 the same kernels of the fp32 inner solve. */
+int spx_get_profile(spx_handle h, int32_t kind, double* total_ms, int64_t* launches);
+int spx_reset_profile(spx_handle h);
 
 /* Thread-local message of the last failure ("" if none). */
 const char* spx_last_error(void);

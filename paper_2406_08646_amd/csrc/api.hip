@@ -72,6 +72,8 @@ extern "C" int spx_destroy(spx_handle h) {
   if (h->scal_host) (void)hipHostFree(h->scal_host);
   for (hipEvent_t& e : h->ev)
     if (e) (void)hipEventDestroy(e);
+  for (int64_t k = 0; k < h->prof_ev_n; ++k) (void)hipEventDestroy(h->prof_ev[k]);
+  delete[] h->prof_ev;
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
   return SPX_OK;
@@ -90,6 +92,9 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
     case SPX_OPT_XCD_REMAP:
       h->xcd_remap = value ? 1 : 0;
       return SPX_OK;
+    case SPX_OPT_PROFILE:
+      h->profile = value ? 1 : 0;
+      return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
   }
@@ -105,9 +110,30 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
     case SPX_OPT_XCD_REMAP:
       *value = h->xcd_remap;
       return SPX_OK;
+    case SPX_OPT_PROFILE:
+      *value = h->profile;
+      return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);
   }
+}
+
+extern "C" int spx_get_profile(spx_handle h, int32_t kind, double* total_ms, int64_t* launches) {
+  clear_error();
+  if (!h || kind < 0 || kind >= 6) return set_error(SPX_INVALID_ARG, "get_profile: bad argument");
+  if (total_ms) *total_ms = h->prof_ms[kind];
+  if (launches) *launches = h->prof_cnt[kind];
+  return SPX_OK;
+}
+
+extern "C" int spx_reset_profile(spx_handle h) {
+  clear_error();
+  if (!h) return set_error(SPX_INVALID_ARG, "reset_profile: NULL handle");
+  for (int k = 0; k < 6; ++k) {
+    h->prof_ms[k] = 0.0;
+    h->prof_cnt[k] = 0;
+  }
+  return SPX_OK;
 }
 
 extern "C" const char* spx_last_error(void) { return g_last_error; }

@@ -414,23 +414,62 @@ inline unsigned grid1(int64_t count) {
   return (unsigned)std::max<int64_t>(1, ceil_div(count, 256));
 }
 
-// Enqueues `count` CG iterations (K1, K2, K3) on the given operator.
+// Enqueues `count` CG iterations (K1, K2, K3) on the given operator.  With
+// `evs` (6 events per iteration) every kernel is bracketed by events.
 template <typename VT>
 int enqueue_iterations(int L, int64_t n, const int32_t* rowptr, const int32_t* col, const VT* val,
                        VT* x, VT* r, VT* p, VT* q, const VT* dinv, CgScalars* st,
-                       double* partials, int remap, int64_t count, hipStream_t s) {
+                       double* partials, int remap, int64_t count, hipStream_t s,
+                       hipEvent_t* evs) {
   const unsigned nb = (unsigned)fused_blocks();
   return with_lanes(L, [&](auto Lc) {
     constexpr int LL = decltype(Lc)::value;
     for (int64_t k = 0; k < count; ++k) {
+      hipEvent_t* e = evs ? evs + 6 * k : nullptr;
+      if (e) (void)hipEventRecord(e[0], s);
       hipLaunchKernelGGL((k_cg_spmv_dot<LL, VT>), dim3(nb), dim3(kBlock), 0, s, n, rowptr, col, val,
                          p, q, st, partials, remap);
+      if (e) (void)hipEventRecord(e[1], s);
+      if (e) (void)hipEventRecord(e[2], s);
       hipLaunchKernelGGL((k_cg_update<VT>), dim3(nb), dim3(kBlock), 0, s, n, x, r, p, q, dinv, st,
                          partials);
+      if (e) (void)hipEventRecord(e[3], s);
+      if (e) (void)hipEventRecord(e[4], s);
       hipLaunchKernelGGL((k_cg_pupdate<VT>), dim3(nb), dim3(kBlock), 0, s, n, p, r, dinv, st);
+      if (e) (void)hipEventRecord(e[5], s);
     }
     return SPX_OK;
   });
+}
+
+int ensure_prof_events(spx_matrix* h, int64_t need) {
+  if (h->prof_ev_n >= need) return SPX_OK;
+  hipEvent_t* ev = new hipEvent_t[need];
+  for (int64_t k = 0; k < h->prof_ev_n; ++k) ev[k] = h->prof_ev[k];
+  for (int64_t k = h->prof_ev_n; k < need; ++k) SPX_CHECK_HIP(hipEventCreate(&ev[k]));
+  delete[] h->prof_ev;
+  h->prof_ev = ev;
+  h->prof_ev_n = need;
+  return SPX_OK;
+}
+
+// Adds the event-timed durations of iterations [first, first+count) of a
+// finished chunk, counting only launches that did work (iterations up to
+// `iters`; the p update of the last iteration is skipped by the kernel).
+void accumulate_profile(spx_matrix* h, hipEvent_t* evs, int64_t first, int64_t count,
+                        int64_t iters, int kind0) {
+  for (int64_t k = 0; k < count; ++k) {
+    const int64_t it = first + k + 1;
+    for (int j = 0; j < 3; ++j) {
+      const bool ran = (j < 2) ? it <= iters : it < iters;
+      if (!ran) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, evs[6 * k + 2 * j], evs[6 * k + 2 * j + 1]) == hipSuccess) {
+        h->prof_ms[kind0 + j] += ms;
+        h->prof_cnt[kind0 + j] += 1;
+      }
+    }
+  }
 }
 
 // Runs iterations until the device flag is set, keeping one chunk of
@@ -442,14 +481,27 @@ int run_until_done(spx_matrix* h, int L, int64_t n, const int32_t* rowptr, const
                    int64_t maxit, int32_t check_every, hipStream_t s, CgScalars* final) {
   int64_t launched = 0;
   CgScalars* host = h->scal_host;
+  const bool prof = h->profile != 0;
+  const int kind0 = sizeof(VT) == 8 ? 0 : 3;
+  if (prof) SPX_TRY(ensure_prof_events(h, 2 * 6 * (int64_t)check_every));
+  int64_t first[2] = {0, 0}, cnt[2] = {0, 0};
   auto chunk = [&](int slot) -> int {
     const int64_t m = std::min<int64_t>(check_every, maxit - launched);
+    hipEvent_t* evs = prof ? h->prof_ev + slot * 6 * (int64_t)check_every : nullptr;
     SPX_TRY(enqueue_iterations<VT>(L, n, rowptr, col, val, x, r, p, q, dinv, st, h->partials,
-                                   h->xcd_remap, m, s));
+                                   h->xcd_remap, m, s, evs));
+    first[slot] = launched;
+    cnt[slot] = m;
     launched += m;
     SPX_CHECK_HIP(hipMemcpyAsync(&host[slot], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     SPX_CHECK_HIP(hipEventRecord(h->ev[slot], s));
     return SPX_OK;
+  };
+  auto harvest = [&](int slot, int64_t iters) {
+    if (prof && cnt[slot] > 0)
+      accumulate_profile(h, h->prof_ev + slot * 6 * (int64_t)check_every, first[slot], cnt[slot],
+                         iters, kind0);
+    cnt[slot] = 0;
   };
   // state before any iteration (init may already have converged)
   SPX_CHECK_HIP(hipMemcpyAsync(&host[0], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
@@ -468,9 +520,12 @@ int run_until_done(spx_matrix* h, int L, int64_t n, const int32_t* rowptr, const
       *final = host[cur];
       break;
     }
+    harvest(cur, host[cur].iters);
     cur ^= 1;
   }
   SPX_CHECK_HIP(hipStreamSynchronize(s));
+  harvest(0, final->iters);
+  harvest(1, final->iters);
   return SPX_OK;
 }
 

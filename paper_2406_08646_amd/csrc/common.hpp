@@ -110,6 +110,12 @@ struct spx_matrix {
   int64_t partial_cap = 0;
   int lanes_opt = 0;  // 0 = auto
   int xcd_remap = 1;
+  // optional per-kernel timing of solver iterations (HIP events)
+  int profile = 0;
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_cnt[6] = {0, 0, 0, 0, 0, 0};
+  hipEvent_t* prof_ev = nullptr;
+  int64_t prof_ev_n = 0;
 };
 
 namespace spx {

@@ -38,6 +38,9 @@ INSERT_VALUES = 0
 ADD_VALUES = 1
 OPT_SPMV_LANES = 1
 OPT_XCD_REMAP = 2
+OPT_PROFILE = 3
+PROFILE_KINDS = ("spmv_dot_f64", "update_f64", "pupdate_f64", "spmv_dot_f32", "update_f32",
+                 "pupdate_f32")
 
 # hard failures raise; solver outcomes are returned as a status
 _SOLVER_OUTCOMES = (OK, NOT_CONVERGED, BREAKDOWN, ZERO_DIAGONAL)
@@ -71,6 +74,8 @@ _SIGNATURES = {
     "spx_get_coo_maps": [_vp, _vp, _vp, _vp],
     "spx_set_option": [_vp, _i32, _i64],
     "spx_get_option": [_vp, _i32, _pi64],
+    "spx_get_profile": [_vp, _i32, _pd, _pi64],
+    "spx_reset_profile": [_vp],
     "spx_last_error": [],
     "spx_version": [],
 }
@@ -297,6 +302,18 @@ class Matrix:
         v = ctypes.c_int64()
         _check(load_library().spx_get_option(self.handle, option, ctypes.byref(v)))
         return v.value
+
+    def get_profile(self) -> dict:
+        out = {}
+        for k, name in enumerate(PROFILE_KINDS):
+            ms, cnt = ctypes.c_double(), ctypes.c_int64()
+            _check(load_library().spx_get_profile(self.handle, k, ctypes.byref(ms),
+                                                  ctypes.byref(cnt)))
+            out[name] = (ms.value, cnt.value)
+        return out
+
+    def reset_profile(self) -> None:
+        _check(load_library().spx_reset_profile(self.handle))
 
 
 def coo_preallocate(n: int, i: torch.Tensor, j: torch.Tensor, stream=None) -> Matrix:
