@@ -203,13 +203,29 @@ int spx_get_csr(spx_handle h, int32_t transpose, int32_t* rowptr, int32_t* col, 
  * perm[nvalid] (either may be NULL).  Asynchronous. */
 int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
 
-/* Tuning knobs.  SPX_OPT_SPMV_LANES: lanes per row for products (0 = auto,
- * else 1..64, a power of two).  SPX_OPT_XCD_REMAP: 1 (default) to give each
- * XCD a contiguous range of rows, 0 for plain block order.  SPX_OPT_PROFILE:
- * 1 to bracket every solver-iteration kernel with HIP events on the
- * solver's stream and accumulate their durations (read with
- * spx_get_profile). */
-enum spx_option { SPX_OPT_SPMV_LANES = 1, SPX_OPT_XCD_REMAP = 2, SPX_OPT_PROFILE = 3 };
+/* Tuning knobs (per handle; defaults chosen from the pattern).
+ *   SPX_OPT_SPMV_LANES: lanes per row of the "vector" row walk (0 = auto,
+ *     else a power of two <= 64).
+ *   SPX_OPT_XCD_REMAP: 1 (default) gives each of the 8 XCDs a contiguous
+ *     range of rows, 0 keeps plain workgroup order.
+ *   SPX_OPT_PROFILE: 1 brackets every solver-iteration kernel with HIP
+ *     events on the solver's stream and accumulates their durations (read
+ *     with spx_get_profile).
+ *   SPX_OPT_SPMV_VARIANT: 0 auto, 1 vector (L lanes per row), 2 stream
+ *     (rows of a workgroup streamed through LDS).
+ *   SPX_OPT_ROWS_PER_BLOCK: stream variant rows per workgroup (0 auto, else
+ *     32, 64, 128 or 256).
+ *   SPX_OPT_NONTEMPORAL: 1 loads matrix values/columns non-temporally.
+ *   SPX_OPT_SOLVER_BLOCKS: workgroups of the solver kernels (0 auto). */
+enum spx_option {
+  SPX_OPT_SPMV_LANES = 1,
+  SPX_OPT_XCD_REMAP = 2,
+  SPX_OPT_PROFILE = 3,
+  SPX_OPT_SPMV_VARIANT = 4,
+  SPX_OPT_ROWS_PER_BLOCK = 5,
+  SPX_OPT_NONTEMPORAL = 6,
+  SPX_OPT_SOLVER_BLOCKS = 7
+};
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);
 

@@ -95,6 +95,26 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
     case SPX_OPT_PROFILE:
       h->profile = value ? 1 : 0;
       return SPX_OK;
+    case SPX_OPT_SPMV_VARIANT:
+      if (value < 0 || value > 2)
+        return set_error(SPX_INVALID_ARG, "set_option: variant %lld not in 0..2", (long long)value);
+      h->variant_opt = (int)value;
+      return SPX_OK;
+    case SPX_OPT_ROWS_PER_BLOCK:
+      if (value != 0 && value != 32 && value != 64 && value != 128 && value != 256)
+        return set_error(SPX_INVALID_ARG, "set_option: rows per block %lld not 0/32/64/128/256",
+                         (long long)value);
+      h->rows_opt = (int)value;
+      return SPX_OK;
+    case SPX_OPT_NONTEMPORAL:
+      h->nt_opt = value ? 1 : 0;
+      return SPX_OK;
+    case SPX_OPT_SOLVER_BLOCKS:
+      if (value < 0 || value > (1 << 20))
+        return set_error(SPX_INVALID_ARG, "set_option: solver blocks %lld out of range",
+                         (long long)value);
+      h->fused_opt = (int)value;
+      return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
   }
@@ -105,13 +125,25 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
   if (!h || !value) return set_error(SPX_INVALID_ARG, "get_option: NULL argument");
   switch (option) {
     case SPX_OPT_SPMV_LANES:
-      *value = h->lanes_opt ? h->lanes_opt : pick_lanes(h->A, 0);
+      *value = spmv_shape(h, h->A).lanes;
       return SPX_OK;
     case SPX_OPT_XCD_REMAP:
       *value = h->xcd_remap;
       return SPX_OK;
     case SPX_OPT_PROFILE:
       *value = h->profile;
+      return SPX_OK;
+    case SPX_OPT_SPMV_VARIANT:
+      *value = spmv_shape(h, h->A).variant;
+      return SPX_OK;
+    case SPX_OPT_ROWS_PER_BLOCK:
+      *value = spmv_shape(h, h->A).rows;
+      return SPX_OK;
+    case SPX_OPT_NONTEMPORAL:
+      *value = h->nt_opt;
+      return SPX_OK;
+    case SPX_OPT_SOLVER_BLOCKS:
+      *value = fused_blocks(h);
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

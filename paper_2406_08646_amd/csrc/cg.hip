@@ -1,24 +1,29 @@
 // Jacobi-preconditioned CG with device-resident scalars (paper Sec. 6, the
 // CG -> CGAsync redesign): every scalar (rho, alpha, beta, the residual
-// norm, the convergence flag) lives in device memory and is produced by the
-// last workgroup of the kernel that reduces it, so the host only enqueues
-// kernels and polls the flag every `check_every` iterations.
+// norm, the convergence flag) lives in device memory, so the host only
+// enqueues kernels and polls the flag every `check_every` iterations.
 //
-// One iteration is three kernels, each fused around its memory traffic:
-//   K1  q = A p and the partial p.q; the last workgroup forms alpha
-//   K2  x += alpha p, r -= alpha q, z = D^-1 r, partial r.z and r.r; the last
-//       workgroup counts the iteration, tests ||r|| <= rtol ||b|| and forms
-//       beta
-//   K3  p = D^-1 r + beta p
-// Kernels return at once when the flag is set, so work queued past
-// convergence costs only the launches.  Dot products are reduced in a fixed
-// order (lanes, waves, workgroups by index), so results are reproducible.
+// One iteration k is three kernels, each fused around its memory traffic:
+//   K1  q = A p; per-workgroup partials of p.q
+//   K2  every workgroup adds the p.q partials (same fixed order, same
+//       result everywhere), alpha = rho_{k-1} / p.q; x += alpha p,
+//       r -= alpha q, z = D^-1 r; partials of r.z and r.r
+//   K3  every workgroup adds those partials: rho_k, ||r_k||; the test
+//       ||r_k|| <= rtol ||b|| or k = maxit stops the run (workgroup 0 records
+//       it); otherwise beta = rho_k / rho_{k-1} and p = D^-1 r + beta p
+// Cross-workgroup results travel only through kernel boundaries: a
+// workgroup never waits for another inside a kernel, and no agent-scope
+// fence is issued (on gfx950 such a fence writes back the XCD's L2).  The
+// kernels return at once when the flag is set, so work queued past
+// convergence costs only the launches.  All sums use a fixed order, so runs
+// are reproducible.
 //
 // The same kernels, instantiated for float, run the inner solve of the
 // mixed-precision refinement (paper Sec. 2 multiprecision plan): fp32
 // matrix copy, vectors and SpMV; fp64 products and sums in every dot.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "device.hpp"
@@ -29,6 +34,7 @@ namespace spx {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kLds = kBlock / 64 + 1;
 
 struct Range {
   int64_t lo, hi;
@@ -41,6 +47,60 @@ __device__ __forceinline__ Range block_range(int64_t total, int64_t b, int64_t n
   int64_t hi = lo + per;
   if (hi > total) hi = total;
   return {lo, hi};
+}
+
+// Sum of nparts partials; every workgroup gets the same value (fixed
+// strided split, fixed tree).
+__device__ __forceinline__ double reduce_all(const double* parts, int64_t nparts, double* lds) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += kBlock) s += parts[i];
+  s = block_sum<kBlock>(s, lds);
+  if (threadIdx.x == 0) lds[kLds - 1] = s;
+  __syncthreads();
+  s = lds[kLds - 1];
+  __syncthreads();
+  return s;
+}
+
+template <int V, int L, bool NT>
+struct Shape {
+  static constexpr int variant = V;
+  static constexpr int lanes = L;
+  static constexpr bool nt = NT;
+};
+
+// Calls epi(row, value) on the thread that owns each row of this
+// workgroup's share, value = sum_t val[t] x[col[t]] over the row.
+template <class SH, typename VT, typename XT, typename ACC, typename Epi>
+__device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ col,
+                                         const VT* __restrict__ val, const XT* __restrict__ x,
+                                         int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi) {
+  if constexpr (SH::variant == kVariantStream) {
+    const Range rg = block_range(ceil_div(n, rows), lb, nb);
+    for (int64_t rb = rg.lo; rb < rg.hi; ++rb) {
+      const int64_t r0 = rb * rows;
+      const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+      const ACC s = stream_rows<kBlock, 8, VT, XT, ACC, SH::nt>(rowptr, col, val, x, r0, r1, prod);
+      if (threadIdx.x < r1 - r0) epi(r0 + threadIdx.x, s);
+    }
+  } else {
+    constexpr int L = SH::lanes;
+    constexpr int RPB = kBlock / L;
+    const Range rg = block_range(ceil_div(n, RPB), lb, nb);
+    const int lane = threadIdx.x % L;
+    for (int64_t g = rg.lo; g < rg.hi; ++g) {
+      const int64_t row = g * RPB + threadIdx.x / L;
+      if (row < n) {
+        const ACC s = group_sum<L>(row_partial<L, VT, XT, ACC, SH::nt>(rowptr, col, val, x, row, lane));
+        if (lane == 0) epi(row, s);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int64_t logical_block(int remap) {
+  return remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
 }
 
 __global__ void k_scal_reset(CgScalars* st, int32_t maxit) {
@@ -61,134 +121,122 @@ __global__ void k_dinv(int64_t n, const double* __restrict__ val, const int32_t*
   const double d = t >= 0 ? val[t] : 0.0;
   double inv = 0.0;
   if (d == 0.0)
-    __hip_atomic_store(&st->status, (int32_t)SPX_ZERO_DIAGONAL, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    st->status = SPX_ZERO_DIAGONAL;
   else
     inv = 1.0 / d;
   dinv[r] = inv;
   if (dinv32) dinv32[r] = (float)inv;
 }
 
-// r = b - A x, z = D^-1 r, p = z, and the dots r.z, r.r, b.b.
-template <int L>
+// r = b - A x, z = D^-1 r, p = z; partials of r.z, r.r, b.b.
+template <class SH>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ col,
                                                     const double* __restrict__ val,
                                                     const double* __restrict__ b,
                                                     const double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
-                                                    const double* __restrict__ dinv, CgScalars* st,
-                                                    double* __restrict__ partials, double rtol,
-                                                    int remap) {
-  __shared__ double lds[kBlock / 64];
-  constexpr int RPB = kBlock / L;
+                                                    const double* __restrict__ dinv,
+                                                    double* __restrict__ P, int rows, int remap) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[kLds];
   const int64_t nb = gridDim.x;
-  const int64_t bl = remap ? xcd_logical_block(blockIdx.x, nb) : (int64_t)blockIdx.x;
-  const Range rg = block_range(ceil_div(n, RPB), bl, nb);
-  const int lane = threadIdx.x % L;
   double rz = 0.0, rr = 0.0, bb = 0.0;
-  for (int64_t g = rg.lo; g < rg.hi; ++g) {
-    const int64_t row = g * RPB + threadIdx.x / L;
-    if (row < n) {
-      const double ax = group_sum<L>(row_partial<L, double, double, double>(rowptr, col, val, x, row, lane));
-      if (lane == 0) {
-        const double bi = b[row];
-        const double ri = bi - ax;
-        const double zi = dinv[row] * ri;
-        r[row] = ri;
-        p[row] = zi;
-        rz += ri * zi;
-        rr += ri * ri;
-        bb += bi * bi;
-      }
-    }
-  }
+  for_rows<SH, double, double, double>(n, rowptr, col, val, x, rows, logical_block(remap), nb,
+                                       reinterpret_cast<double*>(smem), [&](int64_t row, double ax) {
+                                         const double bi = b[row];
+                                         const double ri = bi - ax;
+                                         const double zi = dinv[row] * ri;
+                                         r[row] = ri;
+                                         p[row] = zi;
+                                         rz += ri * zi;
+                                         rr += ri * ri;
+                                         bb += bi * bi;
+                                       });
   rz = block_sum<kBlock>(rz, lds);
   rr = block_sum<kBlock>(rr, lds);
   bb = block_sum<kBlock>(bb, lds);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = rz;
-    partials[nb + blockIdx.x] = rr;
-    partials[2 * nb + blockIdx.x] = bb;
+    P[blockIdx.x] = rz;
+    P[nb + blockIdx.x] = rr;
+    P[2 * nb + blockIdx.x] = bb;
   }
-  if (arrive_last(&st->ticket[0])) {
-    const double trz = reduce_partials<kBlock>(partials, nb, lds);
-    const double trr = reduce_partials<kBlock>(partials + nb, nb, lds);
-    const double tbb = reduce_partials<kBlock>(partials + 2 * nb, nb, lds);
-    if (threadIdx.x == 0) {
-      st->bb = tbb;
-      st->bnorm = sqrt(tbb);
-      st->thresh = rtol * st->bnorm;
-      st->rr = trr;
-      st->rho = trz;
-      st->iters = 0;
-      if (st->status != SPX_OK) {
-        st->done = 1;
-      } else if (sqrt(trr) <= st->thresh) {
-        st->done = 1;
-      } else if (st->maxit <= 0) {
-        st->done = 1;
-        st->status = SPX_NOT_CONVERGED;
-      } else {
-        st->done = 0;
-      }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgScalars* st, const double* P,
+                                                           int64_t G, double rtol) {
+  __shared__ double lds[kLds];
+  const double rz = reduce_all(P, G, lds);
+  const double rr = reduce_all(P + G, G, lds);
+  const double bb = reduce_all(P + 2 * G, G, lds);
+  if (threadIdx.x == 0) {
+    st->rho[0] = rz;
+    st->bb = bb;
+    st->bnorm = sqrt(bb);
+    st->thresh = rtol * st->bnorm;
+    st->rr = rr;
+    st->iters = 0;
+    if (st->status != SPX_OK) {
+      st->done = 1;
+    } else if (sqrt(rr) <= st->thresh) {
+      st->done = 1;
+    } else if (st->maxit <= 0) {
+      st->done = 1;
+      st->status = SPX_NOT_CONVERGED;
+    } else {
+      st->done = 0;
     }
   }
 }
 
-// K1: q = A p, alpha = rho / p.q
-template <int L, typename VT>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv_dot(int64_t n, const int32_t* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ col,
-                                                        const VT* __restrict__ val,
-                                                        const VT* __restrict__ p,
-                                                        VT* __restrict__ q, CgScalars* st,
-                                                        double* __restrict__ partials, int remap) {
-  __shared__ double lds[kBlock / 64];
+// K1: q = A p; partials of p.q
+template <class SH, typename VT>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const VT* __restrict__ val,
+                                                    const VT* __restrict__ p, VT* __restrict__ q,
+                                                    const CgScalars* __restrict__ st,
+                                                    double* __restrict__ P1, int rows, int remap) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[kLds];
   if (st->done) return;
-  constexpr int RPB = kBlock / L;
-  const int64_t nb = gridDim.x;
-  const int64_t bl = remap ? xcd_logical_block(blockIdx.x, nb) : (int64_t)blockIdx.x;
-  const Range rg = block_range(ceil_div(n, RPB), bl, nb);
-  const int lane = threadIdx.x % L;
   double dot = 0.0;
-  for (int64_t g = rg.lo; g < rg.hi; ++g) {
-    const int64_t row = g * RPB + threadIdx.x / L;
-    if (row < n) {
-      const VT s = group_sum<L>(row_partial<L, VT, VT, VT>(rowptr, col, val, p, row, lane));
-      if (lane == 0) {
-        q[row] = s;
-        dot += (double)p[row] * (double)s;
-      }
-    }
-  }
+  for_rows<SH, VT, VT, VT>(n, rowptr, col, val, p, rows, logical_block(remap), gridDim.x,
+                           reinterpret_cast<VT*>(smem), [&](int64_t row, VT s) {
+                             q[row] = s;
+                             dot += (double)p[row] * (double)s;
+                           });
   dot = block_sum<kBlock>(dot, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = dot;
-  if (arrive_last(&st->ticket[1])) {
-    const double pq = reduce_partials<kBlock>(partials, nb, lds);
-    if (threadIdx.x == 0) {
-      st->pq = pq;
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        st->status = SPX_BREAKDOWN;
-        st->done = 1;
-      } else {
-        st->alpha = st->rho / pq;
-      }
-    }
-  }
+  if (threadIdx.x == 0) P1[blockIdx.x] = dot;
 }
 
-// K2: x += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r; convergence; beta
+// K2: alpha = rho_{k-1} / p.q; x += alpha p; r -= alpha q; partials of r.z, r.r
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, VT* __restrict__ x,
                                                       VT* __restrict__ r,
                                                       const VT* __restrict__ p,
                                                       const VT* __restrict__ q,
                                                       const VT* __restrict__ dinv, CgScalars* st,
-                                                      double* __restrict__ partials) {
-  __shared__ double lds[kBlock / 64];
+                                                      const double* __restrict__ P1, int64_t G1,
+                                                      double* __restrict__ P2, int64_t k) {
+  __shared__ double lds[kLds];
   if (st->done) return;
-  const VT a = (VT)st->alpha;
+  const double pq = reduce_all(P1, G1, lds);
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->pq = pq;
+      st->status = SPX_BREAKDOWN;
+      st->iters = (int32_t)(k - 1);
+      st->done = 1;
+    }
+    return;
+  }
+  const double alpha = st->rho[(k - 1) & 1] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->pq = pq;
+    st->alpha = alpha;
+  }
+  const VT a = (VT)alpha;
   const int64_t nb = gridDim.x;
   const Range rg = block_range(n, blockIdx.x, nb);
   double rz = 0.0, rr = 0.0;
@@ -204,155 +252,147 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, VT* __restrict_
   rz = block_sum<kBlock>(rz, lds);
   rr = block_sum<kBlock>(rr, lds);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = rz;
-    partials[nb + blockIdx.x] = rr;
-  }
-  if (arrive_last(&st->ticket[2])) {
-    const double trz = reduce_partials<kBlock>(partials, nb, lds);
-    const double trr = reduce_partials<kBlock>(partials + nb, nb, lds);
-    if (threadIdx.x == 0) {
-      const int32_t it = st->iters + 1;
-      st->iters = it;
-      st->rr = trr;
-      if (sqrt(trr) <= st->thresh) {
-        st->done = 1;
-        st->status = SPX_OK;
-      } else if (it >= st->maxit) {
-        st->done = 1;
-        st->status = SPX_NOT_CONVERGED;
-      } else {
-        st->beta = trz / st->rho;
-        st->rho = trz;
-      }
-    }
+    P2[blockIdx.x] = rz;
+    P2[nb + blockIdx.x] = rr;
   }
 }
 
-// K3: p = D^-1 r + beta p
+// K3: rho_k, ||r_k||, stopping test; beta; p = D^-1 r + beta p
 template <typename VT>
 __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, VT* __restrict__ p,
                                                        const VT* __restrict__ r,
-                                                       const VT* __restrict__ dinv,
-                                                       const CgScalars* st) {
+                                                       const VT* __restrict__ dinv, CgScalars* st,
+                                                       const double* __restrict__ P2, int64_t G2,
+                                                       int64_t k) {
+  __shared__ double lds[kLds];
   if (st->done) return;
-  const VT bt = (VT)st->beta;
+  const double rz = reduce_all(P2, G2, lds);
+  const double rr = reduce_all(P2 + G2, G2, lds);
+  const bool conv = sqrt(rr) <= st->thresh;
+  const bool stop = conv || k >= st->maxit;
+  const double rho_prev = st->rho[(k - 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rr = rr;
+    st->iters = (int32_t)k;
+    if (conv) {
+      st->status = SPX_OK;
+      st->done = 1;
+    } else if (stop) {
+      st->status = SPX_NOT_CONVERGED;
+      st->done = 1;
+    } else {
+      st->rho[k & 1] = rz;
+      st->beta = rz / rho_prev;
+    }
+  }
+  if (stop) return;
+  const VT bt = (VT)(rz / rho_prev);
   const Range rg = block_range(n, blockIdx.x, gridDim.x);
   for (int64_t i = rg.lo + threadIdx.x; i < rg.hi; i += kBlock) p[i] = dinv[i] * r[i] + bt * p[i];
 }
 
-// ||b - A x||^2 into st->rr_true
-template <int L>
+// partials of ||b - A x||^2
+template <class SH>
 __global__ __launch_bounds__(kBlock) void k_resnorm(int64_t n, const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ col,
                                                     const double* __restrict__ val,
                                                     const double* __restrict__ b,
-                                                    const double* __restrict__ x, CgScalars* st,
-                                                    double* __restrict__ partials, int remap) {
-  __shared__ double lds[kBlock / 64];
-  constexpr int RPB = kBlock / L;
-  const int64_t nb = gridDim.x;
-  const int64_t bl = remap ? xcd_logical_block(blockIdx.x, nb) : (int64_t)blockIdx.x;
-  const Range rg = block_range(ceil_div(n, RPB), bl, nb);
-  const int lane = threadIdx.x % L;
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ P, int rows, int remap) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[kLds];
   double rr = 0.0;
-  for (int64_t g = rg.lo; g < rg.hi; ++g) {
-    const int64_t row = g * RPB + threadIdx.x / L;
-    if (row < n) {
-      const double ax = group_sum<L>(row_partial<L, double, double, double>(rowptr, col, val, x, row, lane));
-      if (lane == 0) {
-        const double ri = b[row] - ax;
-        rr += ri * ri;
-      }
-    }
-  }
+  for_rows<SH, double, double, double>(n, rowptr, col, val, x, rows, logical_block(remap), gridDim.x,
+                                       reinterpret_cast<double*>(smem), [&](int64_t row, double ax) {
+                                         const double ri = b[row] - ax;
+                                         rr += ri * ri;
+                                       });
   rr = block_sum<kBlock>(rr, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = rr;
-  if (arrive_last(&st->ticket[3])) {
-    const double t = reduce_partials<kBlock>(partials, nb, lds);
-    if (threadIdx.x == 0) st->rr_true = t;
-  }
+  if (threadIdx.x == 0) P[blockIdx.x] = rr;
+}
+
+__global__ __launch_bounds__(kBlock) void k_resnorm_finish(CgScalars* st, const double* P,
+                                                           int64_t G) {
+  __shared__ double lds[kLds];
+  const double rr = reduce_all(P, G, lds);
+  if (threadIdx.x == 0) st->rr_true = rr;
 }
 
 // ---------------------------------------------------- mixed precision
 
-// ||b||^2 -> outer scalars and the outer threshold
 __global__ __launch_bounds__(kBlock) void k_norm2(int64_t n, const double* __restrict__ b,
-                                                  CgScalars* st, double* __restrict__ partials,
-                                                  double rtol) {
-  __shared__ double lds[kBlock / 64];
-  const int64_t nb = gridDim.x;
-  const Range rg = block_range(n, blockIdx.x, nb);
+                                                  double* __restrict__ P) {
+  __shared__ double lds[kLds];
+  const Range rg = block_range(n, blockIdx.x, gridDim.x);
   double s = 0.0;
   for (int64_t i = rg.lo + threadIdx.x; i < rg.hi; i += kBlock) s += b[i] * b[i];
   s = block_sum<kBlock>(s, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (arrive_last(&st->ticket[0])) {
-    const double t = reduce_partials<kBlock>(partials, nb, lds);
-    if (threadIdx.x == 0) {
-      st->bb = t;
-      st->bnorm = sqrt(t);
-      st->thresh = rtol * st->bnorm;
-    }
+  if (threadIdx.x == 0) P[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm2_finish(CgScalars* st, const double* P, int64_t G,
+                                                         double rtol) {
+  __shared__ double lds[kLds];
+  const double bb = reduce_all(P, G, lds);
+  if (threadIdx.x == 0) {
+    st->bb = bb;
+    st->bnorm = sqrt(bb);
+    st->thresh = rtol * st->bnorm;
   }
 }
 
 // Outer fp64 residual r = b - A x with its norm, rounded to fp32, and the
-// start of the inner solve: d = 0, z = D32^-1 r32, p = z, rho, ||r32||.
-template <int L>
+// start of the inner solve: d = 0, z = D32^-1 r32, p = z; partials of
+// ||r||^2 (fp64), r32.z and r32.r32.
+template <class SH>
 __global__ __launch_bounds__(kBlock) void k_ir_residual(
     int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ b, const double* __restrict__ x,
     const float* __restrict__ dinv32, float* __restrict__ r32, float* __restrict__ d32,
-    float* __restrict__ p32, CgScalars* so, CgScalars* si, double* __restrict__ partials,
-    double rtol_inner, int remap) {
-  __shared__ double lds[kBlock / 64];
-  constexpr int RPB = kBlock / L;
+    float* __restrict__ p32, double* __restrict__ P, int rows, int remap) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[kLds];
   const int64_t nb = gridDim.x;
-  const int64_t bl = remap ? xcd_logical_block(blockIdx.x, nb) : (int64_t)blockIdx.x;
-  const Range rg = block_range(ceil_div(n, RPB), bl, nb);
-  const int lane = threadIdx.x % L;
   double rr64 = 0.0, rz = 0.0, rr32 = 0.0;
-  for (int64_t g = rg.lo; g < rg.hi; ++g) {
-    const int64_t row = g * RPB + threadIdx.x / L;
-    if (row < n) {
-      const double ax = group_sum<L>(row_partial<L, double, double, double>(rowptr, col, val, x, row, lane));
-      if (lane == 0) {
-        const double ri = b[row] - ax;
-        rr64 += ri * ri;
-        const float rf = (float)ri;
-        const float zf = dinv32[row] * rf;
-        r32[row] = rf;
-        d32[row] = 0.0f;
-        p32[row] = zf;
-        rz += (double)rf * (double)zf;
-        rr32 += (double)rf * (double)rf;
-      }
-    }
-  }
+  for_rows<SH, double, double, double>(n, rowptr, col, val, x, rows, logical_block(remap), nb,
+                                       reinterpret_cast<double*>(smem), [&](int64_t row, double ax) {
+                                         const double ri = b[row] - ax;
+                                         rr64 += ri * ri;
+                                         const float rf = (float)ri;
+                                         const float zf = dinv32[row] * rf;
+                                         r32[row] = rf;
+                                         d32[row] = 0.0f;
+                                         p32[row] = zf;
+                                         rz += (double)rf * (double)zf;
+                                         rr32 += (double)rf * (double)rf;
+                                       });
   rr64 = block_sum<kBlock>(rr64, lds);
   rz = block_sum<kBlock>(rz, lds);
   rr32 = block_sum<kBlock>(rr32, lds);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x] = rr64;
-    partials[nb + blockIdx.x] = rz;
-    partials[2 * nb + blockIdx.x] = rr32;
+    P[blockIdx.x] = rr64;
+    P[nb + blockIdx.x] = rz;
+    P[2 * nb + blockIdx.x] = rr32;
   }
-  if (arrive_last(&so->ticket[1])) {
-    const double t64 = reduce_partials<kBlock>(partials, nb, lds);
-    const double trz = reduce_partials<kBlock>(partials + nb, nb, lds);
-    const double t32 = reduce_partials<kBlock>(partials + 2 * nb, nb, lds);
-    if (threadIdx.x == 0) {
-      so->rr = t64;
-      so->rr_true = t64;
-      if (so->status == SPX_OK && sqrt(t64) <= so->thresh) so->done = 1;
-      si->rho = trz;
-      si->r0norm = sqrt(t32);
-      si->thresh = rtol_inner * si->r0norm;
-      si->rr = t32;
-      si->iters = 0;
-      si->status = SPX_OK;
-      si->done = (so->done || so->status != SPX_OK) ? 1 : 0;
-    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ir_finish(CgScalars* so, CgScalars* si, const double* P,
+                                                      int64_t G, double rtol_inner) {
+  __shared__ double lds[kLds];
+  const double t64 = reduce_all(P, G, lds);
+  const double trz = reduce_all(P + G, G, lds);
+  const double t32 = reduce_all(P + 2 * G, G, lds);
+  if (threadIdx.x == 0) {
+    so->rr = t64;
+    so->rr_true = t64;
+    if (so->status == SPX_OK && sqrt(t64) <= so->thresh) so->done = 1;
+    si->rho[0] = trz;
+    si->r0norm = sqrt(t32);
+    si->thresh = rtol_inner * si->r0norm;
+    si->rr = t32;
+    si->iters = 0;
+    si->status = SPX_OK;
+    si->done = (so->done || so->status != SPX_OK) ? 1 : 0;
   }
 }
 
@@ -365,16 +405,23 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(int64_t n, double* __restr
 // ------------------------------------------------------------ dispatch
 
 template <typename F>
-int with_lanes(int L, F&& f) {
-  switch (L) {
-    case 1: return f(std::integral_constant<int, 1>());
-    case 2: return f(std::integral_constant<int, 2>());
-    case 4: return f(std::integral_constant<int, 4>());
-    case 8: return f(std::integral_constant<int, 8>());
-    case 16: return f(std::integral_constant<int, 16>());
-    case 32: return f(std::integral_constant<int, 32>());
-    case 64: return f(std::integral_constant<int, 64>());
-    default: return set_error(SPX_INVALID_ARG, "unsupported lane count %d", L);
+int with_shape(const SpmvShape& sh, F&& f) {
+  if (sh.variant == kVariantStream)
+    return sh.nt ? f(Shape<kVariantStream, 1, true>()) : f(Shape<kVariantStream, 1, false>());
+  switch (sh.lanes) {
+#define SPX_LANES_CASE(LL) \
+  case LL:                 \
+    return sh.nt ? f(Shape<kVariantVector, LL, true>()) : f(Shape<kVariantVector, LL, false>());
+    SPX_LANES_CASE(1)
+    SPX_LANES_CASE(2)
+    SPX_LANES_CASE(4)
+    SPX_LANES_CASE(8)
+    SPX_LANES_CASE(16)
+    SPX_LANES_CASE(32)
+    SPX_LANES_CASE(64)
+#undef SPX_LANES_CASE
+    default:
+      return set_error(SPX_INVALID_ARG, "unsupported lane count %d", sh.lanes);
   }
 }
 
@@ -390,9 +437,8 @@ int ensure_solver(spx_matrix* h) {
                                 hipHostMallocDefault));
     SPX_CHECK_HIP(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
     SPX_CHECK_HIP(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
-    SPX_CHECK_HIP(hipMemset(h->scal, 0, sizeof(CgScalars) * 2));
   }
-  const int64_t cap = (int64_t)fused_blocks() * 4;
+  const int64_t cap = (int64_t)fused_blocks(h) * 4;
   if (h->partial_cap < cap) {
     dfree(h->partials);
     h->partials = nullptr;
@@ -414,28 +460,48 @@ inline unsigned grid1(int64_t count) {
   return (unsigned)std::max<int64_t>(1, ceil_div(count, 256));
 }
 
-// Enqueues `count` CG iterations (K1, K2, K3) on the given operator.  With
-// `evs` (6 events per iteration) every kernel is bracketed by events.
+// The operator of one solve: a matrix in the precision VT plus its shape.
 template <typename VT>
-int enqueue_iterations(int L, int64_t n, const int32_t* rowptr, const int32_t* col, const VT* val,
-                       VT* x, VT* r, VT* p, VT* q, const VT* dinv, CgScalars* st,
-                       double* partials, int remap, int64_t count, hipStream_t s,
+struct Op {
+  int64_t n;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const VT* val;
+  SpmvShape sh;
+};
+
+template <typename VT>
+size_t shape_lds(const SpmvShape& sh) {
+  if (sh.variant != kVariantStream) return 0;
+  return sh.lds / sizeof(double) * sizeof(VT);
+}
+
+// Enqueues iterations first .. first+count-1 (1-based k) of K1, K2, K3.
+// With `evs` (6 events per iteration) every kernel is bracketed by events.
+template <typename VT>
+int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
+                       CgScalars* st, int64_t first, int64_t count, hipStream_t s,
                        hipEvent_t* evs) {
-  const unsigned nb = (unsigned)fused_blocks();
-  return with_lanes(L, [&](auto Lc) {
-    constexpr int LL = decltype(Lc)::value;
-    for (int64_t k = 0; k < count; ++k) {
-      hipEvent_t* e = evs ? evs + 6 * k : nullptr;
+  const unsigned G = (unsigned)fused_blocks(h);
+  double* P1 = h->partials;
+  double* P2 = h->partials + G;
+  const size_t lds = shape_lds<VT>(A.sh);
+  return with_shape(A.sh, [&](auto shc) {
+    using SH = decltype(shc);
+    for (int64_t c = 0; c < count; ++c) {
+      const int64_t k = first + c;
+      hipEvent_t* e = evs ? evs + 6 * c : nullptr;
       if (e) (void)hipEventRecord(e[0], s);
-      hipLaunchKernelGGL((k_cg_spmv_dot<LL, VT>), dim3(nb), dim3(kBlock), 0, s, n, rowptr, col, val,
-                         p, q, st, partials, remap);
+      hipLaunchKernelGGL((k_cg_spmv<SH, VT>), dim3(G), dim3(kBlock), lds, s, A.n, A.rowptr, A.col,
+                         A.val, p, q, st, P1, A.sh.rows, h->xcd_remap);
       if (e) (void)hipEventRecord(e[1], s);
       if (e) (void)hipEventRecord(e[2], s);
-      hipLaunchKernelGGL((k_cg_update<VT>), dim3(nb), dim3(kBlock), 0, s, n, x, r, p, q, dinv, st,
-                         partials);
+      hipLaunchKernelGGL((k_cg_update<VT>), dim3(G), dim3(kBlock), 0, s, A.n, x, r, p, q, dinv, st,
+                         P1, (int64_t)G, P2, k);
       if (e) (void)hipEventRecord(e[3], s);
       if (e) (void)hipEventRecord(e[4], s);
-      hipLaunchKernelGGL((k_cg_pupdate<VT>), dim3(nb), dim3(kBlock), 0, s, n, p, r, dinv, st);
+      hipLaunchKernelGGL((k_cg_pupdate<VT>), dim3(G), dim3(kBlock), 0, s, A.n, p, r, dinv, st, P2,
+                         (int64_t)G, k);
       if (e) (void)hipEventRecord(e[5], s);
     }
     return SPX_OK;
@@ -454,17 +520,17 @@ int ensure_prof_events(spx_matrix* h, int64_t need) {
 }
 
 // Adds the event-timed durations of iterations [first, first+count) of a
-// finished chunk, counting only launches that did work (iterations up to
-// `iters`; the p update of the last iteration is skipped by the kernel).
+// finished chunk, counting only launches that did work: K1 and K2 up to
+// iteration `iters`, K3 before it (the last K3 only records the stop).
 void accumulate_profile(spx_matrix* h, hipEvent_t* evs, int64_t first, int64_t count,
                         int64_t iters, int kind0) {
-  for (int64_t k = 0; k < count; ++k) {
-    const int64_t it = first + k + 1;
+  for (int64_t c = 0; c < count; ++c) {
+    const int64_t it = first + c;
     for (int j = 0; j < 3; ++j) {
       const bool ran = (j < 2) ? it <= iters : it < iters;
       if (!ran) continue;
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, evs[6 * k + 2 * j], evs[6 * k + 2 * j + 1]) == hipSuccess) {
+      if (hipEventElapsedTime(&ms, evs[6 * c + 2 * j], evs[6 * c + 2 * j + 1]) == hipSuccess) {
         h->prof_ms[kind0 + j] += ms;
         h->prof_cnt[kind0 + j] += 1;
       }
@@ -476,9 +542,9 @@ void accumulate_profile(spx_matrix* h, hipEvent_t* evs, int64_t first, int64_t c
 // `check_every` iterations queued ahead of the one being polled.  Returns
 // the last polled state in *final.
 template <typename VT>
-int run_until_done(spx_matrix* h, int L, int64_t n, const int32_t* rowptr, const int32_t* col,
-                   const VT* val, VT* x, VT* r, VT* p, VT* q, const VT* dinv, CgScalars* st,
-                   int64_t maxit, int32_t check_every, hipStream_t s, CgScalars* final) {
+int run_until_done(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
+                   CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s,
+                   CgScalars* final) {
   int64_t launched = 0;
   CgScalars* host = h->scal_host;
   const bool prof = h->profile != 0;
@@ -488,9 +554,8 @@ int run_until_done(spx_matrix* h, int L, int64_t n, const int32_t* rowptr, const
   auto chunk = [&](int slot) -> int {
     const int64_t m = std::min<int64_t>(check_every, maxit - launched);
     hipEvent_t* evs = prof ? h->prof_ev + slot * 6 * (int64_t)check_every : nullptr;
-    SPX_TRY(enqueue_iterations<VT>(L, n, rowptr, col, val, x, r, p, q, dinv, st, h->partials,
-                                   h->xcd_remap, m, s, evs));
-    first[slot] = launched;
+    SPX_TRY(enqueue_iterations<VT>(h, A, x, r, p, q, dinv, st, launched + 1, m, s, evs));
+    first[slot] = launched + 1;
     cnt[slot] = m;
     launched += m;
     SPX_CHECK_HIP(hipMemcpyAsync(&host[slot], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
@@ -503,7 +568,7 @@ int run_until_done(spx_matrix* h, int L, int64_t n, const int32_t* rowptr, const
                          iters, kind0);
     cnt[slot] = 0;
   };
-  // state before any iteration (init may already have converged)
+  // state before any iteration (the start may already satisfy the test)
   SPX_CHECK_HIP(hipMemcpyAsync(&host[0], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
   SPX_CHECK_HIP(hipStreamSynchronize(s));
   if (host[0].done || maxit <= 0) {
@@ -529,40 +594,51 @@ int run_until_done(spx_matrix* h, int L, int64_t n, const int32_t* rowptr, const
   return SPX_OK;
 }
 
-int cg_solve_impl(spx_matrix* h, const Csr& A, const double* b, double* x, double rtol,
+// Launches the fp64 residual-norm kernels for b - A x into st->rr_true.
+int enqueue_resnorm(spx_matrix* h, const Op<double>& A, const double* b, const double* x,
+                    CgScalars* st, hipStream_t s) {
+  const unsigned G = (unsigned)fused_blocks(h);
+  SPX_TRY(with_shape(A.sh, [&](auto shc) {
+    using SH = decltype(shc);
+    hipLaunchKernelGGL((k_resnorm<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, A.n,
+                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, h->xcd_remap);
+    return SPX_OK;
+  }));
+  hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G);
+  return SPX_OK;
+}
+
+int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, double rtol,
                   int64_t maxit, int32_t check_every, hipStream_t s, int64_t* iters_out,
                   double* relres_out) {
   if (!b || !x) return set_error(SPX_INVALID_ARG, "cg_solve: b or x is NULL");
   if (maxit < 0 || check_every < 1 || !(rtol >= 0.0))
     return set_error(SPX_INVALID_ARG, "cg_solve: bad maxit/check_every/rtol");
-  if (maxit > INT32_MAX) maxit = INT32_MAX;
+  if (maxit > INT32_MAX - 1) maxit = INT32_MAX - 1;
   SPX_TRY(ensure_solver(h));
-  const int64_t n = A.n;
+  const int64_t n = M.n;
+  const Op<double> A{n, M.rowptr, M.col, M.val, spmv_shape(h, M)};
   double* r = h->work;
   double* p = h->work + n;
   double* q = h->work + 2 * n;
   CgScalars* st = h->scal;
-  const unsigned nb = (unsigned)fused_blocks();
-  const int L = pick_lanes(A, h->lanes_opt);
+  const unsigned G = (unsigned)fused_blocks(h);
   hipLaunchKernelGGL(k_scal_reset, dim3(1), dim3(64), 0, s, st, (int32_t)maxit);
-  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, A.val, A.dpos, h->dinv,
+  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, h->dinv,
                      (float*)nullptr, st);
-  SPX_TRY(with_lanes(L, [&](auto Lc) {
-    constexpr int LL = decltype(Lc)::value;
-    hipLaunchKernelGGL((k_cg_init<LL>), dim3(nb), dim3(kBlock), 0, s, n, A.rowptr, A.col, A.val, b,
-                       x, r, p, h->dinv, st, h->partials, rtol, h->xcd_remap);
+  SPX_TRY(with_shape(A.sh, [&](auto shc) {
+    using SH = decltype(shc);
+    hipLaunchKernelGGL((k_cg_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
+                       M.rowptr, M.col, M.val, b, x, r, p, h->dinv, h->partials, A.sh.rows,
+                       h->xcd_remap);
     return SPX_OK;
   }));
+  hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G,
+                     rtol);
   SPX_CHECK_HIP(hipGetLastError());
   CgScalars fin;
-  SPX_TRY(run_until_done<double>(h, L, n, A.rowptr, A.col, A.val, x, r, p, q, h->dinv, st, maxit,
-                                 check_every, s, &fin));
-  SPX_TRY(with_lanes(L, [&](auto Lc) {
-    constexpr int LL = decltype(Lc)::value;
-    hipLaunchKernelGGL((k_resnorm<LL>), dim3(nb), dim3(kBlock), 0, s, n, A.rowptr, A.col, A.val, b,
-                       x, st, h->partials, h->xcd_remap);
-    return SPX_OK;
-  }));
+  SPX_TRY(run_until_done<double>(h, A, x, r, p, q, h->dinv, st, maxit, check_every, s, &fin));
+  SPX_TRY(enqueue_resnorm(h, A, b, x, st, s));
   SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
   SPX_CHECK_HIP(hipStreamSynchronize(s));
   const CgScalars& f = h->scal_host[2];
@@ -581,7 +657,8 @@ int cg_solve_impl(spx_matrix* h, const Csr& A, const double* b, double* x, doubl
 
 }  // namespace
 
-int fused_blocks() {
+int fused_blocks(const spx_matrix* h) {
+  if (h && h->fused_opt > 0) return h->fused_opt;
   static int cached[64] = {0};
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -591,7 +668,7 @@ int fused_blocks() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    cached[dev] = cus * 8;
+    cached[dev] = cus * 4;
   }
   return cached[dev];
 }
@@ -628,37 +705,43 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
   if (maxit_outer < 0 || maxit_inner < 1 || check_every < 1 || !(rtol_outer >= 0.0) ||
       !(rtol_inner > 0.0))
     return set_error(SPX_INVALID_ARG, "cg_solve_mixed: bad iteration limits or tolerances");
-  if (maxit_inner > INT32_MAX) maxit_inner = INT32_MAX;
+  if (maxit_inner > INT32_MAX - 1) maxit_inner = INT32_MAX - 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   SPX_TRY(ensure_solver(h));
   SPX_TRY(ensure_solver32(h));
   SPX_TRY(ensure_val32(h, s));
-  const Csr& A = h->A;
-  const int64_t n = A.n;
+  const Csr& M = h->A;
+  const int64_t n = M.n;
+  const SpmvShape sh = spmv_shape(h, M);
+  const Op<double> A64{n, M.rowptr, M.col, M.val, sh};
+  const Op<float> A32{n, M.rowptr, M.col, M.val32, sh};
   float* r32 = h->work32;
   float* d32 = h->work32 + n;
   float* p32 = h->work32 + 2 * n;
   float* q32 = h->work32 + 3 * n;
   CgScalars* so = h->scal;
   CgScalars* si = h->scal + 1;
-  const unsigned nb = (unsigned)fused_blocks();
-  const int L = pick_lanes(A, h->lanes_opt);
+  const unsigned G = (unsigned)fused_blocks(h);
   hipLaunchKernelGGL(k_scal_reset, dim3(1), dim3(64), 0, s, so, (int32_t)0);
   hipLaunchKernelGGL(k_scal_reset, dim3(1), dim3(64), 0, s, si, (int32_t)maxit_inner);
-  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, A.val, A.dpos, h->dinv, h->dinv32,
+  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, h->dinv, h->dinv32,
                      so);
-  hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(kBlock), 0, s, n, b, so, h->partials, rtol_outer);
+  hipLaunchKernelGGL(k_norm2, dim3(G), dim3(kBlock), 0, s, n, b, h->partials);
+  hipLaunchKernelGGL(k_norm2_finish, dim3(1), dim3(kBlock), 0, s, so, h->partials, (int64_t)G,
+                     rtol_outer);
   SPX_CHECK_HIP(hipGetLastError());
   int64_t outer = 0, inner = 0;
   int status = SPX_OK;
   for (;;) {
-    SPX_TRY(with_lanes(L, [&](auto Lc) {
-      constexpr int LL = decltype(Lc)::value;
-      hipLaunchKernelGGL((k_ir_residual<LL>), dim3(nb), dim3(kBlock), 0, s, n, A.rowptr, A.col,
-                         A.val, b, x, h->dinv32, r32, d32, p32, so, si, h->partials, rtol_inner,
-                         h->xcd_remap);
+    SPX_TRY(with_shape(sh, [&](auto shc) {
+      using SH = decltype(shc);
+      hipLaunchKernelGGL((k_ir_residual<SH>), dim3(G), dim3(kBlock), shape_lds<double>(sh), s, n,
+                         M.rowptr, M.col, M.val, b, x, h->dinv32, r32, d32, p32, h->partials,
+                         sh.rows, h->xcd_remap);
       return SPX_OK;
     }));
+    hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, so, si, h->partials, (int64_t)G,
+                       rtol_inner);
     SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], so, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     SPX_CHECK_HIP(hipStreamSynchronize(s));
     const CgScalars o = h->scal_host[2];
@@ -673,21 +756,16 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
     }
     ++outer;
     CgScalars fin;
-    SPX_TRY(run_until_done<float>(h, L, n, A.rowptr, A.col, A.val32, d32, r32, p32, q32, h->dinv32,
-                                  si, maxit_inner, check_every, s, &fin));
+    SPX_TRY(run_until_done<float>(h, A32, d32, r32, p32, q32, h->dinv32, si, maxit_inner,
+                                  check_every, s, &fin));
     inner += fin.iters;
-    hipLaunchKernelGGL(k_ir_update, dim3(nb), dim3(kBlock), 0, s, n, x, d32);
+    hipLaunchKernelGGL(k_ir_update, dim3(G), dim3(kBlock), 0, s, n, x, d32);
     if (fin.status == SPX_BREAKDOWN) {
       status = SPX_BREAKDOWN;
       break;
     }
   }
-  SPX_TRY(with_lanes(L, [&](auto Lc) {
-    constexpr int LL = decltype(Lc)::value;
-    hipLaunchKernelGGL((k_resnorm<LL>), dim3(nb), dim3(kBlock), 0, s, n, A.rowptr, A.col, A.val, b,
-                       x, so, h->partials, h->xcd_remap);
-    return SPX_OK;
-  }));
+  SPX_TRY(enqueue_resnorm(h, A64, b, x, so, s));
   SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], so, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
   SPX_CHECK_HIP(hipStreamSynchronize(s));
   const CgScalars& f = h->scal_host[2];

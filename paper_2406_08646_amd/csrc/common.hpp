@@ -64,6 +64,9 @@ int exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count, uint32_
                        uint32_t* scratch, hipStream_t s);
 
 // -------------------------------------------------------------- matrix
+// How products walk a matrix (chosen once per pattern, see spmv.hip).
+enum SpmvVariant { kVariantAuto = 0, kVariantVector = 1, kVariantStream = 2 };
+
 struct Csr {
   int64_t n = 0, nnz = 0;
   int32_t* rowptr = nullptr;
@@ -72,15 +75,28 @@ struct Csr {
   float* val32 = nullptr;
   int32_t* dpos = nullptr;  // position of the diagonal entry of each row, -1 if absent
   int64_t max_row = 0;
+  // largest number of entries in a block of 32/64/128/256 consecutive rows
+  int64_t tile_nnz[4] = {0, 0, 0, 0};
 };
 
-// Device-resident solver scalars of one CG run.
+// Resolved launch shape of a product on one matrix.
+struct SpmvShape {
+  int variant;   // kVariantVector or kVariantStream
+  int lanes;     // vector: lanes per row
+  int rows;      // stream: rows per workgroup
+  size_t lds;    // stream: LDS bytes per workgroup (for 8-byte products)
+  int nt;        // non-temporal matrix loads
+};
+
+// Device-resident solver scalars of one CG run.  rho[k & 1] holds r_k . z_k,
+// so the kernels of iteration k read rho[(k - 1) & 1] while one thread
+// writes rho[k & 1].
 struct CgScalars {
-  double rho, alpha, beta, pq;
+  double rho[2];
+  double alpha, beta, pq;
   double rr, bb, bnorm, thresh;
-  double r0norm, rr_true, spare0, spare1;
+  double r0norm, rr_true, spare;
   int32_t iters, done, status, maxit;
-  uint32_t ticket[4];
 };
 
 }  // namespace spx
@@ -110,6 +126,10 @@ struct spx_matrix {
   int64_t partial_cap = 0;
   int lanes_opt = 0;  // 0 = auto
   int xcd_remap = 1;
+  int variant_opt = 0;   // SpmvVariant
+  int rows_opt = 0;      // stream rows per workgroup, 0 = auto
+  int nt_opt = 0;        // non-temporal matrix loads
+  int fused_opt = 0;     // workgroups of the solver kernels, 0 = auto
   // optional per-kernel timing of solver iterations (HIP events)
   int profile = 0;
   double prof_ms[6] = {0, 0, 0, 0, 0, 0};
@@ -125,9 +145,12 @@ int ensure_kslot(spx_matrix* h, hipStream_t s);
 int ensure_val32(spx_matrix* h, hipStream_t s);
 // spmv.hip
 int pick_lanes(const Csr& A, int opt);
-int launch_spmv(const Csr& A, const double* x, double* y, int lanes, int remap, hipStream_t s);
+int compute_tiles(Csr& A, hipStream_t s);
+SpmvShape spmv_shape(const spx_matrix* h, const Csr& A);
+int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, int remap,
+                hipStream_t s);
 int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
                 hipStream_t s);
 // cg.hip
-int fused_blocks();
+int fused_blocks(const spx_matrix* h);
 }  // namespace spx

@@ -19,7 +19,7 @@ namespace spx {
 
 namespace {
 
-template <int L, int BLOCK>
+template <int L, int BLOCK, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t* __restrict__ rowptr,
                                                 const int32_t* __restrict__ col,
                                                 const double* __restrict__ val,
@@ -30,19 +30,69 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t* __rest
   const int64_t row = b * RPB + threadIdx.x / L;
   const int lane = threadIdx.x % L;
   if (row >= n) return;
-  double s = row_partial<L, double, double, double>(rowptr, col, val, x, row, lane);
+  double s = row_partial<L, double, double, double, NT>(rowptr, col, val, x, row, lane);
   s = group_sum<L>(s);
   if (lane == 0) y[row] = s;
 }
 
-template <int L>
-int launch_spmv_l(const Csr& A, const double* x, double* y, int remap, hipStream_t s) {
+template <int BLOCK, int U, bool NT>
+__global__ __launch_bounds__(BLOCK) void k_spmv_stream(int64_t n, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y, int rows,
+                                                       int remap) {
+  extern __shared__ __align__(16) char smem[];
+  double* prod = reinterpret_cast<double*>(smem);
+  const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t r0 = b * rows;
+  const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+  const double s = stream_rows<BLOCK, U, double, double, double, NT>(rowptr, col, val, x, r0, r1, prod);
+  if (threadIdx.x < r1 - r0) y[r0 + threadIdx.x] = s;
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = 0;
+}
+
+// Largest entry count of any block of 32, 64, 128 and 256 consecutive rows.
+__global__ void k_tile_nnz(const int32_t* __restrict__ rowptr, int64_t n, int32_t* __restrict__ out) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // index of a 32-row block
+  const int64_t nb32 = (n + 31) / 32;
+  if (b >= nb32) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t R = 32 << k;
+    if ((b * 32) % R != 0) continue;
+    const int64_t r0 = b * 32;
+    const int64_t r1 = r0 + R < n ? r0 + R : n;
+    atomicMax(&out[k], rowptr[r1] - rowptr[r0]);
+  }
+}
+
+template <int L, bool NT>
+int launch_vector_l(const Csr& A, const double* x, double* y, int remap, hipStream_t s) {
   constexpr int BLOCK = 256;
   constexpr int RPB = BLOCK / L;
   const int64_t nb = ceil_div(A.n, RPB);
-  hipLaunchKernelGGL((k_spmv<L, BLOCK>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n, A.rowptr,
+  hipLaunchKernelGGL((k_spmv<L, BLOCK, NT>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n, A.rowptr,
                      A.col, A.val, x, y, remap);
   return SPX_OK;
+}
+
+template <bool NT>
+int launch_vector(const Csr& A, int lanes, const double* x, double* y, int remap, hipStream_t s) {
+  switch (lanes) {
+    case 1: return launch_vector_l<1, NT>(A, x, y, remap, s);
+    case 2: return launch_vector_l<2, NT>(A, x, y, remap, s);
+    case 4: return launch_vector_l<4, NT>(A, x, y, remap, s);
+    case 8: return launch_vector_l<8, NT>(A, x, y, remap, s);
+    case 16: return launch_vector_l<16, NT>(A, x, y, remap, s);
+    case 32: return launch_vector_l<32, NT>(A, x, y, remap, s);
+    case 64: return launch_vector_l<64, NT>(A, x, y, remap, s);
+    default: return set_error(SPX_INVALID_ARG, "spmv: unsupported lane count %d", lanes);
+  }
 }
 
 // Y[r, c] for c < nrhs; a group of G lanes per row, lane c owns column c
@@ -120,18 +170,87 @@ int pick_lanes(const Csr& A, int opt) {
   return L;
 }
 
-int launch_spmv(const Csr& A, const double* x, double* y, int lanes, int remap, hipStream_t s) {
-  if (A.n == 0) return SPX_OK;
-  switch (lanes) {
-    case 1: return launch_spmv_l<1>(A, x, y, remap, s);
-    case 2: return launch_spmv_l<2>(A, x, y, remap, s);
-    case 4: return launch_spmv_l<4>(A, x, y, remap, s);
-    case 8: return launch_spmv_l<8>(A, x, y, remap, s);
-    case 16: return launch_spmv_l<16>(A, x, y, remap, s);
-    case 32: return launch_spmv_l<32>(A, x, y, remap, s);
-    case 64: return launch_spmv_l<64>(A, x, y, remap, s);
-    default: return set_error(SPX_INVALID_ARG, "spmv: unsupported lane count %d", lanes);
+int compute_tiles(Csr& A, hipStream_t s) {
+  int32_t* d = nullptr;
+  SPX_TRY(dalloc_n(&d, 4));
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, d, (int64_t)4);
+  const int64_t nb32 = ceil_div(A.n, 32);
+  if (nb32 > 0)
+    hipLaunchKernelGGL(k_tile_nnz, dim3((unsigned)ceil_div(nb32, 256)), dim3(256), 0, s, A.rowptr,
+                       A.n, d);
+  int32_t hostv[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(hostv, d, sizeof(hostv), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(d);
+  if (e != hipSuccess) return set_error(SPX_HIP_ERROR, "tile sizes: %s", hipGetErrorString(e));
+  for (int k = 0; k < 4; ++k) A.tile_nnz[k] = hostv[k];
+  return SPX_OK;
+}
+
+namespace {
+constexpr size_t kStreamLdsCap = 40 * 1024;  // keeps >= 3 workgroups per CU
+constexpr size_t kStreamLdsMax = 64 * 1024;
+int rows_index(int rows) { return rows == 32 ? 0 : rows == 64 ? 1 : rows == 128 ? 2 : 3; }
+}  // namespace
+
+SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
+  SpmvShape sh;
+  sh.lanes = pick_lanes(A, h ? h->lanes_opt : 0);
+  sh.nt = h ? h->nt_opt : 0;
+  sh.rows = 0;
+  sh.lds = 0;
+  sh.variant = kVariantVector;
+  const int want = h ? h->variant_opt : 0;
+  if (want == kVariantVector) return sh;
+  const int rows_opt = h ? h->rows_opt : 0;
+  if (rows_opt) {
+    const size_t lds = (size_t)A.tile_nnz[rows_index(rows_opt)] * sizeof(double);
+    if (lds <= kStreamLdsMax) {
+      sh.variant = kVariantStream;
+      sh.rows = rows_opt;
+      sh.lds = lds;
+    }
+    return sh;
   }
+  // Automatic: stream when some row count keeps the tile small and rows
+  // are not much longer than 64 entries on average.
+  for (int rows : {128, 64, 256, 32}) {
+    const int64_t tile = A.tile_nnz[rows_index(rows)];
+    const size_t lds = (size_t)tile * sizeof(double);
+    if (lds <= kStreamLdsCap && tile <= 64 * (int64_t)rows) {
+      sh.variant = kVariantStream;
+      sh.rows = rows;
+      sh.lds = lds;
+      return sh;
+    }
+  }
+  if (want == kVariantStream) {
+    const size_t lds = (size_t)A.tile_nnz[0] * sizeof(double);
+    if (lds <= kStreamLdsMax) {
+      sh.variant = kVariantStream;
+      sh.rows = 32;
+      sh.lds = lds;
+    }
+  }
+  return sh;
+}
+
+int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, int remap,
+                hipStream_t s) {
+  if (A.n == 0) return SPX_OK;
+  if (sh.variant == kVariantStream) {
+    const int64_t nb = ceil_div(A.n, sh.rows);
+    const size_t lds = sh.lds > 0 ? sh.lds : 16;
+    if (sh.nt)
+      hipLaunchKernelGGL((k_spmv_stream<256, 8, true>), dim3((unsigned)nb), dim3(256), lds, s, A.n,
+                         A.rowptr, A.col, A.val, x, y, sh.rows, remap);
+    else
+      hipLaunchKernelGGL((k_spmv_stream<256, 8, false>), dim3((unsigned)nb), dim3(256), lds, s,
+                         A.n, A.rowptr, A.col, A.val, x, y, sh.rows, remap);
+    return SPX_OK;
+  }
+  return sh.nt ? launch_vector<true>(A, sh.lanes, x, y, remap, s)
+               : launch_vector<false>(A, sh.lanes, x, y, remap, s);
 }
 
 int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
@@ -153,7 +272,7 @@ extern "C" int spx_matmult(spx_handle h, const double* x, double* y, void* strea
   if (!h || !x || !y) return set_error(SPX_INVALID_ARG, "matmult: NULL argument");
   if (x == y) return set_error(SPX_INVALID_ARG, "matmult: x and y must not alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SPX_TRY(launch_spmv(h->A, x, y, pick_lanes(h->A, h->lanes_opt), h->xcd_remap, s));
+  SPX_TRY(launch_spmv(h->A, spmv_shape(h, h->A), x, y, h->xcd_remap, s));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }
@@ -164,7 +283,7 @@ extern "C" int spx_matmult_transpose(spx_handle h, const double* x, double* y, v
   if (x == y) return set_error(SPX_INVALID_ARG, "matmult_transpose: x and y must not alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
   SPX_TRY(ensure_transpose(h, s));
-  SPX_TRY(launch_spmv(h->At, x, y, pick_lanes(h->At, h->lanes_opt), h->xcd_remap, s));
+  SPX_TRY(launch_spmv(h->At, spmv_shape(h, h->At), x, y, h->xcd_remap, s));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }

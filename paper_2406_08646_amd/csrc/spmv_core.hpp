@@ -1,4 +1,12 @@
-// The per-row inner loop shared by the product and solver kernels.
+// The per-row inner loops shared by the product and solver kernels.
+//
+// Two ways to walk a CSR matrix on a 64-wide wavefront:
+//  * vector: an aligned group of L lanes owns one row (any row length);
+//  * stream: a workgroup owns R consecutive rows; it streams their entire
+//    contiguous run of (value, column) pairs with every lane reading
+//    consecutive entries (fully coalesced, U independent loads in flight per
+//    lane), stages the products a*x[col] in LDS, then one lane per row adds
+//    its row's products in order.  Used when rows are short and regular.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,11 +17,19 @@
 
 namespace spx {
 
+template <bool NT, typename T>
+__device__ __forceinline__ T mload(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
 // Partial dot product of one CSR row handled by lane `lane` of an aligned
 // L-lane group: lane l takes entries t0 + l, t0 + l + L, ...  The caller
 // finishes with group_sum<L>.  VT: stored value type, XT: vector type, ACC:
 // accumulator type.
-template <int L, typename VT, typename XT, typename ACC>
+template <int L, typename VT, typename XT, typename ACC, bool NT = false>
 __device__ __forceinline__ ACC row_partial(const int32_t* __restrict__ rowptr,
                                            const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const XT* __restrict__ x,
@@ -23,15 +39,54 @@ __device__ __forceinline__ ACC row_partial(const int32_t* __restrict__ rowptr,
   int32_t t = t0 + lane;
   // two independent loads in flight per lane before the gathers
   for (; t + L < t1; t += 2 * L) {
-    const VT a0 = stream_load(val + t);
-    const VT a1 = stream_load(val + t + L);
-    const int32_t c0 = stream_load(col + t);
-    const int32_t c1 = stream_load(col + t + L);
+    const VT a0 = mload<NT>(val + t);
+    const VT a1 = mload<NT>(val + t + L);
+    const int32_t c0 = mload<NT>(col + t);
+    const int32_t c1 = mload<NT>(col + t + L);
     acc += (ACC)a0 * (ACC)x[c0];
     acc += (ACC)a1 * (ACC)x[c1];
   }
-  if (t < t1) acc += (ACC)stream_load(val + t) * (ACC)x[stream_load(col + t)];
+  if (t < t1) acc += (ACC)mload<NT>(val + t) * (ACC)x[mload<NT>(col + t)];
   return acc;
+}
+
+// Rows [r0, r1) of one workgroup of BLOCK threads (r1 - r0 <= BLOCK); the
+// products of the rows' entries are staged in `prod` (LDS, at least
+// rowptr[r1] - rowptr[r0] elements).  Returns, in thread t < r1 - r0, the
+// sum of row r0 + t (entries added in order); other threads get 0.
+template <int BLOCK, int U, typename VT, typename XT, typename ACC, bool NT = false>
+__device__ __forceinline__ ACC stream_rows(const int32_t* __restrict__ rowptr,
+                                           const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, const XT* __restrict__ x,
+                                           int64_t r0, int64_t r1, ACC* prod) {
+  const int tid = threadIdx.x;
+  const int32_t t0 = rowptr[r0];
+  const int32_t cnt = rowptr[r1] - t0;
+  for (int32_t base = 0; base < cnt; base += BLOCK * U) {
+    VT a[U];
+    int32_t c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t i = base + u * BLOCK + tid;
+      if (i < cnt) {
+        a[u] = mload<NT>(val + t0 + i);
+        c[u] = mload<NT>(col + t0 + i);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t i = base + u * BLOCK + tid;
+      if (i < cnt) prod[i] = (ACC)a[u] * (ACC)x[c[u]];
+    }
+  }
+  __syncthreads();
+  ACC s = ACC(0);
+  if (tid < r1 - r0) {
+    const int32_t a = rowptr[r0 + tid] - t0, e = rowptr[r0 + tid + 1] - t0;
+    for (int32_t i = a; i < e; ++i) s += prod[i];
+  }
+  __syncthreads();  // prod is reused by the caller's next tile
+  return s;
 }
 
 }  // namespace spx

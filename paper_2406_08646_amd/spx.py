@@ -39,6 +39,10 @@ ADD_VALUES = 1
 OPT_SPMV_LANES = 1
 OPT_XCD_REMAP = 2
 OPT_PROFILE = 3
+OPT_SPMV_VARIANT = 4
+OPT_ROWS_PER_BLOCK = 5
+OPT_NONTEMPORAL = 6
+OPT_SOLVER_BLOCKS = 7
 PROFILE_KINDS = ("spmv_dot_f64", "update_f64", "pupdate_f64", "spmv_dot_f32", "update_f32",
                  "pupdate_f32")
 

@@ -42,6 +42,22 @@ def test_config1_cg(orc):
     check_against_oracle(orc, ref, res, ores, b, 1e-8, lam_min)
 
 
+@pytest.mark.parametrize("variant,blocks", [(1, 0), (2, 0), (2, 37), (1, 2048)])
+def test_config1_cg_shapes(orc, variant, blocks):
+    spx = require_gpu()
+    prob, _, b = W.config1()
+    A = assemble(spx, prob)
+    A.set_option(spx.OPT_SPMV_VARIANT, variant)
+    A.set_option(spx.OPT_SOLVER_BLOCKS, blocks)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    ores = orc.pcg(ref, b, 1e-8)
+    res = A.cg_solve(dev(b), rtol=1e-8)
+    c = math.cos(math.pi / 63)
+    check_against_oracle(orc, ref, res, ores, b, 1e-8, min(1.0, (8 - 4 * c - 4 * c * c) / 3))
+    m = A.cg_solve_mixed(dev(b), rtol_outer=1e-10, rtol_inner=1e-4)
+    assert m.status == 0 and m.relres <= 1e-10
+
+
 def test_cg_check_every_does_not_change_the_result(orc):
     spx = require_gpu()
     prob, _, b = W.config1()

@@ -40,6 +40,35 @@ def test_matmult_every_lane_count(orc, lanes):
     assert np.array_equal(bits(y), bits(y2))
 
 
+@pytest.mark.parametrize("variant,rows", [(1, 0), (2, 32), (2, 64), (2, 128), (2, 256)])
+@pytest.mark.parametrize("case", ["q1_3d", "random", "config1"])
+def test_matmult_variants(orc, variant, rows, case):
+    spx = require_gpu()
+    rng = np.random.default_rng(7)
+    if case == "q1_3d":
+        prob = W.q1_poisson(20, 3, kappa=np.exp(rng.standard_normal(20**3)))
+    elif case == "random":
+        prob = W.random_coo(rng, 7001, 90000, extreme=False)
+    else:
+        prob = W.config1()[0]
+    A = assemble(spx, prob)
+    A.set_option(spx.OPT_SPMV_VARIANT, variant)
+    A.set_option(spx.OPT_ROWS_PER_BLOCK, rows)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    x = rng.uniform(-1, 1, prob.n)
+    y = host(A.matmult(dev(x)))
+    yr = orc.spmv(ref, x)
+    spmv_within(y, yr, orc.abs_spmv(ref, x))
+    if variant == 2 and A.get_option(spx.OPT_SPMV_VARIANT) == 2:
+        # products rounded then added in row order: the oracle's arithmetic
+        assert np.array_equal(bits(y), bits(yr))
+    yt = host(A.matmult_transpose(dev(x)))
+    spmv_within(yt, orc.spmv_transpose(ref, x), orc.abs_spmv_transpose(ref, x))
+    for nt in (0, 1):
+        A.set_option(spx.OPT_NONTEMPORAL, nt)
+        assert np.array_equal(bits(host(A.matmult(dev(x)))), bits(y))
+
+
 def test_matmult_long_and_empty_rows(orc):
     spx = require_gpu()
     rng = np.random.default_rng(30)
