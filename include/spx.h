@@ -215,8 +215,13 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *     (rows of a workgroup streamed through LDS).
  *   SPX_OPT_ROWS_PER_BLOCK: stream variant rows per workgroup (0 auto, else
  *     32, 64, 128 or 256).
- *   SPX_OPT_NONTEMPORAL: 1 loads matrix values/columns non-temporally.
- *   SPX_OPT_SOLVER_BLOCKS: workgroups of the solver kernels (0 auto). */
+ *   SPX_OPT_NONTEMPORAL: 1 (default) loads matrix values/columns
+ *     non-temporally, 0 with the default cache policy.
+ *   SPX_OPT_SOLVER_BLOCKS: workgroups of the solver's SpMV kernels (0 auto).
+ *   SPX_OPT_QUAD_LOADS: 1 (default) streams values/columns with 16-byte
+ *     loads in the stream variant, 0 with element loads.
+ *   SPX_OPT_VECTOR_BLOCKS: workgroups of the solver's vector kernels (0
+ *     auto). */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,
@@ -224,7 +229,9 @@ enum spx_option {
   SPX_OPT_SPMV_VARIANT = 4,
   SPX_OPT_ROWS_PER_BLOCK = 5,
   SPX_OPT_NONTEMPORAL = 6,
-  SPX_OPT_SOLVER_BLOCKS = 7
+  SPX_OPT_SOLVER_BLOCKS = 7,
+  SPX_OPT_QUAD_LOADS = 8,
+  SPX_OPT_VECTOR_BLOCKS = 9
 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);

@@ -110,10 +110,14 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
       h->nt_opt = value ? 1 : 0;
       return SPX_OK;
     case SPX_OPT_SOLVER_BLOCKS:
+    case SPX_OPT_VECTOR_BLOCKS:
       if (value < 0 || value > (1 << 20))
-        return set_error(SPX_INVALID_ARG, "set_option: solver blocks %lld out of range",
+        return set_error(SPX_INVALID_ARG, "set_option: block count %lld out of range",
                          (long long)value);
-      h->fused_opt = (int)value;
+      (option == SPX_OPT_SOLVER_BLOCKS ? h->fused_opt : h->vec_blocks_opt) = (int)value;
+      return SPX_OK;
+    case SPX_OPT_QUAD_LOADS:
+      h->vec_opt = value ? 1 : 0;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
@@ -144,6 +148,12 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       return SPX_OK;
     case SPX_OPT_SOLVER_BLOCKS:
       *value = fused_blocks(h);
+      return SPX_OK;
+    case SPX_OPT_VECTOR_BLOCKS:
+      *value = vector_blocks(h);
+      return SPX_OK;
+    case SPX_OPT_QUAD_LOADS:
+      *value = h->vec_opt;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

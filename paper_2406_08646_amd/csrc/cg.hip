@@ -62,11 +62,12 @@ __device__ __forceinline__ double reduce_all(const double* parts, int64_t nparts
   return s;
 }
 
-template <int V, int L, bool NT>
+template <int V, int L, bool NT, bool VEC = false>
 struct Shape {
   static constexpr int variant = V;
   static constexpr int lanes = L;
   static constexpr bool nt = NT;
+  static constexpr bool vec = VEC;
 };
 
 // Calls epi(row, value) on the thread that owns each row of this
@@ -81,7 +82,11 @@ __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ 
     for (int64_t rb = rg.lo; rb < rg.hi; ++rb) {
       const int64_t r0 = rb * rows;
       const int64_t r1 = r0 + rows < n ? r0 + rows : n;
-      const ACC s = stream_rows<kBlock, 8, VT, XT, ACC, SH::nt>(rowptr, col, val, x, r0, r1, prod);
+      ACC s;
+      if constexpr (SH::vec)
+        s = stream_rows_v4<kBlock, 2, VT, XT, ACC, SH::nt>(rowptr, col, val, x, r0, r1, prod);
+      else
+        s = stream_rows<kBlock, 8, VT, XT, ACC, SH::nt>(rowptr, col, val, x, r0, r1, prod);
       if (threadIdx.x < r1 - r0) epi(r0 + threadIdx.x, s);
     }
   } else {
@@ -406,8 +411,12 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(int64_t n, double* __restr
 
 template <typename F>
 int with_shape(const SpmvShape& sh, F&& f) {
-  if (sh.variant == kVariantStream)
+  if (sh.variant == kVariantStream) {
+    if (sh.vec)
+      return sh.nt ? f(Shape<kVariantStream, 1, true, true>())
+                   : f(Shape<kVariantStream, 1, false, true>());
     return sh.nt ? f(Shape<kVariantStream, 1, true>()) : f(Shape<kVariantStream, 1, false>());
+  }
   switch (sh.lanes) {
 #define SPX_LANES_CASE(LL) \
   case LL:                 \
@@ -438,7 +447,7 @@ int ensure_solver(spx_matrix* h) {
     SPX_CHECK_HIP(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
     SPX_CHECK_HIP(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
   }
-  const int64_t cap = (int64_t)fused_blocks(h) * 4;
+  const int64_t cap = (int64_t)std::max(fused_blocks(h), vector_blocks(h)) * 4;
   if (h->partial_cap < cap) {
     dfree(h->partials);
     h->partials = nullptr;
@@ -482,9 +491,10 @@ template <typename VT>
 int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
                        CgScalars* st, int64_t first, int64_t count, hipStream_t s,
                        hipEvent_t* evs) {
-  const unsigned G = (unsigned)fused_blocks(h);
+  const unsigned G1 = (unsigned)fused_blocks(h);
+  const unsigned G2 = (unsigned)vector_blocks(h);
   double* P1 = h->partials;
-  double* P2 = h->partials + G;
+  double* P2 = h->partials + G1;
   const size_t lds = shape_lds<VT>(A.sh);
   return with_shape(A.sh, [&](auto shc) {
     using SH = decltype(shc);
@@ -492,16 +502,16 @@ int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* 
       const int64_t k = first + c;
       hipEvent_t* e = evs ? evs + 6 * c : nullptr;
       if (e) (void)hipEventRecord(e[0], s);
-      hipLaunchKernelGGL((k_cg_spmv<SH, VT>), dim3(G), dim3(kBlock), lds, s, A.n, A.rowptr, A.col,
+      hipLaunchKernelGGL((k_cg_spmv<SH, VT>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr, A.col,
                          A.val, p, q, st, P1, A.sh.rows, h->xcd_remap);
       if (e) (void)hipEventRecord(e[1], s);
       if (e) (void)hipEventRecord(e[2], s);
-      hipLaunchKernelGGL((k_cg_update<VT>), dim3(G), dim3(kBlock), 0, s, A.n, x, r, p, q, dinv, st,
-                         P1, (int64_t)G, P2, k);
+      hipLaunchKernelGGL((k_cg_update<VT>), dim3(G2), dim3(kBlock), 0, s, A.n, x, r, p, q, dinv, st,
+                         P1, (int64_t)G1, P2, k);
       if (e) (void)hipEventRecord(e[3], s);
       if (e) (void)hipEventRecord(e[4], s);
-      hipLaunchKernelGGL((k_cg_pupdate<VT>), dim3(G), dim3(kBlock), 0, s, A.n, p, r, dinv, st, P2,
-                         (int64_t)G, k);
+      hipLaunchKernelGGL((k_cg_pupdate<VT>), dim3(G2), dim3(kBlock), 0, s, A.n, p, r, dinv, st, P2,
+                         (int64_t)G2, k);
       if (e) (void)hipEventRecord(e[5], s);
     }
     return SPX_OK;
@@ -657,8 +667,8 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
 
 }  // namespace
 
-int fused_blocks(const spx_matrix* h) {
-  if (h && h->fused_opt > 0) return h->fused_opt;
+namespace {
+int cu_count() {
   static int cached[64] = {0};
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -668,9 +678,23 @@ int fused_blocks(const spx_matrix* h) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    cached[dev] = cus * 4;
+    cached[dev] = cus;
   }
   return cached[dev];
+}
+}  // namespace
+
+// Workgroups of the solver's SpMV-shaped kernels (each walks a contiguous
+// share of the rows) and of its vector kernels; every workgroup of the
+// next kernel re-adds this many partials, so the counts stay moderate.
+int fused_blocks(const spx_matrix* h) {
+  if (h && h->fused_opt > 0) return h->fused_opt;
+  return cu_count() * 8;
+}
+
+int vector_blocks(const spx_matrix* h) {
+  if (h && h->vec_blocks_opt > 0) return h->vec_blocks_opt;
+  return cu_count() * 4;
 }
 
 }  // namespace spx

@@ -34,9 +34,11 @@ void clear_error();
 int dalloc(void** p, size_t bytes);
 void dfree(void* p);
 
+// Every array gets 64 bytes of tail padding, so vector loads that round a
+// range up to a whole 16-byte quad stay inside the allocation.
 template <typename T>
 inline int dalloc_n(T** p, size_t count) {
-  return dalloc(reinterpret_cast<void**>(p), count * sizeof(T) + 16);
+  return dalloc(reinterpret_cast<void**>(p), count * sizeof(T) + 64);
 }
 
 // ----------------------------------------------------- launch geometry
@@ -86,6 +88,7 @@ struct SpmvShape {
   int rows;      // stream: rows per workgroup
   size_t lds;    // stream: LDS bytes per workgroup (for 8-byte products)
   int nt;        // non-temporal matrix loads
+  int vec;       // stream: 16-byte quad loads
 };
 
 // Device-resident solver scalars of one CG run.  rho[k & 1] holds r_k . z_k,
@@ -128,8 +131,10 @@ struct spx_matrix {
   int xcd_remap = 1;
   int variant_opt = 0;   // SpmvVariant
   int rows_opt = 0;      // stream rows per workgroup, 0 = auto
-  int nt_opt = 0;        // non-temporal matrix loads
-  int fused_opt = 0;     // workgroups of the solver kernels, 0 = auto
+  int nt_opt = 1;        // non-temporal matrix loads
+  int vec_opt = 1;       // quad loads in the stream walk
+  int fused_opt = 0;     // workgroups of the solver SpMV kernels, 0 = auto
+  int vec_blocks_opt = 0;  // workgroups of the solver vector kernels, 0 = auto
   // optional per-kernel timing of solver iterations (HIP events)
   int profile = 0;
   double prof_ms[6] = {0, 0, 0, 0, 0, 0};
@@ -153,4 +158,5 @@ int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double
                 hipStream_t s);
 // cg.hip
 int fused_blocks(const spx_matrix* h);
+int vector_blocks(const spx_matrix* h);
 }  // namespace spx

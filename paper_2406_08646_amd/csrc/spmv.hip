@@ -35,7 +35,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(int64_t n, const int32_t* __rest
   if (lane == 0) y[row] = s;
 }
 
-template <int BLOCK, int U, bool NT>
+template <int BLOCK, int U, bool NT, bool VEC>
 __global__ __launch_bounds__(BLOCK) void k_spmv_stream(int64_t n, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col,
                                                        const double* __restrict__ val,
@@ -47,7 +47,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_stream(int64_t n, const int32_t*
   const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   const int64_t r0 = b * rows;
   const int64_t r1 = r0 + rows < n ? r0 + rows : n;
-  const double s = stream_rows<BLOCK, U, double, double, double, NT>(rowptr, col, val, x, r0, r1, prod);
+  double s;
+  if constexpr (VEC)
+    s = stream_rows_v4<BLOCK, U, double, double, double, NT>(rowptr, col, val, x, r0, r1, prod);
+  else
+    s = stream_rows<BLOCK, U, double, double, double, NT>(rowptr, col, val, x, r0, r1, prod);
   if (threadIdx.x < r1 - r0) y[r0 + threadIdx.x] = s;
 }
 
@@ -196,7 +200,8 @@ int rows_index(int rows) { return rows == 32 ? 0 : rows == 64 ? 1 : rows == 128 
 SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   SpmvShape sh;
   sh.lanes = pick_lanes(A, h ? h->lanes_opt : 0);
-  sh.nt = h ? h->nt_opt : 0;
+  sh.nt = h ? h->nt_opt : 1;
+  sh.vec = h ? h->vec_opt : 1;
   sh.rows = 0;
   sh.lds = 0;
   sh.variant = kVariantVector;
@@ -241,12 +246,21 @@ int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, i
   if (sh.variant == kVariantStream) {
     const int64_t nb = ceil_div(A.n, sh.rows);
     const size_t lds = sh.lds > 0 ? sh.lds : 16;
-    if (sh.nt)
-      hipLaunchKernelGGL((k_spmv_stream<256, 8, true>), dim3((unsigned)nb), dim3(256), lds, s, A.n,
-                         A.rowptr, A.col, A.val, x, y, sh.rows, remap);
-    else
-      hipLaunchKernelGGL((k_spmv_stream<256, 8, false>), dim3((unsigned)nb), dim3(256), lds, s,
-                         A.n, A.rowptr, A.col, A.val, x, y, sh.rows, remap);
+#define SPX_STREAM_LAUNCH(NT, VEC, U)                                                        \
+  hipLaunchKernelGGL((k_spmv_stream<256, U, NT, VEC>), dim3((unsigned)nb), dim3(256), lds, s, A.n, \
+                     A.rowptr, A.col, A.val, x, y, sh.rows, remap)
+    if (sh.vec) {
+      if (sh.nt)
+        SPX_STREAM_LAUNCH(true, true, 2);
+      else
+        SPX_STREAM_LAUNCH(false, true, 2);
+    } else {
+      if (sh.nt)
+        SPX_STREAM_LAUNCH(true, false, 8);
+      else
+        SPX_STREAM_LAUNCH(false, false, 8);
+    }
+#undef SPX_STREAM_LAUNCH
     return SPX_OK;
   }
   return sh.nt ? launch_vector<true>(A, sh.lanes, x, y, remap, s)

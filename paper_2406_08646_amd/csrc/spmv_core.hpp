@@ -89,4 +89,80 @@ __device__ __forceinline__ ACC stream_rows(const int32_t* __restrict__ rowptr,
   return s;
 }
 
+// Vector types for 16-byte loads.
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+typedef int32_t int4_t __attribute__((ext_vector_type(4)));
+
+// Four consecutive values at a 16-byte aligned address.
+template <bool NT>
+__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
+  const dbl2_t a = mload<NT>(reinterpret_cast<const dbl2_t*>(p));
+  const dbl2_t b = mload<NT>(reinterpret_cast<const dbl2_t*>(p + 2));
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+template <bool NT>
+__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+  const flt4_t a = mload<NT>(reinterpret_cast<const flt4_t*>(p));
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = a.z;
+  v[3] = a.w;
+}
+
+// Same contract as stream_rows, reading the run in aligned quads: every
+// lane issues one 16-byte column load and 16 (fp64) or 16 (fp32) bytes of
+// values per quad.  Entries of the quads that fall outside [t0, t1) are
+// loaded but not used; the value and column arrays are allocated with at
+// least three entries of padding so the last quad stays in bounds.
+template <int BLOCK, int U, typename VT, typename XT, typename ACC, bool NT = false>
+__device__ __forceinline__ ACC stream_rows_v4(const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col,
+                                              const VT* __restrict__ val,
+                                              const XT* __restrict__ x, int64_t r0, int64_t r1,
+                                              ACC* prod) {
+  const int tid = threadIdx.x;
+  const int32_t t0 = rowptr[r0];
+  const int32_t t1 = rowptr[r1];
+  const int32_t ta = t0 & ~3;
+  const int32_t nq = (t1 - ta + 3) >> 2;
+  for (int32_t qb = 0; qb < nq; qb += BLOCK * U) {
+    VT a[U][4];
+    int4_t c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t q = qb + u * BLOCK + tid;
+      if (q < nq) {
+        const int32_t e = ta + 4 * q;
+        c[u] = mload<NT>(reinterpret_cast<const int4_t*>(col + e));
+        load4<NT>(val + e, a[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t q = qb + u * BLOCK + tid;
+      if (q < nq) {
+        const int32_t e = ta + 4 * q;
+        const int32_t cc[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int32_t idx = e + j;
+          if (idx >= t0 && idx < t1) prod[idx - t0] = (ACC)a[u][j] * (ACC)x[cc[j]];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  ACC s = ACC(0);
+  if (tid < r1 - r0) {
+    const int32_t a = rowptr[r0 + tid] - t0, e = rowptr[r0 + tid + 1] - t0;
+    for (int32_t i = a; i < e; ++i) s += prod[i];
+  }
+  __syncthreads();
+  return s;
+}
+
 }  // namespace spx

@@ -43,6 +43,8 @@ OPT_SPMV_VARIANT = 4
 OPT_ROWS_PER_BLOCK = 5
 OPT_NONTEMPORAL = 6
 OPT_SOLVER_BLOCKS = 7
+OPT_QUAD_LOADS = 8
+OPT_VECTOR_BLOCKS = 9
 PROFILE_KINDS = ("spmv_dot_f64", "update_f64", "pupdate_f64", "spmv_dot_f32", "update_f32",
                  "pupdate_f32")
 

@@ -42,13 +42,16 @@ def test_config1_cg(orc):
     check_against_oracle(orc, ref, res, ores, b, 1e-8, lam_min)
 
 
-@pytest.mark.parametrize("variant,blocks", [(1, 0), (2, 0), (2, 37), (1, 2048)])
-def test_config1_cg_shapes(orc, variant, blocks):
+@pytest.mark.parametrize("variant,blocks,vblocks,quad", [(1, 0, 0, 1), (2, 0, 0, 1), (2, 37, 5, 1),
+                                                        (1, 2048, 3000, 1), (2, 0, 0, 0)])
+def test_config1_cg_shapes(orc, variant, blocks, vblocks, quad):
     spx = require_gpu()
     prob, _, b = W.config1()
     A = assemble(spx, prob)
     A.set_option(spx.OPT_SPMV_VARIANT, variant)
     A.set_option(spx.OPT_SOLVER_BLOCKS, blocks)
+    A.set_option(spx.OPT_VECTOR_BLOCKS, vblocks)
+    A.set_option(spx.OPT_QUAD_LOADS, quad)
     ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
     ores = orc.pcg(ref, b, 1e-8)
     res = A.cg_solve(dev(b), rtol=1e-8)

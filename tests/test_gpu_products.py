@@ -65,8 +65,10 @@ def test_matmult_variants(orc, variant, rows, case):
     yt = host(A.matmult_transpose(dev(x)))
     spmv_within(yt, orc.spmv_transpose(ref, x), orc.abs_spmv_transpose(ref, x))
     for nt in (0, 1):
-        A.set_option(spx.OPT_NONTEMPORAL, nt)
-        assert np.array_equal(bits(host(A.matmult(dev(x)))), bits(y))
+        for quad in (0, 1):
+            A.set_option(spx.OPT_NONTEMPORAL, nt)
+            A.set_option(spx.OPT_QUAD_LOADS, quad)
+            assert np.array_equal(bits(host(A.matmult(dev(x)))), bits(y))
 
 
 def test_matmult_long_and_empty_rows(orc):
