@@ -218,8 +218,8 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *   SPX_OPT_NONTEMPORAL: 1 (default) loads matrix values/columns
  *     non-temporally, 0 with the default cache policy.
  *   SPX_OPT_SOLVER_BLOCKS: workgroups of the solver's SpMV kernels (0 auto).
- *   SPX_OPT_QUAD_LOADS: 1 (default) streams values/columns with 16-byte
- *     loads in the stream variant, 0 with element loads.
+ *   SPX_OPT_QUAD_LOADS: 1 streams values/columns with 16-byte loads in the
+ *     stream variant, 0 (default) with element loads.
  *   SPX_OPT_VECTOR_BLOCKS: workgroups of the solver's vector kernels (0
  *     auto). */
 enum spx_option {

@@ -71,15 +71,19 @@ struct Shape {
 };
 
 // Calls epi(row, value) on the thread that owns each row of this
-// workgroup's share, value = sum_t val[t] x[col[t]] over the row.
+// workgroup's share, value = sum_t val[t] x[col[t]] over the row.  Tiles
+// are dealt out grid-stride by logical workgroup number, so at any moment
+// the grid works on one band of consecutive tiles and, with the XCD
+// renumbering, each XCD on a contiguous sub-band: the x entries the band
+// gathers stay in that XCD's L2.
 template <class SH, typename VT, typename XT, typename ACC, typename Epi>
 __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ rowptr,
                                          const int32_t* __restrict__ col,
                                          const VT* __restrict__ val, const XT* __restrict__ x,
                                          int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi) {
   if constexpr (SH::variant == kVariantStream) {
-    const Range rg = block_range(ceil_div(n, rows), lb, nb);
-    for (int64_t rb = rg.lo; rb < rg.hi; ++rb) {
+    const int64_t nrb = ceil_div(n, rows);
+    for (int64_t rb = lb; rb < nrb; rb += nb) {
       const int64_t r0 = rb * rows;
       const int64_t r1 = r0 + rows < n ? r0 + rows : n;
       ACC s;
@@ -92,9 +96,9 @@ __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ 
   } else {
     constexpr int L = SH::lanes;
     constexpr int RPB = kBlock / L;
-    const Range rg = block_range(ceil_div(n, RPB), lb, nb);
+    const int64_t ng = ceil_div(n, RPB);
     const int lane = threadIdx.x % L;
-    for (int64_t g = rg.lo; g < rg.hi; ++g) {
+    for (int64_t g = lb; g < ng; g += nb) {
       const int64_t row = g * RPB + threadIdx.x / L;
       if (row < n) {
         const ACC s = group_sum<L>(row_partial<L, VT, XT, ACC, SH::nt>(rowptr, col, val, x, row, lane));

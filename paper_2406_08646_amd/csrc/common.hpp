@@ -132,7 +132,7 @@ struct spx_matrix {
   int variant_opt = 0;   // SpmvVariant
   int rows_opt = 0;      // stream rows per workgroup, 0 = auto
   int nt_opt = 1;        // non-temporal matrix loads
-  int vec_opt = 1;       // quad loads in the stream walk
+  int vec_opt = 0;       // quad loads in the stream walk
   int fused_opt = 0;     // workgroups of the solver SpMV kernels, 0 = auto
   int vec_blocks_opt = 0;  // workgroups of the solver vector kernels, 0 = auto
   // optional per-kernel timing of solver iterations (HIP events)

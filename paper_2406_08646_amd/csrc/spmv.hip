@@ -201,7 +201,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   SpmvShape sh;
   sh.lanes = pick_lanes(A, h ? h->lanes_opt : 0);
   sh.nt = h ? h->nt_opt : 1;
-  sh.vec = h ? h->vec_opt : 1;
+  sh.vec = h ? h->vec_opt : 0;
   sh.rows = 0;
   sh.lds = 0;
   sh.variant = kVariantVector;
