@@ -124,6 +124,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=int, default=63)
     ap.add_argument("--cpu-calls", type=int, default=10)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a plain streaming kernel of known traffic (y = x + 1 over "
+                         "2^27 doubles: 1 GiB read, 1 GiB written) for counter calibration")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -144,6 +147,15 @@ def main() -> int:
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     N = args.grid
+
+    if args.calibrate:
+        ca = torch.ones(2**27, dtype=torch.float64, device=dev)
+        cb = torch.empty_like(ca)
+        for _ in range(3):
+            torch.add(ca, 1.0, out=cb)
+        torch.cuda.synchronize()
+        del ca, cb
+        log("calibration kernel done (3 x 1 GiB read + 1 GiB write)")
 
     log(f"generating the {N}^3-element workload")
     prob, x_np, b_np = W.config2(N)

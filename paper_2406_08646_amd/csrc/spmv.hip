@@ -219,7 +219,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   }
   // Automatic: stream when some row count keeps the tile small and rows
   // are not much longer than 64 entries on average.
-  for (int rows : {128, 64, 256, 32}) {
+  for (int rows : {64, 128, 32, 256}) {
     const int64_t tile = A.tile_nnz[rows_index(rows)];
     const size_t lds = (size_t)tile * sizeof(double);
     if (lds <= kStreamLdsCap && tile <= 64 * (int64_t)rows) {
