@@ -123,8 +123,10 @@ int spx_cg_solve_transpose(spx_handle h, const double* b, double* x, double rtol
  * lower precision than the solver's).  Iterative refinement: outer fp64
  * residual r = b - A x and norm; inner Jacobi-CG on fl32(A) d = fl32(r) from
  * d = 0 with fp32 matrix, vectors and SpMV but fp64 dot products, stopping
- * at ||r_in|| <= rtol_inner ||fl32(r)||; x += d in fp64; stop when
- * ||b - A x|| <= rtol_outer ||b||.  x: device float64[n], in/out (usually 0).
+ * at ||r_in|| <= max(rtol_inner ||fl32(r)||, rtol_outer ||b|| / 2) (the
+ * second term ends the last step once the outer target is in reach);
+ * x += d in fp64; stop when ||b - A x|| <= rtol_outer ||b||.
+ * x: device float64[n], in/out (usually 0).
  * outer_out: refinement steps; inner_out: total inner iterations.
  * Synchronises `stream`. */
 int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, double rtol_outer,

@@ -318,7 +318,9 @@ int oracle_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const doubl
  * fp64: r = b - A x in fp64, stop when ||r|| <= rtol_outer ||b||; inner
  * Jacobi-CG on fl32(A) d = fl32(r) from d = 0 with fp32 values, vectors
  * and SpMV, dot products formed and summed in fp64, stopping when
- * ||r_inner|| <= rtol_inner ||fl32(r)||; then x += d in fp64.
+ * ||r_inner|| <= max(rtol_inner ||fl32(r)||, rtol_outer ||b|| / 2) (the
+ * second term ends the last refinement step once the outer target is in
+ * reach); then x += d in fp64.
  * ---------------------------------------------------------------------- */
 
 static void spmv32(int64_t n, const int32_t* rowptr, const int32_t* col, const float* val,
@@ -366,6 +368,8 @@ int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const
       for (int64_t i = 0; i < n; i++) ri[i] = (float)r[i];
       for (int64_t i = 0; i < n; i++) d[i] = 0.0f;
       double r0 = sqrt(dot32(n, ri, ri));
+      double stop_at = rtol_inner * r0;
+      if (stop_at < 0.5 * rtol_outer * bnorm) stop_at = 0.5 * rtol_outer * bnorm;
       for (int64_t i = 0; i < n; i++) z[i] = dinv32[i] * ri[i];
       for (int64_t i = 0; i < n; i++) p[i] = z[i];
       double rho = dot32(n, ri, z);
@@ -383,7 +387,7 @@ int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const
         for (int64_t i = 0; i < n; i++) ri[i] = ri[i] - a32 * q[i];
         it++;
         double rr = sqrt(dot32(n, ri, ri));
-        if (rr <= rtol_inner * r0) break;
+        if (rr <= stop_at) break;
         for (int64_t i = 0; i < n; i++) z[i] = dinv32[i] * ri[i];
         double rho_new = dot32(n, ri, z);
         float b32 = (float)(rho_new / rho);

@@ -70,20 +70,35 @@ struct Shape {
   static constexpr bool vec = VEC;
 };
 
+// Share of `total` work items of logical workgroup lb out of nb: the items
+// are cut into 8 contiguous regions, one per XCD (the workgroups of XCD x
+// are the x-th contiguous group of logical numbers), and each region is
+// dealt out grid-stride to its group.  The XCD then sweeps its region as
+// one narrow band, so the x entries the band gathers stay in its L2.
+struct Share {
+  int64_t first, end, step;
+};
+
+__device__ __forceinline__ Share xcd_share(int64_t total, int64_t lb, int64_t nb) {
+  if (nb < 8) return {lb, total, nb};
+  const int64_t q = nb >> 3, rem = nb & 7;
+  const int64_t x = lb < (q + 1) * rem ? lb / (q + 1) : rem + (lb - (q + 1) * rem) / q;
+  const int64_t j = lb - (x * q + (x < rem ? x : rem));
+  const int64_t size = q + (x < rem ? 1 : 0);
+  const int64_t lo = total * x / 8, hi = total * (x + 1) / 8;
+  return {lo + j, hi, size};
+}
+
 // Calls epi(row, value) on the thread that owns each row of this
-// workgroup's share, value = sum_t val[t] x[col[t]] over the row.  Tiles
-// are dealt out grid-stride by logical workgroup number, so at any moment
-// the grid works on one band of consecutive tiles and, with the XCD
-// renumbering, each XCD on a contiguous sub-band: the x entries the band
-// gathers stay in that XCD's L2.
+// workgroup's share, value = sum_t val[t] x[col[t]] over the row.
 template <class SH, typename VT, typename XT, typename ACC, typename Epi>
 __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ rowptr,
                                          const int32_t* __restrict__ col,
                                          const VT* __restrict__ val, const XT* __restrict__ x,
                                          int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi) {
   if constexpr (SH::variant == kVariantStream) {
-    const int64_t nrb = ceil_div(n, rows);
-    for (int64_t rb = lb; rb < nrb; rb += nb) {
+    const Share sh = xcd_share(ceil_div(n, rows), lb, nb);
+    for (int64_t rb = sh.first; rb < sh.end; rb += sh.step) {
       const int64_t r0 = rb * rows;
       const int64_t r1 = r0 + rows < n ? r0 + rows : n;
       ACC s;
@@ -96,9 +111,9 @@ __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ 
   } else {
     constexpr int L = SH::lanes;
     constexpr int RPB = kBlock / L;
-    const int64_t ng = ceil_div(n, RPB);
+    const Share sh = xcd_share(ceil_div(n, RPB), lb, nb);
     const int lane = threadIdx.x % L;
-    for (int64_t g = lb; g < ng; g += nb) {
+    for (int64_t g = sh.first; g < sh.end; g += sh.step) {
       const int64_t row = g * RPB + threadIdx.x / L;
       if (row < n) {
         const ACC s = group_sum<L>(row_partial<L, VT, XT, ACC, SH::nt>(rowptr, col, val, x, row, lane));
@@ -397,7 +412,9 @@ __global__ __launch_bounds__(kBlock) void k_ir_finish(CgScalars* so, CgScalars* 
     if (so->status == SPX_OK && sqrt(t64) <= so->thresh) so->done = 1;
     si->rho[0] = trz;
     si->r0norm = sqrt(t32);
-    si->thresh = rtol_inner * si->r0norm;
+    // the inner solve stops at rtol_inner relative to its right-hand side,
+    // or as soon as the outer target is in reach (last refinement step)
+    si->thresh = fmax(rtol_inner * si->r0norm, 0.5 * so->thresh);
     si->rr = t32;
     si->iters = 0;
     si->status = SPX_OK;

@@ -209,7 +209,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   if (want == kVariantVector) return sh;
   const int rows_opt = h ? h->rows_opt : 0;
   if (rows_opt) {
-    const size_t lds = (size_t)A.tile_nnz[rows_index(rows_opt)] * sizeof(double);
+    const size_t lds = (size_t)(A.tile_nnz[rows_index(rows_opt)] + 8) * sizeof(double);
     if (lds <= kStreamLdsMax) {
       sh.variant = kVariantStream;
       sh.rows = rows_opt;
@@ -221,7 +221,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   // are not much longer than 64 entries on average.
   for (int rows : {64, 128, 32, 256}) {
     const int64_t tile = A.tile_nnz[rows_index(rows)];
-    const size_t lds = (size_t)tile * sizeof(double);
+    const size_t lds = (size_t)(tile + 8) * sizeof(double);
     if (lds <= kStreamLdsCap && tile <= 64 * (int64_t)rows) {
       sh.variant = kVariantStream;
       sh.rows = rows;
@@ -230,7 +230,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
     }
   }
   if (want == kVariantStream) {
-    const size_t lds = (size_t)A.tile_nnz[0] * sizeof(double);
+    const size_t lds = (size_t)(A.tile_nnz[0] + 8) * sizeof(double);
     if (lds <= kStreamLdsMax) {
       sh.variant = kVariantStream;
       sh.rows = 32;

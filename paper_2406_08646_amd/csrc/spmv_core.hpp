@@ -104,6 +104,23 @@ __device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
   v[2] = b.x;
   v[3] = b.y;
 }
+__device__ __forceinline__ void store4(double* p, const double (&v)[4]) {
+  dbl2_t a, b;
+  a.x = v[0];
+  a.y = v[1];
+  b.x = v[2];
+  b.y = v[3];
+  *reinterpret_cast<dbl2_t*>(p) = a;
+  *reinterpret_cast<dbl2_t*>(p + 2) = b;
+}
+__device__ __forceinline__ void store4(float* p, const float (&v)[4]) {
+  flt4_t a;
+  a.x = v[0];
+  a.y = v[1];
+  a.z = v[2];
+  a.w = v[3];
+  *reinterpret_cast<flt4_t*>(p) = a;
+}
 template <bool NT>
 __device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
   const flt4_t a = mload<NT>(reinterpret_cast<const flt4_t*>(p));
@@ -114,10 +131,14 @@ __device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
 }
 
 // Same contract as stream_rows, reading the run in aligned quads: every
-// lane issues one 16-byte column load and 16 (fp64) or 16 (fp32) bytes of
-// values per quad.  Entries of the quads that fall outside [t0, t1) are
-// loaded but not used; the value and column arrays are allocated with at
-// least three entries of padding so the last quad stays in bounds.
+// lane issues one 16-byte column load and 16 (fp32) or 2 x 16 (fp64) bytes
+// of values per quad and stores its four products with 16-byte LDS writes
+// at quad-aligned positions (prod[idx - ta], ta = t0 rounded down to 4), so
+// neither the global loads nor the LDS writes conflict.  The entries of the
+// first and last quad that lie outside [t0, t1) get a zero product without
+// touching x.  The value and column arrays carry at least three entries of
+// padding so the last quad stays inside the allocation; `prod` needs
+// t1 - ta + 3 elements.
 template <int BLOCK, int U, typename VT, typename XT, typename ACC, bool NT = false>
 __device__ __forceinline__ ACC stream_rows_v4(const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col,
@@ -147,18 +168,20 @@ __device__ __forceinline__ ACC stream_rows_v4(const int32_t* __restrict__ rowptr
       if (q < nq) {
         const int32_t e = ta + 4 * q;
         const int32_t cc[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+        ACC pr[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int32_t idx = e + j;
-          if (idx >= t0 && idx < t1) prod[idx - t0] = (ACC)a[u][j] * (ACC)x[cc[j]];
+          pr[j] = (idx >= t0 && idx < t1) ? (ACC)a[u][j] * (ACC)x[cc[j]] : ACC(0);
         }
+        store4(prod + 4 * q, pr);
       }
     }
   }
   __syncthreads();
   ACC s = ACC(0);
   if (tid < r1 - r0) {
-    const int32_t a = rowptr[r0 + tid] - t0, e = rowptr[r0 + tid + 1] - t0;
+    const int32_t a = rowptr[r0 + tid] - ta, e = rowptr[r0 + tid + 1] - ta;
     for (int32_t i = a; i < e; ++i) s += prod[i];
   }
   __syncthreads();
