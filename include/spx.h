@@ -149,19 +149,36 @@ int spx_batch_create(int32_t nsys, const spx_handle* hs, void* stream, spx_batch
 int spx_batch_destroy(spx_batch_handle b);
 int spx_batch_total_rows(spx_batch_handle b, int64_t* total);
 
-/* One persistent launch solves every system with Jacobi-CG to its own
- * ||r_s|| <= rtol ||b_s||.  Workgroups are split into one team per system
- * (team sizes from `team_weight_exponent`: a system's share of the resident
- * workgroups is proportional to (nnz_s * sqrt(n_s))^exponent, at least one
- * workgroup); teams synchronise with bounded device barriers.  lanes: lanes
- * per CSR row (0 = automatic).  b, x: packed device float64[total]; x is
- * the initial guess and receives the solutions.  iters_out / relres_out:
- * HOST int64[nsys] / float64[nsys] (relres here is the recursively updated
- * residual norm ratio).  Returns SPX_NOT_CONVERGED if any system hit
- * maxit, SPX_BREAKDOWN / SPX_ZERO_DIAGONAL if any system failed.
- * Synchronises `stream`. */
+/* Launch shape of spx_batch_cg (all fields may be 0 for automatic).
+ *   blocks: workgroups shared by the systems (0: 8 per compute unit;
+ *     raised to nsys if smaller).
+ *   rows_per_tile: rows per workgroup tile of the stream row walk (0 auto,
+ *     else 32, 64, 128 or 256).
+ *   weight_exponent: a running system's share of the workgroups is
+ *     proportional to nnz_s^weight_exponent, at least one (<= 0 means 1).
+ *   check_every: iterations between host polls, at which the workgroups are
+ *     re-split among the systems still running (0 means 20). */
+typedef struct spx_batch_tuning {
+  int32_t blocks;
+  int32_t rows_per_tile;
+  double weight_exponent;
+  int32_t check_every;
+  int32_t reserved;
+} spx_batch_tuning;
+
+/* Solves every system of the batch with Jacobi-CG to its own
+ * ||r_s|| <= rtol ||b_s|| (the single-system algorithm above, system by
+ * system).  All systems advance together and each CG phase is one launch
+ * for the whole batch: the workgroups form one team per running system;
+ * converged systems drop out and their workgroups go to the others at the
+ * next poll.  b, x: packed device float64[total]; x is the initial guess
+ * and receives the solutions.  tuning: may be NULL.  iters_out /
+ * relres_out: HOST int64[nsys] / float64[nsys]: iterations and true
+ * ||b_s - A_s x_s|| / ||b_s||.  Returns SPX_NOT_CONVERGED if a system hit
+ * maxit, SPX_BREAKDOWN / SPX_ZERO_DIAGONAL if a system failed (the others
+ * are still solved).  Synchronises `stream`. */
 int spx_batch_cg(spx_batch_handle b, const double* bvec, double* x, double rtol, int64_t maxit,
-                 double team_weight_exponent, int32_t lanes, void* stream, int64_t* iters_out,
+                 const spx_batch_tuning* tuning, void* stream, int64_t* iters_out,
                  double* relres_out);
 
 /* ---------------------------------------------------------------------------

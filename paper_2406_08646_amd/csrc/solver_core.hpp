@@ -1,0 +1,139 @@
+// Device building blocks shared by the single-system and batched solvers:
+// work shares, cross-workgroup partial sums and the row walk used by the
+// SpMV-shaped kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+#include "device.hpp"
+#include "spmv_core.hpp"
+
+namespace spx {
+namespace solver {
+
+constexpr int kBlock = 256;
+constexpr int kLds = kBlock / 64 + 1;
+
+struct Range {
+  int64_t lo, hi;
+};
+
+__device__ __forceinline__ Range block_range(int64_t total, int64_t b, int64_t nb) {
+  const int64_t per = (total + nb - 1) / nb;
+  int64_t lo = b * per;
+  if (lo > total) lo = total;
+  int64_t hi = lo + per;
+  if (hi > total) hi = total;
+  return {lo, hi};
+}
+
+// Sum of nparts partials; every workgroup gets the same value (fixed
+// strided split, fixed tree).
+__device__ __forceinline__ double reduce_all(const double* parts, int64_t nparts, double* lds) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += kBlock) s += parts[i];
+  s = block_sum<kBlock>(s, lds);
+  if (threadIdx.x == 0) lds[kLds - 1] = s;
+  __syncthreads();
+  s = lds[kLds - 1];
+  __syncthreads();
+  return s;
+}
+
+template <int V, int L, bool NT, bool VEC = false>
+struct Shape {
+  static constexpr int variant = V;
+  static constexpr int lanes = L;
+  static constexpr bool nt = NT;
+  static constexpr bool vec = VEC;
+};
+
+// Share of `total` work items of logical workgroup lb out of nb: the items
+// are cut into 8 contiguous regions, one per XCD (the workgroups of XCD x
+// are the x-th contiguous group of logical numbers), and each region is
+// dealt out grid-stride to its group.  The XCD then sweeps its region as
+// one narrow band, so the x entries the band gathers stay in its L2.
+struct Share {
+  int64_t first, end, step;
+};
+
+__device__ __forceinline__ Share xcd_share(int64_t total, int64_t lb, int64_t nb) {
+  if (nb < 8) return {lb, total, nb};
+  const int64_t q = nb >> 3, rem = nb & 7;
+  const int64_t x = lb < (q + 1) * rem ? lb / (q + 1) : rem + (lb - (q + 1) * rem) / q;
+  const int64_t j = lb - (x * q + (x < rem ? x : rem));
+  const int64_t size = q + (x < rem ? 1 : 0);
+  const int64_t lo = total * x / 8, hi = total * (x + 1) / 8;
+  return {lo + j, hi, size};
+}
+
+// Calls epi(row, value) on the thread that owns each row of this
+// workgroup's share, value = sum_t val[t] x[col[t]] over the row.
+template <class SH, typename VT, typename XT, typename ACC, typename Epi>
+__device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ col,
+                                         const VT* __restrict__ val, const XT* __restrict__ x,
+                                         int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi) {
+  if constexpr (SH::variant == kVariantStream) {
+    const Share sh = xcd_share(ceil_div(n, rows), lb, nb);
+    for (int64_t rb = sh.first; rb < sh.end; rb += sh.step) {
+      const int64_t r0 = rb * rows;
+      const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+      ACC s;
+      if constexpr (SH::vec)
+        s = stream_rows_v4<kBlock, 2, VT, XT, ACC, SH::nt>(rowptr, col, val, x, r0, r1, prod);
+      else
+        s = stream_rows<kBlock, 8, VT, XT, ACC, SH::nt>(rowptr, col, val, x, r0, r1, prod);
+      if (threadIdx.x < r1 - r0) epi(r0 + threadIdx.x, s);
+    }
+  } else {
+    constexpr int L = SH::lanes;
+    constexpr int RPB = kBlock / L;
+    const Share sh = xcd_share(ceil_div(n, RPB), lb, nb);
+    const int lane = threadIdx.x % L;
+    for (int64_t g = sh.first; g < sh.end; g += sh.step) {
+      const int64_t row = g * RPB + threadIdx.x / L;
+      if (row < n) {
+        const ACC s = group_sum<L>(row_partial<L, VT, XT, ACC, SH::nt>(rowptr, col, val, x, row, lane));
+        if (lane == 0) epi(row, s);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int64_t logical_block(int remap) {
+  return remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+}
+
+
+template <typename F>
+inline int with_shape(const SpmvShape& sh, F&& f) {
+  if (sh.variant == kVariantStream) {
+    if (sh.vec)
+      return sh.nt ? f(Shape<kVariantStream, 1, true, true>())
+                   : f(Shape<kVariantStream, 1, false, true>());
+    return sh.nt ? f(Shape<kVariantStream, 1, true>()) : f(Shape<kVariantStream, 1, false>());
+  }
+  switch (sh.lanes) {
+#define SPX_LANES_CASE(LL) \
+  case LL:                 \
+    return sh.nt ? f(Shape<kVariantVector, LL, true>()) : f(Shape<kVariantVector, LL, false>());
+    SPX_LANES_CASE(1)
+    SPX_LANES_CASE(2)
+    SPX_LANES_CASE(4)
+    SPX_LANES_CASE(8)
+    SPX_LANES_CASE(16)
+    SPX_LANES_CASE(32)
+    SPX_LANES_CASE(64)
+#undef SPX_LANES_CASE
+    default:
+      return set_error(SPX_INVALID_ARG, "unsupported lane count %d", sh.lanes);
+  }
+}
+
+
+}  // namespace solver
+}  // namespace spx

@@ -71,7 +71,7 @@ _SIGNATURES = {
     "spx_batch_create": [_i32, ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp)],
     "spx_batch_destroy": [_vp],
     "spx_batch_total_rows": [_vp, _pi64],
-    "spx_batch_cg": [_vp, _vp, _vp, _d, _i64, _d, _i32, _vp, _pi64, _pd],
+    "spx_batch_cg": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
     "spx_sddmm": [_vp, _vp, _vp, _vp, _vp],
     "spx_coo_gather": [_vp, _vp, _vp, _vp],
     "spx_coo_gather_blocks": [_vp, _vp, _vp, _i64, _vp, _vp],
@@ -333,6 +333,14 @@ def coo_preallocate(n: int, i: torch.Tensor, j: torch.Tensor, stream=None) -> Ma
     return Matrix(h, n, ncoo, i.device)
 
 
+class BatchTuning(ctypes.Structure):
+    """Launch shape of the batched solver (mirrors spx_batch_tuning)."""
+
+    _fields_ = [("blocks", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
+                ("weight_exponent", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Batch:
     """Several assembled matrices solved together by one persistent launch."""
 
@@ -361,16 +369,18 @@ class Batch:
         except Exception:
             pass
 
-    def batch_cg(self, b, x=None, rtol=1e-8, maxit=100000, team_weight_exponent=1.0, lanes=0,
-                 stream=None):
+    def batch_cg(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
+                 weight_exponent=1.0, check_every=20, stream=None):
         _dev(b, torch.float64, self.total, "b")
         x = torch.zeros_like(b) if x is None else _dev(x, torch.float64, self.total, "x")
         ns = len(self.mats)
         iters = (ctypes.c_int64 * ns)()
         rel = (ctypes.c_double * ns)()
+        tune = BatchTuning(blocks, rows_per_tile, weight_exponent, check_every, 0)
         rc = load_library().spx_batch_cg(self._h, _ptr(b), _ptr(x), rtol, maxit,
-                                         team_weight_exponent, lanes, _stream(stream),
-                                         ctypes.cast(iters, _pi64), ctypes.cast(rel, _pd))
+                                         ctypes.cast(ctypes.byref(tune), ctypes.c_void_p),
+                                         _stream(stream), ctypes.cast(iters, _pi64),
+                                         ctypes.cast(rel, _pd))
         _check(rc, _SOLVER_OUTCOMES)
         return x, list(iters), list(rel), rc
 
