@@ -22,7 +22,7 @@ def dev(a, dtype=None):
 
 def host(t):
     torch.cuda.synchronize()
-    return t.cpu().numpy()
+    return t.detach().cpu().numpy()
 
 
 def bits(a):
