@@ -240,7 +240,12 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *   SPX_OPT_QUAD_LOADS: 1 streams values/columns with 16-byte loads in the
  *     stream variant, 0 (default) with element loads.
  *   SPX_OPT_VECTOR_BLOCKS: workgroups of the solver's vector kernels (0
- *     auto). */
+ *     auto).
+ *   SPX_OPT_PIPELINE: 1 (default) lets the solver's SpMV kernels load the
+ *     next tile while reducing the current one (stream variant); reading it
+ *     returns the register depth in use (0 when off).
+ *   SPX_OPT_ROWS_PER_BLOCK_F32: rows per workgroup of the fp32 copy used by
+ *     the mixed-precision inner solve (0 auto: twice the fp64 tile). */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,
@@ -250,7 +255,9 @@ enum spx_option {
   SPX_OPT_NONTEMPORAL = 6,
   SPX_OPT_SOLVER_BLOCKS = 7,
   SPX_OPT_QUAD_LOADS = 8,
-  SPX_OPT_VECTOR_BLOCKS = 9
+  SPX_OPT_VECTOR_BLOCKS = 9,
+  SPX_OPT_PIPELINE = 10,
+  SPX_OPT_ROWS_PER_BLOCK_F32 = 11
 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);

@@ -119,6 +119,15 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
     case SPX_OPT_QUAD_LOADS:
       h->vec_opt = value ? 1 : 0;
       return SPX_OK;
+    case SPX_OPT_PIPELINE:
+      h->pipe_opt = value ? 1 : 0;
+      return SPX_OK;
+    case SPX_OPT_ROWS_PER_BLOCK_F32:
+      if (value != 0 && value != 32 && value != 64 && value != 128 && value != 256)
+        return set_error(SPX_INVALID_ARG, "set_option: rows per block %lld not 0/32/64/128/256",
+                         (long long)value);
+      h->rows32_opt = (int)value;
+      return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
   }
@@ -154,6 +163,12 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       return SPX_OK;
     case SPX_OPT_QUAD_LOADS:
       *value = h->vec_opt;
+      return SPX_OK;
+    case SPX_OPT_PIPELINE:
+      *value = solver_shape(h, h->A).pipe;
+      return SPX_OK;
+    case SPX_OPT_ROWS_PER_BLOCK_F32:
+      *value = spmv_shape32(h, h->A).rows;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

@@ -532,7 +532,7 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
   if (maxit > INT32_MAX - 1) maxit = INT32_MAX - 1;
   SPX_TRY(ensure_solver(h));
   const int64_t n = M.n;
-  const Op<double> A{n, M.rowptr, M.col, M.val, spmv_shape(h, M)};
+  const Op<double> A{n, M.rowptr, M.col, M.val, solver_shape(h, M)};
   double* r = h->work;
   double* p = h->work + n;
   double* q = h->work + 2 * n;
@@ -641,9 +641,9 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
   SPX_TRY(ensure_val32(h, s));
   const Csr& M = h->A;
   const int64_t n = M.n;
-  const SpmvShape sh = spmv_shape(h, M);
+  const SpmvShape sh = solver_shape(h, M);
   const Op<double> A64{n, M.rowptr, M.col, M.val, sh};
-  const Op<float> A32{n, M.rowptr, M.col, M.val32, sh};
+  const Op<float> A32{n, M.rowptr, M.col, M.val32, spmv_shape32(h, M)};
   float* r32 = h->work32;
   float* d32 = h->work32 + n;
   float* p32 = h->work32 + 2 * n;

@@ -89,6 +89,7 @@ struct SpmvShape {
   size_t lds;    // stream: LDS bytes per workgroup (for 8-byte products)
   int nt;        // non-temporal matrix loads
   int vec;       // stream: 16-byte quad loads
+  int pipe;      // stream, persistent kernels: next tile's loads issued early
 };
 
 // Device-resident solver scalars of one CG run.  rho[k & 1] holds r_k . z_k,
@@ -133,6 +134,8 @@ struct spx_matrix {
   int rows_opt = 0;      // stream rows per workgroup, 0 = auto
   int nt_opt = 1;        // non-temporal matrix loads
   int vec_opt = 0;       // quad loads in the stream walk
+  int pipe_opt = 1;      // pipelined tiles in the persistent solver kernels
+  int rows32_opt = 0;    // rows per tile of the fp32 operator, 0 = auto
   int fused_opt = 0;     // workgroups of the solver SpMV kernels, 0 = auto
   int vec_blocks_opt = 0;  // workgroups of the solver vector kernels, 0 = auto
   // optional per-kernel timing of solver iterations (HIP events)
@@ -152,6 +155,8 @@ int ensure_val32(spx_matrix* h, hipStream_t s);
 int pick_lanes(const Csr& A, int opt);
 int compute_tiles(Csr& A, hipStream_t s);
 SpmvShape spmv_shape(const spx_matrix* h, const Csr& A);
+SpmvShape spmv_shape32(const spx_matrix* h, const Csr& A);
+SpmvShape solver_shape(const spx_matrix* h, const Csr& A);
 int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, int remap,
                 hipStream_t s);
 int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,

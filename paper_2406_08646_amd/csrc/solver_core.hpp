@@ -43,13 +43,102 @@ __device__ __forceinline__ double reduce_all(const double* parts, int64_t nparts
   return s;
 }
 
-template <int V, int L, bool NT, bool VEC = false>
+// PIPE: 0 for the plain stream walk, else the per-thread register depth U
+// of the pipelined walk (a tile then holds at most kBlock * U entries).
+template <int V, int L, bool NT, bool VEC = false, int PIPE = 0>
 struct Shape {
   static constexpr int variant = V;
   static constexpr int lanes = L;
   static constexpr bool nt = NT;
   static constexpr bool vec = VEC;
+  static constexpr int pipe = PIPE;
 };
+
+// Loads one tile's values and columns (cnt <= kBlock * U entries from t0)
+// and this thread's row bounds into registers.
+template <int U, typename VT, bool NT>
+__device__ __forceinline__ void pipe_load(const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ col,
+                                          const VT* __restrict__ val, int64_t r0, int64_t r1,
+                                          int32_t t0, int32_t cnt, VT (&a)[U], int32_t (&c)[U],
+                                          int32_t& rs, int32_t& re) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int32_t i = u * kBlock + threadIdx.x;
+    if (i < cnt) {
+      a[u] = mload<NT>(val + t0 + i);
+      c[u] = mload<NT>(col + t0 + i);
+    }
+  }
+  if (threadIdx.x < r1 - r0) {
+    rs = rowptr[r0 + threadIdx.x];
+    re = rowptr[r0 + threadIdx.x + 1];
+  }
+}
+
+// The stream walk over a share of tiles with the next tile's loads issued
+// before the current tile's gathers and row sums, so each workgroup keeps
+// its matrix loads in flight across tiles.  Requires every tile to hold at
+// most kBlock * U entries.  Same results as the plain stream walk.
+template <int U, typename VT, typename XT, typename ACC, bool NT, typename Epi>
+__device__ __forceinline__ void stream_tiles_pipelined(int64_t n, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const VT* __restrict__ val,
+                                                       const XT* __restrict__ x, int rows,
+                                                       int64_t first, int64_t end, int64_t step,
+                                                       ACC* prod, Epi&& epi) {
+  if (first >= end) return;
+  int64_t rb = first;
+  int64_t r0 = rb * rows;
+  int64_t r1 = r0 + rows < n ? r0 + rows : n;
+  int32_t t0 = rowptr[r0];
+  int32_t cnt = rowptr[r1] - t0;
+  VT a[U];
+  int32_t c[U];
+  int32_t rs = 0, re = 0;
+  pipe_load<U, VT, NT>(rowptr, col, val, r0, r1, t0, cnt, a, c, rs, re);
+  for (;;) {
+    const int64_t nrb = rb + step;
+    const bool more = nrb < end;
+    int64_t nr0 = 0, nr1 = 0;
+    int32_t nt0 = 0, ncnt = 0;
+    VT an[U];
+    int32_t cn[U];
+    int32_t nrs = 0, nre = 0;
+    if (more) {
+      nr0 = nrb * rows;
+      nr1 = nr0 + rows < n ? nr0 + rows : n;
+      nt0 = rowptr[nr0];
+      ncnt = rowptr[nr1] - nt0;
+      pipe_load<U, VT, NT>(rowptr, col, val, nr0, nr1, nt0, ncnt, an, cn, nrs, nre);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t i = u * kBlock + threadIdx.x;
+      if (i < cnt) prod[i] = (ACC)a[u] * (ACC)x[c[u]];
+    }
+    __syncthreads();
+    ACC sum = ACC(0);
+    const bool owner = threadIdx.x < r1 - r0;
+    if (owner)
+      for (int32_t i = rs - t0; i < re - t0; ++i) sum += prod[i];
+    __syncthreads();
+    if (owner) epi(r0 + threadIdx.x, sum);
+    if (!more) break;
+    rb = nrb;
+    r0 = nr0;
+    r1 = nr1;
+    t0 = nt0;
+    cnt = ncnt;
+    rs = nrs;
+    re = nre;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = an[u];
+      c[u] = cn[u];
+    }
+  }
+}
 
 // Share of `total` work items of logical workgroup lb out of nb: the items
 // are cut into 8 contiguous regions, one per XCD (the workgroups of XCD x
@@ -77,7 +166,11 @@ __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ 
                                          const int32_t* __restrict__ col,
                                          const VT* __restrict__ val, const XT* __restrict__ x,
                                          int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi) {
-  if constexpr (SH::variant == kVariantStream) {
+  if constexpr (SH::variant == kVariantStream && SH::pipe) {
+    const Share sh = xcd_share(ceil_div(n, rows), lb, nb);
+    stream_tiles_pipelined<SH::pipe, VT, XT, ACC, SH::nt>(n, rowptr, col, val, x, rows, sh.first,
+                                                          sh.end, sh.step, prod, epi);
+  } else if constexpr (SH::variant == kVariantStream) {
     const Share sh = xcd_share(ceil_div(n, rows), lb, nb);
     for (int64_t rb = sh.first; rb < sh.end; rb += sh.step) {
       const int64_t r0 = rb * rows;
@@ -112,6 +205,12 @@ __device__ __forceinline__ int64_t logical_block(int remap) {
 template <typename F>
 inline int with_shape(const SpmvShape& sh, F&& f) {
   if (sh.variant == kVariantStream) {
+    if (sh.pipe == 8)
+      return sh.nt ? f(Shape<kVariantStream, 1, true, false, 8>())
+                   : f(Shape<kVariantStream, 1, false, false, 8>());
+    if (sh.pipe == 16)
+      return sh.nt ? f(Shape<kVariantStream, 1, true, false, 16>())
+                   : f(Shape<kVariantStream, 1, false, false, 16>());
     if (sh.vec)
       return sh.nt ? f(Shape<kVariantStream, 1, true, true>())
                    : f(Shape<kVariantStream, 1, false, true>());

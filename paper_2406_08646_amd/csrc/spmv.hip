@@ -202,6 +202,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   sh.lanes = pick_lanes(A, h ? h->lanes_opt : 0);
   sh.nt = h ? h->nt_opt : 1;
   sh.vec = h ? h->vec_opt : 0;
+  sh.pipe = 0;
   sh.rows = 0;
   sh.lds = 0;
   sh.variant = kVariantVector;
@@ -237,6 +238,41 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
       sh.lds = lds;
     }
   }
+  return sh;
+}
+
+namespace {
+// The pipelined walk holds a whole tile in registers.
+void set_pipe(const spx_matrix* h, const Csr& A, SpmvShape& sh) {
+  sh.pipe = 0;
+  if (!(h ? h->pipe_opt : 1) || sh.variant != kVariantStream || sh.vec) return;
+  const int64_t tile = A.tile_nnz[rows_index(sh.rows)];
+  if (tile <= 256 * 8)
+    sh.pipe = 8;
+  else if (tile <= 256 * 16)
+    sh.pipe = 16;
+}
+}  // namespace
+
+// Shape of the fp32 copy (mixed-precision inner solve): fp32 products take
+// half the LDS, so the tile doubles when it still fits.
+SpmvShape spmv_shape32(const spx_matrix* h, const Csr& A) {
+  SpmvShape sh = spmv_shape(h, A);
+  if (sh.variant != kVariantStream) return sh;
+  int want = h && h->rows32_opt ? h->rows32_opt : (h && h->rows_opt ? h->rows_opt : 2 * sh.rows);
+  if (want > 256) want = 256;
+  const size_t lds = (size_t)(A.tile_nnz[rows_index(want)] + 8) * sizeof(double);
+  if (lds / 2 <= kStreamLdsMax) {
+    sh.rows = want;
+    sh.lds = lds;
+  }
+  set_pipe(h, A, sh);
+  return sh;
+}
+
+SpmvShape solver_shape(const spx_matrix* h, const Csr& A) {
+  SpmvShape sh = spmv_shape(h, A);
+  set_pipe(h, A, sh);
   return sh;
 }
 

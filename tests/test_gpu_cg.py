@@ -61,6 +61,26 @@ def test_config1_cg_shapes(orc, variant, blocks, vblocks, quad):
     assert m.status == 0 and m.relres <= 1e-10
 
 
+@pytest.mark.parametrize("rows", [32, 64, 128, 256])
+def test_pipelined_walk_is_bitwise_identical(rows):
+    spx = require_gpu()
+    N = 14
+    prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(4).standard_normal(N**3)))
+    A = assemble(spx, prob)
+    b = dev(np.random.default_rng(5).uniform(-1, 1, prob.n))
+    A.set_option(spx.OPT_ROWS_PER_BLOCK, rows)
+    A.set_option(spx.OPT_ROWS_PER_BLOCK_F32, rows)
+    outs = []
+    for pipe in (1, 0):
+        A.set_option(spx.OPT_PIPELINE, pipe)
+        r = A.cg_solve(b, rtol=1e-10)
+        m = A.cg_solve_mixed(b, rtol_outer=1e-10, rtol_inner=1e-4)
+        outs.append((r.iters, host(r.x), m.inner, host(m.x)))
+    assert outs[0][0] == outs[1][0] and outs[0][2] == outs[1][2]
+    assert np.array_equal(bits(outs[0][1]), bits(outs[1][1]))
+    assert np.array_equal(bits(outs[0][3]), bits(outs[1][3]))
+
+
 def test_cg_check_every_does_not_change_the_result(orc):
     spx = require_gpu()
     prob, _, b = W.config1()
