@@ -74,6 +74,113 @@ def host_cpu():
     return model, os.cpu_count()
 
 
+def run_extras(spx, W, torch, np, dev, prob, x_np, log):
+    """Measurements of the other workloads, outside the timed steps: the
+    64-system batch (batched vs ensemble vs one solve per system), the
+    16-RHS SpMM on the full 3-D matrix and the 256^2 gradient."""
+    from paper_2406_08646_amd import autograd as AG, autotune
+
+    out = {}
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    def timed(fn, reps=1):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            best = ms if best is None else min(best, ms)
+        return best, r
+
+    # ---- multi-RHS SpMM on the full 3-D matrix
+    A = spx.coo_preallocate(prob.n, d(prob.i), d(prob.j))
+    A.set_values_coo(d(prob.v))
+    X = d(W.spmm_rhs(prob.n, 16))
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        A.spmm(X, Y)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for s_, e_ in ev:
+        s_.record()
+        A.spmm(X, Y)
+        e_.record()
+    torch.cuda.synchronize()
+    spmm_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
+    nnz = A.nnz
+    spmm_bytes = nnz * 12 + (prob.n + 1) * 4 + 2 * 16 * 8 * prob.n
+    xd, yd = d(x_np), torch.empty(prob.n, dtype=torch.float64, device=dev)
+    for s_, e_ in ev:
+        s_.record()
+        A.matmult(xd, yd)
+        e_.record()
+    torch.cuda.synchronize()
+    mv_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
+    out["spmm16"] = {"ms": round(spmm_ms, 4), "bytes": spmm_bytes,
+                     "gbs": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
+                     "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
+    A.destroy()
+    del X, Y
+    log(f"spmm16: {spmm_ms:.3f} ms")
+
+    # ---- 64-system batch
+    probs, bs = W.config4()
+    mats = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs]
+    for m, p in zip(mats, probs):
+        m.set_values_coo(d(p.v))
+    batch = spx.batch_create(mats)
+    bvec = d(np.concatenate(bs))
+    best = autotune.tune_batch(batch, bvec, rtol=1e-8, candidates=[
+        autotune.Candidate(1024, 0, 1.0), autotune.Candidate(2048, 0, 1.0),
+        autotune.Candidate(2048, 64, 1.0), autotune.Candidate(2048, 0, 1.25)])
+    kw = dict(blocks=best["blocks"], rows_per_tile=best["rows_per_tile"],
+              weight_exponent=best["weight_exponent"])
+    bt_ms, (xb, iters, relres, st) = timed(lambda: batch.batch_cg(bvec, rtol=1e-8, **kw), reps=3)
+    work = sum(it * cg_iteration_bytes(p.n, m.nnz) for it, p, m in zip(iters, probs, mats))
+    # one solve per system
+    seq_ms, _ = timed(lambda: [m.cg_solve(d_b, rtol=1e-8) for m, d_b in
+                               zip(mats, [d(b) for b in bs])])
+    # ensemble: the block-diagonal stack as one system (one global norm)
+    offs = np.cumsum([0] + [p.n for p in probs])
+    ei = np.concatenate([p.i + o for p, o in zip(probs, offs)]).astype(np.int32)
+    ej = np.concatenate([p.j + o for p, o in zip(probs, offs)]).astype(np.int32)
+    ev_ = np.concatenate([p.v for p in probs])
+    E = spx.coo_preallocate(int(offs[-1]), d(ei), d(ej))
+    E.set_values_coo(d(ev_))
+    ens_ms, ens = timed(lambda: E.cg_solve(bvec, rtol=1e-8), reps=2)
+    out["batched64"] = {"ms": round(bt_ms, 2), "solves_per_s": round(64 / (bt_ms * 1e-3), 1),
+                        "status": st, "max_relres": max(relres), "iters_max": max(iters),
+                        "iters_min": min(iters), "work_bytes": work,
+                        "gbs": round(work / (bt_ms * 1e-3) / 1e9, 1), "tuning": best,
+                        "sequential_ms": round(seq_ms, 2), "ensemble_ms": round(ens_ms, 2),
+                        "ensemble_iters": ens.iters,
+                        "speedup_vs_ensemble": round(ens_ms / bt_ms, 2),
+                        "speedup_vs_sequential": round(seq_ms / bt_ms, 2)}
+    log(f"batched: {bt_ms:.2f} ms, ensemble {ens_ms:.2f} ms, sequential {seq_ms:.2f} ms")
+    del batch, mats, E
+
+    # ---- gradient on 256 x 256 elements
+    N = 256
+    one = W.q1_poisson(N, 2, kappa=np.ones(N * N))
+    w = one.dv_dlogk
+    base = one.v - w
+    _, theta, target, b = W.config5(N)
+    G = spx.coo_preallocate(one.n, d(one.i), d(one.j))
+    T = spx.coo_preallocate(one.n, d(target.i), d(target.j))
+    T.set_values_coo(d(target.v))
+    ustar = T.cg_solve(d(b), rtol=1e-12).x
+    th = d(theta).requires_grad_(True)
+    bd, based, wd = d(b), d(base), d(w)
+    fw_ms, u = timed(lambda: AG.element_coefficient_solve(th, bd, G, based, wd, 16, rtol=1e-12))
+    loss = 0.5 * torch.sum((u - ustar) ** 2)
+    bw_ms, _ = timed(lambda: loss.backward())
+    out["gradient256"] = {"forward_ms": round(fw_ms, 2), "backward_ms": round(bw_ms, 2),
+                          "loss": float(loss)}
+    log(f"gradient: forward {fw_ms:.2f} ms backward {bw_ms:.2f} ms")
+    return out
+
+
 def cpu_baseline(grid: int, calls: int):
     """The oracle as it stands (plain C, one thread) on a bounded sample:
     its own COO assembly of the same 3-D Q1 workload at grid^3 elements,
@@ -124,6 +231,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=int, default=63)
     ap.add_argument("--cpu-calls", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched / SpMM / gradient measurements")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain streaming kernel of known traffic (y = x + 1 over "
                          "2^27 doubles: 1 GiB read, 1 GiB written) for counter calibration")
@@ -323,6 +432,8 @@ def main() -> int:
                                                max(1, sum(r["profile"][k][1] for r in recs)), 4),
                                         sum(r["profile"][k][1] for r in recs)]
                                     for k in spx.PROFILE_KINDS[:3]}
+    if not args.no_extras:
+        out["extras"] = run_extras(spx, W, torch, np, dev, prob, x_np, log)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on the {args.cpu_grid}^3-element sample")
         out["cpu_baseline"] = cpu_baseline(args.cpu_grid, args.cpu_calls)

@@ -241,9 +241,9 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *     stream variant, 0 (default) with element loads.
  *   SPX_OPT_VECTOR_BLOCKS: workgroups of the solver's vector kernels (0
  *     auto).
- *   SPX_OPT_PIPELINE: 1 (default) lets the solver's SpMV kernels load the
- *     next tile while reducing the current one (stream variant); reading it
- *     returns the register depth in use (0 when off).
+ *   SPX_OPT_PIPELINE: 1 lets the solver's SpMV kernels load the next tile
+ *     while reducing the current one (stream variant; default 0, measured
+ *     slower on gfx950); reading it returns the register depth in use.
  *   SPX_OPT_ROWS_PER_BLOCK_F32: rows per workgroup of the fp32 copy used by
  *     the mixed-precision inner solve (0 auto: twice the fp64 tile). */
 enum spx_option {

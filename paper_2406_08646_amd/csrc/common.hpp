@@ -134,7 +134,7 @@ struct spx_matrix {
   int rows_opt = 0;      // stream rows per workgroup, 0 = auto
   int nt_opt = 1;        // non-temporal matrix loads
   int vec_opt = 0;       // quad loads in the stream walk
-  int pipe_opt = 1;      // pipelined tiles in the persistent solver kernels
+  int pipe_opt = 0;      // pipelined tiles in the persistent solver kernels
   int rows32_opt = 0;    // rows per tile of the fp32 operator, 0 = auto
   int fused_opt = 0;     // workgroups of the solver SpMV kernels, 0 = auto
   int vec_blocks_opt = 0;  // workgroups of the solver vector kernels, 0 = auto

@@ -245,7 +245,7 @@ namespace {
 // The pipelined walk holds a whole tile in registers.
 void set_pipe(const spx_matrix* h, const Csr& A, SpmvShape& sh) {
   sh.pipe = 0;
-  if (!(h ? h->pipe_opt : 1) || sh.variant != kVariantStream || sh.vec) return;
+  if (!(h ? h->pipe_opt : 0) || sh.variant != kVariantStream || sh.vec) return;
   const int64_t tile = A.tile_nnz[rows_index(sh.rows)];
   if (tile <= 256 * 8)
     sh.pipe = 8;
