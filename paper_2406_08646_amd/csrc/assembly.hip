@@ -200,17 +200,40 @@ __global__ void k_max_row(const int32_t* __restrict__ rowptr, int64_t n, int32_t
   if ((threadIdx.x & 63) == 0) atomicMax(out, len);
 }
 
-// One thread per stored entry: in-order sum of its contributions.
-__global__ __launch_bounds__(256) void k_set_values(const int32_t* __restrict__ jmap,
-                                                    const int32_t* __restrict__ perm,
-                                                    const double* __restrict__ v, int64_t nnz,
-                                                    int mode, double* __restrict__ val) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nnz) return;
-  const int32_t q0 = jmap[t], q1 = jmap[t + 1];
-  double s = 0.0;
-  for (int32_t q = q0; q < q1; ++q) s += v[perm[q]];
-  val[t] = mode ? val[t] + s : s;
+// Tiled numeric stage: a workgroup owns kSvEntries consecutive entries.
+// Their contributions form one contiguous run of perm, which the workgroup
+// reads coalesced while gathering v into LDS; then each thread adds its
+// entry's contributions from LDS in order, from +0.0 (bitwise the same sums
+// as one thread walking perm).  A tile whose run exceeds the LDS capacity
+// is summed straight from global memory.
+constexpr int kSvEntries = 256;
+constexpr int kSvCap = 4096;
+
+__global__ __launch_bounds__(256) void k_set_values_tiled(const int32_t* __restrict__ jmap,
+                                                          const int32_t* __restrict__ perm,
+                                                          const double* __restrict__ v,
+                                                          int64_t nnz, int mode,
+                                                          double* __restrict__ val) {
+  __shared__ double lv[kSvCap];
+  const int64_t e0 = (int64_t)blockIdx.x * kSvEntries;
+  const int64_t e1 = e0 + kSvEntries < nnz ? e0 + kSvEntries : nnz;
+  const int32_t q0 = jmap[e0], q1 = jmap[e1];
+  const int64_t t = e0 + threadIdx.x;
+  if (q1 - q0 > kSvCap) {
+    if (t < e1) {
+      double s = 0.0;
+      for (int32_t q = jmap[t]; q < jmap[t + 1]; ++q) s += v[perm[q]];
+      val[t] = mode ? val[t] + s : s;
+    }
+    return;
+  }
+  for (int32_t q = q0 + threadIdx.x; q < q1; q += 256) lv[q - q0] = v[perm[q]];
+  __syncthreads();
+  if (t < e1) {
+    double s = 0.0;
+    for (int32_t q = jmap[t]; q < jmap[t + 1]; ++q) s += lv[q - q0];
+    val[t] = mode ? val[t] + s : s;
+  }
 }
 
 __global__ void k_expand_rows(const int32_t* __restrict__ rowptr, int64_t n,
@@ -528,8 +551,8 @@ extern "C" int spx_set_values_coo(spx_handle h, const double* v, int mode, void*
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t nnz = h->A.nnz;
   if (nnz > 0)
-    hipLaunchKernelGGL(k_set_values, dim3(grid_for(nnz, 256)), dim3(256), 0, s, h->jmap, h->perm,
-                       v, nnz, mode, h->A.val);
+    hipLaunchKernelGGL(k_set_values_tiled, dim3(grid_for(nnz, kSvEntries)), dim3(256), 0, s,
+                       h->jmap, h->perm, v, nnz, mode, h->A.val);
   h->valT_fresh = false;
   h->val32_fresh = false;
   h->valT32_fresh = false;

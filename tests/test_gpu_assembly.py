@@ -42,6 +42,20 @@ def test_random_coo_bitwise(orc, n, ncoo, neg, seed):
     check_full(orc, spx, prob)
 
 
+@pytest.mark.parametrize("n,ncoo,pool", [(10, 50000, 3), (1000, 300000, 40), (5000, 20000, 20000)])
+def test_long_duplicate_runs_bitwise(orc, n, ncoo, pool):
+    """Entries fed by thousands of contributions (runs longer than one LDS
+    tile of the numeric stage) next to ordinary ones."""
+    spx = require_gpu()
+    rng = np.random.default_rng(n + pool)
+    prob = W.random_coo(rng, n, ncoo, neg_frac=0.05, dup_pool=pool)
+    A, ref = check_full(orc, spx, prob)
+    v2 = rng.uniform(-1, 1, prob.ncoo)
+    A.set_values_coo(dev(v2), mode=spx.ADD_VALUES)
+    want = orc.coo_values(ref.jmap, ref.perm, v2, mode=1, val=ref.val)
+    assert np.array_equal(bits(host(A.get_csr()[2])), bits(want))
+
+
 def test_all_ignored_and_empty(orc):
     spx = require_gpu()
     i = np.array([-1, 3, -7], np.int32)
