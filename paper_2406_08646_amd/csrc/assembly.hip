@@ -188,16 +188,17 @@ __global__ void k_rowptr_tail(const K* __restrict__ keys, int64_t count, int cb,
   if (r == 0 && jmap) jmap[nnz] = (int32_t)count;
 }
 
-__global__ void k_max_row(const int32_t* __restrict__ rowptr, int64_t n, int32_t* __restrict__ out) {
+// Longest row: wave max, then workgroup max in LDS, one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_max_row(const int32_t* __restrict__ rowptr, int64_t n,
+                                                 int32_t* __restrict__ out) {
+  __shared__ int32_t wmax[4];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int32_t len = r < n ? rowptr[r + 1] - rowptr[r] : 0;
-  len = max(len, __shfl_xor(len, 32, 64));
-  len = max(len, __shfl_xor(len, 16, 64));
-  len = max(len, __shfl_xor(len, 8, 64));
-  len = max(len, __shfl_xor(len, 4, 64));
-  len = max(len, __shfl_xor(len, 2, 64));
-  len = max(len, __shfl_xor(len, 1, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, len);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])));
 }
 
 // Tiled numeric stage: a workgroup owns kSvEntries consecutive entries.
