@@ -88,7 +88,10 @@ __global__ __launch_bounds__(kBlock) void k_coo_count(const int32_t* __restrict_
 }
 
 // Stable compaction of the kept triplets into (key, k) pairs with
-// key = row << cb | col.  Thread t of a tile handles kIpt consecutive k.
+// key = row << cb | col.  Wave w of a tile owns the contiguous items
+// [w*512, (w+1)*512) and walks them in 64-item steps (coalesced loads); the
+// write position of an item is its wave's offset plus the number of kept
+// items before it, counted with ballots, so input order is preserved.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_coo_compact(const int32_t* __restrict__ i,
                                                         const int32_t* __restrict__ j,
@@ -96,25 +99,34 @@ __global__ __launch_bounds__(kBlock) void k_coo_compact(const int32_t* __restric
                                                         const uint32_t* __restrict__ tileoff,
                                                         K* __restrict__ keys,
                                                         uint32_t* __restrict__ vals) {
-  __shared__ uint32_t lds[kBlock / 64];
-  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kIpt;
+  __shared__ uint32_t wcount[kBlock / 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * (kIpt * 64);
+  const uint64_t lt = (1ull << lane) - 1ull;
   int32_t a[kIpt], b[kIpt];
-  uint32_t c = 0;
+  bool keep[kIpt];
+  uint32_t cnt = 0;
 #pragma unroll
   for (int s = 0; s < kIpt; ++s) {
-    const int64_t k = base + s;
+    const int64_t k = base + s * 64 + lane;
     a[s] = k < ncoo ? i[k] : -1;
     b[s] = k < ncoo ? j[k] : -1;
-    if (a[s] >= 0 && b[s] >= 0 && a[s] < n && b[s] < n) ++c;
+    keep[s] = a[s] >= 0 && b[s] >= 0 && a[s] < n && b[s] < n;
+    cnt += (uint32_t)__popcll(__ballot(keep[s]));
   }
-  uint32_t pos = block_exscan(c, lds, nullptr) + tileoff[blockIdx.x];
+  if (lane == 0) wcount[w] = cnt;
+  __syncthreads();
+  uint32_t pos = tileoff[blockIdx.x];
+  for (int ww = 0; ww < w; ++ww) pos += wcount[ww];
 #pragma unroll
   for (int s = 0; s < kIpt; ++s) {
-    if (a[s] >= 0 && b[s] >= 0 && a[s] < n && b[s] < n) {
-      keys[pos] = ((K)(uint32_t)a[s] << cb) | (K)(uint32_t)b[s];
-      vals[pos] = (uint32_t)(base + s);
-      ++pos;
+    const uint64_t m = __ballot(keep[s]);
+    if (keep[s]) {
+      const uint32_t at = pos + (uint32_t)__popcll(m & lt);
+      keys[at] = ((K)(uint32_t)a[s] << cb) | (K)(uint32_t)b[s];
+      vals[at] = (uint32_t)(base + s * 64 + lane);
     }
+    pos += (uint32_t)__popcll(m);
   }
 }
 
@@ -137,7 +149,9 @@ __global__ __launch_bounds__(kBlock) void k_heads_count(const K* __restrict__ ke
 }
 
 // For each run head q (entry t): jmap[t] = q, col[t], diagonal position,
-// and rowptr for every row that starts at t (empty rows included).
+// and rowptr for every row that starts at t (empty rows included).  Same
+// wave-ordered walk as the compaction: entry numbers are the tile offset
+// plus the heads before q, counted with ballots.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_heads_emit(const K* __restrict__ keys, int64_t count,
                                                        int cb, const uint32_t* __restrict__ tileoff,
@@ -145,34 +159,41 @@ __global__ __launch_bounds__(kBlock) void k_heads_emit(const K* __restrict__ key
                                                        int32_t* __restrict__ col,
                                                        int32_t* __restrict__ rowptr,
                                                        int32_t* __restrict__ dpos) {
-  __shared__ uint32_t lds[kBlock / 64];
-  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kIpt;
+  __shared__ uint32_t wcount[kBlock / 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * (kIpt * 64);
   const K cmask = cb >= (int)(8 * sizeof(K)) ? ~K(0) : ((K(1) << cb) - K(1));
-  K cur[kIpt];
+  const uint64_t lt = (1ull << lane) - 1ull;
+  K cur[kIpt], prev[kIpt];
   bool head[kIpt];
-  uint32_t c = 0;
-  K prev = base > 0 && base - 1 < count ? keys[base - 1] : K(0);
+  uint32_t cnt = 0;
 #pragma unroll
   for (int s = 0; s < kIpt; ++s) {
-    const int64_t q = base + s;
+    const int64_t q = base + s * 64 + lane;
     cur[s] = q < count ? keys[q] : K(0);
-    head[s] = q < count && (q == 0 || cur[s] != prev);
-    prev = cur[s];
-    c += head[s];
+    prev[s] = (q > 0 && q < count) ? keys[q - 1] : K(0);
+    head[s] = q < count && (q == 0 || cur[s] != prev[s]);
+    cnt += (uint32_t)__popcll(__ballot(head[s]));
   }
-  uint32_t t = block_exscan(c, lds, nullptr) + tileoff[blockIdx.x];
+  if (lane == 0) wcount[w] = cnt;
+  __syncthreads();
+  uint32_t pos = tileoff[blockIdx.x];
+  for (int ww = 0; ww < w; ++ww) pos += wcount[ww];
 #pragma unroll
   for (int s = 0; s < kIpt; ++s) {
-    if (!head[s]) continue;
-    const int64_t q = base + s;
-    const int64_t r = (int64_t)(cur[s] >> cb);
-    const int32_t cc = (int32_t)(cur[s] & cmask);
-    jmap[t] = (int32_t)q;
-    col[t] = cc;
-    if (r == cc) dpos[r] = (int32_t)t;
-    const int64_t pr = q == 0 ? -1 : (int64_t)(keys[q - 1] >> cb);
-    for (int64_t rr = pr + 1; rr <= r; ++rr) rowptr[rr] = (int32_t)t;
-    ++t;
+    const uint64_t m = __ballot(head[s]);
+    if (head[s]) {
+      const int64_t q = base + s * 64 + lane;
+      const uint32_t t = pos + (uint32_t)__popcll(m & lt);
+      const int64_t r = (int64_t)(cur[s] >> cb);
+      const int32_t cc = (int32_t)(cur[s] & cmask);
+      jmap[t] = (int32_t)q;
+      col[t] = cc;
+      if (r == cc) dpos[r] = (int32_t)t;
+      const int64_t pr = q == 0 ? -1 : (int64_t)(prev[s] >> cb);
+      for (int64_t rr = pr + 1; rr <= r; ++rr) rowptr[rr] = (int32_t)t;
+    }
+    pos += (uint32_t)__popcll(m);
   }
 }
 
