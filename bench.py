@@ -61,6 +61,40 @@ def cg_iteration_bytes(n: int, nnz: int) -> int:
     return spmv_bytes(n, nnz) + 7 * 8 * n + 4 * 8 * n
 
 
+DOMINANT_SOURCES = ("paper_2406_08646_amd/csrc/cg.hip", "paper_2406_08646_amd/csrc/solver_core.hpp",
+                    "paper_2406_08646_amd/csrc/spmv_core.hpp", "paper_2406_08646_amd/csrc/device.hpp",
+                    "paper_2406_08646_amd/csrc/common.hpp")
+TRAFFIC_SUMMARY = "profiles/traffic_counters_q1_3d_127.md"
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources that define the dominant kernel; a counter
+    summary taken from other sources is stale."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for rel in DOMINANT_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or was taken from other sources."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    with open(path) as f:
+        for line in f:
+            if line.startswith("dominant-kernel-traffic:"):
+                fields = dict(kv.split("=") for kv in line.split(":", 1)[1].split())
+                if fields.get("source") == want:
+                    return int(fields["bytes_per_launch"])
+    return None
+
+
 def host_cpu():
     model = platform.processor() or ""
     try:
@@ -436,9 +470,10 @@ def main() -> int:
         ach = mv_bytes / (avg_ms * 1e-3) / 1e9
         out["roofline"] = {
             "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
             "kernel": "k_cg_spmv_dot (q = A p with the p.q partial, FP64)",
             "bytes_per_launch": mv_bytes, "avg_launch_ms": round(avg_ms, 4), "launches": cnt,
+            "source_hash": kernel_source_hash(),
         }
         out["solver_kernels_ms"] = {k: [round(sum(r["profile"][k][0] for r in recs) /
                                                max(1, sum(r["profile"][k][1] for r in recs)), 4),
