@@ -231,7 +231,9 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *     events on the solver's stream and accumulates their durations (read
  *     with spx_get_profile).
  *   SPX_OPT_SPMV_VARIANT: 0 auto, 1 vector (L lanes per row), 2 stream
- *     (rows of a workgroup streamed through LDS).
+ *     (rows of a workgroup streamed through LDS), 3 DMA (the stream walk
+ *     with columns and values moved into LDS by direct 16-byte loads, two
+ *     staging buffers in the solver kernels).
  *   SPX_OPT_ROWS_PER_BLOCK: stream variant rows per workgroup (0 auto, else
  *     32, 64, 128 or 256).
  *   SPX_OPT_NONTEMPORAL: 1 (default) loads matrix values/columns

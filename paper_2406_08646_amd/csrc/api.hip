@@ -96,8 +96,8 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
       h->profile = value ? 1 : 0;
       return SPX_OK;
     case SPX_OPT_SPMV_VARIANT:
-      if (value < 0 || value > 2)
-        return set_error(SPX_INVALID_ARG, "set_option: variant %lld not in 0..2", (long long)value);
+      if (value < 0 || value > 3)
+        return set_error(SPX_INVALID_ARG, "set_option: variant %lld not in 0..3", (long long)value);
       h->variant_opt = (int)value;
       return SPX_OK;
     case SPX_OPT_ROWS_PER_BLOCK:

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const int32_t* __
                                                     const double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
                                                     const double* __restrict__ dinv,
-                                                    double* __restrict__ P, int rows, int remap) {
+                                                    double* __restrict__ P, int rows, int remap, int64_t tile) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   const int64_t nb = gridDim.x;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const int32_t* __
                                          rz += ri * zi;
                                          rr += ri * ri;
                                          bb += bi * bi;
-                                       });
+                                       }, tile);
   rz = block_sum<kBlock>(rz, lds);
   rr = block_sum<kBlock>(rr, lds);
   bb = block_sum<kBlock>(bb, lds);
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __
                                                     const VT* __restrict__ val,
                                                     const VT* __restrict__ p, VT* __restrict__ q,
                                                     const CgScalars* __restrict__ st,
-                                                    double* __restrict__ P1, int rows, int remap) {
+                                                    double* __restrict__ P1, int rows, int remap, int64_t tile) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   if (st->done) return;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __
                            reinterpret_cast<VT*>(smem), [&](int64_t row, VT s) {
                              q[row] = s;
                              dot += (double)p[row] * (double)s;
-                           });
+                           }, tile);
   dot = block_sum<kBlock>(dot, lds);
   if (threadIdx.x == 0) P1[blockIdx.x] = dot;
 }
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_resnorm(int64_t n, const int32_t* __
                                                     const double* __restrict__ val,
                                                     const double* __restrict__ b,
                                                     const double* __restrict__ x,
-                                                    double* __restrict__ P, int rows, int remap) {
+                                                    double* __restrict__ P, int rows, int remap, int64_t tile) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   double rr = 0.0;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_resnorm(int64_t n, const int32_t* __
                                        reinterpret_cast<double*>(smem), [&](int64_t row, double ax) {
                                          const double ri = b[row] - ax;
                                          rr += ri * ri;
-                                       });
+                                       }, tile);
   rr = block_sum<kBlock>(rr, lds);
   if (threadIdx.x == 0) P[blockIdx.x] = rr;
 }
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
     int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ b, const double* __restrict__ x,
     const float* __restrict__ dinv32, float* __restrict__ r32, float* __restrict__ d32,
-    float* __restrict__ p32, double* __restrict__ P, int rows, int remap) {
+    float* __restrict__ p32, double* __restrict__ P, int rows, int remap, int64_t tile) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   const int64_t nb = gridDim.x;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
                                          p32[row] = zf;
                                          rz += (double)rf * (double)zf;
                                          rr32 += (double)rf * (double)rf;
-                                       });
+                                       }, tile);
   rr64 = block_sum<kBlock>(rr64, lds);
   rz = block_sum<kBlock>(rz, lds);
   rr32 = block_sum<kBlock>(rr32, lds);
@@ -386,6 +386,7 @@ struct Op {
 
 template <typename VT>
 size_t shape_lds(const SpmvShape& sh) {
+  if (sh.variant == kVariantDma) return 2 * ((dma_buffer_bytes(sh.tile, sizeof(VT)) + 15) & ~size_t(15));
   if (sh.variant != kVariantStream) return 0;
   return sh.lds / sizeof(double) * sizeof(VT);
 }
@@ -408,7 +409,7 @@ int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* 
       hipEvent_t* e = evs ? evs + 6 * c : nullptr;
       if (e) (void)hipEventRecord(e[0], s);
       hipLaunchKernelGGL((k_cg_spmv<SH, VT>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr, A.col,
-                         A.val, p, q, st, P1, A.sh.rows, h->xcd_remap);
+                         A.val, p, q, st, P1, A.sh.rows, h->xcd_remap, A.sh.tile);
       if (e) (void)hipEventRecord(e[1], s);
       if (e) (void)hipEventRecord(e[2], s);
       hipLaunchKernelGGL((k_cg_update<VT>), dim3(G2), dim3(kBlock), 0, s, A.n, x, r, p, q, dinv, st,
@@ -516,7 +517,7 @@ int enqueue_resnorm(spx_matrix* h, const Op<double>& A, const double* b, const d
   SPX_TRY(with_shape(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_resnorm<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, A.n,
-                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, h->xcd_remap);
+                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, h->xcd_remap, A.sh.tile);
     return SPX_OK;
   }));
   hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G);
@@ -545,7 +546,7 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_cg_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
                        M.rowptr, M.col, M.val, b, x, r, p, h->dinv, h->partials, A.sh.rows,
-                       h->xcd_remap);
+                       h->xcd_remap, A.sh.tile);
     return SPX_OK;
   }));
   hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G,
@@ -666,7 +667,7 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_ir_residual<SH>), dim3(G), dim3(kBlock), shape_lds<double>(sh), s, n,
                          M.rowptr, M.col, M.val, b, x, h->dinv32, r32, d32, p32, h->partials,
-                         sh.rows, h->xcd_remap);
+                         sh.rows, h->xcd_remap, sh.tile);
       return SPX_OK;
     }));
     hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, so, si, h->partials, (int64_t)G,

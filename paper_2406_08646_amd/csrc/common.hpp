@@ -67,7 +67,7 @@ int exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count, uint32_
 
 // -------------------------------------------------------------- matrix
 // How products walk a matrix (chosen once per pattern, see spmv.hip).
-enum SpmvVariant { kVariantAuto = 0, kVariantVector = 1, kVariantStream = 2 };
+enum SpmvVariant { kVariantAuto = 0, kVariantVector = 1, kVariantStream = 2, kVariantDma = 3 };
 
 struct Csr {
   int64_t n = 0, nnz = 0;
@@ -90,6 +90,7 @@ struct SpmvShape {
   int nt;        // non-temporal matrix loads
   int vec;       // stream: 16-byte quad loads
   int pipe;      // stream, persistent kernels: next tile's loads issued early
+  int64_t tile;  // stream / DMA: most entries in one tile of `rows` rows
 };
 
 // Device-resident solver scalars of one CG run.  rho[k & 1] holds r_k . z_k,

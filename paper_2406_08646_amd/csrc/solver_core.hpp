@@ -161,12 +161,67 @@ __device__ __forceinline__ Share xcd_share(int64_t total, int64_t lb, int64_t nb
 
 // Calls epi(row, value) on the thread that owns each row of this
 // workgroup's share, value = sum_t val[t] x[col[t]] over the row.
+// The DMA walk over a share of tiles, double-buffered: while a tile's rows
+// are being added, the next tile's direct loads are already in flight.
+// `lds` holds two staging buffers for tiles of up to `tile` entries.
+template <typename VT, typename XT, typename ACC, typename Epi>
+__device__ __forceinline__ void dma_tiles(int64_t n, const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ col,
+                                          const VT* __restrict__ val, const XT* __restrict__ x,
+                                          int rows, int64_t tile, int64_t first, int64_t end,
+                                          int64_t step, char* lds, Epi&& epi) {
+  if (first >= end) return;
+  const int64_t capc = (tile + 8 + 3) & ~int64_t(3);
+  const size_t buf = (dma_buffer_bytes(tile, sizeof(VT)) + 15) & ~size_t(15);
+  int32_t* lc[2] = {reinterpret_cast<int32_t*>(lds), reinterpret_cast<int32_t*>(lds + buf)};
+  VT* lv[2] = {reinterpret_cast<VT*>(lds + 4 * capc), reinterpret_cast<VT*>(lds + buf + 4 * capc)};
+  int64_t rb = first;
+  int64_t r0 = rb * rows;
+  int64_t r1 = r0 + rows < n ? r0 + rows : n;
+  int32_t t0 = rowptr[r0], t1 = rowptr[r1];
+  dma_issue<kBlock, VT>(col, val, t0, t1, lc[0], lv[0]);
+  int cur = 0;
+  for (;;) {
+    const bool owner = threadIdx.x < r1 - r0;
+    int32_t rs = 0, re = 0;
+    if (owner) {
+      rs = rowptr[r0 + threadIdx.x];
+      re = rowptr[r0 + threadIdx.x + 1];
+    }
+    dma_products<kBlock, VT, XT, ACC>(x, t0, t1, lc[cur], lv[cur]);
+    const int64_t nrb = rb + step;
+    const bool more = nrb < end;
+    int64_t nr0 = 0, nr1 = 0;
+    int32_t nt0 = 0, nt1 = 0;
+    if (more) {
+      nr0 = nrb * rows;
+      nr1 = nr0 + rows < n ? nr0 + rows : n;
+      nt0 = rowptr[nr0];
+      nt1 = rowptr[nr1];
+      dma_issue<kBlock, VT>(col, val, nt0, nt1, lc[cur ^ 1], lv[cur ^ 1]);
+    }
+    if (owner) epi(r0 + threadIdx.x, dma_row_sum<VT, ACC>(lv[cur], t0, rs, re));
+    if (!more) break;
+    rb = nrb;
+    r0 = nr0;
+    r1 = nr1;
+    t0 = nt0;
+    t1 = nt1;
+    cur ^= 1;
+  }
+}
+
 template <class SH, typename VT, typename XT, typename ACC, typename Epi>
 __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ rowptr,
                                          const int32_t* __restrict__ col,
                                          const VT* __restrict__ val, const XT* __restrict__ x,
-                                         int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi) {
-  if constexpr (SH::variant == kVariantStream && SH::pipe) {
+                                         int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi,
+                                         int64_t tile = 0) {
+  if constexpr (SH::variant == kVariantDma) {
+    const Share sh = xcd_share(ceil_div(n, rows), lb, nb);
+    dma_tiles<VT, XT, ACC>(n, rowptr, col, val, x, rows, tile, sh.first, sh.end, sh.step,
+                           reinterpret_cast<char*>(prod), epi);
+  } else if constexpr (SH::variant == kVariantStream && SH::pipe) {
     const Share sh = xcd_share(ceil_div(n, rows), lb, nb);
     stream_tiles_pipelined<SH::pipe, VT, XT, ACC, SH::nt>(n, rowptr, col, val, x, rows, sh.first,
                                                           sh.end, sh.step, prod, epi);
@@ -204,6 +259,7 @@ __device__ __forceinline__ int64_t logical_block(int remap) {
 
 template <typename F>
 inline int with_shape(const SpmvShape& sh, F&& f) {
+  if (sh.variant == kVariantDma) return f(Shape<kVariantDma, 1, false>());
   if (sh.variant == kVariantStream) {
     if (sh.pipe == 8)
       return sh.nt ? f(Shape<kVariantStream, 1, true, false, 8>())

@@ -60,6 +60,33 @@ __global__ void k_zero_i32(int32_t* p, int64_t count) {
   if (t < count) p[t] = 0;
 }
 
+// One tile per workgroup, its columns and values staged by direct loads.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_spmv_dma(int64_t n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ y, int rows, int remap,
+                                                    int64_t tile) {
+  extern __shared__ __align__(16) char smem[];
+  const int64_t capc = (tile + 8 + 3) & ~int64_t(3);
+  int32_t* lcol = reinterpret_cast<int32_t*>(smem);
+  double* lval = reinterpret_cast<double*>(smem + 4 * capc);
+  const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t r0 = b * rows;
+  const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+  const int32_t t0 = rowptr[r0], t1 = rowptr[r1];
+  dma_issue<BLOCK, double>(col, val, t0, t1, lcol, lval);
+  const bool owner = threadIdx.x < r1 - r0;
+  int32_t rs = 0, re = 0;
+  if (owner) {
+    rs = rowptr[r0 + threadIdx.x];
+    re = rowptr[r0 + threadIdx.x + 1];
+  }
+  dma_products<BLOCK, double, double, double>(x, t0, t1, lcol, lval);
+  if (owner) y[r0 + threadIdx.x] = dma_row_sum<double, double>(lval, t0, rs, re);
+}
+
 // Largest entry count of any block of 32, 64, 128 and 256 consecutive rows.
 __global__ void k_tile_nnz(const int32_t* __restrict__ rowptr, int64_t n, int32_t* __restrict__ out) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // index of a 32-row block
@@ -206,15 +233,32 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   sh.rows = 0;
   sh.lds = 0;
   sh.variant = kVariantVector;
+  sh.tile = 0;
   const int want = h ? h->variant_opt : 0;
   if (want == kVariantVector) return sh;
   const int rows_opt = h ? h->rows_opt : 0;
+  if (want == kVariantDma) {
+    // two staging buffers per workgroup in the solver kernels
+    for (int rows : {64, 32, 128, 256}) {
+      if (rows_opt && rows != rows_opt) continue;
+      const int64_t tile = A.tile_nnz[rows_index(rows)];
+      if (2 * dma_buffer_bytes(tile, sizeof(double)) + 64 <= kStreamLdsMax) {
+        sh.variant = kVariantDma;
+        sh.rows = rows;
+        sh.tile = tile;
+        sh.lds = dma_buffer_bytes(tile, sizeof(double));
+        return sh;
+      }
+    }
+    return sh;
+  }
   if (rows_opt) {
     const size_t lds = (size_t)(A.tile_nnz[rows_index(rows_opt)] + 8) * sizeof(double);
     if (lds <= kStreamLdsMax) {
       sh.variant = kVariantStream;
       sh.rows = rows_opt;
       sh.lds = lds;
+      sh.tile = A.tile_nnz[rows_index(rows_opt)];
     }
     return sh;
   }
@@ -227,6 +271,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
       sh.variant = kVariantStream;
       sh.rows = rows;
       sh.lds = lds;
+      sh.tile = tile;
       return sh;
     }
   }
@@ -236,6 +281,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
       sh.variant = kVariantStream;
       sh.rows = 32;
       sh.lds = lds;
+      sh.tile = A.tile_nnz[0];
     }
   }
   return sh;
@@ -258,6 +304,15 @@ void set_pipe(const spx_matrix* h, const Csr& A, SpmvShape& sh) {
 // half the LDS, so the tile doubles when it still fits.
 SpmvShape spmv_shape32(const spx_matrix* h, const Csr& A) {
   SpmvShape sh = spmv_shape(h, A);
+  if (sh.variant == kVariantDma) {
+    const int want = h && h->rows32_opt ? h->rows32_opt : sh.rows;
+    const int64_t tile = A.tile_nnz[rows_index(want)];
+    if (2 * dma_buffer_bytes(tile, sizeof(float)) + 64 <= kStreamLdsMax) {
+      sh.rows = want;
+      sh.tile = tile;
+    }
+    return sh;
+  }
   if (sh.variant != kVariantStream) return sh;
   int want = h && h->rows32_opt ? h->rows32_opt : (h && h->rows_opt ? h->rows_opt : 2 * sh.rows);
   if (want > 256) want = 256;
@@ -265,6 +320,7 @@ SpmvShape spmv_shape32(const spx_matrix* h, const Csr& A) {
   if (lds / 2 <= kStreamLdsMax) {
     sh.rows = want;
     sh.lds = lds;
+    sh.tile = A.tile_nnz[rows_index(want)];
   }
   set_pipe(h, A, sh);
   return sh;
@@ -279,6 +335,13 @@ SpmvShape solver_shape(const spx_matrix* h, const Csr& A) {
 int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, int remap,
                 hipStream_t s) {
   if (A.n == 0) return SPX_OK;
+  if (sh.variant == kVariantDma) {
+    const int64_t nb = ceil_div(A.n, sh.rows);
+    hipLaunchKernelGGL((k_spmv_dma<256>), dim3((unsigned)nb), dim3(256),
+                       dma_buffer_bytes(sh.tile, sizeof(double)), s, A.n, A.rowptr, A.col, A.val,
+                       x, y, sh.rows, remap, sh.tile);
+    return SPX_OK;
+  }
   if (sh.variant == kVariantStream) {
     const int64_t nb = ceil_div(A.n, sh.rows);
     const size_t lds = sh.lds > 0 ? sh.lds : 16;

@@ -188,4 +188,71 @@ __device__ __forceinline__ ACC stream_rows_v4(const int32_t* __restrict__ rowptr
   return s;
 }
 
+// ---------------------------------------------------------------- DMA walk
+// gfx950 loads global memory straight into LDS (global_load_lds_dwordx4:
+// lane l of a wave writes its 16 bytes at the wave's LDS base + 16 l), so a
+// tile's columns and values can be staged without passing through
+// registers.  Columns are moved in aligned quads (ca = t0 rounded down to
+// 4), values in aligned 16-byte groups (va = t0 rounded down to 16 /
+// sizeof(VT)); the few entries outside [t0, t1) that ride along are never
+// used.  The value and column arrays carry padding so the last group stays
+// inside the allocation.
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef const __attribute__((address_space(1))) void glb_void_t;
+
+__device__ __forceinline__ int32_t dma_col_base(int32_t t0) { return t0 & ~3; }
+template <typename VT>
+__device__ __forceinline__ int32_t dma_val_base(int32_t t0) {
+  return t0 & ~(int32_t)(16 / sizeof(VT) - 1);
+}
+
+// Issues the direct loads of entries [t0, t1) into lcol / lval.
+template <int BLOCK, typename VT>
+__device__ __forceinline__ void dma_issue(const int32_t* __restrict__ col,
+                                          const VT* __restrict__ val, int32_t t0, int32_t t1,
+                                          int32_t* lcol, VT* lval) {
+  constexpr int EV = 16 / sizeof(VT);
+  const int32_t ca = dma_col_base(t0), nq = (t1 - ca + 3) >> 2;
+  const int32_t va = dma_val_base<VT>(t0), nv = (t1 - va + EV - 1) / EV;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int32_t qb = w * 64; qb < nq; qb += BLOCK)
+    if (qb + l < nq)
+      __builtin_amdgcn_global_load_lds((glb_void_t*)(col + ca + 4 * (qb + l)),
+                                       (lds_void_t*)(lcol + 4 * qb), 16, 0, 0);
+  for (int32_t vb = w * 64; vb < nv; vb += BLOCK)
+    if (vb + l < nv)
+      __builtin_amdgcn_global_load_lds((glb_void_t*)(val + va + EV * (vb + l)),
+                                       (lds_void_t*)(lval + EV * vb), 16, 0, 0);
+}
+
+// Waits for the tile's direct loads, forms the products in place
+// (lval[i - va] = val * x[col]), and returns in thread t < r1 - r0 the sum
+// of row r0 + t in entry order (rs / re: that row's bounds, loaded by the
+// caller).  Leaves the workgroup synchronised.
+template <int BLOCK, typename VT, typename XT, typename ACC>
+__device__ __forceinline__ void dma_products(const XT* __restrict__ x, int32_t t0, int32_t t1,
+                                             const int32_t* lcol, VT* lval) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const int32_t ca = dma_col_base(t0), va = dma_val_base<VT>(t0);
+  for (int32_t i = t0 + threadIdx.x; i < t1; i += BLOCK)
+    lval[i - va] = (ACC)lval[i - va] * (ACC)x[lcol[i - ca]];
+  __syncthreads();
+}
+
+template <typename VT, typename ACC>
+__device__ __forceinline__ ACC dma_row_sum(const VT* lval, int32_t t0, int32_t rs, int32_t re) {
+  const int32_t va = dma_val_base<VT>(t0);
+  ACC s = ACC(0);
+  for (int32_t i = rs - va; i < re - va; ++i) s += (ACC)lval[i];
+  return s;
+}
+
+// LDS bytes of one staging buffer for tiles of up to `tile` entries.
+__host__ __device__ inline size_t dma_buffer_bytes(int64_t tile, size_t vbytes) {
+  const int64_t capc = (tile + 8 + 3) & ~int64_t(3);
+  const int64_t capv = tile + 16;
+  return 4 * (size_t)capc + vbytes * (size_t)capv;
+}
+
 }  // namespace spx

@@ -43,7 +43,8 @@ def test_config1_cg(orc):
 
 
 @pytest.mark.parametrize("variant,blocks,vblocks,quad", [(1, 0, 0, 1), (2, 0, 0, 1), (2, 37, 5, 1),
-                                                        (1, 2048, 3000, 1), (2, 0, 0, 0)])
+                                                        (1, 2048, 3000, 1), (2, 0, 0, 0),
+                                                        (3, 0, 0, 0), (3, 37, 5, 0)])
 def test_config1_cg_shapes(orc, variant, blocks, vblocks, quad):
     spx = require_gpu()
     prob, _, b = W.config1()
@@ -79,6 +80,30 @@ def test_pipelined_walk_is_bitwise_identical(rows):
     assert outs[0][0] == outs[1][0] and outs[0][2] == outs[1][2]
     assert np.array_equal(bits(outs[0][1]), bits(outs[1][1]))
     assert np.array_equal(bits(outs[0][3]), bits(outs[1][3]))
+
+
+@pytest.mark.parametrize("rows", [32, 64])
+def test_dma_walk_matches_stream_walk_bitwise(rows):
+    """Same products, same row order, same partial order: the DMA staging
+    changes how bytes reach LDS, not the arithmetic."""
+    spx = require_gpu()
+    N = 14
+    prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(6).standard_normal(N**3)))
+    A = assemble(spx, prob)
+    b = dev(np.random.default_rng(7).uniform(-1, 1, prob.n))
+    outs = []
+    for variant in (2, 3):
+        A.set_option(spx.OPT_SPMV_VARIANT, variant)
+        A.set_option(spx.OPT_ROWS_PER_BLOCK, rows)
+        A.set_option(spx.OPT_ROWS_PER_BLOCK_F32, rows)
+        assert A.get_option(spx.OPT_SPMV_VARIANT) == variant
+        r = A.cg_solve(b, rtol=1e-10)
+        m = A.cg_solve_mixed(b, rtol_outer=1e-10, rtol_inner=1e-4)
+        y = A.matmult(b)
+        outs.append((r.iters, host(r.x), m.inner, host(m.x), host(y)))
+    assert outs[0][0] == outs[1][0] and outs[0][2] == outs[1][2]
+    for k in (1, 3, 4):
+        assert np.array_equal(bits(outs[0][k]), bits(outs[1][k]))
 
 
 def test_cg_check_every_does_not_change_the_result(orc):

@@ -40,7 +40,8 @@ def test_matmult_every_lane_count(orc, lanes):
     assert np.array_equal(bits(y), bits(y2))
 
 
-@pytest.mark.parametrize("variant,rows", [(1, 0), (2, 32), (2, 64), (2, 128), (2, 256)])
+@pytest.mark.parametrize("variant,rows", [(1, 0), (2, 32), (2, 64), (2, 128), (2, 256), (3, 0),
+                                          (3, 32), (3, 64)])
 @pytest.mark.parametrize("case", ["q1_3d", "random", "config1"])
 def test_matmult_variants(orc, variant, rows, case):
     spx = require_gpu()
@@ -59,7 +60,7 @@ def test_matmult_variants(orc, variant, rows, case):
     y = host(A.matmult(dev(x)))
     yr = orc.spmv(ref, x)
     spmv_within(y, yr, orc.abs_spmv(ref, x))
-    if variant == 2 and A.get_option(spx.OPT_SPMV_VARIANT) == 2:
+    if variant >= 2 and A.get_option(spx.OPT_SPMV_VARIANT) == variant:
         # products rounded then added in row order: the oracle's arithmetic
         assert np.array_equal(bits(y), bits(yr))
     yt = host(A.matmult_transpose(dev(x)))
