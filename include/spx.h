@@ -29,6 +29,7 @@ extern "C" {
 
 typedef struct spx_matrix* spx_handle;
 typedef struct spx_batch* spx_batch_handle;
+typedef struct spx_vec_coo* spx_vec_handle;
 
 enum spx_status {
   SPX_OK = 0,
@@ -77,6 +78,26 @@ int spx_set_values_coo(spx_handle h, const double* v, int mode, void* stream);
 
 /* Releases everything the handle owns (synchronises the device). NULL ok. */
 int spx_destroy(spx_handle h);
+
+/* COO vector assembly — paper Sec. 5 (VecSetPreallocationCOO(x, n, i) and
+ * VecSetValuesCOO(x, v, mode), the vector counterpart of the two stages
+ * above).  The pattern is the set of distinct kept indices (negative i[k]
+ * ignored, i[k] >= n is SPX_INDEX_OUT_OF_RANGE); i: device int32[ncoo], not
+ * referenced after the call.  Synchronises `stream`. */
+int spx_vec_coo_preallocate(int64_t n, int64_t ncoo, const int32_t* i, void* stream,
+                            spx_vec_handle* out);
+
+/* For every index i of the pattern, s = +0.0 + v[k] + ... over the kept k
+ * with i[k] = i in increasing k; SPX_INSERT_VALUES stores x[i] = s,
+ * SPX_ADD_VALUES stores x[i] = x[i] + s.  Entries of x outside the pattern
+ * are left unchanged.  v: device float64[ncoo]; x: device float64[n].
+ * Asynchronous. */
+int spx_vec_set_values_coo(spx_vec_handle h, const double* v, int mode, double* x, void* stream);
+
+/* HOST outputs: length, distinct indices, kept triplets, triplets. */
+int spx_vec_coo_get_info(spx_vec_handle h, int64_t* n, int64_t* nunique, int64_t* nvalid,
+                         int64_t* ncoo);
+int spx_vec_coo_destroy(spx_vec_handle h);
 
 /* ---------------------------------------------------------------------------
  * Products — paper Sec. 6 (MatMult inside CG).

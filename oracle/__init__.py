@@ -85,6 +85,8 @@ def _load():
         lib.oracle_coo_grad.restype = None
         lib.oracle_block_reduce.argtypes = [_i64, _i64, _f64p, _f64p, _f64p]
         lib.oracle_block_reduce.restype = None
+        lib.oracle_vec_coo.argtypes = [_i64, _i64, _i32p, _f64p, ctypes.c_int, _f64p]
+        lib.oracle_vec_coo.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -282,4 +284,16 @@ def block_reduce(grad_v: np.ndarray, dv: np.ndarray, block: int) -> np.ndarray:
     nb = grad_v.shape[0] // block
     out = np.empty(nb, np.float64)
     lib.oracle_block_reduce(nb, block, _cf(grad_v), _cf(dv), out)
+    return out
+
+
+def vec_coo(n: int, i, v, x, mode: int = 0) -> np.ndarray:
+    """COO vector assembly into a copy of x (paper Sec. 5, VecSetValuesCOO)."""
+    lib = _load()
+    i = _c32(i)
+    out = _cf(x).copy()
+    st = lib.oracle_vec_coo(n, i.shape[0], i if i.size else np.zeros(1, np.int32),
+                            _cf(v) if i.size else np.zeros(1), mode, out)
+    if st != 0:
+        raise OracleError(st, "vec_coo")
     return out

@@ -171,6 +171,29 @@ int64_t oracle_coo_rows(int64_t n, int64_t ncoo, const int32_t* i, const int32_t
   return w;
 }
 
+/* COO vector assembly (paper Sec. 5, VecSetValuesCOO): x[i] = (x[i] +) the
+ * in-order sum from +0.0 of v[k] over kept k with i[k] = i, for every i that
+ * some kept triplet names; other entries unchanged.  Returns -2 if an index
+ * is >= n (x untouched). */
+int oracle_vec_coo(int64_t n, int64_t ncoo, const int32_t* i, const double* v, int mode,
+                   double* x) {
+  for (int64_t k = 0; k < ncoo; k++)
+    if (i[k] >= n) return OR_RANGE;
+  double* s = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  char* seen = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+  for (int64_t r = 0; r < n; r++) s[r] = 0.0;
+  for (int64_t k = 0; k < ncoo; k++) {
+    if (i[k] < 0) continue;
+    s[i[k]] = s[i[k]] + v[k];
+    seen[i[k]] = 1;
+  }
+  for (int64_t r = 0; r < n; r++)
+    if (seen[r]) x[r] = mode == 1 ? x[r] + s[r] : s[r];
+  free(s);
+  free(seen);
+  return OR_OK;
+}
+
 /* ------------------------------------------------------------------------
  * CSR products (MatMult / MatMultTranspose, paper Sec. 6).
  * ---------------------------------------------------------------------- */

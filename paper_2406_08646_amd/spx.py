@@ -84,6 +84,10 @@ _SIGNATURES = {
     "spx_get_option": [_vp, _i32, _pi64],
     "spx_get_profile": [_vp, _i32, _pd, _pi64],
     "spx_reset_profile": [_vp],
+    "spx_vec_coo_preallocate": [_i64, _i64, _vp, _vp, ctypes.POINTER(_vp)],
+    "spx_vec_set_values_coo": [_vp, _vp, ctypes.c_int, _vp, _vp],
+    "spx_vec_coo_get_info": [_vp, _pi64, _pi64, _pi64, _pi64],
+    "spx_vec_coo_destroy": [_vp],
     "spx_last_error": [],
     "spx_version": [],
 }
@@ -389,6 +393,49 @@ class Batch:
 
 def batch_create(mats: Sequence[Matrix], stream=None) -> Batch:
     return Batch(mats, stream)
+
+
+class CooVector:
+    """A COO vector pattern on the GPU (paper Sec. 5, VecSetPreallocationCOO)."""
+
+    def __init__(self, handle, n: int, ncoo: int, device):
+        self._h = handle
+        self.n = n
+        self.ncoo = ncoo
+        self.device = device
+
+    def destroy(self):
+        if self._h:
+            _check(load_library().spx_vec_coo_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def get_info(self):
+        n, nu, nv, nc = (ctypes.c_int64() for _ in range(4))
+        _check(load_library().spx_vec_coo_get_info(self._h, ctypes.byref(n), ctypes.byref(nu),
+                                                   ctypes.byref(nv), ctypes.byref(nc)))
+        return {"n": n.value, "nunique": nu.value, "nvalid": nv.value, "ncoo": nc.value}
+
+    def set_values_coo(self, v, x, mode: int = INSERT_VALUES, stream=None):
+        _dev(v, torch.float64, self.ncoo, "v")
+        _dev(x, torch.float64, self.n, "x")
+        _check(load_library().spx_vec_set_values_coo(self._h, _ptr(v), mode, _ptr(x),
+                                                     _stream(stream)))
+        return x
+
+
+def vec_coo_preallocate(n: int, i: torch.Tensor, stream=None) -> CooVector:
+    """Symbolic COO stage of a vector on the GPU (paper Sec. 5)."""
+    _dev(i, torch.int32, None, "i")
+    h = ctypes.c_void_p()
+    _check(load_library().spx_vec_coo_preallocate(n, i.numel(), _ptr(i), _stream(stream),
+                                                  ctypes.byref(h)))
+    return CooVector(h, n, i.numel(), i.device)
 
 
 def version() -> str:

@@ -143,3 +143,24 @@ def test_q1_3d_small_bitwise(orc, N):
     spx = require_gpu()
     prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(1).standard_normal(N**3)))
     check_full(orc, spx, prob)
+
+
+@pytest.mark.parametrize("n,ncoo,seed", [(1, 5, 1), (100, 3000, 2), (70000, 400000, 3), (5, 0, 4)])
+def test_vec_coo_bitwise(orc, n, ncoo, seed):
+    spx = require_gpu()
+    rng = np.random.default_rng(seed)
+    p = W.random_coo(rng, n, ncoo, neg_frac=0.2)
+    x0 = rng.uniform(-1, 1, n)
+    V = spx.vec_coo_preallocate(n, dev(p.i))
+    x = dev(x0)
+    V.set_values_coo(dev(p.v), x)
+    assert np.array_equal(bits(host(x)), bits(orc.vec_coo(n, p.i, p.v, x0)))
+    v2 = rng.uniform(-1, 1, p.ncoo)
+    V.set_values_coo(dev(v2), x, mode=spx.ADD_VALUES)
+    want = orc.vec_coo(n, p.i, v2, orc.vec_coo(n, p.i, p.v, x0), mode=1)
+    assert np.array_equal(bits(host(x)), bits(want))
+    info = V.get_info()
+    assert info["nunique"] == len(np.unique(p.i[p.i >= 0]))
+    with pytest.raises(spx.SpxError) as e:
+        spx.vec_coo_preallocate(n, dev(np.array([0, n], np.int32)))
+    assert e.value.code == spx.INDEX_OUT_OF_RANGE

@@ -499,3 +499,30 @@ def test_coo_rows_sample_matches_full_assembly(orc):
         a, b = A.rowptr[r], A.rowptr[r + 1]
         assert np.array_equal(col[ptr[s]:ptr[s + 1]], A.col[a:b])
         assert np.array_equal(bits(val[ptr[s]:ptr[s + 1]]), bits(A.val[a:b]))
+
+
+# ---------------------------------------------------------- COO vectors
+
+@settings(max_examples=40, deadline=None)
+@given(n=st.integers(1, 200), ncoo=st.integers(0, 3000), seed=st.integers(0, 2**32 - 1))
+def test_vec_coo_equals_diagonal_of_matrix_assembly(orc, n, ncoo, seed):
+    """The vector sums (dense in-order accumulation) equal, bitwise, the
+    diagonal of the matrix assembled by sort-and-sum from (i, i, v)."""
+    rng = np.random.default_rng(seed)
+    p = W.random_coo(rng, n, ncoo, neg_frac=0.2)
+    x0 = rng.uniform(-1, 1, n)
+    x = orc.vec_coo(n, p.i, p.v, x0)
+    A = orc.assemble(n, p.i, p.i, p.v)
+    rows = np.repeat(np.arange(n), np.diff(A.rowptr))
+    assert np.all(rows == A.col)
+    touched = np.zeros(n, bool)
+    touched[rows] = True
+    assert np.array_equal(bits(x[rows]), bits(A.val))
+    assert np.array_equal(bits(x[~touched]), bits(x0[~touched]))
+    xa = orc.vec_coo(n, p.i, p.v, x0, mode=1)
+    assert np.array_equal(bits(xa[rows]), bits(x0[rows] + A.val))
+
+
+def test_vec_coo_rejects_out_of_range(orc):
+    with pytest.raises(orc.OracleError):
+        orc.vec_coo(3, np.array([0, 3], np.int32), np.ones(2), np.zeros(3))
