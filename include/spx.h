@@ -268,7 +268,17 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *     while reducing the current one (stream variant; default 0, measured
  *     slower on gfx950); reading it returns the register depth in use.
  *   SPX_OPT_ROWS_PER_BLOCK_F32: rows per workgroup of the fp32 copy used by
- *     the mixed-precision inner solve (0 auto: twice the fp64 tile). */
+ *     the mixed-precision inner solve (0 auto: twice the fp64 tile).
+ *   SPX_OPT_CG_VARIANT: form of the fp64 CG recurrences used by
+ *     spx_cg_solve and spx_cg_solve_transpose.  0 (default): the textbook
+ *     (Hestenes-Stiefel) form, three kernels and two reduction points per
+ *     iteration.  1: the Chronopoulos-Gear single-reduction form of the same
+ *     method (Sec. 6 names fewer synchronisation points as the aim of the
+ *     asynchronous CG): with u = D^-1 r, w = A u, s = A p kept as a vector,
+ *       gamma = r.u, delta = w.u, beta = gamma_k / gamma_{k-1},
+ *       alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}),
+ *     two kernels and ONE reduction point per iteration; its iterates equal
+ *     those of form 0 in exact arithmetic and differ by rounding. */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,
@@ -280,7 +290,8 @@ enum spx_option {
   SPX_OPT_QUAD_LOADS = 8,
   SPX_OPT_VECTOR_BLOCKS = 9,
   SPX_OPT_PIPELINE = 10,
-  SPX_OPT_ROWS_PER_BLOCK_F32 = 11
+  SPX_OPT_ROWS_PER_BLOCK_F32 = 11,
+  SPX_OPT_CG_VARIANT = 12
 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);

@@ -85,6 +85,8 @@ def _load():
         lib.oracle_coo_grad.restype = None
         lib.oracle_block_reduce.argtypes = [_i64, _i64, _f64p, _f64p, _f64p]
         lib.oracle_block_reduce.restype = None
+        lib.oracle_pcg_single_reduction.argtypes = lib.oracle_pcg.argtypes
+        lib.oracle_pcg_single_reduction.restype = ctypes.c_int
         lib.oracle_vec_coo.argtypes = [_i64, _i64, _i32p, _f64p, ctypes.c_int, _f64p]
         lib.oracle_vec_coo.restype = ctypes.c_int
         _lib = lib
@@ -239,6 +241,18 @@ def pcg(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 100000,
     rr = ctypes.c_double(0.0)
     st = lib.oracle_pcg(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit, ctypes.byref(it),
                         ctypes.byref(rr))
+    return CgResult(x, it.value, rr.value, st)
+
+
+def pcg_single_reduction(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 100000,
+                         x0: np.ndarray | None = None) -> CgResult:
+    """Chronopoulos-Gear Jacobi-PCG (one reduction point per iteration)."""
+    lib = _load()
+    x = np.zeros(A.n) if x0 is None else _cf(x0).copy()
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    st = lib.oracle_pcg_single_reduction(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit,
+                                         ctypes.byref(it), ctypes.byref(rr))
     return CgResult(x, it.value, rr.value, st)
 
 

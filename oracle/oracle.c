@@ -336,6 +336,91 @@ int oracle_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const doubl
 }
 
 /* ------------------------------------------------------------------------
+ * Single-reduction Jacobi-PCG (Chronopoulos-Gear form): the same Krylov
+ * iterates in exact arithmetic, with w = A u carried so that the dots
+ * (r,u), (r,r) and (w,u) of one iteration can be reduced together (the
+ * paper's Sec. 6 asynchronous-solver direction: fewer synchronisation
+ * points per iteration).
+ *   r = b - A x; u = D^-1 r; w = A u; gamma = r.u; delta = w.u
+ *   p = u; s = w; alpha = gamma / delta
+ *   repeat (k = 1, 2, ...):
+ *     x += alpha p; r -= alpha s; u = D^-1 r
+ *     stop when ||r|| <= rtol ||b||
+ *     gamma' = r.u; beta = gamma' / gamma; w = A u; delta = w.u
+ *     p = u + beta p; s = w + beta s
+ *     alpha = gamma' / (delta - beta gamma' / alpha); gamma = gamma'
+ * A denominator <= 0 or not finite is a breakdown.
+ * ---------------------------------------------------------------------- */
+int oracle_pcg_single_reduction(int64_t n, const int32_t* rowptr, const int32_t* col,
+                                const double* val, const double* b, double* x, double rtol,
+                                int64_t maxit, int64_t* iters, double* relres) {
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* u = (double*)malloc(sizeof(double) * (size_t)n);
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  double* p = (double*)malloc(sizeof(double) * (size_t)n);
+  double* s = (double*)malloc(sizeof(double) * (size_t)n);
+  double* dinv = (double*)malloc(sizeof(double) * (size_t)n);
+  int status = diag_inverse(n, rowptr, col, val, dinv);
+  int64_t k = 0;
+  double bnorm = sqrt(dot64(n, b, b));
+  if (status == OR_OK) {
+    oracle_spmv(n, rowptr, col, val, x, w);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - w[i];
+    double rnorm = sqrt(dot64(n, r, r));
+    if (!(rnorm <= rtol * bnorm)) {
+      for (int64_t i = 0; i < n; i++) u[i] = dinv[i] * r[i];
+      oracle_spmv(n, rowptr, col, val, u, w);
+      double gamma = dot64(n, r, u);
+      double delta = dot64(n, w, u);
+      for (int64_t i = 0; i < n; i++) p[i] = u[i];
+      for (int64_t i = 0; i < n; i++) s[i] = w[i];
+      double alpha = gamma / delta;
+      status = OR_NOT_CONVERGED;
+      if (!(delta > 0.0) || !isfinite(delta)) {
+        status = OR_BREAKDOWN;
+      } else {
+        while (k < maxit) {
+          for (int64_t i = 0; i < n; i++) x[i] = x[i] + alpha * p[i];
+          for (int64_t i = 0; i < n; i++) r[i] = r[i] - alpha * s[i];
+          for (int64_t i = 0; i < n; i++) u[i] = dinv[i] * r[i];
+          k++;
+          rnorm = sqrt(dot64(n, r, r));
+          if (rnorm <= rtol * bnorm) {
+            status = OR_OK;
+            break;
+          }
+          if (k >= maxit) break;
+          double gamma_new = dot64(n, r, u);
+          double beta = gamma_new / gamma;
+          oracle_spmv(n, rowptr, col, val, u, w);
+          delta = dot64(n, w, u);
+          for (int64_t i = 0; i < n; i++) p[i] = u[i] + beta * p[i];
+          for (int64_t i = 0; i < n; i++) s[i] = w[i] + beta * s[i];
+          double den = delta - beta * gamma_new / alpha;
+          if (!(den > 0.0) || !isfinite(den)) {
+            status = OR_BREAKDOWN;
+            break;
+          }
+          alpha = gamma_new / den;
+          gamma = gamma_new;
+        }
+      }
+    }
+  }
+  oracle_spmv(n, rowptr, col, val, x, w);
+  for (int64_t i = 0; i < n; i++) r[i] = b[i] - w[i];
+  *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
+  *iters = k;
+  free(r);
+  free(u);
+  free(w);
+  free(p);
+  free(s);
+  free(dinv);
+  return status;
+}
+
+/* ------------------------------------------------------------------------
  * Mixed-precision iterative refinement (paper Sec. 2, multiprecision plan:
  * device data in a precision other than the solver's).  Outer loop in
  * fp64: r = b - A x in fp64, stop when ||r|| <= rtol_outer ||b||; inner

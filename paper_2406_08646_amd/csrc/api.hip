@@ -128,6 +128,12 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
                          (long long)value);
       h->rows32_opt = (int)value;
       return SPX_OK;
+    case SPX_OPT_CG_VARIANT:
+      if (value != 0 && value != 1)
+        return set_error(SPX_INVALID_ARG, "set_option: CG variant %lld not 0 or 1",
+                         (long long)value);
+      h->cg_variant = (int)value;
+      return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
   }
@@ -169,6 +175,9 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       return SPX_OK;
     case SPX_OPT_ROWS_PER_BLOCK_F32:
       *value = spmv_shape32(h, h->A).rows;
+      return SPX_OK;
+    case SPX_OPT_CG_VARIANT:
+      *value = h->cg_variant;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

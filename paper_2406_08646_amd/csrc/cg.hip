@@ -251,6 +251,138 @@ __global__ __launch_bounds__(kBlock) void k_resnorm_finish(CgScalars* st, const 
   if (threadIdx.x == 0) st->rr_true = rr;
 }
 
+// ------------------------------------------- single-reduction variant
+// Chronopoulos-Gear form: two kernels per iteration and one reduction
+// point.  KA(k) adds the delta partials of KB(k-1), forms alpha_k and
+// updates x, r and u = D^-1 r with the partials of gamma_k = r.u and
+// ||r||^2; KB(k) adds those, tests convergence, forms beta_k, computes
+// w = A u and updates p = u + beta p, s = w + beta s with the partials of
+// delta_k = w.u.  gamma_j lives in rho[j & 1], alpha_j in alpha_s[j & 1].
+
+// w = A u, p = u, s = w; partials of delta_0 = w.u
+template <class SH>
+__global__ __launch_bounds__(kBlock) void k_sr_init(int64_t n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ u,
+                                                    double* __restrict__ p, double* __restrict__ s,
+                                                    double* __restrict__ P, int rows, int remap,
+                                                    int64_t tile) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[kLds];
+  double delta = 0.0;
+  for_rows<SH, double, double, double>(n, rowptr, col, val, u, rows, logical_block(remap), gridDim.x,
+                                       reinterpret_cast<double*>(smem), [&](int64_t row, double w) {
+                                         const double ur = u[row];
+                                         p[row] = ur;
+                                         s[row] = w;
+                                         delta += w * ur;
+                                       }, tile);
+  delta = block_sum<kBlock>(delta, lds);
+  if (threadIdx.x == 0) P[blockIdx.x] = delta;
+}
+
+// KA(k)
+__global__ __launch_bounds__(kBlock) void k_sr_update(int64_t n, double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ u,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ s,
+                                                      const double* __restrict__ dinv,
+                                                      CgScalars* st, const double* __restrict__ P1,
+                                                      int64_t G1, double* __restrict__ P2,
+                                                      int64_t k) {
+  __shared__ double lds[kLds];
+  if (st->done) return;
+  const double delta = reduce_all(P1, G1, lds);
+  const double g1 = st->rho[(k - 1) & 1];
+  double den = delta;
+  if (k > 1) {
+    const double beta = g1 / st->rho[k & 1];
+    den = delta - beta * g1 / st->alpha_s[(k - 1) & 1];
+  }
+  if (!(den > 0.0) || !isfinite(den)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->pq = den;
+      st->status = SPX_BREAKDOWN;
+      st->iters = (int32_t)(k - 1);
+      st->done = 1;
+    }
+    return;
+  }
+  const double alpha = g1 / den;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->alpha_s[k & 1] = alpha;
+    st->alpha = alpha;
+    st->pq = den;
+  }
+  const int64_t nb = gridDim.x;
+  const Range rg = block_range(n, blockIdx.x, nb);
+  double ru = 0.0, rr = 0.0;
+  for (int64_t i = rg.lo + threadIdx.x; i < rg.hi; i += kBlock) {
+    const double xi = x[i] + alpha * p[i];
+    const double ri = r[i] - alpha * s[i];
+    const double ui = dinv[i] * ri;
+    x[i] = xi;
+    r[i] = ri;
+    u[i] = ui;
+    ru += ri * ui;
+    rr += ri * ri;
+  }
+  ru = block_sum<kBlock>(ru, lds);
+  rr = block_sum<kBlock>(rr, lds);
+  if (threadIdx.x == 0) {
+    P2[blockIdx.x] = ru;
+    P2[nb + blockIdx.x] = rr;
+  }
+}
+
+// KB(k)
+template <class SH>
+__global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ u,
+                                                    double* __restrict__ p, double* __restrict__ s,
+                                                    CgScalars* st, const double* __restrict__ P2,
+                                                    int64_t G2, double* __restrict__ P1, int rows,
+                                                    int remap, int64_t tile, int64_t k) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[kLds];
+  if (st->done) return;
+  const double gk = reduce_all(P2, G2, lds);
+  const double rr = reduce_all(P2 + G2, G2, lds);
+  const bool conv = sqrt(rr) <= st->thresh;
+  const bool stop = conv || k >= st->maxit;
+  const double gprev = st->rho[(k - 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rr = rr;
+    st->iters = (int32_t)k;
+    if (conv) {
+      st->status = SPX_OK;
+      st->done = 1;
+    } else if (stop) {
+      st->status = SPX_NOT_CONVERGED;
+      st->done = 1;
+    } else {
+      st->rho[k & 1] = gk;
+      st->beta = gk / gprev;
+    }
+  }
+  if (stop) return;
+  const double beta = gk / gprev;
+  double delta = 0.0;
+  for_rows<SH, double, double, double>(n, rowptr, col, val, u, rows, logical_block(remap), gridDim.x,
+                                       reinterpret_cast<double*>(smem), [&](int64_t row, double w) {
+                                         const double ur = u[row];
+                                         p[row] = ur + beta * p[row];
+                                         s[row] = w + beta * s[row];
+                                         delta += w * ur;
+                                       }, tile);
+  delta = block_sum<kBlock>(delta, lds);
+  if (threadIdx.x == 0) P1[blockIdx.x] = delta;
+}
+
 // ---------------------------------------------------- mixed precision
 
 __global__ __launch_bounds__(kBlock) void k_norm2(int64_t n, const double* __restrict__ b,
@@ -436,41 +568,45 @@ int ensure_prof_events(spx_matrix* h, int64_t need) {
 }
 
 // Adds the event-timed durations of iterations [first, first+count) of a
-// finished chunk, counting only launches that did work: K1 and K2 up to
-// iteration `iters`, K3 before it (the last K3 only records the stop).
+// finished chunk (kinds[j] is the profile slot of the j-th of K kernels per
+// iteration), counting only launches that did their full work: in the
+// iteration that records the stop (`iters`) the kernels up to index
+// `full_at`, the later ones (which return after the test) not at all.
 void accumulate_profile(spx_matrix* h, hipEvent_t* evs, int64_t first, int64_t count,
-                        int64_t iters, int kind0) {
+                        int64_t iters, int K, const int* kinds, int full_at) {
   for (int64_t c = 0; c < count; ++c) {
     const int64_t it = first + c;
-    for (int j = 0; j < 3; ++j) {
-      const bool ran = (j < 2) ? it <= iters : it < iters;
-      if (!ran) continue;
+    for (int j = 0; j < K; ++j) {
+      const bool ran = it < iters || (it == iters && j <= full_at);
+      if (!ran || kinds[j] < 0) continue;
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, evs[6 * c + 2 * j], evs[6 * c + 2 * j + 1]) == hipSuccess) {
-        h->prof_ms[kind0 + j] += ms;
-        h->prof_cnt[kind0 + j] += 1;
+      if (hipEventElapsedTime(&ms, evs[2 * K * c + 2 * j], evs[2 * K * c + 2 * j + 1]) ==
+          hipSuccess) {
+        h->prof_ms[kinds[j]] += ms;
+        h->prof_cnt[kinds[j]] += 1;
       }
     }
   }
 }
 
 // Runs iterations until the device flag is set, keeping one chunk of
-// `check_every` iterations queued ahead of the one being polled.  Returns
-// the last polled state in *final.
-template <typename VT>
-int run_until_done(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
-                   CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s,
-                   CgScalars* final) {
+// `check_every` iterations queued ahead of the one being polled.  enq(first,
+// count, events) enqueues iterations first .. first+count-1 (K kernels
+// each, bracketed by 2K events when `events` is not null).  Returns the last
+// polled state in *final.
+template <typename Enq>
+int run_until_done(spx_matrix* h, CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s,
+                   int K, const int* kinds, int full_at, Enq&& enq, CgScalars* final) {
   int64_t launched = 0;
   CgScalars* host = h->scal_host;
   const bool prof = h->profile != 0;
-  const int kind0 = sizeof(VT) == 8 ? 0 : 3;
-  if (prof) SPX_TRY(ensure_prof_events(h, 2 * 6 * (int64_t)check_every));
+  const int64_t per_chunk = 2 * K * (int64_t)check_every;
+  if (prof) SPX_TRY(ensure_prof_events(h, 2 * per_chunk));
   int64_t first[2] = {0, 0}, cnt[2] = {0, 0};
   auto chunk = [&](int slot) -> int {
     const int64_t m = std::min<int64_t>(check_every, maxit - launched);
-    hipEvent_t* evs = prof ? h->prof_ev + slot * 6 * (int64_t)check_every : nullptr;
-    SPX_TRY(enqueue_iterations<VT>(h, A, x, r, p, q, dinv, st, launched + 1, m, s, evs));
+    hipEvent_t* evs = prof ? h->prof_ev + slot * per_chunk : nullptr;
+    SPX_TRY(enq(launched + 1, m, evs));
     first[slot] = launched + 1;
     cnt[slot] = m;
     launched += m;
@@ -480,8 +616,8 @@ int run_until_done(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, c
   };
   auto harvest = [&](int slot, int64_t iters) {
     if (prof && cnt[slot] > 0)
-      accumulate_profile(h, h->prof_ev + slot * 6 * (int64_t)check_every, first[slot], cnt[slot],
-                         iters, kind0);
+      accumulate_profile(h, h->prof_ev + slot * per_chunk, first[slot], cnt[slot], iters, K, kinds,
+                         full_at);
     cnt[slot] = 0;
   };
   // state before any iteration (the start may already satisfy the test)
@@ -508,6 +644,53 @@ int run_until_done(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, c
   harvest(0, final->iters);
   harvest(1, final->iters);
   return SPX_OK;
+}
+
+// The Hestenes-Stiefel iteration (K1, K2, K3) on operator A in precision VT.
+template <typename VT>
+int run_hs(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
+           CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s, CgScalars* final) {
+  const int kinds64[3] = {0, 1, 2}, kinds32[3] = {3, 4, 5};
+  return run_until_done(h, st, maxit, check_every, s, 3, sizeof(VT) == 8 ? kinds64 : kinds32, 1,
+                        [&](int64_t first, int64_t count, hipEvent_t* evs) {
+                          return enqueue_iterations<VT>(h, A, x, r, p, q, dinv, st, first, count,
+                                                        s, evs);
+                        },
+                        final);
+}
+
+// The single-reduction iteration (KA, KB), fp64.
+int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, double* p,
+           double* sv, CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s,
+           CgScalars* final) {
+  const unsigned G1 = (unsigned)fused_blocks(h);
+  const unsigned G2 = (unsigned)vector_blocks(h);
+  double* P1 = h->partials;
+  double* P2 = h->partials + G1;
+  const size_t lds = shape_lds<double>(A.sh);
+  const int kinds[2] = {1, 0};  // KA is the vector kernel, KB the SpMV kernel
+  return run_until_done(
+      h, st, maxit, check_every, s, 2, kinds, 0,
+      [&](int64_t first, int64_t count, hipEvent_t* evs) {
+        return with_shape(A.sh, [&](auto shc) {
+          using SH = decltype(shc);
+          for (int64_t c = 0; c < count; ++c) {
+            const int64_t k = first + c;
+            hipEvent_t* e = evs ? evs + 4 * c : nullptr;
+            if (e) (void)hipEventRecord(e[0], s);
+            hipLaunchKernelGGL(k_sr_update, dim3(G2), dim3(kBlock), 0, s, A.n, x, r, u, p, sv,
+                               h->dinv, st, P1, (int64_t)G1, P2, k);
+            if (e) (void)hipEventRecord(e[1], s);
+            if (e) (void)hipEventRecord(e[2], s);
+            hipLaunchKernelGGL((k_sr_spmv<SH>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr,
+                               A.col, A.val, u, p, sv, st, P2, (int64_t)G2, P1, A.sh.rows,
+                               h->xcd_remap, A.sh.tile, k);
+            if (e) (void)hipEventRecord(e[3], s);
+          }
+          return SPX_OK;
+        });
+      },
+      final);
 }
 
 // Launches the fp64 residual-norm kernels for b - A x into st->rr_true.
@@ -553,7 +736,23 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
                      rtol);
   SPX_CHECK_HIP(hipGetLastError());
   CgScalars fin;
-  SPX_TRY(run_until_done<double>(h, A, x, r, p, q, h->dinv, st, maxit, check_every, s, &fin));
+  if (h->cg_variant == 1) {
+    // k_cg_init left u = D^-1 r in p; move it to its own vector and start
+    // w = A u, p = u, s = w, delta_0
+    double* u = h->work + 3 * n;
+    SPX_CHECK_HIP(hipMemcpyAsync(u, p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    SPX_TRY(with_shape(A.sh, [&](auto shc) {
+      using SH = decltype(shc);
+      hipLaunchKernelGGL((k_sr_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
+                         M.rowptr, M.col, M.val, u, p, q, h->partials, A.sh.rows, h->xcd_remap,
+                         A.sh.tile);
+      return SPX_OK;
+    }));
+    SPX_CHECK_HIP(hipGetLastError());
+    SPX_TRY(run_sr(h, A, x, r, u, p, q, st, maxit, check_every, s, &fin));
+  } else {
+    SPX_TRY(run_hs<double>(h, A, x, r, p, q, h->dinv, st, maxit, check_every, s, &fin));
+  }
   SPX_TRY(enqueue_resnorm(h, A, b, x, st, s));
   SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
   SPX_CHECK_HIP(hipStreamSynchronize(s));
@@ -686,8 +885,8 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
     }
     ++outer;
     CgScalars fin;
-    SPX_TRY(run_until_done<float>(h, A32, d32, r32, p32, q32, h->dinv32, si, maxit_inner,
-                                  check_every, s, &fin));
+    SPX_TRY(run_hs<float>(h, A32, d32, r32, p32, q32, h->dinv32, si, maxit_inner, check_every, s,
+                          &fin));
     inner += fin.iters;
     hipLaunchKernelGGL(k_ir_update, dim3(G), dim3(kBlock), 0, s, n, x, d32);
     if (fin.status == SPX_BREAKDOWN) {

@@ -98,6 +98,7 @@ struct SpmvShape {
 // writes rho[k & 1].
 struct CgScalars {
   double rho[2];
+  double alpha_s[2];  // single-reduction variant: alpha_k in slot k & 1
   double alpha, beta, pq;
   double rr, bb, bnorm, thresh;
   double r0norm, rr_true, spare;
@@ -137,6 +138,7 @@ struct spx_matrix {
   int vec_opt = 0;       // quad loads in the stream walk
   int pipe_opt = 0;      // pipelined tiles in the persistent solver kernels
   int rows32_opt = 0;    // rows per tile of the fp32 operator, 0 = auto
+  int cg_variant = 0;    // 0 Hestenes-Stiefel (3 kernels), 1 single reduction (2 kernels)
   int fused_opt = 0;     // workgroups of the solver SpMV kernels, 0 = auto
   int vec_blocks_opt = 0;  // workgroups of the solver vector kernels, 0 = auto
   // optional per-kernel timing of solver iterations (HIP events)

@@ -526,3 +526,43 @@ def test_vec_coo_equals_diagonal_of_matrix_assembly(orc, n, ncoo, seed):
 def test_vec_coo_rejects_out_of_range(orc):
     with pytest.raises(orc.OracleError):
         orc.vec_coo(3, np.array([0, 3], np.int32), np.ones(2), np.zeros(3))
+
+
+# ------------------------------------------------ single-reduction CG
+
+@pytest.mark.parametrize("N,dim", [(3, 2), (8, 2), (3, 3)])
+def test_single_reduction_cg_matches_dense_lu(orc, N, dim):
+    rng = np.random.default_rng(70 + N)
+    p = W.q1_poisson(N, dim, kappa=np.exp(rng.standard_normal(N**dim)))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    b = rng.uniform(-1, 1, p.n)
+    D = np.zeros((p.n, p.n))
+    D[np.repeat(np.arange(p.n), np.diff(A.rowptr)), A.col] = A.val
+    xs = np.linalg.solve(D, b)
+    res = orc.pcg_single_reduction(A, b, 1e-14, 10000)
+    assert res.status == 0 and res.relres <= 1e-13
+    assert np.linalg.norm(res.x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_single_reduction_cg_tracks_hestenes_stiefel(orc):
+    """Same Krylov iterates in exact arithmetic: iteration counts agree and
+    an eigenmode still converges in one step."""
+    prob, _, b = W.config1()
+    A = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    hs = orc.pcg(A, b, 1e-8)
+    cg = orc.pcg_single_reduction(A, b, 1e-8)
+    assert cg.status == 0 and abs(cg.iters - hs.iters) <= 2
+    assert np.linalg.norm(cg.x - hs.x) <= 1e-6 * np.linalg.norm(hs.x)
+    N = 10
+    p = W.q1_poisson(N, 2)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    M = N + 1
+    node = np.arange(p.n)
+    v = np.sin(2 * math.pi * (node % M) / N) * np.sin(3 * math.pi * (node // M) / N)
+    r = orc.pcg_single_reduction(A, v, 1e-12, 50)
+    assert r.status == 0 and r.iters == 1
+    # breakdown on an indefinite matrix, maxit honoured
+    B = orc.assemble(2, np.array([0, 1], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
+    assert orc.pcg_single_reduction(B, np.array([0.0, 1.0]), 1e-8, 10).status == -6
+    rr = orc.pcg_single_reduction(A, np.random.default_rng(0).uniform(-1, 1, p.n), 1e-14, 3)
+    assert rr.status == -5 and rr.iters == 3
