@@ -108,10 +108,11 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def run_extras(spx, W, torch, np, dev, prob, x_np, log):
+def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
     """Measurements of the other workloads, outside the timed steps: the
-    64-system batch (batched vs ensemble vs one solve per system), the
-    16-RHS SpMM on the full 3-D matrix and the 256^2 gradient."""
+    16-RHS SpMM and the single-reduction vs textbook CG on the full 3-D
+    matrix, the 64-system batch (batched vs ensemble vs one solve per
+    system) and the 256^2 gradient."""
     from paper_2406_08646_amd import autograd as AG, autotune
 
     out = {}
@@ -154,9 +155,33 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, log):
     out["spmm16"] = {"ms": round(spmm_ms, 4), "bytes": spmm_bytes,
                      "gbs": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
                      "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
+    log(f"spmm16: {spmm_ms:.3f} ms")
+
+    # ---- single-reduction vs textbook CG on the same matrix and b
+    b_d = d(b_np)
+    forms = {}
+    for name, variant in (("textbook", 0), ("single_reduction", 1)):
+        A.set_option(spx.OPT_CG_VARIANT, variant)
+        A.cg_solve(b_d, rtol=1e-10)  # warm
+        A.set_option(spx.OPT_PROFILE, 1)
+        A.reset_profile()
+        A.cg_solve(b_d, rtol=1e-10)
+        prof = A.get_profile()
+        A.set_option(spx.OPT_PROFILE, 0)
+        ms_plain, r2 = timed(lambda: A.cg_solve(b_d, rtol=1e-10), reps=2)
+        forms[name] = {"ms": round(ms_plain, 2), "iters": r2.iters, "relres": r2.relres,
+                       "status": r2.status,
+                       "ms_per_iter": round(ms_plain / max(1, r2.iters), 4),
+                       "kernels_ms": {k: round(v[0] / max(1, v[1]), 4)
+                                      for k, v in prof.items() if v[1] > 0}}
+    A.set_option(spx.OPT_CG_VARIANT, 0)
+    forms["speedup"] = round(forms["textbook"]["ms_per_iter"]
+                             / forms["single_reduction"]["ms_per_iter"], 3)
+    out["cg_forms"] = forms
+    log(f"cg forms: textbook {forms['textbook']['ms_per_iter']} ms/it, single reduction "
+        f"{forms['single_reduction']['ms_per_iter']} ms/it")
     A.destroy()
     del X, Y
-    log(f"spmm16: {spmm_ms:.3f} ms")
 
     # ---- 64-system batch
     probs, bs = W.config4()
@@ -480,7 +505,7 @@ def main() -> int:
                                         sum(r["profile"][k][1] for r in recs)]
                                     for k in spx.PROFILE_KINDS[:3]}
     if not args.no_extras:
-        out["extras"] = run_extras(spx, W, torch, np, dev, prob, x_np, log)
+        out["extras"] = run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on the {args.cpu_grid}^3-element sample")
         out["cpu_baseline"] = cpu_baseline(args.cpu_grid, args.cpu_calls)
