@@ -89,6 +89,10 @@ def _load():
         lib.oracle_pcg_single_reduction.restype = ctypes.c_int
         lib.oracle_vec_coo.argtypes = [_i64, _i64, _i32p, _f64p, ctypes.c_int, _f64p]
         lib.oracle_vec_coo.restype = ctypes.c_int
+        lib.oracle_bicg.argtypes = lib.oracle_pcg.argtypes
+        lib.oracle_bicg.restype = ctypes.c_int
+        lib.oracle_tfqmr.argtypes = lib.oracle_pcg.argtypes + [_dref]
+        lib.oracle_tfqmr.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -254,6 +258,40 @@ def pcg_single_reduction(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 
     st = lib.oracle_pcg_single_reduction(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit,
                                          ctypes.byref(it), ctypes.byref(rr))
     return CgResult(x, it.value, rr.value, st)
+
+
+def bicg(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 100000,
+         x0: np.ndarray | None = None) -> CgResult:
+    """Jacobi-preconditioned BiCG, shadow residual started at the residual."""
+    lib = _load()
+    x = np.zeros(A.n) if x0 is None else _cf(x0).copy()
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    st = lib.oracle_bicg(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit, ctypes.byref(it),
+                         ctypes.byref(rr))
+    return CgResult(x, it.value, rr.value, st)
+
+
+@dataclass
+class TfqmrResult:
+    x: np.ndarray
+    iters: int  # half-steps, one product with A each
+    relres: float
+    status: int
+    bound: float  # sqrt(m + 1) tau_m at exit, an upper bound of ||b - A x||
+
+
+def tfqmr(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 100000,
+          x0: np.ndarray | None = None) -> TfqmrResult:
+    """Right-Jacobi-preconditioned TFQMR; stops on its residual bound."""
+    lib = _load()
+    x = np.zeros(A.n) if x0 is None else _cf(x0).copy()
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    bd = ctypes.c_double(0.0)
+    st = lib.oracle_tfqmr(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit, ctypes.byref(it),
+                          ctypes.byref(rr), ctypes.byref(bd))
+    return TfqmrResult(x, it.value, rr.value, st, bd.value)
 
 
 @dataclass

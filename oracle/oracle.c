@@ -421,6 +421,225 @@ int oracle_pcg_single_reduction(int64_t n, const int32_t* rowptr, const int32_t*
 }
 
 /* ------------------------------------------------------------------------
+ * Jacobi-preconditioned BiCG (paper Sec. 7 names BiCG with diagonal
+ * preconditioning as one of the two batched Krylov methods).  Textbook
+ * preconditioned biconjugate gradients with M = D = diag(A) and the shadow
+ * residual started at the residual:
+ *
+ *   r = b - A x;  rh = r;  z = D^-1 r;  zh = D^-1 rh;  p = z;  ph = zh
+ *   rho = z.rh
+ *   repeat:  q = A p;  qh = A^T ph;  sigma = ph.q  (0 or not finite: breakdown)
+ *            alpha = rho / sigma;  x += alpha p;  r -= alpha q;  rh -= alpha qh
+ *            stop when ||r|| <= rtol ||b||
+ *            z = D^-1 r;  zh = D^-1 rh;  rho' = z.rh  (0 or not finite: breakdown)
+ *            beta = rho' / rho;  p = z + beta p;  ph = zh + beta ph
+ *
+ * On a symmetric matrix rh stays equal to r and every quantity equals the
+ * CG one above, value for value.
+ * ---------------------------------------------------------------------- */
+int oracle_bicg(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                const double* b, double* x, double rtol, int64_t maxit, int64_t* iters,
+                double* relres) {
+  const size_t bytes = sizeof(double) * (size_t)n;
+  double* r = (double*)malloc(bytes);
+  double* rh = (double*)malloc(bytes);
+  double* z = (double*)malloc(bytes);
+  double* zh = (double*)malloc(bytes);
+  double* p = (double*)malloc(bytes);
+  double* ph = (double*)malloc(bytes);
+  double* q = (double*)malloc(bytes);
+  double* qh = (double*)malloc(bytes);
+  double* dinv = (double*)malloc(bytes);
+  int status = diag_inverse(n, rowptr, col, val, dinv);
+  int64_t k = 0;
+  double bnorm = sqrt(dot64(n, b, b));
+  if (status == OR_OK) {
+    oracle_spmv(n, rowptr, col, val, x, q);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+    for (int64_t i = 0; i < n; i++) rh[i] = r[i];
+    if (!(sqrt(dot64(n, r, r)) <= rtol * bnorm)) {
+      for (int64_t i = 0; i < n; i++) z[i] = dinv[i] * r[i];
+      for (int64_t i = 0; i < n; i++) zh[i] = dinv[i] * rh[i];
+      for (int64_t i = 0; i < n; i++) p[i] = z[i];
+      for (int64_t i = 0; i < n; i++) ph[i] = zh[i];
+      double rho = dot64(n, z, rh);
+      status = OR_NOT_CONVERGED;
+      while (k < maxit) {
+        oracle_spmv(n, rowptr, col, val, p, q);
+        oracle_spmv_transpose(n, rowptr, col, val, ph, qh);
+        double sigma = dot64(n, ph, q);
+        if (sigma == 0.0 || !isfinite(sigma)) {
+          status = OR_BREAKDOWN;
+          break;
+        }
+        double alpha = rho / sigma;
+        for (int64_t i = 0; i < n; i++) x[i] = x[i] + alpha * p[i];
+        for (int64_t i = 0; i < n; i++) r[i] = r[i] - alpha * q[i];
+        for (int64_t i = 0; i < n; i++) rh[i] = rh[i] - alpha * qh[i];
+        k++;
+        if (sqrt(dot64(n, r, r)) <= rtol * bnorm) {
+          status = OR_OK;
+          break;
+        }
+        for (int64_t i = 0; i < n; i++) z[i] = dinv[i] * r[i];
+        for (int64_t i = 0; i < n; i++) zh[i] = dinv[i] * rh[i];
+        double rho_new = dot64(n, z, rh);
+        if (rho_new == 0.0 || !isfinite(rho_new)) {
+          status = OR_BREAKDOWN;
+          break;
+        }
+        double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        for (int64_t i = 0; i < n; i++) ph[i] = zh[i] + beta * ph[i];
+        rho = rho_new;
+      }
+    }
+  }
+  oracle_spmv(n, rowptr, col, val, x, q);
+  for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+  *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
+  *iters = k;
+  free(r);
+  free(rh);
+  free(z);
+  free(zh);
+  free(p);
+  free(ph);
+  free(q);
+  free(qh);
+  free(dinv);
+  return status;
+}
+
+/* ------------------------------------------------------------------------
+ * Jacobi-preconditioned TFQMR (paper Sec. 6 and Sec. 7: the transpose-free
+ * quasi-minimal residual method of Freund, 1993, with diagonal
+ * preconditioning), applied from the right: the method runs on A D^-1,
+ * whose residual is the true residual b - A x, and its search directions
+ * are mapped back by D^-1 before they update x.
+ *
+ * With Ap = A D^-1, shadow vector rs = r0, half-steps m = 0, 1, 2, ...
+ *   w = u = r0;  au = Ap u;  v = au;  d = 0;  tau = ||r0||;
+ *   theta = eta = 0;  rho = rs.r0
+ *   each iteration: sigma = rs.v (0 or not finite: breakdown);
+ *     alpha = rho / sigma, shared by its two half-steps.  Half-step h:
+ *       h = 0: y = au (= Ap u);   h = 1: u = u - alpha v, y = Ap u
+ *       w = w - alpha y
+ *       d = D^-1 u + (theta^2 eta / alpha) d          (x-space direction)
+ *       theta = ||w|| / tau;  c = 1 / sqrt(1 + theta^2)
+ *       tau = tau theta c;  eta = c^2 alpha;  x = x + eta d
+ *       m = m + 1; stop when sqrt(m + 1) tau <= rtol ||b||, the bound
+ *       ||b - A x_m|| <= sqrt(m + 1) tau_m of the method
+ *     then rho' = rs.w (0 or not finite: breakdown);  beta = rho' / rho;
+ *     u_new = w + beta u;  au = Ap u_new;  v = au + beta (y + beta v)
+ * (w is the residual of the unsmoothed iterate, which advances by alpha
+ * times u in each half-step; v is A D^-1 applied to the combined search
+ * direction, which only the u update uses.)
+ * iters counts half-steps (one product with A each); bound returns
+ * sqrt(m + 1) tau at exit.
+ * ---------------------------------------------------------------------- */
+int oracle_tfqmr(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                 const double* b, double* x, double rtol, int64_t maxit, int64_t* iters,
+                 double* relres, double* bound) {
+  const size_t bytes = sizeof(double) * (size_t)n;
+  double* r = (double*)malloc(bytes);
+  double* rs = (double*)malloc(bytes);
+  double* w = (double*)malloc(bytes);
+  double* u = (double*)malloc(bytes);
+  double* uh = (double*)malloc(bytes);
+  double* v = (double*)malloc(bytes);
+  double* au = (double*)malloc(bytes);
+  double* y = (double*)malloc(bytes);
+  double* d = (double*)malloc(bytes);
+  double* dinv = (double*)malloc(bytes);
+  int status = diag_inverse(n, rowptr, col, val, dinv);
+  int64_t m = 0;
+  double bnorm = sqrt(dot64(n, b, b));
+  double tau = 0.0;
+  if (status == OR_OK) {
+    oracle_spmv(n, rowptr, col, val, x, y);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - y[i];
+    tau = sqrt(dot64(n, r, r));
+    if (!(tau <= rtol * bnorm)) {
+      for (int64_t i = 0; i < n; i++) {
+        rs[i] = r[i];
+        w[i] = r[i];
+        u[i] = r[i];
+        d[i] = 0.0;
+      }
+      for (int64_t i = 0; i < n; i++) uh[i] = dinv[i] * u[i];
+      oracle_spmv(n, rowptr, col, val, uh, au);
+      for (int64_t i = 0; i < n; i++) v[i] = au[i];
+      double theta = 0.0, eta = 0.0;
+      double rho = dot64(n, rs, r);
+      status = OR_NOT_CONVERGED;
+      int finished = 0;
+      while (!finished && m < maxit) {
+        double sigma = dot64(n, rs, v);
+        if (sigma == 0.0 || !isfinite(sigma)) {
+          status = OR_BREAKDOWN;
+          break;
+        }
+        double alpha = rho / sigma;
+        for (int h = 0; h < 2 && !finished; h++) {
+          if (h == 0) {
+            for (int64_t i = 0; i < n; i++) y[i] = au[i];
+          } else {
+            for (int64_t i = 0; i < n; i++) u[i] = u[i] - alpha * v[i];
+            for (int64_t i = 0; i < n; i++) uh[i] = dinv[i] * u[i];
+            oracle_spmv(n, rowptr, col, val, uh, y);
+          }
+          for (int64_t i = 0; i < n; i++) w[i] = w[i] - alpha * y[i];
+          double coef = theta * theta * eta / alpha;
+          for (int64_t i = 0; i < n; i++) d[i] = uh[i] + coef * d[i];
+          theta = sqrt(dot64(n, w, w)) / tau;
+          double c = 1.0 / sqrt(1.0 + theta * theta);
+          tau = tau * theta * c;
+          eta = c * c * alpha;
+          for (int64_t i = 0; i < n; i++) x[i] = x[i] + eta * d[i];
+          m++;
+          if (sqrt((double)(m + 1)) * tau <= rtol * bnorm) {
+            status = OR_OK;
+            finished = 1;
+          } else if (m >= maxit) {
+            finished = 1;
+          }
+        }
+        if (finished) break;
+        double rho_new = dot64(n, rs, w);
+        if (rho_new == 0.0 || !isfinite(rho_new)) {
+          status = OR_BREAKDOWN;
+          break;
+        }
+        double beta = rho_new / rho;
+        rho = rho_new;
+        /* y holds Ap u of the second half-step */
+        for (int64_t i = 0; i < n; i++) u[i] = w[i] + beta * u[i];
+        for (int64_t i = 0; i < n; i++) uh[i] = dinv[i] * u[i];
+        oracle_spmv(n, rowptr, col, val, uh, au);
+        for (int64_t i = 0; i < n; i++) v[i] = au[i] + beta * (y[i] + beta * v[i]);
+      }
+    }
+  }
+  *bound = sqrt((double)(m + 1)) * tau;
+  oracle_spmv(n, rowptr, col, val, x, y);
+  for (int64_t i = 0; i < n; i++) r[i] = b[i] - y[i];
+  *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
+  *iters = m;
+  free(r);
+  free(rs);
+  free(w);
+  free(u);
+  free(uh);
+  free(v);
+  free(au);
+  free(y);
+  free(d);
+  free(dinv);
+  return status;
+}
+
+/* ------------------------------------------------------------------------
  * Mixed-precision iterative refinement (paper Sec. 2, multiprecision plan:
  * device data in a precision other than the solver's).  Outer loop in
  * fp64: r = b - A x in fp64, stop when ||r|| <= rtol_outer ||b||; inner

@@ -258,6 +258,66 @@ def config4(nsys: int = 64, lo: int = 32, hi: int = 512, sigma: float = 0.5, see
     return probs, bs
 
 
+def convection_diffusion_system(L: int, c_h: np.ndarray, c_v: np.ndarray, c_b: np.ndarray,
+                                wx: float, wy: float) -> CooProblem:
+    """The 5-point diffusion stream of ``five_point_system`` followed by a
+    first-order upwind convection stream for the constant velocity (wx, wy)
+    on the same cell grid (unit spacing, Dirichlet exterior with value 0).
+
+    Across the face between cells p (upstream) and q (downstream) with
+    normal speed w > 0, the flux w*u_p leaves p and enters q: triplets
+    (p, p, +w), (q, p, -w).  A boundary face with outflow w at cell p
+    emits (p, p, +w); inflow faces carry the zero exterior value and emit
+    nothing.  The matrix is an M-matrix and not symmetric unless w = 0."""
+    base = five_point_system(L, c_h, c_v, c_b)
+    ii, jj, vv = [base.i], [base.j], [base.v]
+    ys, xs = np.meshgrid(np.arange(L), np.arange(L - 1), indexing="ij")
+    hp = (xs + L * ys).reshape(-1)
+    ys, xs = np.meshgrid(np.arange(L - 1), np.arange(L), indexing="ij")
+    vp = (xs + L * ys).reshape(-1)
+    r = np.arange(L)
+    for w, lo, hi, face_lo, face_hi in ((float(wx), hp, hp + 1, r * L, r * L + (L - 1)),
+                                        (float(wy), vp, vp + L, r, r + L * (L - 1))):
+        if w == 0.0:
+            continue
+        up, down = (lo, hi) if w > 0 else (hi, lo)
+        a = abs(w)
+        m = up.shape[0]
+        ii.append(np.stack([up, down], axis=1).reshape(-1))
+        jj.append(np.stack([up, up], axis=1).reshape(-1))
+        vv.append(np.tile([a, -a], m))
+        out = face_hi if w > 0 else face_lo
+        ii.append(out)
+        jj.append(out)
+        vv.append(np.full(L, a))
+    return CooProblem(n=L * L, i=np.concatenate(ii).astype(np.int32),
+                      j=np.concatenate(jj).astype(np.int32), v=np.concatenate(vv), grid=L, dim=2)
+
+
+def config6(nsys: int = 64, lo: int = 32, hi: int = 512, sigma: float = 0.5,
+            speed: tuple = (0.5, 2.0), seed: int = 5):
+    """Non-symmetric batch: ``nsys`` upwind convection-diffusion systems.
+    Draw order from ``default_rng(seed)``: the sides round(exp(U[ln lo,
+    ln hi])); then, system by system, standard normals z for the horizontal,
+    vertical and boundary diffusion edges (coefficient exp(sigma*z)) and the
+    velocity (speed ~ U[speed], angle ~ U[0, 2 pi)); then, system by system,
+    b ~ U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    sides = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), nsys))).astype(np.int64)
+    probs: List[CooProblem] = []
+    for L in sides:
+        L = int(L)
+        z = rng.standard_normal(2 * L * (L - 1) + 4 * L)
+        c = np.exp(sigma * z)
+        sp = rng.uniform(*speed)
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        nh = L * (L - 1)
+        probs.append(convection_diffusion_system(L, c[:nh], c[nh:2 * nh], c[2 * nh:],
+                                                 sp * math.cos(ang), sp * math.sin(ang)))
+    bs = [rng.uniform(-1.0, 1.0, p.n) for p in probs]
+    return probs, bs
+
+
 def config5(N: int = 256):
     """2-D Q1 Poisson on N x N elements with kappa_e = exp(theta_e), theta ~
     N(0, 1) from seed 2, right-hand side b = 1.  Returns the problem (with

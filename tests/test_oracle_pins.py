@@ -566,3 +566,117 @@ def test_single_reduction_cg_tracks_hestenes_stiefel(orc):
     assert orc.pcg_single_reduction(B, np.array([0.0, 1.0]), 1e-8, 10).status == -6
     rr = orc.pcg_single_reduction(A, np.random.default_rng(0).uniform(-1, 1, p.n), 1e-14, 3)
     assert rr.status == -5 and rr.iters == 3
+
+
+# ------------------------------------------- BiCG and TFQMR (non-symmetric)
+
+def dense_of(A):
+    D = np.zeros((A.n, A.n))
+    D[np.repeat(np.arange(A.n), np.diff(A.rowptr)), A.col] = A.val
+    return D
+
+
+def small_nonsymmetric(seed, n=6):
+    """A small well-conditioned non-symmetric matrix as COO (diagonal
+    dominant, every entry present)."""
+    rng = np.random.default_rng(seed)
+    M = rng.uniform(-1, 1, (n, n)) + np.diag(rng.uniform(n, n + 2, n))
+    ii, jj = np.nonzero(np.ones((n, n)))
+    return ii.astype(np.int32), jj.astype(np.int32), M[ii, jj].copy(), rng.uniform(-1, 1, n)
+
+
+@pytest.mark.parametrize("N,dim", [(8, 2), (4, 3)])
+def test_bicg_on_symmetric_matrix_is_cg_value_for_value(orc, N, dim):
+    """With the shadow residual started at r, a symmetric A keeps it equal
+    to r, and BiCG performs CG's arithmetic: same iterates, bit for bit."""
+    rng = np.random.default_rng(90 + N)
+    p = W.q1_poisson(N, dim, kappa=np.exp(rng.standard_normal(N**dim)))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    b = rng.uniform(-1, 1, p.n)
+    for rtol, maxit in ((1e-10, 100000), (1e-14, 7)):
+        c = orc.pcg(A, b, rtol, maxit)
+        g = orc.bicg(A, b, rtol, maxit)
+        assert g.status == c.status and g.iters == c.iters
+        assert np.array_equal(bits(g.x), bits(c.x))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_bicg_and_tfqmr_match_dense_lu_on_convection_diffusion(orc, seed):
+    probs, bs = W.config6(nsys=2, lo=6, hi=20, seed=seed)
+    for p, b in zip(probs, bs):
+        A = orc.assemble(p.n, p.i, p.j, p.v)
+        D = dense_of(A)
+        assert np.max(np.abs(D - D.T)) > 0.1  # really non-symmetric
+        xs = np.linalg.solve(D, b)
+        for res in (orc.bicg(A, b, 1e-11), orc.tfqmr(A, b, 1e-11)):
+            assert res.status == 0
+            assert res.relres <= 1e-11 * 1.01
+            assert np.linalg.norm(res.x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5, 6])
+def test_finite_termination_on_small_systems(orc, seed):
+    """BiCG ends in at most n steps and TFQMR (whose unsmoothed residual is
+    the squared BiCG polynomial) in at most 2n half-steps, up to rounding."""
+    n = 6
+    i, j, v, b = small_nonsymmetric(seed, n)
+    A = orc.assemble(n, i, j, v)
+    xs = np.linalg.solve(dense_of(A), b)
+    g = orc.bicg(A, b, 1e-12)
+    t = orc.tfqmr(A, b, 1e-12)
+    assert g.status == 0 and g.iters <= n + 1
+    assert t.status == 0 and t.iters <= 2 * n + 2
+    for res in (g, t):
+        assert np.linalg.norm(res.x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_tfqmr_bound_dominates_the_true_residual(orc):
+    """sqrt(m + 1) tau_m bounds ||b - A x_m|| at every half-step m: checked at
+    exits forced after m = 1..12 half-steps and at convergence."""
+    probs, bs = W.config6(nsys=1, lo=12, hi=12, seed=7)
+    p, b = probs[0], bs[0]
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    bn = np.linalg.norm(b)
+    for m in range(1, 13):
+        t = orc.tfqmr(A, b, 1e-14, m)
+        assert t.status == -5 and t.iters == m
+        assert t.relres * bn <= t.bound * (1 + 1e-9)
+    t = orc.tfqmr(A, b, 1e-9)
+    assert t.status == 0 and t.relres * bn <= t.bound * (1 + 1e-9) <= 1e-9 * bn * (1 + 1e-9)
+
+
+def test_eigenvector_right_hand_side_converges_at_once(orc):
+    """An eigenvector of A whose support has a constant diagonal is an
+    eigenvector of A D^-1 too: TFQMR is exact after one half-step, BiCG
+    after one step."""
+    N = 10
+    p = W.q1_poisson(N, 2)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    M = N + 1
+    node = np.arange(p.n)
+    v = np.sin(2 * math.pi * (node % M) / N) * np.sin(3 * math.pi * (node // M) / N)
+    cx, cy = math.cos(2 * math.pi / N), math.cos(3 * math.pi / N)
+    lam = (8 - 2 * cx - 2 * cy - 4 * cx * cy) / 3
+    for res in (orc.tfqmr(A, v, 1e-12, 50), orc.bicg(A, v, 1e-12, 50)):
+        assert res.status == 0 and res.iters == 1
+        assert np.max(np.abs(res.x - v / lam)) <= 1e-12 * np.max(np.abs(v / lam))
+
+
+def test_bicg_tfqmr_breakdown_and_limits(orc):
+    # r.(A D^-1 r) = 0 at the start: both methods break down before a step
+    B = orc.assemble(2, np.array([0, 0, 1, 1], np.int32), np.array([0, 1, 0, 1], np.int32),
+                     np.array([1.0, -3.0, 1.0, 1.0]))
+    b = np.array([1.0, 1.0])
+    for res in (orc.bicg(B, b, 1e-10, 10), orc.tfqmr(B, b, 1e-10, 10)):
+        assert res.status == -6 and res.iters == 0
+    # zero diagonal
+    Z = orc.assemble(2, np.array([0, 1], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    assert orc.bicg(Z, b, 1e-10).status == -4 and orc.tfqmr(Z, b, 1e-10).status == -4
+    # limits and the zero right-hand side
+    probs, bs = W.config6(nsys=1, lo=10, hi=10, seed=8)
+    A = orc.assemble(probs[0].n, probs[0].i, probs[0].j, probs[0].v)
+    g = orc.bicg(A, bs[0], 1e-14, 4)
+    t = orc.tfqmr(A, bs[0], 1e-14, 5)
+    assert (g.status, g.iters) == (-5, 4) and (t.status, t.iters) == (-5, 5)
+    for res in (orc.bicg(A, np.zeros(A.n), 1e-8), orc.tfqmr(A, np.zeros(A.n), 1e-8)):
+        assert res.status == 0 and res.iters == 0 and np.all(res.x == 0)
