@@ -170,7 +170,7 @@ int spx_batch_create(int32_t nsys, const spx_handle* hs, void* stream, spx_batch
 int spx_batch_destroy(spx_batch_handle b);
 int spx_batch_total_rows(spx_batch_handle b, int64_t* total);
 
-/* Launch shape of spx_batch_cg (all fields may be 0 for automatic).
+/* Launch shape of the batched solvers (all fields may be 0 for automatic).
  *   blocks: workgroups shared by the systems (0: 8 per compute unit;
  *     raised to nsys if smaller).
  *   rows_per_tile: rows per workgroup tile of the stream row walk (0 auto,
@@ -201,6 +201,44 @@ typedef struct spx_batch_tuning {
 int spx_batch_cg(spx_batch_handle b, const double* bvec, double* x, double rtol, int64_t maxit,
                  const spx_batch_tuning* tuning, void* stream, int64_t* iters_out,
                  double* relres_out);
+
+/* Batched Jacobi-preconditioned BiCG (paper Sec. 7, the batched BiCG with
+ * diagonal preconditioning) for non-symmetric systems, with the arguments,
+ * outputs, stopping test and statuses of spx_batch_cg.  Per system:
+ *   r = b - A x; rh = r; z = D^-1 r; p = z; ph = D^-1 rh; rho = z.rh
+ *   repeat: q = A p; qh = A^T ph; sigma = ph.q; alpha = rho / sigma;
+ *           x += alpha p; r -= alpha q; rh -= alpha qh;
+ *           stop when ||r|| <= rtol ||b||;
+ *           rho' = (D^-1 r).rh; beta = rho' / rho;
+ *           p = D^-1 r + beta p; ph = D^-1 rh + beta ph
+ * sigma or rho' equal to 0 or not finite is SPX_BREAKDOWN.  The first call
+ * builds each matrix's explicit transpose (kept by the handle).  On a
+ * symmetric system the iterates are those of spx_batch_cg, bit for bit.
+ * Synchronises `stream`. */
+int spx_batch_bicg(spx_batch_handle b, const double* bvec, double* x, double rtol, int64_t maxit,
+                   const spx_batch_tuning* tuning, void* stream, int64_t* iters_out,
+                   double* relres_out);
+
+/* Batched TFQMR (paper Secs. 6 and 7: Freund's transpose-free QMR with
+ * diagonal preconditioning) for non-symmetric systems, preconditioned from
+ * the right so that its residual is the true one.  Per system, with
+ * Ap = A D^-1, rs = r0 = b - A x, half-steps m = 1, 2, ...:
+ *   w = u = r0; au = Ap u; v = au; d = 0; tau = ||r0||; theta = eta = 0;
+ *   rho = rs.r0;  per iteration: alpha = rho / rs.v, then two half-steps
+ *   (y = au, then u -= alpha v and y = Ap u):
+ *     w -= alpha y; d = D^-1 u + (theta^2 eta / alpha) d;
+ *     theta = ||w|| / tau; c = (1 + theta^2)^-1/2; tau = tau theta c;
+ *     eta = c^2 alpha; x += eta d; stop when sqrt(m + 1) tau <= rtol ||b||
+ *   then rho' = rs.w, beta = rho' / rho, u = w + beta u, au = Ap u,
+ *   v = au + beta (y + beta v).
+ * sqrt(m + 1) tau bounds ||b - A x||, so the test certifies the true
+ * residual (up to rounding).  maxit and iters_out count half-steps (one
+ * product with A each); check_every counts iterations of two half-steps.
+ * rs.v or rho' equal to 0 or not finite is SPX_BREAKDOWN.  Arguments,
+ * outputs and statuses otherwise as spx_batch_cg.  Synchronises `stream`. */
+int spx_batch_tfqmr(spx_batch_handle b, const double* bvec, double* x, double rtol, int64_t maxit,
+                    const spx_batch_tuning* tuning, void* stream, int64_t* iters_out,
+                    double* relres_out);
 
 /* ---------------------------------------------------------------------------
  * Differentiation of u = A(v)^-1 b through the COO assembly (reverse mode).

@@ -40,6 +40,7 @@ __global__ void k_scal_reset(CgScalars* st, int32_t maxit) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     CgScalars z = {};
     z.maxit = maxit;
+    z.stop_pos = INT32_MAX;
     *st = z;
   }
 }
@@ -637,7 +638,7 @@ int run_until_done(spx_matrix* h, CgScalars* st, int64_t maxit, int32_t check_ev
       *final = host[cur];
       break;
     }
-    harvest(cur, host[cur].iters);
+    harvest(cur, INT64_MAX);  // no stop in this chunk: every launch did its work
     cur ^= 1;
   }
   SPX_CHECK_HIP(hipStreamSynchronize(s));

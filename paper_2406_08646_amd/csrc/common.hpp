@@ -102,7 +102,13 @@ struct CgScalars {
   double alpha, beta, pq;
   double rr, bb, bnorm, thresh;
   double r0norm, rr_true, spare;
+  double tau[2], theta, eta;  // TFQMR quasi-residual recurrences
   int32_t iters, done, status, maxit;
+  // Launch position at which the solve stopped (INT32_MAX while running).
+  // A kernel that must finish its own work after the stopping test compares
+  // it with its own position instead of reading `done`, which another
+  // workgroup of the same launch may already have set.
+  int32_t stop_pos, pad;
 };
 
 }  // namespace spx

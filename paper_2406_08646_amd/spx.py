@@ -75,6 +75,8 @@ _SIGNATURES = {
     "spx_batch_destroy": [_vp],
     "spx_batch_total_rows": [_vp, _pi64],
     "spx_batch_cg": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
+    "spx_batch_bicg": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
+    "spx_batch_tfqmr": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
     "spx_sddmm": [_vp, _vp, _vp, _vp, _vp],
     "spx_coo_gather": [_vp, _vp, _vp, _vp],
     "spx_coo_gather_blocks": [_vp, _vp, _vp, _i64, _vp, _vp],
@@ -376,20 +378,39 @@ class Batch:
         except Exception:
             pass
 
-    def batch_cg(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
-                 weight_exponent=1.0, check_every=20, stream=None):
+    def _solve(self, fn, b, x, rtol, maxit, blocks, rows_per_tile, weight_exponent, check_every,
+               stream):
         _dev(b, torch.float64, self.total, "b")
         x = torch.zeros_like(b) if x is None else _dev(x, torch.float64, self.total, "x")
         ns = len(self.mats)
         iters = (ctypes.c_int64 * ns)()
         rel = (ctypes.c_double * ns)()
         tune = BatchTuning(blocks, rows_per_tile, weight_exponent, check_every, 0)
-        rc = load_library().spx_batch_cg(self._h, _ptr(b), _ptr(x), rtol, maxit,
-                                         ctypes.cast(ctypes.byref(tune), ctypes.c_void_p),
-                                         _stream(stream), ctypes.cast(iters, _pi64),
-                                         ctypes.cast(rel, _pd))
+        rc = fn(self._h, _ptr(b), _ptr(x), rtol, maxit,
+                ctypes.cast(ctypes.byref(tune), ctypes.c_void_p), _stream(stream),
+                ctypes.cast(iters, _pi64), ctypes.cast(rel, _pd))
         _check(rc, _SOLVER_OUTCOMES)
         return x, list(iters), list(rel), rc
+
+    def batch_cg(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
+                 weight_exponent=1.0, check_every=20, stream=None):
+        """Jacobi-CG on every system (SPD systems)."""
+        return self._solve(load_library().spx_batch_cg, b, x, rtol, maxit, blocks, rows_per_tile,
+                           weight_exponent, check_every, stream)
+
+    def batch_bicg(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
+                   weight_exponent=1.0, check_every=20, stream=None):
+        """Jacobi-preconditioned BiCG on every system (iterations: BiCG steps)."""
+        return self._solve(load_library().spx_batch_bicg, b, x, rtol, maxit, blocks,
+                           rows_per_tile, weight_exponent, check_every, stream)
+
+    def batch_tfqmr(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
+                    weight_exponent=1.0, check_every=20, stream=None):
+        """Right-Jacobi TFQMR on every system (iterations: half-steps, one
+        product with A each; maxit counts half-steps, check_every full
+        iterations of two half-steps)."""
+        return self._solve(load_library().spx_batch_tfqmr, b, x, rtol, maxit, blocks,
+                           rows_per_tile, weight_exponent, check_every, stream)
 
 
 def batch_create(mats: Sequence[Matrix], stream=None) -> Batch:

@@ -1,0 +1,131 @@
+"""Batched BiCG and TFQMR with diagonal preconditioning (one launch per phase
+for all systems) on non-symmetric convection-diffusion batches, against the
+oracle's BiCG and TFQMR."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2406_08646_amd import workloads as W
+from gpu_util import assemble, bits, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def sigma_min_lower(p):
+    """Lower bound of the smallest singular value: the symmetric part of the
+    upwind convection operator is positive semi-definite, so x.Ax >=
+    lambda_min(diffusion) |x|^2, and lambda_min(diffusion) >= c_min times
+    the constant-coefficient closed form."""
+    L = p.grid
+    nd = 8 * L * (L - 1) + 4 * L  # the diffusion triplets come first
+    cmin = np.min(np.abs(p.v[:nd]))
+    return cmin * (4 - 4 * math.cos(math.pi / (L + 1)))
+
+
+def check_systems(orc, probs, bs, x, iters, relres, rtol, method, oracle_upto=None):
+    off = 0
+    solver = orc.bicg if method == "bicg" else orc.tfqmr
+    for s, (p, b) in enumerate(zip(probs, bs)):
+        xs = x[off:off + p.n]
+        off += p.n
+        A = orc.assemble(p.n, p.i, p.j, p.v)
+        r = np.linalg.norm(b - orc.spmv(A, xs))
+        slack = 1e-3 if method == "bicg" else 1e-2
+        assert relres[s] <= rtol * (1 + slack), (s, relres[s])
+        assert r <= rtol * np.linalg.norm(b) * (1 + slack), (s, r)
+        if oracle_upto is not None and p.n > oracle_upto:
+            continue
+        ref = solver(A, b, rtol)
+        assert ref.status == 0
+        assert abs(iters[s] - ref.iters) <= max(4, math.ceil(0.03 * ref.iters)), \
+            (s, iters[s], ref.iters)
+        rr = np.linalg.norm(b - orc.spmv(A, ref.x))
+        assert np.linalg.norm(xs - ref.x) <= (r + rr) / sigma_min_lower(p) * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("method", ["bicg", "tfqmr"])
+@pytest.mark.parametrize("nsys,lo,hi,seed,blocks,rows,gamma", [
+    (5, 4, 24, 21, 0, 0, 1.0), (12, 8, 60, 22, 37, 64, 0.5), (12, 8, 60, 22, 7, 0, 1.5),
+    (3, 2, 3, 23, 0, 32, 1.0)])
+def test_nonsymmetric_batch_small(orc, method, nsys, lo, hi, seed, blocks, rows, gamma):
+    spx = require_gpu()
+    probs, bs = W.config6(nsys=nsys, lo=lo, hi=hi, seed=seed)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    fn = batch.batch_bicg if method == "bicg" else batch.batch_tfqmr
+    x, iters, relres, st = fn(bvec, rtol=1e-8, blocks=blocks, rows_per_tile=rows,
+                              weight_exponent=gamma)
+    print(f"{method} nsys={nsys}: iterations {iters}", flush=True)
+    assert st == 0
+    check_systems(orc, probs, bs, host(x), iters, relres, 1e-8, method)
+
+
+def test_bicg_on_symmetric_batch_is_batched_cg_bit_for_bit():
+    spx = require_gpu()
+    probs, bs = W.config4(nsys=7, lo=6, hi=70, seed=24)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    xc, ic, rc, sc = batch.batch_cg(bvec, rtol=1e-9)
+    xb, ib, rb, sb = batch.batch_bicg(bvec, rtol=1e-9)
+    assert sc == 0 and sb == 0 and ic == ib
+    assert np.array_equal(bits(host(xc)), bits(host(xb)))
+
+
+def test_single_system_batch_is_independent_of_check_every():
+    spx = require_gpu()
+    probs, bs = W.config6(nsys=1, lo=40, hi=40, seed=25)
+    batch = spx.batch_create([assemble(spx, probs[0])])
+    b = dev(bs[0])
+    for fn in (batch.batch_bicg, batch.batch_tfqmr):
+        outs = [fn(b, rtol=1e-9, check_every=k) for k in (1, 3, 20)]
+        for o in outs[1:]:
+            assert o[1] == outs[0][1]
+            assert np.array_equal(bits(host(o[0])), bits(host(outs[0][0])))
+
+
+def test_nonsymmetric_batch_statuses():
+    spx = require_gpu()
+    good = W.convection_diffusion_system(6, np.ones(30), np.ones(30), np.ones(24), 1.0, -0.5)
+    A = assemble(spx, good)
+    Z = spx.coo_preallocate(2, dev(np.array([0, 1, 1], np.int32)), dev(np.array([1, 0, 1], np.int32)))
+    Z.set_values_coo(dev(np.array([1.0, 1.0, 2.0])))
+    # r.(A D^-1 r) = 0 at the start
+    Bk = spx.coo_preallocate(2, dev(np.array([0, 0, 1, 1], np.int32)),
+                             dev(np.array([0, 1, 0, 1], np.int32)))
+    Bk.set_values_coo(dev(np.array([1.0, -3.0, 1.0, 1.0])))
+    batch = spx.batch_create([A, Z, Bk])
+    b = dev(np.ones(40))
+    for fn in ("batch_bicg", "batch_tfqmr"):
+        x, iters, relres, st = getattr(batch, fn)(b, rtol=1e-8)
+        assert st == spx.BREAKDOWN or st == spx.ZERO_DIAGONAL
+        assert relres[0] <= 1e-8 * 1.01 and iters[2] == 0
+    one = spx.batch_create([A])
+    x, iters, relres, st = one.batch_tfqmr(dev(np.ones(36)), rtol=1e-14, maxit=5)
+    assert st == spx.NOT_CONVERGED and iters[0] == 5
+    x, iters, relres, st = one.batch_bicg(dev(np.ones(36)), rtol=1e-14, maxit=3)
+    assert st == spx.NOT_CONVERGED and iters[0] == 3
+    for fn in (one.batch_bicg, one.batch_tfqmr):
+        x, iters, relres, st = fn(dev(np.zeros(36)), rtol=1e-8)
+        assert st == 0 and iters[0] == 0 and np.all(host(x) == 0)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("method", ["tfqmr", "bicg"])
+def test_nonsymmetric_batch_full_config(orc, method):
+    """64 convection-diffusion systems (sides 32..512) to 1e-8: every true
+    residual checked; iteration counts and solutions against the oracle for
+    the systems up to 64k unknowns."""
+    spx = require_gpu()
+    probs, bs = W.config6()
+    print(f"{method}: batch sizes", [p.grid for p in probs], flush=True)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    fn = batch.batch_bicg if method == "bicg" else batch.batch_tfqmr
+    x, iters, relres, st = fn(bvec, rtol=1e-8)
+    print("iterations:", iters, flush=True)
+    assert st == 0
+    check_systems(orc, probs, bs, host(x), iters, relres, 1e-8, method, oracle_upto=65536)
