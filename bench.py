@@ -219,6 +219,42 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
     log(f"batched: {bt_ms:.2f} ms, ensemble {ens_ms:.2f} ms, sequential {seq_ms:.2f} ms")
     del batch, mats, E
 
+    # ---- 64-system non-symmetric batch: batched TFQMR / BiCG vs ensemble vs one per system
+    probs6, bs6 = W.config6()
+    mats6 = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs6]
+    for m, p in zip(mats6, probs6):
+        m.set_values_coo(d(p.v))
+    batch6 = spx.batch_create(mats6)
+    bvec6 = d(np.concatenate(bs6))
+    offs6 = np.cumsum([0] + [p.n for p in probs6])
+    E6 = spx.coo_preallocate(int(offs6[-1]),
+                             d(np.concatenate([p.i + o for p, o in zip(probs6, offs6)]).astype(np.int32)),
+                             d(np.concatenate([p.j + o for p, o in zip(probs6, offs6)]).astype(np.int32)))
+    E6.set_values_coo(d(np.concatenate([p.v for p in probs6])))
+    ens6 = spx.batch_create([E6])
+    singles = [spx.batch_create([m]) for m in mats6]
+    b_parts = [d(b) for b in bs6]
+    nonsym = {}
+    for method in ("tfqmr", "bicg"):
+        fn = "batch_" + method
+        getattr(batch6, fn)(bvec6, rtol=1e-8)  # warm (BiCG builds the transposes)
+        ms_b, (xb, it_b, rel_b, st_b) = timed(lambda: getattr(batch6, fn)(bvec6, rtol=1e-8), reps=3)
+        ms_e, (xe, it_e, rel_e, st_e) = timed(lambda: getattr(ens6, fn)(bvec6, rtol=1e-8), reps=2)
+        ms_s, _ = timed(lambda: [getattr(sb, fn)(bp, rtol=1e-8) for sb, bp in zip(singles, b_parts)])
+        nonsym[method] = {"ms": round(ms_b, 2), "solves_per_s": round(64 / (ms_b * 1e-3), 1),
+                          "status": st_b, "max_relres": max(rel_b), "iters_max": max(it_b),
+                          "iters_min": min(it_b), "ensemble_ms": round(ms_e, 2),
+                          "ensemble_iters": it_e[0], "ensemble_status": st_e,
+                          "sequential_ms": round(ms_s, 2),
+                          "speedup_vs_ensemble": round(ms_e / ms_b, 2),
+                          "speedup_vs_sequential": round(ms_s / ms_b, 2)}
+        log(f"nonsymmetric batch {method}: {ms_b:.2f} ms, ensemble {ms_e:.2f} ms, "
+            f"sequential {ms_s:.2f} ms")
+    nonsym["iteration_unit"] = {"tfqmr": "half-steps (one product with A)",
+                                "bicg": "BiCG steps (one product with A and one with A^T)"}
+    out["nonsymmetric_batch64"] = nonsym
+    del batch6, mats6, E6, ens6, singles
+
     # ---- gradient on 256 x 256 elements
     N = 256
     one = W.q1_poisson(N, 2, kappa=np.ones(N * N))

@@ -528,16 +528,26 @@ int oracle_bicg(int64_t n, const int32_t* rowptr, const int32_t* col, const doub
  *       d = D^-1 u + (theta^2 eta / alpha) d          (x-space direction)
  *       theta = ||w|| / tau;  c = 1 / sqrt(1 + theta^2)
  *       tau = tau theta c;  eta = c^2 alpha;  x = x + eta d
- *       m = m + 1; stop when sqrt(m + 1) tau <= rtol ||b||, the bound
- *       ||b - A x_m|| <= sqrt(m + 1) tau_m of the method
+ *       m = m + 1; the cycle ends when sqrt(m + 1) tau <= rtol ||b||, the
+ *       bound ||b - A x_m|| <= sqrt(m + 1) tau_m of the method (m counted
+ *       within the cycle)
  *     then rho' = rs.w (0 or not finite: breakdown);  beta = rho' / rho;
  *     u_new = w + beta u;  au = Ap u_new;  v = au + beta (y + beta v)
  * (w is the residual of the unsmoothed iterate, which advances by alpha
  * times u in each half-step; v is A D^-1 applied to the combined search
  * direction, which only the u update uses.)
+ * The bound holds in exact arithmetic only: the unsmoothed residuals can
+ * grow by many orders of magnitude before they fall, and rounding then
+ * caps the accuracy of x well above the bound.  So when a cycle ends on the
+ * bound, the true residual of x decides: at most rtol ||b|| ends the
+ * solve, otherwise a new cycle starts from x with r0 = b - A x (at most
+ * TFQMR_MAX_RESTARTS restarts, then "not converged").  Half-steps are
+ * counted over all cycles.
  * iters counts half-steps (one product with A each); bound returns
- * sqrt(m + 1) tau at exit.
+ * sqrt(m + 1) tau of the last cycle at exit.
  * ---------------------------------------------------------------------- */
+#define TFQMR_MAX_RESTARTS 8
+
 int oracle_tfqmr(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
                  const double* b, double* x, double rtol, int64_t maxit, int64_t* iters,
                  double* relres, double* bound) {
@@ -553,14 +563,18 @@ int oracle_tfqmr(int64_t n, const int32_t* rowptr, const int32_t* col, const dou
   double* d = (double*)malloc(bytes);
   double* dinv = (double*)malloc(bytes);
   int status = diag_inverse(n, rowptr, col, val, dinv);
-  int64_t m = 0;
+  int64_t m = 0;  /* half-steps over all cycles */
+  int64_t ml = 0; /* half-steps of the current cycle */
   double bnorm = sqrt(dot64(n, b, b));
   double tau = 0.0;
   if (status == OR_OK) {
     oracle_spmv(n, rowptr, col, val, x, y);
     for (int64_t i = 0; i < n; i++) r[i] = b[i] - y[i];
     tau = sqrt(dot64(n, r, r));
-    if (!(tau <= rtol * bnorm)) {
+    int restarts = 0;
+    while (!(tau <= rtol * bnorm)) {
+      /* a cycle from the residual r of the current x */
+      ml = 0;
       for (int64_t i = 0; i < n; i++) {
         rs[i] = r[i];
         w[i] = r[i];
@@ -573,7 +587,7 @@ int oracle_tfqmr(int64_t n, const int32_t* rowptr, const int32_t* col, const dou
       double theta = 0.0, eta = 0.0;
       double rho = dot64(n, rs, r);
       status = OR_NOT_CONVERGED;
-      int finished = 0;
+      int finished = 0, passed = 0;
       while (!finished && m < maxit) {
         double sigma = dot64(n, rs, v);
         if (sigma == 0.0 || !isfinite(sigma)) {
@@ -598,8 +612,9 @@ int oracle_tfqmr(int64_t n, const int32_t* rowptr, const int32_t* col, const dou
           eta = c * c * alpha;
           for (int64_t i = 0; i < n; i++) x[i] = x[i] + eta * d[i];
           m++;
-          if (sqrt((double)(m + 1)) * tau <= rtol * bnorm) {
-            status = OR_OK;
+          ml++;
+          if (sqrt((double)(ml + 1)) * tau <= rtol * bnorm) {
+            passed = 1;
             finished = 1;
           } else if (m >= maxit) {
             finished = 1;
@@ -619,9 +634,24 @@ int oracle_tfqmr(int64_t n, const int32_t* rowptr, const int32_t* col, const dou
         oracle_spmv(n, rowptr, col, val, uh, au);
         for (int64_t i = 0; i < n; i++) v[i] = au[i] + beta * (y[i] + beta * v[i]);
       }
+      if (!passed) break; /* iteration limit or breakdown */
+      /* the bound passed: check the true residual of x */
+      oracle_spmv(n, rowptr, col, val, x, y);
+      for (int64_t i = 0; i < n; i++) r[i] = b[i] - y[i];
+      double rn = sqrt(dot64(n, r, r));
+      if (rn <= rtol * bnorm) {
+        status = OR_OK;
+        break;
+      }
+      if (restarts == TFQMR_MAX_RESTARTS || m >= maxit) {
+        status = OR_NOT_CONVERGED;
+        break;
+      }
+      restarts++;
+      tau = rn;
     }
   }
-  *bound = sqrt((double)(m + 1)) * tau;
+  *bound = sqrt((double)(ml + 1)) * tau;
   oracle_spmv(n, rowptr, col, val, x, y);
   for (int64_t i = 0; i < n; i++) r[i] = b[i] - y[i];
   *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));

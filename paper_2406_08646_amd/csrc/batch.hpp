@@ -208,12 +208,19 @@ inline int prepare(spx_batch* B, const spx_batch_tuning* tuning, const int64_t m
   return upload_plan(B, G, s);
 }
 
+struct NoHook {
+  int operator()(int64_t, bool*) const { return SPX_OK; }
+};
+
 // Polls the per-system state, re-splits the grid when the set of running
 // systems changed, and enqueues chunks of `check_every` iterations with
 // enq(first, count) (1-based iteration numbers) until every system is done
-// or `max_iters` iterations were enqueued.
-template <typename Enq>
-int poll_loop(spx_batch* B, Run& run, int64_t max_iters, hipStream_t s, Enq&& enq) {
+// or `max_iters` iterations were enqueued.  hook(k, &relaunched) runs at
+// every poll on the freshly read state, k iterations in; when it enqueues
+// work it sets relaunched and the state is read again.
+template <typename Enq, typename Hook = NoHook>
+int poll_loop(spx_batch* B, Run& run, int64_t max_iters, hipStream_t s, Enq&& enq,
+              Hook&& hook = Hook()) {
   const int ns = B->nsys;
   std::vector<char> active(ns, 1);
   int64_t k = 0;
@@ -221,6 +228,13 @@ int poll_loop(spx_batch* B, Run& run, int64_t max_iters, hipStream_t s, Enq&& en
     SPX_CHECK_HIP(
         hipMemcpyAsync(B->h_st, B->d_st, sizeof(CgScalars) * ns, hipMemcpyDeviceToHost, s));
     SPX_CHECK_HIP(hipStreamSynchronize(s));
+    bool relaunched = false;
+    SPX_TRY(hook(k, &relaunched));
+    if (relaunched) {
+      SPX_CHECK_HIP(
+          hipMemcpyAsync(B->h_st, B->d_st, sizeof(CgScalars) * ns, hipMemcpyDeviceToHost, s));
+      SPX_CHECK_HIP(hipStreamSynchronize(s));
+    }
     std::vector<char> now(ns, 0);
     int nact = 0;
     for (int t = 0; t < ns; ++t) {

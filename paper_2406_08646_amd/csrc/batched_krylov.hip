@@ -23,6 +23,10 @@
 // test, so a later workgroup of the same launch must not skip its rows when
 // the first one has already marked the system done: launches compare the
 // recorded stop position with their own instead of reading `done`.
+// A cycle that ends on the method's residual bound is only a candidate: at
+// the next host poll the true residual of x decides between done and a new
+// cycle from x (the bound holds in exact arithmetic only, and the large
+// intermediate residuals of this method can leave x far above it).
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_tq_b(const BatchSys* __restrict__ sy
     if (jb == 0 && threadIdx.x == 0) {
       c.pq = sigma;
       c.status = SPX_BREAKDOWN;
-      c.iters = (int32_t)(2 * j);
+      c.iters = (int32_t)(c.m0 + 2 * (j - c.j0));
       c.done = 1;
       c.stop_pos = (int32_t)pos;
     }
@@ -397,16 +401,20 @@ __global__ __launch_bounds__(kBlock) void k_tq_c(const BatchSys* __restrict__ sy
   const double ww = reduce_all(P1 + a, T, lds);
   const double alpha = c.alpha;
   const TqStep h = tq_step(ww, c.tau[0], alpha);
-  const int64_t m = 2 * j + 1;
-  const bool conv = sqrt((double)(m + 1)) * h.tau <= c.thresh;
-  const bool stop = conv || m >= c.maxit;
+  const int64_t ml = 2 * (j - c.j0) + 1;  // half-steps of this cycle
+  const int64_t m = c.m0 + ml;
+  const bool passed = sqrt((double)(ml + 1)) * h.tau <= c.thresh;
+  const bool stop = passed || m >= c.maxit;
   if (jb == 0 && threadIdx.x == 0) {
     c.tau[1] = h.tau;
     c.theta = h.theta;
     c.eta = h.eta;
     c.iters = (int32_t)m;
-    if (stop) {
-      c.status = conv ? SPX_OK : SPX_NOT_CONVERGED;
+    if (passed) {
+      c.verify = 1;
+      c.stop_pos = (int32_t)pos;
+    } else if (stop) {
+      c.status = SPX_NOT_CONVERGED;
       c.done = 1;
       c.stop_pos = (int32_t)pos;
     }
@@ -457,19 +465,23 @@ __global__ __launch_bounds__(kBlock) void k_tq_d(const BatchSys* __restrict__ sy
   const double rho_new = reduce_all(P2 + pl.G + a, T, lds);
   const double alpha = c.alpha;
   const TqStep h = tq_step(ww, c.tau[1], alpha);
-  const int64_t m = 2 * j + 2;
-  const bool conv = sqrt((double)(m + 1)) * h.tau <= c.thresh;
-  const bool limit = !conv && m >= c.maxit;
-  const bool broke = !conv && !limit && (rho_new == 0.0 || !isfinite(rho_new));
-  const bool stop = conv || limit || broke;
+  const int64_t ml = 2 * (j - c.j0) + 2;
+  const int64_t m = c.m0 + ml;
+  const bool passed = sqrt((double)(ml + 1)) * h.tau <= c.thresh;
+  const bool limit = !passed && m >= c.maxit;
+  const bool broke = !passed && !limit && (rho_new == 0.0 || !isfinite(rho_new));
+  const bool stop = passed || limit || broke;
   const double rho_prev = c.rho[j & 1];
   if (jb == 0 && threadIdx.x == 0) {
     c.tau[0] = h.tau;
     c.theta = h.theta;
     c.eta = h.eta;
     c.iters = (int32_t)m;
-    if (stop) {
-      c.status = conv ? SPX_OK : limit ? SPX_NOT_CONVERGED : SPX_BREAKDOWN;
+    if (passed) {
+      c.verify = 1;
+      c.stop_pos = (int32_t)pos;
+    } else if (stop) {
+      c.status = limit ? SPX_NOT_CONVERGED : SPX_BREAKDOWN;
       c.done = 1;
       c.stop_pos = (int32_t)pos;
     } else {
@@ -493,6 +505,76 @@ __global__ __launch_bounds__(kBlock) void k_tq_d(const BatchSys* __restrict__ sy
     V.uh[i] = dinv[i] * ui;
   }
 }
+
+// True residual of a system whose cycle ended on the bound, and the start of
+// a new cycle from it: r = b - A x; w = u = rs = r; uh = D^-1 r;
+// d = t = v = 0; partials of r.r.  Other systems are left alone.
+template <class SH>
+__global__ __launch_bounds__(kBlock) void k_tq_verify(const BatchSys* __restrict__ sys, PlanView pl,
+                                                      const double* __restrict__ b,
+                                                      const double* __restrict__ x, TqVecs V,
+                                                      const double* __restrict__ dinv,
+                                                      const CgScalars* __restrict__ st,
+                                                      double* __restrict__ P, int rows) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[kLds];
+  const int s = pl.sys(blockIdx.x);
+  if (s < 0 || !st[s].verify) return;
+  const BatchSys S = sys[s];
+  const int64_t o = S.off;
+  double rr = 0.0;
+  for_rows<SH, double, double, double>(S.n, S.rowptr, S.col, S.val, x + o, rows,
+                                       blockIdx.x - pl.start(s), pl.size(s),
+                                       reinterpret_cast<double*>(smem), [&](int64_t row, double ax) {
+                                         const int64_t i = o + row;
+                                         const double ri = b[i] - ax;
+                                         V.w[i] = ri;
+                                         V.u[i] = ri;
+                                         V.rs[i] = ri;
+                                         V.uh[i] = dinv[i] * ri;
+                                         V.d[i] = 0.0;
+                                         V.t[i] = 0.0;
+                                         V.v[i] = 0.0;
+                                         rr += ri * ri;
+                                       });
+  rr = block_sum<kBlock>(rr, lds);
+  if (threadIdx.x == 0) P[blockIdx.x] = rr;
+}
+
+// one workgroup per system: done, or a new cycle from iteration jn
+__global__ __launch_bounds__(kBlock) void k_tq_verify_finish(PlanView pl, CgScalars* st,
+                                                             const double* __restrict__ P,
+                                                             int64_t jn, int32_t max_restarts) {
+  __shared__ double lds[kLds];
+  const int s = blockIdx.x;
+  if (!st[s].verify) return;
+  const double rr = reduce_all(P + pl.start(s), pl.size(s), lds);
+  if (threadIdx.x == 0) {
+    CgScalars& c = st[s];
+    c.verify = 0;
+    c.rr = rr;
+    const double tau = sqrt(rr);
+    if (tau <= c.thresh) {
+      c.status = SPX_OK;
+      c.done = 1;
+    } else if (c.restarts >= max_restarts || c.iters >= c.maxit) {
+      c.status = SPX_NOT_CONVERGED;
+      c.done = 1;
+    } else {
+      c.restarts += 1;
+      c.rho[jn & 1] = rr;
+      c.tau[0] = tau;
+      c.theta = 0.0;
+      c.eta = 0.0;
+      c.beta = 0.0;
+      c.j0 = (int32_t)jn;
+      c.m0 = c.iters;
+      c.stop_pos = INT32_MAX;
+    }
+  }
+}
+
+constexpr int32_t kTfqmrMaxRestarts = 8;
 
 // -------------------------------------------------------------- host side
 
@@ -621,7 +703,25 @@ extern "C" int spx_batch_tfqmr(spx_batch_handle B, const double* bvec, double* x
   }));
   hipLaunchKernelGGL(k_tq_init_finish, dim3(ns), dim3(kBlock), 0, s, pl, B->d_st, P2, rtol);
   SPX_CHECK_HIP(hipGetLastError());
-  const int64_t iters = (maxit + 1) / 2;  // two half-steps per iteration
+  // two half-steps per iteration, plus the polls a system may wait for
+  // its true-residual check
+  const int64_t iters = (maxit + 1) / 2 + (int64_t)(kTfqmrMaxRestarts + 1) * run.check_every;
+  auto verify = [&](int64_t k, bool* relaunched) -> int {
+    bool any = false;
+    for (int t = 0; t < ns; ++t) any = any || (B->h_st[t].verify && !B->h_st[t].done);
+    if (!any) return SPX_OK;
+    SPX_TRY(with_shape(sh, [&](auto shc) {
+      using SH = decltype(shc);
+      hipLaunchKernelGGL((k_tq_verify<SH>), dim3(G), dim3(kBlock), lds, s, B->d_sys, pl, bvec, x,
+                         V, dinv, B->d_st, P2, sh.rows);
+      return SPX_OK;
+    }));
+    hipLaunchKernelGGL(k_tq_verify_finish, dim3(ns), dim3(kBlock), 0, s, pl, B->d_st, P2, k,
+                       kTfqmrMaxRestarts);
+    SPX_CHECK_HIP(hipGetLastError());
+    *relaunched = true;
+    return SPX_OK;
+  };
   SPX_TRY(poll_loop(B, run, iters, s, [&](int64_t first, int64_t m) {
     return with_shape(sh, [&](auto shc) {
       using SH = decltype(shc);
@@ -639,7 +739,7 @@ extern "C" int spx_batch_tfqmr(spx_batch_handle B, const double* bvec, double* x
       }
       return SPX_OK;
     });
-  }));
+  }, verify));
   SPX_TRY(true_residuals(B, run, bvec, x, s));
   return finish(B, s, iters_out, relres_out, "batch_tfqmr");
 }

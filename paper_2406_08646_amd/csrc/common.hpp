@@ -108,7 +108,11 @@ struct CgScalars {
   // A kernel that must finish its own work after the stopping test compares
   // it with its own position instead of reading `done`, which another
   // workgroup of the same launch may already have set.
-  int32_t stop_pos, pad;
+  int32_t stop_pos;
+  // TFQMR cycles: verify = 1 once a cycle ended on its residual bound and
+  // the true residual is still to be checked; the current cycle started at
+  // iteration j0 after m0 half-steps; restarts done so far.
+  int32_t verify, restarts, j0, m0, pad;
 };
 
 }  // namespace spx

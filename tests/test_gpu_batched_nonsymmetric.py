@@ -24,24 +24,34 @@ def sigma_min_lower(p):
 
 
 def check_systems(orc, probs, bs, x, iters, relres, rtol, method, oracle_upto=None):
+    """True residuals of every system; against the oracle's own solve: the
+    error bound, each iteration count within max(4, 10%) and the batch's
+    mean relative difference within 2%.  BiCG and TFQMR residuals are not
+    monotone, and where they hover near the threshold rounding moves the
+    crossing by a few percent either way, so single counts get the wider
+    window while the batch average must still agree closely."""
     off = 0
     solver = orc.bicg if method == "bicg" else orc.tfqmr
+    diffs = []
     for s, (p, b) in enumerate(zip(probs, bs)):
         xs = x[off:off + p.n]
         off += p.n
         A = orc.assemble(p.n, p.i, p.j, p.v)
         r = np.linalg.norm(b - orc.spmv(A, xs))
-        slack = 1e-3 if method == "bicg" else 1e-2
-        assert relres[s] <= rtol * (1 + slack), (s, relres[s])
-        assert r <= rtol * np.linalg.norm(b) * (1 + slack), (s, r)
+        assert relres[s] <= rtol * (1 + 1e-3), (s, relres[s])
+        assert r <= rtol * np.linalg.norm(b) * (1 + 1e-3), (s, r)
         if oracle_upto is not None and p.n > oracle_upto:
             continue
         ref = solver(A, b, rtol)
         assert ref.status == 0
-        assert abs(iters[s] - ref.iters) <= max(4, math.ceil(0.03 * ref.iters)), \
+        assert abs(iters[s] - ref.iters) <= max(4, math.ceil(0.10 * ref.iters)), \
             (s, iters[s], ref.iters)
+        diffs.append((iters[s] - ref.iters) / max(1, ref.iters))
         rr = np.linalg.norm(b - orc.spmv(A, ref.x))
         assert np.linalg.norm(xs - ref.x) <= (r + rr) / sigma_min_lower(p) * (1 + 1e-6)
+    print(f"{method}: iteration differences vs oracle, mean {100 * np.mean(diffs):.2f}%, "
+          f"max |.| {100 * np.max(np.abs(diffs)):.2f}%", flush=True)
+    assert abs(np.mean(diffs)) <= 0.02
 
 
 @pytest.mark.parametrize("method", ["bicg", "tfqmr"])
@@ -72,6 +82,25 @@ def test_bicg_on_symmetric_batch_is_batched_cg_bit_for_bit():
     xb, ib, rb, sb = batch.batch_bicg(bvec, rtol=1e-9)
     assert sc == 0 and sb == 0 and ic == ib
     assert np.array_equal(bits(host(xc)), bits(host(xb)))
+
+
+def test_tfqmr_restarts_when_the_bound_passes_early(orc):
+    """System 20 of the full non-symmetric batch: its first cycle ends on the
+    bound with the true residual above 1e-8; the batch must restart it and
+    return a solution that meets the tolerance (the oracle does the same)."""
+    spx = require_gpu()
+    probs, bs = W.config6()
+    p, b = probs[20], bs[20]
+    batch = spx.batch_create([assemble(spx, p)])
+    x, iters, relres, st = batch.batch_tfqmr(dev(b), rtol=1e-8)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    ref = orc.tfqmr(A, b, 1e-8)
+    print(f"restart case: gpu {iters[0]} half-steps relres {relres[0]:.3e}; "
+          f"oracle {ref.iters} relres {ref.relres:.3e}", flush=True)
+    assert st == 0 and ref.status == 0
+    xs = host(x)
+    assert np.linalg.norm(b - orc.spmv(A, xs)) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-3)
+    assert abs(iters[0] - ref.iters) <= max(4, math.ceil(0.10 * ref.iters))
 
 
 def test_single_system_batch_is_independent_of_check_every():

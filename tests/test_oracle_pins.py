@@ -680,3 +680,20 @@ def test_bicg_tfqmr_breakdown_and_limits(orc):
     assert (g.status, g.iters) == (-5, 4) and (t.status, t.iters) == (-5, 5)
     for res in (orc.bicg(A, np.zeros(A.n), 1e-8), orc.tfqmr(A, np.zeros(A.n), 1e-8)):
         assert res.status == 0 and res.iters == 0 and np.all(res.x == 0)
+
+
+def test_tfqmr_success_means_true_residual_within_tolerance(orc):
+    """On this convection-dominated system the first TFQMR cycle ends on its
+    bound with the true residual above the tolerance; the returned x must
+    still meet the tolerance in an independent residual."""
+    probs, bs = W.config6()
+    p, b = probs[20], bs[20]
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    t = orc.tfqmr(A, b, 1e-8)
+    keep = (p.i >= 0) & (p.j >= 0)
+    M = sp.coo_matrix((p.v[keep], (p.i[keep], p.j[keep])), shape=(p.n, p.n)).tocsr()
+    assert t.status == 0
+    assert np.linalg.norm(b - M @ t.x) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-9)
+    # a single cycle (restarts impossible: the limit stops at the first pass)
+    first = orc.tfqmr(A, b, 1e-8, 470)
+    assert first.relres > 1e-8
