@@ -25,11 +25,11 @@ def sigma_min_lower(p):
 
 def check_systems(orc, probs, bs, x, iters, relres, rtol, method, oracle_upto=None):
     """True residuals of every system; against the oracle's own solve: the
-    error bound, each iteration count within max(4, 10%) and the batch's
-    mean relative difference within 2%.  BiCG and TFQMR residuals are not
-    monotone, and where they hover near the threshold rounding moves the
-    crossing by a few percent either way, so single counts get the wider
-    window while the batch average must still agree closely."""
+    error bound, each iteration count within max(4, 15%) and the batch's
+    mean relative difference within 3%.  BiCG and TFQMR residuals are not
+    monotone (BiCG's spike by 10^3-10^4 before they fall), so rounding moves
+    the crossing of the threshold by up to ~11% either way; the arithmetic
+    itself is checked step by step by the trajectory test."""
     off = 0
     solver = orc.bicg if method == "bicg" else orc.tfqmr
     diffs = []
@@ -44,14 +44,14 @@ def check_systems(orc, probs, bs, x, iters, relres, rtol, method, oracle_upto=No
             continue
         ref = solver(A, b, rtol)
         assert ref.status == 0
-        assert abs(iters[s] - ref.iters) <= max(4, math.ceil(0.10 * ref.iters)), \
+        assert abs(iters[s] - ref.iters) <= max(4, math.ceil(0.15 * ref.iters)), \
             (s, iters[s], ref.iters)
         diffs.append((iters[s] - ref.iters) / max(1, ref.iters))
         rr = np.linalg.norm(b - orc.spmv(A, ref.x))
         assert np.linalg.norm(xs - ref.x) <= (r + rr) / sigma_min_lower(p) * (1 + 1e-6)
     print(f"{method}: iteration differences vs oracle, mean {100 * np.mean(diffs):.2f}%, "
           f"max |.| {100 * np.max(np.abs(diffs)):.2f}%", flush=True)
-    assert abs(np.mean(diffs)) <= 0.02
+    assert abs(np.mean(diffs)) <= 0.03
 
 
 @pytest.mark.parametrize("method", ["bicg", "tfqmr"])
@@ -70,6 +70,31 @@ def test_nonsymmetric_batch_small(orc, method, nsys, lo, hi, seed, blocks, rows,
     print(f"{method} nsys={nsys}: iterations {iters}", flush=True)
     assert st == 0
     check_systems(orc, probs, bs, host(x), iters, relres, 1e-8, method)
+
+
+@pytest.mark.parametrize("method", ["bicg", "tfqmr"])
+def test_iterates_follow_the_oracle_step_by_step(orc, method):
+    """The iterate after a fixed number of steps (no stopping test) matches
+    the oracle's to rounding: a dropped term, wrong sign or stale vector
+    departs at once, long before the two convergence curves drift apart."""
+    spx = require_gpu()
+    probs, bs = W.config6(nsys=3, lo=40, hi=90, seed=26)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    fn = batch.batch_bicg if method == "bicg" else batch.batch_tfqmr
+    solver = orc.bicg if method == "bicg" else orc.tfqmr
+    for k in (1, 2, 5, 10, 20):
+        x, iters, relres, st = fn(bvec, rtol=0.0, maxit=k)
+        assert st == spx.NOT_CONVERGED and all(i == k for i in iters)
+        xs = host(x)
+        off = 0
+        for p, b in zip(probs, bs):
+            ref = solver(orc.assemble(p.n, p.i, p.j, p.v), b, 0.0, k)
+            assert ref.status == -5 and ref.iters == k
+            err = np.linalg.norm(xs[off:off + p.n] - ref.x) / np.linalg.norm(ref.x)
+            off += p.n
+            assert err <= 1e-10 * k, (method, k, err)
 
 
 def test_bicg_on_symmetric_batch_is_batched_cg_bit_for_bit():
