@@ -93,6 +93,10 @@ def _load():
         lib.oracle_bicg.restype = ctypes.c_int
         lib.oracle_tfqmr.argtypes = lib.oracle_pcg.argtypes + [_dref]
         lib.oracle_tfqmr.restype = ctypes.c_int
+        for name in ("oracle_lbfgs_recursive", "oracle_lbfgs_dense"):
+            fn = getattr(lib, name)
+            fn.argtypes = [_i64, _i64, _f64p, _f64p, _f64p, _f64p, _f64p]
+            fn.restype = None
         _lib = lib
     return _lib
 
@@ -292,6 +296,26 @@ def tfqmr(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 100000,
     st = lib.oracle_tfqmr(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit, ctypes.byref(it),
                           ctypes.byref(rr), ctypes.byref(bd))
     return TfqmrResult(x, it.value, rr.value, st, bd.value)
+
+
+def _lbfgs(fn, S, Y, g, h0):
+    S = np.asfortranarray(S, np.float64)  # column j contiguous
+    Y = np.asfortranarray(Y, np.float64)
+    n, m = S.shape
+    p = np.empty(n)
+    fn(n, m, S.ravel(order="F"), Y.ravel(order="F"), _cf(g), _cf(h0), p)
+    return p
+
+
+def lbfgs_recursive(S, Y, g, h0):
+    """p = H g by the two-loop recursion; S, Y: n x m, oldest pair first."""
+    return _lbfgs(_load().oracle_lbfgs_recursive, S, Y, g, h0)
+
+
+def lbfgs_dense(S, Y, g, h0):
+    """p = H g by the intermediate dense formula (triangular solves with
+    R = triu(S^T Y))."""
+    return _lbfgs(_load().oracle_lbfgs_dense, S, Y, g, h0)
 
 
 @dataclass

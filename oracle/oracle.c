@@ -809,3 +809,93 @@ void oracle_block_reduce(int64_t nblocks, int64_t block, const double* grad_v, c
     grad_e[e] = s;
   }
 }
+
+/* ------------------------------------------------------------------------
+ * Limited-memory BFGS, product p = H_k g (paper Sec. 8, dense
+ * reformulations).  S = [s_0 .. s_{m-1}], Y = [y_0 .. y_{m-1}] hold the
+ * m most recent pairs, oldest first, column-major (column j at j*n); the
+ * base operator is the diagonal h0 (it may change from call to call).
+ *
+ * oracle_lbfgs_recursive: the two-loop recursion.
+ *   q = g;  for j = m-1 .. 0:  alpha_j = s_j.q / d_j;  q -= alpha_j y_j
+ *   p = h0 q;  for j = 0 .. m-1:  beta_j = y_j.p / d_j;  p += (alpha_j - beta_j) s_j
+ * with d_j = s_j.y_j.  (The paper's printed listing adds a multiple of y_j
+ * in the second loop; only s_j yields H_k g, which its dense formula below
+ * states, so s_j is taken.)
+ *
+ * oracle_lbfgs_dense: the paper's intermediate dense formula
+ *   H_k g = [I, -S R^-T] [I 0; Y^T I] diag(H0, D) [I Y; 0 I] [I; -R^-1 S^T] g
+ * with R = triu(S^T Y), D = diag(S^T Y), evaluated right to left:
+ *   c = -R^-1 (S^T g);  a = h0 (g + Y c);  f = Y^T a + D c;
+ *   e = R^-T f;  p = a - S e.
+ * Dot products are plain in-order sums.
+ * ---------------------------------------------------------------------- */
+static double dot_plain(int64_t n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
+  return s;
+}
+
+void oracle_lbfgs_recursive(int64_t n, int64_t m, const double* S, const double* Y,
+                            const double* g, const double* h0, double* p) {
+  double* q = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double* alpha = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  for (int64_t i = 0; i < n; i++) q[i] = g[i];
+  for (int64_t j = m - 1; j >= 0; j--) {
+    const double* s = S + j * n;
+    const double* y = Y + j * n;
+    alpha[j] = dot_plain(n, s, q) / dot_plain(n, s, y);
+    for (int64_t i = 0; i < n; i++) q[i] = q[i] - alpha[j] * y[i];
+  }
+  for (int64_t i = 0; i < n; i++) p[i] = h0[i] * q[i];
+  for (int64_t j = 0; j < m; j++) {
+    const double* s = S + j * n;
+    const double* y = Y + j * n;
+    double beta = dot_plain(n, y, p) / dot_plain(n, s, y);
+    for (int64_t i = 0; i < n; i++) p[i] = p[i] + (alpha[j] - beta) * s[i];
+  }
+  free(q);
+  free(alpha);
+}
+
+void oracle_lbfgs_dense(int64_t n, int64_t m, const double* S, const double* Y,
+                        const double* g, const double* h0, double* p) {
+  const size_t mm = (size_t)(m > 0 ? m : 1);
+  double* M = (double*)malloc(sizeof(double) * mm * mm); /* M[a*m+b] = s_a.y_b */
+  double* c = (double*)malloc(sizeof(double) * mm);
+  double* f = (double*)malloc(sizeof(double) * mm);
+  double* e = (double*)malloc(sizeof(double) * mm);
+  double* a = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int64_t x = 0; x < m; x++)
+    for (int64_t y = 0; y < m; y++) M[x * m + y] = dot_plain(n, S + x * n, Y + y * n);
+  /* c = -R^-1 (S^T g): back substitution, R upper triangular */
+  for (int64_t x = m - 1; x >= 0; x--) {
+    double t = -dot_plain(n, S + x * n, g);
+    for (int64_t y = x + 1; y < m; y++) t -= M[x * m + y] * c[y];
+    c[x] = t / M[x * m + x];
+  }
+  /* a = h0 (g + Y c) */
+  for (int64_t i = 0; i < n; i++) {
+    double t = g[i];
+    for (int64_t y = 0; y < m; y++) t += Y[y * n + i] * c[y];
+    a[i] = h0[i] * t;
+  }
+  /* f = Y^T a + D c;  e = R^-T f: forward substitution, R^T lower */
+  for (int64_t x = 0; x < m; x++) f[x] = dot_plain(n, Y + x * n, a) + M[x * m + x] * c[x];
+  for (int64_t x = 0; x < m; x++) {
+    double t = f[x];
+    for (int64_t y = 0; y < x; y++) t -= M[y * m + x] * e[y];
+    e[x] = t / M[x * m + x];
+  }
+  /* p = a - S e */
+  for (int64_t i = 0; i < n; i++) {
+    double t = a[i];
+    for (int64_t x = 0; x < m; x++) t -= S[x * n + i] * e[x];
+    p[i] = t;
+  }
+  free(M);
+  free(c);
+  free(f);
+  free(e);
+  free(a);
+}

@@ -318,6 +318,21 @@ def config6(nsys: int = 64, lo: int = 32, hi: int = 512, sigma: float = 0.5,
     return probs, bs
 
 
+def lbfgs_history(n: int, m: int, seed: int = 6):
+    """A limited-memory history for H_k g: S ~ N(0, 1) (n x m, oldest pair
+    first), Y = d * S + 0.1 N(0, 1) with a per-row curvature d ~ U[0.5, 2]
+    (so s_j . y_j > 0), the gradient g ~ N(0, 1) and a diagonal base
+    operator h0 ~ U[0.5, 1.5].  Draw order: d, S, noise, g, h0.  S and Y are
+    column-major (each pair contiguous)."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(0.5, 2.0, n)
+    S = np.asfortranarray(rng.standard_normal((n, m)))
+    Y = np.asfortranarray(d[:, None] * S + 0.1 * rng.standard_normal((n, m)))
+    g = rng.standard_normal(n)
+    h0 = rng.uniform(0.5, 1.5, n)
+    return S, Y, g, h0
+
+
 def config5(N: int = 256):
     """2-D Q1 Poisson on N x N elements with kappa_e = exp(theta_e), theta ~
     N(0, 1) from seed 2, right-hand side b = 1.  Returns the problem (with

@@ -697,3 +697,58 @@ def test_tfqmr_success_means_true_residual_within_tolerance(orc):
     # a single cycle (restarts impossible: the limit stops at the first pass)
     first = orc.tfqmr(A, b, 1e-8, 470)
     assert first.relres > 1e-8
+
+
+# ----------------------------------------------------------- L-BFGS H_k g
+
+def explicit_bfgs(S, Y, h0):
+    """H_k from diag(h0) by the BFGS update with each pair, oldest first:
+    H <- (I - r s y^T) H (I - r y s^T) + r s s^T, r = 1 / s.y."""
+    n, m = S.shape
+    H = np.diag(h0)
+    for j in range(m):
+        s, y = S[:, j], Y[:, j]
+        r = 1.0 / (s @ y)
+        V = np.eye(n) - r * np.outer(y, s)
+        H = V.T @ H @ V + r * np.outer(s, s)
+    return H
+
+
+@pytest.mark.parametrize("n,m,seed", [(40, 0, 1), (40, 1, 2), (40, 5, 3), (60, 12, 4), (25, 25, 5)])
+def test_lbfgs_forms_match_the_explicit_bfgs_matrix(orc, n, m, seed):
+    S, Y, g, h0 = W.lbfgs_history(n, m, seed)
+    if m:
+        assert np.all(np.einsum("ij,ij->j", S, Y) > 0)
+    Hg = explicit_bfgs(S, Y, h0) @ g
+    for p in (orc.lbfgs_recursive(S, Y, g, h0), orc.lbfgs_dense(S, Y, g, h0)):
+        assert np.linalg.norm(p - Hg) <= 1e-12 * np.linalg.norm(Hg)
+
+
+def test_lbfgs_secant_condition_and_symmetry(orc):
+    """H_k y_newest = s_newest exactly in exact arithmetic, and H_k is
+    symmetric: a.(H b) = b.(H a)."""
+    S, Y, g, h0 = W.lbfgs_history(80, 7, 6)
+    for f in (orc.lbfgs_recursive, orc.lbfgs_dense):
+        p = f(S, Y, Y[:, -1], h0)
+        assert np.linalg.norm(p - S[:, -1]) <= 1e-12 * np.linalg.norm(S[:, -1])
+        a, b = np.random.default_rng(7).standard_normal((2, 80))
+        assert abs(a @ f(S, Y, b, h0) - b @ f(S, Y, a, h0)) <= 1e-12 * np.linalg.norm(a) * np.linalg.norm(b) * 10
+
+
+def test_lbfgs_listing_reading(orc):
+    """With y_j instead of s_j in the second loop (as the paper's listing
+    prints it) the result is not H_k g; with s_j it is."""
+    S, Y, g, h0 = W.lbfgs_history(30, 4, 8)
+    m = S.shape[1]
+    q = g.copy()
+    alpha = np.zeros(m)
+    for j in range(m - 1, -1, -1):
+        alpha[j] = (S[:, j] @ q) / (S[:, j] @ Y[:, j])
+        q = q - alpha[j] * Y[:, j]
+    p = h0 * q
+    for j in range(m):
+        beta = (Y[:, j] @ p) / (S[:, j] @ Y[:, j])
+        p = p + (alpha[j] - beta) * Y[:, j]
+    Hg = explicit_bfgs(S, Y, h0) @ g
+    assert np.linalg.norm(p - Hg) > 1e-3 * np.linalg.norm(Hg)
+    assert np.linalg.norm(orc.lbfgs_recursive(S, Y, g, h0) - Hg) <= 1e-12 * np.linalg.norm(Hg)
