@@ -30,6 +30,7 @@ extern "C" {
 typedef struct spx_matrix* spx_handle;
 typedef struct spx_batch* spx_batch_handle;
 typedef struct spx_vec_coo* spx_vec_handle;
+typedef struct spx_lbfgs* spx_lbfgs_handle;
 
 enum spx_status {
   SPX_OK = 0,
@@ -239,6 +240,41 @@ int spx_batch_bicg(spx_batch_handle b, const double* bvec, double* x, double rto
 int spx_batch_tfqmr(spx_batch_handle b, const double* bvec, double* x, double rtol, int64_t maxit,
                     const spx_batch_tuning* tuning, void* stream, int64_t* iters_out,
                     double* relres_out);
+
+/* ---------------------------------------------------------------------------
+ * Limited-memory BFGS — paper Sec. 8 (dense reformulations of algorithms):
+ * the product p = H_k g with the inverse-Hessian approximation built from
+ * the m most recent pairs (s_j, y_j), in the intermediate dense form
+ *   H_k g = [I, -S R^-T] [I 0; Y^T I] diag(H0, D) [I Y; 0 I] [I; -R^-1 S^T] g
+ * with S = [s_oldest .. s_newest], Y likewise, R = triu(S^T Y),
+ * D = diag(S^T Y) and a diagonal base operator H0 = diag(h0) that may change
+ * from call to call (variable metric).  This equals the two-loop recursion
+ * and the m successive BFGS updates of H0.
+ * ------------------------------------------------------------------------- */
+
+/* History of m pairs (1 <= m <= 64) of vectors of length n.  The handle owns
+ * S and Y (n x m each, column-major), the m x m products s_a.y_b and the
+ * workspace (about 2 n m + n doubles of device memory). */
+int spx_lbfgs_create(int64_t n, int32_t m, void* stream, spx_lbfgs_handle* out);
+int spx_lbfgs_destroy(spx_lbfgs_handle h);
+/* Forgets every pair (the next apply returns h0 g). */
+int spx_lbfgs_reset(spx_lbfgs_handle h);
+/* HOST outputs: length, history size, pairs held. */
+int spx_lbfgs_get_info(spx_lbfgs_handle h, int64_t* n, int32_t* m, int32_t* count);
+
+/* Appends the pair (s, y), dropping the oldest when m are held, and updates
+ * the products s_a.y_b of the new row and column (one pass over S and Y).
+ * s, y: device float64[n], copied.  The caller keeps to the curvature
+ * condition s.y > 0 (not checked; a non-positive s_j.y_j makes later
+ * products meaningless).  Asynchronous. */
+int spx_lbfgs_update(spx_lbfgs_handle h, const double* s, const double* y, void* stream);
+
+/* p = H_k g.  g: device float64[n]; h0: device float64[n] (the diagonal of
+ * H0) or NULL for H0 = I; p: device float64[n], must not alias g.  Three
+ * passes over the rows (S^T g; a = h0 (g + Y c) with Y^T a; p = a - S e)
+ * with the two m x m triangular solves between them.  Asynchronous. */
+int spx_lbfgs_apply(spx_lbfgs_handle h, const double* g, const double* h0, double* p,
+                    void* stream);
 
 /* ---------------------------------------------------------------------------
  * Differentiation of u = A(v)^-1 b through the COO assembly (reverse mode).

@@ -74,6 +74,12 @@ _SIGNATURES = {
     "spx_batch_create": [_i32, ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp)],
     "spx_batch_destroy": [_vp],
     "spx_batch_total_rows": [_vp, _pi64],
+    "spx_lbfgs_create": [_i64, _i32, _vp, ctypes.POINTER(_vp)],
+    "spx_lbfgs_destroy": [_vp],
+    "spx_lbfgs_reset": [_vp],
+    "spx_lbfgs_get_info": [_vp, _pi64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "spx_lbfgs_update": [_vp, _vp, _vp, _vp],
+    "spx_lbfgs_apply": [_vp, _vp, _vp, _vp, _vp],
     "spx_batch_cg": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
     "spx_batch_bicg": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
     "spx_batch_tfqmr": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
@@ -415,6 +421,54 @@ class Batch:
 
 def batch_create(mats: Sequence[Matrix], stream=None) -> Batch:
     return Batch(mats, stream)
+
+
+class Lbfgs:
+    """Limited-memory BFGS history on the GPU (paper Sec. 8): update with
+    pairs (s, y), apply p = H_k g in the intermediate dense form."""
+
+    def __init__(self, n: int, m: int, stream=None):
+        h = ctypes.c_void_p()
+        _check(load_library().spx_lbfgs_create(n, m, _stream(stream), ctypes.byref(h)))
+        self._h, self.n, self.m = h, n, m
+
+    def update(self, s, y, stream=None) -> None:
+        _dev(s, torch.float64, self.n, "s")
+        _dev(y, torch.float64, self.n, "y")
+        _check(load_library().spx_lbfgs_update(self._h, _ptr(s), _ptr(y), _stream(stream)))
+
+    def apply(self, g, h0=None, p=None, stream=None):
+        _dev(g, torch.float64, self.n, "g")
+        if h0 is not None:
+            _dev(h0, torch.float64, self.n, "h0")
+        p = torch.empty_like(g) if p is None else _dev(p, torch.float64, self.n, "p")
+        _check(load_library().spx_lbfgs_apply(self._h, _ptr(g), _ptr(h0) if h0 is not None else None,
+                                              _ptr(p), _stream(stream)))
+        return p
+
+    def reset(self) -> None:
+        _check(load_library().spx_lbfgs_reset(self._h))
+
+    @property
+    def count(self) -> int:
+        c = ctypes.c_int32()
+        _check(load_library().spx_lbfgs_get_info(self._h, None, None, ctypes.byref(c)))
+        return c.value
+
+    def destroy(self):
+        if self._h:
+            _check(load_library().spx_lbfgs_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def lbfgs_create(n: int, m: int, stream=None) -> Lbfgs:
+    return Lbfgs(n, m, stream)
 
 
 class CooVector:
