@@ -255,6 +255,51 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
     out["nonsymmetric_batch64"] = nonsym
     del batch6, mats6, E6, ens6, singles
 
+    # ---- L-BFGS H_k g: one update + one apply, effective bandwidth of the paper
+    lb = []
+    gen = torch.Generator(device=dev).manual_seed(6)
+    for n_l, m_l in ((1_000_000, 5), (1_000_000, 50), (10_000_000, 5), (10_000_000, 10),
+                     (10_000_000, 50)):
+        L = spx.lbfgs_create(n_l, m_l)
+        dcurv = torch.rand(n_l, generator=gen, device=dev, dtype=torch.float64) * 1.5 + 0.5
+        hist = []
+        for _ in range(m_l + 4):
+            s_ = torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
+            y_ = dcurv * s_ + 0.1 * torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
+            hist.append((s_, y_))
+        g_ = torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
+        h0_ = torch.rand(n_l, generator=gen, device=dev, dtype=torch.float64) + 0.5
+        p_ = torch.empty_like(g_)
+        for s_, y_ in hist[:m_l]:
+            L.update(s_, y_)
+        evs = []
+        for k in range(8):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            s_, y_ = hist[m_l + (k % 4)]
+            e0.record()
+            L.update(s_, y_)
+            e1.record()
+            L.apply(g_, h0_, p_)
+            e2.record()
+            evs.append((e0, e1, e2))
+        torch.cuda.synchronize()
+        upd = statistics.median(a.elapsed_time(b) for a, b, _ in evs)
+        app = statistics.median(b.elapsed_time(c) for _, b, c in evs)
+        t_ms = statistics.median(a.elapsed_time(c) for a, _, c in evs)
+        be = 8 * n_l * (2 * m_l + 2) / (t_ms * 1e-3) / 1e9
+        lb.append({"n": n_l, "m": m_l, "update_ms": round(upd, 4), "apply_ms": round(app, 4),
+                   "total_ms": round(t_ms, 4), "effective_gbs": round(be, 1),
+                   "hbm_bytes": 8 * n_l * (5 * m_l + 8),
+                   "hbm_gbs": round(8 * n_l * (5 * m_l + 8) / (t_ms * 1e-3) / 1e9, 1)})
+        log(f"lbfgs n={n_l} m={m_l}: update {upd:.3f} ms apply {app:.3f} ms B_e {be:.0f} GB/s")
+        L.destroy()
+        del hist, dcurv, g_, h0_, p_
+    out["lbfgs"] = {"points": lb,
+                    "effective_bandwidth": "8 n (2m + 2) bytes / (T_update + T_apply): "
+                                           "S and Y read once, g read, p written",
+                    "hbm_bytes": "bytes this design moves: S read 3 times and Y twice "
+                                 "(update, S^T g, a and Y^T a, p) plus 8 vector passes"}
+
     # ---- gradient on 256 x 256 elements
     N = 256
     one = W.q1_poisson(N, 2, kappa=np.ones(N * N))

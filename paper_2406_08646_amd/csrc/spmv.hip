@@ -128,7 +128,8 @@ int launch_vector(const Csr& A, int lanes, const double* x, double* y, int remap
 
 // Y[r, c] for c < nrhs; a group of G lanes per row, lane c owns column c
 // (and c + G, ...).  The row's (value, column) pair is loaded once per lane
-// group and the 8*G contiguous bytes of X per nonzero are one transaction.
+// group and the 8*G contiguous bytes of X per nonzero are one transaction;
+// each lane keeps 8 such gathers in flight and adds them in entry order.
 template <int G, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
                                                 const int32_t* __restrict__ col,
@@ -141,11 +142,26 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(int64_t n, const int32_t* __rest
   const int lane = threadIdx.x % G;
   if (row >= n) return;
   const int32_t t0 = rowptr[row], t1 = rowptr[row + 1];
+  constexpr int U = 8;  // independent gathers in flight per lane
   for (int64_t c0 = 0; c0 < nrhs; c0 += G) {
     const int64_t c = c0 + lane;
     double acc = 0.0;
     if (c < nrhs) {
-      for (int32_t t = t0; t < t1; ++t) {
+      int32_t t = t0;
+      for (; t + U <= t1; t += U) {
+        double a[U], xv[U];
+        int64_t cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a[u] = stream_load(val + t + u);
+          cc[u] = stream_load(col + t + u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = X[cc[u] * ldx + c];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += a[u] * xv[u];
+      }
+      for (; t < t1; ++t) {
         const double a = stream_load(val + t);
         const int64_t cc = stream_load(col + t);
         acc += a * X[cc * ldx + c];
