@@ -157,6 +157,35 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
                      "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
     log(f"spmm16: {spmm_ms:.3f} ms")
 
+    # ---- COO vector assembly: the element load vector of the same mesh (8 contributions
+    # per element, one per local node, in element order)
+    iv = d(np.ascontiguousarray(prob.i.reshape(-1, prob.nloc, prob.nloc)[:, :, 0].reshape(-1)))
+    vv = d(W.spmm_rhs(iv.numel(), 1).reshape(-1))
+    xv = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V = spx.vec_coo_preallocate(prob.n, iv)
+    torch.cuda.synchronize()
+    pre_ms = (time.perf_counter() - t0) * 1e3
+    info = V.get_info()
+    for _ in range(3):
+        V.set_values_coo(vv, xv)
+    evv = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for s_, e_ in evv:
+        s_.record()
+        V.set_values_coo(vv, xv)
+        e_.record()
+    torch.cuda.synchronize()
+    vset_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in evv)
+    ncv, nuq = iv.numel(), int(info["nunique"])
+    vbytes = ncv * 8 + ncv * 4 + (nuq + 1) * 4 + nuq * 8 + nuq * 4
+    out["vec_coo"] = {"ncoo": ncv, "entries": nuq, "preallocate_ms": round(pre_ms, 3),
+                      "set_values_ms": round(vset_ms, 4), "bytes": vbytes,
+                      "gbs": round(vbytes / (vset_ms * 1e-3) / 1e9, 1)}
+    log(f"vec_coo: {ncv} triplets -> {nuq} entries, set_values {vset_ms:.3f} ms")
+    V.destroy()
+    del iv, vv, xv
+
     # ---- single-reduction vs textbook CG on the same matrix and b
     b_d = d(b_np)
     forms = {}
