@@ -212,6 +212,38 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
     A.destroy()
     del X, Y
 
+    # ---- host poll after every iteration ("synchronous") vs every 20 ("asynchronous"),
+    # time per iteration against the number of nonzeros, CG and TFQMR
+    curve = []
+    for dim, N in ((2, 16), (2, 32), (2, 64), (2, 128), (2, 256), (2, 512), (3, 24), (3, 48),
+                   (3, 96)):
+        pq = W.q1_poisson(N, dim)
+        Aq = spx.coo_preallocate(pq.n, d(pq.i), d(pq.j))
+        Aq.set_values_coo(d(pq.v))
+        bq = torch.ones(pq.n, dtype=torch.float64, device=dev)
+        one = spx.batch_create([Aq])
+        row = {"dim": dim, "grid": N, "n": pq.n, "nnz": Aq.nnz}
+        for ce, tag in ((1, "sync"), (20, "async")):
+            Aq.cg_solve(bq, rtol=0.0, maxit=20, check_every=ce)
+            ms, r = timed(lambda: Aq.cg_solve(bq, rtol=0.0, maxit=200, check_every=ce), reps=3)
+            row[f"cg_{tag}_us_per_iter"] = round(1e3 * ms / max(1, r.iters), 2)
+            one.batch_tfqmr(bq, rtol=0.0, maxit=20, check_every=ce)
+            ms, r = timed(lambda: one.batch_tfqmr(bq, rtol=0.0, maxit=400, check_every=ce), reps=3)
+            row[f"tfqmr_{tag}_us_per_halfstep"] = round(1e3 * ms / max(1, r[1][0]), 2)
+        row["cg_async_speedup"] = round(row["cg_sync_us_per_iter"] / row["cg_async_us_per_iter"], 2)
+        row["tfqmr_async_speedup"] = round(row["tfqmr_sync_us_per_halfstep"]
+                                           / row["tfqmr_async_us_per_halfstep"], 2)
+        curve.append(row)
+        log(f"async curve nnz={Aq.nnz}: cg {row['cg_sync_us_per_iter']} vs "
+            f"{row['cg_async_us_per_iter']} us/it, tfqmr {row['tfqmr_sync_us_per_halfstep']} vs "
+            f"{row['tfqmr_async_us_per_halfstep']} us/half-step")
+        one.destroy()
+        Aq.destroy()
+    out["sync_vs_async"] = {"points": curve,
+                            "note": "host polls the device stop flag after every iteration (sync) "
+                                    "or every 20 (async); 200 CG iterations / 400 TFQMR half-steps "
+                                    "with rtol = 0, time per iteration"}
+
     # ---- 64-system batch
     probs, bs = W.config4()
     mats = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs]

@@ -20,7 +20,6 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
-#include <type_traits>
 
 #include "common.hpp"
 #include "device.hpp"
@@ -48,11 +47,16 @@ using namespace solver;
 
 constexpr int kMaxHistory = 64;
 constexpr int kLB = 256;
+constexpr int kJB = 8;      // columns per accumulator chunk
+constexpr int kFused = 16;  // up to this many pairs, a and Y^T a share one pass
 
-// Column pointers of the pairs in use, oldest first (a kernel argument, so
-// the walk needs no slot arithmetic).
-struct Cols {
-  const double* p[kMaxHistory];
+// The ring: logical pair b (oldest first) lives in slot start + b (mod m).
+struct Ring {
+  int m, start, cnt;
+  __device__ __forceinline__ int64_t slot(int b) const {
+    const int s = start + b;
+    return s >= m ? s - m : s;
+  }
 };
 
 // Row range of workgroup b of G over n rows (contiguous, balanced).
@@ -61,104 +65,105 @@ __device__ __forceinline__ void rows_of(int64_t n, int b, int G, int64_t* lo, in
   *hi = n * (b + 1) / G;
 }
 
-// Sum over the workgroup of MM per-thread accumulators; thread 0 of the
-// workgroup gets the totals in out[0..cnt).
-template <int MM>
-__device__ __forceinline__ void block_sums(double (&acc)[MM], int cnt, double* lds, double* out) {
+// Workgroup sums of the first cnt of NA per-thread accumulators; the totals
+// land in out[0..cnt).
+template <int NA>
+__device__ __forceinline__ void block_sums(const double (&acc)[NA], int cnt, double* lds,
+                                           double* out) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int j = 0; j < cnt; ++j) {
-    double v = acc[j];
-    v = wave_sum(v);
-    if (lane == 0) lds[w * MM + j] = v;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    if (j < cnt) {
+      const double v = wave_sum(acc[j]);
+      if (lane == 0) lds[w * NA + j] = v;
+    }
   }
   __syncthreads();
   if (threadIdx.x < cnt) {
     double s = 0.0;
-    for (int q = 0; q < kLB / 64; ++q) s += lds[q * MM + threadIdx.x];
+    for (int q = 0; q < kLB / 64; ++q) s += lds[q * NA + threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();
 }
 
-// ---------------------------------------------------------------- update
-// Writes the new pair into its slot (Snew, Ynew) and forms partials of
-// u_b = s_new . y_b and v_b = s_b . y_new over the `cnt` pairs in use,
-// oldest first; logical index cnt - 1 is the new pair, whose values come
-// straight from s and y.
-template <int MM>
-__global__ __launch_bounds__(kLB) void k_lb_update(int64_t n, double* __restrict__ Snew,
-                                                   double* __restrict__ Ynew,
-                                                   const double* __restrict__ s,
-                                                   const double* __restrict__ y, Cols Sc, Cols Yc,
-                                                   int cnt, double* __restrict__ P) {
-  __shared__ double lds[(kLB / 64) * MM];
-  __shared__ double tot[MM];
+// Partials of d_b = sum_i col_b[i] w[i] over the workgroup's rows, for the
+// ring's cnt columns, into P[(row0 + b) * G + workgroup].  Columns go in
+// chunks of kJB accumulators (each element of the history read once; w
+// re-read per chunk, from cache).
+__device__ __forceinline__ void gemvt_partials(int64_t n, const double* __restrict__ base,
+                                               Ring R, const double* __restrict__ w,
+                                               double* __restrict__ P, int row0, double* lds,
+                                               double* tot) {
   int64_t lo, hi;
   rows_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  double u[MM], v[MM];
+  for (int jb = 0; jb < R.cnt; jb += kJB) {
+    const int nc = R.cnt - jb < kJB ? R.cnt - jb : kJB;
+    const double* cp[kJB];
 #pragma unroll
-  for (int b = 0; b < MM; ++b) u[b] = v[b] = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
-    const double si = s[i], yi = y[i];
-    Snew[i] = si;
-    Ynew[i] = yi;
+    for (int u = 0; u < kJB; ++u) cp[u] = base + (u < nc ? R.slot(jb + u) : 0) * n;
+    double acc[kJB];
 #pragma unroll
-    for (int b = 0; b < MM; ++b) {
-      if (b < cnt) {
-        const bool last = b == cnt - 1;
-        const double yb = last ? yi : Yc.p[b][i];
-        const double sbv = last ? si : Sc.p[b][i];
-        u[b] += si * yb;
-        v[b] += sbv * yi;
-      }
+    for (int u = 0; u < kJB; ++u) acc[u] = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
+      const double wi = w[i];
+#pragma unroll
+      for (int u = 0; u < kJB; ++u)
+        if (u < nc) acc[u] += cp[u][i] * wi;
     }
+    block_sums<kJB>(acc, nc, lds, tot);
+    if (threadIdx.x < nc) P[(int64_t)(row0 + jb + threadIdx.x) * gridDim.x + blockIdx.x] = tot[threadIdx.x];
   }
-  const int G = gridDim.x;
-  block_sums<MM>(u, cnt, lds, tot);
-  if (threadIdx.x < cnt) P[(int64_t)threadIdx.x * G + blockIdx.x] = tot[threadIdx.x];
-  block_sums<MM>(v, cnt, lds, tot);
-  if (threadIdx.x < cnt) P[(int64_t)(MM + threadIdx.x) * G + blockIdx.x] = tot[threadIdx.x];
 }
 
-// one workgroup per (logical index, kind): SY row and column of the new
-// slot; workgroups past the pairs in use leave SY alone
-template <int MM>
-__global__ __launch_bounds__(kLB) void k_lb_update_finish(int m, const double* __restrict__ P,
-                                                          int G, int slot, int start, int cnt,
+// ---------------------------------------------------------------- update
+__global__ void k_lb_put(int64_t n, const double* __restrict__ s, const double* __restrict__ y,
+                         double* __restrict__ Snew, double* __restrict__ Ynew) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    Snew[i] = s[i];
+    Ynew[i] = y[i];
+  }
+}
+
+// Partials of u_b = s_new . y_b (rows 0..cnt) and v_b = s_b . y_new (rows
+// kMaxHistory + b); the new pair is already in its slot (logical cnt - 1).
+__global__ __launch_bounds__(kLB) void k_lb_update(int64_t n, const double* __restrict__ S,
+                                                   const double* __restrict__ Y,
+                                                   const double* __restrict__ s,
+                                                   const double* __restrict__ y, Ring R,
+                                                   double* __restrict__ P) {
+  __shared__ double lds[(kLB / 64) * kJB];
+  __shared__ double tot[kJB];
+  gemvt_partials(n, Y, R, s, P, 0, lds, tot);
+  gemvt_partials(n, S, R, y, P, kMaxHistory, lds, tot);
+}
+
+// one workgroup per (kind, logical index): SY row and column of the new slot
+__global__ __launch_bounds__(kLB) void k_lb_update_finish(const double* __restrict__ P, int G,
+                                                          Ring R, int slot,
                                                           double* __restrict__ SY) {
   __shared__ double lds[kLds];
-  const int b = blockIdx.x % MM, kind = blockIdx.x / MM;
-  if (b >= cnt) return;
-  const double t = reduce_all(P + (int64_t)(kind * MM + b) * G, G, lds);
+  const int kind = blockIdx.x >= R.cnt ? 1 : 0;
+  const int b = blockIdx.x - kind * R.cnt;
+  const double t = reduce_all(P + (int64_t)(kind * kMaxHistory + b) * G, G, lds);
   if (threadIdx.x == 0) {
-    const int sb = (start + b) % m;
+    const int64_t sb = R.slot(b);
     if (kind == 0)
-      SY[slot * m + sb] = t;  // s_new . y_b
+      SY[slot * R.m + sb] = t;  // s_new . y_b
     else
-      SY[sb * m + slot] = t;  // s_b . y_new
+      SY[sb * R.m + slot] = t;  // s_b . y_new
   }
 }
 
 // ----------------------------------------------------------------- apply
 // pass 1: partials of q_b = s_b . g
-template <int MM>
-__global__ __launch_bounds__(kLB) void k_lb_sg(int64_t n, Cols Sc, const double* __restrict__ g,
-                                               int cnt, double* __restrict__ P) {
-  __shared__ double lds[(kLB / 64) * MM];
-  __shared__ double tot[MM];
-  int64_t lo, hi;
-  rows_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  double q[MM];
-#pragma unroll
-  for (int b = 0; b < MM; ++b) q[b] = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
-    const double gi = g[i];
-#pragma unroll
-    for (int b = 0; b < MM; ++b)
-      if (b < cnt) q[b] += Sc.p[b][i] * gi;
-  }
-  block_sums<MM>(q, cnt, lds, tot);
-  if (threadIdx.x < cnt) P[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = tot[threadIdx.x];
+__global__ __launch_bounds__(kLB) void k_lb_sg(int64_t n, const double* __restrict__ S, Ring R,
+                                               const double* __restrict__ g,
+                                               double* __restrict__ P) {
+  __shared__ double lds[(kLB / 64) * kJB];
+  __shared__ double tot[kJB];
+  gemvt_partials(n, S, R, g, P, 0, lds, tot);
 }
 
 // one workgroup per logical index: out[b] = sum of the G partials of b
@@ -170,85 +175,114 @@ __global__ __launch_bounds__(kLB) void k_lb_reduce(const double* __restrict__ P,
 }
 
 // R_ab (a <= b, logical) = s_a . y_b
-__device__ __forceinline__ double rmat(const double* SY, int m, int start, int a, int b) {
-  return SY[((start + a) % m) * m + (start + b) % m];
+__device__ __forceinline__ double rmat(const double* SY, const Ring& R, int a, int b) {
+  return SY[R.slot(a) * R.m + R.slot(b)];
 }
 
 // pass 2: c = -R^-1 q (every workgroup; workgroup 0 stores it);
-// a = h0 (g + Y c); partials of f_b = y_b . a
-template <int MM>
-__global__ __launch_bounds__(kLB) void k_lb_ya(int64_t n, int m, Cols Yc,
+// a = h0 (g + Y c); with FUSED, also the partials of f_b = y_b . a
+template <bool FUSED>
+__global__ __launch_bounds__(kLB) void k_lb_ya(int64_t n, const double* __restrict__ Y, Ring R,
                                                const double* __restrict__ g,
                                                const double* __restrict__ h0,
-                                               const double* __restrict__ SY, int start, int cnt,
+                                               const double* __restrict__ SY,
                                                double* __restrict__ red,
                                                double* __restrict__ a_out,
                                                double* __restrict__ P) {
-  __shared__ double lds[(kLB / 64) * MM];
-  __shared__ double tot[MM];
-  __shared__ double cs[MM];
+  __shared__ double lds[(kLB / 64) * kFused];
+  __shared__ double tot[kFused];
+  __shared__ double cs[kMaxHistory];
+  const int cnt = R.cnt;
   if (threadIdx.x == 0) {
     const double* q = red;
     for (int x = cnt - 1; x >= 0; --x) {
       double t = -q[x];
-      for (int y = x + 1; y < cnt; ++y) t -= rmat(SY, m, start, x, y) * cs[y];
-      cs[x] = t / rmat(SY, m, start, x, x);
+      for (int y = x + 1; y < cnt; ++y) t -= rmat(SY, R, x, y) * cs[y];
+      cs[x] = t / rmat(SY, R, x, x);
     }
     if (blockIdx.x == 0)
-      for (int x = 0; x < cnt; ++x) red[MM + x] = cs[x];
+      for (int x = 0; x < cnt; ++x) red[kMaxHistory + x] = cs[x];
   }
   __syncthreads();
-  double c[MM];
-#pragma unroll
-  for (int b = 0; b < MM; ++b) c[b] = b < cnt ? cs[b] : 0.0;
   int64_t lo, hi;
   rows_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  double f[MM];
+  if constexpr (FUSED) {
+    const double* cp[kFused];
+    double c[kFused], f[kFused];
 #pragma unroll
-  for (int b = 0; b < MM; ++b) f[b] = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
-    double t = g[i];
+    for (int b = 0; b < kFused; ++b) {
+      cp[b] = Y + (b < cnt ? R.slot(b) : 0) * n;
+      c[b] = b < cnt ? cs[b] : 0.0;
+      f[b] = 0.0;
+    }
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
+      double yv[kFused];
+      double t = g[i];
 #pragma unroll
-    for (int b = 0; b < MM; ++b)
-      if (b < cnt) t += Yc.p[b][i] * c[b];
-    const double ai = (h0 ? h0[i] : 1.0) * t;
-    a_out[i] = ai;
+      for (int b = 0; b < kFused; ++b)
+        if (b < cnt) {
+          yv[b] = cp[b][i];
+          t += yv[b] * c[b];
+        }
+      const double ai = (h0 ? h0[i] : 1.0) * t;
+      a_out[i] = ai;
 #pragma unroll
-    for (int b = 0; b < MM; ++b)
-      if (b < cnt) f[b] += Yc.p[b][i] * ai;
+      for (int b = 0; b < kFused; ++b)
+        if (b < cnt) f[b] += yv[b] * ai;
+    }
+    block_sums<kFused>(f, cnt, lds, tot);
+    if (threadIdx.x < cnt) P[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = tot[threadIdx.x];
+  } else {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
+      double t = g[i];
+      for (int jb = 0; jb < cnt; jb += kJB) {
+        const int nc = cnt - jb < kJB ? cnt - jb : kJB;
+#pragma unroll
+        for (int u = 0; u < kJB; ++u)
+          if (u < nc) t += Y[R.slot(jb + u) * n + i] * cs[jb + u];
+      }
+      a_out[i] = (h0 ? h0[i] : 1.0) * t;
+    }
   }
-  block_sums<MM>(f, cnt, lds, tot);
-  if (threadIdx.x < cnt) P[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = tot[threadIdx.x];
+}
+
+// pass 2b (histories longer than kFused): partials of f_b = y_b . a
+__global__ __launch_bounds__(kLB) void k_lb_ya_t(int64_t n, const double* __restrict__ Y, Ring R,
+                                                 const double* __restrict__ a,
+                                                 double* __restrict__ P) {
+  __shared__ double lds[(kLB / 64) * kJB];
+  __shared__ double tot[kJB];
+  gemvt_partials(n, Y, R, a, P, 0, lds, tot);
 }
 
 // pass 3: e = R^-T (f + D c) (every workgroup); p = a - S e
-template <int MM>
-__global__ __launch_bounds__(kLB) void k_lb_p(int64_t n, int m, Cols Sc,
+__global__ __launch_bounds__(kLB) void k_lb_p(int64_t n, const double* __restrict__ S, Ring R,
                                               const double* __restrict__ a,
-                                              const double* __restrict__ SY, int start, int cnt,
+                                              const double* __restrict__ SY,
                                               const double* __restrict__ red,
                                               double* __restrict__ p) {
-  __shared__ double es[MM];
+  __shared__ double es[kMaxHistory];
+  const int cnt = R.cnt;
   if (threadIdx.x == 0) {
-    const double* c = red + MM;
-    const double* f = red + 2 * MM;
+    const double* c = red + kMaxHistory;
+    const double* f = red + 2 * kMaxHistory;
     for (int x = 0; x < cnt; ++x) {
-      double t = f[x] + rmat(SY, m, start, x, x) * c[x];
-      for (int y = 0; y < x; ++y) t -= rmat(SY, m, start, y, x) * es[y];
-      es[x] = t / rmat(SY, m, start, x, x);
+      double t = f[x] + rmat(SY, R, x, x) * c[x];
+      for (int y = 0; y < x; ++y) t -= rmat(SY, R, y, x) * es[y];
+      es[x] = t / rmat(SY, R, x, x);
     }
   }
   __syncthreads();
-  double e[MM];
-#pragma unroll
-  for (int b = 0; b < MM; ++b) e[b] = b < cnt ? es[b] : 0.0;
   int64_t lo, hi;
   rows_of(n, blockIdx.x, gridDim.x, &lo, &hi);
   for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
     double t = a[i];
+    for (int jb = 0; jb < cnt; jb += kJB) {
+      const int nc = cnt - jb < kJB ? cnt - jb : kJB;
 #pragma unroll
-    for (int b = 0; b < MM; ++b)
-      if (b < cnt) t -= Sc.p[b][i] * e[b];
+      for (int u = 0; u < kJB; ++u)
+        if (u < nc) t -= S[R.slot(jb + u) * n + i] * es[jb + u];
+    }
     p[i] = t;
   }
 }
@@ -257,20 +291,6 @@ __global__ void k_lb_scale(int64_t n, const double* __restrict__ g, const double
                            double* __restrict__ p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = (h0 ? h0[i] : 1.0) * g[i];
-}
-
-template <typename F>
-int with_mm(int m, F&& f) {
-  if (m <= 8) return f(std::integral_constant<int, 8>());
-  if (m <= 16) return f(std::integral_constant<int, 16>());
-  if (m <= 32) return f(std::integral_constant<int, 32>());
-  return f(std::integral_constant<int, 64>());
-}
-
-Cols columns(const double* base, int64_t n, int m, int start, int cnt) {
-  Cols c = {};
-  for (int b = 0; b < cnt; ++b) c.p[b] = base + (int64_t)((start + b) % m) * n;
-  return c;
 }
 
 int cu_count_lb() {
@@ -365,17 +385,11 @@ extern "C" int spx_lbfgs_update(spx_lbfgs_handle h, const double* s, const doubl
     cnt = h->m;
   }
   const int G = h->G;
-  const Cols Sc = columns(h->S, h->n, h->m, start, cnt);
-  const Cols Yc = columns(h->Y, h->n, h->m, start, cnt);
-  SPX_TRY(with_mm(cnt, [&](auto mmc) {
-    constexpr int MM = decltype(mmc)::value;
-    hipLaunchKernelGGL((k_lb_update<MM>), dim3(G), dim3(kLB), 0, st, h->n,
-                       h->S + (int64_t)slot * h->n, h->Y + (int64_t)slot * h->n, s, y, Sc, Yc, cnt,
-                       h->P);
-    hipLaunchKernelGGL((k_lb_update_finish<MM>), dim3(2 * MM), dim3(kLB), 0, st, h->m, h->P, G,
-                       slot, start, cnt, h->SY);
-    return SPX_OK;
-  }));
+  const Ring R{h->m, start, cnt};
+  hipLaunchKernelGGL(k_lb_put, dim3((unsigned)ceil_div(h->n, 256)), dim3(256), 0, st, h->n, s, y,
+                     h->S + (int64_t)slot * h->n, h->Y + (int64_t)slot * h->n);
+  hipLaunchKernelGGL(k_lb_update, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, s, y, R, h->P);
+  hipLaunchKernelGGL(k_lb_update_finish, dim3(2 * cnt), dim3(kLB), 0, st, h->P, G, R, slot, h->SY);
   SPX_CHECK_HIP(hipGetLastError());
   h->start = start;
   h->count = cnt;
@@ -396,19 +410,19 @@ extern "C" int spx_lbfgs_apply(spx_lbfgs_handle h, const double* g, const double
     return SPX_OK;
   }
   const int G = h->G;
-  const Cols Sc = columns(h->S, n, h->m, h->start, cnt);
-  const Cols Yc = columns(h->Y, n, h->m, h->start, cnt);
-  SPX_TRY(with_mm(cnt, [&](auto mmc) {
-    constexpr int MM = decltype(mmc)::value;
-    hipLaunchKernelGGL((k_lb_sg<MM>), dim3(G), dim3(kLB), 0, st, n, Sc, g, cnt, h->P);
-    hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
-    hipLaunchKernelGGL((k_lb_ya<MM>), dim3(G), dim3(kLB), 0, st, n, h->m, Yc, g, h0, h->SY,
-                       h->start, cnt, h->red, h->a, h->P);
-    hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red + 2 * MM);
-    hipLaunchKernelGGL((k_lb_p<MM>), dim3(G), dim3(kLB), 0, st, n, h->m, Sc, h->a, h->SY,
-                       h->start, cnt, h->red, p);
-    return SPX_OK;
-  }));
+  const Ring R{h->m, h->start, cnt};
+  hipLaunchKernelGGL(k_lb_sg, dim3(G), dim3(kLB), 0, st, n, h->S, R, g, h->P);
+  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
+  if (cnt <= kFused) {
+    hipLaunchKernelGGL((k_lb_ya<true>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY, h->red,
+                       h->a, h->P);
+  } else {
+    hipLaunchKernelGGL((k_lb_ya<false>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY, h->red,
+                       h->a, h->P);
+    hipLaunchKernelGGL(k_lb_ya_t, dim3(G), dim3(kLB), 0, st, n, h->Y, R, h->a, h->P);
+  }
+  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red + 2 * kMaxHistory);
+  hipLaunchKernelGGL(k_lb_p, dim3(G), dim3(kLB), 0, st, n, h->S, R, h->a, h->SY, h->red, p);
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }
