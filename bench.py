@@ -230,19 +230,28 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
             one.batch_tfqmr(bq, rtol=0.0, maxit=20, check_every=ce)
             ms, r = timed(lambda: one.batch_tfqmr(bq, rtol=0.0, maxit=400, check_every=ce), reps=3)
             row[f"tfqmr_{tag}_us_per_halfstep"] = round(1e3 * ms / max(1, r[1][0]), 2)
+        xq = torch.zeros_like(bq)
+        Aq.set_option(spx.OPT_GRAPH, 1)
+        Aq.cg_solve(bq, x=xq.zero_(), rtol=0.0, maxit=200, check_every=20)  # capture
+        ms, r = timed(lambda: Aq.cg_solve(bq, x=xq.zero_(), rtol=0.0, maxit=200, check_every=20),
+                      reps=3)
+        Aq.set_option(spx.OPT_GRAPH, 0)
+        row["cg_async_graph_us_per_iter"] = round(1e3 * ms / max(1, r.iters), 2)
         row["cg_async_speedup"] = round(row["cg_sync_us_per_iter"] / row["cg_async_us_per_iter"], 2)
+        row["cg_graph_speedup"] = round(row["cg_sync_us_per_iter"] / row["cg_async_graph_us_per_iter"], 2)
         row["tfqmr_async_speedup"] = round(row["tfqmr_sync_us_per_halfstep"]
                                            / row["tfqmr_async_us_per_halfstep"], 2)
         curve.append(row)
         log(f"async curve nnz={Aq.nnz}: cg {row['cg_sync_us_per_iter']} vs "
-            f"{row['cg_async_us_per_iter']} us/it, tfqmr {row['tfqmr_sync_us_per_halfstep']} vs "
+            f"{row['cg_async_us_per_iter']} (graph {row['cg_async_graph_us_per_iter']}) us/it, tfqmr {row['tfqmr_sync_us_per_halfstep']} vs "
             f"{row['tfqmr_async_us_per_halfstep']} us/half-step")
         one.destroy()
         Aq.destroy()
     out["sync_vs_async"] = {"points": curve,
                             "note": "host polls the device stop flag after every iteration (sync) "
-                                    "or every 20 (async); 200 CG iterations / 400 TFQMR half-steps "
-                                    "with rtol = 0, time per iteration"}
+                                    "or every 20 (async, also with each chunk replayed as one HIP "
+                                    "graph); 200 CG iterations / 400 TFQMR half-steps with rtol = 0, "
+                                    "time per iteration"}
 
     # ---- 64-system batch
     probs, bs = W.config4()

@@ -352,7 +352,15 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *       gamma = r.u, delta = w.u, beta = gamma_k / gamma_{k-1},
  *       alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}),
  *     two kernels and ONE reduction point per iteration; its iterates equal
- *     those of form 0 in exact arithmetic and differ by rounding. */
+ *     those of form 0 in exact arithmetic and differ by rounding.
+ *   SPX_OPT_GRAPH: 1 replays each full poll chunk of the textbook CG
+ *     (spx_cg_solve, spx_cg_solve_transpose and the fp32 inner solve of
+ *     spx_cg_solve_mixed) as one HIP graph, captured once on a private
+ *     stream and kept while the operator, vectors and launch shape stay the
+ *     same; the kernels then take the iteration number from the device.
+ *     Same arithmetic as 0 (bitwise equal results); it only saves launch
+ *     overhead, which matters for small systems.  Ignored while
+ *     SPX_OPT_PROFILE is on and for the single-reduction form.  Default 0. */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,
@@ -365,7 +373,8 @@ enum spx_option {
   SPX_OPT_VECTOR_BLOCKS = 9,
   SPX_OPT_PIPELINE = 10,
   SPX_OPT_ROWS_PER_BLOCK_F32 = 11,
-  SPX_OPT_CG_VARIANT = 12
+  SPX_OPT_CG_VARIANT = 12,
+  SPX_OPT_GRAPH = 13
 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);

@@ -74,6 +74,9 @@ extern "C" int spx_destroy(spx_handle h) {
     if (e) (void)hipEventDestroy(e);
   for (int64_t k = 0; k < h->prof_ev_n; ++k) (void)hipEventDestroy(h->prof_ev[k]);
   delete[] h->prof_ev;
+  for (auto& gc : h->graph)
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
   return SPX_OK;
@@ -128,6 +131,9 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
                          (long long)value);
       h->rows32_opt = (int)value;
       return SPX_OK;
+    case SPX_OPT_GRAPH:
+      h->graph_opt = value ? 1 : 0;
+      return SPX_OK;
     case SPX_OPT_CG_VARIANT:
       if (value != 0 && value != 1)
         return set_error(SPX_INVALID_ARG, "set_option: CG variant %lld not 0 or 1",
@@ -178,6 +184,9 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       return SPX_OK;
     case SPX_OPT_CG_VARIANT:
       *value = h->cg_variant;
+      return SPX_OK;
+    case SPX_OPT_GRAPH:
+      *value = h->graph_opt;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

@@ -155,6 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, VT* __restrict_
                                                       double* __restrict__ P2, int64_t k) {
   __shared__ double lds[kLds];
   if (st->done) return;
+  if (k <= 0) k = (int64_t)st->iters + 1;  // replayed launch: the iteration count is on the device
   const double pq = reduce_all(P1, G1, lds);
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -169,6 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, VT* __restrict_
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->pq = pq;
     st->alpha = alpha;
+    st->kcur = (int32_t)k;
   }
   const VT a = (VT)alpha;
   const int64_t nb = gridDim.x;
@@ -200,6 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, VT* __restrict
                                                        int64_t k) {
   __shared__ double lds[kLds];
   if (st->done) return;
+  if (k <= 0) k = st->kcur;  // written by this iteration's update kernel
   const double rz = reduce_all(P2, G2, lds);
   const double rr = reduce_all(P2 + G2, G2, lds);
   const bool conv = sqrt(rr) <= st->thresh;
@@ -529,7 +532,7 @@ size_t shape_lds(const SpmvShape& sh) {
 template <typename VT>
 int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
                        CgScalars* st, int64_t first, int64_t count, hipStream_t s,
-                       hipEvent_t* evs) {
+                       hipEvent_t* evs, bool device_k = false) {
   const unsigned G1 = (unsigned)fused_blocks(h);
   const unsigned G2 = (unsigned)vector_blocks(h);
   double* P1 = h->partials;
@@ -538,7 +541,7 @@ int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* 
   return with_shape(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     for (int64_t c = 0; c < count; ++c) {
-      const int64_t k = first + c;
+      const int64_t k = device_k ? 0 : first + c;
       hipEvent_t* e = evs ? evs + 6 * c : nullptr;
       if (e) (void)hipEventRecord(e[0], s);
       hipLaunchKernelGGL((k_cg_spmv<SH, VT>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr, A.col,
@@ -647,13 +650,65 @@ int run_until_done(spx_matrix* h, CgScalars* st, int64_t maxit, int32_t check_ev
   return SPX_OK;
 }
 
+// A graph of one full poll chunk (check_every iterations of K1, K2, K3 that
+// take the iteration number from the device), captured on a private stream
+// and kept while the operator, vectors and launch shape stay the same.
+template <typename VT>
+int chunk_graph(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
+                CgScalars* st, int32_t check_every, hipGraphExec_t* out) {
+  spx_matrix::GraphCache& gc = h->graph[sizeof(VT) == 8 ? 0 : 1];
+  const uintptr_t key[16] = {(uintptr_t)A.rowptr, (uintptr_t)A.col, (uintptr_t)A.val,
+                             (uintptr_t)x, (uintptr_t)r, (uintptr_t)p, (uintptr_t)q,
+                             (uintptr_t)dinv, (uintptr_t)st, (uintptr_t)h->partials,
+                             (uintptr_t)check_every, (uintptr_t)fused_blocks(h),
+                             (uintptr_t)vector_blocks(h),
+                             (uintptr_t)(A.sh.variant * 4096 + A.sh.rows * 8 + A.sh.nt * 2 + A.sh.vec),
+                             (uintptr_t)(A.sh.tile * 64 + A.sh.lanes), (uintptr_t)(A.sh.pipe * 2 + h->xcd_remap)};
+  if (gc.exec && std::equal(key, key + 16, gc.key)) {
+    *out = gc.exec;
+    return SPX_OK;
+  }
+  if (gc.exec) {
+    (void)hipGraphExecDestroy(gc.exec);
+    gc.exec = nullptr;
+  }
+  if (!h->cap_stream) SPX_CHECK_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  SPX_CHECK_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int st_enq = enqueue_iterations<VT>(h, A, x, r, p, q, dinv, st, 0, check_every,
+                                            h->cap_stream, nullptr, true);
+  hipGraph_t graph = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(h->cap_stream, &graph);
+  if (st_enq != SPX_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st_enq;
+  }
+  if (e_end != hipSuccess || !graph)
+    return set_error(SPX_HIP_ERROR, "cg graph capture failed: %s", hipGetErrorString(e_end));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e_inst != hipSuccess)
+    return set_error(SPX_HIP_ERROR, "cg graph instantiation failed: %s", hipGetErrorString(e_inst));
+  gc.exec = exec;
+  std::copy(key, key + 16, gc.key);
+  *out = exec;
+  return SPX_OK;
+}
+
 // The Hestenes-Stiefel iteration (K1, K2, K3) on operator A in precision VT.
 template <typename VT>
 int run_hs(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
            CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s, CgScalars* final) {
   const int kinds64[3] = {0, 1, 2}, kinds32[3] = {3, 4, 5};
+  hipGraphExec_t exec = nullptr;
+  if (h->graph_opt && !h->profile)
+    SPX_TRY(chunk_graph<VT>(h, A, x, r, p, q, dinv, st, check_every, &exec));
   return run_until_done(h, st, maxit, check_every, s, 3, sizeof(VT) == 8 ? kinds64 : kinds32, 1,
-                        [&](int64_t first, int64_t count, hipEvent_t* evs) {
+                        [&](int64_t first, int64_t count, hipEvent_t* evs) -> int {
+                          if (exec && !evs && count == check_every) {
+                            SPX_CHECK_HIP(hipGraphLaunch(exec, s));
+                            return SPX_OK;
+                          }
                           return enqueue_iterations<VT>(h, A, x, r, p, q, dinv, st, first, count,
                                                         s, evs);
                         },

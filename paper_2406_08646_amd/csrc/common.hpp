@@ -112,7 +112,10 @@ struct CgScalars {
   // TFQMR cycles: verify = 1 once a cycle ended on its residual bound and
   // the true residual is still to be checked; the current cycle started at
   // iteration j0 after m0 half-steps; restarts done so far.
-  int32_t verify, restarts, j0, m0, pad;
+  int32_t verify, restarts, j0, m0;
+  // iteration number of the running CG iteration, written by its update
+  // kernel when the launches take it from the device (graph replay)
+  int32_t kcur;
 };
 
 }  // namespace spx
@@ -157,6 +160,13 @@ struct spx_matrix {
   int64_t prof_cnt[6] = {0, 0, 0, 0, 0, 0};
   hipEvent_t* prof_ev = nullptr;
   int64_t prof_ev_n = 0;
+  // replay of one poll chunk of CG iterations as a HIP graph (fp64, fp32)
+  int graph_opt = 0;
+  hipStream_t cap_stream = nullptr;
+  struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    uintptr_t key[16] = {};
+  } graph[2];
 };
 
 namespace spx {

@@ -247,3 +247,39 @@ def test_full_size_pipeline_sampled(orc, N):
     rel = residual_norm(prob, xs, b) / np.linalg.norm(b)
     print(f"cg: {res.iters} iterations relres {res.relres:.3e} (independent {rel:.3e})", flush=True)
     assert res.status == 0 and res.relres <= 1e-10 * 1.001 and rel <= 1e-10 * 1.01
+
+
+def test_graph_replay_is_bitwise_the_eager_solve():
+    """Each full poll chunk replayed as one HIP graph: same kernels, same
+    arithmetic.  Several solves (each replays the graph many times) with eager
+    work and synchronisation between them, every one against the eager
+    result; then the transpose solve and the mixed solve's fp32 inner graph,
+    and a change of vectors that forces a new capture."""
+    spx = require_gpu()
+    N = 14
+    prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(8).standard_normal(N**3)))
+    A = assemble(spx, prob)
+    b = dev(np.random.default_rng(9).uniform(-1, 1, prob.n))
+    eager = A.cg_solve(b, rtol=1e-10, check_every=7)
+    eager_t = A.cg_solve_transpose(b, rtol=1e-10, check_every=7)
+    eager_m = A.cg_solve_mixed(b, rtol_outer=1e-10, rtol_inner=1e-4, check_every=7)
+    A.set_option(spx.OPT_GRAPH, 1)
+    assert A.get_option(spx.OPT_GRAPH) == 1
+    for rep in range(4):
+        y = host(A.matmult(b))  # eager work between replays
+        g = A.cg_solve(b, rtol=1e-10, check_every=7)
+        assert g.iters == eager.iters and g.status == eager.status
+        assert np.array_equal(bits(host(g.x)), bits(host(eager.x))), rep
+        assert np.all(np.isfinite(y))
+    gt = A.cg_solve_transpose(b, rtol=1e-10, check_every=7)
+    assert gt.iters == eager_t.iters and np.array_equal(bits(host(gt.x)), bits(host(eager_t.x)))
+    for rep in range(2):
+        gm = A.cg_solve_mixed(b, rtol_outer=1e-10, rtol_inner=1e-4, check_every=7)
+        assert (gm.outer, gm.inner) == (eager_m.outer, eager_m.inner)
+        assert np.array_equal(bits(host(gm.x)), bits(host(eager_m.x))), rep
+    b2 = dev(np.random.default_rng(10).uniform(-1, 1, prob.n))
+    A.set_option(spx.OPT_GRAPH, 0)
+    e2 = A.cg_solve(b2, rtol=1e-10, check_every=5)
+    A.set_option(spx.OPT_GRAPH, 1)
+    g2 = A.cg_solve(b2, rtol=1e-10, check_every=5)
+    assert g2.iters == e2.iters and np.array_equal(bits(host(g2.x)), bits(host(e2.x)))
