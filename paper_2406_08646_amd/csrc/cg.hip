@@ -848,14 +848,19 @@ int cu_count() {
 // Workgroups of the solver's SpMV-shaped kernels (each walks a contiguous
 // share of the rows) and of its vector kernels; every workgroup of the
 // next kernel re-adds this many partials, so the counts stay moderate.
+// Both shrink with the system: every workgroup of the next kernel re-adds
+// all partials, so a small system with a full-chip grid would spend its
+// iteration reading thousands of partials that hold zeros.
 int fused_blocks(const spx_matrix* h) {
   if (h && h->fused_opt > 0) return h->fused_opt;
-  return cu_count() * 8;
+  const int64_t tiles = h ? ceil_div(h->n, 64) : 1;  // at least one 64-row tile each
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cu_count() * 8, tiles));
 }
 
 int vector_blocks(const spx_matrix* h) {
   if (h && h->vec_blocks_opt > 0) return h->vec_blocks_opt;
-  return cu_count() * 4;
+  const int64_t chunks = h ? ceil_div(h->n, 1024) : 1;  // at least 4 rows per thread
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cu_count() * 4, chunks));
 }
 
 }  // namespace spx
