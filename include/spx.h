@@ -360,7 +360,14 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *     same; the kernels then take the iteration number from the device.
  *     Same arithmetic as 0 (bitwise equal results); it only saves launch
  *     overhead, which matters for small systems.  Ignored while
- *     SPX_OPT_PROFILE is on and for the single-reduction form.  Default 0. */
+ *     SPX_OPT_PROFILE is on and for the single-reduction form.  Default 0.
+ *   SPX_OPT_SMALL_SOLVE: the fp64 textbook CG (spx_cg_solve and its
+ *     transpose) of a small system as ONE workgroup that runs every
+ *     iteration, so no kernel is launched per iteration.  0: never.
+ *     1 (default): for systems of at most 16384 rows when no launch-shape
+ *     option, profiling, graph replay or the single-reduction form is set.
+ *     2: whenever a 256-row tile fits in 64 KB of LDS.  Same recurrences,
+ *     tests and statuses; the dots are summed in another order. */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,
@@ -374,7 +381,8 @@ enum spx_option {
   SPX_OPT_PIPELINE = 10,
   SPX_OPT_ROWS_PER_BLOCK_F32 = 11,
   SPX_OPT_CG_VARIANT = 12,
-  SPX_OPT_GRAPH = 13
+  SPX_OPT_GRAPH = 13,
+  SPX_OPT_SMALL_SOLVE = 14
 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);

@@ -134,6 +134,12 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
     case SPX_OPT_GRAPH:
       h->graph_opt = value ? 1 : 0;
       return SPX_OK;
+    case SPX_OPT_SMALL_SOLVE:
+      if (value < 0 || value > 2)
+        return set_error(SPX_INVALID_ARG, "set_option: small-solve mode %lld not in 0..2",
+                         (long long)value);
+      h->small_opt = (int)value;
+      return SPX_OK;
     case SPX_OPT_CG_VARIANT:
       if (value != 0 && value != 1)
         return set_error(SPX_INVALID_ARG, "set_option: CG variant %lld not 0 or 1",
@@ -187,6 +193,9 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       return SPX_OK;
     case SPX_OPT_GRAPH:
       *value = h->graph_opt;
+      return SPX_OK;
+    case SPX_OPT_SMALL_SOLVE:
+      *value = h->small_opt;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

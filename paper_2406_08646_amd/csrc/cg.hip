@@ -387,6 +387,133 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
   if (threadIdx.x == 0) P1[blockIdx.x] = delta;
 }
 
+// ------------------------------------------------ one-workgroup solve
+// Small systems: one workgroup of kOne threads runs the whole Jacobi-CG, so
+// no kernel is launched per iteration (the working set stays in L2).  The
+// recurrences, the order of the tests and the statuses are those of the
+// K1..K3 path; the SpMV is the same in-order stream walk over tiles of
+// kOneRows rows, the dots are workgroup sums.
+constexpr int kOne = 1024;
+constexpr int kOneRows = 256;
+
+// Workgroup sum returned to every thread (every thread adds the per-wave
+// sums in the same order).
+__device__ __forceinline__ double one_allsum(double v, double* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kOne / 64; ++i) r += lds[i];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kOne) void k_cg_one(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ p, double* __restrict__ q,
+                                                 const double* __restrict__ dinv, CgScalars* st,
+                                                 double rtol) {
+  extern __shared__ __align__(16) char smem[];
+  double* prod = reinterpret_cast<double*>(smem);
+  __shared__ double lds[kOne / 64];
+  const int tid = threadIdx.x;
+  // r = b - A x; p = D^-1 r
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int64_t r0 = 0; r0 < n; r0 += kOneRows) {
+    const int64_t r1 = r0 + kOneRows < n ? r0 + kOneRows : n;
+    const double ax = stream_rows<kOne, 8, double, double, double, false>(rowptr, col, val, x, r0,
+                                                                          r1, prod);
+    if (tid < r1 - r0) {
+      const int64_t row = r0 + tid;
+      const double bi = b[row];
+      const double ri = bi - ax;
+      const double zi = dinv[row] * ri;
+      r[row] = ri;
+      p[row] = zi;
+      rz += ri * zi;
+      rr += ri * ri;
+      bb += bi * bi;
+    }
+  }
+  rz = one_allsum(rz, lds);
+  rr = one_allsum(rr, lds);
+  bb = one_allsum(bb, lds);
+  const double bnorm = sqrt(bb);
+  const double thresh = rtol * bnorm;
+  const int32_t maxit = st->maxit;
+  int32_t status = st->status, iters = 0;
+  double rho = rz, pq = 0.0;
+  bool done = true;
+  if (status != SPX_OK) {
+  } else if (sqrt(rr) <= thresh) {
+  } else if (maxit <= 0) {
+    status = SPX_NOT_CONVERGED;
+  } else {
+    done = false;
+  }
+  for (int32_t k = 1; !done; ++k) {
+    // q = A p; p.q
+    double pqs = 0.0;
+    for (int64_t r0 = 0; r0 < n; r0 += kOneRows) {
+      const int64_t r1 = r0 + kOneRows < n ? r0 + kOneRows : n;
+      const double s = stream_rows<kOne, 8, double, double, double, false>(rowptr, col, val, p, r0,
+                                                                           r1, prod);
+      if (tid < r1 - r0) {
+        q[r0 + tid] = s;
+        pqs += p[r0 + tid] * s;
+      }
+    }
+    pq = one_allsum(pqs, lds);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      status = SPX_BREAKDOWN;
+      iters = k - 1;
+      break;
+    }
+    const double alpha = rho / pq;
+    double rzs = 0.0, rrs = 0.0;
+    for (int64_t i = tid; i < n; i += kOne) {
+      const double xi = x[i] + alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      const double zi = dinv[i] * ri;
+      x[i] = xi;
+      r[i] = ri;
+      rzs += ri * zi;
+      rrs += ri * ri;
+    }
+    rz = one_allsum(rzs, lds);
+    rr = one_allsum(rrs, lds);
+    iters = k;
+    if (sqrt(rr) <= thresh) {
+      status = SPX_OK;
+      break;
+    }
+    if (k >= maxit) {
+      status = SPX_NOT_CONVERGED;
+      break;
+    }
+    const double beta = rz / rho;
+    rho = rz;
+    for (int64_t i = tid; i < n; i += kOne) p[i] = dinv[i] * r[i] + beta * p[i];
+    __syncthreads();  // p is gathered by every thread in the next product
+  }
+  if (tid == 0) {
+    st->rho[0] = rho;
+    st->pq = pq;
+    st->rr = rr;
+    st->bb = bb;
+    st->bnorm = bnorm;
+    st->thresh = thresh;
+    st->iters = iters;
+    st->status = status;
+    st->done = 1;
+  }
+}
+
 // ---------------------------------------------------- mixed precision
 
 __global__ __launch_bounds__(kBlock) void k_norm2(int64_t n, const double* __restrict__ b,
@@ -763,6 +890,24 @@ int enqueue_resnorm(spx_matrix* h, const Op<double>& A, const double* b, const d
   return SPX_OK;
 }
 
+int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const double* x,
+                 CgScalars* st, hipStream_t s, int64_t* iters_out, double* relres_out);
+
+// The one-workgroup solve: forced by SPX_OPT_SMALL_SOLVE = 2, chosen by the
+// default 1 for systems of at most kOneAutoRows rows when no launch-shape
+// option, profiling, graph replay or the single-reduction form asks for the
+// multi-workgroup kernels; either way only if a 256-row tile fits in LDS.
+constexpr int64_t kOneAutoRows = 16384;
+bool use_one_workgroup(const spx_matrix* h, const Csr& M) {
+  if (h->small_opt == 0 || h->cg_variant != 0) return false;
+  if ((M.tile_nnz[3] + 8) * (int64_t)sizeof(double) > 64 * 1024) return false;
+  if (h->small_opt == 2) return true;
+  const bool shape_default = h->lanes_opt == 0 && h->variant_opt == 0 && h->rows_opt == 0 &&
+                             h->rows32_opt == 0 && h->fused_opt == 0 && h->vec_blocks_opt == 0 &&
+                             h->pipe_opt == 0 && h->vec_opt == 0 && h->nt_opt == 1;
+  return shape_default && !h->profile && !h->graph_opt && M.n <= kOneAutoRows;
+}
+
 int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, double rtol,
                   int64_t maxit, int32_t check_every, hipStream_t s, int64_t* iters_out,
                   double* relres_out) {
@@ -781,6 +926,14 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
   hipLaunchKernelGGL(k_scal_reset, dim3(1), dim3(64), 0, s, st, (int32_t)maxit);
   hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, h->dinv,
                      (float*)nullptr, st);
+  CgScalars fin;
+  if (use_one_workgroup(h, M)) {
+    const size_t lds = (size_t)(M.tile_nnz[3] + 8) * sizeof(double);
+    hipLaunchKernelGGL(k_cg_one, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b, x, r,
+                       p, q, h->dinv, st, rtol);
+    SPX_CHECK_HIP(hipGetLastError());
+    return finish_solve(h, A, b, x, st, s, iters_out, relres_out);
+  }
   SPX_TRY(with_shape(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_cg_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
@@ -791,7 +944,6 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
   hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G,
                      rtol);
   SPX_CHECK_HIP(hipGetLastError());
-  CgScalars fin;
   if (h->cg_variant == 1) {
     // k_cg_init left u = D^-1 r in p; move it to its own vector and start
     // w = A u, p = u, s = w, delta_0
@@ -809,6 +961,12 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
   } else {
     SPX_TRY(run_hs<double>(h, A, x, r, p, q, h->dinv, st, maxit, check_every, s, &fin));
   }
+  return finish_solve(h, A, b, x, st, s, iters_out, relres_out);
+}
+
+// True residual of the returned x, the outputs and the status of a solve.
+int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const double* x,
+                 CgScalars* st, hipStream_t s, int64_t* iters_out, double* relres_out) {
   SPX_TRY(enqueue_resnorm(h, A, b, x, st, s));
   SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
   SPX_CHECK_HIP(hipStreamSynchronize(s));

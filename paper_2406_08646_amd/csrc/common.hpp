@@ -162,6 +162,7 @@ struct spx_matrix {
   int64_t prof_ev_n = 0;
   // replay of one poll chunk of CG iterations as a HIP graph (fp64, fp32)
   int graph_opt = 0;
+  int small_opt = 1;  // one-workgroup solve: 0 never, 1 small systems, 2 whenever it fits
   hipStream_t cap_stream = nullptr;
   struct GraphCache {
     hipGraphExec_t exec = nullptr;

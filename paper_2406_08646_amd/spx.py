@@ -49,6 +49,7 @@ OPT_PIPELINE = 10
 OPT_ROWS_PER_BLOCK_F32 = 11
 OPT_CG_VARIANT = 12
 OPT_GRAPH = 13
+OPT_SMALL_SOLVE = 14
 PROFILE_KINDS = ("spmv_dot_f64", "update_f64", "pupdate_f64", "spmv_dot_f32", "update_f32",
                  "pupdate_f32")
 

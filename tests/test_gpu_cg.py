@@ -110,6 +110,7 @@ def test_cg_check_every_does_not_change_the_result(orc):
     spx = require_gpu()
     prob, _, b = W.config1()
     A = assemble(spx, prob)
+    A.set_option(spx.OPT_SMALL_SOLVE, 0)  # the multi-workgroup path polls
     outs = [A.cg_solve(dev(b), rtol=1e-8, check_every=k) for k in (1, 7, 20, 1000)]
     for o in outs[1:]:
         assert o.iters == outs[0].iters
@@ -259,6 +260,7 @@ def test_graph_replay_is_bitwise_the_eager_solve():
     N = 14
     prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(8).standard_normal(N**3)))
     A = assemble(spx, prob)
+    A.set_option(spx.OPT_SMALL_SOLVE, 0)  # compare the graph with the same multi-workgroup kernels
     b = dev(np.random.default_rng(9).uniform(-1, 1, prob.n))
     eager = A.cg_solve(b, rtol=1e-10, check_every=7)
     eager_t = A.cg_solve_transpose(b, rtol=1e-10, check_every=7)
@@ -283,3 +285,64 @@ def test_graph_replay_is_bitwise_the_eager_solve():
     A.set_option(spx.OPT_GRAPH, 1)
     g2 = A.cg_solve(b2, rtol=1e-10, check_every=5)
     assert g2.iters == e2.iters and np.array_equal(bits(host(g2.x)), bits(host(e2.x)))
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_one_workgroup_and_multi_workgroup_solves(orc, mode):
+    """SPX_OPT_SMALL_SOLVE 2 (the whole CG in one workgroup) and 0 (three
+    kernels per iteration) each against the oracle, dense LU, the eigenmode
+    and the statuses."""
+    spx = require_gpu()
+    prob, _, b = W.config1()
+    A = assemble(spx, prob)
+    A.set_option(spx.OPT_SMALL_SOLVE, mode)
+    assert A.get_option(spx.OPT_SMALL_SOLVE) == mode
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    ores = orc.pcg(ref, b, 1e-8)
+    res = A.cg_solve(dev(b), rtol=1e-8)
+    c = math.cos(math.pi / 63)
+    check_against_oracle(orc, ref, res, ores, b, 1e-8, min(1.0, (8 - 4 * c - 4 * c * c) / 3))
+    rt = A.cg_solve_transpose(dev(b), rtol=1e-8)
+    assert rt.iters == res.iters and np.array_equal(bits(host(rt.x)), bits(host(res.x)))
+    for N, dim in ((8, 2), (4, 3)):
+        rng = np.random.default_rng(50 + N)
+        p = W.q1_poisson(N, dim, kappa=np.exp(rng.standard_normal(N**dim)))
+        M = assemble(spx, p)
+        M.set_option(spx.OPT_SMALL_SOLVE, mode)
+        R = orc.assemble(p.n, p.i, p.j, p.v)
+        D = np.zeros((p.n, p.n))
+        D[np.repeat(np.arange(p.n), np.diff(R.rowptr)), R.col] = R.val
+        bb = rng.uniform(-1, 1, p.n)
+        xs = np.linalg.solve(D, bb)
+        r = M.cg_solve(dev(bb), rtol=1e-14, maxit=10000)
+        assert r.status == 0 and np.linalg.norm(host(r.x) - xs) <= 1e-10 * np.linalg.norm(xs)
+    N = 10
+    p = W.q1_poisson(N, 2)
+    E = assemble(spx, p)
+    E.set_option(spx.OPT_SMALL_SOLVE, mode)
+    Mg = N + 1
+    node = np.arange(p.n)
+    v = np.sin(2 * math.pi * (node % Mg) / N) * np.sin(3 * math.pi * (node // Mg) / N)
+    r = E.cg_solve(dev(v), rtol=1e-12, maxit=50)
+    assert r.status == 0 and r.iters == 1
+    Z = spx.coo_preallocate(2, dev(np.array([0, 1, 1], np.int32)), dev(np.array([1, 0, 1], np.int32)))
+    Z.set_values_coo(dev(np.array([1.0, 1.0, 2.0])))
+    Z.set_option(spx.OPT_SMALL_SOLVE, mode)
+    assert Z.cg_solve(dev(np.ones(2)), rtol=1e-8, maxit=10).status == spx.ZERO_DIAGONAL
+    B = spx.coo_preallocate(2, dev(np.array([0, 1], np.int32)), dev(np.array([0, 1], np.int32)))
+    B.set_values_coo(dev(np.array([1.0, -1.0])))
+    B.set_option(spx.OPT_SMALL_SOLVE, mode)
+    rb = B.cg_solve(dev(np.array([0.0, 1.0])), rtol=1e-8, maxit=10)
+    assert rb.status == spx.BREAKDOWN and rb.iters == 0
+    C = assemble(spx, W.q1_poisson(20, 2))
+    C.set_option(spx.OPT_SMALL_SOLVE, mode)
+    bc = np.random.default_rng(0).uniform(-1, 1, C.n)
+    r = C.cg_solve(dev(bc), rtol=1e-12, maxit=3)
+    assert r.status == spx.NOT_CONVERGED and r.iters == 3 and r.relres < 1.0
+    r = C.cg_solve(dev(bc), rtol=1e-12, maxit=0)
+    assert r.status == spx.NOT_CONVERGED and r.iters == 0
+    r = C.cg_solve(dev(np.zeros(C.n)), rtol=1e-8)
+    assert r.status == 0 and r.iters == 0 and np.all(host(r.x) == 0)
+    x0 = np.random.default_rng(1).uniform(-1, 1, C.n)
+    r = C.cg_solve(dev(bc), x=dev(x0), rtol=1e-10)
+    assert r.status == 0 and r.relres <= 1e-10 * 1.001
