@@ -392,9 +392,9 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
 // no kernel is launched per iteration (the working set stays in L2).  The
 // recurrences, the order of the tests and the statuses are those of the
 // K1..K3 path; the SpMV is the same in-order stream walk over tiles of
-// kOneRows rows, the dots are workgroup sums.
+// ROWS rows (as many as LDS holds: a lone workgroup may use all of a CU's),
+// the dots are workgroup sums.
 constexpr int kOne = 1024;
-constexpr int kOneRows = 256;
 
 // Workgroup sum returned to every thread (every thread adds the per-wave
 // sums in the same order).
@@ -410,6 +410,7 @@ __device__ __forceinline__ double one_allsum(double v, double* lds) {
   return r;
 }
 
+template <int ROWS>
 __global__ __launch_bounds__(kOne) void k_cg_one(int64_t n, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ col,
                                                  const double* __restrict__ val,
@@ -424,8 +425,8 @@ __global__ __launch_bounds__(kOne) void k_cg_one(int64_t n, const int32_t* __res
   const int tid = threadIdx.x;
   // r = b - A x; p = D^-1 r
   double rz = 0.0, rr = 0.0, bb = 0.0;
-  for (int64_t r0 = 0; r0 < n; r0 += kOneRows) {
-    const int64_t r1 = r0 + kOneRows < n ? r0 + kOneRows : n;
+  for (int64_t r0 = 0; r0 < n; r0 += ROWS) {
+    const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
     const double ax = stream_rows<kOne, 8, double, double, double, false>(rowptr, col, val, x, r0,
                                                                           r1, prod);
     if (tid < r1 - r0) {
@@ -459,8 +460,8 @@ __global__ __launch_bounds__(kOne) void k_cg_one(int64_t n, const int32_t* __res
   for (int32_t k = 1; !done; ++k) {
     // q = A p; p.q
     double pqs = 0.0;
-    for (int64_t r0 = 0; r0 < n; r0 += kOneRows) {
-      const int64_t r1 = r0 + kOneRows < n ? r0 + kOneRows : n;
+    for (int64_t r0 = 0; r0 < n; r0 += ROWS) {
+      const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
       const double s = stream_rows<kOne, 8, double, double, double, false>(rowptr, col, val, p, r0,
                                                                            r1, prod);
       if (tid < r1 - r0) {
@@ -896,11 +897,12 @@ int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const doub
 // The one-workgroup solve: forced by SPX_OPT_SMALL_SOLVE = 2, chosen by the
 // default 1 for systems of at most kOneAutoRows rows when no launch-shape
 // option, profiling, graph replay or the single-reduction form asks for the
-// multi-workgroup kernels; either way only if a 256-row tile fits in LDS.
+// multi-workgroup kernels; either way only if a 256-row tile fits in 64 KB.
 constexpr int64_t kOneAutoRows = 16384;
+constexpr int64_t kOneLds = 150 * 1024;  // dynamic LDS of the lone workgroup
 bool use_one_workgroup(const spx_matrix* h, const Csr& M) {
   if (h->small_opt == 0 || h->cg_variant != 0) return false;
-  if ((M.tile_nnz[3] + 8) * (int64_t)sizeof(double) > 64 * 1024) return false;
+  if ((M.tile_nnz[3] + 8) * (int64_t)sizeof(double) > 64 * 1024) return false;  // 256-row tiles fit
   if (h->small_opt == 2) return true;
   const bool shape_default = h->lanes_opt == 0 && h->variant_opt == 0 && h->rows_opt == 0 &&
                              h->rows32_opt == 0 && h->fused_opt == 0 && h->vec_blocks_opt == 0 &&
@@ -928,9 +930,31 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
                      (float*)nullptr, st);
   CgScalars fin;
   if (use_one_workgroup(h, M)) {
-    const size_t lds = (size_t)(M.tile_nnz[3] + 8) * sizeof(double);
-    hipLaunchKernelGGL(k_cg_one, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b, x, r,
-                       p, q, h->dinv, st, rtol);
+    // the largest tile whose products fit (4 and 2 tiles of 256 rows bound
+    // the entries of 1024 and 512 consecutive rows)
+    const int64_t t256 = M.tile_nnz[3];
+    // a tile above 64 KB of LDS needs the kernel's limit raised first
+    auto allow = [&](const void* fn, int64_t tiles) {
+      const int64_t bytes = (tiles * t256 + 8) * (int64_t)sizeof(double);
+      if (bytes > kOneLds) return false;
+      return bytes <= 64 * 1024 ||
+             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+                 hipSuccess;
+    };
+    const int rows = allow(reinterpret_cast<const void*>(&k_cg_one<1024>), 4)  ? 1024
+                     : allow(reinterpret_cast<const void*>(&k_cg_one<512>), 2) ? 512
+                                                                                : 256;
+    (void)hipGetLastError();  // a refused attribute leaves no error behind
+    const size_t lds = (size_t)((rows / 256) * t256 + 8) * sizeof(double);
+    if (rows == 1024)
+      hipLaunchKernelGGL(k_cg_one<1024>, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b,
+                         x, r, p, q, h->dinv, st, rtol);
+    else if (rows == 512)
+      hipLaunchKernelGGL(k_cg_one<512>, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b,
+                         x, r, p, q, h->dinv, st, rtol);
+    else
+      hipLaunchKernelGGL(k_cg_one<256>, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b,
+                         x, r, p, q, h->dinv, st, rtol);
     SPX_CHECK_HIP(hipGetLastError());
     return finish_solve(h, A, b, x, st, s, iters_out, relres_out);
   }
