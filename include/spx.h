@@ -364,7 +364,7 @@ int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
  *   SPX_OPT_SMALL_SOLVE: the fp64 textbook CG (spx_cg_solve and its
  *     transpose) of a small system as ONE workgroup that runs every
  *     iteration, so no kernel is launched per iteration.  0: never.
- *     1 (default): for systems of at most 16384 rows when no launch-shape
+ *     1 (default): for systems of at most 2048 rows when no launch-shape
  *     option, profiling, graph replay or the single-reduction form is set.
  *     2: whenever a 256-row tile fits in 64 KB of LDS.  Same recurrences,
  *     tests and statuses; the dots are summed in another order. */

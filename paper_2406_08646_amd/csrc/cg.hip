@@ -898,7 +898,7 @@ int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const doub
 // default 1 for systems of at most kOneAutoRows rows when no launch-shape
 // option, profiling, graph replay or the single-reduction form asks for the
 // multi-workgroup kernels; either way only if a 256-row tile fits in 64 KB.
-constexpr int64_t kOneAutoRows = 16384;
+constexpr int64_t kOneAutoRows = 2048;  // measured crossover with the launch-per-iteration path
 constexpr int64_t kOneLds = 150 * 1024;  // dynamic LDS of the lone workgroup
 bool use_one_workgroup(const spx_matrix* h, const Csr& M) {
   if (h->small_opt == 0 || h->cg_variant != 0) return false;
