@@ -129,6 +129,34 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
             best = ms if best is None else min(best, ms)
         return best, r
 
+    # ---- what this device sustains: the library's copy and read references over
+    # 2 GiB (HBM) and a copy over 2 x 96 MiB (resident in the 256 MB last-level cache)
+    def ev_ms(fn, reps=20):
+        for _ in range(3):
+            fn()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for s_, e_ in evs:
+            s_.record()
+            fn()
+            e_.record()
+        torch.cuda.synchronize()
+        return statistics.median(s_.elapsed_time(e_) for s_, e_ in evs)
+    big = torch.ones(2**28, dtype=torch.float64, device=dev)
+    big2 = torch.empty_like(big)
+    parts = torch.empty(2048, dtype=torch.float64, device=dev)
+    copy_ms = ev_ms(lambda: spx.stream_copy(big, big2))
+    read_ms = ev_ms(lambda: spx.stream_sum(big, parts))
+    del big, big2
+    small = torch.ones(12 * 2**20, dtype=torch.float64, device=dev)
+    small2 = torch.empty_like(small)
+    mall_ms = ev_ms(lambda: spx.stream_copy(small, small2), reps=50)
+    del small, small2
+    out["ceilings"] = {"copy_hbm_gbs": round(2 * 8 * 2**28 / (copy_ms * 1e-3) / 1e9, 1),
+                       "read_hbm_gbs": round(8 * 2**28 / (read_ms * 1e-3) / 1e9, 1),
+                       "copy_llc_resident_gbs": round(2 * 8 * 12 * 2**20 / (mall_ms * 1e-3) / 1e9, 1)}
+    log(f"ceilings: {out['ceilings']}")
+
     # ---- multi-RHS SpMM on the full 3-D matrix
     A = spx.coo_preallocate(prob.n, d(prob.i), d(prob.j))
     A.set_values_coo(d(prob.v))
@@ -211,6 +239,61 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
         f"{forms['single_reduction']['ms_per_iter']} ms/it")
     A.destroy()
     del X, Y
+
+    # ---- C1 (2-D Q1, 63^2 elements): CG latency per iteration, grid path and one workgroup
+    p1, _, b1 = W.config1()
+    A1 = spx.coo_preallocate(p1.n, d(p1.i), d(p1.j))
+    A1.set_values_coo(d(p1.v))
+    b1d = d(b1)
+    c1 = {"n": p1.n, "nnz": A1.nnz}
+    for mode, tag in ((0, "grid"), (2, "one_workgroup")):
+        A1.set_option(spx.OPT_SMALL_SOLVE, mode)
+        A1.cg_solve(b1d, rtol=1e-8)
+        ms, r = timed(lambda: A1.cg_solve(b1d, rtol=1e-8), reps=3)
+        c1[tag] = {"ms": round(ms, 3), "iters": r.iters, "relres": r.relres,
+                   "us_per_iter": round(1e3 * ms / max(1, r.iters), 2)}
+    out["c1_cg"] = c1
+    log(f"C1 CG: {c1}")
+    A1.destroy()
+
+    # ---- one GPU's share of an 8-way row-slab partition of the 3-D matrix: rows of a
+    # 128 x 128 x 16 slab; the diagonal block (columns in the slab) and the off-diagonal
+    # block (ghost columns of the two neighbouring planes, renumbered 0..2*128^2-1)
+    M = prob.grid + 1
+    plane = M * M
+    z0 = 3 * 16
+    lo_r, hi_r = z0 * plane, (z0 + 16) * plane
+    keep = (prob.i >= lo_r) & (prob.i < hi_r) & (prob.j >= 0)
+    ii, jj, vv_ = prob.i[keep] - lo_r, prob.j[keep], prob.v[keep]
+    inside = (jj >= lo_r) & (jj < hi_r)
+    gcol = np.where(jj < lo_r, jj - (lo_r - plane), jj - hi_r + plane)
+    Dg = spx.coo_preallocate(16 * plane, d(ii[inside].astype(np.int32)),
+                             d((jj[inside] - lo_r).astype(np.int32)))
+    Dg.set_values_coo(d(vv_[inside]))
+    ng = 16 * plane
+    # off-diagonal block as a square operator on [ghosts | local rows]: rows ii, columns
+    # the ghost indices (the first 2*plane unknowns)
+    Og = spx.coo_preallocate(max(ng, 2 * plane), d(ii[~inside].astype(np.int32)),
+                             d(gcol[~inside].astype(np.int32)))
+    Og.set_values_coo(d(vv_[~inside]))
+    xs_ = torch.ones(ng, dtype=torch.float64, device=dev)
+    ys_ = torch.empty_like(xs_)
+    xg = torch.ones(max(ng, 2 * plane), dtype=torch.float64, device=dev)
+    yg = torch.empty_like(xg)
+    dms = ev_ms(lambda: Dg.matmult(xs_, ys_))
+    oms = ev_ms(lambda: Og.matmult(xg, yg))
+    dbytes = Dg.nnz * 12 + (ng + 1) * 4 + 16 * ng
+    out["one_gpu_share"] = {"rows": ng, "diag_nnz": Dg.nnz, "offdiag_nnz": Og.nnz,
+                            "ghosts": 2 * plane, "diag_ms": round(dms, 4),
+                            "diag_gbs": round(dbytes / (dms * 1e-3) / 1e9, 1),
+                            "offdiag_ms": round(oms, 4),
+                            "halo_bytes_per_neighbour": plane * 8,
+                            "note": "the off-diagonal block runs as a CSR product over all local "
+                                    "rows, most of them empty; the halo exchange it waits for "
+                                    "is not built (one GPU)"}
+    log(f"one-GPU share: {out['one_gpu_share']}")
+    Dg.destroy()
+    Og.destroy()
 
     # ---- host poll after every iteration ("synchronous") vs every 20 ("asynchronous"),
     # time per iteration against the number of nonzeros, CG and TFQMR

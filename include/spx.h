@@ -21,6 +21,7 @@
 #ifndef SPX_H
 #define SPX_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -116,6 +117,15 @@ int spx_matmult_transpose(spx_handle h, const double* x, double* y, void* stream
  * Y[r*ldy + s], s < nrhs (ldx, ldy >= nrhs).  Asynchronous. */
 int spx_spmm(spx_handle h, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
              void* stream);
+
+/* Bandwidth references for reporting the kernels against what this device
+ * sustains (beside the nominal peak): y = x, and partial sums of x.  The
+ * whole grid (2048 workgroups) sweeps the array in lockstep with one
+ * 16-byte non-temporal access per lane.  x, y: device float64[n], 16-byte
+ * aligned; partials: device float64[2048] (workgroup b's sum in
+ * partials[b]).  Asynchronous. */
+int spx_stream_copy(const double* x, double* y, int64_t n, void* stream);
+int spx_stream_sum(const double* x, int64_t n, double* partials, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Jacobi-preconditioned CG — paper Sec. 6 (CG / CGAsync): scalars stay in
@@ -316,6 +326,18 @@ int spx_get_csr(spx_handle h, int32_t transpose, int32_t* rowptr, int32_t* col, 
 /* Copies the helper maps into caller DEVICE buffers jmap[nnz+1],
  * perm[nvalid] (either may be NULL).  Asynchronous. */
 int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
+
+/* Device-memory hook: every device allocation the library makes (patterns,
+ * values, maps, transposes, solver and batch workspaces) calls
+ * alloc(bytes, ctx), which returns device memory of at least `bytes` bytes
+ * (any alignment of 256 bytes or more) or NULL on failure; the block is later
+ * returned with free(ptr, ctx) of the hook that made it, so the hook may be
+ * changed at any time.  Both NULL restores hipMalloc/hipFree (the default).
+ * Process-wide.  Lets a caller route the library's memory through its own
+ * pool (the Python layer offers PyTorch's caching allocator). */
+typedef void* (*spx_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*spx_free_fn)(void* ptr, void* ctx);
+int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
 
 /* Tuning knobs (per handle; defaults chosen from the pattern).
  *   SPX_OPT_SPMV_LANES: lanes per row of the "vector" row walk (0 = auto,

@@ -2,6 +2,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 #include "common.hpp"
 
@@ -21,9 +23,38 @@ int set_error(int code, const char* fmt, ...) {
 
 void clear_error() { g_last_error[0] = '\0'; }
 
+// The allocator hook: every device allocation goes through the hook that is
+// installed when it is made, and is returned through the same hook (a
+// block's owner is recorded), so the hook may change at any time.
+namespace {
+struct Allocator {
+  spx_alloc_fn alloc = nullptr;
+  spx_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;                                  // current hook (alloc null: hipMalloc)
+std::unordered_map<void*, Allocator> g_hook_blocks;  // blocks that came from a hook
+}  // namespace
+
 int dalloc(void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  Allocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+  }
+  if (a.alloc) {
+    void* q = a.alloc(bytes, a.ctx);
+    if (!q)
+      return set_error(SPX_OUT_OF_MEMORY, "device allocation of %zu bytes failed (allocator hook)",
+                       bytes);
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_hook_blocks[q] = a;
+    *p = q;
+    return SPX_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -35,7 +66,23 @@ int dalloc(void** p, size_t bytes) {
 }
 
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  Allocator owner;
+  bool hooked = false;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_hook_blocks.find(p);
+    if (it != g_hook_blocks.end()) {
+      owner = it->second;
+      hooked = true;
+      g_hook_blocks.erase(it);
+    }
+  }
+  if (hooked) {
+    if (owner.free) owner.free(p, owner.ctx);
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 static void free_csr(Csr& M) {
@@ -79,6 +126,17 @@ extern "C" int spx_destroy(spx_handle h) {
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (cur != h->device) (void)hipSetDevice(cur);
   delete h;
+  return SPX_OK;
+}
+
+extern "C" int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx) {
+  clear_error();
+  if ((alloc == nullptr) != (free == nullptr))
+    return set_error(SPX_INVALID_ARG, "set_allocator: give both functions or neither");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.free = free;
+  g_alloc.ctx = ctx;
   return SPX_OK;
 }
 

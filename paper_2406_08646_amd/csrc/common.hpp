@@ -29,7 +29,8 @@ void clear_error();
   } while (0)
 
 // ------------------------------------------------------------- allocation
-// Device memory through hipMalloc; every failure is reported as
+// Device memory through the installed allocator hook (hipMalloc when none);
+// every failure is reported as
 // SPX_OUT_OF_MEMORY with the requested size.
 int dalloc(void** p, size_t bytes);
 void dfree(void* p);

@@ -82,6 +82,9 @@ _SIGNATURES = {
     "spx_lbfgs_get_info": [_vp, _pi64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "spx_lbfgs_update": [_vp, _vp, _vp, _vp],
     "spx_lbfgs_apply": [_vp, _vp, _vp, _vp, _vp],
+    "spx_set_allocator": [_vp, _vp, _vp],
+    "spx_stream_copy": [_vp, _vp, _i64, _vp],
+    "spx_stream_sum": [_vp, _i64, _vp, _vp],
     "spx_batch_cg": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
     "spx_batch_bicg": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
     "spx_batch_tfqmr": [_vp, _vp, _vp, _d, _i64, _vp, _vp, _pi64, _pd],
@@ -419,6 +422,55 @@ class Batch:
         iterations of two half-steps)."""
         return self._solve(load_library().spx_batch_tfqmr, b, x, rtol, maxit, blocks,
                            rows_per_tile, weight_exponent, check_every, stream)
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_hooks = []  # keeps the installed callbacks alive
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Routes the library's device allocations through PyTorch's caching
+    allocator (on the current device and stream at allocation time), or back
+    to hipMalloc with enable=False.  Blocks are returned to whichever
+    allocator made them."""
+    lib = load_library()
+    if not enable:
+        _check(lib.spx_set_allocator(None, None, None))
+        return
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      torch.cuda.current_stream())
+        except Exception:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _ALLOC_FN(_alloc), _FREE_FN(_free)
+    _hooks.append((a, f))
+    _check(lib.spx_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p),
+                                 None))
+
+
+def stream_copy(x: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+    """y = x with the library's bandwidth-reference copy kernel."""
+    _dev(x, torch.float64, None, "x")
+    _dev(y, torch.float64, x.numel(), "y")
+    _check(load_library().spx_stream_copy(_ptr(x), _ptr(y), x.numel(), _stream(stream)))
+    return y
+
+
+def stream_sum(x: torch.Tensor, partials: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Per-workgroup sums of x (2048 of them) with the bandwidth-reference read kernel."""
+    _dev(x, torch.float64, None, "x")
+    if partials is None:
+        partials = torch.empty(2048, dtype=torch.float64, device=x.device)
+    _dev(partials, torch.float64, 2048, "partials")
+    _check(load_library().spx_stream_sum(_ptr(x), x.numel(), _ptr(partials), _stream(stream)))
+    return partials
 
 
 def batch_create(mats: Sequence[Matrix], stream=None) -> Batch:

@@ -141,3 +141,50 @@ def test_gather_blocks_bitwise(orc):
     ge = A.coo_gather_blocks(G, dev(prob.dv_dlogk), 16)
     gv = orc.coo_grad(prob.i, prob.j, lam, u)
     assert np.array_equal(bits(host(ge)), bits(orc.block_reduce(gv, prob.dv_dlogk, 16)))
+
+
+def test_torch_allocator_hook():
+    """With PyTorch's caching allocator installed, the library's memory shows
+    up in torch's accounting, results are bitwise those of hipMalloc'd
+    handles, and blocks go back to the allocator that made them even when the
+    hook changes in between."""
+    spx = require_gpu()
+    prob, x, b = W.config1()
+    A0 = assemble(spx, prob)
+    y0 = host(A0.matmult(dev(x)))
+    r0 = A0.cg_solve(dev(b), rtol=1e-10)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    spx.use_torch_allocator(True)
+    try:
+        A1 = assemble(spx, prob)
+        y1 = host(A1.matmult(dev(x)))
+        r1 = A1.cg_solve(dev(b), rtol=1e-10)
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() > before + 36100 * 12
+        assert np.array_equal(bits(y1), bits(y0))
+        assert r1.iters == r0.iters and np.array_equal(bits(host(r1.x)), bits(host(r0.x)))
+        batch = spx.batch_create([A1])
+        xb, it, rel, st = batch.batch_cg(dev(b), rtol=1e-8)
+        assert st == 0
+    finally:
+        spx.use_torch_allocator(False)
+    # the hook-made blocks are freed through torch after the hook is gone
+    batch.destroy()
+    A1.destroy()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before + 4 * 1024 * 1024
+    A2 = assemble(spx, prob)
+    assert np.array_equal(bits(host(A2.matmult(dev(x)))), bits(y0))
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 4096, 1_000_003])
+def test_bandwidth_reference_kernels(n):
+    spx = require_gpu()
+    x = np.random.default_rng(60 + n % 97).uniform(-1, 1, n)
+    xd = dev(x)
+    y = torch.full_like(xd, np.nan)
+    spx.stream_copy(xd, y)
+    assert np.array_equal(bits(host(y)), bits(x))
+    parts = host(spx.stream_sum(xd))
+    assert abs(parts.sum() - x.sum()) <= 1e-12 * max(1.0, np.abs(x).sum())
