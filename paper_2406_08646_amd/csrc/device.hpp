@@ -53,33 +53,6 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + i;
 }
 
-// Called by every thread after thread 0 has stored this block's partial
-// results.  Returns true in the one block that arrives last; that block
-// then sees every other block's partials.  The ticket is reset for reuse.
-__device__ __forceinline__ bool arrive_last(uint32_t* ticket) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t t =
-        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1);
-    if (last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  const bool is_last = last != 0;
-  if (is_last) __threadfence();
-  return is_last;
-}
-
-// Deterministic sum of nparts values by one block (fixed strided split,
-// fixed tree), result valid in thread 0.
-template <int BLOCK>
-__device__ __forceinline__ double reduce_partials(const double* parts, int64_t nparts, double* lds) {
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += BLOCK) s += parts[i];
-  return block_sum<BLOCK>(s, lds);
-}
-
 // Loads that bypass the L2 allocation policy for streamed matrix data.
 template <typename T>
 __device__ __forceinline__ T stream_load(const T* p) {
