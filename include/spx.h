@@ -323,6 +323,18 @@ int spx_get_info(spx_handle h, int64_t* n, int64_t* nnz, int64_t* nvalid, int64_
 int spx_get_csr(spx_handle h, int32_t transpose, int32_t* rowptr, int32_t* col, double* val,
                 void* stream);
 
+/* Window index of A (transpose = 0) or of the explicit A^T (1, built on
+ * first use), which the window walk of the products reads.  HOST stats[4] =
+ * {1 if the pattern has an index else 0, largest window in blocks of 64
+ * x entries, total blocks over all tiles, entries of tiles that read x
+ * directly}.  When it exists, non-NULL DEVICE buffers receive
+ * ptr[ceil(n/256) + 1] (tile k's blocks are blk[ptr[k] .. ptr[k+1])),
+ * blk[stats[2]] (ascending block numbers) and lcol[nnz] (entry t's window
+ * position: slot of its block * 64 + col % 64; unset in tiles without a
+ * window).  The copies are asynchronous on `stream`. */
+int spx_get_window(spx_handle h, int32_t transpose, int64_t* stats, int32_t* ptr, int32_t* blk,
+                   uint16_t* lcol, void* stream);
+
 /* Copies the helper maps into caller DEVICE buffers jmap[nnz+1],
  * perm[nvalid] (either may be NULL).  Asynchronous. */
 int spx_get_coo_maps(spx_handle h, int32_t* jmap, int32_t* perm, void* stream);
@@ -350,7 +362,16 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *   SPX_OPT_SPMV_VARIANT: 0 auto, 1 vector (L lanes per row), 2 stream
  *     (rows of a workgroup streamed through LDS), 3 DMA (the stream walk
  *     with columns and values moved into LDS by direct 16-byte loads, two
- *     staging buffers in the solver kernels).
+ *     staging buffers in the solver kernels), 4 window (tiles of 256 rows
+ *     read the x entries they need from LDS, staged once per tile, and
+ *     16-bit window columns instead of the 32-bit ones; results bitwise
+ *     those of the stream walk; only for patterns with a window index, see
+ *     spx_get_window, else as 0).  Auto takes the window walk when the
+ *     pattern has an index and at least 12 of its 256-row tiles per compute
+ *     unit (smaller systems fill the chip better with the stream walk's
+ *     smaller tiles), rows average at most 64 entries in every tile and
+ *     none of SPX_OPT_ROWS_PER_BLOCK, SPX_OPT_QUAD_LOADS, SPX_OPT_PIPELINE
+ *     is set.  Reading the option returns the resolved variant.
  *   SPX_OPT_ROWS_PER_BLOCK: stream variant rows per workgroup (0 auto, else
  *     32, 64, 128 or 256).
  *   SPX_OPT_NONTEMPORAL: 1 (default) loads matrix values/columns

@@ -85,12 +85,30 @@ void dfree(void* p) {
   }
 }
 
+int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
 static void free_csr(Csr& M) {
   dfree(M.rowptr);
   dfree(M.col);
   dfree(M.val);
   dfree(M.val32);
   dfree(M.dpos);
+  dfree(M.win.lcol);
+  dfree(M.win.ptr);
+  dfree(M.win.blk);
   M = Csr();
 }
 
@@ -157,8 +175,8 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
       h->profile = value ? 1 : 0;
       return SPX_OK;
     case SPX_OPT_SPMV_VARIANT:
-      if (value < 0 || value > 3)
-        return set_error(SPX_INVALID_ARG, "set_option: variant %lld not in 0..3", (long long)value);
+      if (value < 0 || value > 4)
+        return set_error(SPX_INVALID_ARG, "set_option: variant %lld not in 0..4", (long long)value);
       h->variant_opt = (int)value;
       return SPX_OK;
     case SPX_OPT_ROWS_PER_BLOCK:

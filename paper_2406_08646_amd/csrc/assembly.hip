@@ -425,6 +425,7 @@ int symbolic(spx_matrix* h, const int32_t* i, const int32_t* j, hipStream_t s) {
     }
     h->A.max_row = host_misc[3];
     if ((st = compute_tiles(h->A, s)) != SPX_OK) break;
+    if ((st = build_window(h->A, s)) != SPX_OK) break;
     if ((st = dalloc_n(&h->perm, (size_t)std::max<int64_t>(nvalid, 1))) != SPX_OK) break;
     if (nvalid > 0 &&
         hipMemcpyAsync(h->perm, svals, sizeof(int32_t) * (size_t)nvalid, hipMemcpyDeviceToDevice,
@@ -494,6 +495,7 @@ int ensure_transpose(spx_matrix* h, hipStream_t s) {
       h->At.n = n;
       h->At.nnz = nnz;
       if ((st = compute_tiles(h->At, s)) != SPX_OK) break;
+      if ((st = build_window(h->At, s)) != SPX_OK) break;
     } while (false);
     dfree(keys);
     dfree(vals);

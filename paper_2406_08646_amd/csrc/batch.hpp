@@ -71,15 +71,6 @@ struct spx_batch {
 namespace spx {
 namespace batch {
 
-inline int cu_count_b() {
-  int dev = 0, cus = 0;
-  (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0)
-    cus = 256;
-  return cus;
-}
-
 // Splits G workgroups among the active systems: team size proportional to
 // nnz_s^gamma, at least one workgroup each, teams contiguous in system order.
 inline void make_plan(const spx_batch* B, const std::vector<char>& active, int G, double gamma,
@@ -175,7 +166,7 @@ struct Run {
 inline int prepare(spx_batch* B, const spx_batch_tuning* tuning, const int64_t max_tile[4],
                    int64_t max_row, int sets, hipStream_t s, Run* run) {
   const int ns = B->nsys;
-  int G = (tuning && tuning->blocks > 0) ? tuning->blocks : cu_count_b() * 8;
+  int G = (tuning && tuning->blocks > 0) ? tuning->blocks : cu_count() * 8;
   G = std::max(G, ns);
   run->G = G;
   run->gamma = (tuning && tuning->weight_exponent > 0.0) ? tuning->weight_exponent : 1.0;

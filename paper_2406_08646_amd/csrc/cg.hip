@@ -71,7 +71,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const int32_t* __
                                                     const double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ p,
                                                     const double* __restrict__ dinv,
-                                                    double* __restrict__ P, int rows, int remap, int64_t tile) {
+                                                    double* __restrict__ P, int rows, int remap,
+                                                    int64_t tile, WinView win) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   const int64_t nb = gridDim.x;
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const int32_t* __
                                          rz += ri * zi;
                                          rr += ri * ri;
                                          bb += bi * bi;
-                                       }, tile);
+                                       }, tile, win);
   rz = block_sum<kBlock>(rz, lds);
   rr = block_sum<kBlock>(rr, lds);
   bb = block_sum<kBlock>(bb, lds);
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __
                                                     const VT* __restrict__ val,
                                                     const VT* __restrict__ p, VT* __restrict__ q,
                                                     const CgScalars* __restrict__ st,
-                                                    double* __restrict__ P1, int rows, int remap, int64_t tile) {
+                                                    double* __restrict__ P1, int rows, int remap,
+                                                    int64_t tile, WinView win) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   if (st->done) return;
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __
                            reinterpret_cast<VT*>(smem), [&](int64_t row, VT s) {
                              q[row] = s;
                              dot += (double)p[row] * (double)s;
-                           }, tile);
+                           }, tile, win);
   dot = block_sum<kBlock>(dot, lds);
   if (threadIdx.x == 0) P1[blockIdx.x] = dot;
 }
@@ -235,7 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_resnorm(int64_t n, const int32_t* __
                                                     const double* __restrict__ val,
                                                     const double* __restrict__ b,
                                                     const double* __restrict__ x,
-                                                    double* __restrict__ P, int rows, int remap, int64_t tile) {
+                                                    double* __restrict__ P, int rows, int remap,
+                                                    int64_t tile, WinView win) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   double rr = 0.0;
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_resnorm(int64_t n, const int32_t* __
                                        reinterpret_cast<double*>(smem), [&](int64_t row, double ax) {
                                          const double ri = b[row] - ax;
                                          rr += ri * ri;
-                                       }, tile);
+                                       }, tile, win);
   rr = block_sum<kBlock>(rr, lds);
   if (threadIdx.x == 0) P[blockIdx.x] = rr;
 }
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_init(int64_t n, const int32_t* __
                                                     const double* __restrict__ u,
                                                     double* __restrict__ p, double* __restrict__ s,
                                                     double* __restrict__ P, int rows, int remap,
-                                                    int64_t tile) {
+                                                    int64_t tile, WinView win) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   double delta = 0.0;
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_init(int64_t n, const int32_t* __
                                          p[row] = ur;
                                          s[row] = w;
                                          delta += w * ur;
-                                       }, tile);
+                                       }, tile, win);
   delta = block_sum<kBlock>(delta, lds);
   if (threadIdx.x == 0) P[blockIdx.x] = delta;
 }
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
                                                     double* __restrict__ p, double* __restrict__ s,
                                                     CgScalars* st, const double* __restrict__ P2,
                                                     int64_t G2, double* __restrict__ P1, int rows,
-                                                    int remap, int64_t tile, int64_t k) {
+                                                    int remap, int64_t tile, int64_t k, WinView win) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   if (st->done) return;
@@ -382,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
                                          p[row] = ur + beta * p[row];
                                          s[row] = w + beta * s[row];
                                          delta += w * ur;
-                                       }, tile);
+                                       }, tile, win);
   delta = block_sum<kBlock>(delta, lds);
   if (threadIdx.x == 0) P1[blockIdx.x] = delta;
 }
@@ -546,7 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
     int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ b, const double* __restrict__ x,
     const float* __restrict__ dinv32, float* __restrict__ r32, float* __restrict__ d32,
-    float* __restrict__ p32, double* __restrict__ P, int rows, int remap, int64_t tile) {
+    float* __restrict__ p32, double* __restrict__ P, int rows, int remap, int64_t tile,
+    WinView win) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   const int64_t nb = gridDim.x;
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
                                          p32[row] = zf;
                                          rz += (double)rf * (double)zf;
                                          rr32 += (double)rf * (double)rf;
-                                       }, tile);
+                                       }, tile, win);
   rr64 = block_sum<kBlock>(rr64, lds);
   rz = block_sum<kBlock>(rz, lds);
   rr32 = block_sum<kBlock>(rr32, lds);
@@ -646,13 +650,22 @@ struct Op {
   const int32_t* col;
   const VT* val;
   SpmvShape sh;
+  WinView win;
 };
 
+// Dynamic LDS of the solver kernels for elements of type VT (sh.lds is
+// sized for doubles).
 template <typename VT>
 size_t shape_lds(const SpmvShape& sh) {
-  if (sh.variant == kVariantDma) return 2 * ((dma_buffer_bytes(sh.tile, sizeof(VT)) + 15) & ~size_t(15));
-  if (sh.variant != kVariantStream) return 0;
-  return sh.lds / sizeof(double) * sizeof(VT);
+  switch (sh.variant) {
+    case kVariantDma:
+      return 2 * ((dma_buffer_bytes(sh.tile, sizeof(VT)) + 15) & ~size_t(15));
+    case kVariantStream:
+    case kVariantWindow:
+      return sh.lds / sizeof(double) * sizeof(VT);
+    default:
+      return 0;  // the vector walk uses none
+  }
 }
 
 // Enqueues iterations first .. first+count-1 (1-based k) of K1, K2, K3.
@@ -666,14 +679,14 @@ int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* 
   double* P1 = h->partials;
   double* P2 = h->partials + G1;
   const size_t lds = shape_lds<VT>(A.sh);
-  return with_shape(A.sh, [&](auto shc) {
+  return with_shape<true>(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     for (int64_t c = 0; c < count; ++c) {
       const int64_t k = device_k ? 0 : first + c;
       hipEvent_t* e = evs ? evs + 6 * c : nullptr;
       if (e) (void)hipEventRecord(e[0], s);
       hipLaunchKernelGGL((k_cg_spmv<SH, VT>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr, A.col,
-                         A.val, p, q, st, P1, A.sh.rows, h->xcd_remap, A.sh.tile);
+                         A.val, p, q, st, P1, A.sh.rows, h->xcd_remap, A.sh.tile, A.win);
       if (e) (void)hipEventRecord(e[1], s);
       if (e) (void)hipEventRecord(e[2], s);
       hipLaunchKernelGGL((k_cg_update<VT>), dim3(G2), dim3(kBlock), 0, s, A.n, x, r, p, q, dinv, st,
@@ -856,7 +869,7 @@ int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, 
   return run_until_done(
       h, st, maxit, check_every, s, 2, kinds, 0,
       [&](int64_t first, int64_t count, hipEvent_t* evs) {
-        return with_shape(A.sh, [&](auto shc) {
+        return with_shape<true>(A.sh, [&](auto shc) {
           using SH = decltype(shc);
           for (int64_t c = 0; c < count; ++c) {
             const int64_t k = first + c;
@@ -868,7 +881,7 @@ int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, 
             if (e) (void)hipEventRecord(e[2], s);
             hipLaunchKernelGGL((k_sr_spmv<SH>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr,
                                A.col, A.val, u, p, sv, st, P2, (int64_t)G2, P1, A.sh.rows,
-                               h->xcd_remap, A.sh.tile, k);
+                               h->xcd_remap, A.sh.tile, k, A.win);
             if (e) (void)hipEventRecord(e[3], s);
           }
           return SPX_OK;
@@ -881,10 +894,11 @@ int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, 
 int enqueue_resnorm(spx_matrix* h, const Op<double>& A, const double* b, const double* x,
                     CgScalars* st, hipStream_t s) {
   const unsigned G = (unsigned)fused_blocks(h);
-  SPX_TRY(with_shape(A.sh, [&](auto shc) {
+  SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_resnorm<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, A.n,
-                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, h->xcd_remap, A.sh.tile);
+                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, h->xcd_remap, A.sh.tile,
+                       A.win);
     return SPX_OK;
   }));
   hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G);
@@ -919,7 +933,7 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
   if (maxit > INT32_MAX - 1) maxit = INT32_MAX - 1;
   SPX_TRY(ensure_solver(h));
   const int64_t n = M.n;
-  const Op<double> A{n, M.rowptr, M.col, M.val, solver_shape(h, M)};
+  const Op<double> A{n, M.rowptr, M.col, M.val, solver_shape(h, M), win_view(M)};
   double* r = h->work;
   double* p = h->work + n;
   double* q = h->work + 2 * n;
@@ -958,11 +972,11 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
     SPX_CHECK_HIP(hipGetLastError());
     return finish_solve(h, A, b, x, st, s, iters_out, relres_out);
   }
-  SPX_TRY(with_shape(A.sh, [&](auto shc) {
+  SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_cg_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
                        M.rowptr, M.col, M.val, b, x, r, p, h->dinv, h->partials, A.sh.rows,
-                       h->xcd_remap, A.sh.tile);
+                       h->xcd_remap, A.sh.tile, A.win);
     return SPX_OK;
   }));
   hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G,
@@ -973,11 +987,11 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
     // w = A u, p = u, s = w, delta_0
     double* u = h->work + 3 * n;
     SPX_CHECK_HIP(hipMemcpyAsync(u, p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
-    SPX_TRY(with_shape(A.sh, [&](auto shc) {
+    SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_sr_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
                          M.rowptr, M.col, M.val, u, p, q, h->partials, A.sh.rows, h->xcd_remap,
-                         A.sh.tile);
+                         A.sh.tile, A.win);
       return SPX_OK;
     }));
     SPX_CHECK_HIP(hipGetLastError());
@@ -1010,22 +1024,6 @@ int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const doub
 
 }  // namespace
 
-namespace {
-int cu_count() {
-  static int cached[64] = {0};
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  if (dev < 0 || dev >= 64) dev = 0;
-  if (!cached[dev]) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    cached[dev] = cus;
-  }
-  return cached[dev];
-}
-}  // namespace
 
 // Workgroups of the solver's SpMV-shaped kernels (each walks a contiguous
 // share of the rows) and of its vector kernels; every workgroup of the
@@ -1033,10 +1031,29 @@ int cu_count() {
 // Both shrink with the system: every workgroup of the next kernel re-adds
 // all partials, so a small system with a full-chip grid would spend its
 // iteration reading thousands of partials that hold zeros.
+// Workgroups of the solver's row-walk kernels: 8 per CU, at least one
+// 64-row tile each.  The window walk works on 256-row tiles and holds more
+// LDS; its grid is cut to the workgroups that are resident at once (taken
+// for the fp64 kernel, which needs the most), so no workgroup of the
+// persistent grid waits for another to finish.
 int fused_blocks(const spx_matrix* h) {
   if (h && h->fused_opt > 0) return h->fused_opt;
-  const int64_t tiles = h ? ceil_div(h->n, 64) : 1;  // at least one 64-row tile each
-  return (int)std::max<int64_t>(1, std::min<int64_t>(cu_count() * 8, tiles));
+  if (!h) return 1;
+  int64_t per_cu = 8;
+  int64_t tiles = ceil_div(h->n, 64);
+  const SpmvShape sh = solver_shape(h, h->A);
+  if (sh.variant == kVariantWindow) {
+    tiles = ceil_div(h->n, kWinRows);
+    const void* fn =
+        sh.nt ? reinterpret_cast<const void*>(&k_cg_spmv<Shape<kVariantWindow, 1, true>, double>)
+              : reinterpret_cast<const void*>(&k_cg_spmv<Shape<kVariantWindow, 1, false>, double>);
+    int fit = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, fn, kBlock, sh.lds) == hipSuccess &&
+        fit > 0)
+      per_cu = std::min<int64_t>(per_cu, fit);
+    (void)hipGetLastError();
+  }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cu_count() * per_cu, tiles));
 }
 
 int vector_blocks(const spx_matrix* h) {
@@ -1085,8 +1102,8 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
   const Csr& M = h->A;
   const int64_t n = M.n;
   const SpmvShape sh = solver_shape(h, M);
-  const Op<double> A64{n, M.rowptr, M.col, M.val, sh};
-  const Op<float> A32{n, M.rowptr, M.col, M.val32, spmv_shape32(h, M)};
+  const Op<double> A64{n, M.rowptr, M.col, M.val, sh, win_view(M)};
+  const Op<float> A32{n, M.rowptr, M.col, M.val32, spmv_shape32(h, M), win_view(M)};
   float* r32 = h->work32;
   float* d32 = h->work32 + n;
   float* p32 = h->work32 + 2 * n;
@@ -1105,11 +1122,11 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
   int64_t outer = 0, inner = 0;
   int status = SPX_OK;
   for (;;) {
-    SPX_TRY(with_shape(sh, [&](auto shc) {
+    SPX_TRY(with_shape<true>(sh, [&](auto shc) {
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_ir_residual<SH>), dim3(G), dim3(kBlock), shape_lds<double>(sh), s, n,
                          M.rowptr, M.col, M.val, b, x, h->dinv32, r32, d32, p32, h->partials,
-                         sh.rows, h->xcd_remap, sh.tile);
+                         sh.rows, h->xcd_remap, sh.tile, A64.win);
       return SPX_OK;
     }));
     hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, so, si, h->partials, (int64_t)G,

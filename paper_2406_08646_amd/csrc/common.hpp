@@ -43,6 +43,8 @@ inline int dalloc_n(T** p, size_t count) {
 }
 
 // ----------------------------------------------------- launch geometry
+// Compute units of the current device (cached per device).
+int cu_count();
 constexpr int kWave = 64;
 constexpr int kXcds = 8;
 
@@ -68,7 +70,40 @@ int exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t count, uint32_
 
 // -------------------------------------------------------------- matrix
 // How products walk a matrix (chosen once per pattern, see spmv.hip).
-enum SpmvVariant { kVariantAuto = 0, kVariantVector = 1, kVariantStream = 2, kVariantDma = 3 };
+enum SpmvVariant {
+  kVariantAuto = 0,
+  kVariantVector = 1,
+  kVariantStream = 2,
+  kVariantDma = 3,
+  kVariantWindow = 4
+};
+
+// x window of a tile of kWinRows consecutive rows: the blocks of kWinBlock
+// consecutive x entries that the tile's columns fall in, ascending.  The
+// window walk stages them in LDS, and lcol[t] = slot * kWinBlock +
+// col[t] % kWinBlock is entry t's position in its tile's window.  A tile
+// with entries whose columns span more than kWinSpan blocks, or fall in
+// more than kWinMaxBlocks of them, gets an empty window and reads x
+// directly.
+constexpr int kWinRows = 256;
+constexpr int kWinBlock = 64;
+constexpr int kWinMaxBlocks = 64;
+constexpr int kWinSpan = 8192;
+struct Window {
+  uint16_t* lcol = nullptr;  // [nnz]
+  int32_t* ptr = nullptr;    // [tiles + 1]: tile k's blocks are blk[ptr[k] .. ptr[k+1])
+  int32_t* blk = nullptr;    // block numbers (x entries blk * kWinBlock ...)
+  int64_t max_blocks = 0;    // largest window of any tile
+  int64_t total_blocks = 0;
+  int64_t gather_entries = 0;  // entries of tiles without a window
+};
+
+// What the kernels of the window walk receive.
+struct WinView {
+  const uint16_t* lcol;
+  const int32_t* ptr;
+  const int32_t* blk;
+};
 
 struct Csr {
   int64_t n = 0, nnz = 0;
@@ -80,11 +115,14 @@ struct Csr {
   int64_t max_row = 0;
   // largest number of entries in a block of 32/64/128/256 consecutive rows
   int64_t tile_nnz[4] = {0, 0, 0, 0};
+  Window win;  // empty (lcol == nullptr) when the pattern does not profit from one
 };
+
+inline WinView win_view(const Csr& A) { return WinView{A.win.lcol, A.win.ptr, A.win.blk}; }
 
 // Resolved launch shape of a product on one matrix.
 struct SpmvShape {
-  int variant;   // kVariantVector or kVariantStream
+  int variant;   // kVariantVector, kVariantStream, kVariantDma or kVariantWindow
   int lanes;     // vector: lanes per row
   int rows;      // stream: rows per workgroup
   size_t lds;    // stream: LDS bytes per workgroup (for 8-byte products)
@@ -92,6 +130,7 @@ struct SpmvShape {
   int vec;       // stream: 16-byte quad loads
   int pipe;      // stream, persistent kernels: next tile's loads issued early
   int64_t tile;  // stream / DMA: most entries in one tile of `rows` rows
+                 // window: x entries of the largest window (LDS slots)
 };
 
 // Device-resident solver scalars of one CG run.  rho[k & 1] holds r_k . z_k,
@@ -179,7 +218,11 @@ int ensure_val32(spx_matrix* h, hipStream_t s);
 // spmv.hip
 int pick_lanes(const Csr& A, int opt);
 int compute_tiles(Csr& A, hipStream_t s);
+// window.hip
+int build_window(Csr& A, hipStream_t s);
 SpmvShape spmv_shape(const spx_matrix* h, const Csr& A);
+// allow_window = false: the shape the options give without the window walk
+SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window);
 SpmvShape spmv_shape32(const spx_matrix* h, const Csr& A);
 SpmvShape solver_shape(const spx_matrix* h, const Csr& A);
 int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, int remap,

@@ -293,14 +293,6 @@ __global__ void k_lb_scale(int64_t n, const double* __restrict__ g, const double
   if (i < n) p[i] = (h0 ? h0[i] : 1.0) * g[i];
 }
 
-int cu_count_lb() {
-  int dev = 0, cus = 0;
-  (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0)
-    cus = 256;
-  return cus;
-}
 
 }  // namespace
 }  // namespace spx
@@ -321,7 +313,7 @@ extern "C" int spx_lbfgs_create(int64_t n, int32_t m, void* stream, spx_lbfgs_ha
   h->n = n;
   h->m = m;
   const int64_t rows_per_wg = 4 * kLB;
-  h->G = (int)std::max<int64_t>(1, std::min<int64_t>(cu_count_lb() * 4, ceil_div(n, rows_per_wg)));
+  h->G = (int)std::max<int64_t>(1, std::min<int64_t>(cu_count() * 4, ceil_div(n, rows_per_wg)));
   int st = SPX_OK;
   do {
     if ((st = dalloc_n(&h->S, (size_t)n * m)) != SPX_OK) break;

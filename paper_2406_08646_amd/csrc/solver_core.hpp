@@ -216,8 +216,20 @@ __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ 
                                          const int32_t* __restrict__ col,
                                          const VT* __restrict__ val, const XT* __restrict__ x,
                                          int rows, int64_t lb, int64_t nb, ACC* prod, Epi&& epi,
-                                         int64_t tile = 0) {
-  if constexpr (SH::variant == kVariantDma) {
+                                         int64_t tile = 0, const WinView& win = WinView{}) {
+  if constexpr (SH::variant == kVariantWindow) {
+    static_assert(kBlock == kWinRows, "one thread per row of a window tile");
+    static_assert(sizeof(VT) == sizeof(ACC) && sizeof(XT) == sizeof(ACC),
+                  "the window walk's LDS is sized for one element type");
+    const Share sh = xcd_share(ceil_div(n, kWinRows), lb, nb);
+    for (int64_t rb = sh.first; rb < sh.end; rb += sh.step) {
+      const int64_t r0 = rb * kWinRows;
+      const int64_t r1 = r0 + kWinRows < n ? r0 + kWinRows : n;
+      const ACC s = window_rows<kBlock, VT, XT, ACC, SH::nt>(rowptr, col, val, x, n, win, rb, r0,
+                                                             r1, prod);
+      if (threadIdx.x < r1 - r0) epi(r0 + threadIdx.x, s);
+    }
+  } else if constexpr (SH::variant == kVariantDma) {
     const Share sh = xcd_share(ceil_div(n, rows), lb, nb);
     dma_tiles<VT, XT, ACC>(n, rowptr, col, val, x, rows, tile, sh.first, sh.end, sh.step,
                            reinterpret_cast<char*>(prod), epi);
@@ -257,8 +269,16 @@ __device__ __forceinline__ int64_t logical_block(int remap) {
 }
 
 
-template <typename F>
+// Calls f with the compile-time Shape of sh.  Only callers whose kernels
+// receive the window index (WIN) may be handed the window walk.
+template <bool WIN = false, typename F>
 inline int with_shape(const SpmvShape& sh, F&& f) {
+  if (sh.variant == kVariantWindow) {
+    if constexpr (WIN)
+      return sh.nt ? f(Shape<kVariantWindow, 1, true>()) : f(Shape<kVariantWindow, 1, false>());
+    else
+      return set_error(SPX_INVALID_ARG, "this kernel has no window walk");
+  }
   if (sh.variant == kVariantDma) return f(Shape<kVariantDma, 1, false>());
   if (sh.variant == kVariantStream) {
     if (sh.pipe == 8)

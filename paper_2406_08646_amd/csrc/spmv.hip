@@ -9,6 +9,12 @@
 // range, which keeps the x entries shared by neighbouring rows in that XCD's
 // L2.  No MFMA: SpMV moves ~6 bytes per flop, far below the matrix-core
 // ridge point, so the kernel is bound by HBM bandwidth.
+//
+// Where the pattern has a window index, the default walk is the window
+// walk: a workgroup per tile of kWinRows rows stages the x blocks its
+// columns touch in LDS and streams values with 16-bit window columns, so
+// the x gather becomes an LDS read and each entry moves 10 bytes instead of
+// 12; its row sums are bitwise those of the stream walk.
 #include <algorithm>
 
 #include "common.hpp"
@@ -52,6 +58,22 @@ __global__ __launch_bounds__(BLOCK) void k_spmv_stream(int64_t n, const int32_t*
     s = stream_rows_v4<BLOCK, U, double, double, double, NT>(rowptr, col, val, x, r0, r1, prod);
   else
     s = stream_rows<BLOCK, U, double, double, double, NT>(rowptr, col, val, x, r0, r1, prod);
+  if (threadIdx.x < r1 - r0) y[r0 + threadIdx.x] = s;
+}
+
+template <bool NT>
+__global__ __launch_bounds__(kWinRows) void k_spmv_window(int64_t n, const int32_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ val,
+                                                          const double* __restrict__ x,
+                                                          double* __restrict__ y, WinView w,
+                                                          int remap) {
+  extern __shared__ __align__(16) char smem[];
+  const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t r0 = b * kWinRows;
+  const int64_t r1 = r0 + kWinRows < n ? r0 + kWinRows : n;
+  const double s = window_rows<kWinRows, double, double, double, NT>(
+      rowptr, col, val, x, n, w, b, r0, r1, reinterpret_cast<double*>(smem));
   if (threadIdx.x < r1 - r0) y[r0 + threadIdx.x] = s;
 }
 
@@ -271,7 +293,35 @@ constexpr size_t kStreamLdsMax = 64 * 1024;
 int rows_index(int rows) { return rows == 32 ? 0 : rows == 64 ? 1 : rows == 128 ? 2 : 3; }
 }  // namespace
 
-SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
+namespace {
+// The window walk's shape when A has a window index and the options leave
+// the choice to the library (or ask for it).  Left to itself the library
+// takes it for patterns of at least kWinAutoTilesPerCu 256-row tiles per
+// compute unit (below that the stream walk's smaller tiles fill the chip
+// better) whose rows average at most 64 entries in every tile (one thread
+// adds each row).  It needs no tile in LDS, so it also takes patterns whose
+// tiles exceed the stream walk's limit.
+constexpr int64_t kWinAutoTilesPerCu = 12;
+bool window_shape(const spx_matrix* h, const Csr& A, bool allow, SpmvShape& sh) {
+  if (!allow || !A.win.lcol) return false;
+  const int want = h ? h->variant_opt : 0;
+  const bool tuned = h && (h->rows_opt || h->vec_opt || h->pipe_opt);
+  const bool large = ceil_div(A.n, kWinRows) >= kWinAutoTilesPerCu * cu_count();
+  if (want == kVariantWindow || (want == kVariantAuto && !tuned && large &&
+                                 A.tile_nnz[3] <= 64 * (int64_t)kWinRows)) {
+    sh.variant = kVariantWindow;
+    sh.rows = kWinRows;
+    sh.tile = A.win.max_blocks * kWinBlock;
+    sh.lds = window_lds_bytes(A.win.max_blocks, sizeof(double));
+    return true;
+  }
+  return false;
+}
+}  // namespace
+
+SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) { return spmv_shape_for(h, A, true); }
+
+SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window) {
   SpmvShape sh;
   sh.lanes = pick_lanes(A, h ? h->lanes_opt : 0);
   sh.nt = h ? h->nt_opt : 1;
@@ -283,6 +333,7 @@ SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) {
   sh.tile = 0;
   const int want = h ? h->variant_opt : 0;
   if (want == kVariantVector) return sh;
+  if (window_shape(h, A, allow_window, sh)) return sh;
   const int rows_opt = h ? h->rows_opt : 0;
   if (want == kVariantDma) {
     // two staging buffers per workgroup in the solver kernels
@@ -350,7 +401,8 @@ void set_pipe(const spx_matrix* h, const Csr& A, SpmvShape& sh) {
 // Shape of the fp32 copy (mixed-precision inner solve): fp32 products take
 // half the LDS, so the tile doubles when it still fits.
 SpmvShape spmv_shape32(const spx_matrix* h, const Csr& A) {
-  SpmvShape sh = spmv_shape(h, A);
+  SpmvShape sh = spmv_shape_for(h, A, !(h && h->rows32_opt));
+  if (sh.variant == kVariantWindow) return sh;
   if (sh.variant == kVariantDma) {
     const int want = h && h->rows32_opt ? h->rows32_opt : sh.rows;
     const int64_t tile = A.tile_nnz[rows_index(want)];
@@ -382,6 +434,16 @@ SpmvShape solver_shape(const spx_matrix* h, const Csr& A) {
 int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, int remap,
                 hipStream_t s) {
   if (A.n == 0) return SPX_OK;
+  if (sh.variant == kVariantWindow) {
+    const int64_t nb = ceil_div(A.n, kWinRows);
+    if (sh.nt)
+      hipLaunchKernelGGL(k_spmv_window<true>, dim3((unsigned)nb), dim3(kWinRows), sh.lds, s, A.n,
+                         A.rowptr, A.col, A.val, x, y, win_view(A), remap);
+    else
+      hipLaunchKernelGGL(k_spmv_window<false>, dim3((unsigned)nb), dim3(kWinRows), sh.lds, s, A.n,
+                         A.rowptr, A.col, A.val, x, y, win_view(A), remap);
+    return SPX_OK;
+  }
   if (sh.variant == kVariantDma) {
     const int64_t nb = ceil_div(A.n, sh.rows);
     hipLaunchKernelGGL((k_spmv_dma<256>), dim3((unsigned)nb), dim3(256),

@@ -13,6 +13,7 @@
 
 #include <cstdint>
 
+#include "common.hpp"
 #include "device.hpp"
 
 namespace spx {
@@ -253,6 +254,144 @@ __host__ __device__ inline size_t dma_buffer_bytes(int64_t tile, size_t vbytes) 
   const int64_t capc = (tile + 8 + 3) & ~int64_t(3);
   const int64_t capv = tile + 16;
   return 4 * (size_t)capc + vbytes * (size_t)capv;
+}
+
+// -------------------------------------------------------------- window walk
+// Entries per thread of one chunk of the window walk.
+constexpr int kWinU = 3;
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
+// Copies blocks blk[k0 .. k0 + nbk) of x (n entries; entries at n and
+// beyond read as 0) into xs, block i at xs + i * kWinBlock, with 16-byte
+// loads when x is 16-byte aligned.  x is read through the caches: each
+// block serves several neighbouring tiles.
+template <int BLOCK, typename XT>
+__device__ __forceinline__ void load_window(const XT* __restrict__ x, int64_t n,
+                                            const int32_t* __restrict__ blk, int32_t k0,
+                                            int32_t nbk, XT* xs) {
+  constexpr int PER = 16 / sizeof(XT);
+  constexpr int LPB = kWinBlock / PER;
+  typedef typename Vec16<XT>::type V;
+  const bool aligned = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  for (int q = threadIdx.x; q < nbk * LPB; q += BLOCK) {
+    const int i = q / LPB, e = (q % LPB) * PER;
+    const int64_t g = (int64_t)blk[k0 + i] * kWinBlock + e;
+    XT* d = xs + i * kWinBlock + e;
+    if (aligned && g + PER <= n) {
+      *reinterpret_cast<V*>(d) = *reinterpret_cast<const V*>(x + g);
+    } else {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) d[j] = g + j < n ? x[g + j] : XT(0);
+    }
+  }
+}
+
+// The chunk loop of one tile of the window walk.  WIN: x is read from the
+// tile's window (blocks blk[k0 .. k0 + nbk), staged into xs before the
+// first barrier while the first chunk's values and indices are in flight)
+// through the 16-bit window columns `cidx`; otherwise straight from memory
+// through the 32-bit columns.  Thread i owns the row whose entries are
+// [ra, re) relative to the tile's first entry t0.
+template <bool WIN, int BLOCK, typename VT, typename XT, typename ACC, bool NT, typename CT>
+__device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const VT* __restrict__ val,
+                                             const XT* __restrict__ x, int64_t n,
+                                             const int32_t* __restrict__ blk, int32_t k0,
+                                             int32_t nbk, int32_t t0, int32_t cnt, int32_t ra,
+                                             int32_t re, ACC* prod) {
+  constexpr int U = kWinU;
+  constexpr int32_t C = BLOCK * U;
+  XT* xs = reinterpret_cast<XT*>(prod + C);
+  const int tid = threadIdx.x;
+  VT a[U];
+  int32_t c[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int32_t i = u * BLOCK + tid;
+    if (i < cnt) {
+      a[u] = mload<NT>(val + t0 + i);
+      c[u] = (int32_t)mload<NT>(cidx + t0 + i);
+    }
+  }
+  if constexpr (WIN) load_window<BLOCK, XT>(x, n, blk, k0, nbk, xs);
+  __syncthreads();
+  ACC s = ACC(0);
+  for (int32_t base = 0; base < cnt; base += C) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t i = base + u * BLOCK + tid;
+      if (i < cnt) {
+        XT xv;
+        if constexpr (WIN)
+          xv = xs[c[u]];
+        else
+          xv = x[c[u]];
+        prod[u * BLOCK + tid] = (ACC)a[u] * (ACC)xv;
+      }
+    }
+    const int32_t next = base + C;
+    if (next < cnt) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t i = next + u * BLOCK + tid;
+        if (i < cnt) {
+          a[u] = mload<NT>(val + t0 + i);
+          c[u] = (int32_t)mload<NT>(cidx + t0 + i);
+        }
+      }
+    }
+    __syncthreads();
+    const int32_t lo = ra > base ? ra : base, hi = re < next ? re : next;
+    for (int32_t i = lo; i < hi; ++i) s += prod[i - base];
+    __syncthreads();
+  }
+  return s;
+}
+
+// One tile of the window walk: tile number `tile` covers rows [r0, r1)
+// (r1 - r0 <= kWinRows == BLOCK) and thread i owns row r0 + i.  The tile's
+// entries are taken in chunks of BLOCK * kWinU: the chunk's products
+// val[t] * x[col[t]] go to prod (x read from the tile's window, staged in
+// LDS behind prod, or directly from memory for a tile without a window),
+// then every thread adds its own row's products of the chunk in entry
+// order, carrying its sum from chunk to chunk.  Each row's sum is thus
+// formed in exactly the order of stream_rows, with LDS use independent of
+// the tile's length.  The next chunk's values and columns are loaded before
+// the current chunk's sums.  LDS: BLOCK * kWinU ACC products, then the
+// largest window's x entries.  Returns the row sum in its owner thread and
+// leaves the workgroup synchronised.
+template <int BLOCK, typename VT, typename XT, typename ACC, bool NT>
+__device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
+                                           const int32_t* __restrict__ col,
+                                           const VT* __restrict__ val, const XT* __restrict__ x,
+                                           int64_t n, const WinView& w, int64_t tile, int64_t r0,
+                                           int64_t r1, ACC* prod) {
+  static_assert(BLOCK == kWinRows, "one thread per row of a window tile");
+  const int tid = threadIdx.x;
+  const int32_t t0 = rowptr[r0], cnt = rowptr[r1] - t0;
+  const int32_t k0 = w.ptr[tile], nbk = w.ptr[tile + 1] - k0;
+  const bool own = tid < r1 - r0;
+  const int32_t ra = own ? rowptr[r0 + tid] - t0 : 0;
+  const int32_t re = own ? rowptr[r0 + tid + 1] - t0 : 0;
+  if (nbk > 0)
+    return window_chunks<true, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0, cnt,
+                                                       ra, re, prod);
+  return window_chunks<false, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, cnt, ra,
+                                                      re, prod);
+}
+
+// LDS bytes of the window walk for elements of `bytes` bytes.
+__host__ __device__ inline size_t window_lds_bytes(int64_t max_blocks, size_t bytes) {
+  return ((size_t)kWinRows * kWinU + (size_t)max_blocks * kWinBlock) * bytes;
 }
 
 }  // namespace spx

@@ -93,6 +93,7 @@ _SIGNATURES = {
     "spx_coo_gather_blocks": [_vp, _vp, _vp, _i64, _vp, _vp],
     "spx_get_info": [_vp, _pi64, _pi64, _pi64, _pi64],
     "spx_get_csr": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "spx_get_window": [_vp, _i32, _pi64, _vp, _vp, _vp, _vp],
     "spx_get_coo_maps": [_vp, _vp, _vp, _vp],
     "spx_set_option": [_vp, _i32, _i64],
     "spx_get_option": [_vp, _i32, _pi64],
@@ -228,6 +229,25 @@ class Matrix:
         _check(load_library().spx_get_csr(self.handle, int(transpose), _ptr(rowptr), _ptr(col),
                                           _ptr(val), _stream(stream)))
         return rowptr, col, val
+
+    def get_window(self, transpose: bool = False, arrays: bool = True, stream=None):
+        """The window index (see spx_get_window): a dict with the statistics
+        and, when the index exists and ``arrays``, its device arrays."""
+        stats = (ctypes.c_int64 * 4)()
+        lib = load_library()
+        _check(lib.spx_get_window(self.handle, int(transpose), ctypes.cast(stats, _pi64), None,
+                                  None, None, _stream(stream)))
+        out = {"built": bool(stats[0]), "max_blocks": stats[1], "total_blocks": stats[2],
+               "gather_entries": stats[3]}
+        if stats[0] and arrays:
+            tiles = (self.n + 255) // 256
+            ptr = torch.empty(tiles + 1, dtype=torch.int32, device=self.device)
+            blk = torch.empty(max(stats[2], 1), dtype=torch.int32, device=self.device)
+            lcol = torch.empty(self.nnz, dtype=torch.uint16, device=self.device)
+            _check(lib.spx_get_window(self.handle, int(transpose), ctypes.cast(stats, _pi64),
+                                      _ptr(ptr), _ptr(blk), _ptr(lcol), _stream(stream)))
+            out.update(ptr=ptr, blk=blk[:stats[2]], lcol=lcol)
+        return out
 
     def get_coo_maps(self, stream=None):
         info = self.get_info()

@@ -33,7 +33,8 @@ def check_against_oracle(orc, ref, res, ores, b, rtol, lam_min):
 
 
 @pytest.mark.parametrize("variant,blocks,vblocks", [(0, 0, 0), (1, 0, 0), (2, 37, 5),
-                                                    (1, 2048, 3000), (3, 0, 0), (3, 37, 5)])
+                                                    (1, 2048, 3000), (3, 0, 0), (3, 37, 5),
+                                                    (4, 0, 0), (4, 37, 5)])
 def test_config1_single_reduction(orc, variant, blocks, vblocks):
     spx = require_gpu()
     prob, _, b = W.config1()

@@ -41,7 +41,7 @@ def test_matmult_every_lane_count(orc, lanes):
 
 
 @pytest.mark.parametrize("variant,rows", [(1, 0), (2, 32), (2, 64), (2, 128), (2, 256), (3, 0),
-                                          (3, 32), (3, 64)])
+                                          (3, 32), (3, 64), (4, 0)])
 @pytest.mark.parametrize("case", ["q1_3d", "random", "config1"])
 def test_matmult_variants(orc, variant, rows, case):
     spx = require_gpu()
