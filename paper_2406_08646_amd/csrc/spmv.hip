@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kWinRows) void k_spmv_window(int64_t n, const int32
   const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   const int64_t r0 = b * kWinRows;
   const int64_t r1 = r0 + kWinRows < n ? r0 + kWinRows : n;
-  const double s = window_rows<kWinRows, double, double, double, NT>(
+  const double s = window_rows<kWinUProduct, kWinRows, double, double, double, NT>(
       rowptr, col, val, x, n, w, b, r0, r1, reinterpret_cast<double*>(smem));
   if (threadIdx.x < r1 - r0) y[r0 + threadIdx.x] = s;
 }
@@ -312,7 +312,7 @@ bool window_shape(const spx_matrix* h, const Csr& A, bool allow, SpmvShape& sh) 
     sh.variant = kVariantWindow;
     sh.rows = kWinRows;
     sh.tile = A.win.max_blocks * kWinBlock;
-    sh.lds = window_lds_bytes(A.win.max_blocks, sizeof(double));
+    sh.lds = window_lds_bytes(A.win.max_blocks, sizeof(double), kWinUSolver);  // solver kernels
     return true;
   }
   return false;
@@ -436,11 +436,12 @@ int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, i
   if (A.n == 0) return SPX_OK;
   if (sh.variant == kVariantWindow) {
     const int64_t nb = ceil_div(A.n, kWinRows);
+    const size_t lds = window_lds_bytes(A.win.max_blocks, sizeof(double), kWinUProduct);
     if (sh.nt)
-      hipLaunchKernelGGL(k_spmv_window<true>, dim3((unsigned)nb), dim3(kWinRows), sh.lds, s, A.n,
+      hipLaunchKernelGGL(k_spmv_window<true>, dim3((unsigned)nb), dim3(kWinRows), lds, s, A.n,
                          A.rowptr, A.col, A.val, x, y, win_view(A), remap);
     else
-      hipLaunchKernelGGL(k_spmv_window<false>, dim3((unsigned)nb), dim3(kWinRows), sh.lds, s, A.n,
+      hipLaunchKernelGGL(k_spmv_window<false>, dim3((unsigned)nb), dim3(kWinRows), lds, s, A.n,
                          A.rowptr, A.col, A.val, x, y, win_view(A), remap);
     return SPX_OK;
   }

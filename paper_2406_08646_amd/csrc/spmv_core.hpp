@@ -257,8 +257,11 @@ __host__ __device__ inline size_t dma_buffer_bytes(int64_t tile, size_t vbytes) 
 }
 
 // -------------------------------------------------------------- window walk
-// Entries per thread of one chunk of the window walk.
-constexpr int kWinU = 3;
+// Entries per thread of one chunk of the window walk: 3 in the solver
+// kernels, whose persistent grids need 8 workgroups per CU to fit (18.4 KB of
+// LDS on the 27-point operator), 4 in the one-shot product kernel.
+constexpr int kWinUSolver = 3;
+constexpr int kWinUProduct = 4;
 
 template <typename T>
 struct Vec16;
@@ -302,13 +305,12 @@ __device__ __forceinline__ void load_window(const XT* __restrict__ x, int64_t n,
 // through the 16-bit window columns `cidx`; otherwise straight from memory
 // through the 32-bit columns.  Thread i owns the row whose entries are
 // [ra, re) relative to the tile's first entry t0.
-template <bool WIN, int BLOCK, typename VT, typename XT, typename ACC, bool NT, typename CT>
+template <bool WIN, int U, int BLOCK, typename VT, typename XT, typename ACC, bool NT, typename CT>
 __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const VT* __restrict__ val,
                                              const XT* __restrict__ x, int64_t n,
                                              const int32_t* __restrict__ blk, int32_t k0,
                                              int32_t nbk, int32_t t0, int32_t cnt, int32_t ra,
                                              int32_t re, ACC* prod) {
-  constexpr int U = kWinU;
   constexpr int32_t C = BLOCK * U;
   XT* xs = reinterpret_cast<XT*>(prod + C);
   const int tid = threadIdx.x;
@@ -359,17 +361,17 @@ __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const 
 
 // One tile of the window walk: tile number `tile` covers rows [r0, r1)
 // (r1 - r0 <= kWinRows == BLOCK) and thread i owns row r0 + i.  The tile's
-// entries are taken in chunks of BLOCK * kWinU: the chunk's products
+// entries are taken in chunks of BLOCK * U: the chunk's products
 // val[t] * x[col[t]] go to prod (x read from the tile's window, staged in
 // LDS behind prod, or directly from memory for a tile without a window),
 // then every thread adds its own row's products of the chunk in entry
 // order, carrying its sum from chunk to chunk.  Each row's sum is thus
 // formed in exactly the order of stream_rows, with LDS use independent of
 // the tile's length.  The next chunk's values and columns are loaded before
-// the current chunk's sums.  LDS: BLOCK * kWinU ACC products, then the
+// the current chunk's sums.  LDS: BLOCK * U ACC products, then the
 // largest window's x entries.  Returns the row sum in its owner thread and
 // leaves the workgroup synchronised.
-template <int BLOCK, typename VT, typename XT, typename ACC, bool NT>
+template <int U, int BLOCK, typename VT, typename XT, typename ACC, bool NT>
 __device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
                                            const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const XT* __restrict__ x,
@@ -383,15 +385,16 @@ __device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
   const int32_t ra = own ? rowptr[r0 + tid] - t0 : 0;
   const int32_t re = own ? rowptr[r0 + tid + 1] - t0 : 0;
   if (nbk > 0)
-    return window_chunks<true, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0, cnt,
-                                                       ra, re, prod);
-  return window_chunks<false, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, cnt, ra,
-                                                      re, prod);
+    return window_chunks<true, U, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0,
+                                                          cnt, ra, re, prod);
+  return window_chunks<false, U, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, cnt,
+                                                         ra, re, prod);
 }
 
-// LDS bytes of the window walk for elements of `bytes` bytes.
-__host__ __device__ inline size_t window_lds_bytes(int64_t max_blocks, size_t bytes) {
-  return ((size_t)kWinRows * kWinU + (size_t)max_blocks * kWinBlock) * bytes;
+// LDS bytes of the window walk with chunks of kWinRows * U entries, for
+// elements of `bytes` bytes.
+__host__ __device__ inline size_t window_lds_bytes(int64_t max_blocks, size_t bytes, int U) {
+  return ((size_t)kWinRows * U + (size_t)max_blocks * kWinBlock) * bytes;
 }
 
 }  // namespace spx
