@@ -224,12 +224,17 @@ __global__ __launch_bounds__(256) void k_max_row(const int32_t* __restrict__ row
 
 // Tiled numeric stage: a workgroup owns kSvEntries consecutive entries.
 // Their contributions form one contiguous run of perm, which the workgroup
-// reads coalesced while gathering v into LDS; then each thread adds its
-// entry's contributions from LDS in order, from +0.0 (bitwise the same sums
-// as one thread walking perm).  A tile whose run exceeds the LDS capacity
-// is summed straight from global memory.
-constexpr int kSvEntries = 256;
-constexpr int kSvCap = 4096;
+// reads coalesced while gathering v into LDS, kSvBatch values per thread at
+// a time with all of a batch's gathers in flight before any is stored; then
+// each thread adds its entries' contributions from LDS in order, from +0.0
+// (bitwise the same sums as one thread walking perm).  The gather is bound
+// by latency, not bytes, so the batches and a small LDS footprint (more
+// workgroups per CU) are what set the rate.  A tile whose run exceeds kSvCap
+// values is summed straight from memory, each thread issuing up to kSvBatch
+// gathers of its own run before adding them in order.
+constexpr int kSvEntries = 512;
+constexpr int kSvBatch = 4;
+constexpr int kSvCap = 2048;
 
 __global__ __launch_bounds__(256) void k_set_values_tiled(const int32_t* __restrict__ jmap,
                                                           const int32_t* __restrict__ perm,
@@ -240,18 +245,40 @@ __global__ __launch_bounds__(256) void k_set_values_tiled(const int32_t* __restr
   const int64_t e0 = (int64_t)blockIdx.x * kSvEntries;
   const int64_t e1 = e0 + kSvEntries < nnz ? e0 + kSvEntries : nnz;
   const int32_t q0 = jmap[e0], q1 = jmap[e1];
-  const int64_t t = e0 + threadIdx.x;
   if (q1 - q0 > kSvCap) {
-    if (t < e1) {
+    for (int64_t t = e0 + threadIdx.x; t < e1; t += 256) {
+      const int32_t qe = jmap[t + 1];
       double s = 0.0;
-      for (int32_t q = jmap[t]; q < jmap[t + 1]; ++q) s += v[perm[q]];
+      for (int32_t q = jmap[t]; q < qe; q += kSvBatch) {
+        double x[kSvBatch];
+#pragma unroll
+        for (int k = 0; k < kSvBatch; ++k) x[k] = q + k < qe ? v[perm[q + k]] : 0.0;
+#pragma unroll
+        for (int k = 0; k < kSvBatch; ++k)
+          if (q + k < qe) s += x[k];
+      }
       val[t] = mode ? val[t] + s : s;
     }
     return;
   }
-  for (int32_t q = q0 + threadIdx.x; q < q1; q += 256) lv[q - q0] = v[perm[q]];
+  for (int32_t base = q0; base < q1; base += 256 * kSvBatch) {
+    int32_t p[kSvBatch];
+#pragma unroll
+    for (int k = 0; k < kSvBatch; ++k) {
+      const int32_t q = base + k * 256 + (int32_t)threadIdx.x;
+      p[k] = q < q1 ? perm[q] : -1;
+    }
+    double x[kSvBatch];
+#pragma unroll
+    for (int k = 0; k < kSvBatch; ++k) x[k] = p[k] >= 0 ? v[p[k]] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kSvBatch; ++k) {
+      const int32_t q = base + k * 256 + (int32_t)threadIdx.x;
+      if (q < q1) lv[q - q0] = x[k];
+    }
+  }
   __syncthreads();
-  if (t < e1) {
+  for (int64_t t = e0 + threadIdx.x; t < e1; t += 256) {
     double s = 0.0;
     for (int32_t q = jmap[t]; q < jmap[t + 1]; ++q) s += lv[q - q0];
     val[t] = mode ? val[t] + s : s;
