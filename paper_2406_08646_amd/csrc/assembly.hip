@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_max_row(const int32_t* __restrict__ row
   if (threadIdx.x == 0) atomicMax(out, max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])));
 }
 
-// Tiled numeric stage: a workgroup owns kSvEntries consecutive entries.
+// Tiled numeric stage: a workgroup owns `ents` consecutive entries.
 // Their contributions form one contiguous run of perm, which the workgroup
 // reads coalesced while gathering v into LDS, kSvBatch values per thread at
 // a time with all of a batch's gathers in flight before any is stored; then
@@ -232,18 +232,26 @@ __global__ __launch_bounds__(256) void k_max_row(const int32_t* __restrict__ row
 // workgroups per CU) are what set the rate.  A tile whose run exceeds kSvCap
 // values is summed straight from memory, each thread issuing up to kSvBatch
 // gathers of its own run before adding them in order.
-constexpr int kSvEntries = 512;
 constexpr int kSvBatch = 4;
 constexpr int kSvCap = 2048;
+
+// Entries per workgroup: the largest of 512, 256 and 128 whose tiles
+// typically (1.5x the mean contributions per entry) fit in kSvCap values.
+int sv_entries(int64_t nvalid, int64_t nnz) {
+  const double per = nnz > 0 ? (double)nvalid / (double)nnz : 0.0;
+  for (int e : {512, 256, 128})
+    if (1.5 * per * e <= kSvCap) return e;
+  return 64;
+}
 
 __global__ __launch_bounds__(256) void k_set_values_tiled(const int32_t* __restrict__ jmap,
                                                           const int32_t* __restrict__ perm,
                                                           const double* __restrict__ v,
-                                                          int64_t nnz, int mode,
+                                                          int64_t nnz, int mode, int ents,
                                                           double* __restrict__ val) {
   __shared__ double lv[kSvCap];
-  const int64_t e0 = (int64_t)blockIdx.x * kSvEntries;
-  const int64_t e1 = e0 + kSvEntries < nnz ? e0 + kSvEntries : nnz;
+  const int64_t e0 = (int64_t)blockIdx.x * ents;
+  const int64_t e1 = e0 + ents < nnz ? e0 + ents : nnz;
   const int32_t q0 = jmap[e0], q1 = jmap[e1];
   if (q1 - q0 > kSvCap) {
     for (int64_t t = e0 + threadIdx.x; t < e1; t += 256) {
@@ -601,9 +609,11 @@ extern "C" int spx_set_values_coo(spx_handle h, const double* v, int mode, void*
   if (h->nvalid > 0 && !v) return set_error(SPX_INVALID_ARG, "set_values_coo: v is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t nnz = h->A.nnz;
-  if (nnz > 0)
-    hipLaunchKernelGGL(k_set_values_tiled, dim3(grid_for(nnz, kSvEntries)), dim3(256), 0, s,
-                       h->jmap, h->perm, v, nnz, mode, h->A.val);
+  if (nnz > 0) {
+    const int ents = sv_entries(h->nvalid, nnz);
+    hipLaunchKernelGGL(k_set_values_tiled, dim3(grid_for(nnz, ents)), dim3(256), 0, s, h->jmap,
+                       h->perm, v, nnz, mode, ents, h->A.val);
+  }
   h->valT_fresh = false;
   h->val32_fresh = false;
   h->valT32_fresh = false;

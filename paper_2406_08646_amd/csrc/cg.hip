@@ -661,8 +661,9 @@ size_t shape_lds(const SpmvShape& sh) {
     case kVariantDma:
       return 2 * ((dma_buffer_bytes(sh.tile, sizeof(VT)) + 15) & ~size_t(15));
     case kVariantStream:
-    case kVariantWindow:
       return sh.lds / sizeof(double) * sizeof(VT);
+    case kVariantWindow:
+      return window_lds_bytes(sh.tile / kWinBlock, sizeof(VT), win_u_solver<VT>());
     default:
       return 0;  // the vector walk uses none
   }

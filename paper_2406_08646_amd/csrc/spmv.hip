@@ -312,7 +312,8 @@ bool window_shape(const spx_matrix* h, const Csr& A, bool allow, SpmvShape& sh) 
     sh.variant = kVariantWindow;
     sh.rows = kWinRows;
     sh.tile = A.win.max_blocks * kWinBlock;
-    sh.lds = window_lds_bytes(A.win.max_blocks, sizeof(double), kWinUSolver);  // solver kernels
+    // the fp64 solver kernels' LDS (the fp32 ones compute theirs from tile)
+    sh.lds = window_lds_bytes(A.win.max_blocks, sizeof(double), win_u_solver<double>());
     return true;
   }
   return false;
