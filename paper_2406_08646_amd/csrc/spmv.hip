@@ -193,6 +193,82 @@ __global__ __launch_bounds__(BLOCK) void k_spmm(int64_t n, const int32_t* __rest
   }
 }
 
+// The same product with each lane owning a pair of right-hand sides (c, c+1)
+// read with one 16-byte load per entry, so a row of X takes G/2 lanes and a
+// wave covers twice the rows per gather.  Needs X and Y 16-byte aligned and
+// ldx, ldy even; an odd last column is read on its own.  Each column is
+// accumulated in entry order exactly as in k_spmm, so the results are the
+// same bits.  FULL: nrhs == ldx == ldy == 2 G (contiguous blocks, one pass,
+// compile-time strides).
+template <int G, int BLOCK, bool FULL>
+__global__ __launch_bounds__(BLOCK) void k_spmm_pairs(int64_t n, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val, int64_t nrhs,
+                                                      const double* __restrict__ X, int64_t ldx,
+                                                      double* __restrict__ Y, int64_t ldy, int remap) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  constexpr int RPB = BLOCK / G;
+  constexpr int U = 8;  // independent gathers in flight per lane
+  const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t row = b * RPB + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  if constexpr (FULL) {
+    ldx = ldy = nrhs = 2 * G;
+  }
+  const int32_t t0 = rowptr[row], t1 = rowptr[row + 1];
+  for (int64_t c0 = 0; c0 < nrhs; c0 += 2 * G) {
+    const int64_t c = c0 + 2 * lane;
+    if (c >= nrhs) continue;
+    if (FULL || c + 1 < nrhs) {
+      d2 acc = {0.0, 0.0};
+      int32_t t = t0;
+      for (; t + U <= t1; t += U) {
+        double a[U];
+        int64_t cc[U];
+        d2 xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a[u] = stream_load(val + t + u);
+          cc[u] = stream_load(col + t + u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = *reinterpret_cast<const d2*>(X + cc[u] * ldx + c);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          acc.x += a[u] * xv[u].x;
+          acc.y += a[u] * xv[u].y;
+        }
+      }
+      for (; t < t1; ++t) {
+        const double a = stream_load(val + t);
+        const d2 xv = *reinterpret_cast<const d2*>(X + (int64_t)stream_load(col + t) * ldx + c);
+        acc.x += a * xv.x;
+        acc.y += a * xv.y;
+      }
+      *reinterpret_cast<d2*>(Y + row * ldy + c) = acc;
+    } else {
+      double acc = 0.0;
+      int32_t t = t0;
+      for (; t + U <= t1; t += U) {
+        double a[U], xv[U];
+        int64_t cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a[u] = stream_load(val + t + u);
+          cc[u] = stream_load(col + t + u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = X[cc[u] * ldx + c];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += a[u] * xv[u];
+      }
+      for (; t < t1; ++t) acc += stream_load(val + t) * X[(int64_t)stream_load(col + t) * ldx + c];
+      Y[row * ldy + c] = acc;
+    }
+  }
+}
+
 // Bandwidth references: the whole grid sweeps the array in lockstep, one
 // 16-byte non-temporal access per lane per step (measured to be the
 // pattern HBM serves best on this chip).
@@ -252,6 +328,19 @@ template <int G>
 int launch_spmm_g(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y,
                   int64_t ldy, hipStream_t s) {
   constexpr int BLOCK = 256;
+  const bool pairs = G >= 2 && ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) &
+                                15) == 0 && ldx % 2 == 0 && ldy % 2 == 0;
+  if (pairs) {
+    constexpr int GP = G >= 2 ? G / 2 : 1;  // a lane per pair of columns
+    const int64_t nb = ceil_div(A.n, BLOCK / GP);
+    if (nrhs == G && ldx == G && ldy == G)
+      hipLaunchKernelGGL((k_spmm_pairs<GP, BLOCK, true>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n,
+                         A.rowptr, A.col, A.val, nrhs, X, ldx, Y, ldy, 1);
+    else
+      hipLaunchKernelGGL((k_spmm_pairs<GP, BLOCK, false>), dim3((unsigned)nb), dim3(BLOCK), 0, s,
+                         A.n, A.rowptr, A.col, A.val, nrhs, X, ldx, Y, ldy, 1);
+    return SPX_OK;
+  }
   constexpr int RPB = BLOCK / G;
   const int64_t nb = ceil_div(A.n, RPB);
   hipLaunchKernelGGL((k_spmm<G, BLOCK>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n, A.rowptr,

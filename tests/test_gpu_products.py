@@ -118,6 +118,39 @@ def test_spmm_matches_oracle(orc):
             spmv_within(Y[:, c], Yr[:, c], orc.abs_spmv(ref, X[:, c]))
 
 
+def test_spmm_layouts_bitwise(orc):
+    """Through the C ABI with explicit leading dimensions: the paired-column
+    kernel (16-byte aligned X and Y, even ld; an odd last column on its own)
+    and the one-column-per-lane kernel (8-byte aligned X) give the same bits,
+    within the SpMV tolerance of the oracle."""
+    import ctypes
+    spx = require_gpu()
+    lib = spx.load_library()
+    rng = np.random.default_rng(34)
+    prob = W.random_coo(rng, 5003, 90000, extreme=False)
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    n = prob.n
+    for nrhs in (1, 7, 16):
+        Xh = rng.uniform(-1, 1, (n, nrhs))
+        ld = nrhs + 1 if nrhs % 2 else nrhs + 2  # even, padded rows
+        Xa = torch.zeros(n * ld + 2, dtype=torch.float64, device="cuda")
+        Xa[: n * ld].view(n, ld)[:, :nrhs] = dev(Xh)
+        Xu = torch.zeros(n * ld + 2, dtype=torch.float64, device="cuda")  # starts 8 bytes in
+        Xu[1: 1 + n * ld].view(n, ld)[:, :nrhs] = dev(Xh)
+        outs = []
+        for X, ldx, ptr in ((Xa, ld, Xa.data_ptr()), (Xu, ld, Xu.data_ptr() + 8)):
+            Y = torch.full((n * ld + 2,), np.nan, dtype=torch.float64, device="cuda")
+            rc = lib.spx_spmm(A.handle, nrhs, ctypes.c_void_p(ptr), ldx, ctypes.c_void_p(Y.data_ptr()),
+                              ld, None)
+            assert rc == 0
+            outs.append(host(Y[: n * ld].view(n, ld)[:, :nrhs]))
+        assert np.array_equal(bits(outs[0]), bits(outs[1]))
+        Yr = orc.spmm(ref, Xh)
+        for c in range(nrhs):
+            spmv_within(outs[0][:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
+
+
 def test_sddmm_and_gather_bitwise(orc):
     spx = require_gpu()
     rng = np.random.default_rng(32)
