@@ -243,6 +243,10 @@ def test_full_size_pipeline_sampled(orc, N):
         scale = float(np.sum(np.abs(v) * np.abs(x[c])))
         assert abs(y[r] - ref) <= 1e-12 * scale + 1e-300
         assert abs(yt[r] - ref) <= 1e-12 * scale + 1e-300  # symmetric operator
+        if A.get_option(spx.OPT_SPMV_VARIANT) in (2, 4):
+            # the stream and window walks round each product and add them in
+            # row order, as this loop does
+            assert y[r] == ref
     print("sampled SpMV rows within 1e-12", flush=True)
     res = A.cg_solve(dev(b), rtol=1e-10, check_every=20)
     xs = host(res.x)
@@ -251,7 +255,8 @@ def test_full_size_pipeline_sampled(orc, N):
     assert res.status == 0 and res.relres <= 1e-10 * 1.001 and rel <= 1e-10 * 1.01
 
 
-def test_graph_replay_is_bitwise_the_eager_solve():
+@pytest.mark.parametrize("variant", [0, 4])  # default walk, window walk
+def test_graph_replay_is_bitwise_the_eager_solve(variant):
     """Each full poll chunk replayed as one HIP graph: same kernels, same
     arithmetic.  Several solves (each replays the graph many times) with eager
     work and synchronisation between them, every one against the eager
@@ -262,6 +267,7 @@ def test_graph_replay_is_bitwise_the_eager_solve():
     prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(8).standard_normal(N**3)))
     A = assemble(spx, prob)
     A.set_option(spx.OPT_SMALL_SOLVE, 0)  # compare the graph with the same multi-workgroup kernels
+    A.set_option(spx.OPT_SPMV_VARIANT, variant)
     b = dev(np.random.default_rng(9).uniform(-1, 1, prob.n))
     eager = A.cg_solve(b, rtol=1e-10, check_every=7)
     eager_t = A.cg_solve_transpose(b, rtol=1e-10, check_every=7)
