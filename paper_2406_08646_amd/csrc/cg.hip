@@ -663,7 +663,7 @@ size_t shape_lds(const SpmvShape& sh) {
     case kVariantStream:
       return sh.lds / sizeof(double) * sizeof(VT);
     case kVariantWindow:
-      return window_lds_bytes(sh.tile / kWinBlock, sizeof(VT), win_u_solver<VT>());
+      return window_lds_bytes(sh.tile / kWinBlock, sizeof(VT), win_u_solver<VT>() * win_v<VT>());
     default:
       return 0;  // the vector walk uses none
   }

@@ -225,7 +225,7 @@ __device__ __forceinline__ void for_rows(int64_t n, const int32_t* __restrict__ 
     for (int64_t rb = sh.first; rb < sh.end; rb += sh.step) {
       const int64_t r0 = rb * kWinRows;
       const int64_t r1 = r0 + kWinRows < n ? r0 + kWinRows : n;
-      const ACC s = window_rows<win_u_solver<VT>(), kBlock, VT, XT, ACC, SH::nt>(
+      const ACC s = window_rows<win_u_solver<VT>(), win_v<VT>(), kBlock, VT, XT, ACC, SH::nt>(
           rowptr, col, val, x, n, win, rb, r0, r1, prod);
       if (threadIdx.x < r1 - r0) epi(r0 + threadIdx.x, s);
     }

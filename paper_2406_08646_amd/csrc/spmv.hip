@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kWinRows) void k_spmv_window(int64_t n, const int32
   const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   const int64_t r0 = b * kWinRows;
   const int64_t r1 = r0 + kWinRows < n ? r0 + kWinRows : n;
-  const double s = window_rows<kWinUProduct, kWinRows, double, double, double, NT>(
+  const double s = window_rows<kWinUProduct, win_v<double>(), kWinRows, double, double, double, NT>(
       rowptr, col, val, x, n, w, b, r0, r1, reinterpret_cast<double*>(smem));
   if (threadIdx.x < r1 - r0) y[r0 + threadIdx.x] = s;
 }
@@ -402,7 +402,8 @@ bool window_shape(const spx_matrix* h, const Csr& A, bool allow, SpmvShape& sh) 
     sh.rows = kWinRows;
     sh.tile = A.win.max_blocks * kWinBlock;
     // the fp64 solver kernels' LDS (the fp32 ones compute theirs from tile)
-    sh.lds = window_lds_bytes(A.win.max_blocks, sizeof(double), win_u_solver<double>());
+    sh.lds = window_lds_bytes(A.win.max_blocks, sizeof(double),
+                              win_u_solver<double>() * win_v<double>());
     return true;
   }
   return false;
@@ -526,7 +527,8 @@ int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, i
   if (A.n == 0) return SPX_OK;
   if (sh.variant == kVariantWindow) {
     const int64_t nb = ceil_div(A.n, kWinRows);
-    const size_t lds = window_lds_bytes(A.win.max_blocks, sizeof(double), kWinUProduct);
+    const size_t lds =
+        window_lds_bytes(A.win.max_blocks, sizeof(double), kWinUProduct * win_v<double>());
     if (sh.nt)
       hipLaunchKernelGGL(k_spmv_window<true>, dim3((unsigned)nb), dim3(kWinRows), lds, s, A.n,
                          A.rowptr, A.col, A.val, x, y, win_view(A), remap);

@@ -257,17 +257,20 @@ __host__ __device__ inline size_t dma_buffer_bytes(int64_t tile, size_t vbytes) 
 }
 
 // -------------------------------------------------------------- window walk
-// Each thread takes kWinV consecutive entries per step (one vector load of
-// values, one of columns) and U steps per chunk: in the fp64 solver kernels
-// U = 1, since their persistent grids need 8 workgroups per CU to fit (16 KB
-// of LDS on the 27-point operator); fp32 entries are smaller, so the fp32
-// solver kernels take U = 4 to keep enough bytes in flight (14 KB); the
-// one-shot fp64 product kernel takes U = 2.
-constexpr int kWinV = 2;
+// Each thread takes V consecutive entries per step (one vector load of
+// values, one of columns) and U steps per chunk.  fp64: V = 2 (16-byte
+// value loads); the solver kernels take U = 1, since their persistent grids
+// need 8 workgroups per CU to fit (16 KB of LDS on the 27-point operator),
+// the one-shot product kernel U = 2.  fp32: V = 4 (16-byte value loads),
+// U = 2 in the solver kernels (14 KB).
 constexpr int kWinUProduct = 2;
 template <typename VT>
+__host__ __device__ constexpr int win_v() {
+  return sizeof(VT) == 8 ? 2 : 4;
+}
+template <typename VT>
 __host__ __device__ constexpr int win_u_solver() {
-  return sizeof(VT) == 8 ? 1 : 4;
+  return sizeof(VT) == 8 ? 1 : 2;
 }
 
 template <typename T>
@@ -281,30 +284,11 @@ struct Vec16<float> {
   typedef float type __attribute__((ext_vector_type(4)));
 };
 
-// Two consecutive values / column indices in one load.
-template <typename T>
-struct Pair;
-template <>
-struct Pair<double> {
-  typedef double type __attribute__((ext_vector_type(2)));
+// V consecutive values or column indices in one load.
+template <typename T, int V>
+struct VecN {
+  typedef T type __attribute__((ext_vector_type(V)));
 };
-template <>
-struct Pair<float> {
-  typedef float type __attribute__((ext_vector_type(2)));
-};
-template <>
-struct Pair<uint16_t> {
-  typedef uint32_t type;
-};
-template <>
-struct Pair<int32_t> {
-  typedef uint64_t type;
-};
-template <typename CT>
-__device__ __forceinline__ int32_t pair_index(typename Pair<CT>::type c, int j) {
-  constexpr int bits = 8 * sizeof(CT);
-  return (int32_t)((c >> (bits * j)) & ((typename Pair<CT>::type(1) << bits) - 1));
-}
 
 // Copies blocks blk[k0 .. k0 + nbk) of x (n entries; entries at n and
 // beyond read as 0) into xs, block i at xs + i * kWinBlock, with 16-byte
@@ -335,33 +319,32 @@ __device__ __forceinline__ void load_window(const XT* __restrict__ x, int64_t n,
 // tile's window (blocks blk[k0 .. k0 + nbk), staged into xs before the
 // first barrier while the first chunk's values and indices are in flight)
 // through the 16-bit window columns `cidx`; otherwise straight from memory
-// through the 32-bit columns.  The entries are walked in pairs from the
-// even entry at or below the tile's first, t0; pair members outside
+// through the 32-bit columns.  The entries are walked V at a time from the
+// multiple of V at or below the tile's first entry t0; members outside
 // [t0, t1) are loaded (the arrays carry tail padding) but never used.
-// Thread i owns the row whose entries are [ra, re) relative to that even
-// entry ta.
-template <bool WIN, int U, int BLOCK, typename VT, typename XT, typename ACC, bool NT, typename CT>
+// Thread i owns the row whose entries are [ra, re) relative to that entry ta.
+template <bool WIN, int U, int V, int BLOCK, typename VT, typename XT, typename ACC, bool NT,
+          typename CT>
 __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const VT* __restrict__ val,
                                              const XT* __restrict__ x, int64_t n,
                                              const int32_t* __restrict__ blk, int32_t k0,
                                              int32_t nbk, int32_t t0, int32_t t1, int32_t ra,
                                              int32_t re, ACC* prod) {
-  static_assert(kWinV == 2, "the walk takes entries in pairs");
-  constexpr int32_t C = BLOCK * U * kWinV;
-  typedef typename Pair<VT>::type VP;
-  typedef typename Pair<CT>::type CP;
+  constexpr int32_t C = BLOCK * U * V;
+  typedef typename VecN<VT, V>::type VV;
+  typedef typename VecN<CT, V>::type CV;
   XT* xs = reinterpret_cast<XT*>(prod + C);
   const int tid = threadIdx.x;
-  const int32_t ta = t0 & ~(kWinV - 1);
+  const int32_t ta = t0 & ~(V - 1);
   const int32_t cnt = t1 - ta, skip = t0 - ta;
-  VP a[U];
-  CP c[U];
+  VV a[U];
+  CV c[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int32_t e = (u * BLOCK + tid) * kWinV;
+    const int32_t e = (u * BLOCK + tid) * V;
     if (e < cnt) {
-      a[u] = mload<NT>(reinterpret_cast<const VP*>(val + ta + e));
-      c[u] = mload<NT>(reinterpret_cast<const CP*>(cidx + ta + e));
+      a[u] = mload<NT>(reinterpret_cast<const VV*>(val + ta + e));
+      c[u] = mload<NT>(reinterpret_cast<const CV*>(cidx + ta + e));
     }
   }
   if constexpr (WIN) load_window<BLOCK, XT>(x, n, blk, k0, nbk, xs);
@@ -370,17 +353,17 @@ __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const 
   for (int32_t base = 0; base < cnt; base += C) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int32_t e = base + (u * BLOCK + tid) * kWinV;
+      const int32_t e = base + (u * BLOCK + tid) * V;
 #pragma unroll
-      for (int j = 0; j < kWinV; ++j) {
+      for (int j = 0; j < V; ++j) {
         if (e + j >= skip && e + j < cnt) {
-          const int32_t cj = pair_index<CT>(c[u], j);
+          const int32_t cj = (int32_t)c[u][j];
           XT xv;
           if constexpr (WIN)
             xv = xs[cj];
           else
             xv = x[cj];
-          prod[(u * BLOCK + tid) * kWinV + j] = (ACC)a[u][j] * (ACC)xv;
+          prod[(u * BLOCK + tid) * V + j] = (ACC)a[u][j] * (ACC)xv;
         }
       }
     }
@@ -388,10 +371,10 @@ __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const 
     if (next < cnt) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int32_t e = next + (u * BLOCK + tid) * kWinV;
+        const int32_t e = next + (u * BLOCK + tid) * V;
         if (e < cnt) {
-          a[u] = mload<NT>(reinterpret_cast<const VP*>(val + ta + e));
-          c[u] = mload<NT>(reinterpret_cast<const CP*>(cidx + ta + e));
+          a[u] = mload<NT>(reinterpret_cast<const VV*>(val + ta + e));
+          c[u] = mload<NT>(reinterpret_cast<const CV*>(cidx + ta + e));
         }
       }
     }
@@ -405,17 +388,17 @@ __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const 
 
 // One tile of the window walk: tile number `tile` covers rows [r0, r1)
 // (r1 - r0 <= kWinRows == BLOCK) and thread i owns row r0 + i.  The tile's
-// entries are taken in chunks of BLOCK * U * kWinV: the chunk's products
+// entries are taken in chunks of BLOCK * U * V: the chunk's products
 // val[t] * x[col[t]] go to prod (x read from the tile's window, staged in
 // LDS behind prod, or directly from memory for a tile without a window),
 // then every thread adds its own row's products of the chunk in entry
 // order, carrying its sum from chunk to chunk.  Each row's sum is thus
 // formed in exactly the order of stream_rows, with LDS use independent of
 // the tile's length.  The next chunk's values and columns are loaded before
-// the current chunk's sums.  LDS: BLOCK * U * kWinV ACC products, then the
+// the current chunk's sums.  LDS: BLOCK * U * V ACC products, then the
 // largest window's x entries.  Returns the row sum in its owner thread and
 // leaves the workgroup synchronised.
-template <int U, int BLOCK, typename VT, typename XT, typename ACC, bool NT>
+template <int U, int V, int BLOCK, typename VT, typename XT, typename ACC, bool NT>
 __device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
                                            const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const XT* __restrict__ x,
@@ -424,22 +407,23 @@ __device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
   static_assert(BLOCK == kWinRows, "one thread per row of a window tile");
   const int tid = threadIdx.x;
   const int32_t t0 = rowptr[r0], t1 = rowptr[r1];
-  const int32_t ta = t0 & ~(kWinV - 1);
+  const int32_t ta = t0 & ~(V - 1);
   const int32_t k0 = w.ptr[tile], nbk = w.ptr[tile + 1] - k0;
   const bool own = tid < r1 - r0;
   const int32_t ra = own ? rowptr[r0 + tid] - ta : 0;
   const int32_t re = own ? rowptr[r0 + tid + 1] - ta : 0;
   if (nbk > 0)
-    return window_chunks<true, U, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0, t1,
-                                                          ra, re, prod);
-  return window_chunks<false, U, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, t1, ra,
-                                                         re, prod);
+    return window_chunks<true, U, V, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0,
+                                                             t1, ra, re, prod);
+  return window_chunks<false, U, V, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, t1,
+                                                            ra, re, prod);
 }
 
-// LDS bytes of the window walk with chunks of kWinRows * U * kWinV entries,
-// for elements of `bytes` bytes.
-__host__ __device__ inline size_t window_lds_bytes(int64_t max_blocks, size_t bytes, int U) {
-  return ((size_t)kWinRows * U * kWinV + (size_t)max_blocks * kWinBlock) * bytes;
+// LDS bytes of the window walk with chunks of kWinRows * per_thread
+// entries, for elements of `bytes` bytes.
+__host__ __device__ inline size_t window_lds_bytes(int64_t max_blocks, size_t bytes,
+                                                   int per_thread) {
+  return ((size_t)kWinRows * per_thread + (size_t)max_blocks * kWinBlock) * bytes;
 }
 
 }  // namespace spx
