@@ -47,8 +47,34 @@ using namespace solver;
 
 constexpr int kMaxHistory = 64;
 constexpr int kLB = 256;
-constexpr int kJB = 8;      // columns per accumulator chunk
+constexpr int kJB = 8;      // columns per unrolled step of the row passes
+constexpr int kJT = 16;     // columns per accumulator chunk of the transposed products
 constexpr int kFused = 16;  // up to this many pairs, a and Y^T a share one pass
+
+// Rows are walked V at a time (V = 2: 16-byte loads of every column and
+// vector, taken when n is even and the caller's vectors are 16-byte
+// aligned; otherwise V = 1).
+template <int V>
+struct Vd;
+template <>
+struct Vd<1> {
+  typedef double type;
+};
+template <>
+struct Vd<2> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <int V>
+__device__ __forceinline__ typename Vd<V>::type ldv(const double* p) {
+  return *reinterpret_cast<const typename Vd<V>::type*>(p);
+}
+template <int V>
+__device__ __forceinline__ double el(const typename Vd<V>::type& v, int j) {
+  if constexpr (V == 1)
+    return v;
+  else
+    return v[j];
+}
 
 // The ring: logical pair b (oldest first) lives in slot start + b (mod m).
 struct Ring {
@@ -59,10 +85,12 @@ struct Ring {
   }
 };
 
-// Row range of workgroup b of G over n rows (contiguous, balanced).
+// Row range of workgroup b of G over n rows (contiguous, balanced), with
+// both ends multiples of V (n is a multiple of V).
+template <int V>
 __device__ __forceinline__ void rows_of(int64_t n, int b, int G, int64_t* lo, int64_t* hi) {
-  *lo = n * b / G;
-  *hi = n * (b + 1) / G;
+  *lo = (n * b / G) & ~(int64_t)(V - 1);
+  *hi = (n * (b + 1) / G) & ~(int64_t)(V - 1);
 }
 
 // Workgroup sums of the first cnt of NA per-thread accumulators; the totals
@@ -89,30 +117,37 @@ __device__ __forceinline__ void block_sums(const double (&acc)[NA], int cnt, dou
 
 // Partials of d_b = sum_i col_b[i] w[i] over the workgroup's rows, for the
 // ring's cnt columns, into P[(row0 + b) * G + workgroup].  Columns go in
-// chunks of kJB accumulators (each element of the history read once; w
+// chunks of kJT accumulators (each element of the history read once; w
 // re-read per chunk, from cache).
+template <int V>
 __device__ __forceinline__ void gemvt_partials(int64_t n, const double* __restrict__ base,
                                                Ring R, const double* __restrict__ w,
                                                double* __restrict__ P, int row0, double* lds,
                                                double* tot) {
+  typedef typename Vd<V>::type VD;
   int64_t lo, hi;
-  rows_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  for (int jb = 0; jb < R.cnt; jb += kJB) {
-    const int nc = R.cnt - jb < kJB ? R.cnt - jb : kJB;
-    const double* cp[kJB];
+  rows_of<V>(n, blockIdx.x, gridDim.x, &lo, &hi);
+  for (int jb = 0; jb < R.cnt; jb += kJT) {
+    const int nc = R.cnt - jb < kJT ? R.cnt - jb : kJT;
+    const double* cp[kJT];
 #pragma unroll
-    for (int u = 0; u < kJB; ++u) cp[u] = base + (u < nc ? R.slot(jb + u) : 0) * n;
-    double acc[kJB];
+    for (int u = 0; u < kJT; ++u) cp[u] = base + (u < nc ? R.slot(jb + u) : 0) * n;
+    double acc[kJT];
 #pragma unroll
-    for (int u = 0; u < kJB; ++u) acc[u] = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
-      const double wi = w[i];
+    for (int u = 0; u < kJT; ++u) acc[u] = 0.0;
+    for (int64_t i = lo + V * (int64_t)threadIdx.x; i < hi; i += V * kLB) {
+      const VD wv = ldv<V>(w + i);
 #pragma unroll
-      for (int u = 0; u < kJB; ++u)
-        if (u < nc) acc[u] += cp[u][i] * wi;
+      for (int u = 0; u < kJT; ++u)
+        if (u < nc) {
+          const VD c = ldv<V>(cp[u] + i);
+#pragma unroll
+          for (int j = 0; j < V; ++j) acc[u] += el<V>(c, j) * el<V>(wv, j);
+        }
     }
-    block_sums<kJB>(acc, nc, lds, tot);
-    if (threadIdx.x < nc) P[(int64_t)(row0 + jb + threadIdx.x) * gridDim.x + blockIdx.x] = tot[threadIdx.x];
+    block_sums<kJT>(acc, nc, lds, tot);
+    if (threadIdx.x < nc)
+      P[(int64_t)(row0 + jb + threadIdx.x) * gridDim.x + blockIdx.x] = tot[threadIdx.x];
   }
 }
 
@@ -127,16 +162,17 @@ __global__ void k_lb_put(int64_t n, const double* __restrict__ s, const double* 
 }
 
 // Partials of u_b = s_new . y_b (rows 0..cnt) and v_b = s_b . y_new (rows
-// kMaxHistory + b); the new pair is already in its slot (logical cnt - 1).
+// kMaxHistory + b); the new pair is already in its slot (logical cnt - 1),
+// which is where it is read from.
+template <int V>
 __global__ __launch_bounds__(kLB) void k_lb_update(int64_t n, const double* __restrict__ S,
-                                                   const double* __restrict__ Y,
-                                                   const double* __restrict__ s,
-                                                   const double* __restrict__ y, Ring R,
+                                                   const double* __restrict__ Y, Ring R,
                                                    double* __restrict__ P) {
-  __shared__ double lds[(kLB / 64) * kJB];
-  __shared__ double tot[kJB];
-  gemvt_partials(n, Y, R, s, P, 0, lds, tot);
-  gemvt_partials(n, S, R, y, P, kMaxHistory, lds, tot);
+  __shared__ double lds[(kLB / 64) * kJT];
+  __shared__ double tot[kJT];
+  const int64_t cur = R.slot(R.cnt - 1) * n;
+  gemvt_partials<V>(n, Y, R, S + cur, P, 0, lds, tot);
+  gemvt_partials<V>(n, S, R, Y + cur, P, kMaxHistory, lds, tot);
 }
 
 // one workgroup per (kind, logical index): SY row and column of the new slot
@@ -158,12 +194,13 @@ __global__ __launch_bounds__(kLB) void k_lb_update_finish(const double* __restri
 
 // ----------------------------------------------------------------- apply
 // pass 1: partials of q_b = s_b . g
+template <int V>
 __global__ __launch_bounds__(kLB) void k_lb_sg(int64_t n, const double* __restrict__ S, Ring R,
                                                const double* __restrict__ g,
                                                double* __restrict__ P) {
-  __shared__ double lds[(kLB / 64) * kJB];
-  __shared__ double tot[kJB];
-  gemvt_partials(n, S, R, g, P, 0, lds, tot);
+  __shared__ double lds[(kLB / 64) * kJT];
+  __shared__ double tot[kJT];
+  gemvt_partials<V>(n, S, R, g, P, 0, lds, tot);
 }
 
 // one workgroup per logical index: out[b] = sum of the G partials of b
@@ -181,7 +218,7 @@ __device__ __forceinline__ double rmat(const double* SY, const Ring& R, int a, i
 
 // pass 2: c = -R^-1 q (every workgroup; workgroup 0 stores it);
 // a = h0 (g + Y c); with FUSED, also the partials of f_b = y_b . a
-template <bool FUSED>
+template <bool FUSED, int V>
 __global__ __launch_bounds__(kLB) void k_lb_ya(int64_t n, const double* __restrict__ Y, Ring R,
                                                const double* __restrict__ g,
                                                const double* __restrict__ h0,
@@ -189,6 +226,7 @@ __global__ __launch_bounds__(kLB) void k_lb_ya(int64_t n, const double* __restri
                                                double* __restrict__ red,
                                                double* __restrict__ a_out,
                                                double* __restrict__ P) {
+  typedef typename Vd<V>::type VD;
   __shared__ double lds[(kLB / 64) * kFused];
   __shared__ double tot[kFused];
   __shared__ double cs[kMaxHistory];
@@ -205,7 +243,7 @@ __global__ __launch_bounds__(kLB) void k_lb_ya(int64_t n, const double* __restri
   }
   __syncthreads();
   int64_t lo, hi;
-  rows_of(n, blockIdx.x, gridDim.x, &lo, &hi);
+  rows_of<V>(n, blockIdx.x, gridDim.x, &lo, &hi);
   if constexpr (FUSED) {
     const double* cp[kFused];
     double c[kFused], f[kFused];
@@ -215,52 +253,58 @@ __global__ __launch_bounds__(kLB) void k_lb_ya(int64_t n, const double* __restri
       c[b] = b < cnt ? cs[b] : 0.0;
       f[b] = 0.0;
     }
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
-      double yv[kFused];
-      double t = g[i];
+    for (int64_t i = lo + V * (int64_t)threadIdx.x; i < hi; i += V * kLB) {
+      VD yv[kFused];
+      VD t = ldv<V>(g + i);
 #pragma unroll
       for (int b = 0; b < kFused; ++b)
         if (b < cnt) {
-          yv[b] = cp[b][i];
+          yv[b] = ldv<V>(cp[b] + i);
           t += yv[b] * c[b];
         }
-      const double ai = (h0 ? h0[i] : 1.0) * t;
-      a_out[i] = ai;
+      const VD ai = h0 ? ldv<V>(h0 + i) * t : t;
+      *reinterpret_cast<VD*>(a_out + i) = ai;
 #pragma unroll
       for (int b = 0; b < kFused; ++b)
-        if (b < cnt) f[b] += yv[b] * ai;
+        if (b < cnt) {
+#pragma unroll
+          for (int j = 0; j < V; ++j) f[b] += el<V>(yv[b], j) * el<V>(ai, j);
+        }
     }
     block_sums<kFused>(f, cnt, lds, tot);
     if (threadIdx.x < cnt) P[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = tot[threadIdx.x];
   } else {
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
-      double t = g[i];
+    for (int64_t i = lo + V * (int64_t)threadIdx.x; i < hi; i += V * kLB) {
+      VD t = ldv<V>(g + i);
       for (int jb = 0; jb < cnt; jb += kJB) {
         const int nc = cnt - jb < kJB ? cnt - jb : kJB;
 #pragma unroll
         for (int u = 0; u < kJB; ++u)
-          if (u < nc) t += Y[R.slot(jb + u) * n + i] * cs[jb + u];
+          if (u < nc) t += ldv<V>(Y + R.slot(jb + u) * n + i) * cs[jb + u];
       }
-      a_out[i] = (h0 ? h0[i] : 1.0) * t;
+      *reinterpret_cast<VD*>(a_out + i) = h0 ? ldv<V>(h0 + i) * t : t;
     }
   }
 }
 
 // pass 2b (histories longer than kFused): partials of f_b = y_b . a
+template <int V>
 __global__ __launch_bounds__(kLB) void k_lb_ya_t(int64_t n, const double* __restrict__ Y, Ring R,
                                                  const double* __restrict__ a,
                                                  double* __restrict__ P) {
-  __shared__ double lds[(kLB / 64) * kJB];
-  __shared__ double tot[kJB];
-  gemvt_partials(n, Y, R, a, P, 0, lds, tot);
+  __shared__ double lds[(kLB / 64) * kJT];
+  __shared__ double tot[kJT];
+  gemvt_partials<V>(n, Y, R, a, P, 0, lds, tot);
 }
 
 // pass 3: e = R^-T (f + D c) (every workgroup); p = a - S e
+template <int V>
 __global__ __launch_bounds__(kLB) void k_lb_p(int64_t n, const double* __restrict__ S, Ring R,
                                               const double* __restrict__ a,
                                               const double* __restrict__ SY,
                                               const double* __restrict__ red,
                                               double* __restrict__ p) {
+  typedef typename Vd<V>::type VD;
   __shared__ double es[kMaxHistory];
   const int cnt = R.cnt;
   if (threadIdx.x == 0) {
@@ -274,16 +318,16 @@ __global__ __launch_bounds__(kLB) void k_lb_p(int64_t n, const double* __restric
   }
   __syncthreads();
   int64_t lo, hi;
-  rows_of(n, blockIdx.x, gridDim.x, &lo, &hi);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kLB) {
-    double t = a[i];
+  rows_of<V>(n, blockIdx.x, gridDim.x, &lo, &hi);
+  for (int64_t i = lo + V * (int64_t)threadIdx.x; i < hi; i += V * kLB) {
+    VD t = ldv<V>(a + i);
     for (int jb = 0; jb < cnt; jb += kJB) {
       const int nc = cnt - jb < kJB ? cnt - jb : kJB;
 #pragma unroll
       for (int u = 0; u < kJB; ++u)
-        if (u < nc) t -= S[R.slot(jb + u) * n + i] * es[jb + u];
+        if (u < nc) t -= ldv<V>(S + R.slot(jb + u) * n + i) * es[jb + u];
     }
-    p[i] = t;
+    *reinterpret_cast<VD*>(p + i) = t;
   }
 }
 
@@ -299,6 +343,30 @@ __global__ void k_lb_scale(int64_t n, const double* __restrict__ g, const double
 
 using namespace spx;
 using namespace spx::solver;
+
+namespace {
+// The apply's passes with rows taken V at a time.
+template <int V>
+int apply_passes(spx_lbfgs* h, const double* g, const double* h0, double* p, hipStream_t st) {
+  const int64_t n = h->n;
+  const int cnt = h->count;
+  const int G = h->G;
+  const Ring R{h->m, h->start, cnt};
+  hipLaunchKernelGGL(k_lb_sg<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, g, h->P);
+  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
+  if (cnt <= kFused) {
+    hipLaunchKernelGGL((k_lb_ya<true, V>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
+                       h->red, h->a, h->P);
+  } else {
+    hipLaunchKernelGGL((k_lb_ya<false, V>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
+                       h->red, h->a, h->P);
+    hipLaunchKernelGGL(k_lb_ya_t<V>, dim3(G), dim3(kLB), 0, st, n, h->Y, R, h->a, h->P);
+  }
+  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red + 2 * kMaxHistory);
+  hipLaunchKernelGGL(k_lb_p<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, h->a, h->SY, h->red, p);
+  return SPX_OK;
+}
+}  // namespace
 
 extern "C" int spx_lbfgs_create(int64_t n, int32_t m, void* stream, spx_lbfgs_handle* out) {
   clear_error();
@@ -380,7 +448,10 @@ extern "C" int spx_lbfgs_update(spx_lbfgs_handle h, const double* s, const doubl
   const Ring R{h->m, start, cnt};
   hipLaunchKernelGGL(k_lb_put, dim3((unsigned)ceil_div(h->n, 256)), dim3(256), 0, st, h->n, s, y,
                      h->S + (int64_t)slot * h->n, h->Y + (int64_t)slot * h->n);
-  hipLaunchKernelGGL(k_lb_update, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, s, y, R, h->P);
+  if (h->n % 2 == 0)
+    hipLaunchKernelGGL(k_lb_update<2>, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, R, h->P);
+  else
+    hipLaunchKernelGGL(k_lb_update<1>, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, R, h->P);
   hipLaunchKernelGGL(k_lb_update_finish, dim3(2 * cnt), dim3(kLB), 0, st, h->P, G, R, slot, h->SY);
   SPX_CHECK_HIP(hipGetLastError());
   h->start = start;
@@ -401,20 +472,10 @@ extern "C" int spx_lbfgs_apply(spx_lbfgs_handle h, const double* g, const double
     SPX_CHECK_HIP(hipGetLastError());
     return SPX_OK;
   }
-  const int G = h->G;
-  const Ring R{h->m, h->start, cnt};
-  hipLaunchKernelGGL(k_lb_sg, dim3(G), dim3(kLB), 0, st, n, h->S, R, g, h->P);
-  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
-  if (cnt <= kFused) {
-    hipLaunchKernelGGL((k_lb_ya<true>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY, h->red,
-                       h->a, h->P);
-  } else {
-    hipLaunchKernelGGL((k_lb_ya<false>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY, h->red,
-                       h->a, h->P);
-    hipLaunchKernelGGL(k_lb_ya_t, dim3(G), dim3(kLB), 0, st, n, h->Y, R, h->a, h->P);
-  }
-  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red + 2 * kMaxHistory);
-  hipLaunchKernelGGL(k_lb_p, dim3(G), dim3(kLB), 0, st, n, h->S, R, h->a, h->SY, h->red, p);
+  const bool wide = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(g) |
+                                      reinterpret_cast<uintptr_t>(h0) |
+                                      reinterpret_cast<uintptr_t>(p)) & 15) == 0;
+  SPX_TRY(wide ? apply_passes<2>(h, g, h0, p, st) : apply_passes<1>(h, g, h0, p, st));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }
