@@ -472,11 +472,15 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
     ustar = T.cg_solve(d(b), rtol=1e-12).x
     th = d(theta).requires_grad_(True)
     bd, based, wd = d(b), d(base), d(w)
+    # one untimed forward and backward first: the first calls load kernel code
+    u0 = AG.element_coefficient_solve(th, bd, G, based, wd, 16, rtol=1e-12)
+    (0.5 * torch.sum((u0 - ustar) ** 2)).backward()
+    th.grad = None
     fw_ms, u = timed(lambda: AG.element_coefficient_solve(th, bd, G, based, wd, 16, rtol=1e-12))
     loss = 0.5 * torch.sum((u - ustar) ** 2)
     bw_ms, _ = timed(lambda: loss.backward())
     out["gradient256"] = {"forward_ms": round(fw_ms, 2), "backward_ms": round(bw_ms, 2),
-                          "loss": float(loss)}
+                          "loss": float(loss.detach())}
     log(f"gradient: forward {fw_ms:.2f} ms backward {bw_ms:.2f} ms")
     return out
 

@@ -184,8 +184,11 @@ int spx_batch_total_rows(spx_batch_handle b, int64_t* total);
 /* Launch shape of the batched solvers (all fields may be 0 for automatic).
  *   blocks: workgroups shared by the systems (0: 8 per compute unit;
  *     raised to nsys if smaller).
- *   rows_per_tile: rows per workgroup tile of the stream row walk (0 auto,
- *     else 32, 64, 128 or 256).
+ *   rows_per_tile: 0 lets the library choose the row walk: the window walk
+ *     (256-row tiles reading x from LDS, see SPX_OPT_SPMV_VARIANT) when
+ *     every system (for BiCG also every transpose) has a window index, else
+ *     the stream walk with the largest tile that fits; 32, 64, 128 or 256
+ *     ask for the stream walk with that many rows per workgroup tile.
  *   weight_exponent: a running system's share of the workgroups is
  *     proportional to nnz_s^weight_exponent, at least one (<= 0 means 1).
  *   check_every: iterations between host polls, at which the workgroups are

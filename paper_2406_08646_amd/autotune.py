@@ -1,8 +1,10 @@
 """Launch-shape autotuner for the batched solver.
 
 The batched Jacobi-CG (``spx_batch_cg``) has three shape knobs: the number
-of workgroups shared by the systems, the rows per tile of the row walk and
-the exponent that turns a system's size into its share of the workgroups.
+of workgroups shared by the systems, the row walk (``rows_per_tile`` 0: the
+library's choice, the window walk when every system has a window index; 64
+or 256: the stream walk with that tile) and the exponent that turns a
+system's size into its share of the workgroups.
 The best values depend on the mix of system sizes, so the tuner times whole
 solves of the actual batch for a small grid of candidates, on the GPU, and
 keeps the fastest.  Results are cached per (device, batch signature,

@@ -30,6 +30,7 @@ struct BatchSys {
   const int32_t* col;
   const double* val;
   const int32_t* dpos;
+  WinView win;  // the system's window index (used when every system has one)
 };
 
 // plan layout (int32): wg_sys[G] | team_start[nsys] | team_size[nsys]
@@ -52,6 +53,7 @@ struct spx_batch {
   int64_t total = 0;
   int64_t max_tile[4] = {0, 0, 0, 0};
   int64_t max_row = 0, max_nnz_sys = 0;
+  int64_t win_blocks = 0;  // largest window of any system; -1 when one has no index
   spx::batch::BatchSys* d_sys = nullptr;
   double* work = nullptr;  // CG: r, p, q, dinv (4 * total)
   spx::CgScalars* d_st = nullptr;
@@ -65,6 +67,7 @@ struct spx_batch {
   spx::batch::BatchSys* d_sysT = nullptr;  // transposes, for BiCG
   int64_t max_tile_t[4] = {0, 0, 0, 0};
   int64_t max_row_t = 0;
+  int64_t win_blocks_t = 0;
   double* kwork = nullptr;  // 8 * total
 };
 
@@ -113,10 +116,12 @@ inline void make_plan(const spx_batch* B, const std::vector<char>& active, int G
   for (; b < G; ++b) wg[b] = -1;
 }
 
-// Row walk of the batch: the stream walk with the largest tile that fits
-// every system's (and, for BiCG, every transpose's) tiles in LDS, else the
-// lane walk.
-inline SpmvShape batch_shape(const int64_t max_tile[4], int64_t max_row, int rows_opt) {
+// Row walk of the batch: the window walk when every system (and, for BiCG,
+// every transpose) has a window index (win_blocks > 0: the largest window)
+// and no row count was asked for; else the stream walk with the largest
+// tile that fits every system's tiles in LDS; else the lane walk.
+inline SpmvShape batch_shape(const int64_t max_tile[4], int64_t max_row, int rows_opt,
+                             int64_t win_blocks) {
   SpmvShape sh;
   sh.nt = 1;
   sh.vec = 0;
@@ -126,6 +131,14 @@ inline SpmvShape batch_shape(const int64_t max_tile[4], int64_t max_row, int row
   sh.rows = 0;
   sh.lds = 0;
   sh.variant = kVariantVector;
+  if (win_blocks > 0 && rows_opt == 0) {
+    sh.variant = kVariantWindow;
+    sh.rows = kWinRows;
+    sh.tile = win_blocks * kWinBlock;
+    sh.lds = window_lds_bytes(win_blocks, sizeof(double),
+                              win_u_solver<double>() * win_v<double>());
+    return sh;
+  }
   auto idx = [](int rows) { return rows == 32 ? 0 : rows == 64 ? 1 : rows == 128 ? 2 : 3; };
   const int cands[4] = {256, 128, 64, 32};
   for (int rows : cands) {
@@ -164,7 +177,7 @@ struct Run {
 // Validates the tuning, sizes the plan and `sets` partial arrays of G
 // doubles, and uploads the plan with every system active.
 inline int prepare(spx_batch* B, const spx_batch_tuning* tuning, const int64_t max_tile[4],
-                   int64_t max_row, int sets, hipStream_t s, Run* run) {
+                   int64_t max_row, int64_t win_blocks, int sets, hipStream_t s, Run* run) {
   const int ns = B->nsys;
   int G = (tuning && tuning->blocks > 0) ? tuning->blocks : cu_count() * 8;
   G = std::max(G, ns);
@@ -174,8 +187,9 @@ inline int prepare(spx_batch* B, const spx_batch_tuning* tuning, const int64_t m
   const int rows_opt = tuning ? tuning->rows_per_tile : 0;
   if (rows_opt != 0 && rows_opt != 32 && rows_opt != 64 && rows_opt != 128 && rows_opt != 256)
     return set_error(SPX_INVALID_ARG, "batch: rows_per_tile must be 0, 32, 64, 128 or 256");
-  run->sh = batch_shape(max_tile, max_row, rows_opt);
-  run->lds = run->sh.variant == kVariantStream ? run->sh.lds : 0;
+  run->sh = batch_shape(max_tile, max_row, rows_opt, win_blocks);
+  run->lds = (run->sh.variant == kVariantStream || run->sh.variant == kVariantWindow) ? run->sh.lds
+                                                                                      : 0;
   const int plan_n = G + 2 * ns;
   if (B->plan_cap < plan_n) {
     dfree(B->d_plan);
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(solver::kBlock) void k_b_resnorm(const BatchSys* __
                                        reinterpret_cast<double*>(smem), [&](int64_t row, double ax) {
                                          const double ri = b[o + row] - ax;
                                          rr += ri * ri;
-                                       });
+                                       }, 0, S.win);
   rr = block_sum<kBlock>(rr, lds);
   if (threadIdx.x == 0) P[blockIdx.x] = rr;
 }
@@ -371,7 +385,7 @@ __global__ __launch_bounds__(solver::kBlock) void k_b_resnorm_finish(PlanView pl
 // True residuals of every system (the plan must hold all of them).
 inline int true_residuals(spx_batch* B, const Run& run, const double* bvec, const double* x,
                           hipStream_t s) {
-  SPX_TRY(solver::with_shape(run.sh, [&](auto shc) {
+  SPX_TRY(solver::with_shape<true>(run.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_b_resnorm<SH>), dim3(run.G), dim3(solver::kBlock), run.lds, s, B->d_sys,
                        run.pl, bvec, x, B->partials, run.sh.rows);

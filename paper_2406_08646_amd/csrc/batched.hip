@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_b_init(const BatchSys* __restrict__ 
                                          rz += ri * zi;
                                          rr += ri * ri;
                                          bb += bi * bi;
-                                       });
+                                       }, 0, S.win);
   rz = block_sum<kBlock>(rz, lds);
   rr = block_sum<kBlock>(rr, lds);
   bb = block_sum<kBlock>(bb, lds);
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_b_spmv(const BatchSys* __restrict__ 
                                        reinterpret_cast<double*>(smem), [&](int64_t row, double v) {
                                          q[o + row] = v;
                                          dot += p[o + row] * v;
-                                       });
+                                       }, 0, S.win);
   dot = block_sum<kBlock>(dot, lds);
   if (threadIdx.x == 0) P1[blockIdx.x] = dot;
 }
@@ -196,7 +196,11 @@ extern "C" int spx_batch_create(int32_t nsys, const spx_handle* hs, void* stream
     S.col = h->A.col;
     S.val = h->A.val;
     S.dpos = h->A.dpos;
+    S.win = win_view(h->A);
     B->sys.push_back(S);
+    B->win_blocks = h->A.win.lcol && B->win_blocks >= 0
+                        ? std::max(B->win_blocks, h->A.win.max_blocks)
+                        : -1;
     off += h->n;
     for (int t = 0; t < 4; ++t) B->max_tile[t] = std::max(B->max_tile[t], h->A.tile_nnz[t]);
     B->max_row = std::max(B->max_row, h->A.max_row);
@@ -261,7 +265,7 @@ extern "C" int spx_batch_cg(spx_batch_handle B, const double* bvec, double* x, d
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = B->nsys;
   Run run;
-  SPX_TRY(prepare(B, tuning, B->max_tile, B->max_row, 3, s, &run));
+  SPX_TRY(prepare(B, tuning, B->max_tile, B->max_row, B->win_blocks, 3, s, &run));
   const int G = run.G;
   const int64_t tot = B->total;
   double* r = B->work;
@@ -277,7 +281,7 @@ extern "C" int spx_batch_cg(spx_batch_handle B, const double* bvec, double* x, d
   hipLaunchKernelGGL(k_b_reset, dim3((unsigned)ceil_div(ns, 64)), dim3(64), 0, s, B->d_st, ns,
                      (int32_t)maxit);
   hipLaunchKernelGGL(k_b_dinv, dim3(G), dim3(kBlock), 0, s, B->d_sys, pl, dinv, B->d_st);
-  SPX_TRY(with_shape(sh, [&](auto shc) {
+  SPX_TRY(with_shape<true>(sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_b_init<SH>), dim3(G), dim3(kBlock), lds, s, B->d_sys, pl, bvec, x, r, p,
                        dinv, B->partials, sh.rows);
@@ -287,7 +291,7 @@ extern "C" int spx_batch_cg(spx_batch_handle B, const double* bvec, double* x, d
   SPX_CHECK_HIP(hipGetLastError());
 
   SPX_TRY(poll_loop(B, run, maxit, s, [&](int64_t first, int64_t m) {
-    return with_shape(sh, [&](auto shc) {
+    return with_shape<true>(sh, [&](auto shc) {
       using SH = decltype(shc);
       for (int64_t c = 0; c < m; ++c) {
         const int64_t kk = first + c;

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_bb_init(const BatchSys* __restrict__
                                          rz += ri * zi;
                                          rr += ri * ri;
                                          bb += bi * bi;
-                                       });
+                                       }, 0, S.win);
   rz = block_sum<kBlock>(rz, lds);
   rr = block_sum<kBlock>(rr, lds);
   bb = block_sum<kBlock>(bb, lds);
@@ -108,11 +108,11 @@ __global__ __launch_bounds__(kBlock) void k_bb_spmv(const BatchSys* __restrict__
                                        reinterpret_cast<double*>(smem), [&](int64_t row, double v) {
                                          q[o + row] = v;
                                          dot += ph[o + row] * v;
-                                       });
+                                       }, 0, S.win);
   __syncthreads();  // the staging area is reused by the second walk
   for_rows<SH, double, double, double>(T.n, T.rowptr, T.col, T.val, ph + o, rows, lb, pl.size(s),
                                        reinterpret_cast<double*>(smem),
-                                       [&](int64_t row, double v) { qh[o + row] = v; });
+                                       [&](int64_t row, double v) { qh[o + row] = v; }, 0, T.win);
   dot = block_sum<kBlock>(dot, lds);
   if (threadIdx.x == 0) P1[blockIdx.x] = dot;
 }
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_tq_init(const BatchSys* __restrict__
                                          V.v[i] = 0.0;
                                          rr += ri * ri;
                                          bb += bi * bi;
-                                       });
+                                       }, 0, S.win);
   rr = block_sum<kBlock>(rr, lds);
   bb = block_sum<kBlock>(bb, lds);
   if (threadIdx.x == 0) {
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_tq_a(const BatchSys* __restrict__ sy
                                          V.au[i] = a;
                                          V.v[i] = vi;
                                          sig += V.rs[i] * vi;
-                                       });
+                                       }, 0, S.win);
   sig = block_sum<kBlock>(sig, lds);
   if (threadIdx.x == 0) P0[blockIdx.x] = sig;
 }
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_tq_c(const BatchSys* __restrict__ sy
                                          V.w[i] = wi;
                                          w2 += wi * wi;
                                          wr += V.rs[i] * wi;
-                                       });
+                                       }, 0, S.win);
   w2 = block_sum<kBlock>(w2, lds);
   wr = block_sum<kBlock>(wr, lds);
   if (threadIdx.x == 0) {
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_tq_verify(const BatchSys* __restrict
                                          V.t[i] = 0.0;
                                          V.v[i] = 0.0;
                                          rr += ri * ri;
-                                       });
+                                       }, 0, S.win);
   rr = block_sum<kBlock>(rr, lds);
   if (threadIdx.x == 0) P[blockIdx.x] = rr;
 }
@@ -610,10 +610,15 @@ extern "C" int spx_batch_bicg(spx_batch_handle B, const double* bvec, double* x,
   std::vector<BatchSys> sysT(ns);
   int64_t tiles[4] = {B->max_tile[0], B->max_tile[1], B->max_tile[2], B->max_tile[3]};
   int64_t max_row = B->max_row;
+  B->win_blocks_t = 0;
   for (int k = 0; k < ns; ++k) {
     spx_matrix* h = B->hs[k];
     SPX_TRY(ensure_transpose(h, s));
-    sysT[k] = BatchSys{h->n, B->sys[k].off, h->At.rowptr, h->At.col, h->At.val, h->At.dpos};
+    sysT[k] = BatchSys{h->n, B->sys[k].off, h->At.rowptr, h->At.col, h->At.val, h->At.dpos,
+                       win_view(h->At)};
+    B->win_blocks_t = h->At.win.lcol && B->win_blocks_t >= 0
+                          ? std::max(B->win_blocks_t, h->At.win.max_blocks)
+                          : -1;
     for (int t = 0; t < 4; ++t) tiles[t] = std::max(tiles[t], h->At.tile_nnz[t]);
     max_row = std::max(max_row, h->At.max_row);
   }
@@ -621,7 +626,10 @@ extern "C" int spx_batch_bicg(spx_batch_handle B, const double* bvec, double* x,
                                hipMemcpyHostToDevice, s));
   SPX_TRY(ensure_kwork(B));
   Run run;
-  SPX_TRY(prepare(B, tuning, tiles, max_row, 3, s, &run));
+  const int64_t wb = B->win_blocks > 0 && B->win_blocks_t > 0
+                         ? std::max(B->win_blocks, B->win_blocks_t)
+                         : -1;
+  SPX_TRY(prepare(B, tuning, tiles, max_row, wb, 3, s, &run));
   const int G = run.G;
   const int64_t tot = B->total;
   double* r = B->kwork;
@@ -640,7 +648,7 @@ extern "C" int spx_batch_bicg(spx_batch_handle B, const double* bvec, double* x,
   hipLaunchKernelGGL(k_b_reset, dim3((unsigned)ceil_div(ns, 64)), dim3(64), 0, s, B->d_st, ns,
                      (int32_t)maxit);
   hipLaunchKernelGGL(k_b_dinv, dim3(G), dim3(kBlock), 0, s, B->d_sys, pl, dinv, B->d_st);
-  SPX_TRY(with_shape(sh, [&](auto shc) {
+  SPX_TRY(with_shape<true>(sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_bb_init<SH>), dim3(G), dim3(kBlock), lds, s, B->d_sys, pl, bvec, x, r, rh,
                        p, ph, dinv, B->partials, sh.rows);
@@ -649,7 +657,7 @@ extern "C" int spx_batch_bicg(spx_batch_handle B, const double* bvec, double* x,
   hipLaunchKernelGGL(k_b_init_finish, dim3(ns), dim3(kBlock), 0, s, pl, B->d_st, B->partials, rtol);
   SPX_CHECK_HIP(hipGetLastError());
   SPX_TRY(poll_loop(B, run, maxit, s, [&](int64_t first, int64_t m) {
-    return with_shape(sh, [&](auto shc) {
+    return with_shape<true>(sh, [&](auto shc) {
       using SH = decltype(shc);
       for (int64_t c = 0; c < m; ++c) {
         const int64_t kk = first + c;
@@ -678,7 +686,7 @@ extern "C" int spx_batch_tfqmr(spx_batch_handle B, const double* bvec, double* x
   const int ns = B->nsys;
   SPX_TRY(ensure_kwork(B));
   Run run;
-  SPX_TRY(prepare(B, tuning, B->max_tile, B->max_row, 4, s, &run));
+  SPX_TRY(prepare(B, tuning, B->max_tile, B->max_row, B->win_blocks, 4, s, &run));
   const int G = run.G;
   const int64_t tot = B->total;
   double* kw = B->kwork;
@@ -695,7 +703,7 @@ extern "C" int spx_batch_tfqmr(spx_batch_handle B, const double* bvec, double* x
   hipLaunchKernelGGL(k_b_reset, dim3((unsigned)ceil_div(ns, 64)), dim3(64), 0, s, B->d_st, ns,
                      (int32_t)maxit);
   hipLaunchKernelGGL(k_b_dinv, dim3(G), dim3(kBlock), 0, s, B->d_sys, pl, dinv, B->d_st);
-  SPX_TRY(with_shape(sh, [&](auto shc) {
+  SPX_TRY(with_shape<true>(sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_tq_init<SH>), dim3(G), dim3(kBlock), lds, s, B->d_sys, pl, bvec, x, V,
                        dinv, P2, sh.rows);
@@ -710,7 +718,7 @@ extern "C" int spx_batch_tfqmr(spx_batch_handle B, const double* bvec, double* x
     bool any = false;
     for (int t = 0; t < ns; ++t) any = any || (B->h_st[t].verify && !B->h_st[t].done);
     if (!any) return SPX_OK;
-    SPX_TRY(with_shape(sh, [&](auto shc) {
+    SPX_TRY(with_shape<true>(sh, [&](auto shc) {
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_tq_verify<SH>), dim3(G), dim3(kBlock), lds, s, B->d_sys, pl, bvec, x,
                          V, dinv, B->d_st, P2, sh.rows);
@@ -723,7 +731,7 @@ extern "C" int spx_batch_tfqmr(spx_batch_handle B, const double* bvec, double* x
     return SPX_OK;
   };
   SPX_TRY(poll_loop(B, run, iters, s, [&](int64_t first, int64_t m) {
-    return with_shape(sh, [&](auto shc) {
+    return with_shape<true>(sh, [&](auto shc) {
       using SH = decltype(shc);
       for (int64_t c = 0; c < m; ++c) {
         const int64_t j = first + c - 1;  // 0-based iteration
