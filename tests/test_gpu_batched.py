@@ -120,3 +120,36 @@ def test_spmm_full_size_sampled(orc):
             ref += vv * X[cc]
         scale = np.abs(v) @ np.abs(X[c])
         assert np.all(np.abs(Y[r] - ref) <= 1e-12 * scale + 1e-300)
+
+
+def test_batched_with_a_system_without_window(orc):
+    """One system's random pattern has no window index, so the whole batch
+    takes the stream walk; every system still converges and matches its
+    single-system solve."""
+    spx = require_gpu()
+    probs, bs = W.config4(nsys=4, lo=20, hi=90, seed=13)
+    rng = np.random.default_rng(14)
+    n = 9000
+    i = rng.integers(0, n, 60000).astype(np.int32)
+    j = rng.integers(0, n, 60000).astype(np.int32)
+    v = rng.uniform(-1, 1, i.size)
+    diag = 1.0 + np.bincount(i, np.abs(v), n) + np.bincount(j, np.abs(v), n)
+    k = np.arange(n, dtype=np.int32)
+    rand = W.CooProblem(n=n, i=np.concatenate([i, j, k]), j=np.concatenate([j, i, k]),
+                        v=np.concatenate([v, v, diag]))
+    mats = [assemble(spx, p) for p in probs] + [assemble(spx, rand)]
+    assert all(m.get_window(arrays=False)["built"] for m in mats[:-1])
+    assert not mats[-1].get_window(arrays=False)["built"]
+    b_r = rng.uniform(-1, 1, n)
+    allb = bs + [b_r]
+    batch = spx.batch_create(mats)
+    x, iters, relres, st = batch.batch_cg(dev(np.concatenate(allb)), rtol=1e-9)
+    assert st == 0 and max(relres) <= 1e-9 * 1.001
+    x = host(x)
+    off = 0
+    for m, b, it in zip(mats, allb, iters):
+        r = m.cg_solve(dev(b), rtol=1e-9)
+        assert abs(r.iters - it) <= 2
+        xs = x[off:off + m.n]
+        off += m.n
+        assert np.linalg.norm(host(r.x) - xs) <= 1e-6 * np.linalg.norm(xs)
