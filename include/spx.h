@@ -371,8 +371,9 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *     those of the stream walk; only for patterns with a window index, see
  *     spx_get_window, else as 0).  Auto takes the window walk when the
  *     pattern has an index and at least 12 of its 256-row tiles per compute
- *     unit (smaller systems fill the chip better with the stream walk's
- *     smaller tiles), rows average at most 64 entries in every tile and
+ *     unit (7 when rows average at most 16 entries; smaller systems fill the
+ *     chip better with the stream walk's smaller tiles), rows average at
+ *     most 64 entries in every tile and
  *     none of SPX_OPT_ROWS_PER_BLOCK, SPX_OPT_QUAD_LOADS, SPX_OPT_PIPELINE
  *     is set.  Reading the option returns the resolved variant.
  *   SPX_OPT_ROWS_PER_BLOCK: stream variant rows per workgroup (0 auto, else

@@ -385,17 +385,20 @@ int rows_index(int rows) { return rows == 32 ? 0 : rows == 64 ? 1 : rows == 128 
 namespace {
 // The window walk's shape when A has a window index and the options leave
 // the choice to the library (or ask for it).  Left to itself the library
-// takes it for patterns of at least kWinAutoTilesPerCu 256-row tiles per
-// compute unit (below that the stream walk's smaller tiles fill the chip
-// better) whose rows average at most 64 entries in every tile (one thread
-// adds each row).  It needs no tile in LDS, so it also takes patterns whose
-// tiles exceed the stream walk's limit.
+// takes it for patterns with enough 256-row tiles per compute unit (below
+// that the stream walk's smaller tiles fill the chip better): 12 when rows
+// average more than 16 entries, 7 for shorter rows, whose gather costs the
+// stream walk more; and whose rows average at most 64 entries in every tile
+// (one thread adds each row).  It needs no tile in LDS, so it also takes
+// patterns whose tiles exceed the stream walk's limit.
 constexpr int64_t kWinAutoTilesPerCu = 12;
+constexpr int64_t kWinAutoTilesPerCuShortRows = 7;
 bool window_shape(const spx_matrix* h, const Csr& A, bool allow, SpmvShape& sh) {
   if (!allow || !A.win.lcol) return false;
   const int want = h ? h->variant_opt : 0;
   const bool tuned = h && (h->rows_opt || h->vec_opt || h->pipe_opt);
-  const bool large = ceil_div(A.n, kWinRows) >= kWinAutoTilesPerCu * cu_count();
+  const int64_t per_cu = A.nnz <= 16 * A.n ? kWinAutoTilesPerCuShortRows : kWinAutoTilesPerCu;
+  const bool large = ceil_div(A.n, kWinRows) >= per_cu * cu_count();
   if (want == kVariantWindow || (want == kVariantAuto && !tuned && large &&
                                  A.tile_nnz[3] <= 64 * (int64_t)kWinRows)) {
     sh.variant = kVariantWindow;
