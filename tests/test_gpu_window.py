@@ -217,3 +217,54 @@ def test_window_option_resolution(orc):
     assert np.array_equal(bits(host(C.matmult(dev(x)))), bits(orc.spmv(ref, x)))
     with pytest.raises(spx.SpxError):
         B.set_option(spx.OPT_SPMV_VARIANT, 5)
+
+
+def stencil_problem(shape, offsets, seed):
+    n = int(np.prod(shape))
+    idx = np.arange(n).reshape(shape)
+    I, J = [], []
+    for off in offsets:
+        src = idx[tuple(slice(max(0, -o), s - max(0, o)) for o, s in zip(off, shape))]
+        dst = idx[tuple(slice(max(0, o), s - max(0, -o)) for o, s in zip(off, shape))]
+        I.append(src.ravel())
+        J.append(dst.ravel())
+    i = np.concatenate(I).astype(np.int32)
+    j = np.concatenate(J).astype(np.int32)
+    v = np.random.default_rng(seed).uniform(-1, 1, i.size)
+    return W.CooProblem(n=n, i=i, j=j, v=v)
+
+
+SHAPES = {
+    "band1": lambda: banded(3001, 1, 95),
+    "band20": lambda: banded(4999, 20, 96),
+    "band900": lambda: banded(6000, 900, 97),  # windows near or over the 64-block limit
+    "5pt_2d": lambda: stencil_problem((77, 61), [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)], 98),
+    "7pt_3d": lambda: stencil_problem((17, 13, 11), [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0),
+                                                      (0, -1, 0), (0, 0, 1), (0, 0, -1)], 99),
+    "9pt_2d": lambda: stencil_problem((90, 45), [(a, b) for a in (-1, 0, 1) for b in (-1, 0, 1)], 100),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SHAPES))
+def test_window_other_patterns(orc, name):
+    """The index against its definition and the window-walk products bitwise
+    against the oracle on banded matrices (up to half-width 900) and 5-, 7-
+    and 9-point stencils on ragged grids."""
+    spx = require_gpu()
+    prob = SHAPES[name]()
+    A = assemble(spx, prob)
+    rowptr, col, _ = A.get_csr()
+    ref = window_reference(host(rowptr), host(col), prob.n)
+    w = A.get_window()
+    assert w["built"] == ref["built"]
+    if w["built"]:
+        assert np.array_equal(host(w["ptr"]), ref["ptr"])
+        assert np.array_equal(host(w["blk"]), ref["blk"])
+        mask = ref["lcol"] >= 0
+        assert np.array_equal(host(w["lcol"]).astype(np.int64)[mask], ref["lcol"][mask])
+        A.set_option(spx.OPT_SPMV_VARIANT, 4)
+        assert A.get_option(spx.OPT_SPMV_VARIANT) == 4
+    oref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    x = np.random.default_rng(101).uniform(-1, 1, prob.n)
+    assert np.array_equal(bits(host(A.matmult(dev(x)))), bits(orc.spmv(oref, x)))
+    assert np.array_equal(bits(host(A.matmult_transpose(dev(x)))), bits(orc.spmv_transpose(oref, x)))
