@@ -253,12 +253,15 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
     A1.set_values_coo(d(p1.v))
     b1d = d(b1)
     c1 = {"n": p1.n, "nnz": A1.nnz}
-    for mode, tag in ((0, "grid"), (2, "one_workgroup")):
+    for mode, form, tag in ((0, 0, "grid"), (2, 0, "one_workgroup"),
+                            (0, 1, "single_reduction")):
         A1.set_option(spx.OPT_SMALL_SOLVE, mode)
+        A1.set_option(spx.OPT_CG_VARIANT, form)
         A1.cg_solve(b1d, rtol=1e-8)
         ms, r = timed(lambda: A1.cg_solve(b1d, rtol=1e-8), reps=3)
         c1[tag] = {"ms": round(ms, 3), "iters": r.iters, "relres": r.relres,
                    "us_per_iter": round(1e3 * ms / max(1, r.iters), 2)}
+    A1.set_option(spx.OPT_CG_VARIANT, 0)
     out["c1_cg"] = c1
     log(f"C1 CG: {c1}")
     A1.destroy()
