@@ -357,8 +357,12 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
 /* Tuning knobs (per handle; defaults chosen from the pattern).
  *   SPX_OPT_SPMV_LANES: lanes per row of the "vector" row walk (0 = auto,
  *     else a power of two <= 64).
- *   SPX_OPT_XCD_REMAP: 1 (default) gives each of the 8 XCDs a contiguous
- *     range of rows, 0 keeps plain workgroup order.
+ *   SPX_OPT_XCD_REMAP: 1 gives each of the 8 XCDs a contiguous range of
+ *     rows, 0 keeps plain workgroup order, -1 (default) picks per walk:
+ *     plain order for the window walk (its x entries are staged from
+ *     LDS windows) and the XCD order for the gather walks (the x entries
+ *     a region gathers then stay in one XCD's L2).  Reading the option
+ *     returns the order the product with A uses.
  *   SPX_OPT_PROFILE: 1 brackets every solver-iteration kernel with HIP
  *     events on the solver's stream and accumulates their durations (read
  *     with spx_get_profile).

@@ -169,7 +169,7 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
       h->lanes_opt = (int)value;
       return SPX_OK;
     case SPX_OPT_XCD_REMAP:
-      h->xcd_remap = value ? 1 : 0;
+      h->xcd_remap = value < 0 ? -1 : value ? 1 : 0;
       return SPX_OK;
     case SPX_OPT_PROFILE:
       h->profile = value ? 1 : 0;
@@ -235,7 +235,7 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       *value = spmv_shape(h, h->A).lanes;
       return SPX_OK;
     case SPX_OPT_XCD_REMAP:
-      *value = h->xcd_remap;
+      *value = remap_for(h, spmv_shape(h, h->A));
       return SPX_OK;
     case SPX_OPT_PROFILE:
       *value = h->profile;

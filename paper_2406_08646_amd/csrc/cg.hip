@@ -687,7 +687,7 @@ int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* 
       hipEvent_t* e = evs ? evs + 6 * c : nullptr;
       if (e) (void)hipEventRecord(e[0], s);
       hipLaunchKernelGGL((k_cg_spmv<SH, VT>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr, A.col,
-                         A.val, p, q, st, P1, A.sh.rows, h->xcd_remap, A.sh.tile, A.win);
+                         A.val, p, q, st, P1, A.sh.rows, remap_for(h, A.sh), A.sh.tile, A.win);
       if (e) (void)hipEventRecord(e[1], s);
       if (e) (void)hipEventRecord(e[2], s);
       hipLaunchKernelGGL((k_cg_update<VT>), dim3(G2), dim3(kBlock), 0, s, A.n, x, r, p, q, dinv, st,
@@ -805,7 +805,7 @@ int chunk_graph(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, cons
                              (uintptr_t)check_every, (uintptr_t)fused_blocks(h),
                              (uintptr_t)vector_blocks(h),
                              (uintptr_t)(A.sh.variant * 4096 + A.sh.rows * 8 + A.sh.nt * 2 + A.sh.vec),
-                             (uintptr_t)(A.sh.tile * 64 + A.sh.lanes), (uintptr_t)(A.sh.pipe * 2 + h->xcd_remap)};
+                             (uintptr_t)(A.sh.tile * 64 + A.sh.lanes), (uintptr_t)(A.sh.pipe * 2 + remap_for(h, A.sh))};
   if (gc.exec && std::equal(key, key + 16, gc.key)) {
     *out = gc.exec;
     return SPX_OK;
@@ -882,7 +882,7 @@ int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, 
             if (e) (void)hipEventRecord(e[2], s);
             hipLaunchKernelGGL((k_sr_spmv<SH>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr,
                                A.col, A.val, u, p, sv, st, P2, (int64_t)G2, P1, A.sh.rows,
-                               h->xcd_remap, A.sh.tile, k, A.win);
+                               remap_for(h, A.sh), A.sh.tile, k, A.win);
             if (e) (void)hipEventRecord(e[3], s);
           }
           return SPX_OK;
@@ -898,7 +898,7 @@ int enqueue_resnorm(spx_matrix* h, const Op<double>& A, const double* b, const d
   SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_resnorm<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, A.n,
-                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, h->xcd_remap, A.sh.tile,
+                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, remap_for(h, A.sh), A.sh.tile,
                        A.win);
     return SPX_OK;
   }));
@@ -977,7 +977,7 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_cg_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
                        M.rowptr, M.col, M.val, b, x, r, p, h->dinv, h->partials, A.sh.rows,
-                       h->xcd_remap, A.sh.tile, A.win);
+                       remap_for(h, A.sh), A.sh.tile, A.win);
     return SPX_OK;
   }));
   hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G,
@@ -991,7 +991,7 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
     SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_sr_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
-                         M.rowptr, M.col, M.val, u, p, q, h->partials, A.sh.rows, h->xcd_remap,
+                         M.rowptr, M.col, M.val, u, p, q, h->partials, A.sh.rows, remap_for(h, A.sh),
                          A.sh.tile, A.win);
       return SPX_OK;
     }));
@@ -1127,7 +1127,7 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_ir_residual<SH>), dim3(G), dim3(kBlock), shape_lds<double>(sh), s, n,
                          M.rowptr, M.col, M.val, b, x, h->dinv32, r32, d32, p32, h->partials,
-                         sh.rows, h->xcd_remap, sh.tile, A64.win);
+                         sh.rows, remap_for(h, sh), sh.tile, A64.win);
       return SPX_OK;
     }));
     hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, so, si, h->partials, (int64_t)G,

@@ -184,7 +184,7 @@ struct spx_matrix {
   double* partials = nullptr;  // device reduction partials
   int64_t partial_cap = 0;
   int lanes_opt = 0;  // 0 = auto
-  int xcd_remap = 1;
+  int xcd_remap = -1;  // block order: 1 XCD-aware, 0 plain, -1 by walk (remap_for)
   int variant_opt = 0;   // SpmvVariant
   int rows_opt = 0;      // stream rows per workgroup, 0 = auto
   int nt_opt = 1;        // non-temporal matrix loads
@@ -211,6 +211,16 @@ struct spx_matrix {
 };
 
 namespace spx {
+// Block order of a product walk: the option's value when set, otherwise
+// plain workgroup order for the window walk (the resident workgroups then
+// sweep one contiguous stretch of the matrix; x comes from the staged
+// windows) and the XCD-aware order for the other walks (the x entries a
+// region gathers stay in its XCD's L2).
+inline int remap_for(const spx_matrix* h, const SpmvShape& sh) {
+  if (h->xcd_remap >= 0) return h->xcd_remap;
+  return sh.variant == kVariantWindow ? 0 : 1;
+}
+
 // assembly.hip
 int ensure_transpose(spx_matrix* h, hipStream_t s);
 int ensure_kslot(spx_matrix* h, hipStream_t s);

@@ -590,7 +590,8 @@ extern "C" int spx_matmult(spx_handle h, const double* x, double* y, void* strea
   if (!h || !x || !y) return set_error(SPX_INVALID_ARG, "matmult: NULL argument");
   if (x == y) return set_error(SPX_INVALID_ARG, "matmult: x and y must not alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SPX_TRY(launch_spmv(h->A, spmv_shape(h, h->A), x, y, h->xcd_remap, s));
+  const SpmvShape sh = spmv_shape(h, h->A);
+  SPX_TRY(launch_spmv(h->A, sh, x, y, remap_for(h, sh), s));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }
@@ -601,7 +602,8 @@ extern "C" int spx_matmult_transpose(spx_handle h, const double* x, double* y, v
   if (x == y) return set_error(SPX_INVALID_ARG, "matmult_transpose: x and y must not alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
   SPX_TRY(ensure_transpose(h, s));
-  SPX_TRY(launch_spmv(h->At, spmv_shape(h, h->At), x, y, h->xcd_remap, s));
+  const SpmvShape sh = spmv_shape(h, h->At);
+  SPX_TRY(launch_spmv(h->At, sh, x, y, remap_for(h, sh), s));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }

@@ -149,13 +149,14 @@ def test_window_products_bitwise(orc, case):
             assert np.array_equal(bits(host(A.matmult_transpose(xu))), yt_ref)
 
 
-def test_window_solvers_match_stream_walk():
-    """With the same solver grid and tiles of the same 256 rows, the window
-    walk and the stream walk give every workgroup the same rows and the same
-    row sums, so every solver form takes the same iterates: same iteration
-    counts, bitwise the same solutions.  (Another grid or tile size moves rows
-    between workgroups and changes the rounding of the dot products, not the
-    products.)"""
+@pytest.mark.parametrize("remap", [1, 0])
+def test_window_solvers_match_stream_walk(remap):
+    """With the same solver grid, block order and tiles of the same 256 rows,
+    the window walk and the stream walk give every workgroup the same rows and
+    the same row sums, so every solver form takes the same iterates: same
+    iteration counts, bitwise the same solutions.  (Another grid, order or
+    tile size moves rows between workgroups and changes the rounding of the
+    dot products, not the products.)"""
     spx = require_gpu()
     prob = make("q1_3d")
     b = dev(np.random.default_rng(91).uniform(-1, 1, prob.n))
@@ -164,11 +165,13 @@ def test_window_solvers_match_stream_walk():
         A = assemble(spx, prob)
         A.set_option(spx.OPT_SPMV_VARIANT, variant)
         A.set_option(spx.OPT_SOLVER_BLOCKS, 48)
+        A.set_option(spx.OPT_XCD_REMAP, remap)
         if variant == 2:
             A.set_option(spx.OPT_ROWS_PER_BLOCK, 256)
             A.set_option(spx.OPT_ROWS_PER_BLOCK_F32, 256)
         assert A.get_option(spx.OPT_SPMV_VARIANT) == variant
         assert A.get_option(spx.OPT_ROWS_PER_BLOCK) == 256
+        assert A.get_option(spx.OPT_XCD_REMAP) == remap
         r = A.cg_solve(b, rtol=1e-10)
         A.set_option(spx.OPT_CG_VARIANT, 1)
         sr = A.cg_solve(b, rtol=1e-10)
@@ -212,9 +215,19 @@ def test_window_option_resolution(orc):
     assert C.get_option(spx.OPT_SPMV_VARIANT) == 2
     C.set_option(spx.OPT_QUAD_LOADS, 0)
     assert C.get_option(spx.OPT_SPMV_VARIANT) == 4
+    # block order by default: plain for the window walk, XCD order otherwise;
+    # an explicit order holds for every walk, -1 restores the choice
+    assert C.get_option(spx.OPT_XCD_REMAP) == 0
+    assert B.get_option(spx.OPT_XCD_REMAP) == 1
+    C.set_option(spx.OPT_XCD_REMAP, 1)
+    assert C.get_option(spx.OPT_XCD_REMAP) == 1
+    y1 = host(C.matmult(dev(np.random.default_rng(94).uniform(-1, 1, C.n))))
+    C.set_option(spx.OPT_XCD_REMAP, -1)
+    assert C.get_option(spx.OPT_XCD_REMAP) == 0
     ref = orc.assemble(C.n, *banded_arrays(12 * 256 * cus + 5, 3, 93))
     x = np.random.default_rng(94).uniform(-1, 1, C.n)
     assert np.array_equal(bits(host(C.matmult(dev(x)))), bits(orc.spmv(ref, x)))
+    assert np.array_equal(bits(y1), bits(orc.spmv(ref, x)))
     with pytest.raises(spx.SpxError):
         B.set_option(spx.OPT_SPMV_VARIANT, 5)
 
