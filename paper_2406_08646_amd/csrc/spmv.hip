@@ -269,6 +269,99 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_pairs(int64_t n, const int32_t* 
   }
 }
 
+// The paired-column product for wide blocks of right-hand sides, with the
+// block's run of (value, column) pairs staged in LDS first.  R = BLOCK / GP
+// rows per block: the run of their entries is loaded once, coalesced,
+// instead of once per lane of each row, and each lane then issues its X
+// gathers U entries at a time with a predicated tail, so a row of 27
+// entries costs four gather rounds, not three plus three dependent ones.
+// A block whose run exceeds CAP entries reads the pairs from global memory.
+// Each column is accumulated in entry order as in k_spmm_pairs (same bits).
+template <int GP, int BLOCK, bool FULL, int CAP>
+__global__ __launch_bounds__(BLOCK) void k_spmm_tile(int64_t n, const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val, int64_t nrhs,
+                                                     const double* __restrict__ X, int64_t ldx,
+                                                     double* __restrict__ Y, int64_t ldy) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  constexpr int R = BLOCK / GP;
+  constexpr int U = 8;
+  __shared__ double s_val[CAP];
+  __shared__ int32_t s_col[CAP];
+  if constexpr (FULL) {
+    ldx = ldy = nrhs = 2 * GP;
+  }
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int64_t rend = row0 + R < n ? row0 + R : n;
+  const int32_t e0 = rowptr[row0];
+  const int32_t cnt = rowptr[rend] - e0;
+  const bool staged = cnt <= CAP;
+  if (staged) {
+    for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+      s_val[i] = stream_load(val + e0 + i);
+      s_col[i] = stream_load(col + e0 + i);
+    }
+  }
+  __syncthreads();
+  const int64_t row = row0 + threadIdx.x / GP;
+  const int lane = threadIdx.x % GP;
+  if (row >= n) return;
+  const int32_t t0 = rowptr[row], t1 = rowptr[row + 1];
+  auto pair_at = [&](int32_t t, double& a, int64_t& c) {
+    if (staged) {
+      a = s_val[t - e0];
+      c = s_col[t - e0];
+    } else {
+      a = stream_load(val + t);
+      c = stream_load(col + t);
+    }
+  };
+  for (int64_t c0 = 0; c0 < nrhs; c0 += 2 * GP) {
+    const int64_t c = c0 + 2 * lane;
+    if (c >= nrhs) continue;
+    if (FULL || c + 1 < nrhs) {
+      d2 acc = {0.0, 0.0};
+      for (int32_t t = t0; t < t1; t += U) {
+        double a[U];
+        d2 xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (t + u < t1) {
+            int64_t cc;
+            pair_at(t + u, a[u], cc);
+            xv[u] = *reinterpret_cast<const d2*>(X + cc * ldx + c);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (t + u < t1) {
+            acc.x += a[u] * xv[u].x;
+            acc.y += a[u] * xv[u].y;
+          }
+        }
+      }
+      *reinterpret_cast<d2*>(Y + row * ldy + c) = acc;
+    } else {
+      double acc = 0.0;
+      for (int32_t t = t0; t < t1; t += U) {
+        double a[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (t + u < t1) {
+            int64_t cc;
+            pair_at(t + u, a[u], cc);
+            xv[u] = X[cc * ldx + c];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (t + u < t1) acc += a[u] * xv[u];
+      }
+      Y[row * ldy + c] = acc;
+    }
+  }
+}
+
 // Bandwidth references: the whole grid sweeps the array in lockstep, one
 // 16-byte non-temporal access per lane per step (measured to be the
 // pattern HBM serves best on this chip).
@@ -333,6 +426,18 @@ int launch_spmm_g(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, doub
   if (pairs) {
     constexpr int GP = G >= 2 ? G / 2 : 1;  // a lane per pair of columns
     const int64_t nb = ceil_div(A.n, BLOCK / GP);
+    if constexpr (G >= 8) {
+      // staged runs: room for 32 entries per row on average (12 KB at 16
+      // columns), plain block order (measured faster than the XCD order)
+      constexpr int CAP = 32 * (BLOCK / GP);
+      if (nrhs == G && ldx == G && ldy == G)
+        hipLaunchKernelGGL((k_spmm_tile<GP, BLOCK, true, CAP>), dim3((unsigned)nb), dim3(BLOCK), 0, s,
+                           A.n, A.rowptr, A.col, A.val, nrhs, X, ldx, Y, ldy);
+      else
+        hipLaunchKernelGGL((k_spmm_tile<GP, BLOCK, false, CAP>), dim3((unsigned)nb), dim3(BLOCK), 0,
+                           s, A.n, A.rowptr, A.col, A.val, nrhs, X, ldx, Y, ldy);
+      return SPX_OK;
+    }
     if (nrhs == G && ldx == G && ldy == G)
       hipLaunchKernelGGL((k_spmm_pairs<GP, BLOCK, true>), dim3((unsigned)nb), dim3(BLOCK), 0, s, A.n,
                          A.rowptr, A.col, A.val, nrhs, X, ldx, Y, ldy, 1);

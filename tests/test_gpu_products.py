@@ -151,6 +151,46 @@ def test_spmm_layouts_bitwise(orc):
             spmv_within(outs[0][:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
 
 
+@pytest.mark.parametrize("nrhs", [8, 13, 16, 32, 64, 65])
+def test_spmm_staged_runs_and_fallback(orc, nrhs):
+    """The staged-run kernel (8 or more columns, 16-byte aligned X and Y):
+    blocks whose run of entries fits the LDS stage and blocks that read their
+    pairs from global memory (32 rows of 60 entries overflow it), empty rows,
+    a ragged last block, contiguous X (one pass) and padded leading
+    dimensions, more than 64 columns (two column chunks, an odd last
+    column).  Bitwise the one-column-per-lane kernel, within the SpMV
+    tolerance of the oracle."""
+    import ctypes
+    spx = require_gpu()
+    lib = spx.load_library()
+    rng = np.random.default_rng(35 + nrhs)
+    n = 3001
+    lengths = np.where(np.arange(n) % 11 == 0, 0, np.where((np.arange(n) // 32) % 5 == 1, 60, 9))
+    i = np.repeat(np.arange(n, dtype=np.int32), lengths)
+    j = rng.integers(0, n, i.size).astype(np.int32)
+    v = rng.uniform(-1, 1, i.size)
+    prob = W.CooProblem(n=n, i=i, j=j, v=v)
+    A = assemble(spx, prob)
+    ref = orc.assemble(n, i, j, v)
+    Xh = rng.uniform(-1, 1, (n, nrhs))
+    Yr = orc.spmm(ref, Xh)
+    outs = []
+    for ld, shift in ((nrhs, 0), (nrhs + 2 if nrhs % 2 == 0 else nrhs + 1, 0), (nrhs + 1, 1)):
+        Xa = torch.zeros(n * ld + 2, dtype=torch.float64, device="cuda")
+        Xa[shift: shift + n * ld].view(n, ld)[:, :nrhs] = dev(Xh)
+        Y = torch.full((n * ld + 2,), np.nan, dtype=torch.float64, device="cuda")
+        rc = lib.spx_spmm(A.handle, nrhs, ctypes.c_void_p(Xa.data_ptr() + 8 * shift), ld,
+                          ctypes.c_void_p(Y.data_ptr()), ld, None)
+        assert rc == 0
+        Yo = host(Y[: n * ld].view(n, ld))
+        assert np.isnan(Yo[:, nrhs:]).all()  # padding untouched
+        outs.append(Yo[:, :nrhs])
+    for o in outs[1:]:
+        assert np.array_equal(bits(o), bits(outs[0]))
+    for c in range(nrhs):
+        spmv_within(outs[0][:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
+
+
 def test_sddmm_and_gather_bitwise(orc):
     spx = require_gpu()
     rng = np.random.default_rng(32)
