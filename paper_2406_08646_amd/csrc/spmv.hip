@@ -273,19 +273,21 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_pairs(int64_t n, const int32_t* 
 // block's run of (value, column) pairs staged in LDS first.  R = BLOCK / GP
 // rows per block: the run of their entries is loaded once, coalesced,
 // instead of once per lane of each row, and each lane then issues its X
-// gathers U entries at a time with a predicated tail, so a row of 27
-// entries costs four gather rounds, not three plus three dependent ones.
+// gathers U entries at a time with a predicated tail.  What bounds the
+// kernel is the number of resident waves, not the gathers in flight per
+// lane (2 to 8 per round measured the same at equal occupancy), so U is
+// small and the register budget is held to 8 waves per SIMD.
 // A block whose run exceeds CAP entries reads the pairs from global memory.
 // Each column is accumulated in entry order as in k_spmm_pairs (same bits).
 template <int GP, int BLOCK, bool FULL, int CAP>
-__global__ __launch_bounds__(BLOCK) void k_spmm_tile(int64_t n, const int32_t* __restrict__ rowptr,
+__global__ __launch_bounds__(BLOCK, 8) void k_spmm_tile(int64_t n, const int32_t* __restrict__ rowptr,
                                                      const int32_t* __restrict__ col,
                                                      const double* __restrict__ val, int64_t nrhs,
                                                      const double* __restrict__ X, int64_t ldx,
                                                      double* __restrict__ Y, int64_t ldy) {
   typedef double d2 __attribute__((ext_vector_type(2)));
   constexpr int R = BLOCK / GP;
-  constexpr int U = 8;
+  constexpr int U = 4;
   __shared__ double s_val[CAP];
   __shared__ int32_t s_col[CAP];
   if constexpr (FULL) {
@@ -293,6 +295,11 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_tile(int64_t n, const int32_t* _
   }
   const int64_t row0 = (int64_t)blockIdx.x * R;
   const int64_t rend = row0 + R < n ? row0 + R : n;
+  const int64_t row = row0 + threadIdx.x / GP;
+  const int lane = threadIdx.x % GP;
+  // the row's bounds are read before the barrier (a clamped row past n)
+  const int64_t rr = row < n ? row : n - 1;
+  const int32_t t0 = rowptr[rr], t1 = rowptr[rr + 1];
   const int32_t e0 = rowptr[row0];
   const int32_t cnt = rowptr[rend] - e0;
   const bool staged = cnt <= CAP;
@@ -303,10 +310,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmm_tile(int64_t n, const int32_t* _
     }
   }
   __syncthreads();
-  const int64_t row = row0 + threadIdx.x / GP;
-  const int lane = threadIdx.x % GP;
   if (row >= n) return;
-  const int32_t t0 = rowptr[row], t1 = rowptr[row + 1];
   auto pair_at = [&](int32_t t, double& a, int64_t& c) {
     if (staged) {
       a = s_val[t - e0];
