@@ -446,22 +446,43 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
             e2.record()
             evs.append((e0, e1, e2))
         torch.cuda.synchronize()
+        # the same step through the fused entry point (S^T g in the update's pass)
+        fevs = []
+        for k in range(8):
+            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            s_, y_ = hist[m_l + (k % 4)]
+            e0.record()
+            L.update_apply(s_, y_, g_, h0_, p_)
+            e1.record()
+            fevs.append((e0, e1))
+        torch.cuda.synchronize()
         upd = statistics.median(a.elapsed_time(b) for a, b, _ in evs)
         app = statistics.median(b.elapsed_time(c) for _, b, c in evs)
         t_ms = statistics.median(a.elapsed_time(c) for a, _, c in evs)
+        f_ms = statistics.median(a.elapsed_time(b) for a, b in fevs)
         be = 8 * n_l * (2 * m_l + 2) / (t_ms * 1e-3) / 1e9
+        be_f = 8 * n_l * (2 * m_l + 2) / (f_ms * 1e-3) / 1e9
+        y_passes = 2 if m_l <= 16 else 3  # update, a (with Y^T a up to 16 pairs), Y^T a
+        col_bytes = 8 * n_l * m_l
         lb.append({"n": n_l, "m": m_l, "update_ms": round(upd, 4), "apply_ms": round(app, 4),
                    "total_ms": round(t_ms, 4), "effective_gbs": round(be, 1),
-                   "hbm_bytes": 8 * n_l * (5 * m_l + 8),
-                   "hbm_gbs": round(8 * n_l * (5 * m_l + 8) / (t_ms * 1e-3) / 1e9, 1)})
-        log(f"lbfgs n={n_l} m={m_l}: update {upd:.3f} ms apply {app:.3f} ms B_e {be:.0f} GB/s")
+                   "hbm_bytes": col_bytes * (3 + y_passes) + 8 * 8 * n_l,
+                   "hbm_gbs": round((col_bytes * (3 + y_passes) + 8 * 8 * n_l) / (t_ms * 1e-3) / 1e9, 1),
+                   "fused_ms": round(f_ms, 4), "fused_effective_gbs": round(be_f, 1),
+                   "fused_hbm_gbs": round((col_bytes * (2 + y_passes) + 8 * 8 * n_l) / (f_ms * 1e-3) / 1e9,
+                                          1)})
+        log(f"lbfgs n={n_l} m={m_l}: update {upd:.3f} ms apply {app:.3f} ms B_e {be:.0f} GB/s; "
+            f"fused {f_ms:.3f} ms B_e {be_f:.0f} GB/s")
         L.destroy()
         del hist, dcurv, g_, h0_, p_
     out["lbfgs"] = {"points": lb,
                     "effective_bandwidth": "8 n (2m + 2) bytes / (T_update + T_apply): "
                                            "S and Y read once, g read, p written",
-                    "hbm_bytes": "bytes this design moves: S read 3 times and Y twice "
-                                 "(update, S^T g, a and Y^T a, p) plus 8 vector passes"}
+                    "hbm_bytes": "bytes this design moves: S read 3 times (update, S^T g, p), Y "
+                                 "twice up to 16 pairs (update; a with Y^T a) and 3 times above, "
+                                 "plus 8 vector passes; the fused step reads S twice",
+                    "fused": "spx_lbfgs_update_apply: the same step with S^T g taken in the "
+                             "update's pass over S (bitwise the two calls)"}
 
     # ---- gradient on 256 x 256 elements
     N = 256

@@ -289,6 +289,16 @@ int spx_lbfgs_update(spx_lbfgs_handle h, const double* s, const double* y, void*
 int spx_lbfgs_apply(spx_lbfgs_handle h, const double* g, const double* h0, double* p,
                     void* stream);
 
+/* spx_lbfgs_update(s, y) followed by spx_lbfgs_apply(g, h0, p), the step of
+ * an optimiser that takes its next direction right after storing the pair,
+ * with S^T g taken in the update's pass over S: one pass over S fewer (of
+ * three) for the same result, bit for bit.  When g, h0 and p would make
+ * the apply walk rows one at a time while the update walks them two at a
+ * time (even n, a pointer off a 16-byte boundary), the two run unfused.
+ * Same arguments, ownership and errors as the two calls.  Asynchronous. */
+int spx_lbfgs_update_apply(spx_lbfgs_handle h, const double* s, const double* y,
+                           const double* g, const double* h0, double* p, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Differentiation of u = A(v)^-1 b through the COO assembly (reverse mode).
  * ------------------------------------------------------------------------- */

@@ -151,6 +151,52 @@ __device__ __forceinline__ void gemvt_partials(int64_t n, const double* __restri
   }
 }
 
+// Partials of d_b = col_b . w1 (into row row1 + b of P) and e_b = col_b . w2
+// (row row2 + b) in one pass over the columns: half as many columns per
+// chunk, two accumulators each.  Every column's products are added in the
+// same per-thread row order as in gemvt_partials, so each total has the
+// bits of the single-vector pass.
+constexpr int kJT2 = kJT / 2;
+template <int V>
+__device__ __forceinline__ void gemvt2_partials(int64_t n, const double* __restrict__ base,
+                                                Ring R, const double* __restrict__ w1,
+                                                const double* __restrict__ w2,
+                                                double* __restrict__ P, int row1, int row2,
+                                                double* lds, double* tot) {
+  typedef typename Vd<V>::type VD;
+  int64_t lo, hi;
+  rows_of<V>(n, blockIdx.x, gridDim.x, &lo, &hi);
+  for (int jb = 0; jb < R.cnt; jb += kJT2) {
+    const int nc = R.cnt - jb < kJT2 ? R.cnt - jb : kJT2;
+    const double* cp[kJT2];
+#pragma unroll
+    for (int u = 0; u < kJT2; ++u) cp[u] = base + (u < nc ? R.slot(jb + u) : 0) * n;
+    double acc[kJT2], acc2[kJT2];
+#pragma unroll
+    for (int u = 0; u < kJT2; ++u) acc[u] = acc2[u] = 0.0;
+    for (int64_t i = lo + V * (int64_t)threadIdx.x; i < hi; i += V * kLB) {
+      const VD wv = ldv<V>(w1 + i);
+      const VD wv2 = ldv<V>(w2 + i);
+#pragma unroll
+      for (int u = 0; u < kJT2; ++u)
+        if (u < nc) {
+          const VD c = ldv<V>(cp[u] + i);
+#pragma unroll
+          for (int j = 0; j < V; ++j) {
+            acc[u] += el<V>(c, j) * el<V>(wv, j);
+            acc2[u] += el<V>(c, j) * el<V>(wv2, j);
+          }
+        }
+    }
+    block_sums<kJT2>(acc, nc, lds, tot);
+    if (threadIdx.x < nc)
+      P[(int64_t)(row1 + jb + threadIdx.x) * gridDim.x + blockIdx.x] = tot[threadIdx.x];
+    block_sums<kJT2>(acc2, nc, lds, tot);
+    if (threadIdx.x < nc)
+      P[(int64_t)(row2 + jb + threadIdx.x) * gridDim.x + blockIdx.x] = tot[threadIdx.x];
+  }
+}
+
 // ---------------------------------------------------------------- update
 __global__ void k_lb_put(int64_t n, const double* __restrict__ s, const double* __restrict__ y,
                          double* __restrict__ Snew, double* __restrict__ Ynew) {
@@ -173,6 +219,20 @@ __global__ __launch_bounds__(kLB) void k_lb_update(int64_t n, const double* __re
   const int64_t cur = R.slot(R.cnt - 1) * n;
   gemvt_partials<V>(n, Y, R, S + cur, P, 0, lds, tot);
   gemvt_partials<V>(n, S, R, Y + cur, P, kMaxHistory, lds, tot);
+}
+
+// The update's pass with the apply's first one folded in: the pass over S
+// also takes the partials of q_b = s_b . g (rows 2 kMaxHistory + b).
+template <int V>
+__global__ __launch_bounds__(kLB) void k_lb_update_g(int64_t n, const double* __restrict__ S,
+                                                     const double* __restrict__ Y, Ring R,
+                                                     const double* __restrict__ g,
+                                                     double* __restrict__ P) {
+  __shared__ double lds[(kLB / 64) * kJT];
+  __shared__ double tot[kJT];
+  const int64_t cur = R.slot(R.cnt - 1) * n;
+  gemvt_partials<V>(n, Y, R, S + cur, P, 0, lds, tot);
+  gemvt2_partials<V>(n, S, R, Y + cur, g, P, kMaxHistory, 2 * kMaxHistory, lds, tot);
 }
 
 // one workgroup per (kind, logical index): SY row and column of the new slot
@@ -346,14 +406,22 @@ using namespace spx::solver;
 
 namespace {
 // The apply's passes with rows taken V at a time.
+// With have_q the partials of S^T g are already in rows 2 kMaxHistory + b of
+// the workspace (left there by the fused update).
 template <int V>
-int apply_passes(spx_lbfgs* h, const double* g, const double* h0, double* p, hipStream_t st) {
+int apply_passes(spx_lbfgs* h, const double* g, const double* h0, double* p, hipStream_t st,
+                 bool have_q = false) {
   const int64_t n = h->n;
   const int cnt = h->count;
   const int G = h->G;
   const Ring R{h->m, h->start, cnt};
-  hipLaunchKernelGGL(k_lb_sg<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, g, h->P);
-  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
+  if (have_q) {
+    hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st,
+                       h->P + (int64_t)2 * kMaxHistory * G, G, h->red);
+  } else {
+    hipLaunchKernelGGL(k_lb_sg<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, g, h->P);
+    hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
+  }
   if (cnt <= kFused) {
     hipLaunchKernelGGL((k_lb_ya<true, V>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
                        h->red, h->a, h->P);
@@ -387,7 +455,7 @@ extern "C" int spx_lbfgs_create(int64_t n, int32_t m, void* stream, spx_lbfgs_ha
     if ((st = dalloc_n(&h->S, (size_t)n * m)) != SPX_OK) break;
     if ((st = dalloc_n(&h->Y, (size_t)n * m)) != SPX_OK) break;
     if ((st = dalloc_n(&h->SY, (size_t)m * m)) != SPX_OK) break;
-    if ((st = dalloc_n(&h->P, (size_t)2 * kMaxHistory * h->G)) != SPX_OK) break;
+    if ((st = dalloc_n(&h->P, (size_t)3 * kMaxHistory * h->G)) != SPX_OK) break;
     if ((st = dalloc_n(&h->red, (size_t)5 * kMaxHistory)) != SPX_OK) break;
     if ((st = dalloc_n(&h->a, (size_t)n)) != SPX_OK) break;
   } while (false);
@@ -429,11 +497,12 @@ extern "C" int spx_lbfgs_get_info(spx_lbfgs_handle h, int64_t* n, int32_t* m, in
   return SPX_OK;
 }
 
-extern "C" int spx_lbfgs_update(spx_lbfgs_handle h, const double* s, const double* y,
-                                void* stream) {
-  clear_error();
-  if (!h || !s || !y) return set_error(SPX_INVALID_ARG, "lbfgs_update: NULL argument");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+namespace {
+// The update; with g (non-NULL) the pass over S also leaves the partials of
+// S^T g for the apply that follows (the caller has checked that g's row
+// width matches the update's).
+int update_impl(spx_lbfgs* h, const double* s, const double* y, const double* g,
+                hipStream_t st) {
   int slot, start, cnt;
   if (h->count < h->m) {
     slot = (h->start + h->count) % h->m;
@@ -448,14 +517,53 @@ extern "C" int spx_lbfgs_update(spx_lbfgs_handle h, const double* s, const doubl
   const Ring R{h->m, start, cnt};
   hipLaunchKernelGGL(k_lb_put, dim3((unsigned)ceil_div(h->n, 256)), dim3(256), 0, st, h->n, s, y,
                      h->S + (int64_t)slot * h->n, h->Y + (int64_t)slot * h->n);
-  if (h->n % 2 == 0)
+  if (g) {
+    if (h->n % 2 == 0)
+      hipLaunchKernelGGL(k_lb_update_g<2>, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, R, g, h->P);
+    else
+      hipLaunchKernelGGL(k_lb_update_g<1>, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, R, g, h->P);
+  } else if (h->n % 2 == 0) {
     hipLaunchKernelGGL(k_lb_update<2>, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, R, h->P);
-  else
+  } else {
     hipLaunchKernelGGL(k_lb_update<1>, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, R, h->P);
+  }
   hipLaunchKernelGGL(k_lb_update_finish, dim3(2 * cnt), dim3(kLB), 0, st, h->P, G, R, slot, h->SY);
   SPX_CHECK_HIP(hipGetLastError());
   h->start = start;
   h->count = cnt;
+  return SPX_OK;
+}
+
+// Rows go two at a time when n is even and g, h0, p are 16-byte aligned.
+bool wide_rows(const spx_lbfgs* h, const double* g, const double* h0, const double* p) {
+  return h->n % 2 == 0 && ((reinterpret_cast<uintptr_t>(g) | reinterpret_cast<uintptr_t>(h0) |
+                            reinterpret_cast<uintptr_t>(p)) & 15) == 0;
+}
+}  // namespace
+
+extern "C" int spx_lbfgs_update(spx_lbfgs_handle h, const double* s, const double* y,
+                                void* stream) {
+  clear_error();
+  if (!h || !s || !y) return set_error(SPX_INVALID_ARG, "lbfgs_update: NULL argument");
+  return update_impl(h, s, y, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int spx_lbfgs_update_apply(spx_lbfgs_handle h, const double* s, const double* y,
+                                      const double* g, const double* h0, double* p,
+                                      void* stream) {
+  clear_error();
+  if (!h || !s || !y || !g || !p)
+    return set_error(SPX_INVALID_ARG, "lbfgs_update_apply: NULL argument");
+  if (p == g) return set_error(SPX_INVALID_ARG, "lbfgs_update_apply: p must not alias g");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool wide = wide_rows(h, g, h0, p);
+  // the folded pass walks rows as the update does (two at a time for even
+  // n); when the apply would walk them otherwise, the two run separately so
+  // that the result is the same either way
+  const bool fold = wide == (h->n % 2 == 0);
+  SPX_TRY(update_impl(h, s, y, fold ? g : nullptr, st));
+  SPX_TRY(wide ? apply_passes<2>(h, g, h0, p, st, fold) : apply_passes<1>(h, g, h0, p, st, fold));
+  SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }
 
@@ -472,9 +580,7 @@ extern "C" int spx_lbfgs_apply(spx_lbfgs_handle h, const double* g, const double
     SPX_CHECK_HIP(hipGetLastError());
     return SPX_OK;
   }
-  const bool wide = n % 2 == 0 && ((reinterpret_cast<uintptr_t>(g) |
-                                      reinterpret_cast<uintptr_t>(h0) |
-                                      reinterpret_cast<uintptr_t>(p)) & 15) == 0;
+  const bool wide = wide_rows(h, g, h0, p);
   SPX_TRY(wide ? apply_passes<2>(h, g, h0, p, st) : apply_passes<1>(h, g, h0, p, st));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;

@@ -82,6 +82,7 @@ _SIGNATURES = {
     "spx_lbfgs_get_info": [_vp, _pi64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "spx_lbfgs_update": [_vp, _vp, _vp, _vp],
     "spx_lbfgs_apply": [_vp, _vp, _vp, _vp, _vp],
+    "spx_lbfgs_update_apply": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "spx_set_allocator": [_vp, _vp, _vp],
     "spx_stream_copy": [_vp, _vp, _i64, _vp],
     "spx_stream_sum": [_vp, _i64, _vp, _vp],
@@ -518,6 +519,20 @@ class Lbfgs:
         p = torch.empty_like(g) if p is None else _dev(p, torch.float64, self.n, "p")
         _check(load_library().spx_lbfgs_apply(self._h, _ptr(g), _ptr(h0) if h0 is not None else None,
                                               _ptr(p), _stream(stream)))
+        return p
+
+    def update_apply(self, s, y, g, h0=None, p=None, stream=None):
+        """update(s, y) then apply(g, h0, p), with S^T g taken in the
+        update's pass over S (the same bits as the two calls)."""
+        _dev(s, torch.float64, self.n, "s")
+        _dev(y, torch.float64, self.n, "y")
+        _dev(g, torch.float64, self.n, "g")
+        if h0 is not None:
+            _dev(h0, torch.float64, self.n, "h0")
+        p = torch.empty_like(g) if p is None else _dev(p, torch.float64, self.n, "p")
+        _check(load_library().spx_lbfgs_update_apply(self._h, _ptr(s), _ptr(y), _ptr(g),
+                                                     _ptr(h0) if h0 is not None else None,
+                                                     _ptr(p), _stream(stream)))
         return p
 
     def reset(self) -> None:

@@ -109,3 +109,33 @@ def test_lbfgs_unaligned_vectors(orc):
     for p in (p_al, p_un):
         assert np.linalg.norm(p - ref) <= tol(n) * np.linalg.norm(ref)
     assert np.linalg.norm(p_un - p_al) <= tol(n) * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,m,pushes,offset", [(3000, 5, 12, 0), (2049, 7, 10, 0), (4096, 20, 24, 0),
+                                               (4096, 20, 6, 1), (1000, 64, 3, 0)])
+def test_lbfgs_update_apply_same_bits(orc, n, m, pushes, offset):
+    """The fused step equals update then apply bit for bit, through ring
+    wrap-around, for even n (two rows per thread), odd n (one), and vectors
+    off a 16-byte boundary (taken unfused); and matches the oracle."""
+    spx = require_gpu()
+    S, Y, g, h0 = W.lbfgs_history(n, pushes, seed=60 + m)
+    A, B = spx.lbfgs_create(n, m), spx.lbfgs_create(n, m)
+    bufs = [torch.zeros(n + offset, dtype=torch.float64, device="cuda") for _ in range(3)]
+    bufs[0][offset:] = dev(g)
+    bufs[1][offset:] = dev(h0)
+    gd, h0d, pd = (b[offset:] for b in bufs)
+    for k in range(1, pushes + 1):
+        s, y = dev(np.ascontiguousarray(S[:, k - 1])), dev(np.ascontiguousarray(Y[:, k - 1]))
+        A.update(s, y)
+        pa = host(A.apply(gd, h0d))
+        B.update_apply(s, y, gd, h0d, p=pd)
+        pb = host(pd)
+        assert A.count == B.count == min(k, m)
+        assert np.array_equal(pa.view(np.int64), pb.view(np.int64)), k
+        Sk, Yk = pairs_in_use(S, Y, k, m)
+        ref = orc.lbfgs_dense(Sk, Yk, g, h0)
+        assert np.linalg.norm(pb - ref) <= tol(n) * np.linalg.norm(ref), k
+    # the products the update stored serve later plain applies
+    assert np.array_equal(host(A.apply(gd)).view(np.int64), host(B.apply(gd)).view(np.int64))
+    with pytest.raises(spx.SpxError):
+        B.update_apply(s, y, gd, p=gd)
