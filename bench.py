@@ -115,7 +115,11 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
+EXTRAS = ("ceilings", "spmm16", "vec_coo", "cg_forms", "c1_cg", "one_gpu_share", "sync_vs_async",
+          "batched64", "nonsymmetric_batch64", "lbfgs", "gradient256")
+
+
+def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
     """Measurements of the other workloads, outside the timed steps: the
     16-RHS SpMM and the single-reduction vs textbook CG on the full 3-D
     matrix, the 64-system batch (batched vs ensemble vs one solve per
@@ -124,6 +128,16 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
 
     out = {}
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    want = lambda name: only is None or name in only
+    shared = {}
+
+    def main_matrix():
+        """The full 3-D matrix, assembled once for the sections that use it."""
+        if "A" not in shared:
+            M = spx.coo_preallocate(prob.n, d(prob.i), d(prob.j))
+            M.set_values_coo(d(prob.v))
+            shared["A"] = M
+        return shared["A"]
 
     def timed(fn, reps=1):
         best = None
@@ -136,8 +150,6 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
             best = ms if best is None else min(best, ms)
         return best, r
 
-    # ---- what this device sustains: the library's copy and read references over
-    # 2 GiB (HBM) and a copy over 2 x 96 MiB (resident in the 256 MB last-level cache)
     def ev_ms(fn, reps=20):
         for _ in range(3):
             fn()
@@ -149,363 +161,377 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log):
             e_.record()
         torch.cuda.synchronize()
         return statistics.median(s_.elapsed_time(e_) for s_, e_ in evs)
-    big = torch.ones(2**28, dtype=torch.float64, device=dev)
-    big2 = torch.empty_like(big)
-    parts = torch.empty(2048, dtype=torch.float64, device=dev)
-    copy_ms = ev_ms(lambda: spx.stream_copy(big, big2))
-    read_ms = ev_ms(lambda: spx.stream_sum(big, parts))
-    del big, big2
-    small = torch.ones(12 * 2**20, dtype=torch.float64, device=dev)
-    small2 = torch.empty_like(small)
-    mall_ms = ev_ms(lambda: spx.stream_copy(small, small2), reps=50)
-    del small, small2
-    out["ceilings"] = {"copy_hbm_gbs": round(2 * 8 * 2**28 / (copy_ms * 1e-3) / 1e9, 1),
-                       "read_hbm_gbs": round(8 * 2**28 / (read_ms * 1e-3) / 1e9, 1),
-                       "copy_llc_resident_gbs": round(2 * 8 * 12 * 2**20 / (mall_ms * 1e-3) / 1e9, 1)}
-    log(f"ceilings: {out['ceilings']}")
+
+    # ---- what this device sustains: the library's copy and read references over
+    # 2 GiB (HBM) and a copy over 2 x 96 MiB (resident in the 256 MB last-level cache)
+    if want("ceilings"):
+        big = torch.ones(2**28, dtype=torch.float64, device=dev)
+        big2 = torch.empty_like(big)
+        parts = torch.empty(2048, dtype=torch.float64, device=dev)
+        copy_ms = ev_ms(lambda: spx.stream_copy(big, big2))
+        read_ms = ev_ms(lambda: spx.stream_sum(big, parts))
+        del big, big2
+        small = torch.ones(12 * 2**20, dtype=torch.float64, device=dev)
+        small2 = torch.empty_like(small)
+        mall_ms = ev_ms(lambda: spx.stream_copy(small, small2), reps=50)
+        del small, small2
+        out["ceilings"] = {"copy_hbm_gbs": round(2 * 8 * 2**28 / (copy_ms * 1e-3) / 1e9, 1),
+                           "read_hbm_gbs": round(8 * 2**28 / (read_ms * 1e-3) / 1e9, 1),
+                           "copy_llc_resident_gbs": round(2 * 8 * 12 * 2**20 / (mall_ms * 1e-3) / 1e9, 1)}
+        log(f"ceilings: {out['ceilings']}")
 
     # ---- multi-RHS SpMM on the full 3-D matrix
-    A = spx.coo_preallocate(prob.n, d(prob.i), d(prob.j))
-    A.set_values_coo(d(prob.v))
-    X = d(W.spmm_rhs(prob.n, 16))
-    Y = torch.empty_like(X)
-    for _ in range(3):
-        A.spmm(X, Y)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
-    for s_, e_ in ev:
-        s_.record()
-        A.spmm(X, Y)
-        e_.record()
-    torch.cuda.synchronize()
-    spmm_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
-    nnz = A.nnz
-    spmm_bytes = nnz * 12 + (prob.n + 1) * 4 + 2 * 16 * 8 * prob.n
-    xd, yd = d(x_np), torch.empty(prob.n, dtype=torch.float64, device=dev)
-    for s_, e_ in ev:
-        s_.record()
-        A.matmult(xd, yd)
-        e_.record()
-    torch.cuda.synchronize()
-    mv_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
-    out["spmm16"] = {"ms": round(spmm_ms, 4), "bytes": spmm_bytes,
-                     "gbs": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
-                     "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
-    log(f"spmm16: {spmm_ms:.3f} ms")
+    if want("spmm16"):
+        A = main_matrix()
+        X = d(W.spmm_rhs(prob.n, 16))
+        Y = torch.empty_like(X)
+        for _ in range(3):
+            A.spmm(X, Y)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+        for s_, e_ in ev:
+            s_.record()
+            A.spmm(X, Y)
+            e_.record()
+        torch.cuda.synchronize()
+        spmm_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
+        nnz = A.nnz
+        spmm_bytes = nnz * 12 + (prob.n + 1) * 4 + 2 * 16 * 8 * prob.n
+        xd, yd = d(x_np), torch.empty(prob.n, dtype=torch.float64, device=dev)
+        for s_, e_ in ev:
+            s_.record()
+            A.matmult(xd, yd)
+            e_.record()
+        torch.cuda.synchronize()
+        mv_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
+        out["spmm16"] = {"ms": round(spmm_ms, 4), "bytes": spmm_bytes,
+                         "gbs": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
+                         "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
+        log(f"spmm16: {spmm_ms:.3f} ms")
 
     # ---- COO vector assembly: the element load vector of the same mesh (8 contributions
     # per element, one per local node, in element order)
-    iv = d(np.ascontiguousarray(prob.i.reshape(-1, prob.nloc, prob.nloc)[:, :, 0].reshape(-1)))
-    vv = d(W.spmm_rhs(iv.numel(), 1).reshape(-1))
-    xv = torch.zeros(prob.n, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    V = spx.vec_coo_preallocate(prob.n, iv)
-    torch.cuda.synchronize()
-    pre_ms = (time.perf_counter() - t0) * 1e3
-    info = V.get_info()
-    for _ in range(3):
-        V.set_values_coo(vv, xv)
-    evv = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
-    for s_, e_ in evv:
-        s_.record()
-        V.set_values_coo(vv, xv)
-        e_.record()
-    torch.cuda.synchronize()
-    vset_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in evv)
-    ncv, nuq = iv.numel(), int(info["nunique"])
-    vbytes = ncv * 8 + ncv * 4 + (nuq + 1) * 4 + nuq * 8 + nuq * 4
-    out["vec_coo"] = {"ncoo": ncv, "entries": nuq, "preallocate_ms": round(pre_ms, 3),
-                      "set_values_ms": round(vset_ms, 4), "bytes": vbytes,
-                      "gbs": round(vbytes / (vset_ms * 1e-3) / 1e9, 1)}
-    log(f"vec_coo: {ncv} triplets -> {nuq} entries, set_values {vset_ms:.3f} ms")
-    V.destroy()
-    del iv, vv, xv
+    if want("vec_coo"):
+        iv = d(np.ascontiguousarray(prob.i.reshape(-1, prob.nloc, prob.nloc)[:, :, 0].reshape(-1)))
+        vv = d(W.spmm_rhs(iv.numel(), 1).reshape(-1))
+        xv = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V = spx.vec_coo_preallocate(prob.n, iv)
+        torch.cuda.synchronize()
+        pre_ms = (time.perf_counter() - t0) * 1e3
+        info = V.get_info()
+        for _ in range(3):
+            V.set_values_coo(vv, xv)
+        evv = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+        for s_, e_ in evv:
+            s_.record()
+            V.set_values_coo(vv, xv)
+            e_.record()
+        torch.cuda.synchronize()
+        vset_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in evv)
+        ncv, nuq = iv.numel(), int(info["nunique"])
+        vbytes = ncv * 8 + ncv * 4 + (nuq + 1) * 4 + nuq * 8 + nuq * 4
+        out["vec_coo"] = {"ncoo": ncv, "entries": nuq, "preallocate_ms": round(pre_ms, 3),
+                          "set_values_ms": round(vset_ms, 4), "bytes": vbytes,
+                          "gbs": round(vbytes / (vset_ms * 1e-3) / 1e9, 1)}
+        log(f"vec_coo: {ncv} triplets -> {nuq} entries, set_values {vset_ms:.3f} ms")
+        V.destroy()
+        del iv, vv, xv
 
     # ---- single-reduction vs textbook CG on the same matrix and b
-    b_d = d(b_np)
-    forms = {}
-    for name, variant in (("textbook", 0), ("single_reduction", 1)):
-        A.set_option(spx.OPT_CG_VARIANT, variant)
-        A.cg_solve(b_d, rtol=1e-10)  # warm
-        A.set_option(spx.OPT_PROFILE, 1)
-        A.reset_profile()
-        A.cg_solve(b_d, rtol=1e-10)
-        prof = A.get_profile()
-        A.set_option(spx.OPT_PROFILE, 0)
-        ms_plain, r2 = timed(lambda: A.cg_solve(b_d, rtol=1e-10), reps=2)
-        forms[name] = {"ms": round(ms_plain, 2), "iters": r2.iters, "relres": r2.relres,
-                       "status": r2.status,
-                       "ms_per_iter": round(ms_plain / max(1, r2.iters), 4),
-                       "kernels_ms": {k: round(v[0] / max(1, v[1]), 4)
-                                      for k, v in prof.items() if v[1] > 0}}
-    A.set_option(spx.OPT_CG_VARIANT, 0)
-    forms["speedup"] = round(forms["textbook"]["ms_per_iter"]
-                             / forms["single_reduction"]["ms_per_iter"], 3)
-    out["cg_forms"] = forms
-    log(f"cg forms: textbook {forms['textbook']['ms_per_iter']} ms/it, single reduction "
-        f"{forms['single_reduction']['ms_per_iter']} ms/it")
-    A.destroy()
-    del X, Y
+    if want("cg_forms"):
+        A = main_matrix()
+        b_d = d(b_np)
+        forms = {}
+        for name, variant in (("textbook", 0), ("single_reduction", 1)):
+            A.set_option(spx.OPT_CG_VARIANT, variant)
+            A.cg_solve(b_d, rtol=1e-10)  # warm
+            A.set_option(spx.OPT_PROFILE, 1)
+            A.reset_profile()
+            A.cg_solve(b_d, rtol=1e-10)
+            prof = A.get_profile()
+            A.set_option(spx.OPT_PROFILE, 0)
+            ms_plain, r2 = timed(lambda: A.cg_solve(b_d, rtol=1e-10), reps=2)
+            forms[name] = {"ms": round(ms_plain, 2), "iters": r2.iters, "relres": r2.relres,
+                           "status": r2.status,
+                           "ms_per_iter": round(ms_plain / max(1, r2.iters), 4),
+                           "kernels_ms": {k: round(v[0] / max(1, v[1]), 4)
+                                          for k, v in prof.items() if v[1] > 0}}
+        A.set_option(spx.OPT_CG_VARIANT, 0)
+        forms["speedup"] = round(forms["textbook"]["ms_per_iter"]
+                                 / forms["single_reduction"]["ms_per_iter"], 3)
+        out["cg_forms"] = forms
+        log(f"cg forms: textbook {forms['textbook']['ms_per_iter']} ms/it, single reduction "
+            f"{forms['single_reduction']['ms_per_iter']} ms/it")
+        A.destroy()
+        del X, Y
 
     # ---- C1 (2-D Q1, 63^2 elements): CG latency per iteration, grid path and one workgroup
-    p1, _, b1 = W.config1()
-    A1 = spx.coo_preallocate(p1.n, d(p1.i), d(p1.j))
-    A1.set_values_coo(d(p1.v))
-    b1d = d(b1)
-    c1 = {"n": p1.n, "nnz": A1.nnz}
-    for mode, form, tag in ((0, 0, "grid"), (2, 0, "one_workgroup"),
-                            (0, 1, "single_reduction")):
-        A1.set_option(spx.OPT_SMALL_SOLVE, mode)
-        A1.set_option(spx.OPT_CG_VARIANT, form)
-        A1.cg_solve(b1d, rtol=1e-8)
-        ms, r = timed(lambda: A1.cg_solve(b1d, rtol=1e-8), reps=3)
-        c1[tag] = {"ms": round(ms, 3), "iters": r.iters, "relres": r.relres,
-                   "us_per_iter": round(1e3 * ms / max(1, r.iters), 2)}
-    A1.set_option(spx.OPT_CG_VARIANT, 0)
-    out["c1_cg"] = c1
-    log(f"C1 CG: {c1}")
-    A1.destroy()
+    if want("c1_cg"):
+        p1, _, b1 = W.config1()
+        A1 = spx.coo_preallocate(p1.n, d(p1.i), d(p1.j))
+        A1.set_values_coo(d(p1.v))
+        b1d = d(b1)
+        c1 = {"n": p1.n, "nnz": A1.nnz}
+        for mode, form, tag in ((0, 0, "grid"), (2, 0, "one_workgroup"),
+                                (0, 1, "single_reduction")):
+            A1.set_option(spx.OPT_SMALL_SOLVE, mode)
+            A1.set_option(spx.OPT_CG_VARIANT, form)
+            A1.cg_solve(b1d, rtol=1e-8)
+            ms, r = timed(lambda: A1.cg_solve(b1d, rtol=1e-8), reps=3)
+            c1[tag] = {"ms": round(ms, 3), "iters": r.iters, "relres": r.relres,
+                       "us_per_iter": round(1e3 * ms / max(1, r.iters), 2)}
+        A1.set_option(spx.OPT_CG_VARIANT, 0)
+        out["c1_cg"] = c1
+        log(f"C1 CG: {c1}")
+        A1.destroy()
 
     # ---- one GPU's share of an 8-way row-slab partition of the 3-D matrix: rows of a
     # 128 x 128 x 16 slab; the diagonal block (columns in the slab) and the off-diagonal
     # block (ghost columns of the two neighbouring planes, renumbered 0..2*128^2-1)
-    M = prob.grid + 1
-    plane = M * M
-    z0 = 3 * 16
-    lo_r, hi_r = z0 * plane, (z0 + 16) * plane
-    keep = (prob.i >= lo_r) & (prob.i < hi_r) & (prob.j >= 0)
-    ii, jj, vv_ = prob.i[keep] - lo_r, prob.j[keep], prob.v[keep]
-    inside = (jj >= lo_r) & (jj < hi_r)
-    gcol = np.where(jj < lo_r, jj - (lo_r - plane), jj - hi_r + plane)
-    Dg = spx.coo_preallocate(16 * plane, d(ii[inside].astype(np.int32)),
-                             d((jj[inside] - lo_r).astype(np.int32)))
-    Dg.set_values_coo(d(vv_[inside]))
-    ng = 16 * plane
-    # off-diagonal block as a square operator on [ghosts | local rows]: rows ii, columns
-    # the ghost indices (the first 2*plane unknowns)
-    Og = spx.coo_preallocate(max(ng, 2 * plane), d(ii[~inside].astype(np.int32)),
-                             d(gcol[~inside].astype(np.int32)))
-    Og.set_values_coo(d(vv_[~inside]))
-    xs_ = torch.ones(ng, dtype=torch.float64, device=dev)
-    ys_ = torch.empty_like(xs_)
-    xg = torch.ones(max(ng, 2 * plane), dtype=torch.float64, device=dev)
-    yg = torch.empty_like(xg)
-    dms = ev_ms(lambda: Dg.matmult(xs_, ys_))
-    oms = ev_ms(lambda: Og.matmult(xg, yg))
-    dbytes = Dg.nnz * 12 + (ng + 1) * 4 + 16 * ng
-    out["one_gpu_share"] = {"rows": ng, "diag_nnz": Dg.nnz, "offdiag_nnz": Og.nnz,
-                            "ghosts": 2 * plane, "diag_ms": round(dms, 4),
-                            "diag_gbs": round(dbytes / (dms * 1e-3) / 1e9, 1),
-                            "offdiag_ms": round(oms, 4),
-                            "halo_bytes_per_neighbour": plane * 8,
-                            "note": "the off-diagonal block runs as a CSR product over all local "
-                                    "rows, most of them empty; the halo exchange it waits for "
-                                    "is not built (one GPU)"}
-    log(f"one-GPU share: {out['one_gpu_share']}")
-    Dg.destroy()
-    Og.destroy()
+    if want("one_gpu_share"):
+        M = prob.grid + 1
+        plane = M * M
+        z0 = 3 * 16
+        lo_r, hi_r = z0 * plane, (z0 + 16) * plane
+        keep = (prob.i >= lo_r) & (prob.i < hi_r) & (prob.j >= 0)
+        ii, jj, vv_ = prob.i[keep] - lo_r, prob.j[keep], prob.v[keep]
+        inside = (jj >= lo_r) & (jj < hi_r)
+        gcol = np.where(jj < lo_r, jj - (lo_r - plane), jj - hi_r + plane)
+        Dg = spx.coo_preallocate(16 * plane, d(ii[inside].astype(np.int32)),
+                                 d((jj[inside] - lo_r).astype(np.int32)))
+        Dg.set_values_coo(d(vv_[inside]))
+        ng = 16 * plane
+        # off-diagonal block as a square operator on [ghosts | local rows]: rows ii, columns
+        # the ghost indices (the first 2*plane unknowns)
+        Og = spx.coo_preallocate(max(ng, 2 * plane), d(ii[~inside].astype(np.int32)),
+                                 d(gcol[~inside].astype(np.int32)))
+        Og.set_values_coo(d(vv_[~inside]))
+        xs_ = torch.ones(ng, dtype=torch.float64, device=dev)
+        ys_ = torch.empty_like(xs_)
+        xg = torch.ones(max(ng, 2 * plane), dtype=torch.float64, device=dev)
+        yg = torch.empty_like(xg)
+        dms = ev_ms(lambda: Dg.matmult(xs_, ys_))
+        oms = ev_ms(lambda: Og.matmult(xg, yg))
+        dbytes = Dg.nnz * 12 + (ng + 1) * 4 + 16 * ng
+        out["one_gpu_share"] = {"rows": ng, "diag_nnz": Dg.nnz, "offdiag_nnz": Og.nnz,
+                                "ghosts": 2 * plane, "diag_ms": round(dms, 4),
+                                "diag_gbs": round(dbytes / (dms * 1e-3) / 1e9, 1),
+                                "offdiag_ms": round(oms, 4),
+                                "halo_bytes_per_neighbour": plane * 8,
+                                "note": "the off-diagonal block runs as a CSR product over all local "
+                                        "rows, most of them empty; the halo exchange it waits for "
+                                        "is not built (one GPU)"}
+        log(f"one-GPU share: {out['one_gpu_share']}")
+        Dg.destroy()
+        Og.destroy()
 
     # ---- host poll after every iteration ("synchronous") vs every 20 ("asynchronous"),
     # time per iteration against the number of nonzeros, CG and TFQMR
-    curve = []
-    for dim, N in ((2, 16), (2, 32), (2, 64), (2, 128), (2, 256), (2, 512), (3, 24), (3, 48),
-                   (3, 96)):
-        pq = W.q1_poisson(N, dim)
-        Aq = spx.coo_preallocate(pq.n, d(pq.i), d(pq.j))
-        Aq.set_values_coo(d(pq.v))
-        bq = torch.ones(pq.n, dtype=torch.float64, device=dev)
-        one = spx.batch_create([Aq])
-        row = {"dim": dim, "grid": N, "n": pq.n, "nnz": Aq.nnz}
-        for ce, tag in ((1, "sync"), (20, "async")):
-            Aq.cg_solve(bq, rtol=0.0, maxit=20, check_every=ce)
-            ms, r = timed(lambda: Aq.cg_solve(bq, rtol=0.0, maxit=200, check_every=ce), reps=3)
-            row[f"cg_{tag}_us_per_iter"] = round(1e3 * ms / max(1, r.iters), 2)
-            one.batch_tfqmr(bq, rtol=0.0, maxit=20, check_every=ce)
-            ms, r = timed(lambda: one.batch_tfqmr(bq, rtol=0.0, maxit=400, check_every=ce), reps=3)
-            row[f"tfqmr_{tag}_us_per_halfstep"] = round(1e3 * ms / max(1, r[1][0]), 2)
-        xq = torch.zeros_like(bq)
-        Aq.set_option(spx.OPT_GRAPH, 1)
-        Aq.cg_solve(bq, x=xq.zero_(), rtol=0.0, maxit=200, check_every=20)  # capture
-        ms, r = timed(lambda: Aq.cg_solve(bq, x=xq.zero_(), rtol=0.0, maxit=200, check_every=20),
-                      reps=3)
-        Aq.set_option(spx.OPT_GRAPH, 0)
-        row["cg_async_graph_us_per_iter"] = round(1e3 * ms / max(1, r.iters), 2)
-        row["cg_async_speedup"] = round(row["cg_sync_us_per_iter"] / row["cg_async_us_per_iter"], 2)
-        row["cg_graph_speedup"] = round(row["cg_sync_us_per_iter"] / row["cg_async_graph_us_per_iter"], 2)
-        row["tfqmr_async_speedup"] = round(row["tfqmr_sync_us_per_halfstep"]
-                                           / row["tfqmr_async_us_per_halfstep"], 2)
-        curve.append(row)
-        log(f"async curve nnz={Aq.nnz}: cg {row['cg_sync_us_per_iter']} vs "
-            f"{row['cg_async_us_per_iter']} (graph {row['cg_async_graph_us_per_iter']}) us/it, tfqmr {row['tfqmr_sync_us_per_halfstep']} vs "
-            f"{row['tfqmr_async_us_per_halfstep']} us/half-step")
-        one.destroy()
-        Aq.destroy()
-    out["sync_vs_async"] = {"points": curve,
-                            "note": "host polls the device stop flag after every iteration (sync) "
-                                    "or every 20 (async, also with each chunk replayed as one HIP "
-                                    "graph); 200 CG iterations / 400 TFQMR half-steps with rtol = 0, "
-                                    "time per iteration"}
+    if want("sync_vs_async"):
+        curve = []
+        for dim, N in ((2, 16), (2, 32), (2, 64), (2, 128), (2, 256), (2, 512), (3, 24), (3, 48),
+                       (3, 96)):
+            pq = W.q1_poisson(N, dim)
+            Aq = spx.coo_preallocate(pq.n, d(pq.i), d(pq.j))
+            Aq.set_values_coo(d(pq.v))
+            bq = torch.ones(pq.n, dtype=torch.float64, device=dev)
+            one = spx.batch_create([Aq])
+            row = {"dim": dim, "grid": N, "n": pq.n, "nnz": Aq.nnz}
+            for ce, tag in ((1, "sync"), (20, "async")):
+                Aq.cg_solve(bq, rtol=0.0, maxit=20, check_every=ce)
+                ms, r = timed(lambda: Aq.cg_solve(bq, rtol=0.0, maxit=200, check_every=ce), reps=3)
+                row[f"cg_{tag}_us_per_iter"] = round(1e3 * ms / max(1, r.iters), 2)
+                one.batch_tfqmr(bq, rtol=0.0, maxit=20, check_every=ce)
+                ms, r = timed(lambda: one.batch_tfqmr(bq, rtol=0.0, maxit=400, check_every=ce), reps=3)
+                row[f"tfqmr_{tag}_us_per_halfstep"] = round(1e3 * ms / max(1, r[1][0]), 2)
+            xq = torch.zeros_like(bq)
+            Aq.set_option(spx.OPT_GRAPH, 1)
+            Aq.cg_solve(bq, x=xq.zero_(), rtol=0.0, maxit=200, check_every=20)  # capture
+            ms, r = timed(lambda: Aq.cg_solve(bq, x=xq.zero_(), rtol=0.0, maxit=200, check_every=20),
+                          reps=3)
+            Aq.set_option(spx.OPT_GRAPH, 0)
+            row["cg_async_graph_us_per_iter"] = round(1e3 * ms / max(1, r.iters), 2)
+            row["cg_async_speedup"] = round(row["cg_sync_us_per_iter"] / row["cg_async_us_per_iter"], 2)
+            row["cg_graph_speedup"] = round(row["cg_sync_us_per_iter"] / row["cg_async_graph_us_per_iter"], 2)
+            row["tfqmr_async_speedup"] = round(row["tfqmr_sync_us_per_halfstep"]
+                                               / row["tfqmr_async_us_per_halfstep"], 2)
+            curve.append(row)
+            log(f"async curve nnz={Aq.nnz}: cg {row['cg_sync_us_per_iter']} vs "
+                f"{row['cg_async_us_per_iter']} (graph {row['cg_async_graph_us_per_iter']}) us/it, tfqmr {row['tfqmr_sync_us_per_halfstep']} vs "
+                f"{row['tfqmr_async_us_per_halfstep']} us/half-step")
+            one.destroy()
+            Aq.destroy()
+        out["sync_vs_async"] = {"points": curve,
+                                "note": "host polls the device stop flag after every iteration (sync) "
+                                        "or every 20 (async, also with each chunk replayed as one HIP "
+                                        "graph); 200 CG iterations / 400 TFQMR half-steps with rtol = 0, "
+                                        "time per iteration"}
 
     # ---- 64-system batch
-    probs, bs = W.config4()
-    mats = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs]
-    for m, p in zip(mats, probs):
-        m.set_values_coo(d(p.v))
-    batch = spx.batch_create(mats)
-    bvec = d(np.concatenate(bs))
-    best = autotune.tune_batch(batch, bvec, rtol=1e-8, candidates=[
-        autotune.Candidate(1024, 0, 1.0), autotune.Candidate(2048, 0, 1.0),
-        autotune.Candidate(2048, 64, 1.0), autotune.Candidate(2048, 0, 1.25)])
-    kw = dict(blocks=best["blocks"], rows_per_tile=best["rows_per_tile"],
-              weight_exponent=best["weight_exponent"])
-    bt_ms, (xb, iters, relres, st) = timed(lambda: batch.batch_cg(bvec, rtol=1e-8, **kw), reps=3)
-    work = sum(it * cg_iteration_bytes(p.n, m.nnz) for it, p, m in zip(iters, probs, mats))
-    # one solve per system
-    seq_ms, _ = timed(lambda: [m.cg_solve(d_b, rtol=1e-8) for m, d_b in
-                               zip(mats, [d(b) for b in bs])])
-    # ensemble: the block-diagonal stack as one system (one global norm)
-    offs = np.cumsum([0] + [p.n for p in probs])
-    ei = np.concatenate([p.i + o for p, o in zip(probs, offs)]).astype(np.int32)
-    ej = np.concatenate([p.j + o for p, o in zip(probs, offs)]).astype(np.int32)
-    ev_ = np.concatenate([p.v for p in probs])
-    E = spx.coo_preallocate(int(offs[-1]), d(ei), d(ej))
-    E.set_values_coo(d(ev_))
-    ens_ms, ens = timed(lambda: E.cg_solve(bvec, rtol=1e-8), reps=2)
-    out["batched64"] = {"ms": round(bt_ms, 2), "solves_per_s": round(64 / (bt_ms * 1e-3), 1),
-                        "status": st, "max_relres": max(relres), "iters_max": max(iters),
-                        "iters_min": min(iters), "work_bytes": work,
-                        "gbs": round(work / (bt_ms * 1e-3) / 1e9, 1), "tuning": best,
-                        "sequential_ms": round(seq_ms, 2), "ensemble_ms": round(ens_ms, 2),
-                        "ensemble_iters": ens.iters,
-                        "speedup_vs_ensemble": round(ens_ms / bt_ms, 2),
-                        "speedup_vs_sequential": round(seq_ms / bt_ms, 2)}
-    log(f"batched: {bt_ms:.2f} ms, ensemble {ens_ms:.2f} ms, sequential {seq_ms:.2f} ms")
-    del batch, mats, E
+    if want("batched64"):
+        probs, bs = W.config4()
+        mats = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs]
+        for m, p in zip(mats, probs):
+            m.set_values_coo(d(p.v))
+        batch = spx.batch_create(mats)
+        bvec = d(np.concatenate(bs))
+        best = autotune.tune_batch(batch, bvec, rtol=1e-8, candidates=[
+            autotune.Candidate(1024, 0, 1.0), autotune.Candidate(2048, 0, 1.0),
+            autotune.Candidate(2048, 64, 1.0), autotune.Candidate(2048, 0, 1.25)])
+        kw = dict(blocks=best["blocks"], rows_per_tile=best["rows_per_tile"],
+                  weight_exponent=best["weight_exponent"])
+        bt_ms, (xb, iters, relres, st) = timed(lambda: batch.batch_cg(bvec, rtol=1e-8, **kw), reps=3)
+        work = sum(it * cg_iteration_bytes(p.n, m.nnz) for it, p, m in zip(iters, probs, mats))
+        # one solve per system
+        seq_ms, _ = timed(lambda: [m.cg_solve(d_b, rtol=1e-8) for m, d_b in
+                                   zip(mats, [d(b) for b in bs])])
+        # ensemble: the block-diagonal stack as one system (one global norm)
+        offs = np.cumsum([0] + [p.n for p in probs])
+        ei = np.concatenate([p.i + o for p, o in zip(probs, offs)]).astype(np.int32)
+        ej = np.concatenate([p.j + o for p, o in zip(probs, offs)]).astype(np.int32)
+        ev_ = np.concatenate([p.v for p in probs])
+        E = spx.coo_preallocate(int(offs[-1]), d(ei), d(ej))
+        E.set_values_coo(d(ev_))
+        ens_ms, ens = timed(lambda: E.cg_solve(bvec, rtol=1e-8), reps=2)
+        out["batched64"] = {"ms": round(bt_ms, 2), "solves_per_s": round(64 / (bt_ms * 1e-3), 1),
+                            "status": st, "max_relres": max(relres), "iters_max": max(iters),
+                            "iters_min": min(iters), "work_bytes": work,
+                            "gbs": round(work / (bt_ms * 1e-3) / 1e9, 1), "tuning": best,
+                            "sequential_ms": round(seq_ms, 2), "ensemble_ms": round(ens_ms, 2),
+                            "ensemble_iters": ens.iters,
+                            "speedup_vs_ensemble": round(ens_ms / bt_ms, 2),
+                            "speedup_vs_sequential": round(seq_ms / bt_ms, 2)}
+        log(f"batched: {bt_ms:.2f} ms, ensemble {ens_ms:.2f} ms, sequential {seq_ms:.2f} ms")
+        del batch, mats, E
 
     # ---- 64-system non-symmetric batch: batched TFQMR / BiCG vs ensemble vs one per system
-    probs6, bs6 = W.config6()
-    mats6 = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs6]
-    for m, p in zip(mats6, probs6):
-        m.set_values_coo(d(p.v))
-    batch6 = spx.batch_create(mats6)
-    bvec6 = d(np.concatenate(bs6))
-    offs6 = np.cumsum([0] + [p.n for p in probs6])
-    E6 = spx.coo_preallocate(int(offs6[-1]),
-                             d(np.concatenate([p.i + o for p, o in zip(probs6, offs6)]).astype(np.int32)),
-                             d(np.concatenate([p.j + o for p, o in zip(probs6, offs6)]).astype(np.int32)))
-    E6.set_values_coo(d(np.concatenate([p.v for p in probs6])))
-    ens6 = spx.batch_create([E6])
-    singles = [spx.batch_create([m]) for m in mats6]
-    b_parts = [d(b) for b in bs6]
-    nonsym = {}
-    for method in ("tfqmr", "bicg"):
-        fn = "batch_" + method
-        getattr(batch6, fn)(bvec6, rtol=1e-8)  # warm (BiCG builds the transposes)
-        ms_b, (xb, it_b, rel_b, st_b) = timed(lambda: getattr(batch6, fn)(bvec6, rtol=1e-8), reps=3)
-        ms_e, (xe, it_e, rel_e, st_e) = timed(lambda: getattr(ens6, fn)(bvec6, rtol=1e-8), reps=2)
-        ms_s, _ = timed(lambda: [getattr(sb, fn)(bp, rtol=1e-8) for sb, bp in zip(singles, b_parts)])
-        nonsym[method] = {"ms": round(ms_b, 2), "solves_per_s": round(64 / (ms_b * 1e-3), 1),
-                          "status": st_b, "max_relres": max(rel_b), "iters_max": max(it_b),
-                          "iters_min": min(it_b), "ensemble_ms": round(ms_e, 2),
-                          "ensemble_iters": it_e[0], "ensemble_status": st_e,
-                          "sequential_ms": round(ms_s, 2),
-                          "speedup_vs_ensemble": round(ms_e / ms_b, 2),
-                          "speedup_vs_sequential": round(ms_s / ms_b, 2)}
-        log(f"nonsymmetric batch {method}: {ms_b:.2f} ms, ensemble {ms_e:.2f} ms, "
-            f"sequential {ms_s:.2f} ms")
-    nonsym["iteration_unit"] = {"tfqmr": "half-steps (one product with A)",
-                                "bicg": "BiCG steps (one product with A and one with A^T)"}
-    out["nonsymmetric_batch64"] = nonsym
-    del batch6, mats6, E6, ens6, singles
+    if want("nonsymmetric_batch64"):
+        probs6, bs6 = W.config6()
+        mats6 = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs6]
+        for m, p in zip(mats6, probs6):
+            m.set_values_coo(d(p.v))
+        batch6 = spx.batch_create(mats6)
+        bvec6 = d(np.concatenate(bs6))
+        offs6 = np.cumsum([0] + [p.n for p in probs6])
+        E6 = spx.coo_preallocate(int(offs6[-1]),
+                                 d(np.concatenate([p.i + o for p, o in zip(probs6, offs6)]).astype(np.int32)),
+                                 d(np.concatenate([p.j + o for p, o in zip(probs6, offs6)]).astype(np.int32)))
+        E6.set_values_coo(d(np.concatenate([p.v for p in probs6])))
+        ens6 = spx.batch_create([E6])
+        singles = [spx.batch_create([m]) for m in mats6]
+        b_parts = [d(b) for b in bs6]
+        nonsym = {}
+        for method in ("tfqmr", "bicg"):
+            fn = "batch_" + method
+            getattr(batch6, fn)(bvec6, rtol=1e-8)  # warm (BiCG builds the transposes)
+            ms_b, (xb, it_b, rel_b, st_b) = timed(lambda: getattr(batch6, fn)(bvec6, rtol=1e-8), reps=3)
+            ms_e, (xe, it_e, rel_e, st_e) = timed(lambda: getattr(ens6, fn)(bvec6, rtol=1e-8), reps=2)
+            ms_s, _ = timed(lambda: [getattr(sb, fn)(bp, rtol=1e-8) for sb, bp in zip(singles, b_parts)])
+            nonsym[method] = {"ms": round(ms_b, 2), "solves_per_s": round(64 / (ms_b * 1e-3), 1),
+                              "status": st_b, "max_relres": max(rel_b), "iters_max": max(it_b),
+                              "iters_min": min(it_b), "ensemble_ms": round(ms_e, 2),
+                              "ensemble_iters": it_e[0], "ensemble_status": st_e,
+                              "sequential_ms": round(ms_s, 2),
+                              "speedup_vs_ensemble": round(ms_e / ms_b, 2),
+                              "speedup_vs_sequential": round(ms_s / ms_b, 2)}
+            log(f"nonsymmetric batch {method}: {ms_b:.2f} ms, ensemble {ms_e:.2f} ms, "
+                f"sequential {ms_s:.2f} ms")
+        nonsym["iteration_unit"] = {"tfqmr": "half-steps (one product with A)",
+                                    "bicg": "BiCG steps (one product with A and one with A^T)"}
+        out["nonsymmetric_batch64"] = nonsym
+        del batch6, mats6, E6, ens6, singles
 
     # ---- L-BFGS H_k g: one update + one apply, effective bandwidth of the paper
-    lb = []
-    gen = torch.Generator(device=dev).manual_seed(6)
-    for n_l, m_l in ((1_000_000, 5), (1_000_000, 50), (10_000_000, 5), (10_000_000, 10),
-                     (10_000_000, 50)):
-        L = spx.lbfgs_create(n_l, m_l)
-        dcurv = torch.rand(n_l, generator=gen, device=dev, dtype=torch.float64) * 1.5 + 0.5
-        hist = []
-        for _ in range(m_l + 4):
-            s_ = torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
-            y_ = dcurv * s_ + 0.1 * torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
-            hist.append((s_, y_))
-        g_ = torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
-        h0_ = torch.rand(n_l, generator=gen, device=dev, dtype=torch.float64) + 0.5
-        p_ = torch.empty_like(g_)
-        for s_, y_ in hist[:m_l]:
-            L.update(s_, y_)
-        evs = []
-        for k in range(8):
-            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-            s_, y_ = hist[m_l + (k % 4)]
-            e0.record()
-            L.update(s_, y_)
-            e1.record()
-            L.apply(g_, h0_, p_)
-            e2.record()
-            evs.append((e0, e1, e2))
-        torch.cuda.synchronize()
-        # the same step through the fused entry point (S^T g in the update's pass)
-        fevs = []
-        for k in range(8):
-            e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
-            s_, y_ = hist[m_l + (k % 4)]
-            e0.record()
-            L.update_apply(s_, y_, g_, h0_, p_)
-            e1.record()
-            fevs.append((e0, e1))
-        torch.cuda.synchronize()
-        upd = statistics.median(a.elapsed_time(b) for a, b, _ in evs)
-        app = statistics.median(b.elapsed_time(c) for _, b, c in evs)
-        t_ms = statistics.median(a.elapsed_time(c) for a, _, c in evs)
-        f_ms = statistics.median(a.elapsed_time(b) for a, b in fevs)
-        be = 8 * n_l * (2 * m_l + 2) / (t_ms * 1e-3) / 1e9
-        be_f = 8 * n_l * (2 * m_l + 2) / (f_ms * 1e-3) / 1e9
-        y_passes = 2 if m_l <= 16 else 3  # update, a (with Y^T a up to 16 pairs), Y^T a
-        col_bytes = 8 * n_l * m_l
-        lb.append({"n": n_l, "m": m_l, "update_ms": round(upd, 4), "apply_ms": round(app, 4),
-                   "total_ms": round(t_ms, 4), "effective_gbs": round(be, 1),
-                   "hbm_bytes": col_bytes * (3 + y_passes) + 8 * 8 * n_l,
-                   "hbm_gbs": round((col_bytes * (3 + y_passes) + 8 * 8 * n_l) / (t_ms * 1e-3) / 1e9, 1),
-                   "fused_ms": round(f_ms, 4), "fused_effective_gbs": round(be_f, 1),
-                   "fused_hbm_gbs": round((col_bytes * (2 + y_passes) + 8 * 8 * n_l) / (f_ms * 1e-3) / 1e9,
-                                          1)})
-        log(f"lbfgs n={n_l} m={m_l}: update {upd:.3f} ms apply {app:.3f} ms B_e {be:.0f} GB/s; "
-            f"fused {f_ms:.3f} ms B_e {be_f:.0f} GB/s")
-        L.destroy()
-        del hist, dcurv, g_, h0_, p_
-    out["lbfgs"] = {"points": lb,
-                    "effective_bandwidth": "8 n (2m + 2) bytes / (T_update + T_apply): "
-                                           "S and Y read once, g read, p written",
-                    "hbm_bytes": "bytes this design moves: S read 3 times (update, S^T g, p), Y "
-                                 "twice up to 16 pairs (update; a with Y^T a) and 3 times above, "
-                                 "plus 8 vector passes; the fused step reads S twice",
-                    "fused": "spx_lbfgs_update_apply: the same step with S^T g taken in the "
-                             "update's pass over S (bitwise the two calls)"}
+    if want("lbfgs"):
+        lb = []
+        gen = torch.Generator(device=dev).manual_seed(6)
+        for n_l, m_l in ((1_000_000, 5), (1_000_000, 50), (10_000_000, 5), (10_000_000, 10),
+                         (10_000_000, 50)):
+            L = spx.lbfgs_create(n_l, m_l)
+            dcurv = torch.rand(n_l, generator=gen, device=dev, dtype=torch.float64) * 1.5 + 0.5
+            hist = []
+            for _ in range(m_l + 4):
+                s_ = torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
+                y_ = dcurv * s_ + 0.1 * torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
+                hist.append((s_, y_))
+            g_ = torch.randn(n_l, generator=gen, device=dev, dtype=torch.float64)
+            h0_ = torch.rand(n_l, generator=gen, device=dev, dtype=torch.float64) + 0.5
+            p_ = torch.empty_like(g_)
+            for s_, y_ in hist[:m_l]:
+                L.update(s_, y_)
+            evs = []
+            for k in range(8):
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                s_, y_ = hist[m_l + (k % 4)]
+                e0.record()
+                L.update(s_, y_)
+                e1.record()
+                L.apply(g_, h0_, p_)
+                e2.record()
+                evs.append((e0, e1, e2))
+            torch.cuda.synchronize()
+            # the same step through the fused entry point (S^T g in the update's pass)
+            fevs = []
+            for k in range(8):
+                e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+                s_, y_ = hist[m_l + (k % 4)]
+                e0.record()
+                L.update_apply(s_, y_, g_, h0_, p_)
+                e1.record()
+                fevs.append((e0, e1))
+            torch.cuda.synchronize()
+            upd = statistics.median(a.elapsed_time(b) for a, b, _ in evs)
+            app = statistics.median(b.elapsed_time(c) for _, b, c in evs)
+            t_ms = statistics.median(a.elapsed_time(c) for a, _, c in evs)
+            f_ms = statistics.median(a.elapsed_time(b) for a, b in fevs)
+            be = 8 * n_l * (2 * m_l + 2) / (t_ms * 1e-3) / 1e9
+            be_f = 8 * n_l * (2 * m_l + 2) / (f_ms * 1e-3) / 1e9
+            y_passes = 2 if m_l <= 16 else 3  # update, a (with Y^T a up to 16 pairs), Y^T a
+            col_bytes = 8 * n_l * m_l
+            lb.append({"n": n_l, "m": m_l, "update_ms": round(upd, 4), "apply_ms": round(app, 4),
+                       "total_ms": round(t_ms, 4), "effective_gbs": round(be, 1),
+                       "hbm_bytes": col_bytes * (3 + y_passes) + 8 * 8 * n_l,
+                       "hbm_gbs": round((col_bytes * (3 + y_passes) + 8 * 8 * n_l) / (t_ms * 1e-3) / 1e9, 1),
+                       "fused_ms": round(f_ms, 4), "fused_effective_gbs": round(be_f, 1),
+                       "fused_hbm_gbs": round((col_bytes * (2 + y_passes) + 8 * 8 * n_l) / (f_ms * 1e-3) / 1e9,
+                                              1)})
+            log(f"lbfgs n={n_l} m={m_l}: update {upd:.3f} ms apply {app:.3f} ms B_e {be:.0f} GB/s; "
+                f"fused {f_ms:.3f} ms B_e {be_f:.0f} GB/s")
+            L.destroy()
+            del hist, dcurv, g_, h0_, p_
+        out["lbfgs"] = {"points": lb,
+                        "effective_bandwidth": "8 n (2m + 2) bytes / (T_update + T_apply): "
+                                               "S and Y read once, g read, p written",
+                        "hbm_bytes": "bytes this design moves: S read 3 times (update, S^T g, p), Y "
+                                     "twice up to 16 pairs (update; a with Y^T a) and 3 times above, "
+                                     "plus 8 vector passes; the fused step reads S twice",
+                        "fused": "spx_lbfgs_update_apply: the same step with S^T g taken in the "
+                                 "update's pass over S (bitwise the two calls)"}
 
     # ---- gradient on 256 x 256 elements
-    N = 256
-    one = W.q1_poisson(N, 2, kappa=np.ones(N * N))
-    w = one.dv_dlogk
-    base = one.v - w
-    _, theta, target, b = W.config5(N)
-    G = spx.coo_preallocate(one.n, d(one.i), d(one.j))
-    T = spx.coo_preallocate(one.n, d(target.i), d(target.j))
-    T.set_values_coo(d(target.v))
-    ustar = T.cg_solve(d(b), rtol=1e-12).x
-    th = d(theta).requires_grad_(True)
-    bd, based, wd = d(b), d(base), d(w)
-    # one untimed forward and backward first: the first calls load kernel code
-    u0 = AG.element_coefficient_solve(th, bd, G, based, wd, 16, rtol=1e-12)
-    (0.5 * torch.sum((u0 - ustar) ** 2)).backward()
-    th.grad = None
-    fw_ms, u = timed(lambda: AG.element_coefficient_solve(th, bd, G, based, wd, 16, rtol=1e-12))
-    loss = 0.5 * torch.sum((u - ustar) ** 2)
-    bw_ms, _ = timed(lambda: loss.backward())
-    out["gradient256"] = {"forward_ms": round(fw_ms, 2), "backward_ms": round(bw_ms, 2),
-                          "loss": float(loss.detach())}
-    log(f"gradient: forward {fw_ms:.2f} ms backward {bw_ms:.2f} ms")
+    if want("gradient256"):
+        N = 256
+        one = W.q1_poisson(N, 2, kappa=np.ones(N * N))
+        w = one.dv_dlogk
+        base = one.v - w
+        _, theta, target, b = W.config5(N)
+        G = spx.coo_preallocate(one.n, d(one.i), d(one.j))
+        T = spx.coo_preallocate(one.n, d(target.i), d(target.j))
+        T.set_values_coo(d(target.v))
+        ustar = T.cg_solve(d(b), rtol=1e-12).x
+        th = d(theta).requires_grad_(True)
+        bd, based, wd = d(b), d(base), d(w)
+        # one untimed forward and backward first: the first calls load kernel code
+        u0 = AG.element_coefficient_solve(th, bd, G, based, wd, 16, rtol=1e-12)
+        (0.5 * torch.sum((u0 - ustar) ** 2)).backward()
+        th.grad = None
+        fw_ms, u = timed(lambda: AG.element_coefficient_solve(th, bd, G, based, wd, 16, rtol=1e-12))
+        loss = 0.5 * torch.sum((u - ustar) ** 2)
+        bw_ms, _ = timed(lambda: loss.backward())
+        out["gradient256"] = {"forward_ms": round(fw_ms, 2), "backward_ms": round(bw_ms, 2),
+                              "loss": float(loss.detach())}
+        log(f"gradient: forward {fw_ms:.2f} ms backward {bw_ms:.2f} ms")
     return out
 
 
@@ -571,6 +597,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=int, default=63)
     ap.add_argument("--cpu-calls", type=int, default=10)
+    ap.add_argument("--extras", default=None,
+                    help="comma-separated subset of the extra measurements to run (default: all): "
+                         + ", ".join(EXTRAS))
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched / SpMM / gradient measurements")
     ap.add_argument("--calibrate", action="store_true",
@@ -795,7 +824,15 @@ def main() -> int:
                                         sum(r["profile"][k][1] for r in recs)]
                                     for k in spx.PROFILE_KINDS[:3]}
     if not args.no_extras:
-        out["extras"] = run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log)
+        only = None
+        if args.extras:
+            only = set(args.extras.split(","))
+            unknown = only - set(EXTRAS)
+            if unknown:
+                print(f"bench.py: unknown extras {sorted(unknown)}; choose from {', '.join(EXTRAS)}",
+                      file=sys.stderr)
+                return 2
+        out["extras"] = run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on the {args.cpu_grid}^3-element sample")
         out["cpu_baseline"] = cpu_baseline(args.cpu_grid, args.cpu_calls)
