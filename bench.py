@@ -335,6 +335,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
             pq = W.q1_poisson(N, dim)
             Aq = spx.coo_preallocate(pq.n, d(pq.i), d(pq.j))
             Aq.set_values_coo(d(pq.v))
+            Aq.set_option(spx.OPT_CG_VARIANT, 0)  # the textbook form on both sides of the comparison
             bq = torch.ones(pq.n, dtype=torch.float64, device=dev)
             one = spx.batch_create([Aq])
             row = {"dim": dim, "grid": N, "n": pq.n, "nnz": Aq.nnz}

@@ -405,9 +405,13 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *   SPX_OPT_ROWS_PER_BLOCK_F32: rows per workgroup of the fp32 copy used by
  *     the mixed-precision inner solve (0 auto: twice the fp64 tile).
  *   SPX_OPT_CG_VARIANT: form of the fp64 CG recurrences used by
- *     spx_cg_solve and spx_cg_solve_transpose.  0 (default): the textbook
- *     (Hestenes-Stiefel) form, three kernels and two reduction points per
- *     iteration.  1: the Chronopoulos-Gear single-reduction form of the same
+ *     spx_cg_solve and spx_cg_solve_transpose.  -1 (default): form 1 for
+ *     matrices of at most 2,000,000 entries (where its saved launch and
+ *     reduction point per iteration pay) unless SPX_OPT_GRAPH is on, form 0
+ *     otherwise; systems small enough for the one-workgroup solve still
+ *     take it; reading the option returns the form a solve with A takes.
+ *     0: the textbook (Hestenes-Stiefel) form, three kernels and two
+ *     reduction points per iteration.  1: the Chronopoulos-Gear single-reduction form of the same
  *     method (Sec. 6 names fewer synchronisation points as the aim of the
  *     asynchronous CG): with u = D^-1 r, w = A u, s = A p kept as a vector,
  *       gamma = r.u, delta = w.u, beta = gamma_k / gamma_{k-1},

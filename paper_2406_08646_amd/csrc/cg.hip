@@ -914,9 +914,17 @@ int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const doub
 // option, profiling, graph replay or the single-reduction form asks for the
 // multi-workgroup kernels; either way only if a 256-row tile fits in 64 KB.
 constexpr int64_t kOneAutoRows = 2048;  // measured crossover with the launch-per-iteration path
+
+// Without an explicit SPX_OPT_CG_VARIANT, systems of at most kSrAutoNnz
+// entries take the single-reduction form: one launch and one reduction
+// point fewer per iteration save about 2 us of each (11.7 vs 13.9 us at 36K
+// entries, 15.5 vs 17.4 at 591K, 14.9 vs 16.7 at 831K; even at 2.4M; 36.3
+// vs 35.7 at 6.9M).  Larger systems, and any solve with graph replay asked
+// for (the captured chunk is the textbook iteration), take the textbook form.
+constexpr int64_t kSrAutoNnz = 2000000;
 constexpr int64_t kOneLds = 150 * 1024;  // dynamic LDS of the lone workgroup
 bool use_one_workgroup(const spx_matrix* h, const Csr& M) {
-  if (h->small_opt == 0 || h->cg_variant != 0) return false;
+  if (h->small_opt == 0 || h->cg_variant == 1) return false;
   if ((M.tile_nnz[3] + 8) * (int64_t)sizeof(double) > 64 * 1024) return false;  // 256-row tiles fit
   if (h->small_opt == 2) return true;
   const bool shape_default = h->lanes_opt == 0 && h->variant_opt == 0 && h->rows_opt == 0 &&
@@ -924,6 +932,15 @@ bool use_one_workgroup(const spx_matrix* h, const Csr& M) {
                              h->pipe_opt == 0 && h->vec_opt == 0 && h->nt_opt == 1;
   return shape_default && !h->profile && !h->graph_opt && M.n <= kOneAutoRows;
 }
+
+}  // namespace
+
+int cg_form(const spx_matrix* h, const Csr& M) {
+  if (h->cg_variant >= 0) return h->cg_variant;
+  return !h->graph_opt && M.nnz <= kSrAutoNnz ? 1 : 0;
+}
+
+namespace {
 
 int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, double rtol,
                   int64_t maxit, int32_t check_every, hipStream_t s, int64_t* iters_out,
@@ -983,7 +1000,7 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
   hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G,
                      rtol);
   SPX_CHECK_HIP(hipGetLastError());
-  if (h->cg_variant == 1) {
+  if (cg_form(h, M) == 1) {
     // k_cg_init left u = D^-1 r in p; move it to its own vector and start
     // w = A u, p = u, s = w, delta_0
     double* u = h->work + 3 * n;

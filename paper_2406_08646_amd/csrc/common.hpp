@@ -191,7 +191,7 @@ struct spx_matrix {
   int vec_opt = 0;       // quad loads in the stream walk
   int pipe_opt = 0;      // pipelined tiles in the persistent solver kernels
   int rows32_opt = 0;    // rows per tile of the fp32 operator, 0 = auto
-  int cg_variant = 0;    // 0 Hestenes-Stiefel (3 kernels), 1 single reduction (2 kernels)
+  int cg_variant = -1;   // 0 Hestenes-Stiefel (3 kernels), 1 single reduction (2), -1 by size (cg_form)
   int fused_opt = 0;     // workgroups of the solver SpMV kernels, 0 = auto
   int vec_blocks_opt = 0;  // workgroups of the solver vector kernels, 0 = auto
   // optional per-kernel timing of solver iterations (HIP events)
@@ -230,6 +230,8 @@ int pick_lanes(const Csr& A, int opt);
 int compute_tiles(Csr& A, hipStream_t s);
 // window.hip
 int build_window(Csr& A, hipStream_t s);
+// cg.hip: the CG form (0 textbook, 1 single reduction) a solve on M takes
+int cg_form(const spx_matrix* h, const Csr& M);
 SpmvShape spmv_shape(const spx_matrix* h, const Csr& A);
 // allow_window = false: the shape the options give without the window walk
 SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window);

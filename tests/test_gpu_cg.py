@@ -112,6 +112,7 @@ def test_cg_check_every_does_not_change_the_result(orc):
     prob, _, b = W.config1()
     A = assemble(spx, prob)
     A.set_option(spx.OPT_SMALL_SOLVE, 0)  # the multi-workgroup path polls
+    A.set_option(spx.OPT_CG_VARIANT, 0)
     outs = [A.cg_solve(dev(b), rtol=1e-8, check_every=k) for k in (1, 7, 20, 1000)]
     for o in outs[1:]:
         assert o.iters == outs[0].iters
@@ -267,6 +268,7 @@ def test_graph_replay_is_bitwise_the_eager_solve(variant):
     prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(8).standard_normal(N**3)))
     A = assemble(spx, prob)
     A.set_option(spx.OPT_SMALL_SOLVE, 0)  # compare the graph with the same multi-workgroup kernels
+    A.set_option(spx.OPT_CG_VARIANT, 0)  # the textbook form, the one graphs capture
     A.set_option(spx.OPT_SPMV_VARIANT, variant)
     b = dev(np.random.default_rng(9).uniform(-1, 1, prob.n))
     eager = A.cg_solve(b, rtol=1e-10, check_every=7)
@@ -303,6 +305,7 @@ def test_one_workgroup_and_multi_workgroup_solves(orc, mode):
     prob, _, b = W.config1()
     A = assemble(spx, prob)
     A.set_option(spx.OPT_SMALL_SOLVE, mode)
+    A.set_option(spx.OPT_CG_VARIANT, 0)
     assert A.get_option(spx.OPT_SMALL_SOLVE) == mode
     ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
     ores = orc.pcg(ref, b, 1e-8)
@@ -316,6 +319,7 @@ def test_one_workgroup_and_multi_workgroup_solves(orc, mode):
         p = W.q1_poisson(N, dim, kappa=np.exp(rng.standard_normal(N**dim)))
         M = assemble(spx, p)
         M.set_option(spx.OPT_SMALL_SOLVE, mode)
+        M.set_option(spx.OPT_CG_VARIANT, 0)
         R = orc.assemble(p.n, p.i, p.j, p.v)
         D = np.zeros((p.n, p.n))
         D[np.repeat(np.arange(p.n), np.diff(R.rowptr)), R.col] = R.val
@@ -327,6 +331,7 @@ def test_one_workgroup_and_multi_workgroup_solves(orc, mode):
     p = W.q1_poisson(N, 2)
     E = assemble(spx, p)
     E.set_option(spx.OPT_SMALL_SOLVE, mode)
+    E.set_option(spx.OPT_CG_VARIANT, 0)
     Mg = N + 1
     node = np.arange(p.n)
     v = np.sin(2 * math.pi * (node % Mg) / N) * np.sin(3 * math.pi * (node // Mg) / N)
@@ -335,14 +340,17 @@ def test_one_workgroup_and_multi_workgroup_solves(orc, mode):
     Z = spx.coo_preallocate(2, dev(np.array([0, 1, 1], np.int32)), dev(np.array([1, 0, 1], np.int32)))
     Z.set_values_coo(dev(np.array([1.0, 1.0, 2.0])))
     Z.set_option(spx.OPT_SMALL_SOLVE, mode)
+    Z.set_option(spx.OPT_CG_VARIANT, 0)
     assert Z.cg_solve(dev(np.ones(2)), rtol=1e-8, maxit=10).status == spx.ZERO_DIAGONAL
     B = spx.coo_preallocate(2, dev(np.array([0, 1], np.int32)), dev(np.array([0, 1], np.int32)))
     B.set_values_coo(dev(np.array([1.0, -1.0])))
     B.set_option(spx.OPT_SMALL_SOLVE, mode)
+    B.set_option(spx.OPT_CG_VARIANT, 0)
     rb = B.cg_solve(dev(np.array([0.0, 1.0])), rtol=1e-8, maxit=10)
     assert rb.status == spx.BREAKDOWN and rb.iters == 0
     C = assemble(spx, W.q1_poisson(20, 2))
     C.set_option(spx.OPT_SMALL_SOLVE, mode)
+    C.set_option(spx.OPT_CG_VARIANT, 0)
     bc = np.random.default_rng(0).uniform(-1, 1, C.n)
     r = C.cg_solve(dev(bc), rtol=1e-12, maxit=3)
     assert r.status == spx.NOT_CONVERGED and r.iters == 3 and r.relres < 1.0

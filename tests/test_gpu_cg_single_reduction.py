@@ -167,3 +167,27 @@ def test_full_size_single_reduction(orc):
     assert hs.status == 0 and res.status == 0
     assert res.relres <= 1e-10 * 1.001 and rel <= 1e-10 * 1.01
     assert abs(res.iters - hs.iters) <= max(2, math.ceil(0.01 * hs.iters))
+
+
+def test_cg_form_chosen_by_size():
+    """Without an explicit form, matrices of at most 2M entries solve with
+    the single-reduction form (the same bits as asking for it), larger ones
+    and graph replay with the textbook form; -1 restores the choice."""
+    spx = require_gpu()
+    prob, _, b = W.config1()
+    A = assemble(spx, prob)
+    assert A.get_option(spx.OPT_CG_VARIANT) == 1
+    A.set_option(spx.OPT_GRAPH, 1)
+    assert A.get_option(spx.OPT_CG_VARIANT) == 0
+    A.set_option(spx.OPT_GRAPH, 0)
+    r_auto = A.cg_solve(dev(b), rtol=1e-8)
+    A.set_option(spx.OPT_CG_VARIANT, 1)
+    r_sr = A.cg_solve(dev(b), rtol=1e-8)
+    assert r_auto.iters == r_sr.iters
+    assert np.array_equal(bits(host(r_auto.x)), bits(host(r_sr.x)))
+    A.set_option(spx.OPT_CG_VARIANT, 0)
+    assert A.get_option(spx.OPT_CG_VARIANT) == 0
+    A.set_option(spx.OPT_CG_VARIANT, -1)
+    assert A.get_option(spx.OPT_CG_VARIANT) == 1
+    B = assemble(spx, W.q1_poisson(45, 3))  # 2,515,456 entries
+    assert B.nnz > 2000000 and B.get_option(spx.OPT_CG_VARIANT) == 0
