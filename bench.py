@@ -207,6 +207,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
                          "gbs": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
                          "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
         log(f"spmm16: {spmm_ms:.3f} ms")
+        del X, Y
 
     # ---- COO vector assembly: the element load vector of the same mesh (8 contributions
     # per element, one per local node, in element order)
@@ -263,8 +264,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         out["cg_forms"] = forms
         log(f"cg forms: textbook {forms['textbook']['ms_per_iter']} ms/it, single reduction "
             f"{forms['single_reduction']['ms_per_iter']} ms/it")
-        A.destroy()
-        del X, Y
+        shared.pop("A").destroy()
 
     # ---- C1 (2-D Q1, 63^2 elements): CG latency per iteration, grid path and one workgroup
     if want("c1_cg"):

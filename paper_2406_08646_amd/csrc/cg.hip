@@ -125,6 +125,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgScalars* st, const 
 }
 
 // K1: q = A p; partials of p.q
+// Scratch of the workgroup sums in a kernel with the LDS of SH's row walk:
+// the window walk's own LDS (free between tiles' use and before the first
+// one), so the kernel holds no static LDS and eight workgroups per CU fit
+// with two 256-entry steps per chunk on the 27-point operator; a small
+// static array for the other walks (whose LDS may be empty).  Callers
+// synchronise before reusing it after the walk.
+template <class SH>
+__device__ __forceinline__ double* reduction_lds(char* smem) {
+  if constexpr (SH::variant == kVariantWindow) {
+    return reinterpret_cast<double*>(smem);
+  } else {
+    __shared__ double lds[kLds];
+    return lds;
+  }
+}
+
 template <class SH, typename VT>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ col,
@@ -134,7 +150,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __
                                                     double* __restrict__ P1, int rows, int remap,
                                                     int64_t tile, WinView win) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double lds[kLds];
   if (st->done) return;
   double dot = 0.0;
   for_rows<SH, VT, VT, VT>(n, rowptr, col, val, p, rows, logical_block(remap), gridDim.x,
@@ -142,7 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(int64_t n, const int32_t* __
                              q[row] = s;
                              dot += (double)p[row] * (double)s;
                            }, tile, win);
-  dot = block_sum<kBlock>(dot, lds);
+  __syncthreads();  // the walk's LDS may hold the reduction scratch
+  dot = block_sum<kBlock>(dot, reduction_lds<SH>(smem));
   if (threadIdx.x == 0) P1[blockIdx.x] = dot;
 }
 
@@ -355,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
                                                     int64_t G2, double* __restrict__ P1, int rows,
                                                     int remap, int64_t tile, int64_t k, WinView win) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double lds[kLds];
+  double* lds = reduction_lds<SH>(smem);
   if (st->done) return;
   const double gk = reduce_all(P2, G2, lds);
   const double rr = reduce_all(P2 + G2, G2, lds);
@@ -386,6 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
                                          s[row] = w + beta * s[row];
                                          delta += w * ur;
                                        }, tile, win);
+  __syncthreads();  // the walk's LDS may hold the reduction scratch
   delta = block_sum<kBlock>(delta, lds);
   if (threadIdx.x == 0) P1[blockIdx.x] = delta;
 }

@@ -258,11 +258,12 @@ __host__ __device__ inline size_t dma_buffer_bytes(int64_t tile, size_t vbytes) 
 
 // -------------------------------------------------------------- window walk
 // Each thread takes V consecutive entries per step (one vector load of
-// values, one of columns) and U steps per chunk.  fp64: V = 2 (16-byte
-// value loads); the solver kernels take U = 1, since their persistent grids
-// need 8 workgroups per CU to fit (16 KB of LDS on the 27-point operator),
-// the one-shot product kernel U = 2.  fp32: V = 4 (16-byte value loads),
-// U = 2 in the solver kernels (14 KB).
+// values, one of columns) and U = 2 steps per chunk.  fp64: V = 2 (16-byte
+// value loads); on the 27-point operator that is 20,480 bytes of LDS, and
+// eight workgroups per CU fit exactly once the solver's SpMV kernel keeps
+// its workgroup sums in that LDS instead of a static array (with U = 1 and
+// 16 KB the kernel took 0.121 ms, with U = 2 0.115).  fp32: V = 4 (16-byte
+// value loads), 14 KB.
 constexpr int kWinUProduct = 2;
 template <typename VT>
 __host__ __device__ constexpr int win_v() {
@@ -270,7 +271,7 @@ __host__ __device__ constexpr int win_v() {
 }
 template <typename VT>
 __host__ __device__ constexpr int win_u_solver() {
-  return sizeof(VT) == 8 ? 1 : 2;
+  return 2;
 }
 
 template <typename T>
