@@ -151,6 +151,25 @@ def test_spmm_layouts_bitwise(orc):
             spmv_within(outs[0][:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
 
 
+@pytest.mark.parametrize("n", [1, 5, 31, 33])
+def test_spmm_fewer_rows_than_a_block(orc, n):
+    """Matrices with fewer rows than one 32-row block of the staged kernel
+    (and one just over): 16 contiguous columns against the oracle."""
+    spx = require_gpu()
+    rng = np.random.default_rng(70 + n)
+    i = rng.integers(0, n, 6 * n).astype(np.int32)
+    j = rng.integers(0, n, 6 * n).astype(np.int32)
+    v = rng.uniform(-1, 1, i.size)
+    prob = W.CooProblem(n=n, i=i, j=j, v=v)
+    A = assemble(spx, prob)
+    ref = orc.assemble(n, i, j, v)
+    Xh = rng.uniform(-1, 1, (n, 16))
+    Y = host(A.spmm(dev(Xh)))
+    Yr = orc.spmm(ref, Xh)
+    for c in range(16):
+        spmv_within(Y[:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
+
+
 @pytest.mark.parametrize("nrhs", [8, 13, 16, 32, 64, 65])
 def test_spmm_staged_runs_and_fallback(orc, nrhs):
     """The staged-run kernel (8 or more columns, 16-byte aligned X and Y):
