@@ -36,8 +36,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "index out of range", -4: "zero d
 def build(force: bool = False) -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` with gcc."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp", "-fPIC",
+               "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -77,7 +77,8 @@ def _load():
                                    _i64ref, _dref]
         lib.oracle_pcg.restype = ctypes.c_int
         lib.oracle_pcg_mixed.argtypes = [_i64, _i32p, _i32p, _f64p, _f64p, _f64p, ctypes.c_double,
-                                         ctypes.c_double, _i64, _i64, _i64ref, _i64ref, _dref]
+                                         ctypes.c_double, _i64, _i64, ctypes.c_int, _i64ref,
+                                         _i64ref, _dref]
         lib.oracle_pcg_mixed.restype = ctypes.c_int
         lib.oracle_sddmm.argtypes = [_i64, _i32p, _i32p, _f64p, _f64p, _f64p]
         lib.oracle_sddmm.restype = None
@@ -93,12 +94,26 @@ def _load():
         lib.oracle_bicg.restype = ctypes.c_int
         lib.oracle_tfqmr.argtypes = lib.oracle_pcg.argtypes + [_dref]
         lib.oracle_tfqmr.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_get_threads.argtypes = []
+        lib.oracle_get_threads.restype = ctypes.c_int
         for name in ("oracle_lbfgs_recursive", "oracle_lbfgs_dense"):
             fn = getattr(lib, name)
             fn.argtypes = [_i64, _i64, _f64p, _f64p, _f64p, _f64p, _f64p]
             fn.restype = None
         _lib = lib
     return _lib
+
+
+def set_threads(nthreads: int) -> None:
+    """OpenMP threads of the products, vector updates and dot blocks (the
+    results are bitwise the same for any count)."""
+    _load().oracle_set_threads(int(nthreads))
+
+
+def get_threads() -> int:
+    return int(_load().oracle_get_threads())
 
 
 class OracleError(RuntimeError):
@@ -328,15 +343,19 @@ class MixedResult:
 
 
 def pcg_mixed(A: CsrMatrix, b: np.ndarray, rtol_outer: float = 1e-10, rtol_inner: float = 1e-4,
-              maxit_outer: int = 100, maxit_inner: int = 100000) -> MixedResult:
+              maxit_outer: int = 100, maxit_inner: int = 100000,
+              early_exit: bool = False) -> MixedResult:
+    """FP32-inner / FP64-outer refinement.  The inner solve stops at
+    rtol_inner relative to its right-hand side; with ``early_exit`` also as
+    soon as its residual is below rtol_outer ||b|| / 2."""
     lib = _load()
     x = np.zeros(A.n)
     outer = ctypes.c_int64(0)
     inner = ctypes.c_int64(0)
     rr = ctypes.c_double(0.0)
     st = lib.oracle_pcg_mixed(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol_outer, rtol_inner,
-                              maxit_outer, maxit_inner, ctypes.byref(outer), ctypes.byref(inner),
-                              ctypes.byref(rr))
+                              maxit_outer, maxit_inner, 1 if early_exit else 0,
+                              ctypes.byref(outer), ctypes.byref(inner), ctypes.byref(rr))
     return MixedResult(x, outer.value, inner.value, rr.value, st)
 
 

@@ -6,15 +6,24 @@
  * the smoke check and the CPU-baseline leg of the benchmark may load it.
  * It shares no code, header, table or constant with the GPU library.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so every
- * floating-point operation below is evaluated exactly as written, in the
- * written order.
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no fast-math),
+ * so every floating-point operation below is evaluated exactly as written,
+ * in the written order.
+ *
+ * Threads.  The row loops of the products, the element-wise vector updates
+ * of the solvers and the 4096-element blocks of the dot products may run on
+ * several OpenMP threads (oracle_set_threads).  Each output element and each
+ * block sum is still formed by one thread in the written order, and block
+ * sums are added in block order by one thread, so every result is bitwise
+ * the same for any thread count.  The COO assembly and the other solvers
+ * stay sequential.
  *
  * Status codes (same meaning as the GPU library's, defined independently):
  *   0 ok, -1 invalid argument, -2 index out of range, -4 zero diagonal,
  *   -5 not converged, -6 breakdown.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -25,6 +34,13 @@
 #define OR_ZERO_DIAG (-4)
 #define OR_NOT_CONVERGED (-5)
 #define OR_BREAKDOWN (-6)
+
+/* Loops over n independent elements go parallel from this length on. */
+#define PAR_MIN 32768
+#define PAR_FOR _Pragma("omp parallel for schedule(static) if (n >= PAR_MIN)")
+
+void oracle_set_threads(int nthreads) { omp_set_num_threads(nthreads > 0 ? nthreads : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------
  * COO -> CSR (paper Sec. 5, "Portable matrix assembly on GPUs").
@@ -200,6 +216,7 @@ int oracle_vec_coo(int64_t n, int64_t ncoo, const int32_t* i, const double* v, i
 
 void oracle_spmv(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
                  const double* x, double* y) {
+  PAR_FOR
   for (int64_t r = 0; r < n; r++) {
     double s = 0.0;
     for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) s += val[t] * x[col[t]];
@@ -243,25 +260,35 @@ void oracle_spmm(int64_t n, const int32_t* rowptr, const int32_t* col, const dou
 #define DOT_BLOCK 4096
 
 static double dot64(int64_t n, const double* a, const double* b) {
-  double total = 0.0;
-  for (int64_t s = 0; s < n; s += DOT_BLOCK) {
-    int64_t e = s + DOT_BLOCK < n ? s + DOT_BLOCK : n;
-    double part = 0.0;
-    for (int64_t i = s; i < e; i++) part += a[i] * b[i];
-    total += part;
+  const int64_t nb = (n + DOT_BLOCK - 1) / DOT_BLOCK;
+  double* part = (double*)malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
+#pragma omp parallel for schedule(static) if (nb >= 8)
+  for (int64_t blk = 0; blk < nb; blk++) {
+    int64_t s = blk * DOT_BLOCK, e = s + DOT_BLOCK < n ? s + DOT_BLOCK : n;
+    double sum = 0.0;
+    for (int64_t i = s; i < e; i++) sum += a[i] * b[i];
+    part[blk] = sum;
   }
+  double total = 0.0;
+  for (int64_t blk = 0; blk < nb; blk++) total += part[blk];
+  free(part);
   return total;
 }
 
 /* fp32 vectors, products and sums in fp64 */
 static double dot32(int64_t n, const float* a, const float* b) {
-  double total = 0.0;
-  for (int64_t s = 0; s < n; s += DOT_BLOCK) {
-    int64_t e = s + DOT_BLOCK < n ? s + DOT_BLOCK : n;
-    double part = 0.0;
-    for (int64_t i = s; i < e; i++) part += (double)a[i] * (double)b[i];
-    total += part;
+  const int64_t nb = (n + DOT_BLOCK - 1) / DOT_BLOCK;
+  double* part = (double*)malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
+#pragma omp parallel for schedule(static) if (nb >= 8)
+  for (int64_t blk = 0; blk < nb; blk++) {
+    int64_t s = blk * DOT_BLOCK, e = s + DOT_BLOCK < n ? s + DOT_BLOCK : n;
+    double sum = 0.0;
+    for (int64_t i = s; i < e; i++) sum += (double)a[i] * (double)b[i];
+    part[blk] = sum;
   }
+  double total = 0.0;
+  for (int64_t blk = 0; blk < nb; blk++) total += part[blk];
+  free(part);
   return total;
 }
 
@@ -292,10 +319,13 @@ int oracle_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const doubl
   double bnorm = sqrt(dot64(n, b, b));
   if (status == OR_OK) {
     oracle_spmv(n, rowptr, col, val, x, q);
+    PAR_FOR
     for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
     double rnorm = sqrt(dot64(n, r, r));
     if (!(rnorm <= rtol * bnorm)) {
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) z[i] = dinv[i] * r[i];
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) p[i] = z[i];
       double rho = dot64(n, r, z);
       status = OR_NOT_CONVERGED;
@@ -307,7 +337,9 @@ int oracle_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const doubl
           break;
         }
         double alpha = rho / pq;
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) x[i] = x[i] + alpha * p[i];
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) r[i] = r[i] - alpha * q[i];
         k++;
         rnorm = sqrt(dot64(n, r, r));
@@ -315,15 +347,18 @@ int oracle_pcg(int64_t n, const int32_t* rowptr, const int32_t* col, const doubl
           status = OR_OK;
           break;
         }
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) z[i] = dinv[i] * r[i];
         double rho_new = dot64(n, r, z);
         double beta = rho_new / rho;
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
         rho = rho_new;
       }
     }
   }
   oracle_spmv(n, rowptr, col, val, x, q);
+  PAR_FOR
   for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
   *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
   *iters = k;
@@ -675,13 +710,16 @@ int oracle_tfqmr(int64_t n, const int32_t* rowptr, const int32_t* col, const dou
  * fp64: r = b - A x in fp64, stop when ||r|| <= rtol_outer ||b||; inner
  * Jacobi-CG on fl32(A) d = fl32(r) from d = 0 with fp32 values, vectors
  * and SpMV, dot products formed and summed in fp64, stopping when
- * ||r_inner|| <= max(rtol_inner ||fl32(r)||, rtol_outer ||b|| / 2) (the
+ * ||r_inner|| <= rtol_inner ||fl32(r)||; then x += d in fp64.
+ * With early_exit = 1 the inner stop is instead
+ * ||r_inner|| <= max(rtol_inner ||fl32(r)||, rtol_outer ||b|| / 2): the
  * second term ends the last refinement step once the outer target is in
- * reach); then x += d in fp64.
+ * reach (a reading of the plan, which fixes no inner tolerance).
  * ---------------------------------------------------------------------- */
 
 static void spmv32(int64_t n, const int32_t* rowptr, const int32_t* col, const float* val,
                    const float* x, float* y) {
+  PAR_FOR
   for (int64_t r = 0; r < n; r++) {
     float s = 0.0f;
     for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) s += val[t] * x[col[t]];
@@ -691,8 +729,8 @@ static void spmv32(int64_t n, const int32_t* rowptr, const int32_t* col, const f
 
 int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
                      const double* b, double* x, double rtol_outer, double rtol_inner,
-                     int64_t maxit_outer, int64_t maxit_inner, int64_t* outer_steps,
-                     int64_t* inner_total, double* relres) {
+                     int64_t maxit_outer, int64_t maxit_inner, int early_exit,
+                     int64_t* outer_steps, int64_t* inner_total, double* relres) {
   int64_t nnz = rowptr[n];
   float* val32 = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
   float* dinv32 = (float*)malloc(sizeof(float) * (size_t)n);
@@ -708,11 +746,14 @@ int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const
   int status = diag_inverse(n, rowptr, col, val, dinv);
   double bnorm = sqrt(dot64(n, b, b));
   if (status == OR_OK) {
+#pragma omp parallel for schedule(static) if (nnz >= PAR_MIN)
     for (int64_t t = 0; t < nnz; t++) val32[t] = (float)val[t];
+    PAR_FOR
     for (int64_t i = 0; i < n; i++) dinv32[i] = (float)dinv[i];
     status = OR_NOT_CONVERGED;
     for (;;) {
       oracle_spmv(n, rowptr, col, val, x, t64);
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) r[i] = b[i] - t64[i];
       double rn = sqrt(dot64(n, r, r));
       if (rn <= rtol_outer * bnorm) {
@@ -722,12 +763,16 @@ int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const
       if (outer >= maxit_outer) break;
       outer++;
       /* inner fp32 Jacobi-CG from d = 0 */
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) ri[i] = (float)r[i];
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) d[i] = 0.0f;
       double r0 = sqrt(dot32(n, ri, ri));
       double stop_at = rtol_inner * r0;
-      if (stop_at < 0.5 * rtol_outer * bnorm) stop_at = 0.5 * rtol_outer * bnorm;
+      if (early_exit && stop_at < 0.5 * rtol_outer * bnorm) stop_at = 0.5 * rtol_outer * bnorm;
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) z[i] = dinv32[i] * ri[i];
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) p[i] = z[i];
       double rho = dot32(n, ri, z);
       int64_t it = 0;
@@ -740,18 +785,23 @@ int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const
           break;
         }
         float a32 = (float)(rho / pq);
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) d[i] = d[i] + a32 * p[i];
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) ri[i] = ri[i] - a32 * q[i];
         it++;
         double rr = sqrt(dot32(n, ri, ri));
         if (rr <= stop_at) break;
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) z[i] = dinv32[i] * ri[i];
         double rho_new = dot32(n, ri, z);
         float b32 = (float)(rho_new / rho);
+        PAR_FOR
         for (int64_t i = 0; i < n; i++) p[i] = z[i] + b32 * p[i];
         rho = rho_new;
       }
       inner += it;
+      PAR_FOR
       for (int64_t i = 0; i < n; i++) x[i] = x[i] + (double)d[i];
       if (bad) {
         status = OR_BREAKDOWN;
@@ -760,6 +810,7 @@ int oracle_pcg_mixed(int64_t n, const int32_t* rowptr, const int32_t* col, const
     }
   }
   oracle_spmv(n, rowptr, col, val, x, t64);
+  PAR_FOR
   for (int64_t i = 0; i < n; i++) r[i] = b[i] - t64[i];
   *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
   *outer_steps = outer;

@@ -402,6 +402,75 @@ def test_mixed_refinement_reaches_fp64_tolerance(orc):
     assert np.linalg.norm(ref.x - xs) <= 1e-9 * np.linalg.norm(xs)
 
 
+def _lognormal_q1(orc, N, seed=1):
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal(N**3)
+    p = W.q1_poisson(N, 3, kappa=np.exp(z))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    return A, rng.uniform(-1, 1, p.n)
+
+
+def _fp32_residual(A, b, x):
+    """||fl32(b) - fl32(A) x|| / ||fl32(b)||, formed in fp64 with numpy."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    A32 = sp.csr_matrix((A.val.astype(np.float32).astype(np.float64), (rows, A.col)),
+                        shape=(A.n, A.n))
+    b32 = b.astype(np.float32).astype(np.float64)
+    return np.linalg.norm(b32 - A32 @ x) / np.linalg.norm(b32)
+
+
+def test_mixed_inner_stop_rules(orc):
+    """One refinement step from x = 0 is one inner fp32 solve on fl32(b).
+    The literal rule stops it once the inner residual has fallen by
+    rtol_inner (checked on the true fp32-operator residual of the returned
+    x, which CG reduces smoothly, so it lands within a few factors of the
+    target, not orders below it).  The early exit stops as soon as the
+    residual is under rtol_outer ||b|| / 2, which for a loose outer target
+    ends the step far above rtol_inner."""
+    A, b = _lognormal_q1(orc, 10)
+    lit = orc.pcg_mixed(A, b, 1e-10, 1e-4, maxit_outer=1)
+    assert lit.outer == 1 and lit.status == -5
+    rel = _fp32_residual(A, b, lit.x)
+    assert 1e-6 < rel <= 1.5e-4, rel
+    early = orc.pcg_mixed(A, b, 2e-2, 1e-4, maxit_outer=1, early_exit=True)
+    rel_e = _fp32_residual(A, b, early.x)
+    assert 1e-3 < rel_e <= 1.5e-2, rel_e
+    assert early.inner < lit.inner
+    # to 1e-10 both rules reach the target in the same number of steps;
+    # the early exit only shortens the last inner solve
+    full_l = orc.pcg_mixed(A, b, 1e-10, 1e-4)
+    full_e = orc.pcg_mixed(A, b, 1e-10, 1e-4, early_exit=True)
+    assert full_l.status == 0 and full_e.status == 0
+    assert full_l.relres <= 1e-10 and full_e.relres <= 1e-10
+    assert full_e.outer == full_l.outer and full_e.inner < full_l.inner
+
+
+def test_thread_count_does_not_change_results(orc):
+    """The parallel loops keep every element and every 4096-entry dot block
+    in one thread, in order: results are bitwise those of one thread."""
+    p = W.q1_poisson(40, 3)  # 68,921 rows: above the parallel threshold
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, p.n)
+    b = rng.uniform(-1, 1, p.n)
+    old = orc.get_threads()
+    try:
+        out = {}
+        for t in (1, 5):
+            orc.set_threads(t)
+            y = orc.spmv(A, x)
+            c = orc.pcg(A, b, 1e-8)
+            m = orc.pcg_mixed(A, b, 1e-10, 1e-4)
+            out[t] = (y, c, m)
+        (y1, c1, m1), (y5, c5, m5) = out[1], out[5]
+        assert np.array_equal(bits(y1), bits(y5))
+        assert c1.iters == c5.iters and np.array_equal(bits(c1.x), bits(c5.x))
+        assert (m1.outer, m1.inner) == (m5.outer, m5.inner)
+        assert np.array_equal(bits(m1.x), bits(m5.x))
+    finally:
+        orc.set_threads(old)
+
+
 # ----------------------------------------------------------- gradient
 
 def _dense(orc, n, i, j, v):
