@@ -155,9 +155,10 @@ int spx_cg_solve_transpose(spx_handle h, const double* b, double* x, double rtol
  * lower precision than the solver's).  Iterative refinement: outer fp64
  * residual r = b - A x and norm; inner Jacobi-CG on fl32(A) d = fl32(r) from
  * d = 0 with fp32 matrix, vectors and SpMV but fp64 dot products, stopping
- * at ||r_in|| <= max(rtol_inner ||fl32(r)||, rtol_outer ||b|| / 2) (the
- * second term ends the last step once the outer target is in reach);
- * x += d in fp64; stop when ||b - A x|| <= rtol_outer ||b||.
+ * at ||r_in|| <= rtol_inner ||fl32(r)|| (with SPX_OPT_IR_EARLY_EXIT at
+ * ||r_in|| <= max(rtol_inner ||fl32(r)||, rtol_outer ||b|| / 2), which ends
+ * the last step once the outer target is in reach); x += d in fp64; stop
+ * when ||b - A x|| <= rtol_outer ||b||.
  * x: device float64[n], in/out (usually 0).
  * outer_out: refinement steps; inner_out: total inner iterations.
  * Synchronises `stream`. */
@@ -432,7 +433,13 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *     1 (default): for systems of at most 2048 rows when no launch-shape
  *     option, profiling, graph replay or the single-reduction form is set.
  *     2: whenever a 256-row tile fits in 64 KB of LDS.  Same recurrences,
- *     tests and statuses; the dots are summed in another order. */
+ *     tests and statuses; the dots are summed in another order.
+ *   SPX_OPT_IR_EARLY_EXIT: inner stopping rule of spx_cg_solve_mixed.
+ *     0 (default): each inner solve runs to rtol_inner relative to its
+ *     right-hand side.  1: it also stops once its residual is at most
+ *     rtol_outer ||b|| / 2, so the last refinement step does no more inner
+ *     iterations than the outer target needs (a reading of the Sec. 2 plan,
+ *     which names no inner tolerance). */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,
@@ -447,7 +454,8 @@ enum spx_option {
   SPX_OPT_ROWS_PER_BLOCK_F32 = 11,
   SPX_OPT_CG_VARIANT = 12,
   SPX_OPT_GRAPH = 13,
-  SPX_OPT_SMALL_SOLVE = 14
+  SPX_OPT_SMALL_SOLVE = 14,
+  SPX_OPT_IR_EARLY_EXIT = 15
 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);

@@ -72,7 +72,12 @@ static int cmp_key(const void* pa, const void* pb) {
 }
 
 /* rowptr[n+1], col[ncoo], jmap[ncoo+1], perm[ncoo] are caller-allocated
- * with room for the worst case (every kept triplet distinct). */
+ * with room for the worst case (every kept triplet distinct).
+ *
+ * The sort is two stable counting sorts of the kept k: by column, then by
+ * row.  The second pass keeps the column order of equal rows and the first
+ * keeps the increasing k of equal (i, j), so perm ends ordered by (i, j)
+ * with ties in increasing k. */
 int oracle_coo_pattern(int64_t n, int64_t ncoo, const int32_t* i, const int32_t* j,
                        int32_t* rowptr, int32_t* col, int64_t* jmap, int32_t* perm,
                        int64_t* nnz_out, int64_t* nvalid_out) {
@@ -83,33 +88,42 @@ int oracle_coo_pattern(int64_t n, int64_t ncoo, const int32_t* i, const int32_t*
     if (i[k] >= n || j[k] >= n) return OR_RANGE;
     nvalid++;
   }
-  coo_key* keys = (coo_key*)malloc(sizeof(coo_key) * (size_t)(nvalid > 0 ? nvalid : 1));
-  if (!keys) return OR_INVALID;
-  int64_t m = 0;
-  for (int64_t k = 0; k < ncoo; k++) {
-    if (i[k] < 0 || j[k] < 0) continue;
-    keys[m].i = i[k];
-    keys[m].j = j[k];
-    keys[m].k = k;
-    m++;
+  int64_t* start = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int32_t* by_col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nvalid > 0 ? nvalid : 1));
+  if (!start || !by_col) {
+    free(start);
+    free(by_col);
+    return OR_INVALID;
   }
-  qsort(keys, (size_t)nvalid, sizeof(coo_key), cmp_key);
+  /* pass 1: kept k in increasing k, placed by column */
+  for (int64_t c = 0; c <= n; c++) start[c] = 0;
+  for (int64_t k = 0; k < ncoo; k++)
+    if (i[k] >= 0 && j[k] >= 0) start[j[k] + 1]++;
+  for (int64_t c = 0; c < n; c++) start[c + 1] += start[c];
+  for (int64_t k = 0; k < ncoo; k++)
+    if (i[k] >= 0 && j[k] >= 0) by_col[start[j[k]]++] = (int32_t)k;
+  /* pass 2: that sequence, placed by row */
+  for (int64_t r = 0; r <= n; r++) start[r] = 0;
+  for (int64_t q = 0; q < nvalid; q++) start[i[by_col[q]] + 1]++;
+  for (int64_t r = 0; r < n; r++) start[r + 1] += start[r];
+  for (int64_t q = 0; q < nvalid; q++) perm[start[i[by_col[q]]]++] = by_col[q];
+  free(by_col);
+  free(start);
 
   int64_t nnz = 0;
   for (int64_t r = 0; r <= n; r++) rowptr[r] = 0;
   for (int64_t q = 0; q < nvalid; q++) {
-    perm[q] = (int32_t)keys[q].k;
-    int first = (q == 0) || keys[q].i != keys[q - 1].i || keys[q].j != keys[q - 1].j;
+    const int64_t k = perm[q];
+    int first = (q == 0) || i[k] != i[perm[q - 1]] || j[k] != j[perm[q - 1]];
     if (first) {
       jmap[nnz] = q;
-      col[nnz] = keys[q].j;
-      rowptr[keys[q].i + 1] += 1; /* count entries per row */
+      col[nnz] = j[k];
+      rowptr[i[k] + 1] += 1; /* count entries per row */
       nnz++;
     }
   }
   jmap[nnz] = nvalid;
   for (int64_t r = 0; r < n; r++) rowptr[r + 1] += rowptr[r];
-  free(keys);
   *nnz_out = nnz;
   *nvalid_out = nvalid;
   return OR_OK;

@@ -222,6 +222,9 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
                          (long long)value);
       h->cg_variant = (int)value;
       return SPX_OK;
+    case SPX_OPT_IR_EARLY_EXIT:
+      h->ir_early_exit = value ? 1 : 0;
+      return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
   }
@@ -272,6 +275,9 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       return SPX_OK;
     case SPX_OPT_SMALL_SOLVE:
       *value = h->small_opt;
+      return SPX_OK;
+    case SPX_OPT_IR_EARLY_EXIT:
+      *value = h->ir_early_exit;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

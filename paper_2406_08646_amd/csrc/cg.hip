@@ -595,7 +595,8 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
 }
 
 __global__ __launch_bounds__(kBlock) void k_ir_finish(CgScalars* so, CgScalars* si, const double* P,
-                                                      int64_t G, double rtol_inner) {
+                                                      int64_t G, double rtol_inner,
+                                                      int early_exit) {
   __shared__ double lds[kLds];
   const double t64 = reduce_all(P, G, lds);
   const double trz = reduce_all(P + G, G, lds);
@@ -606,9 +607,11 @@ __global__ __launch_bounds__(kBlock) void k_ir_finish(CgScalars* so, CgScalars* 
     if (so->status == SPX_OK && sqrt(t64) <= so->thresh) so->done = 1;
     si->rho[0] = trz;
     si->r0norm = sqrt(t32);
-    // the inner solve stops at rtol_inner relative to its right-hand side,
-    // or as soon as the outer target is in reach (last refinement step)
-    si->thresh = fmax(rtol_inner * si->r0norm, 0.5 * so->thresh);
+    // the inner solve stops at rtol_inner relative to its right-hand side;
+    // with early_exit also as soon as the outer target is in reach (this
+    // shortens the last refinement step)
+    si->thresh = early_exit ? fmax(rtol_inner * si->r0norm, 0.5 * so->thresh)
+                            : rtol_inner * si->r0norm;
     si->rr = t32;
     si->iters = 0;
     si->status = SPX_OK;
@@ -1165,7 +1168,7 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
       return SPX_OK;
     }));
     hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, so, si, h->partials, (int64_t)G,
-                       rtol_inner);
+                       rtol_inner, h->ir_early_exit);
     SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], so, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     SPX_CHECK_HIP(hipStreamSynchronize(s));
     const CgScalars o = h->scal_host[2];

@@ -203,6 +203,7 @@ struct spx_matrix {
   // replay of one poll chunk of CG iterations as a HIP graph (fp64, fp32)
   int graph_opt = 0;
   int small_opt = 1;  // one-workgroup solve: 0 never, 1 small systems, 2 whenever it fits
+  int ir_early_exit = 0;  // refinement: 1 also ends an inner solve at rtol_outer ||b|| / 2
   hipStream_t cap_stream = nullptr;
   struct GraphCache {
     hipGraphExec_t exec = nullptr;

@@ -50,6 +50,7 @@ OPT_ROWS_PER_BLOCK_F32 = 11
 OPT_CG_VARIANT = 12
 OPT_GRAPH = 13
 OPT_SMALL_SOLVE = 14
+OPT_IR_EARLY_EXIT = 15
 PROFILE_KINDS = ("spmv_dot_f64", "update_f64", "pupdate_f64", "spmv_dot_f32", "update_f32",
                  "pupdate_f32")
 
@@ -302,8 +303,13 @@ class Matrix:
                            stream)
 
     def cg_solve_mixed(self, b, x=None, rtol_outer=1e-10, rtol_inner=1e-4, maxit_outer=100,
-                       maxit_inner=100000, check_every=20, stream=None):
+                       maxit_inner=100000, check_every=20, stream=None, early_exit=None):
+        """FP32-inner / FP64-outer refinement.  ``early_exit`` (when not None)
+        sets OPT_IR_EARLY_EXIT on the handle first: False runs every inner
+        solve to rtol_inner, True also ends it at rtol_outer ||b|| / 2."""
         _dev(b, torch.float64, self.n, "b")
+        if early_exit is not None:
+            self.set_option(OPT_IR_EARLY_EXIT, 1 if early_exit else 0)
         x = torch.zeros_like(b) if x is None else _dev(x, torch.float64, self.n, "x")
         outer, inner = ctypes.c_int64(), ctypes.c_int64()
         rr = ctypes.c_double()
