@@ -536,16 +536,37 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
     return out
 
 
-def cpu_baseline(grid: int, calls: int):
-    """The oracle as it stands (plain C, one thread) on a bounded sample:
-    its own COO assembly of the same 3-D Q1 workload at grid^3 elements,
-    then `calls` SpMV calls, reported as SpMV GB/s with the same byte
-    count as the GPU figure."""
+def host_threads() -> int:
+    """Host CPUs this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(grid: int, calls: int, full=None):
+    """The oracle as it stands (plain C, gcc -O2) timed on the host, in two
+    legs:
+
+    * one thread on a bounded sample: its own COO assembly of the same 3-D
+      Q1 workload at grid^3 elements, `calls` SpMV calls and 20 Jacobi-CG
+      iterations;
+    * every host thread (OpenMP rows and fixed dot blocks, bitwise the one-
+      thread results) on the full-size matrix when `full` is given: its own
+      assembly (one thread: the sort is sequential), `calls` SpMV calls,
+      Jacobi-CG to 1e-10, and FP64 CG to 1e-12 on the log-normal values,
+      whose solution is the reference for the GPU solutions' errors.
+
+    `full` = (prob, b2, v3, b3, x_c3) with x_c3 the GPU's log-normal
+    solutions by name.  Returns (baseline object, errors object or None)."""
     import numpy as np
 
     import oracle
     from paper_2406_08646_amd import workloads as W
 
+    model, ncpu = host_cpu()
+    threads = host_threads()
+    oracle.set_threads(1)
     prob, x, _ = W.config2(grid)
     t0 = time.perf_counter()
     A = oracle.assemble(prob.n, prob.i, prob.j, prob.v)
@@ -564,24 +585,77 @@ def cpu_baseline(grid: int, calls: int):
     t0 = time.perf_counter()
     cg = oracle.pcg(A, b, 1e-30, maxit=20)
     t_cg = (time.perf_counter() - t0) / max(1, cg.iters)
-    model, ncpu = host_cpu()
-    return {
-        "value": round(gbs, 3),
-        "unit": "GB/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle (plain C, 1 thread, gcc -O2) on the {grid}^3-element 3-D Q1 matrix "
-                   f"(n={A.n}, ncoo={prob.ncoo}, nnz={A.nnz}): its own COO assembly "
-                   f"{t_asm:.2f} s (numeric stage {t_val * 1e3:.1f} ms), median of {calls} SpMV "
-                   f"calls {med * 1e3:.2f} ms, Jacobi-CG {t_cg * 1e3:.2f} ms per iteration; "
-                   f"host '{model}', {ncpu} logical CPUs"),
-        "assembly_s": round(t_asm, 3),
-        "set_values_ms": round(t_val * 1e3, 2),
+    one = {
+        "cores": 1, "value": round(gbs, 3), "unit": "GB/s",
+        "sample": (f"{grid}^3-element 3-D Q1 matrix (n={A.n}, ncoo={prob.ncoo}, nnz={A.nnz})"),
+        "assembly_s": round(t_asm, 3), "set_values_ms": round(t_val * 1e3, 2),
         "set_values_gbs": round(set_values_bytes(prob.ncoo, A.nvalid, A.nnz) / t_val / 1e9, 3),
-        "spmv_ms": round(med * 1e3, 3),
-        "cg_ms_per_iter": round(t_cg * 1e3, 3),
+        "spmv_ms": round(med * 1e3, 3), "cg_ms_per_iter": round(t_cg * 1e3, 3),
         "cg_gbs": round(cg_iteration_bytes(A.n, A.nnz) / t_cg / 1e9, 3),
     }
+    del A, prob
+    legs = [one]
+    errors = None
+    if full is not None:
+        fprob, b2, v3, b3, x_c3 = full
+        t0 = time.perf_counter()
+        rowptr, col, jmap, perm = oracle.coo_pattern(fprob.n, fprob.i, fprob.j)
+        t_pat = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        val2 = oracle.coo_values(jmap, perm, fprob.v)
+        t_val2 = time.perf_counter() - t0
+        F = oracle.CsrMatrix(fprob.n, rowptr, col, val2, jmap, perm, fprob.ncoo)
+        xr = np.random.default_rng(0).uniform(-1.0, 1.0, F.n)
+        times = []
+        for _ in range(calls):
+            t0 = time.perf_counter()
+            oracle.spmv(F, xr)
+            times.append(time.perf_counter() - t0)
+        fmed = statistics.median(times)
+        t0 = time.perf_counter()
+        c2 = oracle.pcg(F, b2, 1e-10)
+        t_c2 = time.perf_counter() - t0
+        F3 = oracle.CsrMatrix(fprob.n, rowptr, col, oracle.coo_values(jmap, perm, v3), jmap, perm,
+                              fprob.ncoo)
+        del F, val2
+        t0 = time.perf_counter()
+        o64 = oracle.pcg(F3, b3, 1e-12)
+        t_o64 = time.perf_counter() - t0
+        nrm = float(np.linalg.norm(o64.x))
+        bn = float(np.linalg.norm(b3))
+        errors = {"reference": (f"oracle FP64 Jacobi-CG to 1e-12 on the log-normal matrix "
+                                f"({o64.iters} iterations, relres {o64.relres:.3e})")}
+        for name, xg in x_c3.items():
+            errors[name] = {
+                "rel_error": float(np.linalg.norm(xg - o64.x) / nrm),
+                "true_relres": float(np.linalg.norm(b3 - oracle.spmv(F3, xg)) / bn)}
+        legs.append({
+            "cores": threads, "value": round(spmv_bytes(fprob.n, len(col)) / fmed / 1e9, 3),
+            "unit": "GB/s",
+            "sample": (f"timed {fprob.grid}^3-element 3-D Q1 matrix (n={fprob.n}, "
+                       f"ncoo={fprob.ncoo}, nnz={len(col)})"),
+            "symbolic_s_one_thread": round(t_pat, 2), "set_values_ms": round(t_val2 * 1e3, 1),
+            "spmv_ms": round(fmed * 1e3, 3),
+            "cg_1e-10_ms": round(t_c2 * 1e3, 1), "cg_1e-10_iters": c2.iters,
+            "cg_ms_per_iter": round(t_c2 * 1e3 / max(1, c2.iters), 3),
+            "lognormal_cg_1e-12_ms": round(t_o64 * 1e3, 1),
+            "lognormal_cg_1e-12_iters": o64.iters,
+        })
+        oracle.set_threads(1)
+    top = legs[-1]
+    out = {
+        "value": top["value"],
+        "unit": "GB/s",
+        "cores": top["cores"],
+        "kind": "oracle",
+        "sample": ("oracle SpMV GB/s (same byte count as the GPU figure) on the "
+                   + top["sample"] + f" with {top['cores']} thread(s); legs: "
+                   + "; ".join(f"{leg['cores']} thread(s) on the {leg['sample']}" for leg in legs)
+                   + f"; host '{model}', {ncpu} logical CPUs, {threads} usable"),
+        "legs": legs,
+    }
+    return out, errors
 
 
 def main() -> int:
@@ -598,6 +672,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=int, default=63)
     ap.add_argument("--cpu-calls", type=int, default=10)
+    ap.add_argument("--cpu-sample-only", action="store_true",
+                    help="time the oracle on the small sample only (no full-size leg, no errors "
+                         "against the FP64 oracle)")
     ap.add_argument("--extras", default=None,
                     help="comma-separated subset of the extra measurements to run (default: all): "
                          + ", ".join(EXTRAS))
@@ -644,6 +721,7 @@ def main() -> int:
     i_d, j_d = d(prob.i), d(prob.j)
     v2_d, v3_d = d(prob.v), d(prob3.v)
     x_d, b2_d, b3_d = d(x_np), d(b_np), d(b3_np)
+    v3_np = prob3.v
     del prob3
     y_d = torch.empty_like(x_d)
     yt_d = torch.empty_like(x_d)
@@ -655,7 +733,7 @@ def main() -> int:
 
     def run_step(profile: bool):
         rec = {}
-        e = [ev() for _ in range(16)]
+        e = [ev() for _ in range(16)]  # e[0..11] used
         t0 = time.perf_counter()
         e[0].record()
         A = spx.coo_preallocate(n, i_d, j_d)
@@ -697,8 +775,12 @@ def main() -> int:
         r3 = A.cg_solve(b3_d, rtol=1e-10, check_every=args.check_every)
         e[8].record()
         rm = A.cg_solve_mixed(b3_d, rtol_outer=1e-10, rtol_inner=1e-4,
-                              check_every=args.check_every)
+                              check_every=args.check_every, early_exit=False)
         e[9].record()
+        re_ = A.cg_solve_mixed(b3_d, rtol_outer=1e-10, rtol_inner=1e-4,
+                               check_every=args.check_every, early_exit=True)
+        e[11].record()
+        A.set_option(spx.OPT_IR_EARLY_EXIT, 0)
         nnz = A.nnz
         rec["walk"] = A.get_option(spx.OPT_SPMV_VARIANT)
         rec["window"] = A.get_window(arrays=False)
@@ -719,6 +801,9 @@ def main() -> int:
         rec["cg64_ln"] = (r3.iters, r3.relres, r3.status)
         rec["mixed_ms"] = e[8].elapsed_time(e[9])
         rec["mixed"] = (rm.outer, rm.inner, rm.relres, rm.status)
+        rec["mixed_early_ms"] = e[9].elapsed_time(e[11])
+        rec["mixed_early"] = (re_.outer, re_.inner, re_.relres, re_.status)
+        rec["x_c3"] = (r3.x, rm.x, re_.x)
         rec["profile"] = prof
         rec["nnz"] = nnz
         return rec
@@ -735,9 +820,15 @@ def main() -> int:
         recs.append(r)
         log(f"step {k + 1}/{args.steps}: {r['wall_ms']:.1f} ms; cg {r['cg64'][0]} it; "
             f"lognormal fp64 {r['cg64_ln'][0]} it {r['cg64_ln_ms']:.1f} ms; mixed "
-            f"{r['mixed'][0]} outer/{r['mixed'][1]} inner {r['mixed_ms']:.1f} ms")
+            f"{r['mixed'][0]} outer/{r['mixed'][1]} inner {r['mixed_ms']:.1f} ms; early exit "
+            f"{r['mixed_early'][1]} inner {r['mixed_early_ms']:.1f} ms")
+        if k + 1 < args.steps:
+            r.pop("x_c3")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    # the last step's log-normal solutions, for their error against the FP64 oracle
+    x_c3 = {name: t.cpu().numpy() for name, t in zip(("fp64", "mixed", "mixed_early_exit"),
+                                                   recs[-1].pop("x_c3"))}
 
     nnz = recs[0]["nnz"]
     mv_bytes = spmv_bytes(n, nnz)
@@ -791,20 +882,6 @@ def main() -> int:
                                     / (med("set_values_ms") * 1e-3) / 1e9, 1),
             "set_values_bytes": set_values_bytes(ncoo, ncoo, nnz),
         },
-        "cg": {
-            "kappa1_fp64": {"ms": round(med("cg64_ms"), 2), "iters": recs[0]["cg64"][0],
-                            "relres": recs[0]["cg64"][1], "status": recs[0]["cg64"][2],
-                            "ms_per_iter": round(med("cg64_ms") / max(1, recs[0]["cg64"][0]), 4),
-                            "profiled_ms": round(med("cg64_profiled_ms"), 2),
-                            "gbs_per_iter": round(cg_iteration_bytes(n, nnz) * recs[0]["cg64"][0]
-                                                  / (med("cg64_ms") * 1e-3) / 1e9, 1)},
-            "lognormal_fp64": {"ms": round(med("cg64_ln_ms"), 2), "iters": recs[0]["cg64_ln"][0],
-                               "relres": recs[0]["cg64_ln"][1], "status": recs[0]["cg64_ln"][2]},
-            "lognormal_mixed": {"ms": round(med("mixed_ms"), 2), "outer": recs[0]["mixed"][0],
-                                "inner": recs[0]["mixed"][1], "relres": recs[0]["mixed"][2],
-                                "status": recs[0]["mixed"][3]},
-            "mixed_speedup": round(med("cg64_ln_ms") / med("mixed_ms"), 3),
-        },
     }
     if profile:
         tot_ms = sum(r["profile"]["spmv_dot_f64"][0] for r in recs)
@@ -817,6 +894,10 @@ def main() -> int:
             "kernel": (f"k_cg_spmv ({WALKS.get(walk, walk)} walk: q = A p with the p.q partial, "
                        "FP64)"),
             "bytes_per_launch": mv_bytes, "format_bytes_per_launch": fmt_bytes,
+            # the same launches counted in the bytes of the format the walk
+            # reads (16-bit window columns): the stricter figure
+            "format_achieved": round(fmt_bytes / (avg_ms * 1e-3) / 1e9, 1),
+            "format_frac": round(fmt_bytes / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
             "avg_launch_ms": round(avg_ms, 4), "launches": cnt,
             "source_hash": kernel_source_hash(),
         }
@@ -834,9 +915,37 @@ def main() -> int:
                       file=sys.stderr)
                 return 2
         out["extras"] = run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only)
+    errors = None
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle on the {args.cpu_grid}^3-element sample")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_grid, args.cpu_calls)
+        log(f"cpu baseline: oracle on the {args.cpu_grid}^3-element sample (1 thread) and the "
+            f"full-size matrix ({host_threads()} threads)")
+        full = None if args.cpu_sample_only else (prob, b_np, v3_np, b3_np, x_c3)
+        out["cpu_baseline"], errors = cpu_baseline(args.cpu_grid, args.cpu_calls, full)
+    # the whole CG half of the metric, last on the line
+    first = recs[0]
+    out["cg"] = {
+        "kappa1_fp64": {"ms": round(med("cg64_ms"), 2), "iters": first["cg64"][0],
+                        "relres": first["cg64"][1], "status": first["cg64"][2],
+                        "ms_per_iter": round(med("cg64_ms") / max(1, first["cg64"][0]), 4),
+                        "profiled_ms": round(med("cg64_profiled_ms"), 2),
+                        "gbs_per_iter": round(cg_iteration_bytes(n, nnz) * first["cg64"][0]
+                                              / (med("cg64_ms") * 1e-3) / 1e9, 1)},
+        "lognormal_fp64": {"ms": round(med("cg64_ln_ms"), 2), "iters": first["cg64_ln"][0],
+                           "relres": first["cg64_ln"][1], "status": first["cg64_ln"][2]},
+        "lognormal_mixed": {"inner_rule": "rtol_inner 1e-4 (literal)",
+                            "ms": round(med("mixed_ms"), 2), "outer": first["mixed"][0],
+                            "inner": first["mixed"][1], "relres": first["mixed"][2],
+                            "status": first["mixed"][3]},
+        "lognormal_mixed_early_exit": {"inner_rule": "max(rtol_inner ||r32||, rtol_outer ||b|| / 2)",
+                                       "ms": round(med("mixed_early_ms"), 2),
+                                       "outer": first["mixed_early"][0],
+                                       "inner": first["mixed_early"][1],
+                                       "relres": first["mixed_early"][2],
+                                       "status": first["mixed_early"][3]},
+        "mixed_speedup": round(med("cg64_ln_ms") / med("mixed_ms"), 3),
+        "mixed_speedup_early_exit": round(med("cg64_ln_ms") / med("mixed_early_ms"), 3),
+        "error_vs_oracle64": errors,
+    }
     print(json.dumps(out), flush=True)
     return 0
 
