@@ -145,6 +145,32 @@ int spx_stream_sum(const double* x, int64_t n, double* partials, void* stream);
 int spx_cg_solve(spx_handle h, const double* b, double* x, double rtol, int64_t maxit,
                  int32_t check_every, void* stream, int64_t* iters_out, double* relres_out);
 
+/* ---------------------------------------------------------------------------
+ * CG without allocation — for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same kernels, arguments, results and errors as spx_cg_solve
+ * (bitwise the same x and iteration count), but the solver workspace (the
+ * vectors r, p, q, u, the inverse diagonal, the workgroup partials and the
+ * device scalars) lives in one static device array of the library, about
+ * 80 MiB, which every GPU that runs the library holds until the process
+ * ends; the host polls with plain stream synchronisations instead of events
+ * and no HIP graph is captured (SPX_OPT_GRAPH and SPX_OPT_PROFILE have no
+ * effect).  The call allocates nothing, provided the handle itself is
+ * complete: its matrix, values and window index exist once
+ * spx_set_values_coo has run.
+ * Limits: n <= SPX_NOALLOC_MAX_ROWS, and at most 4096 workgroups per solver
+ * kernel (the automatic launch shape uses at most 2048); beyond either the
+ * call returns SPX_INVALID_ARG and launches nothing.  The current device
+ * must be the handle's.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other host threads, or other streams before the first call returns)
+ * race and give wrong results.  The array keeps the last call's contents;
+ * each call initialises everything it reads. */
+#define SPX_NOALLOC_MAX_ROWS 2097152
+int spx_cg_solve_noalloc(spx_handle h, const double* b, double* x, double rtol, int64_t maxit,
+                         int32_t check_every, void* stream, int64_t* iters_out,
+                         double* relres_out);
+
 /* The same solver applied to A^T (adjoint solves). */
 int spx_cg_solve_transpose(spx_handle h, const double* b, double* x, double rtol, int64_t maxit,
                            int32_t check_every, void* stream, int64_t* iters_out,

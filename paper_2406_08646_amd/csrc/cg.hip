@@ -23,6 +23,7 @@
 // matrix copy, vectors and SpMV; fp64 products and sums in every dot.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -658,6 +659,32 @@ int ensure_solver32(spx_matrix* h) {
   return SPX_OK;
 }
 
+// The memory one fp64 solve works in: four vectors of n (r, p, q and the
+// single-reduction form's u), the inverse diagonal, the workgroup partials,
+// the device scalars and their host mirror.  With events, the host polls a
+// chunk while the next one is queued; without, it polls by synchronising
+// the stream.
+struct Work {
+  double* vec = nullptr;       // [4 n]
+  double* dinv = nullptr;      // [n]
+  double* partials = nullptr;  // [4 max(fused_blocks, vector_blocks)]
+  CgScalars* scal = nullptr;   // device [2]
+  CgScalars* host = nullptr;   // host [4]
+  const hipEvent_t* ev = nullptr;  // 2 events or null
+};
+
+// The handle's own workspace, allocated on first use.
+int handle_work(spx_matrix* h, Work* w) {
+  SPX_TRY(ensure_solver(h));
+  w->vec = h->work;
+  w->dinv = h->dinv;
+  w->partials = h->partials;
+  w->scal = h->scal;
+  w->host = h->scal_host;
+  w->ev = h->ev;
+  return SPX_OK;
+}
+
 inline unsigned grid1(int64_t count) {
   return (unsigned)std::max<int64_t>(1, ceil_div(count, 256));
 }
@@ -692,13 +719,13 @@ size_t shape_lds(const SpmvShape& sh) {
 // Enqueues iterations first .. first+count-1 (1-based k) of K1, K2, K3.
 // With `evs` (6 events per iteration) every kernel is bracketed by events.
 template <typename VT>
-int enqueue_iterations(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
-                       CgScalars* st, int64_t first, int64_t count, hipStream_t s,
+int enqueue_iterations(spx_matrix* h, const Work& w, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q,
+                       const VT* dinv, CgScalars* st, int64_t first, int64_t count, hipStream_t s,
                        hipEvent_t* evs, bool device_k = false) {
   const unsigned G1 = (unsigned)fused_blocks(h);
   const unsigned G2 = (unsigned)vector_blocks(h);
-  double* P1 = h->partials;
-  double* P2 = h->partials + G1;
+  double* P1 = w.partials;
+  double* P2 = w.partials + G1;
   const size_t lds = shape_lds<VT>(A.sh);
   return with_shape<true>(A.sh, [&](auto shc) {
     using SH = decltype(shc);
@@ -761,11 +788,12 @@ void accumulate_profile(spx_matrix* h, hipEvent_t* evs, int64_t first, int64_t c
 // each, bracketed by 2K events when `events` is not null).  Returns the last
 // polled state in *final.
 template <typename Enq>
-int run_until_done(spx_matrix* h, CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s,
-                   int K, const int* kinds, int full_at, Enq&& enq, CgScalars* final) {
+int run_until_done(spx_matrix* h, const Work& w, CgScalars* st, int64_t maxit,
+                   int32_t check_every, hipStream_t s, int K, const int* kinds, int full_at,
+                   Enq&& enq, CgScalars* final) {
   int64_t launched = 0;
-  CgScalars* host = h->scal_host;
-  const bool prof = h->profile != 0;
+  CgScalars* host = w.host;
+  const bool prof = h->profile != 0 && w.ev;
   const int64_t per_chunk = 2 * K * (int64_t)check_every;
   if (prof) SPX_TRY(ensure_prof_events(h, 2 * per_chunk));
   int64_t first[2] = {0, 0}, cnt[2] = {0, 0};
@@ -777,7 +805,7 @@ int run_until_done(spx_matrix* h, CgScalars* st, int64_t maxit, int32_t check_ev
     cnt[slot] = m;
     launched += m;
     SPX_CHECK_HIP(hipMemcpyAsync(&host[slot], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-    SPX_CHECK_HIP(hipEventRecord(h->ev[slot], s));
+    if (w.ev) SPX_CHECK_HIP(hipEventRecord(w.ev[slot], s));
     return SPX_OK;
   };
   auto harvest = [&](int slot, int64_t iters) {
@@ -797,8 +825,15 @@ int run_until_done(spx_matrix* h, CgScalars* st, int64_t maxit, int32_t check_ev
   int cur = 0;
   for (;;) {
     const bool more = launched < maxit;
-    if (more) SPX_TRY(chunk(cur ^ 1));
-    SPX_CHECK_HIP(hipEventSynchronize(h->ev[cur]));
+    if (w.ev) {
+      // queue the next chunk, then wait for this one's copy of the scalars
+      if (more) SPX_TRY(chunk(cur ^ 1));
+      SPX_CHECK_HIP(hipEventSynchronize(w.ev[cur]));
+    } else {
+      // no events: wait for this chunk, then queue the next one
+      SPX_CHECK_HIP(hipStreamSynchronize(s));
+      if (!host[cur].done && more) SPX_TRY(chunk(cur ^ 1));
+    }
     if (host[cur].done || !more) {
       *final = host[cur];
       break;
@@ -816,12 +851,12 @@ int run_until_done(spx_matrix* h, CgScalars* st, int64_t maxit, int32_t check_ev
 // take the iteration number from the device), captured on a private stream
 // and kept while the operator, vectors and launch shape stay the same.
 template <typename VT>
-int chunk_graph(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
-                CgScalars* st, int32_t check_every, hipGraphExec_t* out) {
+int chunk_graph(spx_matrix* h, const Work& w, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q,
+                const VT* dinv, CgScalars* st, int32_t check_every, hipGraphExec_t* out) {
   spx_matrix::GraphCache& gc = h->graph[sizeof(VT) == 8 ? 0 : 1];
   const uintptr_t key[16] = {(uintptr_t)A.rowptr, (uintptr_t)A.col, (uintptr_t)A.val,
                              (uintptr_t)x, (uintptr_t)r, (uintptr_t)p, (uintptr_t)q,
-                             (uintptr_t)dinv, (uintptr_t)st, (uintptr_t)h->partials,
+                             (uintptr_t)dinv, (uintptr_t)st, (uintptr_t)w.partials,
                              (uintptr_t)check_every, (uintptr_t)fused_blocks(h),
                              (uintptr_t)vector_blocks(h),
                              (uintptr_t)(A.sh.variant * 4096 + A.sh.rows * 8 + A.sh.nt * 2 + A.sh.vec),
@@ -836,7 +871,7 @@ int chunk_graph(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, cons
   }
   if (!h->cap_stream) SPX_CHECK_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   SPX_CHECK_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-  const int st_enq = enqueue_iterations<VT>(h, A, x, r, p, q, dinv, st, 0, check_every,
+  const int st_enq = enqueue_iterations<VT>(h, w, A, x, r, p, q, dinv, st, 0, check_every,
                                             h->cap_stream, nullptr, true);
   hipGraph_t graph = nullptr;
   const hipError_t e_end = hipStreamEndCapture(h->cap_stream, &graph);
@@ -858,37 +893,39 @@ int chunk_graph(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, cons
 }
 
 // The Hestenes-Stiefel iteration (K1, K2, K3) on operator A in precision VT.
+// Graph replay needs the handle's workspace (a graph may outlive the call).
 template <typename VT>
-int run_hs(spx_matrix* h, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q, const VT* dinv,
-           CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s, CgScalars* final) {
+int run_hs(spx_matrix* h, const Work& w, const Op<VT>& A, VT* x, VT* r, VT* p, VT* q,
+           const VT* dinv, CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s,
+           CgScalars* final, bool allow_graph = true) {
   const int kinds64[3] = {0, 1, 2}, kinds32[3] = {3, 4, 5};
   hipGraphExec_t exec = nullptr;
-  if (h->graph_opt && !h->profile)
-    SPX_TRY(chunk_graph<VT>(h, A, x, r, p, q, dinv, st, check_every, &exec));
-  return run_until_done(h, st, maxit, check_every, s, 3, sizeof(VT) == 8 ? kinds64 : kinds32, 1,
+  if (allow_graph && h->graph_opt && !h->profile)
+    SPX_TRY(chunk_graph<VT>(h, w, A, x, r, p, q, dinv, st, check_every, &exec));
+  return run_until_done(h, w, st, maxit, check_every, s, 3, sizeof(VT) == 8 ? kinds64 : kinds32, 1,
                         [&](int64_t first, int64_t count, hipEvent_t* evs) -> int {
                           if (exec && !evs && count == check_every) {
                             SPX_CHECK_HIP(hipGraphLaunch(exec, s));
                             return SPX_OK;
                           }
-                          return enqueue_iterations<VT>(h, A, x, r, p, q, dinv, st, first, count,
-                                                        s, evs);
+                          return enqueue_iterations<VT>(h, w, A, x, r, p, q, dinv, st, first,
+                                                        count, s, evs);
                         },
                         final);
 }
 
 // The single-reduction iteration (KA, KB), fp64.
-int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, double* p,
-           double* sv, CgScalars* st, int64_t maxit, int32_t check_every, hipStream_t s,
-           CgScalars* final) {
+int run_sr(spx_matrix* h, const Work& w, const Op<double>& A, double* x, double* r, double* u,
+           double* p, double* sv, CgScalars* st, int64_t maxit, int32_t check_every,
+           hipStream_t s, CgScalars* final) {
   const unsigned G1 = (unsigned)fused_blocks(h);
   const unsigned G2 = (unsigned)vector_blocks(h);
-  double* P1 = h->partials;
-  double* P2 = h->partials + G1;
+  double* P1 = w.partials;
+  double* P2 = w.partials + G1;
   const size_t lds = shape_lds<double>(A.sh);
   const int kinds[2] = {1, 0};  // KA is the vector kernel, KB the SpMV kernel
   return run_until_done(
-      h, st, maxit, check_every, s, 2, kinds, 0,
+      h, w, st, maxit, check_every, s, 2, kinds, 0,
       [&](int64_t first, int64_t count, hipEvent_t* evs) {
         return with_shape<true>(A.sh, [&](auto shc) {
           using SH = decltype(shc);
@@ -897,7 +934,7 @@ int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, 
             hipEvent_t* e = evs ? evs + 4 * c : nullptr;
             if (e) (void)hipEventRecord(e[0], s);
             hipLaunchKernelGGL(k_sr_update, dim3(G2), dim3(kBlock), 0, s, A.n, x, r, u, p, sv,
-                               h->dinv, st, P1, (int64_t)G1, P2, k);
+                               w.dinv, st, P1, (int64_t)G1, P2, k);
             if (e) (void)hipEventRecord(e[1], s);
             if (e) (void)hipEventRecord(e[2], s);
             hipLaunchKernelGGL((k_sr_spmv<SH>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr,
@@ -912,22 +949,23 @@ int run_sr(spx_matrix* h, const Op<double>& A, double* x, double* r, double* u, 
 }
 
 // Launches the fp64 residual-norm kernels for b - A x into st->rr_true.
-int enqueue_resnorm(spx_matrix* h, const Op<double>& A, const double* b, const double* x,
-                    CgScalars* st, hipStream_t s) {
+int enqueue_resnorm(spx_matrix* h, const Work& w, const Op<double>& A, const double* b,
+                    const double* x, CgScalars* st, hipStream_t s) {
   const unsigned G = (unsigned)fused_blocks(h);
   SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_resnorm<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, A.n,
-                       A.rowptr, A.col, A.val, b, x, h->partials, A.sh.rows, remap_for(h, A.sh), A.sh.tile,
-                       A.win);
+                       A.rowptr, A.col, A.val, b, x, w.partials, A.sh.rows, remap_for(h, A.sh),
+                       A.sh.tile, A.win);
     return SPX_OK;
   }));
-  hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G);
+  hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(kBlock), 0, s, st, w.partials, (int64_t)G);
   return SPX_OK;
 }
 
-int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const double* x,
-                 CgScalars* st, hipStream_t s, int64_t* iters_out, double* relres_out);
+int finish_solve(spx_matrix* h, const Work& w, const Op<double>& A, const double* b,
+                 const double* x, CgScalars* st, hipStream_t s, int64_t* iters_out,
+                 double* relres_out);
 
 // The one-workgroup solve: forced by SPX_OPT_SMALL_SOLVE = 2, chosen by the
 // default 1 for systems of at most kOneAutoRows rows when no launch-shape
@@ -962,23 +1000,25 @@ int cg_form(const spx_matrix* h, const Csr& M) {
 
 namespace {
 
-int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, double rtol,
-                  int64_t maxit, int32_t check_every, hipStream_t s, int64_t* iters_out,
-                  double* relres_out) {
+// The fp64 solve on M in workspace w.  `scratch` marks the static scratch
+// of spx_cg_solve_noalloc: no graph is captured (a graph would keep
+// pointers into memory the next call reuses).
+int cg_solve_impl(spx_matrix* h, const Work& w, const Csr& M, const double* b, double* x,
+                  double rtol, int64_t maxit, int32_t check_every, hipStream_t s,
+                  int64_t* iters_out, double* relres_out, bool scratch = false) {
   if (!b || !x) return set_error(SPX_INVALID_ARG, "cg_solve: b or x is NULL");
   if (maxit < 0 || check_every < 1 || !(rtol >= 0.0))
     return set_error(SPX_INVALID_ARG, "cg_solve: bad maxit/check_every/rtol");
   if (maxit > INT32_MAX - 1) maxit = INT32_MAX - 1;
-  SPX_TRY(ensure_solver(h));
   const int64_t n = M.n;
   const Op<double> A{n, M.rowptr, M.col, M.val, solver_shape(h, M), win_view(M)};
-  double* r = h->work;
-  double* p = h->work + n;
-  double* q = h->work + 2 * n;
-  CgScalars* st = h->scal;
+  double* r = w.vec;
+  double* p = w.vec + n;
+  double* q = w.vec + 2 * n;
+  CgScalars* st = w.scal;
   const unsigned G = (unsigned)fused_blocks(h);
   hipLaunchKernelGGL(k_scal_reset, dim3(1), dim3(64), 0, s, st, (int32_t)maxit);
-  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, h->dinv,
+  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, w.dinv,
                      (float*)nullptr, st);
   CgScalars fin;
   if (use_one_workgroup(h, M)) {
@@ -1000,53 +1040,55 @@ int cg_solve_impl(spx_matrix* h, const Csr& M, const double* b, double* x, doubl
     const size_t lds = (size_t)((rows / 256) * t256 + 8) * sizeof(double);
     if (rows == 1024)
       hipLaunchKernelGGL(k_cg_one<1024>, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b,
-                         x, r, p, q, h->dinv, st, rtol);
+                         x, r, p, q, w.dinv, st, rtol);
     else if (rows == 512)
       hipLaunchKernelGGL(k_cg_one<512>, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b,
-                         x, r, p, q, h->dinv, st, rtol);
+                         x, r, p, q, w.dinv, st, rtol);
     else
       hipLaunchKernelGGL(k_cg_one<256>, dim3(1), dim3(kOne), lds, s, n, M.rowptr, M.col, M.val, b,
-                         x, r, p, q, h->dinv, st, rtol);
+                         x, r, p, q, w.dinv, st, rtol);
     SPX_CHECK_HIP(hipGetLastError());
-    return finish_solve(h, A, b, x, st, s, iters_out, relres_out);
+    return finish_solve(h, w, A, b, x, st, s, iters_out, relres_out);
   }
   SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
     using SH = decltype(shc);
     hipLaunchKernelGGL((k_cg_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
-                       M.rowptr, M.col, M.val, b, x, r, p, h->dinv, h->partials, A.sh.rows,
+                       M.rowptr, M.col, M.val, b, x, r, p, w.dinv, w.partials, A.sh.rows,
                        remap_for(h, A.sh), A.sh.tile, A.win);
     return SPX_OK;
   }));
-  hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, h->partials, (int64_t)G,
+  hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, w.partials, (int64_t)G,
                      rtol);
   SPX_CHECK_HIP(hipGetLastError());
   if (cg_form(h, M) == 1) {
     // k_cg_init left u = D^-1 r in p; move it to its own vector and start
     // w = A u, p = u, s = w, delta_0
-    double* u = h->work + 3 * n;
+    double* u = w.vec + 3 * n;
     SPX_CHECK_HIP(hipMemcpyAsync(u, p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
     SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_sr_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
-                         M.rowptr, M.col, M.val, u, p, q, h->partials, A.sh.rows, remap_for(h, A.sh),
+                         M.rowptr, M.col, M.val, u, p, q, w.partials, A.sh.rows, remap_for(h, A.sh),
                          A.sh.tile, A.win);
       return SPX_OK;
     }));
     SPX_CHECK_HIP(hipGetLastError());
-    SPX_TRY(run_sr(h, A, x, r, u, p, q, st, maxit, check_every, s, &fin));
+    SPX_TRY(run_sr(h, w, A, x, r, u, p, q, st, maxit, check_every, s, &fin));
   } else {
-    SPX_TRY(run_hs<double>(h, A, x, r, p, q, h->dinv, st, maxit, check_every, s, &fin));
+    SPX_TRY(run_hs<double>(h, w, A, x, r, p, q, w.dinv, st, maxit, check_every, s, &fin,
+                           !scratch));
   }
-  return finish_solve(h, A, b, x, st, s, iters_out, relres_out);
+  return finish_solve(h, w, A, b, x, st, s, iters_out, relres_out);
 }
 
 // True residual of the returned x, the outputs and the status of a solve.
-int finish_solve(spx_matrix* h, const Op<double>& A, const double* b, const double* x,
-                 CgScalars* st, hipStream_t s, int64_t* iters_out, double* relres_out) {
-  SPX_TRY(enqueue_resnorm(h, A, b, x, st, s));
-  SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+int finish_solve(spx_matrix* h, const Work& w, const Op<double>& A, const double* b,
+                 const double* x, CgScalars* st, hipStream_t s, int64_t* iters_out,
+                 double* relres_out) {
+  SPX_TRY(enqueue_resnorm(h, w, A, b, x, st, s));
+  SPX_CHECK_HIP(hipMemcpyAsync(&w.host[2], st, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
   SPX_CHECK_HIP(hipStreamSynchronize(s));
-  const CgScalars& f = h->scal_host[2];
+  const CgScalars& f = w.host[2];
   if (iters_out) *iters_out = f.iters;
   if (relres_out) *relres_out = f.bnorm > 0.0 ? sqrt(f.rr_true) / f.bnorm : sqrt(f.rr_true);
   if (f.status == SPX_ZERO_DIAGONAL)
@@ -1109,8 +1151,10 @@ extern "C" int spx_cg_solve(spx_handle h, const double* b, double* x, double rto
                             double* relres_out) {
   clear_error();
   if (!h) return set_error(SPX_INVALID_ARG, "cg_solve: NULL handle");
-  return cg_solve_impl(h, h->A, b, x, rtol, maxit, check_every, static_cast<hipStream_t>(stream),
-                       iters_out, relres_out);
+  Work w;
+  SPX_TRY(handle_work(h, &w));
+  return cg_solve_impl(h, w, h->A, b, x, rtol, maxit, check_every,
+                       static_cast<hipStream_t>(stream), iters_out, relres_out);
 }
 
 extern "C" int spx_cg_solve_transpose(spx_handle h, const double* b, double* x, double rtol,
@@ -1120,7 +1164,9 @@ extern "C" int spx_cg_solve_transpose(spx_handle h, const double* b, double* x, 
   if (!h) return set_error(SPX_INVALID_ARG, "cg_solve_transpose: NULL handle");
   hipStream_t s = static_cast<hipStream_t>(stream);
   SPX_TRY(ensure_transpose(h, s));
-  return cg_solve_impl(h, h->At, b, x, rtol, maxit, check_every, s, iters_out, relres_out);
+  Work w;
+  SPX_TRY(handle_work(h, &w));
+  return cg_solve_impl(h, w, h->At, b, x, rtol, maxit, check_every, s, iters_out, relres_out);
 }
 
 extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, double rtol_outer,
@@ -1134,7 +1180,8 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
     return set_error(SPX_INVALID_ARG, "cg_solve_mixed: bad iteration limits or tolerances");
   if (maxit_inner > INT32_MAX - 1) maxit_inner = INT32_MAX - 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SPX_TRY(ensure_solver(h));
+  Work w;
+  SPX_TRY(handle_work(h, &w));
   SPX_TRY(ensure_solver32(h));
   SPX_TRY(ensure_val32(h, s));
   const Csr& M = h->A;
@@ -1146,15 +1193,15 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
   float* d32 = h->work32 + n;
   float* p32 = h->work32 + 2 * n;
   float* q32 = h->work32 + 3 * n;
-  CgScalars* so = h->scal;
-  CgScalars* si = h->scal + 1;
+  CgScalars* so = w.scal;
+  CgScalars* si = w.scal + 1;
   const unsigned G = (unsigned)fused_blocks(h);
   hipLaunchKernelGGL(k_scal_reset, dim3(1), dim3(64), 0, s, so, (int32_t)0);
   hipLaunchKernelGGL(k_scal_reset, dim3(1), dim3(64), 0, s, si, (int32_t)maxit_inner);
-  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, h->dinv, h->dinv32,
+  hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, w.dinv, h->dinv32,
                      so);
-  hipLaunchKernelGGL(k_norm2, dim3(G), dim3(kBlock), 0, s, n, b, h->partials);
-  hipLaunchKernelGGL(k_norm2_finish, dim3(1), dim3(kBlock), 0, s, so, h->partials, (int64_t)G,
+  hipLaunchKernelGGL(k_norm2, dim3(G), dim3(kBlock), 0, s, n, b, w.partials);
+  hipLaunchKernelGGL(k_norm2_finish, dim3(1), dim3(kBlock), 0, s, so, w.partials, (int64_t)G,
                      rtol_outer);
   SPX_CHECK_HIP(hipGetLastError());
   int64_t outer = 0, inner = 0;
@@ -1163,15 +1210,15 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
     SPX_TRY(with_shape<true>(sh, [&](auto shc) {
       using SH = decltype(shc);
       hipLaunchKernelGGL((k_ir_residual<SH>), dim3(G), dim3(kBlock), shape_lds<double>(sh), s, n,
-                         M.rowptr, M.col, M.val, b, x, h->dinv32, r32, d32, p32, h->partials,
+                         M.rowptr, M.col, M.val, b, x, h->dinv32, r32, d32, p32, w.partials,
                          sh.rows, remap_for(h, sh), sh.tile, A64.win);
       return SPX_OK;
     }));
-    hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, so, si, h->partials, (int64_t)G,
+    hipLaunchKernelGGL(k_ir_finish, dim3(1), dim3(kBlock), 0, s, so, si, w.partials, (int64_t)G,
                        rtol_inner, h->ir_early_exit);
-    SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], so, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+    SPX_CHECK_HIP(hipMemcpyAsync(&w.host[2], so, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     SPX_CHECK_HIP(hipStreamSynchronize(s));
-    const CgScalars o = h->scal_host[2];
+    const CgScalars o = w.host[2];
     if (o.status != SPX_OK) {
       status = o.status;
       break;
@@ -1183,7 +1230,7 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
     }
     ++outer;
     CgScalars fin;
-    SPX_TRY(run_hs<float>(h, A32, d32, r32, p32, q32, h->dinv32, si, maxit_inner, check_every, s,
+    SPX_TRY(run_hs<float>(h, w, A32, d32, r32, p32, q32, h->dinv32, si, maxit_inner, check_every, s,
                           &fin));
     inner += fin.iters;
     hipLaunchKernelGGL(k_ir_update, dim3(G), dim3(kBlock), 0, s, n, x, d32);
@@ -1192,10 +1239,10 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
       break;
     }
   }
-  SPX_TRY(enqueue_resnorm(h, A64, b, x, so, s));
-  SPX_CHECK_HIP(hipMemcpyAsync(&h->scal_host[2], so, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+  SPX_TRY(enqueue_resnorm(h, w, A64, b, x, so, s));
+  SPX_CHECK_HIP(hipMemcpyAsync(&w.host[2], so, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
   SPX_CHECK_HIP(hipStreamSynchronize(s));
-  const CgScalars& f = h->scal_host[2];
+  const CgScalars& f = w.host[2];
   if (outer_out) *outer_out = outer;
   if (inner_out) *inner_out = inner;
   if (relres_out) *relres_out = f.bnorm > 0.0 ? sqrt(f.rr_true) / f.bnorm : sqrt(f.rr_true);
@@ -1206,4 +1253,90 @@ extern "C" int spx_cg_solve_mixed(spx_handle h, const double* b, double* x, doub
     return set_error(status, "cg_solve_mixed: %lld outer steps, relres %g", (long long)outer,
                      f.bnorm > 0.0 ? sqrt(f.rr_true) / f.bnorm : 0.0);
   return SPX_OK;
+}
+
+// ------------------------------------------------ solve without allocation
+//
+// spx_cg_solve_noalloc runs spx_cg_solve's kernels in the library's own
+// device array `scratch` instead of the handle's lazily allocated workspace.
+// Layout (doubles, every part 256-byte aligned): the two solver scalar
+// blocks, the workgroup partials, r, p, q, u packed at stride n as in the
+// handle's workspace, and the inverse diagonal after four times
+// SPX_NOALLOC_MAX_ROWS (rounded up to 32).
+
+namespace spx {
+namespace {
+
+constexpr int64_t kNoallocMaxBlocks = 4096;  // workgroups of a solver kernel
+constexpr int64_t kScratchScal = 2 * ((sizeof(CgScalars) + 255) / 256) * 32;
+constexpr int64_t kScratchPartials = 4 * kNoallocMaxBlocks;
+constexpr int64_t kScratchStride = (SPX_NOALLOC_MAX_ROWS + 31) / 32 * 32;
+constexpr int64_t kScratchDoubles = kScratchScal + kScratchPartials + 5 * kScratchStride;
+constexpr int kScratchDevices = 64;
+
+}  // namespace
+}  // namespace spx
+
+static __device__ __align__(256) double scratch[spx::kScratchDoubles];
+
+namespace spx {
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kScratchDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device), looked
+// up on the first call there and kept: each GPU holds its own copy of the
+// array at its own address, and host code must never use the array's name.
+int scratch_on_device(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kScratchDevices)
+    return set_error(SPX_INVALID_ARG, "cg_solve_noalloc: device %d out of range", dev);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(SPX_HIP_ERROR, "cg_solve_noalloc: scratch address on device %d: %s", dev,
+                       hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return SPX_OK;
+}
+
+}  // namespace
+}  // namespace spx
+
+extern "C" int spx_cg_solve_noalloc(spx_handle h, const double* b, double* x, double rtol,
+                                    int64_t maxit, int32_t check_every, void* stream,
+                                    int64_t* iters_out, double* relres_out) {
+  clear_error();
+  if (!h) return set_error(SPX_INVALID_ARG, "cg_solve_noalloc: NULL handle");
+  const int64_t n = h->n;
+  if (n > SPX_NOALLOC_MAX_ROWS)
+    return set_error(SPX_INVALID_ARG, "cg_solve_noalloc: %lld rows exceed the limit of %d",
+                     (long long)n, SPX_NOALLOC_MAX_ROWS);
+  const int64_t G = std::max(fused_blocks(h), vector_blocks(h));
+  if (G > kNoallocMaxBlocks)
+    return set_error(SPX_INVALID_ARG,
+                     "cg_solve_noalloc: %lld workgroups per solver kernel exceed the limit of %lld",
+                     (long long)G, (long long)kNoallocMaxBlocks);
+  int dev = -1;
+  SPX_CHECK_HIP(hipGetDevice(&dev));
+  if (dev != h->device)
+    return set_error(SPX_INVALID_ARG,
+                     "cg_solve_noalloc: the current device %d is not the handle's device %d", dev,
+                     h->device);
+  double* base = nullptr;
+  SPX_TRY(scratch_on_device(dev, &base));
+  Work w;
+  w.scal = reinterpret_cast<CgScalars*>(base);
+  w.partials = base + kScratchScal;
+  w.vec = w.partials + kScratchPartials;
+  w.dinv = w.vec + 4 * kScratchStride;
+  CgScalars host[4];  // pageable: read only after the stream is synchronised
+  w.host = host;
+  w.ev = nullptr;
+  return cg_solve_impl(h, w, h->A, b, x, rtol, maxit, check_every,
+                       static_cast<hipStream_t>(stream), iters_out, relres_out, true);
 }

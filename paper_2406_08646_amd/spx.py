@@ -51,6 +51,7 @@ OPT_CG_VARIANT = 12
 OPT_GRAPH = 13
 OPT_SMALL_SOLVE = 14
 OPT_IR_EARLY_EXIT = 15
+NOALLOC_MAX_ROWS = 2097152  # SPX_NOALLOC_MAX_ROWS
 PROFILE_KINDS = ("spmv_dot_f64", "update_f64", "pupdate_f64", "spmv_dot_f32", "update_f32",
                  "pupdate_f32")
 
@@ -72,6 +73,7 @@ _SIGNATURES = {
     "spx_matmult_transpose": [_vp, _vp, _vp, _vp],
     "spx_spmm": [_vp, _i64, _vp, _i64, _vp, _i64, _vp],
     "spx_cg_solve": [_vp, _vp, _vp, _d, _i64, _i32, _vp, _pi64, _pd],
+    "spx_cg_solve_noalloc": [_vp, _vp, _vp, _d, _i64, _i32, _vp, _pi64, _pd],
     "spx_cg_solve_transpose": [_vp, _vp, _vp, _d, _i64, _i32, _vp, _pi64, _pd],
     "spx_cg_solve_mixed": [_vp, _vp, _vp, _d, _d, _i64, _i64, _i32, _vp, _pi64, _pi64, _pd],
     "spx_batch_create": [_i32, ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp)],
@@ -297,6 +299,15 @@ class Matrix:
 
     def cg_solve(self, b, x=None, rtol=1e-10, maxit=100000, check_every=20, stream=None):
         return self._solve(load_library().spx_cg_solve, b, x, rtol, maxit, check_every, stream)
+
+    def cg_solve_noalloc(self, b, x, rtol=1e-10, maxit=100000, check_every=20, stream=None):
+        """spx_cg_solve_noalloc: the same solve in the library's static
+        scratch (n <= NOALLOC_MAX_ROWS).  x is required (in: x0, out: the
+        solution), so that the call allocates nothing on this side either."""
+        if x is None:
+            raise ValueError("cg_solve_noalloc needs x (the call allocates nothing)")
+        return self._solve(load_library().spx_cg_solve_noalloc, b, x, rtol, maxit, check_every,
+                           stream)
 
     def cg_solve_transpose(self, b, x=None, rtol=1e-10, maxit=100000, check_every=20, stream=None):
         return self._solve(load_library().spx_cg_solve_transpose, b, x, rtol, maxit, check_every,
