@@ -32,6 +32,7 @@ typedef struct spx_matrix* spx_handle;
 typedef struct spx_batch* spx_batch_handle;
 typedef struct spx_vec_coo* spx_vec_handle;
 typedef struct spx_lbfgs* spx_lbfgs_handle;
+typedef struct spx_split* spx_split_handle;
 
 enum spx_status {
   SPX_OK = 0,
@@ -100,6 +101,61 @@ int spx_vec_set_values_coo(spx_vec_handle h, const double* v, int mode, double* 
 int spx_vec_coo_get_info(spx_vec_handle h, int64_t* n, int64_t* nunique, int64_t* nvalid,
                          int64_t* ncoo);
 int spx_vec_coo_destroy(spx_vec_handle h);
+
+/* ---------------------------------------------------------------------------
+ * One rank's rows as a diagonal and an off-diagonal block — paper Sec. 5
+ * (parallel matrices are distributed by rows, each process storing its
+ * diagonal block, intra-process coupling, and its off-diagonal block,
+ * inter-process coupling, as two sequential CSR matrices; the numeric stage
+ * fills both from the one v[]).  The single-GPU half of that assembly: the
+ * rank owns rows and columns [row_lo, row_hi) of an n_global x n_global
+ * matrix.  A kept triplet with row in the range goes to the diagonal block
+ * when its column is in the range too, else to the off-diagonal block; one
+ * with its row outside the range belongs to another rank (PETSc sends it;
+ * here it is only counted, as nremote, and not assembled).  Negative
+ * indices are ignored; an index >= n_global is SPX_INDEX_OUT_OF_RANGE.
+ *   diagonal block: (row_hi - row_lo) square, local row and column numbers;
+ *   off-diagonal block: compressed both ways.  Its rows are the local rows
+ *     with at least one off-diagonal entry (orows[], ascending local row
+ *     numbers) and its columns the distinct off-diagonal global columns
+ *     (garray[], ascending: the ghost entries of x).  It is stored as a
+ *     square spx matrix of order max(nrows_offdiag, nghost, 1) whose rows
+ *     from nrows_offdiag on are empty.
+ * Each block is assembled exactly as spx_coo_preallocate would assemble the
+ * stream with every triplet of the other block and of other ranks given
+ * index -1, so its values are bitwise those sums and its jmap/perm index
+ * the caller's v directly.  i, j: device int32[ncoo], not referenced after
+ * the call.  Synchronises `stream`. */
+int spx_split_preallocate(int64_t n_global, int64_t row_lo, int64_t row_hi, int64_t ncoo,
+                          const int32_t* i, const int32_t* j, void* stream,
+                          spx_split_handle* out);
+/* Numeric stage of both blocks from v (device float64[ncoo], the order of
+ * i/j), INSERT or ADD as spx_set_values_coo.  Asynchronous. */
+int spx_split_set_values_coo(spx_split_handle h, const double* v, int mode, void* stream);
+/* y = A_d x_local + A_o x_ghost: the diagonal block's product (as
+ * spx_matmult), then each off-diagonal row's products added in column order
+ * from +0.0 and that sum added to y at its local row.  x_local, y: device
+ * float64[row_hi - row_lo]; x_ghost: device float64[nghost], x_ghost[c] the
+ * value of global entry garray[c].  Asynchronous. */
+int spx_split_matmult(spx_split_handle h, const double* x_local, const double* x_ghost, double* y,
+                      void* stream);
+/* x_ghost[c] = x_global[garray[c]]: on one GPU this stands in for the halo
+ * exchange that brings the ghost entries from their owners.  x_global:
+ * device float64[n_global].  Asynchronous. */
+int spx_split_gather_ghosts(spx_split_handle h, const double* x_global, double* x_ghost,
+                            void* stream);
+/* HOST outputs: local rows, ghost columns, off-diagonal rows, triplets of
+ * other ranks' rows. */
+int spx_split_get_info(spx_split_handle h, int64_t* rows, int64_t* nghost, int64_t* nrows_offdiag,
+                       int64_t* nremote);
+/* The two blocks as borrowed matrix handles (owned by h: valid until
+ * spx_split_destroy, never passed to spx_destroy), for products, solves and
+ * introspection of one block. */
+int spx_split_blocks(spx_split_handle h, spx_handle* diag, spx_handle* offdiag);
+/* Copies garray (device int32[nghost]) and orows (device int32[nrows_offdiag]);
+ * either may be NULL.  Asynchronous. */
+int spx_split_get_maps(spx_split_handle h, int32_t* garray, int32_t* orows, void* stream);
+int spx_split_destroy(spx_split_handle h);
 
 /* ---------------------------------------------------------------------------
  * Products — paper Sec. 6 (MatMult inside CG).

@@ -107,6 +107,14 @@ _SIGNATURES = {
     "spx_vec_set_values_coo": [_vp, _vp, ctypes.c_int, _vp, _vp],
     "spx_vec_coo_get_info": [_vp, _pi64, _pi64, _pi64, _pi64],
     "spx_vec_coo_destroy": [_vp],
+    "spx_split_preallocate": [_i64, _i64, _i64, _i64, _vp, _vp, _vp, ctypes.POINTER(_vp)],
+    "spx_split_set_values_coo": [_vp, _vp, ctypes.c_int, _vp],
+    "spx_split_matmult": [_vp, _vp, _vp, _vp, _vp],
+    "spx_split_gather_ghosts": [_vp, _vp, _vp, _vp],
+    "spx_split_get_info": [_vp, _pi64, _pi64, _pi64, _pi64],
+    "spx_split_blocks": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)],
+    "spx_split_get_maps": [_vp, _vp, _vp, _vp],
+    "spx_split_destroy": [_vp],
     "spx_last_error": [],
     "spx_version": [],
 }
@@ -184,19 +192,24 @@ class MixedResult:
 
 
 class Matrix:
-    """A matrix assembled from COO triplets on the GPU (owns a spx handle)."""
+    """A matrix assembled from COO triplets on the GPU (owns a spx handle,
+    or borrows one that ``owner`` keeps alive)."""
 
-    def __init__(self, handle: ctypes.c_void_p, n: int, ncoo: int, device: torch.device):
+    def __init__(self, handle: ctypes.c_void_p, n: int, ncoo: int, device: torch.device,
+                 owner=None):
         self._h = handle
         self.n = n
         self.ncoo = ncoo
         self.device = device
+        self._owner = owner
 
     # -- lifetime
     def destroy(self) -> None:
         if self._h:
-            _check(load_library().spx_destroy(self._h))
+            if self._owner is None:
+                _check(load_library().spx_destroy(self._h))
             self._h = None
+            self._owner = None
 
     def __del__(self):
         try:
@@ -389,6 +402,90 @@ def coo_preallocate(n: int, i: torch.Tensor, j: torch.Tensor, stream=None) -> Ma
     _check(load_library().spx_coo_preallocate(n, ncoo, _ptr(i), _ptr(j), _stream(stream),
                                               ctypes.byref(h)))
     return Matrix(h, n, ncoo, i.device)
+
+
+class SplitMatrix:
+    """One rank's rows [row_lo, row_hi) of an n_global x n_global matrix as a
+    diagonal block and a compressed off-diagonal block (spx_split_*)."""
+
+    def __init__(self, n_global: int, row_lo: int, row_hi: int, i: torch.Tensor, j: torch.Tensor,
+                 stream=None):
+        ncoo = i.numel()
+        _dev(i, torch.int32, None, "i")
+        _dev(j, torch.int32, ncoo, "j")
+        self._h = None
+        h = ctypes.c_void_p()
+        _check(load_library().spx_split_preallocate(n_global, row_lo, row_hi, ncoo, _ptr(i),
+                                                    _ptr(j), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.n_global, self.row_lo, self.row_hi, self.ncoo = n_global, row_lo, row_hi, ncoo
+        self.device = i.device
+        rows, ng, nro, nrem = (ctypes.c_int64() for _ in range(4))
+        _check(load_library().spx_split_get_info(h, ctypes.byref(rows), ctypes.byref(ng),
+                                                 ctypes.byref(nro), ctypes.byref(nrem)))
+        self.rows, self.nghost, self.nrows_offdiag, self.nremote = (rows.value, ng.value,
+                                                                    nro.value, nrem.value)
+        d, o = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(load_library().spx_split_blocks(h, ctypes.byref(d), ctypes.byref(o)))
+        self.diag = Matrix(d, self.rows, ncoo, self.device, owner=self)
+        self.offdiag = Matrix(o, max(self.nrows_offdiag, self.nghost, 1), ncoo, self.device,
+                              owner=self)
+
+    def destroy(self) -> None:
+        if self._h:
+            self.diag.destroy()
+            self.offdiag.destroy()
+            _check(load_library().spx_split_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise RuntimeError("split matrix has been destroyed")
+        return self._h
+
+    def set_values_coo(self, v: torch.Tensor, mode: int = INSERT_VALUES, stream=None) -> None:
+        _dev(v, torch.float64, self.ncoo, "v")
+        _check(load_library().spx_split_set_values_coo(self.handle, _ptr(v), mode, _stream(stream)))
+
+    def maps(self, stream=None):
+        """(garray, orows): the ghost columns' global numbers and the local rows
+        of the off-diagonal block."""
+        garray = torch.empty(self.nghost, dtype=torch.int32, device=self.device)
+        orows = torch.empty(self.nrows_offdiag, dtype=torch.int32, device=self.device)
+        _check(load_library().spx_split_get_maps(self.handle, _ptr(garray), _ptr(orows),
+                                                 _stream(stream)))
+        return garray, orows
+
+    def gather_ghosts(self, x_global: torch.Tensor, x_ghost=None, stream=None) -> torch.Tensor:
+        _dev(x_global, torch.float64, self.n_global, "x_global")
+        x_ghost = torch.empty(self.nghost, dtype=torch.float64, device=self.device) \
+            if x_ghost is None else _dev(x_ghost, torch.float64, self.nghost, "x_ghost")
+        _check(load_library().spx_split_gather_ghosts(self.handle, _ptr(x_global), _ptr(x_ghost),
+                                                      _stream(stream)))
+        return x_ghost
+
+    def matmult(self, x_local: torch.Tensor, x_ghost: torch.Tensor, y=None,
+                stream=None) -> torch.Tensor:
+        _dev(x_local, torch.float64, self.rows, "x_local")
+        _dev(x_ghost, torch.float64, self.nghost, "x_ghost")
+        y = torch.empty_like(x_local) if y is None else _dev(y, torch.float64, self.rows, "y")
+        _check(load_library().spx_split_matmult(self.handle, _ptr(x_local), _ptr(x_ghost), _ptr(y),
+                                                _stream(stream)))
+        return y
+
+
+def split_preallocate(n_global: int, row_lo: int, row_hi: int, i: torch.Tensor, j: torch.Tensor,
+                      stream=None) -> SplitMatrix:
+    """Rows [row_lo, row_hi) of the COO stream as diagonal and off-diagonal
+    blocks (paper Sec. 5)."""
+    return SplitMatrix(n_global, row_lo, row_hi, i, j, stream)
 
 
 class BatchTuning(ctypes.Structure):
