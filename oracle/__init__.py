@@ -92,6 +92,8 @@ def _load():
         lib.oracle_vec_coo.restype = ctypes.c_int
         lib.oracle_bicg.argtypes = lib.oracle_pcg.argtypes
         lib.oracle_bicg.restype = ctypes.c_int
+        lib.oracle_pcg_pipelined.argtypes = lib.oracle_pcg.argtypes
+        lib.oracle_pcg_pipelined.restype = ctypes.c_int
         lib.oracle_tfqmr.argtypes = lib.oracle_pcg.argtypes + [_dref]
         lib.oracle_tfqmr.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -276,6 +278,19 @@ def pcg_single_reduction(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 
     rr = ctypes.c_double(0.0)
     st = lib.oracle_pcg_single_reduction(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit,
                                          ctypes.byref(it), ctypes.byref(rr))
+    return CgResult(x, it.value, rr.value, st)
+
+
+def pcg_pipelined(A: CsrMatrix, b: np.ndarray, rtol: float, maxit: int = 100000,
+                  x0: np.ndarray | None = None) -> CgResult:
+    """Pipelined (Ghysels-Vanroose) Jacobi-PCG: one reduction per iteration,
+    overlappable with the next product."""
+    lib = _load()
+    x = np.zeros(A.n) if x0 is None else _cf(x0).copy()
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    st = lib.oracle_pcg_pipelined(A.n, A.rowptr, A.col, A.val, _cf(b), x, rtol, maxit,
+                                  ctypes.byref(it), ctypes.byref(rr))
     return CgResult(x, it.value, rr.value, st)
 
 

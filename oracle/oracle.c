@@ -470,6 +470,92 @@ int oracle_pcg_single_reduction(int64_t n, const int32_t* rowptr, const int32_t*
 }
 
 /* ------------------------------------------------------------------------
+ * Pipelined Jacobi-PCG (Ghysels and Vanroose, 2014, preconditioned form):
+ * the same Krylov iterates as CG in exact arithmetic, rearranged so that
+ * the dots of an iteration need not finish before its next product starts
+ * (the paper's Sec. 6 aim of hiding the synchronisation of the reductions).
+ * With M = D:
+ *   r = b - A x; u = D^-1 r; w = A u
+ *   for i = 0, 1, ...:
+ *     gamma = r.u; delta = w.u; ||r||    (one reduction)
+ *     stop when ||r|| <= rtol ||b||      (iters = i)
+ *     m = D^-1 w; nv = A m
+ *     i = 0: beta = 0, alpha = gamma / delta
+ *     else:  beta = gamma / gamma_prev,
+ *            alpha = gamma / (delta - beta gamma / alpha_prev)
+ *     z = nv + beta z; q = m + beta q; s = w + beta s; p = u + beta p
+ *       (at i = 0: z = nv, q = m, s = w, p = u)
+ *     x += alpha p; r -= alpha s; u -= alpha q; w -= alpha z
+ * An alpha denominator <= 0 or not finite is a breakdown; i = maxit before
+ * the test passes is "not converged".
+ * ---------------------------------------------------------------------- */
+int oracle_pcg_pipelined(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                         const double* b, double* x, double rtol, int64_t maxit, int64_t* iters,
+                         double* relres) {
+  double* buf = (double*)malloc(sizeof(double) * (size_t)n * 11);
+  double *r = buf, *u = buf + n, *w = buf + 2 * n, *m = buf + 3 * n, *nv = buf + 4 * n;
+  double *z = buf + 5 * n, *q = buf + 6 * n, *s = buf + 7 * n, *p = buf + 8 * n;
+  double *dinv = buf + 9 * n, *t = buf + 10 * n;
+  int status = diag_inverse(n, rowptr, col, val, dinv);
+  int64_t i = 0;
+  double bnorm = sqrt(dot64(n, b, b));
+  if (status == OR_OK) {
+    oracle_spmv(n, rowptr, col, val, x, t);
+    for (int64_t e = 0; e < n; e++) r[e] = b[e] - t[e];
+    for (int64_t e = 0; e < n; e++) u[e] = dinv[e] * r[e];
+    oracle_spmv(n, rowptr, col, val, u, w);
+    double gamma_prev = 0.0, alpha_prev = 0.0;
+    status = OR_NOT_CONVERGED;
+    for (;;) {
+      double gamma = dot64(n, r, u);
+      double delta = dot64(n, w, u);
+      double rnorm = sqrt(dot64(n, r, r));
+      if (rnorm <= rtol * bnorm) {
+        status = OR_OK;
+        break;
+      }
+      if (i >= maxit) break;
+      for (int64_t e = 0; e < n; e++) m[e] = dinv[e] * w[e];
+      oracle_spmv(n, rowptr, col, val, m, nv);
+      double beta = 0.0, den = delta;
+      if (i > 0) {
+        beta = gamma / gamma_prev;
+        den = delta - beta * gamma / alpha_prev;
+      }
+      if (!(den > 0.0) || !isfinite(den)) {
+        status = OR_BREAKDOWN;
+        break;
+      }
+      double alpha = gamma / den;
+      if (i == 0) {
+        for (int64_t e = 0; e < n; e++) z[e] = nv[e];
+        for (int64_t e = 0; e < n; e++) q[e] = m[e];
+        for (int64_t e = 0; e < n; e++) s[e] = w[e];
+        for (int64_t e = 0; e < n; e++) p[e] = u[e];
+      } else {
+        for (int64_t e = 0; e < n; e++) z[e] = nv[e] + beta * z[e];
+        for (int64_t e = 0; e < n; e++) q[e] = m[e] + beta * q[e];
+        for (int64_t e = 0; e < n; e++) s[e] = w[e] + beta * s[e];
+        for (int64_t e = 0; e < n; e++) p[e] = u[e] + beta * p[e];
+      }
+      for (int64_t e = 0; e < n; e++) x[e] = x[e] + alpha * p[e];
+      for (int64_t e = 0; e < n; e++) r[e] = r[e] - alpha * s[e];
+      for (int64_t e = 0; e < n; e++) u[e] = u[e] - alpha * q[e];
+      for (int64_t e = 0; e < n; e++) w[e] = w[e] - alpha * z[e];
+      gamma_prev = gamma;
+      alpha_prev = alpha;
+      i++;
+    }
+  }
+  oracle_spmv(n, rowptr, col, val, x, t);
+  for (int64_t e = 0; e < n; e++) r[e] = b[e] - t[e];
+  *relres = bnorm > 0.0 ? sqrt(dot64(n, r, r)) / bnorm : sqrt(dot64(n, r, r));
+  *iters = i;
+  free(buf);
+  return status;
+}
+
+/* ------------------------------------------------------------------------
  * Jacobi-preconditioned BiCG (paper Sec. 7 names BiCG with diagonal
  * preconditioning as one of the two batched Krylov methods).  Textbook
  * preconditioned biconjugate gradients with M = D = diag(A) and the shadow

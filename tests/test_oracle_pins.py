@@ -637,6 +637,72 @@ def test_single_reduction_cg_tracks_hestenes_stiefel(orc):
     assert rr.status == -5 and rr.iters == 3
 
 
+# ------------------------------------------- pipelined (Ghysels-Vanroose) CG
+
+@pytest.mark.parametrize("N,dim", [(3, 2), (8, 2), (2, 3), (4, 3)])
+def test_pipelined_cg_matches_dense_lu(orc, N, dim):
+    rng = np.random.default_rng(90 + N)
+    p = W.q1_poisson(N, dim, kappa=np.exp(rng.standard_normal(N**dim)))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    b = rng.uniform(-1, 1, p.n)
+    D = np.zeros((p.n, p.n))
+    D[np.repeat(np.arange(p.n), np.diff(A.rowptr)), A.col] = A.val
+    xs = np.linalg.solve(D, b)
+    res = orc.pcg_pipelined(A, b, 1e-13, 10000)
+    assert res.status == 0 and res.relres <= 1e-12
+    assert np.linalg.norm(res.x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_pipelined_cg_iterates_equal_hestenes_stiefel(orc):
+    """The k-th iterate is the k-th CG iterate (same Krylov space, same
+    minimisation), so after a fixed k steps the two forms agree to rounding.
+    The first one is closed form: x_1 = (r.u / (A u).u) u with u = D^-1 b."""
+    rng = np.random.default_rng(7)
+    N = 9
+    p = W.q1_poisson(N, 2, kappa=np.exp(rng.standard_normal(N * N)))
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    b = rng.uniform(-1, 1, p.n)
+    D = np.zeros((p.n, p.n))
+    D[np.repeat(np.arange(p.n), np.diff(A.rowptr)), A.col] = A.val
+    u = b / np.diag(D)
+    x1 = (b @ u) / ((D @ u) @ u) * u
+    one = orc.pcg_pipelined(A, b, 1e-30, 1)
+    assert one.status == -5 and one.iters == 1
+    assert np.linalg.norm(one.x - x1) <= 1e-13 * np.linalg.norm(x1)
+    for k in (2, 3, 5, 8, 13):
+        pl = orc.pcg_pipelined(A, b, 1e-30, k)
+        hs = orc.pcg(A, b, 1e-30, k)
+        assert pl.iters == hs.iters == k
+        assert np.linalg.norm(pl.x - hs.x) <= 1e-10 * np.linalg.norm(hs.x), k
+
+
+def test_pipelined_cg_modes_statuses(orc):
+    prob, _, b = W.config1()
+    A = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    hs = orc.pcg(A, b, 1e-8)
+    pl = orc.pcg_pipelined(A, b, 1e-8)
+    assert pl.status == 0 and abs(pl.iters - hs.iters) <= 2 and pl.relres <= 1e-8 * 1.001
+    N = 10
+    p = W.q1_poisson(N, 2)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    M = N + 1
+    node = np.arange(p.n)
+    mode = lambda a, c: np.sin(a * math.pi * (node % M) / N) * np.sin(c * math.pi * (node // M) / N)
+    r = orc.pcg_pipelined(A, mode(2, 3), 1e-12, 50)
+    assert r.status == 0 and r.iters == 1
+    r = orc.pcg_pipelined(A, mode(1, 1) + mode(2, 3) + mode(4, 1), 1e-10, 50)
+    assert r.status == 0 and r.iters <= 3 + 1
+    B = orc.assemble(2, np.array([0, 1], np.int32), np.array([0, 1], np.int32), np.array([1.0, -1.0]))
+    assert orc.pcg_pipelined(B, np.array([0.0, 1.0]), 1e-8, 10).status == -6
+    rr = orc.pcg_pipelined(A, np.random.default_rng(0).uniform(-1, 1, p.n), 1e-14, 3)
+    assert rr.status == -5 and rr.iters == 3
+    z = orc.pcg_pipelined(A, np.zeros(p.n), 1e-8)
+    assert z.status == 0 and z.iters == 0 and np.all(z.x == 0)
+    Z = orc.assemble(2, np.array([0, 1, 1], np.int32), np.array([1, 0, 1], np.int32),
+                     np.array([1.0, 1.0, 2.0]))
+    assert orc.pcg_pipelined(Z, np.ones(2), 1e-8, 10).status == -4
+
+
 # ------------------------------------------- BiCG and TFQMR (non-symmetric)
 
 def dense_of(A):
