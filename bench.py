@@ -244,7 +244,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         A = main_matrix()
         b_d = d(b_np)
         forms = {}
-        for name, variant in (("textbook", 0), ("single_reduction", 1)):
+        for name, variant in (("textbook", 0), ("single_reduction", 1), ("pipelined", 2)):
             A.set_option(spx.OPT_CG_VARIANT, variant)
             A.cg_solve(b_d, rtol=1e-10)  # warm
             A.set_option(spx.OPT_PROFILE, 1)
@@ -261,9 +261,12 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         A.set_option(spx.OPT_CG_VARIANT, 0)
         forms["speedup"] = round(forms["textbook"]["ms_per_iter"]
                                  / forms["single_reduction"]["ms_per_iter"], 3)
+        forms["pipelined_speedup"] = round(forms["textbook"]["ms_per_iter"]
+                                           / forms["pipelined"]["ms_per_iter"], 3)
         out["cg_forms"] = forms
         log(f"cg forms: textbook {forms['textbook']['ms_per_iter']} ms/it, single reduction "
-            f"{forms['single_reduction']['ms_per_iter']} ms/it")
+            f"{forms['single_reduction']['ms_per_iter']} ms/it, pipelined "
+            f"{forms['pipelined']['ms_per_iter']} ms/it")
         shared.pop("A").destroy()
 
     # ---- C1 (2-D Q1, 63^2 elements): CG latency per iteration, grid path and one workgroup
@@ -274,7 +277,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         b1d = d(b1)
         c1 = {"n": p1.n, "nnz": A1.nnz}
         for mode, form, tag in ((0, 0, "grid"), (2, 0, "one_workgroup"),
-                                (0, 1, "single_reduction")):
+                                (0, 1, "single_reduction"), (0, 2, "pipelined")):
             A1.set_option(spx.OPT_SMALL_SOLVE, mode)
             A1.set_option(spx.OPT_CG_VARIANT, form)
             A1.cg_solve(b1d, rtol=1e-8)

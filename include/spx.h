@@ -501,6 +501,14 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *       alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}),
  *     two kernels and ONE reduction point per iteration; its iterates equal
  *     those of form 0 in exact arithmetic and differ by rounding.
+ *     2: the pipelined form of Ghysels and Vanroose (preconditioned, M = D):
+ *     the dots of an iteration are reduced by the next update kernel, so
+ *     the product nv = A m in between never waits for a reduction (the
+ *     overlap that hides an all-reduce across GPUs); two kernels per
+ *     iteration, nine work vectors, about 20 vector reads and writes per
+ *     row per iteration against 11 for form 0.  Same iterates in exact
+ *     arithmetic.  Never chosen automatically; spx_cg_solve_noalloc refuses
+ *     it (its scratch holds four vectors).
  *   SPX_OPT_GRAPH: 1 replays each full poll chunk of the textbook CG
  *     (spx_cg_solve, spx_cg_solve_transpose and the fp32 inner solve of
  *     spx_cg_solve_mixed) as one HIP graph, captured once on a private

@@ -217,8 +217,8 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
       h->small_opt = (int)value;
       return SPX_OK;
     case SPX_OPT_CG_VARIANT:
-      if (value < -1 || value > 1)
-        return set_error(SPX_INVALID_ARG, "set_option: CG variant %lld not -1, 0 or 1",
+      if (value < -1 || value > 2)
+        return set_error(SPX_INVALID_ARG, "set_option: CG variant %lld not in -1..2",
                          (long long)value);
       h->cg_variant = (int)value;
       return SPX_OK;

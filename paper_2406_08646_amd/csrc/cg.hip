@@ -408,6 +408,162 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
   if (threadIdx.x == 0) P1[blockIdx.x] = delta;
 }
 
+// ------------------------------------------------ pipelined variant
+// Ghysels-Vanroose pipelined CG with M = D: the dots of iteration i
+// (gamma_i = r.u, delta_i = w.u, ||r_i||) are formed by the update kernel
+// that writes r_i, u_i, w_i, and reduced by the next update kernel, so the
+// product between them (nv = A m) never waits for a reduction.  Per
+// iteration k (1-based, i = k - 1):
+//   KP(k)  nv = A m                                   (m = D^-1 w_i)
+//   KU(k)  add the partials of KU(k-1): gamma_i, delta_i, ||r_i||; stop
+//          when ||r_i|| <= rtol ||b|| (iters = i) or i = maxit; beta_i,
+//          alpha_i; z = nv + beta z, q = m + beta q, s = w + beta s,
+//          p = u + beta p (z = nv, ... at i = 0); x += alpha p,
+//          r -= alpha s, u -= alpha q, w -= alpha z, m = D^-1 w; partials of
+//          the next gamma, delta, ||r||.
+// The partials alternate between two sets (KU(k) reads set (k-1) & 1 and
+// writes set k & 1); gamma_i lives in rho[i & 1], alpha_i in alpha_s[i & 1].
+
+// w = A u, m = D^-1 w; partials of gamma_0 = r.u, delta_0 = w.u, ||r_0||^2
+template <class SH>
+__global__ __launch_bounds__(kBlock) void k_pl_init(int64_t n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ r,
+                                                    const double* __restrict__ u,
+                                                    double* __restrict__ w, double* __restrict__ m,
+                                                    const double* __restrict__ dinv,
+                                                    double* __restrict__ P, int rows, int remap,
+                                                    int64_t tile, WinView win) {
+  extern __shared__ __align__(16) char smem[];
+  double* lds = reduction_lds<SH>(smem);
+  double g = 0.0, dl = 0.0, rr = 0.0;
+  for_rows<SH, double, double, double>(n, rowptr, col, val, u, rows, logical_block(remap), gridDim.x,
+                                       reinterpret_cast<double*>(smem), [&](int64_t row, double wr) {
+                                         const double ur = u[row], rv = r[row];
+                                         w[row] = wr;
+                                         m[row] = dinv[row] * wr;
+                                         g += rv * ur;
+                                         dl += wr * ur;
+                                         rr += rv * rv;
+                                       }, tile, win);
+  __syncthreads();  // the walk's LDS may hold the reduction scratch
+  const int64_t nb = gridDim.x;
+  g = block_sum<kBlock>(g, lds);
+  dl = block_sum<kBlock>(dl, lds);
+  rr = block_sum<kBlock>(rr, lds);
+  if (threadIdx.x == 0) {
+    P[blockIdx.x] = g;
+    P[nb + blockIdx.x] = dl;
+    P[2 * nb + blockIdx.x] = rr;
+  }
+}
+
+// KP(k): nv = A m
+template <class SH>
+__global__ __launch_bounds__(kBlock) void k_pl_spmv(int64_t n, const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ m,
+                                                    double* __restrict__ nv, const CgScalars* st,
+                                                    int rows, int remap, int64_t tile, WinView win) {
+  extern __shared__ __align__(16) char smem[];
+  if (st->done) return;
+  for_rows<SH, double, double, double>(n, rowptr, col, val, m, rows, logical_block(remap), gridDim.x,
+                                       reinterpret_cast<double*>(smem),
+                                       [&](int64_t row, double a) { nv[row] = a; }, tile, win);
+}
+
+// KU(k)
+struct PlVectors {
+  double *x, *r, *u, *w, *m, *nv, *z, *q, *s, *p;
+  const double* dinv;
+};
+
+__global__ __launch_bounds__(kBlock) void k_pl_update(int64_t n, PlVectors v, CgScalars* st,
+                                                      const double* __restrict__ Pin, int64_t Gin,
+                                                      double* __restrict__ Pout, int64_t k) {
+  __shared__ double lds[kLds];
+  if (st->done) return;
+  const int64_t i = k - 1;
+  const double g = reduce_all(Pin, Gin, lds);
+  const double dl = reduce_all(Pin + Gin, Gin, lds);
+  const double rr = reduce_all(Pin + 2 * Gin, Gin, lds);
+  const bool conv = sqrt(rr) <= st->thresh;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (conv || i >= st->maxit) {
+    if (lead) {
+      st->rr = rr;
+      st->iters = (int32_t)i;
+      st->status = conv ? SPX_OK : SPX_NOT_CONVERGED;
+      st->done = 1;
+    }
+    return;
+  }
+  double beta = 0.0, den = dl;
+  if (i > 0) {
+    beta = g / st->rho[(i - 1) & 1];
+    den = dl - beta * g / st->alpha_s[(i - 1) & 1];
+  }
+  if (!(den > 0.0) || !isfinite(den)) {
+    if (lead) {
+      st->rr = rr;
+      st->pq = den;
+      st->iters = (int32_t)i;
+      st->status = SPX_BREAKDOWN;
+      st->done = 1;
+    }
+    return;
+  }
+  const double alpha = g / den;
+  if (lead) {
+    st->rho[i & 1] = g;
+    st->alpha_s[i & 1] = alpha;
+    st->alpha = alpha;
+    st->beta = beta;
+    st->pq = den;
+    st->rr = rr;
+    st->iters = (int32_t)i;
+  }
+  const int64_t nb = gridDim.x;
+  const Range rg = block_range(n, blockIdx.x, nb);
+  double gn = 0.0, dn = 0.0, rn = 0.0;
+  for (int64_t e = rg.lo + threadIdx.x; e < rg.hi; e += kBlock) {
+    const double nve = v.nv[e], me = v.m[e], we = v.w[e], ue = v.u[e];
+    double ze = nve, qe = me, se = we, pe = ue;
+    if (i > 0) {
+      ze = nve + beta * v.z[e];
+      qe = me + beta * v.q[e];
+      se = we + beta * v.s[e];
+      pe = ue + beta * v.p[e];
+    }
+    const double xe = v.x[e] + alpha * pe;
+    const double re = v.r[e] - alpha * se;
+    const double u2 = ue - alpha * qe;
+    const double w2 = we - alpha * ze;
+    v.z[e] = ze;
+    v.q[e] = qe;
+    v.s[e] = se;
+    v.p[e] = pe;
+    v.x[e] = xe;
+    v.r[e] = re;
+    v.u[e] = u2;
+    v.w[e] = w2;
+    v.m[e] = v.dinv[e] * w2;
+    gn += re * u2;
+    dn += w2 * u2;
+    rn += re * re;
+  }
+  gn = block_sum<kBlock>(gn, lds);
+  dn = block_sum<kBlock>(dn, lds);
+  rn = block_sum<kBlock>(rn, lds);
+  if (threadIdx.x == 0) {
+    Pout[blockIdx.x] = gn;
+    Pout[nb + blockIdx.x] = dn;
+    Pout[2 * nb + blockIdx.x] = rn;
+  }
+}
+
 // ------------------------------------------------ one-workgroup solve
 // Small systems: one workgroup of kOne threads runs the whole Jacobi-CG, so
 // no kernel is launched per iteration (the working set stays in L2).  The
@@ -628,12 +784,19 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(int64_t n, double* __restr
 
 // ------------------------------------------------------------ dispatch
 
-int ensure_solver(spx_matrix* h) {
+// Vectors of n in the fp64 workspace: 4 (r, p, q and the single-reduction
+// form's u) or 9 (the pipelined form).
+int ensure_solver(spx_matrix* h, int nvec = 4) {
   const int64_t n = h->n;
-  if (!h->work) {
-    SPX_TRY(dalloc_n(&h->work, (size_t)n * 4));
-    SPX_TRY(dalloc_n(&h->dinv, (size_t)n));
+  const size_t need = (size_t)n * (size_t)nvec;
+  if (h->work_elems < need) {
+    dfree(h->work);
+    h->work = nullptr;
+    h->work_elems = 0;
+    SPX_TRY(dalloc_n(&h->work, need));
+    h->work_elems = need;
   }
+  if (!h->dinv) SPX_TRY(dalloc_n(&h->dinv, (size_t)n));
   if (!h->scal) {
     SPX_TRY(dalloc_n(&h->scal, 2));
     SPX_CHECK_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->scal_host), sizeof(CgScalars) * 4,
@@ -641,7 +804,8 @@ int ensure_solver(spx_matrix* h) {
     SPX_CHECK_HIP(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
     SPX_CHECK_HIP(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
   }
-  const int64_t cap = (int64_t)std::max(fused_blocks(h), vector_blocks(h)) * 4;
+  // two sets of three partials (the pipelined form), four for the others
+  const int64_t cap = (int64_t)std::max(fused_blocks(h), vector_blocks(h)) * 6;
   if (h->partial_cap < cap) {
     dfree(h->partials);
     h->partials = nullptr;
@@ -665,17 +829,17 @@ int ensure_solver32(spx_matrix* h) {
 // chunk while the next one is queued; without, it polls by synchronising
 // the stream.
 struct Work {
-  double* vec = nullptr;       // [4 n]
+  double* vec = nullptr;       // [4 n], [9 n] for the pipelined form
   double* dinv = nullptr;      // [n]
-  double* partials = nullptr;  // [4 max(fused_blocks, vector_blocks)]
+  double* partials = nullptr;  // [6 max(fused_blocks, vector_blocks)]
   CgScalars* scal = nullptr;   // device [2]
   CgScalars* host = nullptr;   // host [4]
   const hipEvent_t* ev = nullptr;  // 2 events or null
 };
 
-// The handle's own workspace, allocated on first use.
-int handle_work(spx_matrix* h, Work* w) {
-  SPX_TRY(ensure_solver(h));
+// The handle's own workspace (nvec vectors of n), allocated on first use.
+int handle_work(spx_matrix* h, Work* w, int nvec = 4) {
+  SPX_TRY(ensure_solver(h, nvec));
   w->vec = h->work;
   w->dinv = h->dinv;
   w->partials = h->partials;
@@ -783,14 +947,16 @@ void accumulate_profile(spx_matrix* h, hipEvent_t* evs, int64_t first, int64_t c
 }
 
 // Runs iterations until the device flag is set, keeping one chunk of
-// `check_every` iterations queued ahead of the one being polled.  enq(first,
+// `check_every` iterations queued ahead of the one being polled.  The
+// launch that records the stop is iteration iters + stop_offset (1 for
+// the pipelined form, whose update kernel tests the previous iterate).  enq(first,
 // count, events) enqueues iterations first .. first+count-1 (K kernels
 // each, bracketed by 2K events when `events` is not null).  Returns the last
 // polled state in *final.
 template <typename Enq>
 int run_until_done(spx_matrix* h, const Work& w, CgScalars* st, int64_t maxit,
                    int32_t check_every, hipStream_t s, int K, const int* kinds, int full_at,
-                   Enq&& enq, CgScalars* final) {
+                   Enq&& enq, CgScalars* final, int stop_offset = 0) {
   int64_t launched = 0;
   CgScalars* host = w.host;
   const bool prof = h->profile != 0 && w.ev;
@@ -842,8 +1008,8 @@ int run_until_done(spx_matrix* h, const Work& w, CgScalars* st, int64_t maxit,
     cur ^= 1;
   }
   SPX_CHECK_HIP(hipStreamSynchronize(s));
-  harvest(0, final->iters);
-  harvest(1, final->iters);
+  harvest(0, final->iters + stop_offset);
+  harvest(1, final->iters + stop_offset);
   return SPX_OK;
 }
 
@@ -948,6 +1114,42 @@ int run_sr(spx_matrix* h, const Work& w, const Op<double>& A, double* x, double*
       final);
 }
 
+// The pipelined iteration (KP, KU), fp64.  KU(k) tests the residual of
+// iteration k - 1, so a solve of at most maxit iterations launches up to
+// maxit + 1 of them.
+int run_pl(spx_matrix* h, const Work& w, const Op<double>& A, const PlVectors& v, CgScalars* st,
+           int64_t maxit, int32_t check_every, hipStream_t s, CgScalars* final) {
+  const unsigned G1 = (unsigned)fused_blocks(h);
+  const unsigned G2 = (unsigned)vector_blocks(h);
+  const int64_t set = 3 * (int64_t)std::max(G1, G2);  // one set of partials
+  const size_t lds = shape_lds<double>(A.sh);
+  const int kinds[2] = {0, 1};  // KP is the SpMV kernel, KU the vector kernel
+  return run_until_done(
+      h, w, st, maxit + 1, check_every, s, 2, kinds, 0,
+      [&](int64_t first, int64_t count, hipEvent_t* evs) {
+        return with_shape<true>(A.sh, [&](auto shc) {
+          using SH = decltype(shc);
+          for (int64_t c = 0; c < count; ++c) {
+            const int64_t k = first + c;
+            hipEvent_t* e = evs ? evs + 4 * c : nullptr;
+            if (e) (void)hipEventRecord(e[0], s);
+            hipLaunchKernelGGL((k_pl_spmv<SH>), dim3(G1), dim3(kBlock), lds, s, A.n, A.rowptr,
+                               A.col, A.val, v.m, v.nv, st, A.sh.rows, remap_for(h, A.sh),
+                               A.sh.tile, A.win);
+            if (e) (void)hipEventRecord(e[1], s);
+            if (e) (void)hipEventRecord(e[2], s);
+            const double* Pin = w.partials + ((k - 1) & 1) * set;
+            double* Pout = w.partials + (k & 1) * set;
+            hipLaunchKernelGGL(k_pl_update, dim3(G2), dim3(kBlock), 0, s, A.n, v, st, Pin,
+                               (int64_t)(k == 1 ? G1 : G2), Pout, k);
+            if (e) (void)hipEventRecord(e[3], s);
+          }
+          return SPX_OK;
+        });
+      },
+      final, 1);
+}
+
 // Launches the fp64 residual-norm kernels for b - A x into st->rr_true.
 int enqueue_resnorm(spx_matrix* h, const Work& w, const Op<double>& A, const double* b,
                     const double* x, CgScalars* st, hipStream_t s) {
@@ -982,7 +1184,7 @@ constexpr int64_t kOneAutoRows = 2048;  // measured crossover with the launch-pe
 constexpr int64_t kSrAutoNnz = 2000000;
 constexpr int64_t kOneLds = 150 * 1024;  // dynamic LDS of the lone workgroup
 bool use_one_workgroup(const spx_matrix* h, const Csr& M) {
-  if (h->small_opt == 0 || h->cg_variant == 1) return false;
+  if (h->small_opt == 0 || h->cg_variant >= 1) return false;
   if ((M.tile_nnz[3] + 8) * (int64_t)sizeof(double) > 64 * 1024) return false;  // 256-row tiles fit
   if (h->small_opt == 2) return true;
   const bool shape_default = h->lanes_opt == 0 && h->variant_opt == 0 && h->rows_opt == 0 &&
@@ -1012,6 +1214,7 @@ int cg_solve_impl(spx_matrix* h, const Work& w, const Csr& M, const double* b, d
   if (maxit > INT32_MAX - 1) maxit = INT32_MAX - 1;
   const int64_t n = M.n;
   const Op<double> A{n, M.rowptr, M.col, M.val, solver_shape(h, M), win_view(M)};
+  const int form = cg_form(h, M);
   double* r = w.vec;
   double* p = w.vec + n;
   double* q = w.vec + 2 * n;
@@ -1021,6 +1224,31 @@ int cg_solve_impl(spx_matrix* h, const Work& w, const Csr& M, const double* b, d
   hipLaunchKernelGGL(k_dinv, dim3(grid1(n)), dim3(256), 0, s, n, M.val, M.dpos, w.dinv,
                      (float*)nullptr, st);
   CgScalars fin;
+  if (form == 2) {
+    // r, u = D^-1 r and the partials of gamma_0, ||r_0||, ||b||; then
+    // w = A u, m = D^-1 w and the first set of KU partials
+    const PlVectors v{x, w.vec, w.vec + n, w.vec + 2 * n, w.vec + 3 * n, w.vec + 4 * n,
+                      w.vec + 5 * n, w.vec + 6 * n, w.vec + 7 * n, w.vec + 8 * n, w.dinv};
+    SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
+      using SH = decltype(shc);
+      hipLaunchKernelGGL((k_cg_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
+                         M.rowptr, M.col, M.val, b, x, v.r, v.u, w.dinv, w.partials, A.sh.rows,
+                         remap_for(h, A.sh), A.sh.tile, A.win);
+      return SPX_OK;
+    }));
+    hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, w.partials,
+                       (int64_t)G, rtol);
+    SPX_TRY(with_shape<true>(A.sh, [&](auto shc) {
+      using SH = decltype(shc);
+      hipLaunchKernelGGL((k_pl_init<SH>), dim3(G), dim3(kBlock), shape_lds<double>(A.sh), s, n,
+                         M.rowptr, M.col, M.val, v.r, v.u, v.w, v.m, w.dinv, w.partials,
+                         A.sh.rows, remap_for(h, A.sh), A.sh.tile, A.win);
+      return SPX_OK;
+    }));
+    SPX_CHECK_HIP(hipGetLastError());
+    SPX_TRY(run_pl(h, w, A, v, st, maxit, check_every, s, &fin));
+    return finish_solve(h, w, A, b, x, st, s, iters_out, relres_out);
+  }
   if (use_one_workgroup(h, M)) {
     // the largest tile whose products fit (4 and 2 tiles of 256 rows bound
     // the entries of 1024 and 512 consecutive rows)
@@ -1060,7 +1288,7 @@ int cg_solve_impl(spx_matrix* h, const Work& w, const Csr& M, const double* b, d
   hipLaunchKernelGGL(k_cg_init_finish, dim3(1), dim3(kBlock), 0, s, st, w.partials, (int64_t)G,
                      rtol);
   SPX_CHECK_HIP(hipGetLastError());
-  if (cg_form(h, M) == 1) {
+  if (form == 1) {
     // k_cg_init left u = D^-1 r in p; move it to its own vector and start
     // w = A u, p = u, s = w, delta_0
     double* u = w.vec + 3 * n;
@@ -1152,7 +1380,7 @@ extern "C" int spx_cg_solve(spx_handle h, const double* b, double* x, double rto
   clear_error();
   if (!h) return set_error(SPX_INVALID_ARG, "cg_solve: NULL handle");
   Work w;
-  SPX_TRY(handle_work(h, &w));
+  SPX_TRY(handle_work(h, &w, cg_form(h, h->A) == 2 ? 9 : 4));
   return cg_solve_impl(h, w, h->A, b, x, rtol, maxit, check_every,
                        static_cast<hipStream_t>(stream), iters_out, relres_out);
 }
@@ -1165,7 +1393,7 @@ extern "C" int spx_cg_solve_transpose(spx_handle h, const double* b, double* x, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   SPX_TRY(ensure_transpose(h, s));
   Work w;
-  SPX_TRY(handle_work(h, &w));
+  SPX_TRY(handle_work(h, &w, cg_form(h, h->At) == 2 ? 9 : 4));
   return cg_solve_impl(h, w, h->At, b, x, rtol, maxit, check_every, s, iters_out, relres_out);
 }
 
@@ -1321,6 +1549,9 @@ extern "C" int spx_cg_solve_noalloc(spx_handle h, const double* b, double* x, do
     return set_error(SPX_INVALID_ARG,
                      "cg_solve_noalloc: %lld workgroups per solver kernel exceed the limit of %lld",
                      (long long)G, (long long)kNoallocMaxBlocks);
+  if (cg_form(h, h->A) == 2)
+    return set_error(SPX_INVALID_ARG,
+                     "cg_solve_noalloc: the pipelined form needs nine vectors, the scratch holds four");
   int dev = -1;
   SPX_CHECK_HIP(hipGetDevice(&dev));
   if (dev != h->device)

@@ -118,7 +118,7 @@ def test_single_reduction_status_codes():
     r = C.cg_solve(dev(b), x=dev(x0), rtol=1e-10)
     assert r.status == 0 and r.relres <= 1e-10 * 1.001
     with pytest.raises(spx.SpxError):
-        C.set_option(spx.OPT_CG_VARIANT, 2)
+        C.set_option(spx.OPT_CG_VARIANT, 3)
 
 
 def test_single_reduction_transpose_of_symmetric_is_identical():
