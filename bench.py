@@ -498,7 +498,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
             f_ms = statistics.median(a.elapsed_time(b) for a, b in fevs)
             be = 8 * n_l * (2 * m_l + 2) / (t_ms * 1e-3) / 1e9
             be_f = 8 * n_l * (2 * m_l + 2) / (f_ms * 1e-3) / 1e9
-            y_passes = 2 if m_l <= 16 else 3  # update, a (with Y^T a up to 16 pairs), Y^T a
+            y_passes = 1  # a with Y^T a (the update reads S only)
             col_bytes = 8 * n_l * m_l
             lb.append({"n": n_l, "m": m_l, "update_ms": round(upd, 4), "apply_ms": round(app, 4),
                        "total_ms": round(t_ms, 4), "effective_gbs": round(be, 1),
@@ -515,8 +515,8 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
                         "effective_bandwidth": "8 n (2m + 2) bytes / (T_update + T_apply): "
                                                "S and Y read once, g read, p written",
                         "hbm_bytes": "bytes this design moves: S read 3 times (update, S^T g, p), Y "
-                                     "twice up to 16 pairs (update; a with Y^T a) and 3 times above, "
-                                     "plus 8 vector passes; the fused step reads S twice",
+                                     "once (a with Y^T a), plus 8 vector passes; the fused step reads "
+                                     "S twice",
                         "fused": "spx_lbfgs_update_apply: the same step with S^T g taken in the "
                                  "update's pass over S (bitwise the two calls)"}
 

@@ -10,9 +10,12 @@
 // column-major (slot j's pair contiguous at j*n), so every pass walks rows
 // with coalesced loads of each column and a new pair overwrites one column
 // with contiguous stores.  The m x m matrix of pair products s_a.y_b is kept
-// by slot and grows by one row and one column per update.  One apply is
-// three passes over the rows (S^T g; then a and Y^T a in one pass over Y;
-// then p from S), separated by the two reductions the formula needs; each
+// by slot; R = triu(S^T Y) in time order only ever reads s_a.y_b with pair a
+// no newer than pair b, so an update fills the new slot's column
+// (s_b.y_new for every held b, the diagonal included) from one pass over S
+// and never reads Y.  One apply is three passes over the rows (S^T g; then
+// a and Y^T a in one pass over Y, long histories staging row blocks of Y
+// in LDS; then p from S), separated by the two reductions the formula needs; each
 // pass kernel re-adds the per-workgroup partials of the previous one, so
 // no workgroup waits for another and no fence is needed.  The two m x m
 // triangular solves are done by every workgroup of the pass that needs
@@ -32,6 +35,7 @@ struct spx_lbfgs {
   int count = 0;  // pairs held
   int start = 0;  // slot of the oldest pair
   int G = 0;      // workgroups of the pass kernels
+  int Gy = 0;     // workgroups of the staged a / Y^T a pass (long histories)
   double* S = nullptr;
   double* Y = nullptr;
   double* SY = nullptr;  // SY[a*m + b] = s_a . y_b, by slot
@@ -268,9 +272,8 @@ __global__ void k_lb_put(int64_t n, const double* __restrict__ s, const double* 
   }
 }
 
-// Partials of u_b = s_new . y_b (rows 0..cnt) and v_b = s_b . y_new (rows
-// kMaxHistory + b); the new pair is already in its slot (logical cnt - 1),
-// which is where it is read from.
+// Partials of v_b = s_b . y_new (rows kMaxHistory + b) for every held pair,
+// the new one (already in its slot, logical cnt - 1) included.
 template <int V>
 __global__ __launch_bounds__(kLB, kGemvtWaves) void k_lb_update(int64_t n, const double* __restrict__ S,
                                                    const double* __restrict__ Y, Ring R,
@@ -278,7 +281,6 @@ __global__ __launch_bounds__(kLB, kGemvtWaves) void k_lb_update(int64_t n, const
   __shared__ double lds[(kLB / 64) * kJT];
   __shared__ double tot[kJT];
   const int64_t cur = R.slot(R.cnt - 1) * n;
-  gemvt_partials<V>(n, Y, R, S + cur, P, 0, lds, tot);
   gemvt_partials<V>(n, S, R, Y + cur, P, kMaxHistory, lds, tot);
 }
 
@@ -292,25 +294,17 @@ __global__ __launch_bounds__(kLB, kGemvtWaves) void k_lb_update_g(int64_t n, con
   __shared__ double lds[(kLB / 64) * kJT];
   __shared__ double tot[kJT];
   const int64_t cur = R.slot(R.cnt - 1) * n;
-  gemvt_partials<V>(n, Y, R, S + cur, P, 0, lds, tot);
   gemvt2_partials<V>(n, S, R, Y + cur, g, P, kMaxHistory, 2 * kMaxHistory, lds, tot);
 }
 
-// one workgroup per (kind, logical index): SY row and column of the new slot
+// one workgroup per logical index b: SY column of the new slot, s_b . y_new
 __global__ __launch_bounds__(kLB) void k_lb_update_finish(const double* __restrict__ P, int G,
                                                           Ring R, int slot,
                                                           double* __restrict__ SY) {
   __shared__ double lds[kLds];
-  const int kind = blockIdx.x >= R.cnt ? 1 : 0;
-  const int b = blockIdx.x - kind * R.cnt;
-  const double t = reduce_all(P + (int64_t)(kind * kMaxHistory + b) * G, G, lds);
-  if (threadIdx.x == 0) {
-    const int64_t sb = R.slot(b);
-    if (kind == 0)
-      SY[slot * R.m + sb] = t;  // s_new . y_b
-    else
-      SY[sb * R.m + slot] = t;  // s_b . y_new
-  }
+  const int b = blockIdx.x;
+  const double t = reduce_all(P + (int64_t)(kMaxHistory + b) * G, G, lds);
+  if (threadIdx.x == 0) SY[R.slot(b) * R.m + slot] = t;
 }
 
 // ----------------------------------------------------------------- apply
@@ -337,10 +331,11 @@ __device__ __forceinline__ double rmat(const double* SY, const Ring& R, int a, i
   return SY[R.slot(a) * R.m + R.slot(b)];
 }
 
-// pass 2: c = -R^-1 q (every workgroup; workgroup 0 stores it);
-// a = h0 (g + Y c); with FUSED, also the partials of f_b = y_b . a
-template <bool FUSED, int V>
-__global__ __launch_bounds__(kLB, FUSED ? 1 : kGemvtWaves) void k_lb_ya(int64_t n, const double* __restrict__ Y, Ring R,
+// pass 2 for histories of at most kFused pairs: c = -R^-1 q (every
+// workgroup; workgroup 0 stores it); a = h0 (g + Y c) and the partials of
+// f_b = y_b . a, each row's history values held in registers
+template <int V>
+__global__ __launch_bounds__(kLB, 1) void k_lb_ya(int64_t n, const double* __restrict__ Y, Ring R,
                                                const double* __restrict__ g,
                                                const double* __restrict__ h0,
                                                const double* __restrict__ SY,
@@ -365,7 +360,7 @@ __global__ __launch_bounds__(kLB, FUSED ? 1 : kGemvtWaves) void k_lb_ya(int64_t 
   __syncthreads();
   int64_t lo, hi;
   rows_of<V>(n, blockIdx.x, gridDim.x, &lo, &hi);
-  if constexpr (FUSED) {
+  {
     const double* cp[kFused];
     double c[kFused], f[kFused];
 #pragma unroll
@@ -394,25 +389,99 @@ __global__ __launch_bounds__(kLB, FUSED ? 1 : kGemvtWaves) void k_lb_ya(int64_t 
     }
     block_sums<kFused>(f, cnt, lds, tot);
     if (threadIdx.x < cnt) P[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = tot[threadIdx.x];
-  } else {
-    (void)lo;
-    (void)hi;
-    row_blocks<V, false>(
-        n, Y, R, cs, [&](int64_t i) { return ldv<V>(g + i); },
-        [&](int64_t i, const VD& t) {
-          *reinterpret_cast<VD*>(a_out + i) = h0 ? ldv<V>(h0 + i) * t : t;
-        });
   }
 }
 
-// pass 2b (histories longer than kFused): partials of f_b = y_b . a
-template <int V>
-__global__ __launch_bounds__(kLB, kGemvtWaves) void k_lb_ya_t(int64_t n, const double* __restrict__ Y, Ring R,
-                                                 const double* __restrict__ a,
-                                                 double* __restrict__ P) {
-  __shared__ double lds[(kLB / 64) * kJT];
-  __shared__ double tot[kJT];
-  gemvt_partials<V>(n, Y, R, a, P, 0, lds, tot);
+// pass 2 for histories longer than kFused: c as in k_lb_ya, then a and the
+// partials of f_b = y_b . a from ONE pass over Y.  Each block of kYRows rows
+// is staged in LDS (kYRows x cnt, column stride kYRows + 1 so that the
+// column-wise reads below hit distinct banks): thread r < kYRows forms
+// a_r = h0_r (g_r + sum_b y_b[r] c_b) with the columns in order; then
+// thread t adds y_b[r] a_r for column b = t % 64 over its quarter of the
+// block's rows.  Every element of Y is read from memory once; the next
+// block's elements are loaded into registers (kYPer per thread, all issued
+// together) while the current block is used.  (Measured at n = 10^7,
+// m = 50: one block ahead 2.9 ms for the fused step; two blocks ahead, in
+// 64- or 32-row blocks, 3.3-3.5 ms.)
+constexpr int kYRows = 64;
+constexpr int kYStride = kYRows + 1;
+constexpr int kYPer = kMaxHistory * kYRows / kLB;
+__global__ __launch_bounds__(kLB) void k_lb_ya_staged(int64_t n, const double* __restrict__ Y,
+                                                      Ring R, const double* __restrict__ g,
+                                                      const double* __restrict__ h0,
+                                                      const double* __restrict__ SY,
+                                                      double* __restrict__ red,
+                                                      double* __restrict__ a_out,
+                                                      double* __restrict__ P) {
+  __shared__ double tile[kMaxHistory * kYStride];
+  __shared__ double as[kYRows];
+  __shared__ double cs[kMaxHistory];
+  __shared__ int64_t cols[kMaxHistory];
+  const int cnt = R.cnt;
+  if (threadIdx.x == 0) {
+    const double* q = red;
+    for (int x = cnt - 1; x >= 0; --x) {
+      double t = -q[x];
+      for (int y = x + 1; y < cnt; ++y) t -= rmat(SY, R, x, y) * cs[y];
+      cs[x] = t / rmat(SY, R, x, x);
+    }
+    if (blockIdx.x == 0)
+      for (int x = 0; x < cnt; ++x) red[kMaxHistory + x] = cs[x];
+  }
+  if (threadIdx.x < cnt) cols[threadIdx.x] = R.slot(threadIdx.x) * n;
+  __syncthreads();
+  int64_t lo, hi;
+  rows_of<1>(n, blockIdx.x, gridDim.x, &lo, &hi);
+  // element k of this thread in a block: column eb + k kBStep, row er
+  const int er = threadIdx.x % kYRows, eb = threadIdx.x / kYRows;
+  constexpr int kBStep = kLB / kYRows;
+  double v[kYPer];
+  auto load = [&](int64_t r0) {
+    const bool in = r0 + er < hi;
+#pragma unroll
+    for (int k = 0; k < kYPer; ++k) {
+      const int b = eb + k * kBStep;
+      if (in && b < cnt) v[k] = Y[cols[b] + r0 + er];
+    }
+  };
+  const int fb = threadIdx.x & 63;  // column of this thread's f accumulator
+  const int fq = threadIdx.x >> 6;  // its quarter of each block's rows
+  constexpr int kQ = kYRows / (kLB / 64);
+  double f = 0.0;
+  if (lo < hi) load(lo);
+  for (int64_t r0 = lo; r0 < hi; r0 += kYRows) {
+    const int nr = hi - r0 < kYRows ? (int)(hi - r0) : kYRows;
+#pragma unroll
+    for (int k = 0; k < kYPer; ++k) {
+      const int b = eb + k * kBStep;
+      if (er < nr && b < cnt) tile[b * kYStride + er] = v[k];
+    }
+    __syncthreads();
+    if (r0 + kYRows < hi) load(r0 + kYRows);
+    if (threadIdx.x < nr) {
+      const int r = threadIdx.x;
+      double t = g[r0 + r];
+      for (int b = 0; b < cnt; ++b) t += tile[b * kYStride + r] * cs[b];
+      const double ar = h0 ? h0[r0 + r] * t : t;
+      a_out[r0 + r] = ar;
+      as[r] = ar;
+    }
+    __syncthreads();
+    if (fb < cnt) {
+      const int rl = fq * kQ, rh = rl + kQ < nr ? rl + kQ : nr;
+      for (int r = rl; r < rh; ++r) f += tile[fb * kYStride + r] * as[r];
+    }
+    __syncthreads();
+  }
+  // the workgroup's f: the four quarters of each column, added in order
+  double* fs = tile;
+  fs[threadIdx.x] = f;
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    double t = 0.0;
+    for (int q = 0; q < kLB / 64; ++q) t += fs[q * 64 + threadIdx.x];
+    P[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
 }
 
 // pass 3: e = R^-T (f + D c) (every workgroup); p = a - S e
@@ -471,15 +540,16 @@ int apply_passes(spx_lbfgs* h, const double* g, const double* h0, double* p, hip
     hipLaunchKernelGGL(k_lb_sg<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, g, h->P);
     hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
   }
+  int Gf = G;  // workgroups whose partials of f the reduction adds
   if (cnt <= kFused) {
-    hipLaunchKernelGGL((k_lb_ya<true, V>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
+    hipLaunchKernelGGL(k_lb_ya<V>, dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
                        h->red, h->a, h->P);
   } else {
-    hipLaunchKernelGGL((k_lb_ya<false, V>), dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
+    Gf = h->Gy;
+    hipLaunchKernelGGL(k_lb_ya_staged, dim3(Gf), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
                        h->red, h->a, h->P);
-    hipLaunchKernelGGL(k_lb_ya_t<V>, dim3(G), dim3(kLB), 0, st, n, h->Y, R, h->a, h->P);
   }
-  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red + 2 * kMaxHistory);
+  hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, Gf, h->red + 2 * kMaxHistory);
   hipLaunchKernelGGL(k_lb_p<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, h->a, h->SY, h->red, p);
   return SPX_OK;
 }
@@ -498,12 +568,21 @@ extern "C" int spx_lbfgs_create(int64_t n, int32_t m, void* stream, spx_lbfgs_ha
   h->n = n;
   h->m = m;
   const int64_t rows_per_wg = 4 * kLB;
-  // histories longer than kFused take the transposed products at 8 waves per
-  // SIMD and fill them with 8 workgroups per CU; shorter ones run the fused
-  // a / Y^T a pass (184 VGPRs), which keeps 4 (measured: 0.58 vs 0.57 ms at
-  // m = 5, 4.28 vs 4.44 ms at m = 50, n = 10^7)
+  // histories longer than kFused run the passes over S (the update's and
+  // p's) at 8 waves per SIMD with 8 workgroups per CU; shorter ones run the
+  // register-held a / Y^T a pass (184 VGPRs), which keeps 4 (measured: 0.58
+  // vs 0.57 ms at m = 5, 4.28 vs 4.44 ms at m = 50, n = 10^7)
   const int per_cu = m > kFused ? 8 : 4;
   h->G = (int)std::max<int64_t>(1, std::min<int64_t>(cu_count() * per_cu, ceil_div(n, rows_per_wg)));
+  // the staged pass runs as many workgroups as are resident at once (its
+  // LDS allows four per CU)
+  int fit = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, reinterpret_cast<const void*>(&k_lb_ya_staged),
+                                                   kLB, 0) != hipSuccess || fit <= 0)
+    fit = 4;
+  (void)hipGetLastError();
+  h->Gy = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cu_count() * fit,
+                                                      ceil_div(n, rows_per_wg)));
   int st = SPX_OK;
   do {
     if ((st = dalloc_n(&h->S, (size_t)n * m)) != SPX_OK) break;
@@ -581,7 +660,7 @@ int update_impl(spx_lbfgs* h, const double* s, const double* y, const double* g,
   } else {
     hipLaunchKernelGGL(k_lb_update<1>, dim3(G), dim3(kLB), 0, st, h->n, h->S, h->Y, R, h->P);
   }
-  hipLaunchKernelGGL(k_lb_update_finish, dim3(2 * cnt), dim3(kLB), 0, st, h->P, G, R, slot, h->SY);
+  hipLaunchKernelGGL(k_lb_update_finish, dim3(cnt), dim3(kLB), 0, st, h->P, G, R, slot, h->SY);
   SPX_CHECK_HIP(hipGetLastError());
   h->start = start;
   h->count = cnt;
