@@ -711,6 +711,9 @@ def main() -> int:
         return 2
     spx.load_library()
     torch.cuda.set_device(0)
+    # the library's device memory comes from PyTorch's caching allocator, so
+    # the symbolic stage's large temporaries are reused from step to step
+    spx.use_torch_allocator(True)
     dev = torch.device("cuda", 0)
     N = args.grid
 

@@ -164,3 +164,48 @@ def test_vec_coo_bitwise(orc, n, ncoo, seed):
     with pytest.raises(spx.SpxError) as e:
         spx.vec_coo_preallocate(n, dev(np.array([0, n], np.int32)))
     assert e.value.code == spx.INDEX_OUT_OF_RANGE
+
+
+def rows_of_lengths(rng, n, lengths, ncols_pool=None):
+    """A COO stream whose row r holds lengths[r] triplets (rows in a random
+    order, triplets of one row scattered through the stream), columns drawn
+    with duplicates."""
+    rows = np.repeat(np.arange(len(lengths)), lengths)
+    perm = rng.permutation(rows.size)
+    i = rows[perm].astype(np.int32)
+    pool = ncols_pool or n
+    j = rng.integers(0, pool, rows.size).astype(np.int32)
+    v = rng.uniform(-1, 1, rows.size)
+    return W.CooProblem(n=n, i=i, j=j, v=v)
+
+
+@pytest.mark.parametrize("case", ["ragged", "tile_edges", "one_long_row", "many_long_rows"])
+def test_two_stage_order_bitwise(orc, case):
+    """Patterns of more than 65536 rows sort by row, then re-sort each tile's
+    whole rows by column in LDS (a tile takes the rows that start in its
+    512 items and may hold up to 1024); rows that do not fit send the whole
+    pattern to the full-key sort.  Both paths must give the oracle's pattern,
+    values and maps bit for bit."""
+    spx = require_gpu()
+    rng = np.random.default_rng({"ragged": 1, "tile_edges": 2, "one_long_row": 3,
+                                 "many_long_rows": 4}[case])
+    n = 70001
+    if case == "ragged":  # rows of 0 to 300 triplets
+        lengths = rng.integers(0, 300, 3000)
+    elif case == "tile_edges":  # rows of 255 to 513 triplets straddle the tile edges
+        lengths = rng.integers(255, 514, 600)
+    elif case == "one_long_row":  # one row longer than a tile holds: the full-key sort
+        lengths = np.full(2000, 7)
+        lengths[1234] = 5000
+    else:  # a tile's rows at exactly the limit and just over it
+        lengths = np.array([511, 513, 3, 1, 1020, 1024, 2, 1025, 1], np.int64)
+    prob = rows_of_lengths(rng, n, lengths, ncols_pool=4000)
+    print(f"two-stage order {case}: n={n} ncoo={prob.ncoo} longest row {lengths.max()}", flush=True)
+    check_full(orc, spx, prob)
+
+
+def test_two_stage_order_q1(orc):
+    spx = require_gpu()
+    N = 45  # 97,336 rows: the two-stage order
+    prob = W.q1_poisson(N, 3, kappa=np.exp(np.random.default_rng(3).standard_normal(N**3)))
+    check_full(orc, spx, prob)
