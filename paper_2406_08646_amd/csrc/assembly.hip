@@ -555,12 +555,6 @@ int symbolic(spx_matrix* h, const int32_t* i, const int32_t* j, hipStream_t s) {
     // alternate buffer live in the first half of `keys`; the full keys come
     // out in the second half.
     bool two_stage = sizeof(K) == 8 && cb <= kRowColBits;
-    if (two_stage)
-      hipLaunchKernelGGL((k_coo_compact<uint32_t, true>), dim3((unsigned)ntiles), dim3(kBlock), 0,
-                         s, i, j, ncoo, n, cb, tilecnt, reinterpret_cast<uint32_t*>(keys), vals);
-    else
-      hipLaunchKernelGGL(k_coo_compact<K>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, i, j, ncoo,
-                         n, cb, tilecnt, keys, vals);
     if (hipMemcpyAsync(host_misc, misc, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       st = set_error(SPX_HIP_ERROR, "coo_preallocate: %s", hipGetErrorString(hipGetLastError()));
@@ -572,11 +566,21 @@ int symbolic(spx_matrix* h, const int32_t* i, const int32_t* j, hipStream_t s) {
       break;
     }
     nvalid = host_misc[1];
+    // With every triplet kept the row sort reads the caller's rows and takes
+    // the triplet numbers as its values: no compaction.
+    const bool all_kept = nvalid == ncoo;
+    if (two_stage && !all_kept)
+      hipLaunchKernelGGL((k_coo_compact<uint32_t, true>), dim3((unsigned)ntiles), dim3(kBlock), 0,
+                         s, i, j, ncoo, n, cb, tilecnt, reinterpret_cast<uint32_t*>(keys), vals);
+    else if (!two_stage)
+      hipLaunchKernelGGL(k_coo_compact<K>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, i, j, ncoo,
+                         n, cb, tilecnt, keys, vals);
     if (two_stage) {
       uint32_t* rk = reinterpret_cast<uint32_t*>(keys);
       uint32_t *rk_out = nullptr, *rv_out = nullptr;
-      if ((st = radix_sort_pairs_u32(rk, rk + cap, vals, vals_alt, nvalid, cb, s, &rk_out,
-                                     &rv_out)) != SPX_OK)
+      if ((st = radix_sort_pairs_u32(rk, rk + cap, vals, vals_alt, nvalid, cb, s, &rk_out, &rv_out,
+                                     all_kept ? reinterpret_cast<const uint32_t*>(i) : nullptr,
+                                     all_kept)) != SPX_OK)
         break;
       K* ok = keys + cap;
       uint32_t* ov = rv_out == vals ? vals_alt : vals;

@@ -58,9 +58,12 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 int radix_sort_pairs_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
                          int64_t count, int bits, hipStream_t s, uint64_t** keys_out,
                          uint32_t** vals_out);
+// first_keys (optional): the first pass reads its keys there (keys is still
+// overwritten); iota_vals: the values are the item indices 0 .. count-1.
 int radix_sort_pairs_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
                          int64_t count, int bits, hipStream_t s, uint32_t** keys_out,
-                         uint32_t** vals_out);
+                         uint32_t** vals_out, const uint32_t* first_keys = nullptr,
+                         bool iota_vals = false);
 
 // Exclusive scan of uint32 counts; out may alias in.  If total != nullptr
 // the sum is written there (device).  scratch: scan_scratch_elems(count).

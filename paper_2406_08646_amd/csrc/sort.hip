@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const int local = w * (kSortSteps * 64) + s * 64 + lane;
     if (local < tile_n) {
       k[s] = keys[base + local];
-      v[s] = vals[base + local];
+      v[s] = vals ? vals[base + local] : (uint32_t)(base + local);
     } else {
       k[s] = K(0);
       v[s] = 0;
@@ -232,12 +232,25 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
   }
 }
 
+// first_keys (optional): the first pass reads its keys there instead of in
+// keys, and with iota_vals its values are the item indices (vals is then
+// only written); keys and vals are overwritten either way.
 template <typename K>
 int radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t* vals_alt, int64_t count,
-                    int bits, hipStream_t s, K** keys_out, uint32_t** vals_out) {
+                    int bits, hipStream_t s, K** keys_out, uint32_t** vals_out,
+                    const K* first_keys = nullptr, bool iota_vals = false) {
   *keys_out = keys;
   *vals_out = vals;
-  if (count <= 1 || bits <= 0) return SPX_OK;
+  if (count <= 1 || bits <= 0) {
+    if (first_keys || iota_vals) {
+      // nothing to order: the output is the input
+      if (count == 1 && first_keys)
+        SPX_CHECK_HIP(hipMemcpyAsync(keys, first_keys, sizeof(K), hipMemcpyDeviceToDevice, s));
+      if (count == 1 && iota_vals)
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, vals, (int64_t)1, 0u);
+    }
+    return SPX_OK;
+  }
   if (bits > (int)(8 * sizeof(K)))
     return set_error(SPX_INVALID_ARG, "radix sort: %d bits exceed the key width", bits);
   const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
@@ -252,10 +265,15 @@ int radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t* vals_alt, in
   const int64_t scratch_n = scan_scratch_elems(hist_n);
   SPX_TRY(dalloc_n(&hist, (size_t)(hist_n + scratch_n)));
   uint32_t* scratch = hist + hist_n;
-  K* ck = keys;
+  // pass p reads (ck, cv) and writes (ak, av); with first_keys the first
+  // pass reads the caller's keys and writes keys_alt, so the passes after
+  // it alternate between keys_alt and keys
+  const K* ck = first_keys ? first_keys : keys;
   K* ak = keys_alt;
-  uint32_t* cv = vals;
+  const uint32_t* cv = iota_vals ? nullptr : vals;
   uint32_t* av = vals_alt;
+  K* next_k = keys;
+  uint32_t* next_v = vals;
   int st = SPX_OK;
   for (int p = 0; p < passes && st == SPX_OK; ++p) {
     const int shift = p * dbits;
@@ -265,8 +283,16 @@ int radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t* vals_alt, in
     if (st != SPX_OK) break;
     hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)ntiles), dim3(kSortBlock), 0, s, ck,
                        cv, ak, av, count, shift, dbits, hist, ntiles);
-    std::swap(ck, ak);
-    std::swap(cv, av);
+    // the buffer just written is the next input; the other one takes the
+    // next output
+    K* wk = ak;
+    uint32_t* wv = av;
+    ak = next_k;
+    av = next_v;
+    next_k = wk;
+    next_v = wv;
+    ck = wk;
+    cv = wv;
   }
   hipError_t e = hipGetLastError();
   // The free below waits for the passes; preallocation is synchronous.
@@ -276,8 +302,8 @@ int radix_sort_impl(K* keys, K* keys_alt, uint32_t* vals, uint32_t* vals_alt, in
   if (e != hipSuccess) return set_error(SPX_HIP_ERROR, "radix sort launch: %s", hipGetErrorString(e));
   if (e2 != hipSuccess)
     return set_error(SPX_HIP_ERROR, "radix sort: %s", hipGetErrorString(e2));
-  *keys_out = ck;
-  *vals_out = cv;
+  *keys_out = const_cast<K*>(ck);
+  *vals_out = const_cast<uint32_t*>(cv);
   return SPX_OK;
 }
 
@@ -323,9 +349,9 @@ int radix_sort_pairs_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uin
 
 int radix_sort_pairs_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
                          int64_t count, int bits, hipStream_t s, uint32_t** keys_out,
-                         uint32_t** vals_out) {
+                         uint32_t** vals_out, const uint32_t* first_keys, bool iota_vals) {
   return radix_sort_impl<uint32_t>(keys, keys_alt, vals, vals_alt, count, bits, s, keys_out,
-                                   vals_out);
+                                   vals_out, first_keys, iota_vals);
 }
 
 }  // namespace spx
