@@ -60,6 +60,27 @@ def set_values_bytes(ncoo: int, nvalid: int, nnz: int) -> int:
     return ncoo * 8 + nvalid * 4 + (nnz + 1) * 4 + nnz * 8
 
 
+def preallocate_bytes(n: int, ncoo: int, nvalid: int, nnz: int) -> int:
+    """Algorithmic bytes of the symbolic stage: i and j read once; perm,
+    jmap, col and rowptr written once."""
+    return 8 * ncoo + 4 * nvalid + 4 * (nnz + 1) + 4 * nnz + 4 * (n + 1)
+
+
+def preallocate_design_bytes(n: int, ncoo: int, nnz: int) -> int:
+    """Bytes the two-stage order moves when every triplet is kept: the count
+    pass reads i and j; three row passes each read their keys for the
+    histogram, then keys and values and write both (the first reads i and
+    writes values it does not read); the row-tile pass reads keys and
+    values, gathers j and writes 64-bit keys and values; the heads passes
+    read the keys (twice) and write jmap, col, rowptr, the diagonal
+    positions."""
+    count = 8 * ncoo
+    passes = 3 * (4 * ncoo + 16 * ncoo) - 4 * ncoo
+    tiles = (4 + 4 + 4 + 8 + 4) * ncoo
+    heads = 2 * 8 * ncoo + 8 * nnz + 8 * (n + 1)
+    return count + passes + tiles + heads
+
+
 def cg_iteration_bytes(n: int, nnz: int) -> int:
     """SpMV + update (reads x p r q dinv, writes x r) + p update (reads r
     dinv p, writes p), FP64."""
@@ -890,6 +911,12 @@ def main() -> int:
         },
         "assembly": {
             "preallocate_ms": round(med("preallocate_ms"), 3),
+            "preallocate_bytes": preallocate_bytes(n, ncoo, ncoo, nnz),
+            "preallocate_gbs": round(preallocate_bytes(n, ncoo, ncoo, nnz)
+                                     / (med("preallocate_ms") * 1e-3) / 1e9, 1),
+            "preallocate_frac": round(preallocate_bytes(n, ncoo, ncoo, nnz)
+                                      / (med("preallocate_ms") * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "preallocate_design_bytes": preallocate_design_bytes(n, ncoo, nnz),
             "set_values_ms": round(med("set_values_ms"), 4),
             "set_values_gbs": round(set_values_bytes(ncoo, ncoo, nnz)
                                     / (med("set_values_ms") * 1e-3) / 1e9, 1),
