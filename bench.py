@@ -224,8 +224,15 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
             e_.record()
         torch.cuda.synchronize()
         mv_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
+        # what the staged kernel reads: values and 2-byte list positions per
+        # entry, row bounds, one 320-int list per 32-row tile, X and Y
+        spmm_format_bytes = (nnz * 10 + (prob.n + 1) * 4 + (prob.n + 31) // 32 * 1280
+                             + 2 * 16 * 8 * prob.n)
         out["spmm16"] = {"ms": round(spmm_ms, 4), "bytes": spmm_bytes,
                          "gbs": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
+                         "format_bytes": spmm_format_bytes,
+                         "format_gbs": round(spmm_format_bytes / (spmm_ms * 1e-3) / 1e9, 1),
+                         "kernel": "k_spmm_rowset",
                          "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
         log(f"spmm16: {spmm_ms:.3f} ms")
         del X, Y

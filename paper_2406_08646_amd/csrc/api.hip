@@ -109,6 +109,8 @@ static void free_csr(Csr& M) {
   dfree(M.win.lcol);
   dfree(M.win.ptr);
   dfree(M.win.blk);
+  dfree(M.rs.col);
+  dfree(M.rs.lidx);
   M = Csr();
 }
 

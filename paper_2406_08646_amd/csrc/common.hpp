@@ -101,6 +101,22 @@ struct Window {
   int64_t gather_entries = 0;  // entries of tiles without a window
 };
 
+// Rows of X a tile of kRsRows consecutive rows of the matrix touches, for
+// the 16-column product (spmm.hip): tile b's list at col + b * kRsStride
+// holds its number of distinct columns, then those columns ascending, and
+// lidx holds each entry's position in its tile's list.  A tile with more
+// than kRsCap entries or kRsMax distinct columns has the count -1 and is
+// gathered directly.  kRsMax rows of X and one row of zeros fill 40 KB.
+constexpr int kRsRows = 32;
+constexpr int kRsCap = 1024;
+constexpr int kRsMax = 319;
+constexpr int kRsStride = kRsMax + 1;
+struct RowSet {
+  int32_t* col = nullptr;    // [tiles * kRsStride] count, then the columns
+  uint16_t* lidx = nullptr;  // [nnz] entry t's position in its tile's list
+  bool built = false;
+};
+
 // What the kernels of the window walk receive.
 struct WinView {
   const uint16_t* lcol;
@@ -119,6 +135,7 @@ struct Csr {
   // largest number of entries in a block of 32/64/128/256 consecutive rows
   int64_t tile_nnz[4] = {0, 0, 0, 0};
   Window win;  // empty (lcol == nullptr) when the pattern does not profit from one
+  RowSet rs;   // built on the first 16-column product
 };
 
 inline WinView win_view(const Csr& A) { return WinView{A.win.lcol, A.win.ptr, A.win.blk}; }
@@ -245,6 +262,10 @@ int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, i
                 hipStream_t s);
 int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double* Y, int64_t ldy,
                 hipStream_t s);
+// spmm.hip: the row-set index of A (once) and the 16-column product that
+// stages each tile's rows of X in LDS (X and Y contiguous, 16-byte aligned)
+int build_rowset(Csr& A, hipStream_t s);
+int launch_spmm_rowset(const Csr& A, const double* X, double* Y, hipStream_t s);
 // cg.hip
 int fused_blocks(const spx_matrix* h);
 int vector_blocks(const spx_matrix* h);

@@ -1,0 +1,296 @@
+// Y = A X for 16 contiguous right-hand sides (multi-RHS product of the
+// batched forms, paper Sec. 7) with each tile's rows of X staged in LDS.
+//
+// A 16-column row of X is 128 bytes, and on a stencil operator the 27
+// entries of a row and the entries of the rows next to it name mostly the
+// same rows of X: a tile of 32 consecutive rows of the 3-D 27-point
+// operator has 864 entries but only 306 distinct columns.  Gathering a row
+// of X per entry (the pair kernels in spmv.hip) moves 3.5 KB per matrix row
+// from L2 to the compute units; staging the tile's distinct rows once, with
+// coalesced 128-byte loads, moves 1.2 KB, and the products then read X from
+// LDS.  The distinct columns of every tile and each entry's position among
+// them (16 bits, 2 bytes per entry where the column index takes 4) are
+// built once per pattern on the first such product.
+//
+// Each row's products are added in entry order from +0.0, as the pair
+// kernels do, so the results are bitwise theirs.
+#include <algorithm>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace spx {
+namespace {
+
+constexpr int kRsBlock = 256;  // threads of the index builder
+static_assert(kRsCap % kRsBlock == 0, "whole sort steps");
+constexpr int kRsIpt = kRsCap / kRsBlock;
+
+// The tile's columns (m <= kRsCap of them, from entry e0) in LDS, sorted
+// ascending; the slots after m hold INT32_MAX.
+__device__ __forceinline__ void rs_sorted_columns(const int32_t* __restrict__ col, int32_t e0,
+                                                  int m, int32_t* keys) {
+  for (int i = threadIdx.x; i < kRsCap; i += kRsBlock) keys[i] = i < m ? col[e0 + i] : INT32_MAX;
+  __syncthreads();
+  // bitonic network over kRsCap keys
+  for (int k = 2; k <= kRsCap; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < kRsCap; i += kRsBlock) {
+        const int p = i ^ j;
+        if (p > i) {
+          const int32_t a = keys[i], b = keys[p];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ bool rs_first(const int32_t* keys, int i) {
+  return keys[i] != INT32_MAX && (i == 0 || keys[i] != keys[i - 1]);
+}
+
+// The list of tile b (count, then the distinct columns) at ucol + b *
+// kRsStride and every entry's position in it; the count -1 for a tile that
+// is gathered instead.
+__global__ __launch_bounds__(kRsBlock) void k_rs_build(int64_t n, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col,
+                                                       int32_t* __restrict__ ucol,
+                                                       uint16_t* __restrict__ lidx) {
+  __shared__ int32_t keys[kRsCap];
+  __shared__ int32_t list[kRsMax];
+  __shared__ int32_t wsum[kRsBlock / 64];
+  const int64_t b = blockIdx.x, r0 = b * kRsRows;
+  const int64_t r1 = r0 + kRsRows < n ? r0 + kRsRows : n;
+  int32_t* out = ucol + b * kRsStride;
+  const int32_t e0 = rowptr[r0];
+  const int m = rowptr[r1] - e0;
+  if (m > kRsCap) {
+    if (threadIdx.x == 0) out[0] = -1;
+    return;
+  }
+  rs_sorted_columns(col, e0, m, keys);
+  // rank of every first occurrence: thread t owns kRsIpt consecutive keys
+  const int i0 = threadIdx.x * kRsIpt;
+  int firsts = 0;
+#pragma unroll
+  for (int u = 0; u < kRsIpt; ++u) firsts += rs_first(keys, i0 + u) ? 1 : 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = firsts;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int d = 0, rank = inc - firsts;
+  for (int ww = 0; ww < kRsBlock / 64; ++ww) {
+    if (ww < w) rank += wsum[ww];
+    d += wsum[ww];
+  }
+  if (d > kRsMax) {
+    if (threadIdx.x == 0) out[0] = -1;
+    return;
+  }
+  if (threadIdx.x == 0) out[0] = d;
+#pragma unroll
+  for (int u = 0; u < kRsIpt; ++u) {
+    if (rs_first(keys, i0 + u)) {
+      list[rank] = keys[i0 + u];
+      out[1 + rank] = keys[i0 + u];
+      ++rank;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += kRsBlock) {
+    const int32_t c = col[e0 + i];
+    int lo = 0, hi = d;  // list[lo] == c at the end
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (list[mid] <= c)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    lidx[e0 + i] = (uint16_t)lo;
+  }
+}
+
+// The product: tile b of kRsRows rows, 16 lanes per row, lane c computing
+// column c.  A staged tile first loads its rows of X into registers (every
+// load of a thread issued before any of its stores) and copies them to LDS,
+// after them one row of zeros (kRsMax + 1 rows of 128 bytes: 40 KB, four
+// workgroups per CU).  It then walks each row's entries in chunks of 32:
+// lanes l and 16 + l of the chunk hold entry l and 16 + l as a value and the
+// byte offset of its row of X in LDS, and entry j reaches the whole row by a
+// DPP broadcast within the 16-lane row (row_newbcast), which the compiler
+// folds into the address add; the value takes one 64-bit DPP move.  So the
+// entries never pass through LDS and X is the only LDS traffic: one
+// conflict-free 128-byte read per row and entry.  The slots of a chunk past
+// the row's end hold the value 0 and the zero row, and add +0.0 to a sum
+// that is never -0.0, so they change nothing.  A gathered tile (cnt -1)
+// reads columns and X directly.
+constexpr int kRpBlock = 512;
+constexpr int kRpLanes = 16;
+constexpr int kRpRow = kRpLanes * 8;  // bytes of a row of X
+static_assert(kRsRows * kRpLanes == kRpBlock, "one lane per column of every row");
+constexpr int kRpXq = (kRsMax * 8 + kRpBlock - 1) / kRpBlock;  // 16-byte pieces per thread
+typedef double rs_d2 __attribute__((ext_vector_type(2)));
+
+template <int J>
+__device__ __forceinline__ int rs_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + J, 0xf, 0xf, true);
+}
+template <int J>
+__device__ __forceinline__ double rs_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, true);
+}
+
+// Entries J..J+3 of a chunk into s, in entry order.
+template <int J>
+__device__ __forceinline__ void rs_entries(double va, int ca, double vb, int cb,
+                                           const char* __restrict__ xl, double& s) {
+  double x[4], v[4];
+  x[0] = *reinterpret_cast<const double*>(xl + (J < 16 ? rs_bcast<J & 15>(ca) : rs_bcast<J & 15>(cb)));
+  x[1] = *reinterpret_cast<const double*>(xl + (J + 1 < 16 ? rs_bcast<(J + 1) & 15>(ca) : rs_bcast<(J + 1) & 15>(cb)));
+  x[2] = *reinterpret_cast<const double*>(xl + (J + 2 < 16 ? rs_bcast<(J + 2) & 15>(ca) : rs_bcast<(J + 2) & 15>(cb)));
+  x[3] = *reinterpret_cast<const double*>(xl + (J + 3 < 16 ? rs_bcast<(J + 3) & 15>(ca) : rs_bcast<(J + 3) & 15>(cb)));
+  v[0] = J < 16 ? rs_bcast<J & 15>(va) : rs_bcast<J & 15>(vb);
+  v[1] = J + 1 < 16 ? rs_bcast<(J + 1) & 15>(va) : rs_bcast<(J + 1) & 15>(vb);
+  v[2] = J + 2 < 16 ? rs_bcast<(J + 2) & 15>(va) : rs_bcast<(J + 2) & 15>(vb);
+  v[3] = J + 3 < 16 ? rs_bcast<(J + 3) & 15>(va) : rs_bcast<(J + 3) & 15>(vb);
+  s += v[0] * x[0];
+  s += v[1] * x[1];
+  s += v[2] * x[2];
+  s += v[3] * x[3];
+}
+
+// The m <= 32 entries of a chunk, in groups of four.
+template <int J>
+__device__ __forceinline__ void rs_chunk(int m, double va, int ca, double vb, int cb,
+                                         const char* __restrict__ xl, double& s) {
+  if constexpr (J < 32) {
+    if (J < m) {
+      rs_entries<J>(va, ca, vb, cb, xl, s);
+      rs_chunk<J + 4>(m, va, ca, vb, cb, xl, s);
+    }
+  }
+}
+
+// Entries base + lane and base + 16 + lane of a row: value and byte offset
+// of the entry's row of X in LDS, or 0 and the zero row past the row's end.
+__device__ __forceinline__ void rs_load_chunk(const double* __restrict__ val,
+                                              const uint16_t* __restrict__ lidx, int32_t t0,
+                                              int len, int base, int lane, double& va, int& ca,
+                                              double& vb, int& cb) {
+  va = vb = 0.0;
+  ca = cb = kRsMax * kRpRow;
+  if (base + lane < len) {
+    va = stream_load(val + t0 + base + lane);
+    ca = (int)lidx[t0 + base + lane] * kRpRow;
+  }
+  if (base + kRpLanes + lane < len) {
+    vb = stream_load(val + t0 + base + kRpLanes + lane);
+    cb = (int)lidx[t0 + base + kRpLanes + lane] * kRpRow;
+  }
+}
+
+__global__ __launch_bounds__(kRpBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmm_rowset(
+    int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const int32_t* __restrict__ ucol,
+    const uint16_t* __restrict__ lidx, const double* __restrict__ X, double* __restrict__ Y) {
+  __shared__ rs_d2 xs2[(kRsMax + 1) * 8];
+  const int64_t b = blockIdx.x, r0 = b * kRsRows;
+  const int64_t row = r0 + threadIdx.x / kRpLanes;
+  const int lane = threadIdx.x % kRpLanes;
+  const int64_t rr = row < n ? row : n - 1;
+  const int32_t t0 = rowptr[rr];
+  const int len = row < n ? rowptr[rr + 1] - t0 : 0;
+  // the list and its count in one go: the list's place is fixed
+  const int32_t* list = ucol + b * kRsStride;
+  const int d = list[0];
+  int32_t lst[kRpXq];
+#pragma unroll
+  for (int u = 0; u < kRpXq; ++u) {
+    const int q = threadIdx.x + u * kRpBlock;
+    if (q < kRsMax * 8) lst[u] = list[1 + q / 8];
+  }
+  if (d >= 0) {
+    // the first chunk of the row's entries, loaded ahead of the staging
+    double va, vb;
+    int ca, cb;
+    rs_load_chunk(val, lidx, t0, len, 0, lane, va, ca, vb, cb);
+    const rs_d2* X2 = reinterpret_cast<const rs_d2*>(X);
+    rs_d2 xv[kRpXq];
+#pragma unroll
+    for (int u = 0; u < kRpXq; ++u) {
+      const int q = threadIdx.x + u * kRpBlock;
+      if (q < d * 8) xv[u] = X2[(int64_t)lst[u] * 8 + q % 8];
+    }
+#pragma unroll
+    for (int u = 0; u < kRpXq; ++u) {
+      const int q = threadIdx.x + u * kRpBlock;
+      if (q < d * 8) xs2[q] = xv[u];
+    }
+    if (threadIdx.x < 8) xs2[kRsMax * 8 + threadIdx.x] = rs_d2{0.0, 0.0};
+    __syncthreads();
+    if (row >= n) return;
+    const char* xl = reinterpret_cast<const char*>(xs2) + lane * 8;
+    double s = 0.0;
+    for (int base = 0;;) {
+      rs_chunk<0>(len - base, va, ca, vb, cb, xl, s);
+      base += 2 * kRpLanes;
+      if (base >= len) break;
+      rs_load_chunk(val, lidx, t0, len, base, lane, va, ca, vb, cb);
+    }
+    Y[row * 16 + lane] = s;
+    return;
+  }
+  if (row >= n) return;
+  double s = 0.0;
+  for (int32_t t = t0; t < t0 + len; ++t) s += val[t] * X[(int64_t)col[t] * 16 + lane];
+  Y[row * 16 + lane] = s;
+}
+
+}  // namespace
+
+int build_rowset(Csr& A, hipStream_t s) {
+  RowSet& R = A.rs;
+  if (R.built || A.n == 0) return SPX_OK;
+  const int64_t tiles = ceil_div(A.n, kRsRows);
+  int st = SPX_OK;
+  do {
+    if ((st = dalloc_n(&R.col, (size_t)(tiles * kRsStride))) != SPX_OK) break;
+    if ((st = dalloc_n(&R.lidx, (size_t)std::max<int64_t>(A.nnz, 1))) != SPX_OK) break;
+    hipLaunchKernelGGL(k_rs_build, dim3((unsigned)tiles), dim3(kRsBlock), 0, s, A.n, A.rowptr,
+                       A.col, R.col, R.lidx);
+    if (hipGetLastError() != hipSuccess) {
+      st = set_error(SPX_HIP_ERROR, "spmm: row-set index: launch failed");
+      break;
+    }
+  } while (false);
+  if (st != SPX_OK) {
+    dfree(R.col);
+    dfree(R.lidx);
+    R = RowSet();
+    return st;
+  }
+  R.built = true;
+  return SPX_OK;
+}
+
+int launch_spmm_rowset(const Csr& A, const double* X, double* Y, hipStream_t s) {
+  const RowSet& R = A.rs;
+  if (A.n == 0) return SPX_OK;
+  hipLaunchKernelGGL(k_spmm_rowset, dim3((unsigned)ceil_div(A.n, kRsRows)), dim3(kRpBlock), 0, s,
+                     A.n, A.rowptr, A.col, A.val, R.col, R.lidx, X, Y);
+  return SPX_OK;
+}
+
+}  // namespace spx

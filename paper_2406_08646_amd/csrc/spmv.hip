@@ -745,7 +745,16 @@ extern "C" int spx_spmm(spx_handle h, int64_t nrhs, const double* X, int64_t ldx
   if (!h || nrhs < 0 || (nrhs > 0 && (!X || !Y)) || ldx < nrhs || ldy < nrhs)
     return set_error(SPX_INVALID_ARG, "spmm: bad argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SPX_TRY(launch_spmm(h->A, nrhs, X, ldx, Y, ldy, s));
+  // 16 contiguous, 16-byte aligned columns: each tile's rows of X staged in
+  // LDS (spmm.hip), the index built on the first call
+  const bool rowset = nrhs == 16 && ldx == 16 && ldy == 16 &&
+                      ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15) == 0;
+  if (rowset) {
+    SPX_TRY(build_rowset(h->A, s));
+    SPX_TRY(launch_spmm_rowset(h->A, X, Y, s));
+  } else {
+    SPX_TRY(launch_spmm(h->A, nrhs, X, ldx, Y, ldy, s));
+  }
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
 }

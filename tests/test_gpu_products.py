@@ -210,6 +210,103 @@ def test_spmm_staged_runs_and_fallback(orc, nrhs):
         spmv_within(outs[0][:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
 
 
+def _row_set_pattern(rng, tiles, tail):
+    """Tiles of 32 rows of five kinds, in turn: 9 random columns a row (the
+    tile's rows of X staged), 12 (too many distinct columns: gathered), rows
+    of 0..65 entries from a 100-column window (staged, rows longer than one
+    32-entry chunk), 40 a row (too many entries: gathered), and no entries;
+    then a ragged last tile."""
+    n = 32 * tiles + tail
+    I, J = [], []
+    cycle = [0, 1, 31, 32, 33, 64, 65, 16, 17, 2]
+    for r in range(n):
+        kind = (r // 32) % 5
+        if kind == 0:
+            cols = rng.choice(n, 9, replace=False)
+        elif kind == 1:
+            cols = rng.choice(n, 12, replace=False)
+        elif kind == 2:
+            lo = min(max(r - 50, 0), n - 100)
+            cols = lo + rng.choice(100, cycle[r % len(cycle)], replace=False)
+        elif kind == 3:
+            cols = rng.choice(n, 40, replace=False)
+        else:
+            cols = np.zeros(0, np.int64)
+        I.append(np.full(cols.size, r))
+        J.append(cols)
+    i = np.concatenate(I).astype(np.int32)
+    j = np.concatenate(J).astype(np.int32)
+    return W.CooProblem(n=n, i=i, j=j, v=rng.uniform(-1, 1, i.size))
+
+
+def _spmm16(lib, A, Xh, ld):
+    import ctypes
+    n = Xh.shape[0]
+    Xa = torch.zeros(n * ld + 2, dtype=torch.float64, device="cuda")
+    Xa[: n * ld].view(n, ld)[:, :16] = dev(Xh)
+    Y = torch.full((n * ld + 2,), np.nan, dtype=torch.float64, device="cuda")
+    rc = lib.spx_spmm(A.handle, 16, ctypes.c_void_p(Xa.data_ptr()), ld,
+                      ctypes.c_void_p(Y.data_ptr()), ld, None)
+    assert rc == 0
+    return host(Y[: n * ld].view(n, ld)[:, :16])
+
+
+@pytest.mark.parametrize("tiles,tail", [(40, 7), (5, 0), (0, 9)])
+def test_spmm16_row_set_tiles(orc, tiles, tail):
+    """The 16-column product with each tile's rows of X staged in LDS (16
+    contiguous columns): every kind of tile, bitwise equal to the paired-
+    column kernel (16 columns at leading dimension 18) and within the SpMV
+    tolerance of the oracle; a second product reuses the index."""
+    spx = require_gpu()
+    lib = spx.load_library()
+    rng = np.random.default_rng(90 + tiles)
+    prob = _row_set_pattern(rng, tiles, tail)
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    for rep in range(2):
+        Xh = rng.uniform(-1, 1, (prob.n, 16))
+        Ys = _spmm16(lib, A, Xh, 16)
+        Yp = _spmm16(lib, A, Xh, 18)
+        assert np.array_equal(bits(Ys), bits(Yp)), rep
+        Yr = orc.spmm(ref, Xh)
+        for c in range(16):
+            spmv_within(Ys[:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
+
+
+def test_spmm16_row_set_non_finite_x(orc):
+    """Rows of X holding inf and NaN: only the rows of Y whose entries name
+    them turn non-finite (a chunk's unused slots add +0.0 times a row of
+    zeros, never a staged row), and the bits match the paired-column
+    kernel's."""
+    spx = require_gpu()
+    lib = spx.load_library()
+    rng = np.random.default_rng(97)
+    prob = _row_set_pattern(rng, 12, 5)
+    A = assemble(spx, prob)
+    ref = orc.assemble(prob.n, prob.i, prob.j, prob.v)
+    Xh = rng.uniform(-1, 1, (prob.n, 16))
+    k_inf, k_nan = int(prob.j[0]), int(prob.j[prob.j.size // 2])
+    Xh[k_inf, :] = np.inf
+    Xh[k_nan, 5] = np.nan
+    Ys = _spmm16(lib, A, Xh, 16)
+    Yp = _spmm16(lib, A, Xh, 18)
+    fin = np.isfinite(Yp)
+    assert np.array_equal(fin, np.isfinite(Ys))
+    assert np.array_equal(np.isnan(Yp), np.isnan(Ys))
+    assert np.array_equal(bits(Ys[fin]), bits(Yp[fin]))
+    assert np.array_equal(Ys[np.isinf(Yp)], Yp[np.isinf(Yp)])
+    touched = np.zeros(prob.n, bool)
+    touched[prob.i[(prob.j == k_inf) | (prob.j == k_nan)]] = True
+    assert np.isfinite(Ys[~touched]).all()
+    Xf = Xh.copy()
+    Xf[k_inf, :] = 0.0
+    Xf[k_nan, 5] = 0.0
+    Yr = orc.spmm(ref, Xf)
+    for c in range(16):
+        rows = ~touched
+        spmv_within(Ys[rows, c], Yr[rows, c], orc.abs_spmv(ref, Xf[:, c])[rows])
+
+
 def test_sddmm_and_gather_bitwise(orc):
     spx = require_gpu()
     rng = np.random.default_rng(32)
