@@ -40,7 +40,7 @@ struct spx_lbfgs {
   double* Y = nullptr;
   double* SY = nullptr;  // SY[a*m + b] = s_a . y_b, by slot
   double* P = nullptr;   // partials [2m][G]
-  double* red = nullptr; // reduced vectors: q[m] | c[m] | f[m] | u[m] | v[m]
+  double* red = nullptr; // reduced vectors: q[m] | c[m] | f[m] | e[m] | spare
   double* a = nullptr;   // n
 };
 
@@ -331,9 +331,50 @@ __device__ __forceinline__ double rmat(const double* SY, const Ring& R, int a, i
   return SY[R.slot(a) * R.m + R.slot(b)];
 }
 
-// pass 2 for histories of at most kFused pairs: c = -R^-1 q (every
-// workgroup; workgroup 0 stores it); a = h0 (g + Y c) and the partials of
-// f_b = y_b . a, each row's history values held in registers
+// The two triangular solves of the apply, R = triu(S^T Y) in the ring's
+// logical order: c = -R^-1 q (WHICH 0, into red[m..]) after the first
+// pass, e = R^-T (f + D c) (WHICH 1, into red[3m..]) after the second.
+// One workgroup stages R in LDS, then one wave sweeps the columns: lane x
+// holds row x's running sum, and at step y every lane takes the finished
+// unknown y by a shuffle and lanes still open subtract their entry of
+// column y times it (cnt <= 64 lanes).
+template <int WHICH>
+__global__ __launch_bounds__(kLB) void k_lb_solve(const double* __restrict__ SY, Ring R,
+                                                  double* __restrict__ red) {
+  __shared__ double rl[kMaxHistory * kMaxHistory];
+  const int cnt = R.cnt;
+  for (int i = threadIdx.x; i < cnt * cnt; i += kLB) {
+    const int a = i / cnt, b = i % cnt;
+    rl[i] = a <= b ? rmat(SY, R, a, b) : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int x = threadIdx.x;
+  double out = 0.0;
+  if constexpr (WHICH == 0) {
+    double t = x < cnt ? -red[x] : 0.0;
+    for (int y = cnt - 1; y >= 0; --y) {
+      const double uy = __shfl(t, y, 64) / rl[y * cnt + y];
+      if (x == y) out = uy;
+      if (x < y) t -= rl[x * cnt + y] * uy;
+    }
+    if (x < cnt) red[kMaxHistory + x] = out;
+  } else {
+    const double* c = red + kMaxHistory;
+    const double* f = red + 2 * kMaxHistory;
+    double t = x < cnt ? f[x] + rl[x * cnt + x] * c[x] : 0.0;
+    for (int y = 0; y < cnt; ++y) {
+      const double uy = __shfl(t, y, 64) / rl[y * cnt + y];
+      if (x == y) out = uy;
+      if (x > y) t -= rl[y * cnt + x] * uy;
+    }
+    if (x < cnt) red[3 * kMaxHistory + x] = out;
+  }
+}
+
+// pass 2 for histories of at most kFused pairs: a = h0 (g + Y c) with c
+// from red[m..], and the partials of f_b = y_b . a, each row's history
+// values held in registers
 template <int V>
 __global__ __launch_bounds__(kLB, 1) void k_lb_ya(int64_t n, const double* __restrict__ Y, Ring R,
                                                const double* __restrict__ g,
@@ -347,16 +388,7 @@ __global__ __launch_bounds__(kLB, 1) void k_lb_ya(int64_t n, const double* __res
   __shared__ double tot[kFused];
   __shared__ double cs[kMaxHistory];
   const int cnt = R.cnt;
-  if (threadIdx.x == 0) {
-    const double* q = red;
-    for (int x = cnt - 1; x >= 0; --x) {
-      double t = -q[x];
-      for (int y = x + 1; y < cnt; ++y) t -= rmat(SY, R, x, y) * cs[y];
-      cs[x] = t / rmat(SY, R, x, x);
-    }
-    if (blockIdx.x == 0)
-      for (int x = 0; x < cnt; ++x) red[kMaxHistory + x] = cs[x];
-  }
+  if (threadIdx.x < cnt) cs[threadIdx.x] = red[kMaxHistory + threadIdx.x];
   __syncthreads();
   int64_t lo, hi;
   rows_of<V>(n, blockIdx.x, gridDim.x, &lo, &hi);
@@ -392,8 +424,8 @@ __global__ __launch_bounds__(kLB, 1) void k_lb_ya(int64_t n, const double* __res
   }
 }
 
-// pass 2 for histories longer than kFused: c as in k_lb_ya, then a and the
-// partials of f_b = y_b . a from ONE pass over Y.  Each block of kYRows rows
+// pass 2 for histories longer than kFused: a and the partials of
+// f_b = y_b . a from ONE pass over Y.  Each block of kYRows rows
 // is staged in LDS (kYRows x cnt, column stride kYRows + 1 so that the
 // column-wise reads below hit distinct banks): thread r < kYRows forms
 // a_r = h0_r (g_r + sum_b y_b[r] c_b) with the columns in order; then
@@ -418,17 +450,10 @@ __global__ __launch_bounds__(kLB) void k_lb_ya_staged(int64_t n, const double* _
   __shared__ double cs[kMaxHistory];
   __shared__ int64_t cols[kMaxHistory];
   const int cnt = R.cnt;
-  if (threadIdx.x == 0) {
-    const double* q = red;
-    for (int x = cnt - 1; x >= 0; --x) {
-      double t = -q[x];
-      for (int y = x + 1; y < cnt; ++y) t -= rmat(SY, R, x, y) * cs[y];
-      cs[x] = t / rmat(SY, R, x, x);
-    }
-    if (blockIdx.x == 0)
-      for (int x = 0; x < cnt; ++x) red[kMaxHistory + x] = cs[x];
+  if (threadIdx.x < cnt) {
+    cs[threadIdx.x] = red[kMaxHistory + threadIdx.x];
+    cols[threadIdx.x] = R.slot(threadIdx.x) * n;
   }
-  if (threadIdx.x < cnt) cols[threadIdx.x] = R.slot(threadIdx.x) * n;
   __syncthreads();
   int64_t lo, hi;
   rows_of<1>(n, blockIdx.x, gridDim.x, &lo, &hi);
@@ -484,7 +509,7 @@ __global__ __launch_bounds__(kLB) void k_lb_ya_staged(int64_t n, const double* _
   }
 }
 
-// pass 3: e = R^-T (f + D c) (every workgroup); p = a - S e
+// pass 3: p = a - S e, e from red[3m..]
 template <int V>
 __global__ __launch_bounds__(kLB, kGemvtWaves) void k_lb_p(int64_t n, const double* __restrict__ S, Ring R,
                                               const double* __restrict__ a,
@@ -494,15 +519,7 @@ __global__ __launch_bounds__(kLB, kGemvtWaves) void k_lb_p(int64_t n, const doub
   typedef typename Vd<V>::type VD;
   __shared__ double es[kMaxHistory];
   const int cnt = R.cnt;
-  if (threadIdx.x == 0) {
-    const double* c = red + kMaxHistory;
-    const double* f = red + 2 * kMaxHistory;
-    for (int x = 0; x < cnt; ++x) {
-      double t = f[x] + rmat(SY, R, x, x) * c[x];
-      for (int y = 0; y < x; ++y) t -= rmat(SY, R, y, x) * es[y];
-      es[x] = t / rmat(SY, R, x, x);
-    }
-  }
+  if (threadIdx.x < cnt) es[threadIdx.x] = red[3 * kMaxHistory + threadIdx.x];
   __syncthreads();
   row_blocks<V, true>(
       n, S, R, es, [&](int64_t i) { return ldv<V>(a + i); },
@@ -540,6 +557,7 @@ int apply_passes(spx_lbfgs* h, const double* g, const double* h0, double* p, hip
     hipLaunchKernelGGL(k_lb_sg<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, g, h->P);
     hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, G, h->red);
   }
+  hipLaunchKernelGGL(k_lb_solve<0>, dim3(1), dim3(kLB), 0, st, h->SY, R, h->red);
   int Gf = G;  // workgroups whose partials of f the reduction adds
   if (cnt <= kFused) {
     hipLaunchKernelGGL(k_lb_ya<V>, dim3(G), dim3(kLB), 0, st, n, h->Y, R, g, h0, h->SY,
@@ -550,6 +568,7 @@ int apply_passes(spx_lbfgs* h, const double* g, const double* h0, double* p, hip
                        h->red, h->a, h->P);
   }
   hipLaunchKernelGGL(k_lb_reduce, dim3(cnt), dim3(kLB), 0, st, h->P, Gf, h->red + 2 * kMaxHistory);
+  hipLaunchKernelGGL(k_lb_solve<1>, dim3(1), dim3(kLB), 0, st, h->SY, R, h->red);
   hipLaunchKernelGGL(k_lb_p<V>, dim3(G), dim3(kLB), 0, st, n, h->S, R, h->a, h->SY, h->red, p);
   return SPX_OK;
 }
