@@ -428,7 +428,8 @@ __global__ __launch_bounds__(kLB, 1) void k_lb_ya(int64_t n, const double* __res
 // f_b = y_b . a from ONE pass over Y.  Each block of kYRows rows
 // is staged in LDS (kYRows x cnt, column stride kYRows + 1 so that the
 // column-wise reads below hit distinct banks): thread r < kYRows forms
-// a_r = h0_r (g_r + sum_b y_b[r] c_b) with the columns in order; then
+// a_r = h0_r (g_r + sum_b y_b[r] c_b) with the columns in order (its g_r
+// and h0_r loaded with the block's elements of Y); then
 // thread t adds y_b[r] a_r for column b = t % 64 over its quarter of the
 // block's rows.  Every element of Y is read from memory once; the next
 // block's elements are loaded into registers (kYPer per thread, all issued
@@ -461,12 +462,17 @@ __global__ __launch_bounds__(kLB) void k_lb_ya_staged(int64_t n, const double* _
   const int er = threadIdx.x % kYRows, eb = threadIdx.x / kYRows;
   constexpr int kBStep = kLB / kYRows;
   double v[kYPer];
+  double gn = 0.0, hn = 1.0;  // g and h0 of row er of the block, for threads below kYRows
   auto load = [&](int64_t r0) {
     const bool in = r0 + er < hi;
 #pragma unroll
     for (int k = 0; k < kYPer; ++k) {
       const int b = eb + k * kBStep;
       if (in && b < cnt) v[k] = Y[cols[b] + r0 + er];
+    }
+    if (in && threadIdx.x < kYRows) {
+      gn = g[r0 + er];
+      if (h0) hn = h0[r0 + er];
     }
   };
   const int fb = threadIdx.x & 63;  // column of this thread's f accumulator
@@ -481,13 +487,14 @@ __global__ __launch_bounds__(kLB) void k_lb_ya_staged(int64_t n, const double* _
       const int b = eb + k * kBStep;
       if (er < nr && b < cnt) tile[b * kYStride + er] = v[k];
     }
+    const double gc = gn, hc = hn;
     __syncthreads();
     if (r0 + kYRows < hi) load(r0 + kYRows);
     if (threadIdx.x < nr) {
       const int r = threadIdx.x;
-      double t = g[r0 + r];
+      double t = gc;
       for (int b = 0; b < cnt; ++b) t += tile[b * kYStride + r] * cs[b];
-      const double ar = h0 ? h0[r0 + r] * t : t;
+      const double ar = h0 ? hc * t : t;
       a_out[r0 + r] = ar;
       as[r] = ar;
     }
