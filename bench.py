@@ -137,7 +137,7 @@ def host_cpu():
 
 
 EXTRAS = ("ceilings", "spmm16", "vec_coo", "cg_forms", "c1_cg", "one_gpu_share", "sync_vs_async",
-          "batched64", "nonsymmetric_batch64", "lbfgs", "gradient256")
+          "batched64", "batched_small", "nonsymmetric_batch64", "lbfgs", "gradient256")
 
 
 def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
@@ -419,7 +419,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
             autotune.Candidate(1024, 0, 1.0), autotune.Candidate(2048, 0, 1.0),
             autotune.Candidate(2048, 64, 1.0), autotune.Candidate(2048, 0, 1.25)])
         kw = dict(blocks=best["blocks"], rows_per_tile=best["rows_per_tile"],
-                  weight_exponent=best["weight_exponent"])
+                  weight_exponent=best["weight_exponent"], persistent=best["persistent"])
         bt_ms, (xb, iters, relres, st) = timed(lambda: batch.batch_cg(bvec, rtol=1e-8, **kw), reps=3)
         work = sum(it * cg_iteration_bytes(p.n, m.nnz) for it, p, m in zip(iters, probs, mats))
         # one solve per system
@@ -443,6 +443,42 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
                             "speedup_vs_sequential": round(seq_ms / bt_ms, 2)}
         log(f"batched: {bt_ms:.2f} ms, ensemble {ens_ms:.2f} ms, sequential {seq_ms:.2f} ms")
         del batch, mats, E
+
+    # ---- many small systems (the batched solvers' own regime): the persistent
+    # launch (a workgroup per system, from a queue) vs one launch per phase vs
+    # the ensemble
+    if want("batched_small"):
+        nsm, lo_s, hi_s = 2048, 16, 64
+        probs_s, bs_s = W.config4(nsys=nsm, lo=lo_s, hi=hi_s, seed=5)
+        mats_s = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs_s]
+        for m, p in zip(mats_s, probs_s):
+            m.set_values_coo(d(p.v))
+        batch_s = spx.batch_create(mats_s)
+        bvec_s = d(np.concatenate(bs_s))
+        ms_p, (xp_, it_p, rel_p, st_p) = timed(lambda: batch_s.batch_cg(bvec_s, rtol=1e-8, persistent=1),
+                                              reps=3)
+        ms_f, (xf_, it_f, rel_f, st_f) = timed(lambda: batch_s.batch_cg(bvec_s, rtol=1e-8, persistent=-1),
+                                              reps=3)
+        offs_s = np.cumsum([0] + [p.n for p in probs_s])
+        E_s = spx.coo_preallocate(int(offs_s[-1]),
+                                  d(np.concatenate([p.i + o for p, o in zip(probs_s, offs_s)]).astype(np.int32)),
+                                  d(np.concatenate([p.j + o for p, o in zip(probs_s, offs_s)]).astype(np.int32)))
+        E_s.set_values_coo(d(np.concatenate([p.v for p in probs_s])))
+        ms_e, ens_s = timed(lambda: E_s.cg_solve(bvec_s, rtol=1e-8), reps=2)
+        work_s = sum(it * cg_iteration_bytes(p.n, m.nnz) for it, p, m in zip(it_p, probs_s, mats_s))
+        out["batched_small"] = {
+            "systems": nsm, "sides": [lo_s, hi_s], "rows": int(offs_s[-1]),
+            "persistent_ms": round(ms_p, 2), "persistent_status": st_p,
+            "persistent_solves_per_s": round(nsm / (ms_p * 1e-3), 1),
+            "persistent_gbs": round(work_s / (ms_p * 1e-3) / 1e9, 1),
+            "per_phase_ms": round(ms_f, 2), "per_phase_status": st_f,
+            "ensemble_ms": round(ms_e, 2), "ensemble_iters": ens_s.iters,
+            "max_relres": max(max(rel_p), max(rel_f)), "iters_max": max(it_p),
+            "persistent_vs_per_phase": round(ms_f / ms_p, 2),
+            "persistent_vs_ensemble": round(ms_e / ms_p, 2)}
+        log(f"batched small ({nsm} systems): persistent {ms_p:.2f} ms, per phase {ms_f:.2f} ms, "
+            f"ensemble {ms_e:.2f} ms")
+        del batch_s, mats_s, E_s
 
     # ---- 64-system non-symmetric batch: batched TFQMR / BiCG vs ensemble vs one per system
     if want("nonsymmetric_batch64"):

@@ -275,21 +275,33 @@ int spx_batch_total_rows(spx_batch_handle b, int64_t* total);
  *   weight_exponent: a running system's share of the workgroups is
  *     proportional to nnz_s^weight_exponent, at least one (<= 0 means 1).
  *   check_every: iterations between host polls, at which the workgroups are
- *     re-split among the systems still running (0 means 20). */
+ *     re-split among the systems still running (0 means 20).
+ *   persistent (spx_batch_cg only; ignored by BiCG and TFQMR): 1 asks for
+ *     ONE launch for the whole solve, in which each workgroup (256 threads)
+ *     takes the next system from a queue, largest first, and runs its whole
+ *     Jacobi-CG alone (the fields above are then unused, and a system's
+ *     largest 256-row tile must fit 64 KB of LDS, else SPX_INVALID_ARG);
+ *     -1 asks for the launch-per-phase solve above; 0 lets the library
+ *     choose (persistent for at least 256 systems of at most 8192 rows
+ *     each). */
 typedef struct spx_batch_tuning {
   int32_t blocks;
   int32_t rows_per_tile;
   double weight_exponent;
   int32_t check_every;
-  int32_t reserved;
+  int32_t persistent;
 } spx_batch_tuning;
 
 /* Solves every system of the batch with Jacobi-CG to its own
  * ||r_s|| <= rtol ||b_s|| (the single-system algorithm above, system by
- * system).  All systems advance together and each CG phase is one launch
- * for the whole batch: the workgroups form one team per running system;
- * converged systems drop out and their workgroups go to the others at the
- * next poll.  b, x: packed device float64[total]; x is the initial guess
+ * system).  Two launch forms (tuning->persistent): either all systems
+ * advance together and each CG phase is one launch for the whole batch
+ * (the workgroups form one team per running system; converged systems drop
+ * out and their workgroups go to the others at the next poll), or ONE
+ * launch solves the batch with each workgroup taking whole systems from a
+ * queue, largest first (no host poll).  The dots are summed in different
+ * orders, so the two forms' iterates agree to rounding, not bitwise.
+ * b, x: packed device float64[total]; x is the initial guess
  * and receives the solutions.  tuning: may be NULL.  iters_out /
  * relres_out: HOST int64[nsys] / float64[nsys]: iterations and true
  * ||b_s - A_s x_s|| / ||b_s||.  Returns SPX_NOT_CONVERGED if a system hit

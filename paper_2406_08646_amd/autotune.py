@@ -1,10 +1,12 @@
 """Launch-shape autotuner for the batched solver.
 
-The batched Jacobi-CG (``spx_batch_cg``) has three shape knobs: the number
-of workgroups shared by the systems, the row walk (``rows_per_tile`` 0: the
-library's choice, the window walk when every system has a window index; 64
-or 256: the stream walk with that tile) and the exponent that turns a
-system's size into its share of the workgroups.
+The batched Jacobi-CG (``spx_batch_cg``) has two launch forms: one launch
+per CG phase for the whole batch, or one persistent launch in which each
+workgroup solves whole systems from a queue (``persistent``).  The first has
+three shape knobs: the number of workgroups shared by the systems, the row
+walk (``rows_per_tile`` 0: the library's choice, the window walk when every
+system has a window index; 64 or 256: the stream walk with that tile) and
+the exponent that turns a system's size into its share of the workgroups.
 The best values depend on the mix of system sizes, so the tuner times whole
 solves of the actual batch for a small grid of candidates, on the GPU, and
 keeps the fastest.  Results are cached per (device, batch signature,
@@ -32,10 +34,11 @@ class Candidate:
     blocks: int
     rows_per_tile: int
     weight_exponent: float
+    persistent: int = -1  # 1: the persistent form (the other knobs unused)
 
 
 def default_candidates(cus: int) -> List[Candidate]:
-    out = []
+    out = [Candidate(0, 0, 1.0, persistent=1)]
     for blocks, rows, gamma in itertools.product((4 * cus, 8 * cus, 16 * cus), (0, 64, 256),
                                                  (0.75, 1.0, 1.25)):
         out.append(Candidate(blocks, rows, gamma))
@@ -55,7 +58,7 @@ def tune_batch(batch: "spx.Batch", b: torch.Tensor, rtol: float = 1e-8, maxit: i
                candidates: Optional[Iterable[Candidate]] = None, repeats: int = 1,
                cache_file: Optional[str] = None, verbose: bool = False) -> dict:
     """Times full batched solves for each candidate and returns the fastest
-    as ``{"blocks", "rows_per_tile", "weight_exponent", "ms"}``."""
+    as ``{"blocks", "rows_per_tile", "weight_exponent", "persistent", "ms"}``."""
     key = batch_signature(batch, rtol)
     if key in _MEMO:
         return _MEMO[key]
@@ -71,14 +74,20 @@ def tune_batch(batch: "spx.Batch", b: torch.Tensor, rtol: float = 1e-8, maxit: i
     x = torch.zeros_like(b)
     for c in cands:
         times = []
-        for _ in range(repeats + 1):  # first run warms the shape up
-            x.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            batch.batch_cg(b, x=x, rtol=rtol, maxit=maxit, blocks=c.blocks,
-                           rows_per_tile=c.rows_per_tile, weight_exponent=c.weight_exponent)
-            torch.cuda.synchronize()
-            times.append((time.perf_counter() - t0) * 1e3)
+        try:
+            for _ in range(repeats + 1):  # first run warms the shape up
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                batch.batch_cg(b, x=x, rtol=rtol, maxit=maxit, blocks=c.blocks,
+                               rows_per_tile=c.rows_per_tile, weight_exponent=c.weight_exponent,
+                               persistent=c.persistent)
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) * 1e3)
+        except spx.SpxError as e:
+            if e.code != spx.INVALID_ARG:  # a form this batch cannot take is skipped
+                raise
+            continue
         ms = min(times[1:])
         if verbose:
             print(f"[autotune] {asdict(c)} -> {ms:.3f} ms", flush=True)

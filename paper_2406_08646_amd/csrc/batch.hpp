@@ -69,6 +69,9 @@ struct spx_batch {
   int64_t max_row_t = 0;
   int64_t win_blocks_t = 0;
   double* kwork = nullptr;  // 8 * total
+  // persistent solve: [0] the next queue position, [1 + k] the k-th system
+  // to take (largest first)
+  int32_t* d_queue = nullptr;
 };
 
 namespace spx {

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "cg_one.hpp"
 #include "common.hpp"
 #include "device.hpp"
 #include "solver_core.hpp"
@@ -162,6 +163,53 @@ __global__ __launch_bounds__(kBlock) void k_b_pupdate(const BatchSys* __restrict
     p[i] = dinv[i] * r[i] + bt * p[i];
 }
 
+// One persistent launch for the whole batch: each workgroup takes the next
+// system from a queue (largest first), runs its whole Jacobi-CG alone
+// (cg_one.hpp: the K1..K3 recurrences, tests and statuses, workgroup sums
+// for the dots), and takes another until the queue is empty.  A workgroup
+// never waits for another; a system's vectors are touched by its own
+// workgroup only.  Thread t owns rows t, t + BLOCK, ... of every pass, the
+// D^-1 it writes included.  BLOCK = 256 for systems of at most 1024 rows
+// (more systems in flight), 1024 above (each system faster); tiles of ROWS
+// rows.
+__global__ void k_b_queue_reset(int32_t* queue) {
+  if (threadIdx.x == 0) queue[0] = 0;
+}
+
+template <int BLOCK, int ROWS>
+__global__ __launch_bounds__(BLOCK) void k_b_cg_persistent(
+    const BatchSys* __restrict__ sys, int nsys, int32_t* __restrict__ queue,
+    const double* __restrict__ bvec, double* __restrict__ x, double* __restrict__ r,
+    double* __restrict__ p, double* __restrict__ q, double* __restrict__ dinv, CgScalars* st,
+    double rtol) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[BLOCK / 64];
+  __shared__ int32_t pick, zero;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      pick = atomicAdd(queue, 1);
+      zero = 0;
+    }
+    __syncthreads();
+    const int32_t k = pick;
+    if (k >= nsys) break;
+    const int s = queue[1 + k];
+    const BatchSys S = sys[s];
+    const int64_t o = S.off;
+    for (int64_t i = threadIdx.x; i < S.n; i += BLOCK) {
+      const int32_t t = S.dpos[i];
+      const double d = t >= 0 ? S.val[t] : 0.0;
+      if (d == 0.0) zero = 1;
+      dinv[o + i] = d == 0.0 ? 0.0 : 1.0 / d;
+    }
+    __syncthreads();
+    one::cg_solve<BLOCK, ROWS>(S.n, S.rowptr, S.col, S.val, bvec + o, x + o, r + o, p + o, q + o,
+                               dinv + o, zero ? SPX_ZERO_DIAGONAL : SPX_OK, st[s].maxit, rtol,
+                               st + s, reinterpret_cast<double*>(smem), lds);
+    __syncthreads();  // `pick` and `zero` read by every thread before thread 0 rewrites them
+  }
+}
+
 }  // namespace
 }  // namespace spx
 
@@ -169,6 +217,59 @@ using namespace spx;
 using namespace spx::solver;
 
 using namespace spx::batch;
+
+namespace {
+// Shape of the persistent solve: workgroup size, rows per tile and the
+// dynamic LDS for the products of the largest such tile of any system
+// (max_tile[3] bounds a 256-row tile; 512 and 1024 rows take 2 and 4 of
+// them); lds 0 when not even a 256-row tile fits 64 KB.
+struct PersistShape {
+  int block = 256, rows = 256;
+  size_t lds = 0;
+};
+PersistShape persistent_shape(const spx_batch* B) {
+  PersistShape ps;
+  int64_t max_n = 0;
+  for (const BatchSys& S : B->sys) max_n = std::max(max_n, S.n);
+  auto bytes = [&](int64_t tiles) { return (size_t)(tiles * B->max_tile[3] + 8) * sizeof(double); };
+  if (bytes(1) > 64 * 1024) return ps;
+  if (max_n > 1024) {
+    ps.block = 1024;
+    ps.rows = bytes(4) <= 64 * 1024 ? 1024 : bytes(2) <= 64 * 1024 ? 512 : 256;
+  }
+  ps.lds = bytes(ps.rows / 256);
+  return ps;
+}
+
+// The persistent solve pays off when there are enough systems to keep the
+// workgroups busy and each is small enough for one workgroup: at least
+// kPersistAutoSystems systems, none above kPersistAutoRows rows.  Measured
+// on 5-point batches (persistent vs one launch per phase): 4096 systems of
+// 16-256 rows 6.5x, 1024 of 64-1024 rows 2.0x, 2048 of 256-4096 1.8x, 256
+// of 1024-4096 1.2x, 1024 of 1024-8100 1.4x; 512 of 4096-16384 0.91x, and
+// 64 of 1024-262144 0.05x (the largest system alone on one workgroup).
+constexpr int kPersistAutoSystems = 256;
+constexpr int64_t kPersistAutoRows = 8192;
+bool persistent_by_default(const spx_batch* B) {
+  if (B->nsys < kPersistAutoSystems || persistent_shape(B).lds == 0) return false;
+  for (const BatchSys& S : B->sys)
+    if (S.n > kPersistAutoRows) return false;
+  return true;
+}
+
+template <int BLOCK, int ROWS>
+int launch_persistent(spx_batch* B, const PersistShape& ps, const double* bvec, double* x,
+                      double* r, double* p, double* q, double* dinv, double rtol, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&k_b_cg_persistent<BLOCK, ROWS>);
+  int fit = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, fn, BLOCK, ps.lds) != hipSuccess || fit < 1)
+    fit = 1;
+  const int G = (int)std::min<int64_t>(B->nsys, (int64_t)cu_count() * fit);
+  hipLaunchKernelGGL((k_b_cg_persistent<BLOCK, ROWS>), dim3((unsigned)G), dim3(BLOCK), ps.lds, s,
+                     B->d_sys, B->nsys, B->d_queue, bvec, x, r, p, q, dinv, B->d_st, rtol);
+  return SPX_OK;
+}
+}  // namespace
 
 extern "C" int spx_batch_create(int32_t nsys, const spx_handle* hs, void* stream,
                                 spx_batch_handle* out) {
@@ -212,12 +313,22 @@ extern "C" int spx_batch_create(int32_t nsys, const spx_handle* hs, void* stream
     if ((st = dalloc_n(&B->d_sys, (size_t)nsys)) != SPX_OK) break;
     if ((st = dalloc_n(&B->work, (size_t)B->total * 4)) != SPX_OK) break;
     if ((st = dalloc_n(&B->d_st, (size_t)nsys)) != SPX_OK) break;
+    if ((st = dalloc_n(&B->d_queue, (size_t)nsys + 1)) != SPX_OK) break;
     if (hipHostMalloc(reinterpret_cast<void**>(&B->h_st), sizeof(CgScalars) * (size_t)nsys,
                       hipHostMallocDefault) != hipSuccess) {
       st = set_error(SPX_OUT_OF_MEMORY, "batch_create: pinned allocation failed");
       break;
     }
+    // the persistent solve's queue: systems by decreasing entry count
+    // (ties in system order), so the longest solves start first
+    std::vector<int32_t> order(nsys + 1, 0);
+    for (int k = 0; k < nsys; ++k) order[1 + k] = k;
+    std::stable_sort(order.begin() + 1, order.end(), [&](int32_t a, int32_t b) {
+      return B->hs[a]->A.nnz > B->hs[b]->A.nnz;
+    });
     if (hipMemcpyAsync(B->d_sys, B->sys.data(), sizeof(BatchSys) * (size_t)nsys,
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(B->d_queue, order.data(), sizeof(int32_t) * (size_t)(nsys + 1),
                        hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
       st = set_error(SPX_HIP_ERROR, "batch_create: descriptor upload failed");
@@ -242,6 +353,7 @@ extern "C" int spx_batch_destroy(spx_batch_handle B) {
   dfree(B->partials);
   dfree(B->d_sysT);
   dfree(B->kwork);
+  dfree(B->d_queue);
   if (B->h_st) (void)hipHostFree(B->h_st);
   if (B->h_plan) (void)hipHostFree(B->h_plan);
   delete B;
@@ -264,6 +376,8 @@ extern "C" int spx_batch_cg(spx_batch_handle B, const double* bvec, double* x, d
   if (maxit > INT32_MAX - 1) maxit = INT32_MAX - 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = B->nsys;
+  const int32_t pmode = tuning ? tuning->persistent : 0;
+  if (pmode < -1 || pmode > 1) return set_error(SPX_INVALID_ARG, "batch_cg: persistent must be -1, 0 or 1");
   Run run;
   SPX_TRY(prepare(B, tuning, B->max_tile, B->max_row, B->win_blocks, 3, s, &run));
   const int G = run.G;
@@ -272,6 +386,26 @@ extern "C" int spx_batch_cg(spx_batch_handle B, const double* bvec, double* x, d
   double* p = B->work + tot;
   double* q = B->work + 2 * tot;
   double* dinv = B->work + 3 * tot;
+  if (pmode == 1 || (pmode == 0 && persistent_by_default(B))) {
+    const PersistShape ps = persistent_shape(B);
+    if (ps.lds == 0)
+      return set_error(SPX_INVALID_ARG,
+                       "batch_cg: a 256-row tile of a system exceeds the persistent solve's LDS");
+    hipLaunchKernelGGL(k_b_reset, dim3((unsigned)ceil_div(ns, 64)), dim3(64), 0, s, B->d_st, ns,
+                       (int32_t)maxit);
+    hipLaunchKernelGGL(k_b_queue_reset, dim3(1), dim3(64), 0, s, B->d_queue);
+    if (ps.block == 256)
+      SPX_TRY((launch_persistent<256, 256>(B, ps, bvec, x, r, p, q, dinv, rtol, s)));
+    else if (ps.rows == 1024)
+      SPX_TRY((launch_persistent<1024, 1024>(B, ps, bvec, x, r, p, q, dinv, rtol, s)));
+    else if (ps.rows == 512)
+      SPX_TRY((launch_persistent<1024, 512>(B, ps, bvec, x, r, p, q, dinv, rtol, s)));
+    else
+      SPX_TRY((launch_persistent<1024, 256>(B, ps, bvec, x, r, p, q, dinv, rtol, s)));
+    SPX_CHECK_HIP(hipGetLastError());
+    SPX_TRY(true_residuals(B, run, bvec, x, s));
+    return finish(B, s, iters_out, relres_out, "batch_cg");
+  }
   double* P1 = B->partials;
   double* P2 = B->partials + G;
   const PlanView pl = run.pl;

@@ -26,6 +26,7 @@
 #include <mutex>
 #include <type_traits>
 
+#include "cg_one.hpp"
 #include "common.hpp"
 #include "device.hpp"
 #include "solver_core.hpp"
@@ -565,27 +566,11 @@ __global__ __launch_bounds__(kBlock) void k_pl_update(int64_t n, PlVectors v, Cg
 }
 
 // ------------------------------------------------ one-workgroup solve
-// Small systems: one workgroup of kOne threads runs the whole Jacobi-CG, so
-// no kernel is launched per iteration (the working set stays in L2).  The
-// recurrences, the order of the tests and the statuses are those of the
-// K1..K3 path; the SpMV is the same in-order stream walk over tiles of
-// ROWS rows (as many as LDS holds: a lone workgroup may use all of a CU's),
-// the dots are workgroup sums.
+// Small systems: one workgroup of kOne threads runs the whole Jacobi-CG
+// (cg_one.hpp), so no kernel is launched per iteration (the working set
+// stays in L2); tiles of ROWS rows, as many as LDS holds (a lone workgroup
+// may use all of a CU's).
 constexpr int kOne = 1024;
-
-// Workgroup sum returned to every thread (every thread adds the per-wave
-// sums in the same order).
-__device__ __forceinline__ double one_allsum(double v, double* lds) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) lds[w] = v;
-  __syncthreads();
-  double r = 0.0;
-#pragma unroll
-  for (int i = 0; i < kOne / 64; ++i) r += lds[i];
-  __syncthreads();
-  return r;
-}
 
 template <int ROWS>
 __global__ __launch_bounds__(kOne) void k_cg_one(int64_t n, const int32_t* __restrict__ rowptr,
@@ -597,99 +582,9 @@ __global__ __launch_bounds__(kOne) void k_cg_one(int64_t n, const int32_t* __res
                                                  const double* __restrict__ dinv, CgScalars* st,
                                                  double rtol) {
   extern __shared__ __align__(16) char smem[];
-  double* prod = reinterpret_cast<double*>(smem);
   __shared__ double lds[kOne / 64];
-  const int tid = threadIdx.x;
-  // r = b - A x; p = D^-1 r
-  double rz = 0.0, rr = 0.0, bb = 0.0;
-  for (int64_t r0 = 0; r0 < n; r0 += ROWS) {
-    const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
-    const double ax = stream_rows<kOne, 8, double, double, double, false>(rowptr, col, val, x, r0,
-                                                                          r1, prod);
-    if (tid < r1 - r0) {
-      const int64_t row = r0 + tid;
-      const double bi = b[row];
-      const double ri = bi - ax;
-      const double zi = dinv[row] * ri;
-      r[row] = ri;
-      p[row] = zi;
-      rz += ri * zi;
-      rr += ri * ri;
-      bb += bi * bi;
-    }
-  }
-  rz = one_allsum(rz, lds);
-  rr = one_allsum(rr, lds);
-  bb = one_allsum(bb, lds);
-  const double bnorm = sqrt(bb);
-  const double thresh = rtol * bnorm;
-  const int32_t maxit = st->maxit;
-  int32_t status = st->status, iters = 0;
-  double rho = rz, pq = 0.0;
-  bool done = true;
-  if (status != SPX_OK) {
-  } else if (sqrt(rr) <= thresh) {
-  } else if (maxit <= 0) {
-    status = SPX_NOT_CONVERGED;
-  } else {
-    done = false;
-  }
-  for (int32_t k = 1; !done; ++k) {
-    // q = A p; p.q
-    double pqs = 0.0;
-    for (int64_t r0 = 0; r0 < n; r0 += ROWS) {
-      const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
-      const double s = stream_rows<kOne, 8, double, double, double, false>(rowptr, col, val, p, r0,
-                                                                           r1, prod);
-      if (tid < r1 - r0) {
-        q[r0 + tid] = s;
-        pqs += p[r0 + tid] * s;
-      }
-    }
-    pq = one_allsum(pqs, lds);
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      status = SPX_BREAKDOWN;
-      iters = k - 1;
-      break;
-    }
-    const double alpha = rho / pq;
-    double rzs = 0.0, rrs = 0.0;
-    for (int64_t i = tid; i < n; i += kOne) {
-      const double xi = x[i] + alpha * p[i];
-      const double ri = r[i] - alpha * q[i];
-      const double zi = dinv[i] * ri;
-      x[i] = xi;
-      r[i] = ri;
-      rzs += ri * zi;
-      rrs += ri * ri;
-    }
-    rz = one_allsum(rzs, lds);
-    rr = one_allsum(rrs, lds);
-    iters = k;
-    if (sqrt(rr) <= thresh) {
-      status = SPX_OK;
-      break;
-    }
-    if (k >= maxit) {
-      status = SPX_NOT_CONVERGED;
-      break;
-    }
-    const double beta = rz / rho;
-    rho = rz;
-    for (int64_t i = tid; i < n; i += kOne) p[i] = dinv[i] * r[i] + beta * p[i];
-    __syncthreads();  // p is gathered by every thread in the next product
-  }
-  if (tid == 0) {
-    st->rho[0] = rho;
-    st->pq = pq;
-    st->rr = rr;
-    st->bb = bb;
-    st->bnorm = bnorm;
-    st->thresh = thresh;
-    st->iters = iters;
-    st->status = status;
-    st->done = 1;
-  }
+  one::cg_solve<kOne, ROWS>(n, rowptr, col, val, b, x, r, p, q, dinv, st->status, st->maxit, rtol,
+                            st, reinterpret_cast<double*>(smem), lds);
 }
 
 // ---------------------------------------------------- mixed precision

@@ -493,7 +493,7 @@ class BatchTuning(ctypes.Structure):
 
     _fields_ = [("blocks", ctypes.c_int32), ("rows_per_tile", ctypes.c_int32),
                 ("weight_exponent", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32)]
 
 
 class Batch:
@@ -525,13 +525,13 @@ class Batch:
             pass
 
     def _solve(self, fn, b, x, rtol, maxit, blocks, rows_per_tile, weight_exponent, check_every,
-               stream):
+               stream, persistent=0):
         _dev(b, torch.float64, self.total, "b")
         x = torch.zeros_like(b) if x is None else _dev(x, torch.float64, self.total, "x")
         ns = len(self.mats)
         iters = (ctypes.c_int64 * ns)()
         rel = (ctypes.c_double * ns)()
-        tune = BatchTuning(blocks, rows_per_tile, weight_exponent, check_every, 0)
+        tune = BatchTuning(blocks, rows_per_tile, weight_exponent, check_every, persistent)
         rc = fn(self._h, _ptr(b), _ptr(x), rtol, maxit,
                 ctypes.cast(ctypes.byref(tune), ctypes.c_void_p), _stream(stream),
                 ctypes.cast(iters, _pi64), ctypes.cast(rel, _pd))
@@ -539,10 +539,12 @@ class Batch:
         return x, list(iters), list(rel), rc
 
     def batch_cg(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
-                 weight_exponent=1.0, check_every=20, stream=None):
-        """Jacobi-CG on every system (SPD systems)."""
+                 weight_exponent=1.0, check_every=20, stream=None, persistent=0):
+        """Jacobi-CG on every system (SPD systems).  persistent: 1 for one
+        launch in which each workgroup solves whole systems taken from a
+        queue, -1 for one launch per phase, 0 to let the library choose."""
         return self._solve(load_library().spx_batch_cg, b, x, rtol, maxit, blocks, rows_per_tile,
-                           weight_exponent, check_every, stream)
+                           weight_exponent, check_every, stream, persistent)
 
     def batch_bicg(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
                    weight_exponent=1.0, check_every=20, stream=None):

@@ -1,5 +1,6 @@
-"""Batched Jacobi-CG (one launch per phase for all systems) and multi-RHS
-SpMM against the oracle."""
+"""Batched Jacobi-CG (one launch per phase for all systems, or one persistent
+launch with a workgroup per system) and multi-RHS SpMM against the
+oracle."""
 import math
 
 import numpy as np
@@ -81,6 +82,106 @@ def test_batched_status_per_system():
     assert st == spx.NOT_CONVERGED and iters[0] == 2
 
 
+@pytest.mark.parametrize("nsys,lo,hi,seed", [(40, 4, 40, 21), (7, 2, 70, 22), (1500, 3, 12, 23)])
+def test_batched_persistent(orc, nsys, lo, hi, seed):
+    """One launch for the whole batch, each workgroup solving whole systems
+    from a queue (largest first): every system against its own oracle
+    solve.  1500 systems exceed the resident workgroups, so workgroups take
+    several systems each; the smallest systems are 3x3 grids."""
+    spx = require_gpu()
+    probs, bs = W.config4(nsys=nsys, lo=lo, hi=hi, seed=seed)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    x, iters, relres, st = batch.batch_cg(bvec, rtol=1e-8, persistent=1)
+    assert st == 0
+    check_systems(orc, probs, bs, host(x), iters, relres, 1e-8)
+    # the launch-per-phase solve: the same iteration counts within 2, the
+    # same solutions within the solves' tolerance
+    x2, iters2, relres2, st2 = batch.batch_cg(bvec, rtol=1e-8, persistent=-1)
+    assert st2 == 0
+    assert max(abs(a - b) for a, b in zip(iters, iters2)) <= 2
+    xh, x2h = host(x), host(x2)
+    off = 0
+    for p in probs:
+        a, b2 = xh[off:off + p.n], x2h[off:off + p.n]
+        off += p.n
+        assert np.linalg.norm(a - b2) <= 1e-6 * np.linalg.norm(b2)
+
+
+def test_batched_persistent_statuses_and_guess():
+    """A zero diagonal stops only its own system; the iteration limit; a
+    second solve from the first one's solution stops at once."""
+    spx = require_gpu()
+    good = W.five_point_system(6, np.ones(30), np.ones(30), np.ones(24))
+    A = assemble(spx, good)
+    Z = spx.coo_preallocate(2, dev(np.array([0, 1, 1], np.int32)), dev(np.array([1, 0, 1], np.int32)))
+    Z.set_values_coo(dev(np.array([1.0, 1.0, 2.0])))
+    batch = spx.batch_create([A, Z, A])
+    b = dev(np.ones(74))
+    x, iters, relres, st = batch.batch_cg(b, rtol=1e-8, persistent=1)
+    assert st == spx.ZERO_DIAGONAL
+    assert relres[0] <= 1e-8 * 1.001 and relres[2] <= 1e-8 * 1.001 and iters[1] == 0
+    x2, iters2, relres2, st2 = batch.batch_cg(b, x=x.clone(), rtol=1e-6, persistent=1)
+    assert iters2[0] == 0 and iters2[2] == 0
+    batch2 = spx.batch_create([A])
+    x, iters, relres, st = batch2.batch_cg(dev(np.ones(36)), rtol=1e-14, maxit=2, persistent=1)
+    assert st == spx.NOT_CONVERGED and iters[0] == 2
+
+
+def test_batched_persistent_arguments():
+    spx = require_gpu()
+    A = assemble(spx, W.five_point_system(5, np.ones(20), np.ones(20), np.ones(20)))
+    batch = spx.batch_create([A])
+    with pytest.raises(spx.SpxError) as e:
+        batch.batch_cg(dev(np.ones(25)), persistent=2)
+    assert e.value.code == spx.INVALID_ARG
+    # 256 dense rows: a 256-row tile of 65,536 entries does not fit
+    n = 256
+    i = np.repeat(np.arange(n, dtype=np.int32), n)
+    j = np.tile(np.arange(n, dtype=np.int32), n)
+    v = np.where(i == j, float(n), -1.0 / n)
+    D = spx.coo_preallocate(n, dev(i), dev(j))
+    D.set_values_coo(dev(v))
+    batch = spx.batch_create([D])
+    with pytest.raises(spx.SpxError) as e:
+        batch.batch_cg(dev(np.ones(n)), persistent=1)
+    assert e.value.code == spx.INVALID_ARG
+    x, iters, relres, st = batch.batch_cg(dev(np.ones(n)), rtol=1e-10)
+    assert st == 0 and relres[0] <= 1e-10 * 1.001
+
+
+def test_autotune_takes_both_forms(orc):
+    """The tuner times the persistent form beside launch shapes of the
+    per-phase form and returns a working pick; on a batch the persistent
+    form cannot take (a 256-row tile beyond its LDS) that candidate is
+    skipped."""
+    spx = require_gpu()
+    probs, bs = W.config4(nsys=300, lo=4, hi=24, seed=31)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    cands = [autotune.Candidate(0, 0, 1.0, persistent=1), autotune.Candidate(1024, 0, 1.0),
+             autotune.Candidate(2048, 64, 1.0)]
+    best = autotune.tune_batch(batch, bvec, rtol=1e-8, candidates=cands)
+    print("autotune:", best, flush=True)
+    x, iters, relres, st = batch.batch_cg(bvec, rtol=1e-8, blocks=best["blocks"],
+                                          rows_per_tile=best["rows_per_tile"],
+                                          weight_exponent=best["weight_exponent"],
+                                          persistent=best["persistent"])
+    assert st == 0
+    check_systems(orc, probs[:20], bs[:20], host(x)[:sum(p.n for p in probs[:20])], iters[:20],
+                  relres[:20], 1e-8)
+    n = 256
+    i = np.repeat(np.arange(n, dtype=np.int32), n)
+    j = np.tile(np.arange(n, dtype=np.int32), n)
+    D = spx.coo_preallocate(n, dev(i), dev(j))
+    D.set_values_coo(dev(np.where(i == j, float(n), -1.0 / n)))
+    dense = spx.batch_create([D])
+    best = autotune.tune_batch(dense, dev(np.ones(n)), rtol=1e-10, candidates=cands)
+    assert best["persistent"] == -1
+
+
 @pytest.mark.timeout(900)
 def test_batched_full_config(orc):
     """The full 64-system batch (sides 32..512) to 1e-8, every system checked
@@ -101,7 +202,8 @@ def test_batched_full_config(orc):
     print("autotune:", best, flush=True)
     x2, iters2, relres2, st2 = batch.batch_cg(bvec, rtol=1e-8, blocks=best["blocks"],
                                               rows_per_tile=best["rows_per_tile"],
-                                              weight_exponent=best["weight_exponent"])
+                                              weight_exponent=best["weight_exponent"],
+                                              persistent=best["persistent"])
     assert st2 == 0 and max(relres2) <= 1e-8 * 1.001
 
 
