@@ -479,6 +479,37 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         log(f"batched small ({nsm} systems): persistent {ms_p:.2f} ms, per phase {ms_f:.2f} ms, "
             f"ensemble {ms_e:.2f} ms")
         del batch_s, mats_s, E_s
+        # the non-symmetric methods on as many convection-diffusion systems
+        probs_n, bs_n = W.config6(nsys=nsm, lo=lo_s, hi=hi_s, seed=6)
+        mats_n = [spx.coo_preallocate(p.n, d(p.i), d(p.j)) for p in probs_n]
+        for m, p in zip(mats_n, probs_n):
+            m.set_values_coo(d(p.v))
+        batch_n = spx.batch_create(mats_n)
+        bvec_n = d(np.concatenate(bs_n))
+        offs_n = np.cumsum([0] + [p.n for p in probs_n])
+        E_n = spx.coo_preallocate(int(offs_n[-1]),
+                                  d(np.concatenate([p.i + o for p, o in zip(probs_n, offs_n)]).astype(np.int32)),
+                                  d(np.concatenate([p.j + o for p, o in zip(probs_n, offs_n)]).astype(np.int32)))
+        E_n.set_values_coo(d(np.concatenate([p.v for p in probs_n])))
+        ens_n = spx.batch_create([E_n])
+        for method in ("tfqmr", "bicg"):
+            fn = "batch_" + method
+            getattr(batch_n, fn)(bvec_n, rtol=1e-8, persistent=-1)  # warm (BiCG builds the transposes)
+            ms_pn, (_, it_pn, rel_pn, st_pn) = timed(
+                lambda: getattr(batch_n, fn)(bvec_n, rtol=1e-8, persistent=1), reps=3)
+            ms_fn, (_, it_fn, rel_fn, st_fn) = timed(
+                lambda: getattr(batch_n, fn)(bvec_n, rtol=1e-8, persistent=-1), reps=3)
+            ms_en, (_, it_en, _, st_en) = timed(lambda: getattr(ens_n, fn)(bvec_n, rtol=1e-8), reps=2)
+            out["batched_small"][method] = {
+                "persistent_ms": round(ms_pn, 2), "persistent_status": st_pn,
+                "per_phase_ms": round(ms_fn, 2), "per_phase_status": st_fn,
+                "ensemble_ms": round(ms_en, 2), "ensemble_iters": it_en[0], "ensemble_status": st_en,
+                "max_relres": max(max(rel_pn), max(rel_fn)), "iters_max": max(it_pn),
+                "persistent_vs_per_phase": round(ms_fn / ms_pn, 2),
+                "persistent_vs_ensemble": round(ms_en / ms_pn, 2)}
+            log(f"batched small {method}: persistent {ms_pn:.2f} ms, per phase {ms_fn:.2f} ms, "
+                f"ensemble {ms_en:.2f} ms")
+        del batch_n, mats_n, E_n, ens_n
 
     # ---- 64-system non-symmetric batch: batched TFQMR / BiCG vs ensemble vs one per system
     if want("nonsymmetric_batch64"):

@@ -276,11 +276,12 @@ int spx_batch_total_rows(spx_batch_handle b, int64_t* total);
  *     proportional to nnz_s^weight_exponent, at least one (<= 0 means 1).
  *   check_every: iterations between host polls, at which the workgroups are
  *     re-split among the systems still running (0 means 20).
- *   persistent (spx_batch_cg only; ignored by BiCG and TFQMR): 1 asks for
- *     ONE launch for the whole solve, in which each workgroup (256 threads)
- *     takes the next system from a queue, largest first, and runs its whole
- *     Jacobi-CG alone (the fields above are then unused, and a system's
- *     largest 256-row tile must fit 64 KB of LDS, else SPX_INVALID_ARG);
+ *   persistent: 1 asks for ONE launch for the whole solve, in which each
+ *     workgroup (256 threads, 1024 when a system exceeds 1024 rows) takes
+ *     the next system from a queue, largest first, and runs the whole
+ *     method on it alone (the fields above are then unused, and a system's
+ *     largest 256-row tile, for BiCG also its transpose's, must fit 64 KB of
+ *     LDS, else SPX_INVALID_ARG);
  *     -1 asks for the launch-per-phase solve above; 0 lets the library
  *     choose (persistent for at least 256 systems of at most 8192 rows
  *     each). */

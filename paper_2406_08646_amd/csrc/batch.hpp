@@ -266,6 +266,56 @@ int poll_loop(spx_batch* B, Run& run, int64_t max_iters, hipStream_t s, Enq&& en
   return upload_plan(B, run.G, s);
 }
 
+// ------------------------------------------------------- persistent form
+// Shape of the persistent solve (one launch, each workgroup solving whole
+// systems from the queue): workgroup size, rows per tile and the dynamic LDS
+// for the products of the largest such tile of any system.  tile256 bounds
+// the entries of a 256-row tile of every matrix the solve walks; 512 and
+// 1024 rows take 2 and 4 of them.  256 threads for systems of at most 1024
+// rows (more systems in flight), 1024 above (each system faster); lds 0
+// when not even a 256-row tile fits 64 KB.
+struct PersistShape {
+  int block = 256, rows = 256;
+  size_t lds = 0;
+};
+inline PersistShape persistent_shape(const spx_batch* B, int64_t tile256) {
+  PersistShape ps;
+  int64_t max_n = 0;
+  for (const BatchSys& S : B->sys) max_n = std::max(max_n, S.n);
+  auto bytes = [&](int64_t tiles) { return (size_t)(tiles * tile256 + 8) * sizeof(double); };
+  if (bytes(1) > 64 * 1024) return ps;
+  if (max_n > 1024) {
+    ps.block = 1024;
+    ps.rows = bytes(4) <= 64 * 1024 ? 1024 : bytes(2) <= 64 * 1024 ? 512 : 256;
+  }
+  ps.lds = bytes(ps.rows / 256);
+  return ps;
+}
+
+// The persistent solve pays off when there are enough systems to keep the
+// workgroups busy and each is small enough for one workgroup: at least
+// kPersistAutoSystems systems, none above kPersistAutoRows rows.  Measured
+// with CG on 5-point batches (persistent vs one launch per phase): 4096
+// systems of 16-256 rows 6.5x, 1024 of 64-1024 rows 2.0x, 2048 of 256-4096
+// 1.8x, 256 of 1024-4096 1.2x, 1024 of 1024-8100 1.4x; 512 of 4096-16384
+// 0.91x, and 64 of 1024-262144 0.05x (the largest system alone on one
+// workgroup).
+constexpr int kPersistAutoSystems = 256;
+constexpr int64_t kPersistAutoRows = 8192;
+inline bool persistent_by_default(const spx_batch* B, const PersistShape& ps) {
+  if (B->nsys < kPersistAutoSystems || ps.lds == 0) return false;
+  for (const BatchSys& S : B->sys)
+    if (S.n > kPersistAutoRows) return false;
+  return true;
+}
+
+inline int persistent_mode(const spx_batch_tuning* tuning, const char* what, int32_t* mode) {
+  *mode = tuning ? tuning->persistent : 0;
+  if (*mode < -1 || *mode > 1)
+    return set_error(SPX_INVALID_ARG, "%s: persistent must be -1, 0 or 1", what);
+  return SPX_OK;
+}
+
 // Copies the final state out and folds the per-system statuses.
 inline int finish(spx_batch* B, hipStream_t s, int64_t* iters_out, double* relres_out,
                   const char* what) {
@@ -289,6 +339,10 @@ inline int finish(spx_batch* B, hipStream_t s, int64_t* iters_out, double* relre
 // ---------------------------------------------------------------- kernels
 // shared by every batched method (one copy per translation unit)
 namespace {
+
+__global__ void k_b_queue_reset(int32_t* queue) {
+  if (threadIdx.x == 0) queue[0] = 0;
+}
 
 __global__ void k_b_reset(CgScalars* st, int nsys, int32_t maxit) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;

@@ -172,10 +172,6 @@ __global__ __launch_bounds__(kBlock) void k_b_pupdate(const BatchSys* __restrict
 // D^-1 it writes included.  BLOCK = 256 for systems of at most 1024 rows
 // (more systems in flight), 1024 above (each system faster); tiles of ROWS
 // rows.
-__global__ void k_b_queue_reset(int32_t* queue) {
-  if (threadIdx.x == 0) queue[0] = 0;
-}
-
 template <int BLOCK, int ROWS>
 __global__ __launch_bounds__(BLOCK) void k_b_cg_persistent(
     const BatchSys* __restrict__ sys, int nsys, int32_t* __restrict__ queue,
@@ -219,44 +215,6 @@ using namespace spx::solver;
 using namespace spx::batch;
 
 namespace {
-// Shape of the persistent solve: workgroup size, rows per tile and the
-// dynamic LDS for the products of the largest such tile of any system
-// (max_tile[3] bounds a 256-row tile; 512 and 1024 rows take 2 and 4 of
-// them); lds 0 when not even a 256-row tile fits 64 KB.
-struct PersistShape {
-  int block = 256, rows = 256;
-  size_t lds = 0;
-};
-PersistShape persistent_shape(const spx_batch* B) {
-  PersistShape ps;
-  int64_t max_n = 0;
-  for (const BatchSys& S : B->sys) max_n = std::max(max_n, S.n);
-  auto bytes = [&](int64_t tiles) { return (size_t)(tiles * B->max_tile[3] + 8) * sizeof(double); };
-  if (bytes(1) > 64 * 1024) return ps;
-  if (max_n > 1024) {
-    ps.block = 1024;
-    ps.rows = bytes(4) <= 64 * 1024 ? 1024 : bytes(2) <= 64 * 1024 ? 512 : 256;
-  }
-  ps.lds = bytes(ps.rows / 256);
-  return ps;
-}
-
-// The persistent solve pays off when there are enough systems to keep the
-// workgroups busy and each is small enough for one workgroup: at least
-// kPersistAutoSystems systems, none above kPersistAutoRows rows.  Measured
-// on 5-point batches (persistent vs one launch per phase): 4096 systems of
-// 16-256 rows 6.5x, 1024 of 64-1024 rows 2.0x, 2048 of 256-4096 1.8x, 256
-// of 1024-4096 1.2x, 1024 of 1024-8100 1.4x; 512 of 4096-16384 0.91x, and
-// 64 of 1024-262144 0.05x (the largest system alone on one workgroup).
-constexpr int kPersistAutoSystems = 256;
-constexpr int64_t kPersistAutoRows = 8192;
-bool persistent_by_default(const spx_batch* B) {
-  if (B->nsys < kPersistAutoSystems || persistent_shape(B).lds == 0) return false;
-  for (const BatchSys& S : B->sys)
-    if (S.n > kPersistAutoRows) return false;
-  return true;
-}
-
 template <int BLOCK, int ROWS>
 int launch_persistent(spx_batch* B, const PersistShape& ps, const double* bvec, double* x,
                       double* r, double* p, double* q, double* dinv, double rtol, hipStream_t s) {
@@ -376,8 +334,8 @@ extern "C" int spx_batch_cg(spx_batch_handle B, const double* bvec, double* x, d
   if (maxit > INT32_MAX - 1) maxit = INT32_MAX - 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int ns = B->nsys;
-  const int32_t pmode = tuning ? tuning->persistent : 0;
-  if (pmode < -1 || pmode > 1) return set_error(SPX_INVALID_ARG, "batch_cg: persistent must be -1, 0 or 1");
+  int32_t pmode = 0;
+  SPX_TRY(persistent_mode(tuning, "batch_cg", &pmode));
   Run run;
   SPX_TRY(prepare(B, tuning, B->max_tile, B->max_row, B->win_blocks, 3, s, &run));
   const int G = run.G;
@@ -386,8 +344,8 @@ extern "C" int spx_batch_cg(spx_batch_handle B, const double* bvec, double* x, d
   double* p = B->work + tot;
   double* q = B->work + 2 * tot;
   double* dinv = B->work + 3 * tot;
-  if (pmode == 1 || (pmode == 0 && persistent_by_default(B))) {
-    const PersistShape ps = persistent_shape(B);
+  const PersistShape ps = persistent_shape(B, B->max_tile[3]);
+  if (pmode == 1 || (pmode == 0 && persistent_by_default(B, ps))) {
     if (ps.lds == 0)
       return set_error(SPX_INVALID_ARG,
                        "batch_cg: a 256-row tile of a system exceeds the persistent solve's LDS");

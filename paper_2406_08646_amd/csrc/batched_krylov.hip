@@ -30,10 +30,12 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "batch.hpp"
 #include "common.hpp"
+#include "krylov_one.hpp"
 #include "device.hpp"
 #include "solver_core.hpp"
 #include "spmv_core.hpp"
@@ -576,6 +578,104 @@ __global__ __launch_bounds__(kBlock) void k_tq_verify_finish(PlanView pl, CgScal
 
 constexpr int32_t kTfqmrMaxRestarts = 8;
 
+// ------------------------------------------------------- persistent form
+// One launch for the whole batch: each workgroup takes the next system from
+// the queue (largest first) and runs BiCG (METHOD 1) or TFQMR (METHOD 2) on
+// it alone (krylov_one.hpp), D^-1 included; thread t owns rows t, t + BLOCK,
+// ... of every pass.  No workgroup waits for another.
+template <int METHOD, int BLOCK, int ROWS>
+__global__ __launch_bounds__(BLOCK) void k_bk_persistent(
+    const BatchSys* __restrict__ sys, const BatchSys* __restrict__ sysT, int nsys,
+    int32_t* __restrict__ queue, const double* __restrict__ bvec, double* __restrict__ x,
+    double* __restrict__ kw, int64_t tot, CgScalars* st, double rtol) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double lds[BLOCK / 64];
+  __shared__ int32_t pick, zero;
+  double* dinv = kw + (METHOD == 1 ? 6 : 8) * tot;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      pick = atomicAdd(queue, 1);
+      zero = 0;
+    }
+    __syncthreads();
+    const int32_t k = pick;
+    if (k >= nsys) break;
+    const int s = queue[1 + k];
+    const BatchSys S = sys[s];
+    const int64_t o = S.off;
+    for (int64_t i = threadIdx.x; i < S.n; i += BLOCK) {
+      const int32_t t = S.dpos[i];
+      const double d = t >= 0 ? S.val[t] : 0.0;
+      if (d == 0.0) zero = 1;
+      dinv[o + i] = d == 0.0 ? 0.0 : 1.0 / d;
+    }
+    __syncthreads();
+    const int32_t status0 = zero ? SPX_ZERO_DIAGONAL : SPX_OK;
+    const one::Csr3 A{S.rowptr, S.col, S.val};
+    double* prod = reinterpret_cast<double*>(smem);
+    if constexpr (METHOD == 1) {
+      const BatchSys T = sysT[s];
+      one::bicg_solve<BLOCK, ROWS>(S.n, A, one::Csr3{T.rowptr, T.col, T.val}, bvec + o, x + o,
+                                   kw + o, kw + tot + o, kw + 2 * tot + o, kw + 3 * tot + o,
+                                   kw + 4 * tot + o, kw + 5 * tot + o, dinv + o, status0,
+                                   st[s].maxit, rtol, st + s, prod, lds);
+    } else {
+      const one::TqVectors V{kw + o,           kw + tot + o,     kw + 2 * tot + o,
+                             kw + 3 * tot + o, kw + 4 * tot + o, kw + 5 * tot + o,
+                             kw + 6 * tot + o, kw + 7 * tot + o};
+      one::tfqmr_solve<BLOCK, ROWS>(S.n, A, bvec + o, x + o, V, dinv + o, status0, st[s].maxit,
+                                    kTfqmrMaxRestarts, rtol, st + s, prod, lds);
+    }
+    __syncthreads();  // `pick` and `zero` read by every thread before thread 0 rewrites them
+  }
+}
+
+// Runs the persistent form of METHOD when the caller asks for it or the
+// library picks it; *ran tells which.
+template <int METHOD>
+int maybe_persistent(spx_batch* B, const spx_batch_tuning* tuning, int64_t tile256,
+                     const double* bvec, double* x, double rtol, int64_t maxit, hipStream_t s,
+                     const char* what, bool* ran) {
+  *ran = false;
+  int32_t mode = 0;
+  SPX_TRY(persistent_mode(tuning, what, &mode));
+  const PersistShape ps = persistent_shape(B, tile256);
+  if (!(mode == 1 || (mode == 0 && persistent_by_default(B, ps)))) return SPX_OK;
+  if (ps.lds == 0)
+    return set_error(SPX_INVALID_ARG,
+                     "%s: a 256-row tile of a system exceeds the persistent solve's LDS", what);
+  const int ns = B->nsys;
+  hipLaunchKernelGGL(k_b_reset, dim3((unsigned)ceil_div(ns, 64)), dim3(64), 0, s, B->d_st, ns,
+                     (int32_t)maxit);
+  hipLaunchKernelGGL(k_b_queue_reset, dim3(1), dim3(64), 0, s, B->d_queue);
+  auto launch = [&](auto blk, auto rws) {
+    constexpr int BLOCK = decltype(blk)::value, ROWS = decltype(rws)::value;
+    const void* fn = reinterpret_cast<const void*>(&k_bk_persistent<METHOD, BLOCK, ROWS>);
+    int fit = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, fn, BLOCK, ps.lds) != hipSuccess ||
+        fit < 1)
+      fit = 1;
+    const int G = (int)std::min<int64_t>(ns, (int64_t)cu_count() * fit);
+    hipLaunchKernelGGL((k_bk_persistent<METHOD, BLOCK, ROWS>), dim3((unsigned)G), dim3(BLOCK),
+                       ps.lds, s, B->d_sys, B->d_sysT, ns, B->d_queue, bvec, x, B->kwork,
+                       B->total, B->d_st, rtol);
+  };
+  using I256 = std::integral_constant<int, 256>;
+  using I512 = std::integral_constant<int, 512>;
+  using I1024 = std::integral_constant<int, 1024>;
+  if (ps.block == 256)
+    launch(I256(), I256());
+  else if (ps.rows == 1024)
+    launch(I1024(), I1024());
+  else if (ps.rows == 512)
+    launch(I1024(), I512());
+  else
+    launch(I1024(), I256());
+  SPX_CHECK_HIP(hipGetLastError());
+  *ran = true;
+  return SPX_OK;
+}
+
 // -------------------------------------------------------------- host side
 
 int ensure_kwork(spx_batch* B) {
@@ -630,6 +730,12 @@ extern "C" int spx_batch_bicg(spx_batch_handle B, const double* bvec, double* x,
                          ? std::max(B->win_blocks, B->win_blocks_t)
                          : -1;
   SPX_TRY(prepare(B, tuning, tiles, max_row, wb, 3, s, &run));
+  bool ran = false;
+  SPX_TRY(maybe_persistent<1>(B, tuning, tiles[3], bvec, x, rtol, maxit, s, "batch_bicg", &ran));
+  if (ran) {
+    SPX_TRY(true_residuals(B, run, bvec, x, s));
+    return finish(B, s, iters_out, relres_out, "batch_bicg");
+  }
   const int G = run.G;
   const int64_t tot = B->total;
   double* r = B->kwork;
@@ -687,6 +793,13 @@ extern "C" int spx_batch_tfqmr(spx_batch_handle B, const double* bvec, double* x
   SPX_TRY(ensure_kwork(B));
   Run run;
   SPX_TRY(prepare(B, tuning, B->max_tile, B->max_row, B->win_blocks, 4, s, &run));
+  bool ran = false;
+  SPX_TRY(maybe_persistent<2>(B, tuning, B->max_tile[3], bvec, x, rtol, maxit, s, "batch_tfqmr",
+                              &ran));
+  if (ran) {
+    SPX_TRY(true_residuals(B, run, bvec, x, s));
+    return finish(B, s, iters_out, relres_out, "batch_tfqmr");
+  }
   const int G = run.G;
   const int64_t tot = B->total;
   double* kw = B->kwork;

@@ -547,18 +547,19 @@ class Batch:
                            weight_exponent, check_every, stream, persistent)
 
     def batch_bicg(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
-                   weight_exponent=1.0, check_every=20, stream=None):
-        """Jacobi-preconditioned BiCG on every system (iterations: BiCG steps)."""
+                   weight_exponent=1.0, check_every=20, stream=None, persistent=0):
+        """Jacobi-preconditioned BiCG on every system (iterations: BiCG steps);
+        persistent as in batch_cg."""
         return self._solve(load_library().spx_batch_bicg, b, x, rtol, maxit, blocks,
-                           rows_per_tile, weight_exponent, check_every, stream)
+                           rows_per_tile, weight_exponent, check_every, stream, persistent)
 
     def batch_tfqmr(self, b, x=None, rtol=1e-8, maxit=100000, blocks=0, rows_per_tile=0,
-                    weight_exponent=1.0, check_every=20, stream=None):
+                    weight_exponent=1.0, check_every=20, stream=None, persistent=0):
         """Right-Jacobi TFQMR on every system (iterations: half-steps, one
         product with A each; maxit counts half-steps, check_every full
-        iterations of two half-steps)."""
+        iterations of two half-steps); persistent as in batch_cg."""
         return self._solve(load_library().spx_batch_tfqmr, b, x, rtol, maxit, blocks,
-                           rows_per_tile, weight_exponent, check_every, stream)
+                           rows_per_tile, weight_exponent, check_every, stream, persistent)
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

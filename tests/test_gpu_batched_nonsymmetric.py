@@ -1,6 +1,7 @@
 """Batched BiCG and TFQMR with diagonal preconditioning (one launch per phase
-for all systems) on non-symmetric convection-diffusion batches, against the
-oracle's BiCG and TFQMR."""
+for all systems, or one persistent launch with a workgroup per system) on
+non-symmetric convection-diffusion batches, against the oracle's BiCG and
+TFQMR."""
 import math
 
 import numpy as np
@@ -183,3 +184,87 @@ def test_nonsymmetric_batch_full_config(orc, method):
     print("iterations:", iters, flush=True)
     assert st == 0
     check_systems(orc, probs, bs, host(x), iters, relres, 1e-8, method, oracle_upto=65536)
+
+
+# ------------------------------------------------------------ persistent form
+# One launch for the whole batch, each workgroup running the method on whole
+# systems taken from a queue (largest first).
+
+@pytest.mark.parametrize("method", ["bicg", "tfqmr"])
+@pytest.mark.parametrize("nsys,lo,hi,seed", [(5, 4, 24, 21), (7, 2, 70, 27), (1500, 3, 12, 28)])
+def test_nonsymmetric_batch_persistent(orc, method, nsys, lo, hi, seed):
+    """Every system against its own oracle solve; 1500 systems exceed the
+    resident workgroups, so each workgroup takes several."""
+    spx = require_gpu()
+    probs, bs = W.config6(nsys=nsys, lo=lo, hi=hi, seed=seed)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    fn = batch.batch_bicg if method == "bicg" else batch.batch_tfqmr
+    x, iters, relres, st = fn(bvec, rtol=1e-8, persistent=1)
+    assert st == 0
+    check_systems(orc, probs, bs, host(x), iters, relres, 1e-8, method)
+
+
+@pytest.mark.parametrize("method", ["bicg", "tfqmr"])
+def test_persistent_iterates_follow_the_oracle_step_by_step(orc, method):
+    spx = require_gpu()
+    probs, bs = W.config6(nsys=3, lo=40, hi=90, seed=26)
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    bvec = dev(np.concatenate(bs))
+    fn = batch.batch_bicg if method == "bicg" else batch.batch_tfqmr
+    solver = orc.bicg if method == "bicg" else orc.tfqmr
+    for k in (1, 2, 5, 10, 20):
+        x, iters, relres, st = fn(bvec, rtol=0.0, maxit=k, persistent=1)
+        assert st == spx.NOT_CONVERGED and all(i == k for i in iters)
+        xs = host(x)
+        off = 0
+        for p, b in zip(probs, bs):
+            ref = solver(orc.assemble(p.n, p.i, p.j, p.v), b, 0.0, k)
+            err = np.linalg.norm(xs[off:off + p.n] - ref.x) / np.linalg.norm(ref.x)
+            off += p.n
+            assert err <= 1e-10 * k, (method, k, err)
+
+
+def test_persistent_tfqmr_restarts_when_the_bound_passes_early(orc):
+    spx = require_gpu()
+    probs, bs = W.config6()
+    p, b = probs[20], bs[20]
+    batch = spx.batch_create([assemble(spx, p)])
+    x, iters, relres, st = batch.batch_tfqmr(dev(b), rtol=1e-8, persistent=1)
+    A = orc.assemble(p.n, p.i, p.j, p.v)
+    ref = orc.tfqmr(A, b, 1e-8)
+    print(f"restart case (persistent): gpu {iters[0]} half-steps relres {relres[0]:.3e}; "
+          f"oracle {ref.iters}", flush=True)
+    assert st == 0
+    assert np.linalg.norm(b - orc.spmv(A, host(x))) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-3)
+    assert abs(iters[0] - ref.iters) <= max(4, math.ceil(0.10 * ref.iters))
+
+
+def test_persistent_nonsymmetric_statuses():
+    spx = require_gpu()
+    good = W.convection_diffusion_system(6, np.ones(30), np.ones(30), np.ones(24), 1.0, -0.5)
+    A = assemble(spx, good)
+    Z = spx.coo_preallocate(2, dev(np.array([0, 1, 1], np.int32)), dev(np.array([1, 0, 1], np.int32)))
+    Z.set_values_coo(dev(np.array([1.0, 1.0, 2.0])))
+    Bk = spx.coo_preallocate(2, dev(np.array([0, 0, 1, 1], np.int32)),
+                             dev(np.array([0, 1, 0, 1], np.int32)))
+    Bk.set_values_coo(dev(np.array([1.0, -3.0, 1.0, 1.0])))
+    batch = spx.batch_create([A, Z, Bk])
+    b = dev(np.ones(40))
+    for fn in ("batch_bicg", "batch_tfqmr"):
+        x, iters, relres, st = getattr(batch, fn)(b, rtol=1e-8, persistent=1)
+        assert st == spx.BREAKDOWN or st == spx.ZERO_DIAGONAL
+        assert relres[0] <= 1e-8 * 1.01 and iters[1] == 0 and iters[2] == 0
+    one = spx.batch_create([A])
+    x, iters, relres, st = one.batch_tfqmr(dev(np.ones(36)), rtol=1e-14, maxit=5, persistent=1)
+    assert st == spx.NOT_CONVERGED and iters[0] == 5
+    x, iters, relres, st = one.batch_bicg(dev(np.ones(36)), rtol=1e-14, maxit=3, persistent=1)
+    assert st == spx.NOT_CONVERGED and iters[0] == 3
+    for fn in (one.batch_bicg, one.batch_tfqmr):
+        x, iters, relres, st = fn(dev(np.zeros(36)), rtol=1e-8, persistent=1)
+        assert st == 0 and iters[0] == 0 and np.all(host(x) == 0)
+    with pytest.raises(spx.SpxError) as e:
+        one.batch_tfqmr(dev(np.ones(36)), persistent=-2)
+    assert e.value.code == spx.INVALID_ARG
