@@ -109,6 +109,33 @@ def test_batched_persistent(orc, nsys, lo, hi, seed):
         assert np.linalg.norm(a - b2) <= 1e-6 * np.linalg.norm(b2)
 
 
+def test_batched_persistent_27_point_systems(orc):
+    """3-D Q1 systems (27-entry rows, up to 13,824 rows, so 1024-thread
+    workgroups with 256-row tiles) with log-normal coefficients, one
+    persistent launch, every system against the oracle's CG."""
+    spx = require_gpu()
+    rng = np.random.default_rng(41)
+    probs, bs = [], []
+    for N in (2, 3, 5, 8, 11, 23):
+        p = W.q1_poisson(N, 3, kappa=np.exp(rng.standard_normal(N**3)))
+        probs.append(p)
+        bs.append(rng.uniform(-1, 1, p.n))
+    mats = [assemble(spx, p) for p in probs]
+    batch = spx.batch_create(mats)
+    x, iters, relres, st = batch.batch_cg(dev(np.concatenate(bs)), rtol=1e-9, persistent=1)
+    assert st == 0
+    xh = host(x)
+    off = 0
+    for s_, (p, b) in enumerate(zip(probs, bs)):
+        A = orc.assemble(p.n, p.i, p.j, p.v)
+        ref = orc.pcg(A, b, 1e-9)
+        xs = xh[off:off + p.n]
+        off += p.n
+        assert ref.status == 0 and relres[s_] <= 1e-9 * (1 + 1e-3)
+        assert np.linalg.norm(b - orc.spmv(A, xs)) <= 1e-9 * np.linalg.norm(b) * (1 + 1e-3)
+        assert abs(iters[s_] - ref.iters) <= max(2, math.ceil(0.01 * ref.iters)), (s_, iters[s_], ref.iters)
+
+
 def test_batched_persistent_statuses_and_guess():
     """A zero diagonal stops only its own system; the iteration limit; a
     second solve from the first one's solution stops at once."""
