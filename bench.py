@@ -206,6 +206,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         A = main_matrix()
         X = d(W.spmm_rhs(prob.n, 16))
         Y = torch.empty_like(X)
+        spmm_tune = autotune.tune_spmm(A, X)
         for _ in range(3):
             A.spmm(X, Y)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
@@ -225,14 +226,19 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         torch.cuda.synchronize()
         mv_ms = statistics.median(s_.elapsed_time(e_) for s_, e_ in ev)
         # what the staged kernel reads: values and 2-byte list positions per
-        # entry, row bounds, one 320-int list per 32-row tile, X and Y
-        spmm_format_bytes = (nnz * 10 + (prob.n + 1) * 4 + (prob.n + 31) // 32 * 1280
+        # entry, row bounds, one list per tile (192, 320 or 640 ints for 16-,
+        # 32- and 64-row tiles), X and Y
+        tr = spmm_tune["rows"]
+        list_ints = {16: 192, 32: 320, 64: 640}[tr]
+        spmm_format_bytes = (nnz * 10 + (prob.n + 1) * 4 + (prob.n + tr - 1) // tr * 4 * list_ints
                              + 2 * 16 * 8 * prob.n)
         out["spmm16"] = {"ms": round(spmm_ms, 4), "bytes": spmm_bytes,
                          "gbs": round(spmm_bytes / (spmm_ms * 1e-3) / 1e9, 1),
                          "format_bytes": spmm_format_bytes,
                          "format_gbs": round(spmm_format_bytes / (spmm_ms * 1e-3) / 1e9, 1),
                          "kernel": "k_spmm_rowset",
+                         "tile_rows": spmm_tune["rows"],
+                         "tile_rows_ms": {str(k): round(v, 4) for k, v in spmm_tune["all"].items()},
                          "vs_16_spmv": round(16 * mv_ms / spmm_ms, 2)}
         log(f"spmm16: {spmm_ms:.3f} ms")
         del X, Y

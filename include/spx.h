@@ -542,7 +542,13 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *     right-hand side.  1: it also stops once its residual is at most
  *     rtol_outer ||b|| / 2, so the last refinement step does no more inner
  *     iterations than the outer target needs (a reading of the Sec. 2 plan,
- *     which names no inner tolerance). */
+ *     which names no inner tolerance).
+ *   SPX_OPT_SPMM_TILE_ROWS: rows per tile of the staged 16-column product
+ *     of spx_spmm (16, 32 or 64; 0 = default 32): each tile's distinct rows
+ *     of X are staged in LDS, so the height trades the rows of X staged per
+ *     matrix row against the workgroups that fit per CU.  The tiles' index
+ *     is rebuilt on the next product after a change.  Results are the same
+ *     bits at every height. */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,
@@ -558,7 +564,8 @@ enum spx_option {
   SPX_OPT_CG_VARIANT = 12,
   SPX_OPT_GRAPH = 13,
   SPX_OPT_SMALL_SOLVE = 14,
-  SPX_OPT_IR_EARLY_EXIT = 15
+  SPX_OPT_IR_EARLY_EXIT = 15,
+  SPX_OPT_SPMM_TILE_ROWS = 16
 };
 int spx_set_option(spx_handle h, int32_t option, int64_t value);
 int spx_get_option(spx_handle h, int32_t option, int64_t* value);

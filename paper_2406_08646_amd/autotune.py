@@ -1,4 +1,5 @@
-"""Launch-shape autotuner for the batched solver.
+"""Launch-shape autotuners: the batched solver's launch form and shape, and
+the tile height of the staged 16-column SpMM.
 
 The batched Jacobi-CG (``spx_batch_cg``) has two launch forms: one launch
 per CG phase for the whole batch, or one persistent launch in which each
@@ -104,3 +105,38 @@ def tune_batch(batch: "spx.Batch", b: torch.Tensor, rtol: float = 1e-8, maxit: i
         with open(cache_file, "w") as f:
             json.dump(disk, f, indent=1)
     return best
+
+
+def tune_spmm(A: "spx.Matrix", X: torch.Tensor, candidates: Iterable[int] = (16, 32, 64),
+              repeats: int = 5, verbose: bool = False) -> dict:
+    """Tile height of the staged 16-column product (``OPT_SPMM_TILE_ROWS``):
+    times ``repeats`` products of the actual matrix with X at each height
+    (the first product at a height builds that height's index and is not
+    timed), leaves the fastest set on A and returns ``{"rows", "ms",
+    "all"}``.  Every height gives the same bits, so only time decides.
+    Cached in memory per (device, matrix shape)."""
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    key = f"spmm|{props.name}|{A.n}|{A.nnz}|{tuple(candidates)}"
+    if key in _MEMO:
+        A.set_option(spx.OPT_SPMM_TILE_ROWS, _MEMO[key]["rows"])
+        return _MEMO[key]
+    Y = torch.empty_like(X)
+    times = {}
+    for rows in candidates:
+        A.set_option(spx.OPT_SPMM_TILE_ROWS, rows)
+        A.spmm(X, Y)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(repeats)]
+        for s, e in ev:
+            s.record()
+            A.spmm(X, Y)
+            e.record()
+        torch.cuda.synchronize()
+        times[rows] = min(s.elapsed_time(e) for s, e in ev)
+        if verbose:
+            print(f"[autotune] spmm tile rows {rows} -> {times[rows]:.4f} ms", flush=True)
+    best = min(times, key=times.get)
+    A.set_option(spx.OPT_SPMM_TILE_ROWS, best)
+    _MEMO[key] = {"rows": best, "ms": times[best], "all": times}
+    return _MEMO[key]

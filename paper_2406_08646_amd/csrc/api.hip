@@ -227,6 +227,11 @@ extern "C" int spx_set_option(spx_handle h, int32_t option, int64_t value) {
     case SPX_OPT_IR_EARLY_EXIT:
       h->ir_early_exit = value ? 1 : 0;
       return SPX_OK;
+    case SPX_OPT_SPMM_TILE_ROWS:
+      if (value != 0 && value != 16 && value != 32 && value != 64)
+        return set_error(SPX_INVALID_ARG, "set_option: SpMM tile height must be 0, 16, 32 or 64");
+      h->spmm_rows_opt = (int)value;
+      return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "set_option: unknown option %d", option);
   }
@@ -280,6 +285,9 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
       return SPX_OK;
     case SPX_OPT_IR_EARLY_EXIT:
       *value = h->ir_early_exit;
+      return SPX_OK;
+    case SPX_OPT_SPMM_TILE_ROWS:
+      *value = h->spmm_rows_opt ? h->spmm_rows_opt : 32;
       return SPX_OK;
     default:
       return set_error(SPX_INVALID_ARG, "get_option: unknown option %d", option);

@@ -101,19 +101,16 @@ struct Window {
   int64_t gather_entries = 0;  // entries of tiles without a window
 };
 
-// Rows of X a tile of kRsRows consecutive rows of the matrix touches, for
-// the 16-column product (spmm.hip): tile b's list at col + b * kRsStride
-// holds its number of distinct columns, then those columns ascending, and
-// lidx holds each entry's position in its tile's list.  A tile with more
-// than kRsCap entries or kRsMax distinct columns has the count -1 and is
-// gathered directly.  kRsMax rows of X and one row of zeros fill 40 KB.
-constexpr int kRsRows = 32;
-constexpr int kRsCap = 1024;
-constexpr int kRsMax = 319;
-constexpr int kRsStride = kRsMax + 1;
+// Rows of X a tile of `rows` consecutive rows of the matrix touches, for
+// the 16-column product (spmm.hip): tile b's list holds its number of
+// distinct columns, then those columns ascending, at a fixed stride; lidx
+// holds each entry's position in its tile's list.  A tile with more entries
+// or distinct columns than its kernel stages has the count -1 and is
+// gathered directly.
 struct RowSet {
-  int32_t* col = nullptr;    // [tiles * kRsStride] count, then the columns
+  int32_t* col = nullptr;    // [tiles * stride] count, then the columns
   uint16_t* lidx = nullptr;  // [nnz] entry t's position in its tile's list
+  int rows = 0;              // tile height the lists were built for
   bool built = false;
 };
 
@@ -224,6 +221,7 @@ struct spx_matrix {
   int graph_opt = 0;
   int small_opt = 1;  // one-workgroup solve: 0 never, 1 small systems, 2 whenever it fits
   int ir_early_exit = 0;  // refinement: 1 also ends an inner solve at rtol_outer ||b|| / 2
+  int spmm_rows_opt = 0;  // tile height of the staged 16-column product, 0 = 32
   hipStream_t cap_stream = nullptr;
   struct GraphCache {
     hipGraphExec_t exec = nullptr;
@@ -264,7 +262,7 @@ int launch_spmm(const Csr& A, int64_t nrhs, const double* X, int64_t ldx, double
                 hipStream_t s);
 // spmm.hip: the row-set index of A (once) and the 16-column product that
 // stages each tile's rows of X in LDS (X and Y contiguous, 16-byte aligned)
-int build_rowset(Csr& A, hipStream_t s);
+int build_rowset(Csr& A, int rows, hipStream_t s);
 int launch_spmm_rowset(const Csr& A, const double* X, double* Y, hipStream_t s);
 // cg.hip
 int fused_blocks(const spx_matrix* h);

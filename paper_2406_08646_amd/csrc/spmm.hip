@@ -13,7 +13,8 @@
 // built once per pattern on the first such product.
 //
 // Each row's products are added in entry order from +0.0, as the pair
-// kernels do, so the results are bitwise theirs.
+// kernels do, so the results are bitwise theirs, at every tile height
+// (16, 32 or 64 rows; SPX_OPT_SPMM_TILE_ROWS, 32 by default).
 #include <algorithm>
 
 #include "common.hpp"
@@ -22,20 +23,37 @@
 namespace spx {
 namespace {
 
-constexpr int kRsBlock = 256;  // threads of the index builder
-static_assert(kRsCap % kRsBlock == 0, "whole sort steps");
-constexpr int kRsIpt = kRsCap / kRsBlock;
+// Tile shapes: entries a tile may hold (the index builder sorts that many
+// columns in LDS) and distinct columns it may stage (kMax rows of X and a
+// row of zeros: 24, 40 and 80 KB of LDS).
+template <int ROWS>
+struct RsShape;
+template <>
+struct RsShape<16> {
+  static constexpr int kCap = 1024, kMax = 191;
+};
+template <>
+struct RsShape<32> {
+  static constexpr int kCap = 1024, kMax = 319;
+};
+template <>
+struct RsShape<64> {
+  static constexpr int kCap = 2048, kMax = 639;
+};
 
-// The tile's columns (m <= kRsCap of them, from entry e0) in LDS, sorted
+constexpr int kRsBlock = 256;  // threads of the index builder
+
+// The tile's columns (m <= CAP of them, from entry e0) in LDS, sorted
 // ascending; the slots after m hold INT32_MAX.
+template <int CAP>
 __device__ __forceinline__ void rs_sorted_columns(const int32_t* __restrict__ col, int32_t e0,
                                                   int m, int32_t* keys) {
-  for (int i = threadIdx.x; i < kRsCap; i += kRsBlock) keys[i] = i < m ? col[e0 + i] : INT32_MAX;
+  for (int i = threadIdx.x; i < CAP; i += kRsBlock) keys[i] = i < m ? col[e0 + i] : INT32_MAX;
   __syncthreads();
-  // bitonic network over kRsCap keys
-  for (int k = 2; k <= kRsCap; k <<= 1) {
+  // bitonic network over CAP keys
+  for (int k = 2; k <= CAP; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < kRsCap; i += kRsBlock) {
+      for (int i = threadIdx.x; i < CAP; i += kRsBlock) {
         const int p = i ^ j;
         if (p > i) {
           const int32_t a = keys[i], b = keys[p];
@@ -56,30 +74,34 @@ __device__ __forceinline__ bool rs_first(const int32_t* keys, int i) {
 }
 
 // The list of tile b (count, then the distinct columns) at ucol + b *
-// kRsStride and every entry's position in it; the count -1 for a tile that
+// (kMax + 1) and every entry's position in it; the count -1 for a tile that
 // is gathered instead.
+template <int ROWS>
 __global__ __launch_bounds__(kRsBlock) void k_rs_build(int64_t n, const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ col,
                                                        int32_t* __restrict__ ucol,
                                                        uint16_t* __restrict__ lidx) {
-  __shared__ int32_t keys[kRsCap];
-  __shared__ int32_t list[kRsMax];
+  constexpr int CAP = RsShape<ROWS>::kCap, MAX = RsShape<ROWS>::kMax;
+  static_assert(CAP % kRsBlock == 0, "whole sort steps");
+  constexpr int IPT = CAP / kRsBlock;
+  __shared__ int32_t keys[CAP];
+  __shared__ int32_t list[MAX];
   __shared__ int32_t wsum[kRsBlock / 64];
-  const int64_t b = blockIdx.x, r0 = b * kRsRows;
-  const int64_t r1 = r0 + kRsRows < n ? r0 + kRsRows : n;
-  int32_t* out = ucol + b * kRsStride;
+  const int64_t b = blockIdx.x, r0 = b * ROWS;
+  const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
+  int32_t* out = ucol + b * (MAX + 1);
   const int32_t e0 = rowptr[r0];
   const int m = rowptr[r1] - e0;
-  if (m > kRsCap) {
+  if (m > CAP) {
     if (threadIdx.x == 0) out[0] = -1;
     return;
   }
-  rs_sorted_columns(col, e0, m, keys);
-  // rank of every first occurrence: thread t owns kRsIpt consecutive keys
-  const int i0 = threadIdx.x * kRsIpt;
+  rs_sorted_columns<CAP>(col, e0, m, keys);
+  // rank of every first occurrence: thread t owns IPT consecutive keys
+  const int i0 = threadIdx.x * IPT;
   int firsts = 0;
 #pragma unroll
-  for (int u = 0; u < kRsIpt; ++u) firsts += rs_first(keys, i0 + u) ? 1 : 0;
+  for (int u = 0; u < IPT; ++u) firsts += rs_first(keys, i0 + u) ? 1 : 0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int inc = firsts;
 #pragma unroll
@@ -94,13 +116,13 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_build(int64_t n, const int32_t*
     if (ww < w) rank += wsum[ww];
     d += wsum[ww];
   }
-  if (d > kRsMax) {
+  if (d > MAX) {
     if (threadIdx.x == 0) out[0] = -1;
     return;
   }
   if (threadIdx.x == 0) out[0] = d;
 #pragma unroll
-  for (int u = 0; u < kRsIpt; ++u) {
+  for (int u = 0; u < IPT; ++u) {
     if (rs_first(keys, i0 + u)) {
       list[rank] = keys[i0 + u];
       out[1 + rank] = keys[i0 + u];
@@ -122,25 +144,21 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_build(int64_t n, const int32_t*
   }
 }
 
-// The product: tile b of kRsRows rows, 16 lanes per row, lane c computing
+// The product: tile b of ROWS rows, 16 lanes per row, lane c computing
 // column c.  A staged tile first loads its rows of X into registers (every
 // load of a thread issued before any of its stores) and copies them to LDS,
-// after them one row of zeros (kRsMax + 1 rows of 128 bytes: 40 KB, four
-// workgroups per CU).  It then walks each row's entries in chunks of 32:
-// lanes l and 16 + l of the chunk hold entry l and 16 + l as a value and the
-// byte offset of its row of X in LDS, and entry j reaches the whole row by a
-// DPP broadcast within the 16-lane row (row_newbcast), which the compiler
-// folds into the address add; the value takes one 64-bit DPP move.  So the
-// entries never pass through LDS and X is the only LDS traffic: one
-// conflict-free 128-byte read per row and entry.  The slots of a chunk past
-// the row's end hold the value 0 and the zero row, and add +0.0 to a sum
-// that is never -0.0, so they change nothing.  A gathered tile (cnt -1)
-// reads columns and X directly.
-constexpr int kRpBlock = 512;
+// after them one row of zeros (kMax + 1 rows of 128 bytes).  It then walks
+// each row's entries in chunks of 32: lanes l and 16 + l of the chunk hold
+// entry l and 16 + l as a value and the byte offset of its row of X in LDS,
+// and entry j reaches the whole row by a DPP broadcast within the 16-lane
+// row (row_newbcast), which the compiler folds into the address add; the
+// value takes one 64-bit DPP move.  So the entries never pass through LDS
+// and X is the only LDS traffic: one conflict-free 128-byte read per row
+// and entry.  The slots of a chunk past the row's end hold the value 0 and
+// the zero row, and add +0.0 to a sum that is never -0.0, so they change
+// nothing.  A gathered tile (count -1) reads columns and X directly.
 constexpr int kRpLanes = 16;
 constexpr int kRpRow = kRpLanes * 8;  // bytes of a row of X
-static_assert(kRsRows * kRpLanes == kRpBlock, "one lane per column of every row");
-constexpr int kRpXq = (kRsMax * 8 + kRpBlock - 1) / kRpBlock;  // 16-byte pieces per thread
 typedef double rs_d2 __attribute__((ext_vector_type(2)));
 
 template <int J>
@@ -184,13 +202,14 @@ __device__ __forceinline__ void rs_chunk(int m, double va, int ca, double vb, in
 }
 
 // Entries base + lane and base + 16 + lane of a row: value and byte offset
-// of the entry's row of X in LDS, or 0 and the zero row past the row's end.
+// of the entry's row of X in LDS, or 0 and the zero row (row zrow) past the
+// row's end.
 __device__ __forceinline__ void rs_load_chunk(const double* __restrict__ val,
                                               const uint16_t* __restrict__ lidx, int32_t t0,
-                                              int len, int base, int lane, double& va, int& ca,
-                                              double& vb, int& cb) {
+                                              int len, int base, int lane, int zrow, double& va,
+                                              int& ca, double& vb, int& cb) {
   va = vb = 0.0;
-  ca = cb = kRsMax * kRpRow;
+  ca = cb = zrow * kRpRow;
   if (base + lane < len) {
     va = stream_load(val + t0 + base + lane);
     ca = (int)lidx[t0 + base + lane] * kRpRow;
@@ -201,44 +220,48 @@ __device__ __forceinline__ void rs_load_chunk(const double* __restrict__ val,
   }
 }
 
-__global__ __launch_bounds__(kRpBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmm_rowset(
+template <int ROWS>
+__global__ __launch_bounds__(ROWS * kRpLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmm_rowset(
     int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const int32_t* __restrict__ ucol,
     const uint16_t* __restrict__ lidx, const double* __restrict__ X, double* __restrict__ Y) {
-  __shared__ rs_d2 xs2[(kRsMax + 1) * 8];
-  const int64_t b = blockIdx.x, r0 = b * kRsRows;
+  constexpr int MAX = RsShape<ROWS>::kMax;
+  constexpr int BLOCK = ROWS * kRpLanes;
+  constexpr int XQ = (MAX * 8 + BLOCK - 1) / BLOCK;  // 16-byte pieces per thread
+  __shared__ rs_d2 xs2[(MAX + 1) * 8];
+  const int64_t b = blockIdx.x, r0 = b * ROWS;
   const int64_t row = r0 + threadIdx.x / kRpLanes;
   const int lane = threadIdx.x % kRpLanes;
   const int64_t rr = row < n ? row : n - 1;
   const int32_t t0 = rowptr[rr];
   const int len = row < n ? rowptr[rr + 1] - t0 : 0;
   // the list and its count in one go: the list's place is fixed
-  const int32_t* list = ucol + b * kRsStride;
+  const int32_t* list = ucol + b * (MAX + 1);
   const int d = list[0];
-  int32_t lst[kRpXq];
+  int32_t lst[XQ];
 #pragma unroll
-  for (int u = 0; u < kRpXq; ++u) {
-    const int q = threadIdx.x + u * kRpBlock;
-    if (q < kRsMax * 8) lst[u] = list[1 + q / 8];
+  for (int u = 0; u < XQ; ++u) {
+    const int q = threadIdx.x + u * BLOCK;
+    if (q < MAX * 8) lst[u] = list[1 + q / 8];
   }
   if (d >= 0) {
     // the first chunk of the row's entries, loaded ahead of the staging
     double va, vb;
     int ca, cb;
-    rs_load_chunk(val, lidx, t0, len, 0, lane, va, ca, vb, cb);
+    rs_load_chunk(val, lidx, t0, len, 0, lane, MAX, va, ca, vb, cb);
     const rs_d2* X2 = reinterpret_cast<const rs_d2*>(X);
-    rs_d2 xv[kRpXq];
+    rs_d2 xv[XQ];
 #pragma unroll
-    for (int u = 0; u < kRpXq; ++u) {
-      const int q = threadIdx.x + u * kRpBlock;
+    for (int u = 0; u < XQ; ++u) {
+      const int q = threadIdx.x + u * BLOCK;
       if (q < d * 8) xv[u] = X2[(int64_t)lst[u] * 8 + q % 8];
     }
 #pragma unroll
-    for (int u = 0; u < kRpXq; ++u) {
-      const int q = threadIdx.x + u * kRpBlock;
+    for (int u = 0; u < XQ; ++u) {
+      const int q = threadIdx.x + u * BLOCK;
       if (q < d * 8) xs2[q] = xv[u];
     }
-    if (threadIdx.x < 8) xs2[kRsMax * 8 + threadIdx.x] = rs_d2{0.0, 0.0};
+    if (threadIdx.x < 8) xs2[MAX * 8 + threadIdx.x] = rs_d2{0.0, 0.0};
     __syncthreads();
     if (row >= n) return;
     const char* xl = reinterpret_cast<const char*>(xs2) + lane * 8;
@@ -247,7 +270,7 @@ __global__ __launch_bounds__(kRpBlock) __attribute__((amdgpu_waves_per_eu(8, 8))
       rs_chunk<0>(len - base, va, ca, vb, cb, xl, s);
       base += 2 * kRpLanes;
       if (base >= len) break;
-      rs_load_chunk(val, lidx, t0, len, base, lane, va, ca, vb, cb);
+      rs_load_chunk(val, lidx, t0, len, base, lane, MAX, va, ca, vb, cb);
     }
     Y[row * 16 + lane] = s;
     return;
@@ -258,29 +281,45 @@ __global__ __launch_bounds__(kRpBlock) __attribute__((amdgpu_waves_per_eu(8, 8))
   Y[row * 16 + lane] = s;
 }
 
-}  // namespace
-
-int build_rowset(Csr& A, hipStream_t s) {
+template <int ROWS>
+int build_rowset_t(Csr& A, hipStream_t s) {
   RowSet& R = A.rs;
-  if (R.built || A.n == 0) return SPX_OK;
-  const int64_t tiles = ceil_div(A.n, kRsRows);
+  const int64_t tiles = ceil_div(A.n, ROWS);
   int st = SPX_OK;
   do {
-    if ((st = dalloc_n(&R.col, (size_t)(tiles * kRsStride))) != SPX_OK) break;
+    if ((st = dalloc_n(&R.col, (size_t)(tiles * (RsShape<ROWS>::kMax + 1)))) != SPX_OK) break;
     if ((st = dalloc_n(&R.lidx, (size_t)std::max<int64_t>(A.nnz, 1))) != SPX_OK) break;
-    hipLaunchKernelGGL(k_rs_build, dim3((unsigned)tiles), dim3(kRsBlock), 0, s, A.n, A.rowptr,
-                       A.col, R.col, R.lidx);
+    hipLaunchKernelGGL(k_rs_build<ROWS>, dim3((unsigned)tiles), dim3(kRsBlock), 0, s, A.n,
+                       A.rowptr, A.col, R.col, R.lidx);
     if (hipGetLastError() != hipSuccess) {
       st = set_error(SPX_HIP_ERROR, "spmm: row-set index: launch failed");
       break;
     }
   } while (false);
+  return st;
+}
+
+}  // namespace
+
+int build_rowset(Csr& A, int rows, hipStream_t s) {
+  RowSet& R = A.rs;
+  if (rows != 16 && rows != 32 && rows != 64)
+    return set_error(SPX_INVALID_ARG, "spmm: tile height %d is not 16, 32 or 64", rows);
+  if (A.n == 0 || (R.built && R.rows == rows)) return SPX_OK;
+  // a new tile height: the lists are built again
+  dfree(R.col);
+  dfree(R.lidx);
+  R = RowSet();
+  const int st = rows == 16   ? build_rowset_t<16>(A, s)
+                 : rows == 32 ? build_rowset_t<32>(A, s)
+                              : build_rowset_t<64>(A, s);
   if (st != SPX_OK) {
     dfree(R.col);
     dfree(R.lidx);
     R = RowSet();
     return st;
   }
+  R.rows = rows;
   R.built = true;
   return SPX_OK;
 }
@@ -288,8 +327,16 @@ int build_rowset(Csr& A, hipStream_t s) {
 int launch_spmm_rowset(const Csr& A, const double* X, double* Y, hipStream_t s) {
   const RowSet& R = A.rs;
   if (A.n == 0) return SPX_OK;
-  hipLaunchKernelGGL(k_spmm_rowset, dim3((unsigned)ceil_div(A.n, kRsRows)), dim3(kRpBlock), 0, s,
-                     A.n, A.rowptr, A.col, A.val, R.col, R.lidx, X, Y);
+  auto go = [&](auto k, int rows) {
+    hipLaunchKernelGGL(k, dim3((unsigned)ceil_div(A.n, rows)), dim3(rows * kRpLanes), 0, s, A.n,
+                       A.rowptr, A.col, A.val, R.col, R.lidx, X, Y);
+  };
+  if (R.rows == 16)
+    go(k_spmm_rowset<16>, 16);
+  else if (R.rows == 64)
+    go(k_spmm_rowset<64>, 64);
+  else
+    go(k_spmm_rowset<32>, 32);
   return SPX_OK;
 }
 

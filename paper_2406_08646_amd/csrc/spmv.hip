@@ -750,7 +750,7 @@ extern "C" int spx_spmm(spx_handle h, int64_t nrhs, const double* X, int64_t ldx
   const bool rowset = nrhs == 16 && ldx == 16 && ldy == 16 &&
                       ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15) == 0;
   if (rowset) {
-    SPX_TRY(build_rowset(h->A, s));
+    SPX_TRY(build_rowset(h->A, h->spmm_rows_opt ? h->spmm_rows_opt : 32, s));
     SPX_TRY(launch_spmm_rowset(h->A, X, Y, s));
   } else {
     SPX_TRY(launch_spmm(h->A, nrhs, X, ldx, Y, ldy, s));

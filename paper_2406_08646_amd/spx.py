@@ -51,6 +51,7 @@ OPT_CG_VARIANT = 12
 OPT_GRAPH = 13
 OPT_SMALL_SOLVE = 14
 OPT_IR_EARLY_EXIT = 15
+OPT_SPMM_TILE_ROWS = 16
 NOALLOC_MAX_ROWS = 2097152  # SPX_NOALLOC_MAX_ROWS
 PROFILE_KINDS = ("spmv_dot_f64", "update_f64", "pupdate_f64", "spmv_dot_f32", "update_f32",
                  "pupdate_f32")

@@ -273,6 +273,31 @@ def test_spmm16_row_set_tiles(orc, tiles, tail):
             spmv_within(Ys[:, c], Yr[:, c], orc.abs_spmv(ref, Xh[:, c]))
 
 
+def test_spmm16_tile_heights_same_bits(orc):
+    """16-, 32- and 64-row tiles (the index rebuilt at each change) give the
+    same bits as the paired-column kernel; the autotuner leaves one of them
+    set; other heights are refused."""
+    spx = require_gpu()
+    from paper_2406_08646_amd import autotune
+    lib = spx.load_library()
+    rng = np.random.default_rng(95)
+    prob = _row_set_pattern(rng, 30, 11)
+    A = assemble(spx, prob)
+    Xh = rng.uniform(-1, 1, (prob.n, 16))
+    Yp = _spmm16(lib, A, Xh, 18)
+    assert A.get_option(spx.OPT_SPMM_TILE_ROWS) == 32
+    for rows in (16, 64, 32, 16):
+        A.set_option(spx.OPT_SPMM_TILE_ROWS, rows)
+        assert A.get_option(spx.OPT_SPMM_TILE_ROWS) == rows
+        assert np.array_equal(bits(_spmm16(lib, A, Xh, 16)), bits(Yp)), rows
+    with pytest.raises(spx.SpxError) as e:
+        A.set_option(spx.OPT_SPMM_TILE_ROWS, 48)
+    assert e.value.code == spx.INVALID_ARG
+    best = autotune.tune_spmm(A, dev(Xh), repeats=2)
+    assert best["rows"] in (16, 32, 64) and A.get_option(spx.OPT_SPMM_TILE_ROWS) == best["rows"]
+    assert np.array_equal(bits(_spmm16(lib, A, Xh, 16)), bits(Yp))
+
+
 def test_spmm16_row_set_non_finite_x(orc):
     """Rows of X holding inf and NaN: only the rows of Y whose entries name
     them turn non-finite (a chunk's unused slots add +0.0 times a row of
