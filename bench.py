@@ -124,16 +124,18 @@ def measured_traffic():
 
 
 def host_cpu():
-    model = platform.processor() or ""
+    """CPU model name, logical CPU count and socket count of this host."""
+    model, sockets = "", set()
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
+                if line.startswith("model name") and not model:
                     model = line.split(":", 1)[1].strip()
-                    break
+                elif line.startswith("physical id"):
+                    sockets.add(line.split(":", 1)[1].strip())
     except OSError:
         pass
-    return model, os.cpu_count()
+    return model or platform.processor() or "", os.cpu_count(), max(1, len(sockets))
 
 
 EXTRAS = ("ceilings", "spmm16", "vec_coo", "cg_forms", "c1_cg", "one_gpu_share", "sync_vs_async",
@@ -427,6 +429,9 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
         kw = dict(blocks=best["blocks"], rows_per_tile=best["rows_per_tile"],
                   weight_exponent=best["weight_exponent"], persistent=best["persistent"])
         bt_ms, (xb, iters, relres, st) = timed(lambda: batch.batch_cg(bvec, rtol=1e-8, **kw), reps=3)
+        # the persistent form on this batch: its largest system (512^2 rows)
+        # alone on one workgroup sets the time
+        pc_ms, (_, _, _, pc_st) = timed(lambda: batch.batch_cg(bvec, rtol=1e-8, persistent=1))
         work = sum(it * cg_iteration_bytes(p.n, m.nnz) for it, p, m in zip(iters, probs, mats))
         # one solve per system
         seq_ms, _ = timed(lambda: [m.cg_solve(d_b, rtol=1e-8) for m, d_b in
@@ -446,7 +451,8 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
                             "sequential_ms": round(seq_ms, 2), "ensemble_ms": round(ens_ms, 2),
                             "ensemble_iters": ens.iters,
                             "speedup_vs_ensemble": round(ens_ms / bt_ms, 2),
-                            "speedup_vs_sequential": round(seq_ms / bt_ms, 2)}
+                            "speedup_vs_sequential": round(seq_ms / bt_ms, 2),
+                            "persistent_ms": round(pc_ms, 2), "persistent_status": pc_st}
         log(f"batched: {bt_ms:.2f} ms, ensemble {ens_ms:.2f} ms, sequential {seq_ms:.2f} ms")
         del batch, mats, E
 
@@ -675,7 +681,7 @@ def cpu_baseline(grid: int, calls: int, full=None):
     import oracle
     from paper_2406_08646_amd import workloads as W
 
-    model, ncpu = host_cpu()
+    model, ncpu, nsock = host_cpu()
     threads = host_threads()
     oracle.set_threads(1)
     prob, x, _ = W.config2(grid)
@@ -763,7 +769,7 @@ def cpu_baseline(grid: int, calls: int, full=None):
         "sample": ("oracle SpMV GB/s (same byte count as the GPU figure) on the "
                    + top["sample"] + f" with {top['cores']} thread(s); legs: "
                    + "; ".join(f"{leg['cores']} thread(s) on the {leg['sample']}" for leg in legs)
-                   + f"; host '{model}', {ncpu} logical CPUs, {threads} usable"),
+                   + f"; host '{model}', {nsock} socket(s), {ncpu} logical CPUs, {threads} usable"),
         "legs": legs,
     }
     return out, errors
