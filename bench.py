@@ -423,9 +423,11 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
             m.set_values_coo(d(p.v))
         batch = spx.batch_create(mats)
         bvec = d(np.concatenate(bs))
-        best = autotune.tune_batch(batch, bvec, rtol=1e-8, candidates=[
-            autotune.Candidate(1024, 0, 1.0), autotune.Candidate(2048, 0, 1.0),
-            autotune.Candidate(2048, 64, 1.0), autotune.Candidate(2048, 0, 1.25)])
+        # the tuner's full default grid: the persistent form and 27 shapes of
+        # the per-phase form (workgroups, row walk, weight exponent)
+        cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        best = autotune.tune_batch(batch, bvec, rtol=1e-8,
+                                   candidates=autotune.default_candidates(cus))
         kw = dict(blocks=best["blocks"], rows_per_tile=best["rows_per_tile"],
                   weight_exponent=best["weight_exponent"], persistent=best["persistent"])
         bt_ms, (xb, iters, relres, st) = timed(lambda: batch.batch_cg(bvec, rtol=1e-8, **kw), reps=3)
@@ -448,6 +450,7 @@ def run_extras(spx, W, torch, np, dev, prob, x_np, b_np, log, only=None):
                             "status": st, "max_relres": max(relres), "iters_max": max(iters),
                             "iters_min": min(iters), "work_bytes": work,
                             "gbs": round(work / (bt_ms * 1e-3) / 1e9, 1), "tuning": best,
+                            "tuning_candidates": len(autotune.default_candidates(cus)),
                             "sequential_ms": round(seq_ms, 2), "ensemble_ms": round(ens_ms, 2),
                             "ensemble_iters": ens.iters,
                             "speedup_vs_ensemble": round(ens_ms / bt_ms, 2),
