@@ -12,6 +12,10 @@
 // proportional to nnz_s^exponent), so the large, slow-converging systems
 // get the whole chip once the small ones are done.  Workgroups of one
 // kernel never wait for each other: no agent-scope fence, no co-residency.
+//
+// The persistent form (below, and cg_one.hpp / krylov_one.hpp) launches
+// once: each workgroup takes whole systems from a queue and runs the method
+// on them alone, which pays off for many small systems.
 #pragma once
 
 #include <algorithm>
