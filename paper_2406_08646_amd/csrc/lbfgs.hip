@@ -435,7 +435,8 @@ __global__ __launch_bounds__(kLB, 1) void k_lb_ya(int64_t n, const double* __res
 // block's elements are loaded into registers (kYPer per thread, all issued
 // together) while the current block is used.  (Measured at n = 10^7,
 // m = 50: one block ahead 2.9 ms for the fused step; two blocks ahead, in
-// 64- or 32-row blocks, 3.3-3.5 ms.)
+// 64- or 32-row blocks, 3.3-3.5 ms; 128-row blocks of 512 threads, apply
+// 3.0 ms against 2.45; (Y c)_r split over the four waves, no change.)
 constexpr int kYRows = 64;
 constexpr int kYStride = kYRows + 1;
 constexpr int kYPer = kMaxHistory * kYRows / kLB;
