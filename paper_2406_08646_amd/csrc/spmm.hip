@@ -30,15 +30,15 @@ template <int ROWS>
 struct RsShape;
 template <>
 struct RsShape<16> {
-  static constexpr int kCap = 1024, kMax = 191;
+  static constexpr int kCap = 1024, kMax = 191, kWaves = 6;
 };
 template <>
 struct RsShape<32> {
-  static constexpr int kCap = 1024, kMax = 319;
+  static constexpr int kCap = 1024, kMax = 319, kWaves = 8;
 };
 template <>
 struct RsShape<64> {
-  static constexpr int kCap = 2048, kMax = 639;
+  static constexpr int kCap = 2048, kMax = 639, kWaves = 8;
 };
 
 constexpr int kRsBlock = 256;  // threads of the index builder
@@ -221,20 +221,21 @@ __device__ __forceinline__ void rs_load_chunk(const double* __restrict__ val,
 }
 
 template <int ROWS>
-__global__ __launch_bounds__(ROWS * kRpLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spmm_rowset(
+__global__ __launch_bounds__(ROWS * kRpLanes) __attribute__((amdgpu_waves_per_eu(RsShape<ROWS>::kWaves, 8))) void k_spmm_rowset(
     int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const int32_t* __restrict__ ucol,
     const uint16_t* __restrict__ lidx, const double* __restrict__ X, double* __restrict__ Y) {
   constexpr int MAX = RsShape<ROWS>::kMax;
   constexpr int BLOCK = ROWS * kRpLanes;
   constexpr int XQ = (MAX * 8 + BLOCK - 1) / BLOCK;  // 16-byte pieces per thread
+  static_assert(XQ * BLOCK == (MAX + 1) * 8, "the pieces past the list cover the zero row");
   __shared__ rs_d2 xs2[(MAX + 1) * 8];
   const int64_t b = blockIdx.x, r0 = b * ROWS;
   const int64_t row = r0 + threadIdx.x / kRpLanes;
   const int lane = threadIdx.x % kRpLanes;
   const int64_t rr = row < n ? row : n - 1;
-  const int32_t t0 = rowptr[rr];
-  const int len = row < n ? rowptr[rr + 1] - t0 : 0;
+  const int32_t t0 = rowptr[rr], t1 = rowptr[rr + 1];
+  const int len = row < n ? t1 - t0 : 0;
   // the list and its count in one go: the list's place is fixed
   const int32_t* list = ucol + b * (MAX + 1);
   const int d = list[0];
@@ -242,26 +243,44 @@ __global__ __launch_bounds__(ROWS * kRpLanes) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
   for (int u = 0; u < XQ; ++u) {
     const int q = threadIdx.x + u * BLOCK;
-    if (q < MAX * 8) lst[u] = list[1 + q / 8];
+    lst[u] = list[1 + (q < MAX * 8 ? q : MAX * 8 - 1) / 8];
   }
+  // the whole list in registers here, its loads in flight with the row's
+  // bounds: a load of it left for later would hold back the loads of X
+#pragma unroll
+  for (int u = 0; u < XQ; ++u) asm volatile("" : "+v"(lst[u]));
   if (d >= 0) {
-    // the first chunk of the row's entries, loaded ahead of the staging
-    double va, vb;
-    int ca, cb;
-    rs_load_chunk(val, lidx, t0, len, 0, lane, MAX, va, ca, vb, cb);
+    // Every load of the staging is issued, where its result goes unused
+    // from a valid address near the ones in use (the row's first entry,
+    // which the tail padding keeps inside the arrays even for an empty last
+    // row; a row of X of the tile's own rows), so that none has to wait for
+    // another: loads under data-dependent branches each waited for all the
+    // loads before them.  The chain is list, then X, then the barrier.  The
+    // first chunk of the row's entries comes with them.
+    const bool ha = lane < len, hb = kRpLanes + lane < len;
+    const int32_t ia = ha ? t0 + lane : t0, ib = hb ? t0 + kRpLanes + lane : t0;
+    double va0 = stream_load(val + ia), vb0 = stream_load(val + ib);
+    int pa = lidx[ia], pb = lidx[ib];
     const rs_d2* X2 = reinterpret_cast<const rs_d2*>(X);
     rs_d2 xv[XQ];
 #pragma unroll
     for (int u = 0; u < XQ; ++u) {
       const int q = threadIdx.x + u * BLOCK;
-      if (q < d * 8) xv[u] = X2[(int64_t)lst[u] * 8 + q % 8];
+      const int64_t own = r0 + (q / 8) % ROWS;
+      xv[u] = X2[(q < d * 8 ? (int64_t)lst[u] : own < n ? own : n - 1) * 8 + q % 8];
     }
+    // pieces past the list write zeros into the zero row (row MAX), which
+    // they cover whole since XQ * BLOCK == (MAX + 1) * 8
 #pragma unroll
     for (int u = 0; u < XQ; ++u) {
       const int q = threadIdx.x + u * BLOCK;
-      if (q < d * 8) xs2[q] = xv[u];
+      const bool in = q < d * 8;
+      xs2[in ? q : MAX * 8 + q % 8] = in ? xv[u] : rs_d2{0.0, 0.0};
     }
-    if (threadIdx.x < 8) xs2[MAX * 8 + threadIdx.x] = rs_d2{0.0, 0.0};
+    // the entries are needed here, so their loads stay ahead of the barrier
+    asm volatile("" : "+v"(va0), "+v"(vb0), "+v"(pa), "+v"(pb));
+    double va = ha ? va0 : 0.0, vb = hb ? vb0 : 0.0;
+    int ca = (ha ? pa : MAX) * kRpRow, cb = (hb ? pb : MAX) * kRpRow;
     __syncthreads();
     if (row >= n) return;
     const char* xl = reinterpret_cast<const char*>(xs2) + lane * 8;

@@ -72,8 +72,9 @@ __global__ __launch_bounds__(kWinRows) void k_spmv_window(int64_t n, const int32
   const int64_t b = remap ? xcd_logical_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   const int64_t r0 = b * kWinRows;
   const int64_t r1 = r0 + kWinRows < n ? r0 + kWinRows : n;
-  const double s = window_rows<kWinUProduct, win_v<double>(), kWinRows, double, double, double, NT>(
-      rowptr, col, val, x, n, w, b, r0, r1, reinterpret_cast<double*>(smem));
+  const double s =
+      window_rows<kWinUProduct, win_v<double>(), kWinRows, double, double, double, NT, true>(
+          rowptr, col, val, x, n, w, b, r0, r1, reinterpret_cast<double*>(smem));
   if (threadIdx.x < r1 - r0) y[r0 + threadIdx.x] = s;
 }
 

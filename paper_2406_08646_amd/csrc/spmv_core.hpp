@@ -295,23 +295,72 @@ struct VecN {
 // beyond read as 0) into xs, block i at xs + i * kWinBlock, with 16-byte
 // loads when x is 16-byte aligned.  x is read through the caches: each
 // block serves several neighbouring tiles.
-template <int BLOCK, typename XT>
+//
+// EAGER: a thread loads all its block numbers, then all its pieces of x,
+// then stores them; otherwise it loads and stores one piece at a time.
+// Loads left under data-dependent branches each wait for every load before
+// them, a round trip per piece, which the eager form avoids: threads past
+// the window load its last piece again, and a piece that runs past n loads
+// 16 bytes of the block list instead (unused) and is read entry by entry
+// once the others are in flight.  One tile per workgroup (MatMult) gains
+// from it; the solver's persistent walk measured slower with it, so it
+// keeps the plain loop.
+template <int BLOCK, typename XT, bool EAGER>
 __device__ __forceinline__ void load_window(const XT* __restrict__ x, int64_t n,
                                             const int32_t* __restrict__ blk, int32_t k0,
                                             int32_t nbk, XT* xs) {
   constexpr int PER = 16 / sizeof(XT);
   constexpr int LPB = kWinBlock / PER;
+  constexpr int PRE = 4;  // pieces per thread in flight together
   typedef typename Vec16<XT>::type V;
-  const bool aligned = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
-  for (int q = threadIdx.x; q < nbk * LPB; q += BLOCK) {
-    const int i = q / LPB, e = (q % LPB) * PER;
-    const int64_t g = (int64_t)blk[k0 + i] * kWinBlock + e;
-    XT* d = xs + i * kWinBlock + e;
-    if (aligned && g + PER <= n) {
-      *reinterpret_cast<V*>(d) = *reinterpret_cast<const V*>(x + g);
-    } else {
+  const int cnt = nbk * LPB;
+  if (!EAGER || (reinterpret_cast<uintptr_t>(x) & 15) != 0) {
+    const bool aligned = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    for (int q = threadIdx.x; q < cnt; q += BLOCK) {
+      const int i = q / LPB, e = (q % LPB) * PER;
+      const int64_t g = (int64_t)blk[k0 + i] * kWinBlock + e;
+      XT* d = xs + i * kWinBlock + e;
+      if (aligned && g + PER <= n) {
+        *reinterpret_cast<V*>(d) = *reinterpret_cast<const V*>(x + g);
+      } else {
 #pragma unroll
-      for (int j = 0; j < PER; ++j) d[j] = g + j < n ? x[g + j] : XT(0);
+        for (int j = 0; j < PER; ++j) d[j] = g + j < n ? x[g + j] : XT(0);
+      }
+    }
+    return;
+  }
+  for (int q0 = 0; q0 < cnt; q0 += PRE * BLOCK) {
+    int32_t bq[PRE];
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+      const int q = q0 + threadIdx.x + u * BLOCK;
+      bq[u] = blk[k0 + (q < cnt ? q : cnt - 1) / LPB];
+    }
+    V v[PRE];
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+      const int q = q0 + threadIdx.x + u * BLOCK;
+      const int64_t g = (int64_t)bq[u] * kWinBlock + ((q < cnt ? q : cnt - 1) % LPB) * PER;
+      v[u] = *(g + PER <= n ? reinterpret_cast<const V*>(x + g) : reinterpret_cast<const V*>(blk));
+    }
+    // all pieces in registers here: a load sunk into the branch of its
+    // store would wait for every load before it
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) asm volatile("" : "+v"(v[u]));
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+      const int q = q0 + threadIdx.x + u * BLOCK;
+      if (q < cnt) {
+        const int i = q / LPB, e = (q % LPB) * PER;
+        const int64_t g = (int64_t)bq[u] * kWinBlock + e;
+        XT* d = xs + i * kWinBlock + e;
+        if (g + PER <= n) {
+          *reinterpret_cast<V*>(d) = v[u];
+        } else {
+#pragma unroll
+          for (int j = 0; j < PER; ++j) d[j] = g + j < n ? x[g + j] : XT(0);
+        }
+      }
     }
   }
 }
@@ -324,8 +373,8 @@ __device__ __forceinline__ void load_window(const XT* __restrict__ x, int64_t n,
 // multiple of V at or below the tile's first entry t0; members outside
 // [t0, t1) are loaded (the arrays carry tail padding) but never used.
 // Thread i owns the row whose entries are [ra, re) relative to that entry ta.
-template <bool WIN, int U, int V, int BLOCK, typename VT, typename XT, typename ACC, bool NT,
-          typename CT>
+template <bool WIN, bool EAGER, int U, int V, int BLOCK, typename VT, typename XT, typename ACC,
+          bool NT, typename CT>
 __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const VT* __restrict__ val,
                                              const XT* __restrict__ x, int64_t n,
                                              const int32_t* __restrict__ blk, int32_t k0,
@@ -338,17 +387,23 @@ __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const 
   const int tid = threadIdx.x;
   const int32_t ta = t0 & ~(V - 1);
   const int32_t cnt = t1 - ta, skip = t0 - ta;
+  // EAGER: members past the tile load its first group again (unused), so
+  // that no load sits under a data-dependent branch
   VV a[U];
   CV c[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int32_t e = (u * BLOCK + tid) * V;
-    if (e < cnt) {
+    if constexpr (EAGER) {
+      const int32_t ec = e < cnt ? e : 0;
+      a[u] = mload<NT>(reinterpret_cast<const VV*>(val + ta + ec));
+      c[u] = mload<NT>(reinterpret_cast<const CV*>(cidx + ta + ec));
+    } else if (e < cnt) {
       a[u] = mload<NT>(reinterpret_cast<const VV*>(val + ta + e));
       c[u] = mload<NT>(reinterpret_cast<const CV*>(cidx + ta + e));
     }
   }
-  if constexpr (WIN) load_window<BLOCK, XT>(x, n, blk, k0, nbk, xs);
+  if constexpr (WIN) load_window<BLOCK, XT, EAGER>(x, n, blk, k0, nbk, xs);
   __syncthreads();
   ACC s = ACC(0);
   for (int32_t base = 0; base < cnt; base += C) {
@@ -373,7 +428,11 @@ __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t e = next + (u * BLOCK + tid) * V;
-        if (e < cnt) {
+        if constexpr (EAGER) {
+          const int32_t ec = e < cnt ? e : next;
+          a[u] = mload<NT>(reinterpret_cast<const VV*>(val + ta + ec));
+          c[u] = mload<NT>(reinterpret_cast<const CV*>(cidx + ta + ec));
+        } else if (e < cnt) {
           a[u] = mload<NT>(reinterpret_cast<const VV*>(val + ta + e));
           c[u] = mload<NT>(reinterpret_cast<const CV*>(cidx + ta + e));
         }
@@ -399,7 +458,8 @@ __device__ __forceinline__ ACC window_chunks(const CT* __restrict__ cidx, const 
 // the current chunk's sums.  LDS: BLOCK * U * V ACC products, then the
 // largest window's x entries.  Returns the row sum in its owner thread and
 // leaves the workgroup synchronised.
-template <int U, int V, int BLOCK, typename VT, typename XT, typename ACC, bool NT>
+template <int U, int V, int BLOCK, typename VT, typename XT, typename ACC, bool NT,
+          bool EAGER = false>
 __device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
                                            const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const XT* __restrict__ x,
@@ -411,12 +471,20 @@ __device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
   const int32_t ta = t0 & ~(V - 1);
   const int32_t k0 = w.ptr[tile], nbk = w.ptr[tile + 1] - k0;
   const bool own = tid < r1 - r0;
-  const int32_t ra = own ? rowptr[r0 + tid] - ta : 0;
-  const int32_t re = own ? rowptr[r0 + tid + 1] - ta : 0;
+  int32_t ra, re;
+  if constexpr (EAGER) {
+    const int64_t ri = own ? r0 + tid : r0;  // loaded either way: no branch
+    const int32_t ra0 = rowptr[ri], re0 = rowptr[ri + 1];
+    ra = own ? ra0 - ta : 0;
+    re = own ? re0 - ta : 0;
+  } else {
+    ra = own ? rowptr[r0 + tid] - ta : 0;
+    re = own ? rowptr[r0 + tid + 1] - ta : 0;
+  }
   if (nbk > 0)
-    return window_chunks<true, U, V, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0,
+    return window_chunks<true, EAGER, U, V, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0,
                                                              t1, ra, re, prod);
-  return window_chunks<false, U, V, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, t1,
+  return window_chunks<false, EAGER, U, V, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, t1,
                                                             ra, re, prod);
 }
 
