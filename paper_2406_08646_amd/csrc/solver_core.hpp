@@ -31,10 +31,26 @@ __device__ __forceinline__ Range block_range(int64_t total, int64_t b, int64_t n
 }
 
 // Sum of nparts partials; every workgroup gets the same value (fixed
-// strided split, fixed tree).
+// strided split, fixed tree).  A thread takes its partials in groups of
+// kReduceGroup, every load of a group issued before the first add (a
+// partial past the end loads partial 0 and is not added), so the adds keep
+// their order and the sum its bits, at one round trip per group: one load
+// and add at a time paid a round trip per partial, at the start of every
+// kernel that reads the previous one's partials.
+constexpr int kReduceGroup = 8;
 __device__ __forceinline__ double reduce_all(const double* parts, int64_t nparts, double* lds) {
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += kBlock) s += parts[i];
+  for (int64_t i0 = threadIdx.x; i0 < nparts; i0 += (int64_t)kReduceGroup * kBlock) {
+    double v[kReduceGroup];
+#pragma unroll
+    for (int u = 0; u < kReduceGroup; ++u) {
+      const int64_t i = i0 + (int64_t)u * kBlock;
+      v[u] = parts[i < nparts ? i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < kReduceGroup; ++u)
+      if (i0 + (int64_t)u * kBlock < nparts) s += v[u];
+  }
   s = block_sum<kBlock>(s, lds);
   if (threadIdx.x == 0) lds[kLds - 1] = s;
   __syncthreads();
