@@ -383,9 +383,8 @@ __global__ __launch_bounds__(solver::kBlock) void k_b_init_finish(PlanView pl, C
   __shared__ double lds[kLds];
   const int s = blockIdx.x;
   const int a = pl.start(s), T = pl.size(s);
-  const double rz = reduce_all(P + a, T, lds);
-  const double rr = reduce_all(P + pl.G + a, T, lds);
-  const double bb = reduce_all(P + 2 * pl.G + a, T, lds);
+  double rz, rr, bb;
+  reduce_all(P + a, P + pl.G + a, P + 2 * pl.G + a, T, lds, rz, rr, bb);
   if (threadIdx.x == 0) {
     CgScalars& c = st[s];
     c.rho[0] = rz;

@@ -134,8 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_b_pupdate(const BatchSys* __restrict
   if (s < 0 || st[s].done) return;
   const int a = pl.start(s), T = pl.size(s);
   const int64_t j = blockIdx.x - a;
-  const double rz = reduce_all(P2 + a, T, lds);
-  const double rr = reduce_all(P2 + pl.G + a, T, lds);
+  double rz, rr;
+  reduce_all(P2 + a, P2 + pl.G + a, T, lds, rz, rr);
   CgScalars& c = st[s];
   const bool conv = sqrt(rr) <= c.thresh;
   const bool stop = conv || k >= c.maxit;

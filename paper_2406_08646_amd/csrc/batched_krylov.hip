@@ -183,8 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_bb_pupdate(const BatchSys* __restric
   if (s < 0 || st[s].done) return;
   const int a = pl.start(s), T = pl.size(s);
   const int64_t j = blockIdx.x - a;
-  const double rz = reduce_all(P2 + a, T, lds);
-  const double rr = reduce_all(P2 + pl.G + a, T, lds);
+  double rz, rr;
+  reduce_all(P2 + a, P2 + pl.G + a, T, lds, rz, rr);
   CgScalars& c = st[s];
   const bool conv = sqrt(rr) <= c.thresh;
   const bool broke = !conv && (rz == 0.0 || !isfinite(rz));
@@ -274,8 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_tq_init_finish(PlanView pl, CgScalar
   __shared__ double lds[kLds];
   const int s = blockIdx.x;
   const int a = pl.start(s), T = pl.size(s);
-  const double rr = reduce_all(P + a, T, lds);
-  const double bb = reduce_all(P + pl.G + a, T, lds);
+  double rr, bb;
+  reduce_all(P + a, P + pl.G + a, T, lds, rr, bb);
   if (threadIdx.x == 0) {
     CgScalars& c = st[s];
     c.rho[0] = rr;
@@ -463,8 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_tq_d(const BatchSys* __restrict__ sy
   const int a = pl.start(s), T = pl.size(s);
   const int64_t jb = blockIdx.x - a;
   CgScalars& c = st[s];
-  const double ww = reduce_all(P2 + a, T, lds);
-  const double rho_new = reduce_all(P2 + pl.G + a, T, lds);
+  double ww, rho_new;
+  reduce_all(P2 + a, P2 + pl.G + a, T, lds, ww, rho_new);
   const double alpha = c.alpha;
   const TqStep h = tq_step(ww, c.tau[1], alpha);
   const int64_t ml = 2 * (j - c.j0) + 2;

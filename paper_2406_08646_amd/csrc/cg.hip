@@ -103,9 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const int32_t* __
 __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgScalars* st, const double* P,
                                                            int64_t G, double rtol) {
   __shared__ double lds[kLds];
-  const double rz = reduce_all(P, G, lds);
-  const double rr = reduce_all(P + G, G, lds);
-  const double bb = reduce_all(P + 2 * G, G, lds);
+  double rz, rr, bb;
+  reduce_all(P, P + G, P + 2 * G, G, lds, rz, rr, bb);
   if (threadIdx.x == 0) {
     st->rho[0] = rz;
     st->bb = bb;
@@ -223,8 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, VT* __restrict
   __shared__ double lds[kLds];
   if (st->done) return;
   if (k <= 0) k = st->kcur;  // written by this iteration's update kernel
-  const double rz = reduce_all(P2, G2, lds);
-  const double rr = reduce_all(P2 + G2, G2, lds);
+  double rz, rr;
+  reduce_all(P2, P2 + G2, G2, lds, rz, rr);
   const bool conv = sqrt(rr) <= st->thresh;
   const bool stop = conv || k >= st->maxit;
   const double rho_prev = st->rho[(k - 1) & 1];
@@ -375,8 +374,8 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
   extern __shared__ __align__(16) char smem[];
   double* lds = reduction_lds<SH>(smem);
   if (st->done) return;
-  const double gk = reduce_all(P2, G2, lds);
-  const double rr = reduce_all(P2 + G2, G2, lds);
+  double gk, rr;
+  reduce_all(P2, P2 + G2, G2, lds, gk, rr);
   const bool conv = sqrt(rr) <= st->thresh;
   const bool stop = conv || k >= st->maxit;
   const double gprev = st->rho[(k - 1) & 1];
@@ -487,9 +486,8 @@ __global__ __launch_bounds__(kBlock) void k_pl_update(int64_t n, PlVectors v, Cg
   __shared__ double lds[kLds];
   if (st->done) return;
   const int64_t i = k - 1;
-  const double g = reduce_all(Pin, Gin, lds);
-  const double dl = reduce_all(Pin + Gin, Gin, lds);
-  const double rr = reduce_all(Pin + 2 * Gin, Gin, lds);
+  double g, dl, rr;
+  reduce_all(Pin, Pin + Gin, Pin + 2 * Gin, Gin, lds, g, dl, rr);
   const bool conv = sqrt(rr) <= st->thresh;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (conv || i >= st->maxit) {
@@ -650,9 +648,8 @@ __global__ __launch_bounds__(kBlock) void k_ir_finish(CgScalars* so, CgScalars* 
                                                       int64_t G, double rtol_inner,
                                                       int early_exit) {
   __shared__ double lds[kLds];
-  const double t64 = reduce_all(P, G, lds);
-  const double trz = reduce_all(P + G, G, lds);
-  const double t32 = reduce_all(P + 2 * G, G, lds);
+  double t64, trz, t32;
+  reduce_all(P, P + G, P + 2 * G, G, lds, t64, trz, t32);
   if (threadIdx.x == 0) {
     so->rr = t64;
     so->rr_true = t64;

@@ -15,7 +15,9 @@ namespace spx {
 namespace solver {
 
 constexpr int kBlock = 256;
-constexpr int kLds = kBlock / 64 + 1;
+// LDS of a solver kernel's reductions: a wave sum and a result for each of
+// up to three sums at once.
+constexpr int kLds = 3 * (kBlock / 64) + 3;
 
 struct Range {
   int64_t lo, hi;
@@ -30,33 +32,94 @@ __device__ __forceinline__ Range block_range(int64_t total, int64_t b, int64_t n
   return {lo, hi};
 }
 
-// Sum of nparts partials; every workgroup gets the same value (fixed
-// strided split, fixed tree).  A thread takes its partials in groups of
-// kReduceGroup, every load of a group issued before the first add (a
-// partial past the end loads partial 0 and is not added), so the adds keep
-// their order and the sum its bits, at one round trip per group: one load
+// Sums of N arrays of nparts partials each (parts[k][0 .. nparts)); every
+// workgroup gets the same values (fixed strided split, fixed tree: each
+// thread adds its partials in index order, each wave its threads, thread 0
+// the waves in order).  A thread loads its partials of all N arrays in
+// groups of kReduceGroup before the first add (a partial past the end
+// loads partial 0 and is not added), at one round trip per group: one load
 // and add at a time paid a round trip per partial, at the start of every
-// kernel that reads the previous one's partials.
+// kernel that reads the previous one's partials.  The N sums share three
+// barriers.  lds: kLds doubles.
 constexpr int kReduceGroup = 8;
-__device__ __forceinline__ double reduce_all(const double* parts, int64_t nparts, double* lds) {
-  double s = 0.0;
-  for (int64_t i0 = threadIdx.x; i0 < nparts; i0 += (int64_t)kReduceGroup * kBlock) {
-    double v[kReduceGroup];
+constexpr int kReduceMax = 3;
+template <int N>
+__device__ __forceinline__ void reduce_all_n(const double* const (&parts)[N], int64_t nparts,
+                                             double* lds, double (&out)[N]) {
+  static_assert(N >= 1 && N <= kReduceMax, "lds holds kReduceMax sums");
+  constexpr int W = kBlock / 64;
+  double s[N];
 #pragma unroll
-    for (int u = 0; u < kReduceGroup; ++u) {
-      const int64_t i = i0 + (int64_t)u * kBlock;
-      v[u] = parts[i < nparts ? i : 0];
+  for (int k = 0; k < N; ++k) s[k] = 0.0;
+  if (nparts <= kBlock) {  // one partial per thread at most: no groups
+    if (threadIdx.x < nparts) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) s[k] += parts[k][threadIdx.x];
     }
+  } else {
+    for (int64_t i0 = threadIdx.x; i0 < nparts; i0 += (int64_t)kReduceGroup * kBlock) {
+      double v[N][kReduceGroup];
 #pragma unroll
-    for (int u = 0; u < kReduceGroup; ++u)
-      if (i0 + (int64_t)u * kBlock < nparts) s += v[u];
+      for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int u = 0; u < kReduceGroup; ++u) {
+          const int64_t i = i0 + (int64_t)u * kBlock;
+          v[k][u] = parts[k][i < nparts ? i : 0];
+        }
+#pragma unroll
+      for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int u = 0; u < kReduceGroup; ++u)
+          if (i0 + (int64_t)u * kBlock < nparts) s[k] += v[k][u];
+    }
   }
-  s = block_sum<kBlock>(s, lds);
-  if (threadIdx.x == 0) lds[kLds - 1] = s;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    s[k] = wave_sum(s[k]);
+    if (lane == 0) lds[k * W + w] = s[k];
+  }
   __syncthreads();
-  s = lds[kLds - 1];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double r = 0.0;
+#pragma unroll
+      for (int i = 0; i < W; ++i) r += lds[k * W + i];
+      lds[N * W + k] = r;
+    }
+  }
   __syncthreads();
-  return s;
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[k] = lds[N * W + k];
+  __syncthreads();
+}
+
+__device__ __forceinline__ double reduce_all(const double* parts, int64_t nparts, double* lds) {
+  const double* const pp[1] = {parts};
+  double out[1];
+  reduce_all_n<1>(pp, nparts, lds, out);
+  return out[0];
+}
+
+// Two or three sums at once (see reduce_all_n).
+__device__ __forceinline__ void reduce_all(const double* pa, const double* pb, int64_t nparts,
+                                           double* lds, double& a, double& b) {
+  const double* const pp[2] = {pa, pb};
+  double out[2];
+  reduce_all_n<2>(pp, nparts, lds, out);
+  a = out[0];
+  b = out[1];
+}
+__device__ __forceinline__ void reduce_all(const double* pa, const double* pb, const double* pc,
+                                           int64_t nparts, double* lds, double& a, double& b,
+                                           double& c) {
+  const double* const pp[3] = {pa, pb, pc};
+  double out[3];
+  reduce_all_n<3>(pp, nparts, lds, out);
+  a = out[0];
+  b = out[1];
+  c = out[2];
 }
 
 // PIPE: 0 for the plain stream walk, else the per-thread register depth U
