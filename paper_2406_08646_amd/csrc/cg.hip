@@ -173,9 +173,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, VT* __restrict_
                                                       const double* __restrict__ P1, int64_t G1,
                                                       double* __restrict__ P2, int64_t k) {
   __shared__ double lds[kLds];
-  if (st->done) return;
-  if (k <= 0) k = (int64_t)st->iters + 1;  // replayed launch: the iteration count is on the device
+  // the flag is tested once the partials are in: both loads are in flight
+  // together (after the solve stopped the partials are stale and unused)
+  const auto done = st->done;
   const double pq = reduce_all(P1, G1, lds);
+  if (done) return;
+  if (k <= 0) k = (int64_t)st->iters + 1;  // replayed launch: the iteration count is on the device
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->pq = pq;
@@ -220,10 +223,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, VT* __restrict
                                                        const double* __restrict__ P2, int64_t G2,
                                                        int64_t k) {
   __shared__ double lds[kLds];
-  if (st->done) return;
-  if (k <= 0) k = st->kcur;  // written by this iteration's update kernel
+  const auto done = st->done;  // tested once the partials are in
   double rz, rr;
   reduce_all(P2, P2 + G2, G2, lds, rz, rr);
+  if (done) return;
+  if (k <= 0) k = st->kcur;  // written by this iteration's update kernel
   const bool conv = sqrt(rr) <= st->thresh;
   const bool stop = conv || k >= st->maxit;
   const double rho_prev = st->rho[(k - 1) & 1];
@@ -317,8 +321,9 @@ __global__ __launch_bounds__(kBlock) void k_sr_update(int64_t n, double* __restr
                                                       int64_t G1, double* __restrict__ P2,
                                                       int64_t k) {
   __shared__ double lds[kLds];
-  if (st->done) return;
+  const auto done = st->done;  // tested once the partials are in
   const double delta = reduce_all(P1, G1, lds);
+  if (done) return;
   const double g1 = st->rho[(k - 1) & 1];
   double den = delta;
   if (k > 1) {
@@ -373,9 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_sr_spmv(int64_t n, const int32_t* __
                                                     int remap, int64_t tile, int64_t k, WinView win) {
   extern __shared__ __align__(16) char smem[];
   double* lds = reduction_lds<SH>(smem);
-  if (st->done) return;
+  const auto done = st->done;  // tested once the partials are in
   double gk, rr;
   reduce_all(P2, P2 + G2, G2, lds, gk, rr);
+  if (done) return;
   const bool conv = sqrt(rr) <= st->thresh;
   const bool stop = conv || k >= st->maxit;
   const double gprev = st->rho[(k - 1) & 1];
@@ -484,10 +490,11 @@ __global__ __launch_bounds__(kBlock) void k_pl_update(int64_t n, PlVectors v, Cg
                                                       const double* __restrict__ Pin, int64_t Gin,
                                                       double* __restrict__ Pout, int64_t k) {
   __shared__ double lds[kLds];
-  if (st->done) return;
-  const int64_t i = k - 1;
+  const auto done = st->done;  // tested once the partials are in
   double g, dl, rr;
   reduce_all(Pin, Pin + Gin, Pin + 2 * Gin, Gin, lds, g, dl, rr);
+  if (done) return;
+  const int64_t i = k - 1;
   const bool conv = sqrt(rr) <= st->thresh;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (conv || i >= st->maxit) {
