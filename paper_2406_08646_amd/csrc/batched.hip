@@ -88,10 +88,14 @@ __global__ __launch_bounds__(kBlock) void k_b_update(const BatchSys* __restrict_
                                                      double* __restrict__ P2, int64_t k) {
   __shared__ double lds[kLds];
   const int s = pl.sys(blockIdx.x);
-  if (s < 0 || st[s].done) return;
+  if (s < 0) return;
+  // the system's flag, team and partials are loaded together, the flag
+  // tested once the partials are in
+  const auto done = st[s].done;
   const int a = pl.start(s), T = pl.size(s);
   const int64_t j = blockIdx.x - a;
   const double pq = reduce_all(P1 + a, T, lds);
+  if (done) return;
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (j == 0 && threadIdx.x == 0) {
       st[s].pq = pq;
@@ -131,11 +135,13 @@ __global__ __launch_bounds__(kBlock) void k_b_pupdate(const BatchSys* __restrict
                                                       int64_t k) {
   __shared__ double lds[kLds];
   const int s = pl.sys(blockIdx.x);
-  if (s < 0 || st[s].done) return;
+  if (s < 0) return;
+  const auto done = st[s].done;  // tested once the partials are in
   const int a = pl.start(s), T = pl.size(s);
   const int64_t j = blockIdx.x - a;
   double rz, rr;
   reduce_all(P2 + a, P2 + pl.G + a, T, lds, rz, rr);
+  if (done) return;
   CgScalars& c = st[s];
   const bool conv = sqrt(rr) <= c.thresh;
   const bool stop = conv || k >= c.maxit;

@@ -132,10 +132,12 @@ __global__ __launch_bounds__(kBlock) void k_bb_update(const BatchSys* __restrict
                                                       double* __restrict__ P2, int64_t k) {
   __shared__ double lds[kLds];
   const int s = pl.sys(blockIdx.x);
-  if (s < 0 || st[s].done) return;
+  if (s < 0) return;
+  const auto done = st[s].done;  // tested once the partials are in
   const int a = pl.start(s), T = pl.size(s);
   const int64_t j = blockIdx.x - a;
   const double sigma = reduce_all(P1 + a, T, lds);
+  if (done) return;
   if (sigma == 0.0 || !isfinite(sigma)) {
     if (j == 0 && threadIdx.x == 0) {
       st[s].pq = sigma;
@@ -180,11 +182,13 @@ __global__ __launch_bounds__(kBlock) void k_bb_pupdate(const BatchSys* __restric
                                                        int64_t k) {
   __shared__ double lds[kLds];
   const int s = pl.sys(blockIdx.x);
-  if (s < 0 || st[s].done) return;
+  if (s < 0) return;
+  const auto done = st[s].done;  // tested once the partials are in
   const int a = pl.start(s), T = pl.size(s);
   const int64_t j = blockIdx.x - a;
   double rz, rr;
   reduce_all(P2 + a, P2 + pl.G + a, T, lds, rz, rr);
+  if (done) return;
   CgScalars& c = st[s];
   const bool conv = sqrt(rr) <= c.thresh;
   const bool broke = !conv && (rz == 0.0 || !isfinite(rz));
@@ -334,11 +338,13 @@ __global__ __launch_bounds__(kBlock) void k_tq_b(const BatchSys* __restrict__ sy
                                                  double* __restrict__ P1, int64_t j, int64_t pos) {
   __shared__ double lds[kLds];
   const int s = pl.sys(blockIdx.x);
-  if (s < 0 || tq_skip(st[s], pos)) return;
+  if (s < 0) return;
+  const bool skip = tq_skip(st[s], pos);  // tested once the partials are in
   const int a = pl.start(s), T = pl.size(s);
   const int64_t jb = blockIdx.x - a;
   CgScalars& c = st[s];
   const double sigma = reduce_all(P0 + a, T, lds);
+  if (skip) return;
   if (sigma == 0.0 || !isfinite(sigma)) {
     if (jb == 0 && threadIdx.x == 0) {
       c.pq = sigma;
@@ -396,11 +402,13 @@ __global__ __launch_bounds__(kBlock) void k_tq_c(const BatchSys* __restrict__ sy
   extern __shared__ __align__(16) char smem[];
   __shared__ double lds[kLds];
   const int s = pl.sys(blockIdx.x);
-  if (s < 0 || tq_skip(st[s], pos)) return;
+  if (s < 0) return;
+  const bool skip = tq_skip(st[s], pos);  // tested once the partials are in
   const int a = pl.start(s), T = pl.size(s);
   const int64_t jb = blockIdx.x - a;
   CgScalars& c = st[s];
   const double ww = reduce_all(P1 + a, T, lds);
+  if (skip) return;
   const double alpha = c.alpha;
   const TqStep h = tq_step(ww, c.tau[0], alpha);
   const int64_t ml = 2 * (j - c.j0) + 1;  // half-steps of this cycle
@@ -459,12 +467,14 @@ __global__ __launch_bounds__(kBlock) void k_tq_d(const BatchSys* __restrict__ sy
                                                  int64_t pos) {
   __shared__ double lds[kLds];
   const int s = pl.sys(blockIdx.x);
-  if (s < 0 || tq_skip(st[s], pos)) return;
+  if (s < 0) return;
+  const bool skip = tq_skip(st[s], pos);  // tested once the partials are in
   const int a = pl.start(s), T = pl.size(s);
   const int64_t jb = blockIdx.x - a;
   CgScalars& c = st[s];
   double ww, rho_new;
   reduce_all(P2 + a, P2 + pl.G + a, T, lds, ww, rho_new);
+  if (skip) return;
   const double alpha = c.alpha;
   const TqStep h = tq_step(ww, c.tau[1], alpha);
   const int64_t ml = 2 * (j - c.j0) + 2;
