@@ -480,12 +480,13 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *     16-bit window columns instead of the 32-bit ones; results bitwise
  *     those of the stream walk; only for patterns with a window index, see
  *     spx_get_window, else as 0).  Auto takes the window walk when the
- *     pattern has an index and at least 12 of its 256-row tiles per compute
- *     unit (7 when rows average at most 16 entries; smaller systems fill the
- *     chip better with the stream walk's smaller tiles), rows average at
- *     most 64 entries in every tile and
+ *     pattern has an index and enough 256-row tiles per compute unit
+ *     (smaller systems fill the chip better with the stream walk's smaller
+ *     tiles): for MatMult and MatMultTranspose 2.5, for the solvers 12 (7
+ *     when rows average at most 16 entries); and when rows average at most
+ *     64 entries in every tile and
  *     none of SPX_OPT_ROWS_PER_BLOCK, SPX_OPT_QUAD_LOADS, SPX_OPT_PIPELINE
- *     is set.  Reading the option returns the resolved variant.
+ *     is set.  Reading the option returns the variant MatMult resolves to.
  *   SPX_OPT_ROWS_PER_BLOCK: stream variant rows per workgroup (0 auto, else
  *     32, 64, 128 or 256).
  *   SPX_OPT_NONTEMPORAL: 1 (default) loads matrix values/columns

@@ -242,19 +242,19 @@ extern "C" int spx_get_option(spx_handle h, int32_t option, int64_t* value) {
   if (!h || !value) return set_error(SPX_INVALID_ARG, "get_option: NULL argument");
   switch (option) {
     case SPX_OPT_SPMV_LANES:
-      *value = spmv_shape(h, h->A).lanes;
+      *value = matmult_shape(h, h->A).lanes;
       return SPX_OK;
     case SPX_OPT_XCD_REMAP:
-      *value = remap_for(h, spmv_shape(h, h->A));
+      *value = remap_for(h, matmult_shape(h, h->A));
       return SPX_OK;
     case SPX_OPT_PROFILE:
       *value = h->profile;
       return SPX_OK;
     case SPX_OPT_SPMV_VARIANT:
-      *value = spmv_shape(h, h->A).variant;
+      *value = matmult_shape(h, h->A).variant;
       return SPX_OK;
     case SPX_OPT_ROWS_PER_BLOCK:
-      *value = spmv_shape(h, h->A).rows;
+      *value = matmult_shape(h, h->A).rows;
       return SPX_OK;
     case SPX_OPT_NONTEMPORAL:
       *value = h->nt_opt;

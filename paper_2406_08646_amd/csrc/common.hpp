@@ -252,8 +252,12 @@ int build_window(Csr& A, hipStream_t s);
 // cg.hip: the CG form (0 textbook, 1 single reduction) a solve on M takes
 int cg_form(const spx_matrix* h, const Csr& M);
 SpmvShape spmv_shape(const spx_matrix* h, const Csr& A);
-// allow_window = false: the shape the options give without the window walk
-SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window);
+// MatMult's shape: the window walk from fewer tiles than the solvers'
+SpmvShape matmult_shape(const spx_matrix* h, const Csr& A);
+// allow_window = false: the shape the options give without the window walk;
+// matmult: MatMult's threshold for the window walk
+SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window,
+                         bool matmult = false);
 SpmvShape spmv_shape32(const spx_matrix* h, const Csr& A);
 SpmvShape solver_shape(const spx_matrix* h, const Csr& A);
 int launch_spmv(const Csr& A, const SpmvShape& sh, const double* x, double* y, int remap,

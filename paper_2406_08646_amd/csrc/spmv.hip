@@ -501,14 +501,21 @@ namespace {
 // stream walk more; and whose rows average at most 64 entries in every tile
 // (one thread adds each row).  It needs no tile in LDS, so it also takes
 // patterns whose tiles exceed the stream walk's limit.
+// MatMult's own kernel (one tile per workgroup, a tile's loads issued
+// together) gains from the window walk from fewer tiles: 2.5 per compute
+// unit (measured crossover between 1.7 and 2.7 on 27-point patterns, about
+// 2 on 9-point ones).
 constexpr int64_t kWinAutoTilesPerCu = 12;
 constexpr int64_t kWinAutoTilesPerCuShortRows = 7;
-bool window_shape(const spx_matrix* h, const Csr& A, bool allow, SpmvShape& sh) {
+constexpr int64_t kWinAutoHalfTilesPerCuMatMult = 5;
+bool window_shape(const spx_matrix* h, const Csr& A, bool allow, bool matmult, SpmvShape& sh) {
   if (!allow || !A.win.lcol) return false;
   const int want = h ? h->variant_opt : 0;
   const bool tuned = h && (h->rows_opt || h->vec_opt || h->pipe_opt);
   const int64_t per_cu = A.nnz <= 16 * A.n ? kWinAutoTilesPerCuShortRows : kWinAutoTilesPerCu;
-  const bool large = ceil_div(A.n, kWinRows) >= per_cu * cu_count();
+  const int64_t tiles = ceil_div(A.n, kWinRows);
+  const bool large = matmult ? 2 * tiles >= kWinAutoHalfTilesPerCuMatMult * cu_count()
+                             : tiles >= per_cu * cu_count();
   if (want == kVariantWindow || (want == kVariantAuto && !tuned && large &&
                                  A.tile_nnz[3] <= 64 * (int64_t)kWinRows)) {
     sh.variant = kVariantWindow;
@@ -525,7 +532,11 @@ bool window_shape(const spx_matrix* h, const Csr& A, bool allow, SpmvShape& sh) 
 
 SpmvShape spmv_shape(const spx_matrix* h, const Csr& A) { return spmv_shape_for(h, A, true); }
 
-SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window) {
+SpmvShape matmult_shape(const spx_matrix* h, const Csr& A) {
+  return spmv_shape_for(h, A, true, true);
+}
+
+SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window, bool matmult) {
   SpmvShape sh;
   sh.lanes = pick_lanes(A, h ? h->lanes_opt : 0);
   sh.nt = h ? h->nt_opt : 1;
@@ -537,7 +548,7 @@ SpmvShape spmv_shape_for(const spx_matrix* h, const Csr& A, bool allow_window) {
   sh.tile = 0;
   const int want = h ? h->variant_opt : 0;
   if (want == kVariantVector) return sh;
-  if (window_shape(h, A, allow_window, sh)) return sh;
+  if (window_shape(h, A, allow_window, matmult, sh)) return sh;
   const int rows_opt = h ? h->rows_opt : 0;
   if (want == kVariantDma) {
     // two staging buffers per workgroup in the solver kernels
@@ -700,7 +711,7 @@ extern "C" int spx_matmult(spx_handle h, const double* x, double* y, void* strea
   if (!h || !x || !y) return set_error(SPX_INVALID_ARG, "matmult: NULL argument");
   if (x == y) return set_error(SPX_INVALID_ARG, "matmult: x and y must not alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const SpmvShape sh = spmv_shape(h, h->A);
+  const SpmvShape sh = matmult_shape(h, h->A);
   SPX_TRY(launch_spmv(h->A, sh, x, y, remap_for(h, sh), s));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
@@ -712,7 +723,7 @@ extern "C" int spx_matmult_transpose(spx_handle h, const double* x, double* y, v
   if (x == y) return set_error(SPX_INVALID_ARG, "matmult_transpose: x and y must not alias");
   hipStream_t s = static_cast<hipStream_t>(stream);
   SPX_TRY(ensure_transpose(h, s));
-  const SpmvShape sh = spmv_shape(h, h->At);
+  const SpmvShape sh = matmult_shape(h, h->At);
   SPX_TRY(launch_spmv(h->At, sh, x, y, remap_for(h, sh), s));
   SPX_CHECK_HIP(hipGetLastError());
   return SPX_OK;
