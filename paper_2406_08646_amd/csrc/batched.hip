@@ -205,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void k_b_cg_persistent(
       dinv[o + i] = d == 0.0 ? 0.0 : 1.0 / d;
     }
     __syncthreads();
-    one::cg_solve<BLOCK, ROWS>(S.n, S.rowptr, S.col, S.val, bvec + o, x + o, r + o, p + o, q + o,
+    one::cg_solve<BLOCK, ROWS, true>(S.n, S.rowptr, S.col, S.val, bvec + o, x + o, r + o, p + o, q + o,
                                dinv + o, zero ? SPX_ZERO_DIAGONAL : SPX_OK, st[s].maxit, rtol,
                                st + s, reinterpret_cast<double*>(smem), lds);
     __syncthreads();  // `pick` and `zero` read by every thread before thread 0 rewrites them

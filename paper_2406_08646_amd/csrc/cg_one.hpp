@@ -36,7 +36,10 @@ __device__ __forceinline__ double allsum(double v, double* lds) {
 // work vectors.  status0 / maxit: the solve's entry status (a nonzero one,
 // e.g. a zero diagonal, stops it before any iteration) and iteration limit.
 // Thread 0 stores the outcome in *st (done = 1).
-template <int BLOCK, int ROWS>
+// EAGER: the products' loads issued together (stream_rows): faster with
+// many workgroups solving at once (the persistent batch), not for one
+// system alone.
+template <int BLOCK, int ROWS, bool EAGER = false>
 __device__ __forceinline__ void cg_solve(int64_t n, const int32_t* __restrict__ rowptr,
                                          const int32_t* __restrict__ col,
                                          const double* __restrict__ val,
@@ -51,7 +54,7 @@ __device__ __forceinline__ void cg_solve(int64_t n, const int32_t* __restrict__ 
   double rz = 0.0, rr = 0.0, bb = 0.0;
   for (int64_t r0 = 0; r0 < n; r0 += ROWS) {
     const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
-    const double ax = stream_rows<BLOCK, 8, double, double, double, false>(rowptr, col, val, x, r0,
+    const double ax = stream_rows<BLOCK, 8, double, double, double, false, EAGER>(rowptr, col, val, x, r0,
                                                                            r1, prod);
     if (tid < r1 - r0) {
       const int64_t row = r0 + tid;
@@ -85,7 +88,7 @@ __device__ __forceinline__ void cg_solve(int64_t n, const int32_t* __restrict__ 
     double pqs = 0.0;
     for (int64_t r0 = 0; r0 < n; r0 += ROWS) {
       const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
-      const double s = stream_rows<BLOCK, 8, double, double, double, false>(rowptr, col, val, p,
+      const double s = stream_rows<BLOCK, 8, double, double, double, false, EAGER>(rowptr, col, val, p,
                                                                             r0, r1, prod);
       if (tid < r1 - r0) {
         q[r0 + tid] = s;

@@ -51,11 +51,65 @@ __device__ __forceinline__ ACC row_partial(const int32_t* __restrict__ rowptr,
   return acc;
 }
 
+// K members of a chunk of the stream walk per thread (member u of thread t
+// is entry base + u * BLOCK + t): values and columns, then the gathers of
+// x, then the products into prod.  Every load is issued, a member past the
+// tile loading the tile's last entry again (unused): a gather left under a
+// data-dependent branch waited for every load before it, one round trip
+// per member.  K is the number of members the chunk reaches, so whole
+// waves past the tile issue nothing.
+template <int K, int BLOCK, typename VT, typename XT, typename ACC, bool NT>
+__device__ __forceinline__ void stream_chunk(const int32_t* __restrict__ col,
+                                             const VT* __restrict__ val,
+                                             const XT* __restrict__ x, int32_t t0, int32_t cnt,
+                                             int32_t base, ACC* prod) {
+  const int tid = threadIdx.x;
+  VT a[K];
+  int32_t c[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int32_t i = base + u * BLOCK + tid, ic = i < cnt ? i : cnt - 1;
+    a[u] = mload<NT>(val + t0 + ic);
+    c[u] = mload<NT>(col + t0 + ic);
+  }
+  XT xv[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) xv[u] = x[c[u]];
+  // all gathers in registers here: one sunk into the branch of its store
+  // would wait for the loads before it again
+#pragma unroll
+  for (int u = 0; u < K; ++u) asm volatile("" : "+v"(xv[u]));
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int32_t i = base + u * BLOCK + tid;
+    if (i < cnt) prod[i] = (ACC)a[u] * (ACC)xv[u];
+  }
+}
+
+// stream_chunk with K = k (1 <= k <= KMAX, the same in every thread).
+template <int KMAX, int BLOCK, typename VT, typename XT, typename ACC, bool NT>
+__device__ __forceinline__ void stream_chunk_k(int k, const int32_t* __restrict__ col,
+                                               const VT* __restrict__ val,
+                                               const XT* __restrict__ x, int32_t t0,
+                                               int32_t cnt, int32_t base, ACC* prod) {
+  if constexpr (KMAX >= 1) {
+    if (k == KMAX)
+      stream_chunk<KMAX, BLOCK, VT, XT, ACC, NT>(col, val, x, t0, cnt, base, prod);
+    else
+      stream_chunk_k<KMAX - 1, BLOCK, VT, XT, ACC, NT>(k, col, val, x, t0, cnt, base, prod);
+  }
+}
+
 // Rows [r0, r1) of one workgroup of BLOCK threads (r1 - r0 <= BLOCK); the
 // products of the rows' entries are staged in `prod` (LDS, at least
 // rowptr[r1] - rowptr[r0] elements).  Returns, in thread t < r1 - r0, the
 // sum of row r0 + t (entries added in order); other threads get 0.
-template <int BLOCK, int U, typename VT, typename XT, typename ACC, bool NT = false>
+// EAGER: every load of a chunk issued together (stream_chunk).  It makes
+// the one-workgroup solvers' iterations faster; the grid kernels (MatMult
+// on small patterns, the solvers' persistent SpMV kernels) measured as
+// fast or slower with it, so they keep the plain form.
+template <int BLOCK, int U, typename VT, typename XT, typename ACC, bool NT = false,
+          bool EAGER = false>
 __device__ __forceinline__ ACC stream_rows(const int32_t* __restrict__ rowptr,
                                            const int32_t* __restrict__ col,
                                            const VT* __restrict__ val, const XT* __restrict__ x,
@@ -63,31 +117,54 @@ __device__ __forceinline__ ACC stream_rows(const int32_t* __restrict__ rowptr,
   const int tid = threadIdx.x;
   const int32_t t0 = rowptr[r0];
   const int32_t cnt = rowptr[r1] - t0;
-  for (int32_t base = 0; base < cnt; base += BLOCK * U) {
-    VT a[U];
-    int32_t c[U];
+  if constexpr (EAGER) {
+    // this thread's row bounds, loaded with the tile's (held in registers so
+    // that their loads are not left until after the barrier), and every
+    // chunk's loads issued together (stream_chunk)
+    const bool own = tid < r1 - r0;
+    const int64_t ri = own ? r0 + tid : r0;
+    int32_t ra = rowptr[ri], re = rowptr[ri + 1];
+    asm volatile("" : "+v"(ra), "+v"(re));
+    for (int32_t base = 0; base < cnt; base += BLOCK * U) {
+      const int32_t left = cnt - base;
+      stream_chunk_k<U, BLOCK, VT, XT, ACC, NT>(
+          left >= BLOCK * U ? U : (int)((left + BLOCK - 1) / BLOCK), col, val, x, t0, cnt, base,
+          prod);
+    }
+    __syncthreads();
+    ACC s = ACC(0);
+    if (own) {
+      for (int32_t i = ra - t0; i < re - t0; ++i) s += prod[i];
+    }
+    __syncthreads();  // prod is reused by the caller's next tile
+    return s;
+  } else {
+    for (int32_t base = 0; base < cnt; base += BLOCK * U) {
+      VT a[U];
+      int32_t c[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t i = base + u * BLOCK + tid;
-      if (i < cnt) {
-        a[u] = mload<NT>(val + t0 + i);
-        c[u] = mload<NT>(col + t0 + i);
+      for (int u = 0; u < U; ++u) {
+        const int32_t i = base + u * BLOCK + tid;
+        if (i < cnt) {
+          a[u] = mload<NT>(val + t0 + i);
+          c[u] = mload<NT>(col + t0 + i);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t i = base + u * BLOCK + tid;
+        if (i < cnt) prod[i] = (ACC)a[u] * (ACC)x[c[u]];
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t i = base + u * BLOCK + tid;
-      if (i < cnt) prod[i] = (ACC)a[u] * (ACC)x[c[u]];
+    __syncthreads();
+    ACC s = ACC(0);
+    if (tid < r1 - r0) {
+      const int32_t a = rowptr[r0 + tid] - t0, e = rowptr[r0 + tid + 1] - t0;
+      for (int32_t i = a; i < e; ++i) s += prod[i];
     }
+    __syncthreads();  // prod is reused by the caller's next tile
+    return s;
   }
-  __syncthreads();
-  ACC s = ACC(0);
-  if (tid < r1 - r0) {
-    const int32_t a = rowptr[r0 + tid] - t0, e = rowptr[r0 + tid + 1] - t0;
-    for (int32_t i = a; i < e; ++i) s += prod[i];
-  }
-  __syncthreads();  // prod is reused by the caller's next tile
-  return s;
 }
 
 // Vector types for 16-byte loads.
