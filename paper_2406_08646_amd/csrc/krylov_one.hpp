@@ -27,8 +27,8 @@ __device__ __forceinline__ void walk(int64_t n, const int32_t* __restrict__ rowp
                                      double* prod, F&& f) {
   for (int64_t r0 = 0; r0 < n; r0 += ROWS) {
     const int64_t r1 = r0 + ROWS < n ? r0 + ROWS : n;
-    const double s =
-        stream_rows<BLOCK, 8, double, double, double, false, true>(rowptr, col, val, v, r0, r1, prod);
+    const double s = stream_rows<BLOCK, kOneDepth<true>, double, double, double, false, true>(
+        rowptr, col, val, v, r0, r1, prod);
     if (threadIdx.x < r1 - r0) f(r0 + threadIdx.x, s);
   }
 }

@@ -559,10 +559,10 @@ __device__ __forceinline__ ACC window_rows(const int32_t* __restrict__ rowptr,
     re = own ? rowptr[r0 + tid + 1] - ta : 0;
   }
   if (nbk > 0)
-    return window_chunks<true, EAGER, U, V, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0, nbk, t0,
-                                                             t1, ra, re, prod);
-  return window_chunks<false, EAGER, U, V, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk, t0, t1,
-                                                            ra, re, prod);
+    return window_chunks<true, EAGER, U, V, BLOCK, VT, XT, ACC, NT>(w.lcol, val, x, n, w.blk, k0,
+                                                                    nbk, t0, t1, ra, re, prod);
+  return window_chunks<false, EAGER, U, V, BLOCK, VT, XT, ACC, NT>(col, val, x, n, w.blk, k0, nbk,
+                                                                   t0, t1, ra, re, prod);
 }
 
 // LDS bytes of the window walk with chunks of kWinRows * per_thread
