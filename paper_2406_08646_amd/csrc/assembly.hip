@@ -784,6 +784,19 @@ extern "C" int spx_coo_preallocate(int64_t n, int64_t ncoo, const int32_t* i, co
   return SPX_OK;
 }
 
+namespace spx {
+int set_values_into(spx_handle h, const double* v, int mode, double* out, hipStream_t s) {
+  const int64_t nnz = h->A.nnz;
+  if (nnz > 0) {
+    const int ents = sv_entries(h->nvalid, nnz);
+    hipLaunchKernelGGL(k_set_values_tiled, dim3(grid_for(nnz, ents)), dim3(256), 0, s, h->jmap,
+                       h->perm, v, nnz, mode, ents, out);
+  }
+  SPX_CHECK_HIP(hipGetLastError());
+  return SPX_OK;
+}
+}  // namespace spx
+
 extern "C" int spx_set_values_coo(spx_handle h, const double* v, int mode, void* stream) {
   clear_error();
   if (!h) return set_error(SPX_INVALID_ARG, "set_values_coo: NULL handle");

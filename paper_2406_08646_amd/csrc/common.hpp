@@ -249,6 +249,9 @@ int pick_lanes(const Csr& A, int opt);
 int compute_tiles(Csr& A, hipStream_t s);
 // window.hip
 int build_window(Csr& A, hipStream_t s);
+// assembly.hip: the numeric stage of h's pattern into out (nnz entries) in
+// mode (SPX_INSERT_VALUES or SPX_ADD_VALUES); h's own values are untouched
+int set_values_into(spx_handle h, const double* v, int mode, double* out, hipStream_t s);
 // cg.hip: the CG form (0 textbook, 1 single reduction) a solve on M takes
 int cg_form(const spx_matrix* h, const Csr& M);
 SpmvShape spmv_shape(const spx_matrix* h, const Csr& A);

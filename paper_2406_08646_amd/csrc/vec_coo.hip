@@ -55,8 +55,14 @@ extern "C" int spx_vec_set_values_coo(spx_vec_handle h, const double* v, int mod
   if (mode != SPX_INSERT_VALUES && mode != SPX_ADD_VALUES)
     return set_error(SPX_INVALID_ARG, "vec_set_values_coo: mode %d is not INSERT(0) or ADD(1)",
                      mode);
-  SPX_TRY(spx_set_values_coo(h->m, v, SPX_INSERT_VALUES, stream));
+  if (h->m->nvalid > 0 && !v) return set_error(SPX_INVALID_ARG, "vec_set_values_coo: v is NULL");
   const int64_t cnt = h->m->A.nnz;
+  if (cnt == h->m->n) {
+    // every index is present: entry k of the pattern is x[k], so the sums
+    // go straight into x (no scatter)
+    return set_values_into(h->m, v, mode, x, static_cast<hipStream_t>(stream));
+  }
+  SPX_TRY(spx_set_values_coo(h->m, v, SPX_INSERT_VALUES, stream));
   if (cnt > 0)
     hipLaunchKernelGGL(k_vec_scatter, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), h->m->A.col, h->m->A.val, cnt, mode, x);

@@ -166,6 +166,27 @@ def test_vec_coo_bitwise(orc, n, ncoo, seed):
     assert e.value.code == spx.INDEX_OUT_OF_RANGE
 
 
+@pytest.mark.parametrize("n,extra,seed", [(1, 3, 5), (3000, 9000, 6), (70000, 300000, 7)])
+def test_vec_coo_full_pattern_bitwise(orc, n, extra, seed):
+    """Every index present (the sums then go straight into x, with no
+    scatter): INSERT then ADD, bitwise the oracle's."""
+    spx = require_gpu()
+    rng = np.random.default_rng(seed)
+    i = np.concatenate([np.arange(n), rng.integers(0, n, extra)]).astype(np.int32)
+    i = i[rng.permutation(i.size)]
+    v = rng.uniform(-1, 1, i.size)
+    x0 = rng.uniform(-1, 1, n)
+    V = spx.vec_coo_preallocate(n, dev(i))
+    assert V.get_info()["nunique"] == n
+    x = dev(x0)
+    V.set_values_coo(dev(v), x)
+    assert np.array_equal(bits(host(x)), bits(orc.vec_coo(n, i, v, x0)))
+    v2 = rng.uniform(-1, 1, i.size)
+    V.set_values_coo(dev(v2), x, mode=spx.ADD_VALUES)
+    want = orc.vec_coo(n, i, v2, orc.vec_coo(n, i, v, x0), mode=1)
+    assert np.array_equal(bits(host(x)), bits(want))
+
+
 def rows_of_lengths(rng, n, lengths, ncols_pool=None):
     """A COO stream whose row r holds lengths[r] triplets (rows in a random
     order, triplets of one row scattered through the stream), columns drawn
