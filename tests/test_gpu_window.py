@@ -232,6 +232,38 @@ def test_window_option_resolution(orc):
         B.set_option(spx.OPT_SPMV_VARIANT, 5)
 
 
+def test_matmult_window_threshold(orc):
+    """MatMult takes the window walk from 2.5 tiles of 256 rows per compute
+    unit (its loads go out together), the solvers from 12: on the 3-D Q1
+    operator with 58^3 nodes (about 3 tiles per CU on 256 CUs) MatMult
+    reports and runs the window walk, bitwise the oracle's product and
+    transposed product, and CG on the solvers' own walk still matches the
+    oracle's residual bound."""
+    spx = require_gpu()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    N = 57
+    prob = W.q1_poisson(N, 3)
+    n = prob.n
+    tiles = (n + 255) // 256
+    assert 2.5 * cus <= tiles < 12 * cus
+    A = assemble(spx, prob)
+    assert A.get_window()["built"] and A.get_option(spx.OPT_SPMV_VARIANT) == 4
+    ref = orc.assemble(n, prob.i, prob.j, prob.v)
+    x = np.random.default_rng(97).uniform(-1, 1, n)
+    assert np.array_equal(bits(host(A.matmult(dev(x)))), bits(orc.spmv(ref, x)))
+    refT = orc.assemble(n, prob.j, prob.i, prob.v)
+    assert np.array_equal(bits(host(A.matmult_transpose(dev(x)))), bits(orc.spmv(refT, x)))
+    b_h = np.random.default_rng(98).uniform(-1, 1, n)
+    r = A.cg_solve(dev(b_h), rtol=1e-10)
+    assert r.status == 0
+    res = b_h - orc.spmv(ref, host(r.x))
+    assert np.linalg.norm(res) <= 2e-10 * np.linalg.norm(b_h)
+    # half as many tiles: MatMult keeps the stream walk
+    small = assemble(spx, W.q1_poisson(45, 3))
+    if (small.n + 255) // 256 < 2.5 * cus:
+        assert small.get_option(spx.OPT_SPMV_VARIANT) != 4
+
+
 def stencil_problem(shape, offsets, seed):
     n = int(np.prod(shape))
     idx = np.arange(n).reshape(shape)
