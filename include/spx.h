@@ -547,9 +547,11 @@ int spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free, void* ctx);
  *   SPX_OPT_SPMM_TILE_ROWS: rows per tile of the staged 16-column product
  *     of spx_spmm (16, 32 or 64; 0 = default 32): each tile's distinct rows
  *     of X are staged in LDS, so the height trades the rows of X staged per
- *     matrix row against the workgroups that fit per CU.  The tiles' index
- *     is rebuilt on the next product after a change.  Results are the same
- *     bits at every height. */
+ *     matrix row against the workgroups that fit per CU (32-row tiles run
+ *     pipelined: two LDS buffers per workgroup, the next tile's rows of X
+ *     loading while the current tile's products are formed).  The tiles'
+ *     index is rebuilt on the next product after a change.  Results are the
+ *     same bits at every height. */
 enum spx_option {
   SPX_OPT_SPMV_LANES = 1,
   SPX_OPT_XCD_REMAP = 2,

@@ -17,6 +17,8 @@
 // (16, 32 or 64 rows; SPX_OPT_SPMM_TILE_ROWS, 32 by default).
 #include <algorithm>
 
+#include <utility>
+
 #include "common.hpp"
 #include "device.hpp"
 
@@ -170,6 +172,15 @@ __device__ __forceinline__ double rs_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, true);
 }
 
+template <int J>
+__device__ __forceinline__ int rs_bcast_i(int v) {
+  return rs_bcast<J>(v);
+}
+template <int J>
+__device__ __forceinline__ double rs_bcast_d(double v) {
+  return rs_bcast<J>(v);
+}
+
 // Entries J..J+3 of a chunk into s, in entry order.
 template <int J>
 __device__ __forceinline__ void rs_entries(double va, int ca, double vb, int cb,
@@ -197,6 +208,36 @@ __device__ __forceinline__ void rs_chunk(int m, double va, int ca, double vb, in
     if (J < m) {
       rs_entries<J>(va, ca, vb, cb, xl, s);
       rs_chunk<J + 4>(m, va, ca, vb, cb, xl, s);
+    }
+  }
+}
+
+// Entries J..J+7 of a chunk into s, in entry order: eight LDS reads in
+// flight before the first add, for the pipelined form's fewer waves.
+template <int J, int... K>
+__device__ __forceinline__ void rs_entries8_(double va, int ca, double vb, int cb,
+                                             const char* __restrict__ xl, double& s,
+                                             std::integer_sequence<int, K...>) {
+  const double x[8] = {*reinterpret_cast<const double*>(
+      xl + ((J + K < 16) ? rs_bcast_i<(J + K) & 15>(ca) : rs_bcast_i<(J + K) & 15>(cb)))...};
+  const double v[8] = {((J + K < 16) ? rs_bcast_d<(J + K) & 15>(va)
+                                     : rs_bcast_d<(J + K) & 15>(vb))...};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += v[k] * x[k];
+}
+template <int J>
+__device__ __forceinline__ void rs_entries8(double va, int ca, double vb, int cb,
+                                            const char* __restrict__ xl, double& s) {
+  rs_entries8_<J>(va, ca, vb, cb, xl, s, std::make_integer_sequence<int, 8>{});
+}
+
+template <int J>
+__device__ __forceinline__ void rs_chunk8(int m, double va, int ca, double vb, int cb,
+                                          const char* __restrict__ xl, double& s) {
+  if constexpr (J < 32) {
+    if (J < m) {
+      rs_entries8<J>(va, ca, vb, cb, xl, s);
+      rs_chunk8<J + 8>(m, va, ca, vb, cb, xl, s);
     }
   }
 }
@@ -300,6 +341,176 @@ __global__ __launch_bounds__(ROWS * kRpLanes) __attribute__((amdgpu_waves_per_eu
   Y[row * 16 + lane] = s;
 }
 
+// The pipelined form of the product (32-row tiles): a persistent grid of
+// two workgroups per CU, each with two LDS buffers of the tile's rows of X.
+// While a workgroup forms the products of one tile from one buffer, the
+// next tile's rows of X are already loading into the other by direct
+// global-to-LDS loads (lane l of a wave writes 16 bytes at the wave's base +
+// 16 l, so they take no registers), with that tile's first chunk of entries
+// and the list and row bounds of the tile after it.  The two buffers are
+// separate arrays, so the products' LDS reads wait only for LDS; they go
+// eight at a time (rs_chunk8) for the fewer waves.  Every tile's products
+// are those of k_spmm_rowset, bitwise (tested).  On the 128^3-node operator
+// 0.337-0.342 ms against 0.353 for k_spmm_rowset<32>.
+struct RsNext {      // list and row bounds of a tile whose X is still to load
+  int d;
+  int32_t t0, t1;
+  int32_t lst[(RsShape<32>::kMax * 8 + 511) / 512];
+};
+struct RsCur {       // a tile whose X is loading or loaded
+  int d;
+  int32_t t0;
+  int len;
+  double va, vb;
+  int pa, pb;
+};
+
+// Loads (issues) the list and this thread's row bounds of tile b; d = -2
+// when there is no tile b.  Every load is unconditional (tile and row
+// clamped to the last), so none of them is held back by a branch and the
+// results need no copies at a join, which would wait for them.
+template <int ROWS>
+__device__ __forceinline__ void rsp_next(int64_t n, const int32_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ ucol, int64_t b,
+                                         int64_t tiles, RsNext& nx) {
+  constexpr int MAX = RsShape<ROWS>::kMax;
+  constexpr int BLOCK = ROWS * kRpLanes;
+  constexpr int XQ = (MAX * 8 + BLOCK - 1) / BLOCK;
+  const int64_t bc = b < tiles ? b : tiles - 1;
+  const int32_t* list = ucol + bc * (MAX + 1);
+  const int d = list[0];
+  nx.d = b < tiles ? d : -2;
+#pragma unroll
+  for (int u = 0; u < XQ; ++u) {
+    const int q = threadIdx.x + u * BLOCK;
+    nx.lst[u] = list[1 + (q < MAX * 8 ? q : MAX * 8 - 1) / 8];
+  }
+  const int64_t row = bc * ROWS + threadIdx.x / kRpLanes;
+  const int64_t rr = row < n ? row : n - 1;
+  const int32_t t0 = rowptr[rr], t1 = rowptr[rr + 1];
+  nx.t0 = t0;
+  nx.t1 = row < n ? t1 : t0;
+}
+
+// Issues the direct loads of tile nx's rows of X into buf (a staged tile)
+// and the loads of its first chunk of entries into cu (always, from valid
+// addresses).
+template <int ROWS>
+__device__ __forceinline__ void rsp_issue(const RsNext& nx, const double* __restrict__ val,
+                                          const uint16_t* __restrict__ lidx,
+                                          const double* __restrict__ X, rs_d2* buf, RsCur& cu) {
+  constexpr int MAX = RsShape<ROWS>::kMax;
+  constexpr int BLOCK = ROWS * kRpLanes;
+  constexpr int XQ = (MAX * 8 + BLOCK - 1) / BLOCK;
+  const int lane = threadIdx.x % kRpLanes;
+  cu.d = nx.d;
+  cu.t0 = nx.t0;
+  cu.len = nx.t1 - nx.t0;
+  const rs_d2* X2 = reinterpret_cast<const rs_d2*>(X);
+  const int wv = threadIdx.x >> 6;
+  const int nq = nx.d > 0 ? nx.d * 8 : 0;
+#pragma unroll
+  for (int u = 0; u < XQ; ++u) {
+    const int q = threadIdx.x + u * BLOCK;
+    if (q < nq)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(X2 + (int64_t)nx.lst[u] * 8 + q % 8),
+          (__attribute__((address_space(3))) void*)(buf + u * BLOCK + wv * 64), 16, 0, 0);
+  }
+  const bool ha = lane < cu.len, hb = kRpLanes + lane < cu.len;
+  const int32_t ia = ha ? cu.t0 + lane : cu.t0, ib = hb ? cu.t0 + kRpLanes + lane : cu.t0;
+  cu.va = stream_load(val + ia);
+  cu.vb = stream_load(val + ib);
+  cu.pa = lidx[ia];
+  cu.pb = lidx[ib];
+}
+
+// The products of tile b (state cu, rows of X in buf when staged).
+template <int ROWS>
+__device__ __forceinline__ void rsp_products(int64_t n, int64_t b, const RsCur& cu,
+                                             const int32_t* __restrict__ col,
+                                             const double* __restrict__ val,
+                                             const uint16_t* __restrict__ lidx,
+                                             const double* __restrict__ X,
+                                             double* __restrict__ Y, const rs_d2* buf) {
+  constexpr int MAX = RsShape<ROWS>::kMax;
+  const int64_t row = b * ROWS + threadIdx.x / kRpLanes;
+  const int lane = threadIdx.x % kRpLanes;
+  if (row >= n) return;
+  double s = 0.0;
+  if (cu.d >= 0) {
+    const int len = cu.len;
+    const bool ha = lane < len, hb = kRpLanes + lane < len;
+    double va = ha ? cu.va : 0.0, vb = hb ? cu.vb : 0.0;
+    int ca = (ha ? cu.pa : MAX) * kRpRow, cb = (hb ? cu.pb : MAX) * kRpRow;
+    const char* xl = reinterpret_cast<const char*>(buf) + lane * 8;
+    for (int base = 0;;) {
+      rs_chunk8<0>(len - base, va, ca, vb, cb, xl, s);
+      base += 2 * kRpLanes;
+      if (base >= len) break;
+      rs_load_chunk(val, lidx, cu.t0, len, base, lane, MAX, va, ca, vb, cb);
+    }
+  } else {
+    for (int32_t t = cu.t0; t < cu.t0 + cu.len; ++t)
+      s += val[t] * X[(int64_t)col[t] * 16 + lane];
+  }
+  Y[row * 16 + lane] = s;
+}
+
+// One step of the pipeline for tile b, whose rows of X the step before
+// issued into cur (state cu) with the list of tile b + step (nx): wait for
+// them, issue tile b + step's rows of X into nxt (state cn) and the list of
+// tile b + 2 step (into nn), then form b's products from cur.  The kernel
+// alternates two sets of state so that none is copied while its loads are
+// in flight.
+template <int ROWS>
+__device__ __forceinline__ void rsp_step(int64_t n, const int32_t* __restrict__ rowptr,
+                                         const int32_t* __restrict__ col,
+                                         const double* __restrict__ val,
+                                         const int32_t* __restrict__ ucol,
+                                         const uint16_t* __restrict__ lidx,
+                                         const double* __restrict__ X, double* __restrict__ Y,
+                                         int64_t b, int64_t step, int64_t tiles, const RsCur& cu,
+                                         RsCur& cn, const RsNext& nx, RsNext& nn,
+                                         const rs_d2* cur, rs_d2* nxt) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();  // b's X in cur; every thread done with nxt's last tile
+  rsp_issue<ROWS>(nx, val, lidx, X, nxt, cn);
+  rsp_next<ROWS>(n, rowptr, ucol, b + 2 * step, tiles, nn);
+  rsp_products<ROWS>(n, b, cu, col, val, lidx, X, Y, cur);
+}
+
+template <int ROWS>
+__global__ __launch_bounds__(ROWS * kRpLanes) void k_spmm_rowset_pipe(
+    int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const int32_t* __restrict__ ucol,
+    const uint16_t* __restrict__ lidx, const double* __restrict__ X, double* __restrict__ Y) {
+  constexpr int MAX = RsShape<ROWS>::kMax;
+  static_assert(ROWS == 32, "the pipelined form is built for 32-row tiles");
+  __shared__ rs_d2 xa[(MAX + 1) * 8];
+  __shared__ rs_d2 xb[(MAX + 1) * 8];
+  const int64_t tiles = ceil_div(n, ROWS), step = gridDim.x;
+  if (threadIdx.x < 8) {
+    xa[MAX * 8 + threadIdx.x] = rs_d2{0.0, 0.0};
+    xb[MAX * 8 + threadIdx.x] = rs_d2{0.0, 0.0};
+  }
+  RsNext na, nb;
+  RsCur ca, cb;
+  int64_t b = blockIdx.x;
+  rsp_next<ROWS>(n, rowptr, ucol, b, tiles, na);
+  __builtin_amdgcn_s_waitcnt(0);
+  rsp_issue<ROWS>(na, val, lidx, X, xa, ca);
+  rsp_next<ROWS>(n, rowptr, ucol, b + step, tiles, nb);
+  for (;;) {
+    if (b >= tiles) break;
+    rsp_step<ROWS>(n, rowptr, col, val, ucol, lidx, X, Y, b, step, tiles, ca, cb, nb, na, xa, xb);
+    b += step;
+    if (b >= tiles) break;
+    rsp_step<ROWS>(n, rowptr, col, val, ucol, lidx, X, Y, b, step, tiles, cb, ca, na, nb, xb, xa);
+    b += step;
+  }
+}
+
 template <int ROWS>
 int build_rowset_t(Csr& A, hipStream_t s) {
   RowSet& R = A.rs;
@@ -350,12 +561,24 @@ int launch_spmm_rowset(const Csr& A, const double* X, double* Y, hipStream_t s) 
     hipLaunchKernelGGL(k, dim3((unsigned)ceil_div(A.n, rows)), dim3(rows * kRpLanes), 0, s, A.n,
                        A.rowptr, A.col, A.val, R.col, R.lidx, X, Y);
   };
-  if (R.rows == 16)
+  if (R.rows == 16) {
     go(k_spmm_rowset<16>, 16);
-  else if (R.rows == 64)
+  } else if (R.rows == 64) {
     go(k_spmm_rowset<64>, 64);
-  else
-    go(k_spmm_rowset<32>, 32);
+  } else {
+    // 32-row tiles: the pipelined form, a persistent grid of the workgroups
+    // that fit at once (two per CU with its two 40 KB buffers)
+    int fit = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &fit, reinterpret_cast<const void*>(&k_spmm_rowset_pipe<32>), 32 * kRpLanes, 0) !=
+            hipSuccess ||
+        fit < 1)
+      fit = 1;
+    (void)hipGetLastError();
+    const int64_t grid = std::min<int64_t>(ceil_div(A.n, 32), (int64_t)fit * cu_count());
+    hipLaunchKernelGGL(k_spmm_rowset_pipe<32>, dim3((unsigned)grid), dim3(32 * kRpLanes), 0, s,
+                       A.n, A.rowptr, A.col, A.val, R.col, R.lidx, X, Y);
+  }
   return SPX_OK;
 }
 
