@@ -567,14 +567,17 @@ int launch_spmm_rowset(const Csr& A, const double* X, double* Y, hipStream_t s) 
     go(k_spmm_rowset<64>, 64);
   } else {
     // 32-row tiles: the pipelined form, a persistent grid of the workgroups
-    // that fit at once (two per CU with its two 40 KB buffers)
-    int fit = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &fit, reinterpret_cast<const void*>(&k_spmm_rowset_pipe<32>), 32 * kRpLanes, 0) !=
-            hipSuccess ||
-        fit < 1)
-      fit = 1;
-    (void)hipGetLastError();
+    // that fit at once (two per CU with its two 40 KB buffers; asked once)
+    static const int fit = [] {
+      int f = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &f, reinterpret_cast<const void*>(&k_spmm_rowset_pipe<32>), 32 * kRpLanes, 0) !=
+              hipSuccess ||
+          f < 1)
+        f = 1;
+      (void)hipGetLastError();
+      return f;
+    }();
     const int64_t grid = std::min<int64_t>(ceil_div(A.n, 32), (int64_t)fit * cu_count());
     hipLaunchKernelGGL(k_spmm_rowset_pipe<32>, dim3((unsigned)grid), dim3(32 * kRpLanes), 0, s,
                        A.n, A.rowptr, A.col, A.val, R.col, R.lidx, X, Y);
