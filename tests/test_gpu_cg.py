@@ -38,7 +38,7 @@ def test_config1_cg(orc):
 @pytest.mark.parametrize("variant,blocks,vblocks,quad", [(1, 0, 0, 1), (2, 0, 0, 1), (2, 37, 5, 1),
                                                         (1, 2048, 3000, 1), (2, 0, 0, 0),
                                                         (3, 0, 0, 0), (3, 37, 5, 0), (4, 0, 0, 0),
-                                                        (4, 37, 5, 1)])
+                                                        (4, 37, 5, 1), (2, 777, 1500, 0)])
 def test_config1_cg_shapes(orc, variant, blocks, vblocks, quad):
     spx = require_gpu()
     prob, _, b = W.config1()
