@@ -351,7 +351,9 @@ __global__ __launch_bounds__(ROWS * kRpLanes) __attribute__((amdgpu_waves_per_eu
 // separate arrays, so the products' LDS reads wait only for LDS; they go
 // eight at a time (rs_chunk8) for the fewer waves.  Every tile's products
 // are those of k_spmm_rowset, bitwise (tested).  On the 128^3-node operator
-// 0.337-0.342 ms against 0.353 for k_spmm_rowset<32>.
+// 0.337-0.342 ms against 0.353 for k_spmm_rowset at 32-row tiles (which
+// keeps the 16- and 64-row tiles: one workgroup per CU at 64 rows, and
+// three at 16 where a second buffer would leave two).
 struct RsNext {      // list and row bounds of a tile whose X is still to load
   int d;
   int32_t t0, t1;
