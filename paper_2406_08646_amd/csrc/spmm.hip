@@ -352,8 +352,8 @@ __global__ __launch_bounds__(ROWS * kRpLanes) __attribute__((amdgpu_waves_per_eu
 // eight at a time (rs_chunk8) for the fewer waves.  Every tile's products
 // are those of k_spmm_rowset, bitwise (tested).  On the 128^3-node operator
 // 0.337-0.342 ms against 0.353 for k_spmm_rowset at 32-row tiles (which
-// keeps the 16- and 64-row tiles: one workgroup per CU at 64 rows, and
-// three at 16 where a second buffer would leave two).
+// keeps the 16- and 64-row tiles: at 64 rows a second 80 KB buffer would
+// leave one workgroup per CU, at 16 rows three instead of six).
 struct RsNext {      // list and row bounds of a tile whose X is still to load
   int d;
   int32_t t0, t1;
