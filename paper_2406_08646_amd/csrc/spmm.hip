@@ -498,7 +498,11 @@ __global__ __launch_bounds__(ROWS * kRpLanes) void k_spmm_rowset_pipe(
   }
   RsNext na, nb;
   RsCur ca, cb;
-  int64_t b = blockIdx.x;
+  // workgroup w takes tiles b0, b0 + step, ... with b0 its XCD-grouped
+  // number: at any time the grid works on one stretch of step tiles, and
+  // each XCD on a contiguous part of it, so neighbouring lines' tiles share
+  // an L2 (0.336-0.338 ms against 0.341-0.342 in workgroup order)
+  int64_t b = xcd_logical_block(blockIdx.x, gridDim.x);
   rsp_next<ROWS>(n, rowptr, ucol, b, tiles, na);
   __builtin_amdgcn_s_waitcnt(0);
   rsp_issue<ROWS>(na, val, lidx, X, xa, ca);
